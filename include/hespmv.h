@@ -1,0 +1,185 @@
+/*
+ * hespmv.h -- C ABI of an MI355X (gfx950) library for encrypted sparse matrix-vector
+ * multiplication over the Compressed Sparse Sorted Column (CSSC) format, arXiv 2603.04742.
+ *
+ * The calls follow the paper's three-party protocol (Sec. 3.2; Sec. 4.4, Alg. "Sparse
+ * Matrix-Vector Multiplication"):
+ *   Client A   hs_cssc_pack        CSR -> CSSC (App. B), row partitions (Sec. 4.7), chunks
+ *                                  (Alg. generateChunk), slot packing and encoding/encryption
+ *              hs_matrix_column_index   the plaintext column-index array sent to Client B
+ *   Client B   hs_encrypt          reorganised vector (Alg. reorgVector), encoded and encrypted
+ *   Cloud      hs_he_spmv          slot-wise products (HE-CMult, or HE-Mult when the matrix values
+ *                                  are encrypted) and Alg. Aggregation (totalSum rotations, masks)
+ *   Key holder hs_decrypt          decryption and the row-map scatter
+ * plus hs_keygen (secret, public, power-of-two rotation and relinearisation keys).
+ *
+ * Scheme: BFV-style RLWE over Z_q[X]/(X^N + 1), RNS with L data primes and K special primes (all
+ * NTT-friendly, < 2^50), plaintext modulus t prime with t = 1 mod 2N, ternary secret, discrete
+ * Gaussian errors (sigma 3.2).  Conventions (prime choice, slot order, NTT order, sampling, key
+ * switching, ct x ct) are pinned so that every ciphertext limb is reproducible bit for bit.
+ *
+ * Conventions of the ABI:
+ *  - Every function returns HS_OK (0) or a negative HS_E* code; hs_last_error() then returns a
+ *    thread-local message.  On error no output handle is created.
+ *  - Handles are opaque and library-owned; each has a matching *_destroy.  Device memory held by a
+ *    handle is allocated on the device that was current at hs_ctx_create.
+ *  - Pointers documented as "device" are HBM addresses on that device (e.g. torch tensor
+ *    data_ptr()); "host" pointers are ordinary CPU memory.  Input arrays are read during the call
+ *    (device inputs: in stream order) and not retained.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued on it; calls that
+ *    return host data synchronise it.  Two calls that share no output handle may run on different
+ *    streams concurrently; an hs_ctx and an hs_keyset are read-only after creation.
+ *  - Ciphertexts are stored limb-major, [2][L][N] u64 residues in [0, q_i), NTT form, where the
+ *    NTT order is A[k] = a(psi_i^(2 bitrev(k) + 1)), psi_i the smallest primitive 2N-th root of
+ *    unity mod q_i.
+ */
+#ifndef HESPMV_H
+#define HESPMV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- status codes */
+#define HS_OK 0
+#define HS_EINVAL (-1)     /* bad argument or malformed CSR (unsorted row pointers, index out of range) */
+#define HS_EPARAM (-2)     /* unsupported parameters: N not a power of two in [2^3, 2^16], t prime with t = 1 mod 2N required,
+                              not enough NTT-friendly primes, prime width above 50 bits */
+#define HS_ECAPACITY (-3)  /* a size exceeds what the handle or parameter set can hold */
+#define HS_EKEY (-4)       /* keys missing or from another context */
+#define HS_ENOMEM (-5)     /* host or device allocation failed */
+#define HS_EDEVICE (-6)    /* HIP runtime error (message names the call) */
+
+/* Thread-local description of the last error of a failed call on this thread. */
+const char* hs_last_error(void);
+
+/* ---------------------------------------------------------------- parameters and context */
+typedef struct hs_params {
+  uint32_t log_n;    /* ring degree N = 2^log_n, 3 <= log_n <= 15 */
+  uint32_t n_q;      /* L: number of data primes */
+  uint32_t q_bits;   /* bit width of data and special primes (<= 50) */
+  uint32_t n_p;      /* K: number of special (key-switching) primes, >= 1; also the digit size */
+  uint32_t p_bits;   /* must equal q_bits */
+  uint64_t t;        /* plaintext modulus, prime, t = 1 mod 2N (65537 for N <= 32768) */
+  double sigma;      /* error width; only 3.2 is supported */
+  uint32_t agg_mode; /* 0 = paper aggregation: chunk heights NNZ[start] and masks (Alg. Aggregation);
+                        1 = uniform heights NNZ[0] in a partition and no masks (one fewer ct x pt,
+                            needed when Q/t leaves too little noise room for the mask product) */
+} hs_params;
+
+typedef struct hs_ctx hs_ctx;
+typedef struct hs_keyset hs_keyset;
+typedef struct hs_matrix hs_matrix;
+typedef struct hs_ctvec hs_ctvec;
+
+/* Create a context: prime selection (the largest primes q < 2^q_bits with q = 1 mod 2N, first K
+   special, next L data primes, then tensor primes for exact ct x ct), NTT tables, constants.
+   Uses the current HIP device.  HS_EPARAM for unsupported parameter sets. */
+int hs_ctx_create(const hs_params* params, hs_ctx** out);
+void hs_ctx_destroy(hs_ctx* ctx);
+/* Moduli in chain order (L data, K special, then tensor primes) into host `out` (capacity
+   `cap`); *n receives the total count.  HS_ECAPACITY if cap is too small. */
+int hs_ctx_moduli(const hs_ctx* ctx, uint64_t* out, int cap, int* n);
+
+/* The 20 thresholds of the discrete Gaussian sampler, T[k] = floor(2^63 P(|e| <= k)) for sigma = 3.2
+   truncated at |e| <= 19, computed by the library in 128-bit fixed point (host `out`). */
+int hs_cdt_table(uint64_t out[20]);
+
+/* ---------------------------------------------------------------- keys (Sec. 5 setup: one
+   relinearisation key set plus power-of-two rotation keys) */
+/* Generate a key-set from a 64-bit seed (ChaCha20 streams, RFC 8439): ternary secret s, public
+   key (-a s + e, a), rotation keys for left rotations by 2^i, i = 0 .. log_n - 2 (Galois elements
+   3^(2^i) mod 2N), and a relinearisation key for s^2.  Key-switching keys use the hybrid form with
+   digits of K data primes and special modulus P.  The key-set holds the secret key too: it plays
+   both the key holder and the evaluation-key owner of the protocol. */
+int hs_keygen(hs_ctx* ctx, uint64_t seed, void* stream, hs_keyset** out);
+void hs_keyset_destroy(hs_keyset* ks);
+/* Copy key material to host memory, for verification.  which: 0 = secret key, NTT form
+   [n_moduli][N]; 1 = public key [2][L][N]; 2 = rotation key `index` [2][dnum][L+K][N]
+   (b then a); 3 = relinearisation key, same layout.  cap in u64 words; HS_ECAPACITY if short. */
+int hs_keyset_export(const hs_keyset* ks, int which, int index, uint64_t* host_out, int64_t cap);
+
+/* ---------------------------------------------------------------- Client A: matrix */
+/* Pack an R x C integer matrix given in CSR form (device arrays: row_ptr int64[R+1] with
+   row_ptr[0] = 0 and nondecreasing, col_idx int32[nnz] in [0, C) ascending within each row,
+   vals int64[nnz], any magnitude; values are taken mod t).  Rows are split into partitions of
+   N/2 rows (Sec. 4.7); each partition is converted to CSSC (rows sorted by descending nonzero
+   count, stable, App. B), cut into chunks (Alg. generateChunk: column i joins the chunk started at
+   column `start` while h * (i - start + 1) <= N/2), and each chunk's values are packed into the
+   first slot row (slot k <-> column block k / h, sorted row k % h) and batch-encoded
+   (encrypt_values = 0) or encrypted under `ks` with `seed` (encrypt_values = 1, both-encrypted
+   variant).  Masks 1^h || 0 are encoded per chunk when agg_mode = 0.  Synchronises `stream`. */
+int hs_cssc_pack(hs_ctx* ctx, int64_t rows, int64_t cols, const int64_t* row_ptr,
+                 const int32_t* col_idx, const int64_t* vals, int encrypt_values,
+                 const hs_keyset* ks, uint64_t seed, void* stream, hs_matrix** out);
+void hs_matrix_destroy(hs_matrix* m);
+int hs_matrix_info(const hs_matrix* m, int64_t* n_parts, int64_t* n_chunks);
+/* Chunk k (global numbering over partitions): out4 = (partition, first CSSC column, columns c,
+   height h). */
+int hs_matrix_chunk(const hs_matrix* m, int64_t k, int64_t out4[4]);
+/* The CSSC column-index array (all partitions, concatenated) that Client A sends to Client B
+   (Alg. "Sparse Matrix-Vector Multiplication"), into host memory. *len receives nnz. */
+int hs_matrix_column_index(const hs_matrix* m, int32_t* host_ci, int64_t cap, int64_t* len);
+/* Encoded (NTT-form [L][N]) or encrypted ([2][L][N]) chunk k, or its mask (which = 1), to host. */
+int hs_matrix_export(const hs_matrix* m, int which, int64_t k, uint64_t* host_out, int64_t cap);
+
+/* ---------------------------------------------------------------- Client B: vector */
+/* Reorganise the dense vector v (device int64[len], len = cols) per chunk (slot k = v[CI[k]], 0 for
+   padding; Alg. reorgVector), batch-encode and encrypt under the public key of `ks` with `seed`:
+   one ciphertext per chunk, ciphertext index = global chunk number. */
+int hs_encrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const int64_t* v,
+               int64_t len, uint64_t seed, void* stream, hs_ctvec** out);
+
+/* ---------------------------------------------------------------- Cloud */
+/* Encrypted SpMV: for each chunk the slot-wise product with the encrypted vector (HE-CMult, or
+   HE-Mult + relinearisation for an encrypted matrix), the intra-chunk totalSum by rotations of
+   e*h slots (Alg. Aggregation; each rotation applied as its binary digits in ascending order, one
+   key switch per digit), the mask product (agg_mode 0), and the sum over the chunks of each
+   partition.  *y receives one ciphertext per row partition. */
+int hs_he_spmv(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* x,
+               void* stream, hs_ctvec** y);
+
+/* ---------------------------------------------------------------- key holder */
+/* Decrypt the per-partition results and scatter them with the row map: out (device int64[rows])
+   receives y = A v reduced into (-t/2, t/2]; rows without nonzeros receive 0. */
+int hs_decrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* y,
+               int64_t* out, int64_t rows, void* stream);
+
+/* ---------------------------------------------------------------- ciphertext vectors */
+int hs_ctvec_count(const hs_ctvec* v, int64_t* n);
+/* Ciphertext i as [2][L][N] NTT-form residues, into host memory (synchronises the device). */
+int hs_ct_export(const hs_ctvec* v, int64_t i, uint64_t* host_limbs, int64_t cap);
+/* Build a vector of n ciphertexts from host limbs [n][2][L][N] (NTT form, residues < q_i). */
+int hs_ctvec_import(hs_ctx* ctx, const uint64_t* host_limbs, int64_t n, hs_ctvec** out);
+void hs_ctvec_destroy(hs_ctvec* v);
+
+/* ---------------------------------------------------------------- primitive operations
+   (the building blocks of the protocol, exposed for verification and composition; device
+   pointers, enqueued on `stream`) */
+/* In-place negacyclic NTT (inverse = 0) or inverse NTT (inverse = 1) of n_polys polynomials of
+   n_limbs limbs each, limb l reduced modulo chain modulus mod0 + l (mod0 = -1: the plaintext
+   modulus t, n_limbs = 1).  d_limbs: device u64 [n_polys][n_limbs][N], residues < modulus. */
+int hs_ntt(hs_ctx* ctx, uint64_t* d_limbs, int64_t n_polys, int mod0, int n_limbs, int inverse,
+           void* stream);
+/* Slot-wise product of every ciphertext of `in` with the NTT-form plaintext pt (device u64
+   [L][N]) (HE-CMult). */
+int hs_mul_plain(hs_ctx* ctx, const hs_ctvec* in, const uint64_t* d_pt, void* stream, hs_ctvec** out);
+/* Left rotation of every ciphertext of `in` by k slots within each slot row (HE-Rot): the binary
+   digits of k mod N/2 in ascending order, each a Galois automorphism 3^(2^i) plus a key switch. */
+int hs_rotate(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* in, int64_t k, void* stream,
+              hs_ctvec** out);
+/* Slot-wise product of two ciphertexts (HE-Mult): exact scaled tensor round(t/Q * (a (x) b)) of the
+   centered lifts, then relinearisation.  Vectors of equal length, element by element. */
+int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctvec* b,
+              void* stream, hs_ctvec** out);
+
+/* Counters of the calling thread's last hs_he_spmv / hs_he_spmv_batch: [0] key switches,
+   [1] logical rotations, [2] kernel launches, [3] slot-wise products, [4] mask products. */
+int hs_last_counters(int64_t out[5]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HESPMV_H */

@@ -1,0 +1,825 @@
+// C ABI of the encrypted-SpMV library: host orchestration of the HIP kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <stdexcept>
+
+#include "kernels.hpp"
+
+namespace hs {
+const char* last_error_cstr();
+
+static thread_local int64_t g_counters[5] = {0, 0, 0, 0, 0};
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    f();
+    return HS_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return HS_ENOMEM;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return HS_EINVAL;
+  }
+}
+
+static hipStream_t S(void* s) { return (hipStream_t)s; }
+
+template <class T>
+static void h2d(T* d, const T* h, size_t n, hipStream_t st) {
+  if (n) HS_CHECK_HIP(hipMemcpyAsync(d, h, n * sizeof(T), hipMemcpyHostToDevice, st));
+}
+template <class T>
+static void d2h(T* h, const T* d, size_t n, hipStream_t st) {
+  if (n) HS_CHECK_HIP(hipMemcpyAsync(h, d, n * sizeof(T), hipMemcpyDeviceToHost, st));
+}
+template <class T>
+static T* dmalloc(size_t n) {
+  T* p = nullptr;
+  if (!n) n = 1;
+  if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) throw Error{HS_ENOMEM, "device allocation failed"};
+  return p;
+}
+
+// ------------------------------------------------------------------ Gaussian CDT (library copy)
+// T[k] = floor(2^63 P(|e| <= k)) for the discrete Gaussian with sigma = 3.2 truncated at 19,
+// rho(x) = exp(-x^2 / 20.48).  Computed in 128-bit fixed point with 120 fractional bits:
+// exp(-x) = (exp(-x/64))^64 with a 40-term Taylor series; the ratio by binary long division.
+static u128 fx_mul(u128 a, u128 b) {
+  const u64 a0 = (u64)a, a1 = (u64)(a >> 64), b0 = (u64)b, b1 = (u64)(b >> 64);
+  const u128 p00 = (u128)a0 * b0, p01 = (u128)a0 * b1, p10 = (u128)a1 * b0, p11 = (u128)a1 * b1;
+  const u128 mid = (p00 >> 64) + (u64)p01 + (u64)p10;
+  const u128 hi = p11 + (p01 >> 64) + (p10 >> 64) + (mid >> 64);
+  return (hi << 8) | ((u64)mid >> 56);
+}
+static void compute_cdt(u64 out[20]) {
+  const int F = 120;
+  const u128 one = (u128)1 << F;
+  u128 rho[20];
+  for (int j = 0; j < 20; j++) {
+    // y = 25 j^2 / 2^15  (= x / 64 with x = j^2 / 20.48 = 25 j^2 / 512)
+    const u128 y = (u128)(25 * j * j) << (F - 15);
+    u128 sum = one, term = one;
+    for (int n = 1; n <= 40; n++) {
+      term = fx_mul(term, y) / (u128)n;
+      if (n & 1) sum -= term; else sum += term;
+    }
+    for (int sq = 0; sq < 6; sq++) sum = fx_mul(sum, sum);
+    rho[j] = sum;
+  }
+  u128 cum[20];
+  u128 acc = rho[0];
+  cum[0] = acc;
+  for (int k = 1; k < 20; k++) { acc += 2 * rho[k]; cum[k] = acc; }
+  const u128 total = cum[19];
+  for (int k = 0; k < 19; k++) {
+    u128 rem = cum[k];
+    u64 q = 0;
+    for (int bit = 62; bit >= 0; bit--) {
+      rem <<= 1;
+      if (rem >= total) { rem -= total; q |= 1ULL << bit; }
+    }
+    out[k] = q;
+  }
+  out[19] = 1ULL << 63;
+}
+
+// ------------------------------------------------------------------ sampling purposes
+enum : u32 { P_SK = 1, P_PK_A = 2, P_PK_E = 3, P_KSK_A = 4, P_KSK_E = 5, P_ENC_U = 6, P_ENC_E0 = 7, P_ENC_E1 = 8 };
+static const u32 RELIN_ID = 255;
+
+static u64 galois_pow2(const hs_ctx* c, int i) { return pow_mod(3, 1ULL << i, 2 * c->N); }
+
+// ------------------------------------------------------------------ key generation
+static u64* make_ksk(hs_ctx* c, hs_keyset* ks, u32 key_id, int sprime_mode, u32 galois, hipStream_t st) {
+  const int LK = c->L + c->K;
+  const size_t N = c->N;
+  u64* key = dmalloc<u64>(2ULL * c->dnum * LK * N);
+  DBuf e(&c->pool, (size_t)c->dnum * N * sizeof(int));
+  launch_sample_small(c, e.as<int>(), c->dnum, (i64)N, ks->seed, P_KSK_E, ((u64)key_id << 16), 1ULL << 8, 1, st);
+  std::vector<KskArgs> args;
+  std::vector<u64> ps(c->mod.begin() + c->L, c->mod.begin() + LK);
+  for (int j = 0; j < c->dnum; j++) {
+    for (int m = 0; m < LK; m++) {
+      const u64 q = c->mod[m];
+      KskArgs a{};
+      a.b = key + (((size_t)0 * c->dnum + j) * LK + m) * N;
+      a.a = key + (((size_t)1 * c->dnum + j) * LK + m) * N;
+      a.e_coef = e.as<int>() + (size_t)j * N;
+      a.sk = ks->sk + (size_t)m * N;
+      a.mod_index = m;
+      a.seed = ks->seed;
+      a.purpose_a = P_KSK_A;
+      a.idx_a = ((u64)key_id << 16) | ((u64)j << 8) | (u64)m;
+      a.sprime_mode = sprime_mode;
+      a.galois = galois;
+      const bool in_digit = m < c->L && m / c->alpha == j;
+      u64 pm = 1;
+      for (u64 p : ps) pm = mul_mod(pm, p % q, q);
+      a.pfac = in_digit ? make_const(pm, q) : double2{0.0, 0.0};
+      const u64 r64 = (u64)(((u128)1 << 64) % q);
+      a.r64 = make_const(r64, q);
+      args.push_back(a);
+    }
+  }
+  DBuf dargs(&c->pool, args.size() * sizeof(KskArgs));
+  h2d(dargs.as<KskArgs>(), args.data(), args.size(), st);
+  launch_ksk_limbs(c, dargs.as<KskArgs>(), (int)args.size(), st);
+  HS_CHECK_HIP(hipStreamSynchronize(st));
+  return key;
+}
+
+// ------------------------------------------------------------------ CSSC structure (host)
+static std::vector<hs_chunk> make_chunks(const std::vector<i64>& cp, i64 s, int uniform, int part) {
+  std::vector<hs_chunk> out;
+  const int nC = (int)cp.size() - 1;
+  int i = 0;
+  while (i < nC) {
+    const int start = i;
+    const i64 h = uniform ? cp[1] - cp[0] : cp[start + 1] - cp[start];
+    while (i < nC && h * (i - start + 1) <= s) i++;
+    out.push_back(hs_chunk{part, start, i - start, h});
+  }
+  return out;
+}
+
+// ------------------------------------------------------------------ he_spmv plan
+// Micro-op of a chunk's totalSum: one power-of-two rotation, in -> out (+ addend).
+struct MicroOp {
+  int in, out, addend;  // buffer ids per chunk: 0 = V (product), 1 = WA, 2 = WB, 3 = TA, 4 = TB; -1 none
+  int pow2;
+};
+
+static std::vector<MicroOp> total_sum_program(const hs_ctx* c, i64 r, int cols, int* n_logical) {
+  std::vector<MicroOp> prog;
+  int w = 0;  // current accumulator buffer
+  i64 e = 1;
+  const int nb = 32 - __builtin_clz((unsigned)cols);
+  const i64 half = (i64)c->N / 2;
+  auto rotate_into = [&](int src, i64 amount, int addend) {
+    // rotation by `amount` applied as its binary digits (ascending), last one lands in the W
+    // buffer that is not the current accumulator, plus `addend`
+    const i64 k = amount % half;
+    std::vector<int> bits;
+    for (int i = 0; i + 1 < c->logn; i++)
+      if ((k >> i) & 1) bits.push_back(i);
+    if (bits.empty()) throw Error{HS_EINVAL, "internal: zero rotation in totalSum"};
+    const int dst_w = (w == 1) ? 2 : 1;
+    int cur = src;
+    for (size_t b = 0; b < bits.size(); b++) {
+      const bool last = b + 1 == bits.size();
+      const int dst = last ? dst_w : (cur == 3 ? 4 : 3);
+      prog.push_back(MicroOp{cur, dst, last ? addend : -1, bits[b]});
+      cur = dst;
+    }
+    if (n_logical) (*n_logical)++;
+    w = dst_w;
+  };
+  for (int j = nb - 2; j >= 0; j--) {
+    rotate_into(w, e * r, w);     // w <- w + Rot(w, e r)
+    e *= 2;
+    if ((cols >> j) & 1) {
+      rotate_into(w, r, 0);       // w <- ctV + Rot(w, r)
+      e += 1;
+    }
+  }
+  (void)e;
+  prog.push_back(MicroOp{w, w, -2, -1});  // terminal marker: result buffer id
+  return prog;
+}
+
+static KsShape ks_shape(const hs_ctx* c, int B) {
+  KsShape S{};
+  S.L = c->L; S.K = c->K; S.alpha = c->alpha; S.dnum = c->dnum;
+  const int LK = c->L + c->K;
+  int ndg = (512 + LK * B - 1) / (LK * B);
+  ndg = std::max(1, std::min(ndg, c->dnum));
+  S.dpg = (c->dnum + ndg - 1) / ndg;
+  S.ndg = (c->dnum + S.dpg - 1) / S.dpg;
+  return S;
+}
+
+// Levels of batched power-of-two rotations: every item of a level is independent of the others;
+// level k + 1 may read what level k wrote.  All item arrays are uploaded once and the scratch is
+// sized for the widest level, so the launches of all levels are enqueued without host waits.
+static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels, hipStream_t st) {
+  size_t total = 0, widest = 0;
+  for (auto& l : levels) { total += l.size(); widest = std::max(widest, l.size()); }
+  if (!total) return;
+  const size_t N = c->N;
+  const int LK = c->L + c->K;
+  std::vector<RotItem> flat;
+  flat.reserve(total);
+  for (auto& l : levels) flat.insert(flat.end(), l.begin(), l.end());
+  const KsShape Smax = ks_shape(c, 1);  // the most digit groups any level uses
+  DBuf ditems(&c->pool, total * sizeof(RotItem));
+  DBuf D(&c->pool, widest * c->L * N * sizeof(u64));
+  DBuf ACC(&c->pool, widest * Smax.ndg * 2 * LK * N * sizeof(double));
+  DBuf PC(&c->pool, widest * 2 * c->K * N * sizeof(double));
+  h2d(ditems.as<RotItem>(), flat.data(), flat.size(), st);
+  size_t off = 0;
+  for (auto& l : levels) {
+    const int B = (int)l.size();
+    if (!B) continue;
+    const KsShape Sh = ks_shape(c, B);
+    launch_rotate_batch(c, ditems.as<RotItem>() + off, B, Sh, D.as<u64>(), ACC.as<double>(), PC.as<double>(), st);
+    off += B;
+    g_counters[0] += B;
+    g_counters[2] += 4;
+  }
+  // the item array and scratch return to the pool: wait until the kernels are done with them
+  HS_CHECK_HIP(hipStreamSynchronize(st));
+}
+
+static hs_ctvec* new_ctvec(hs_ctx* c, i64 n) {
+  hs_ctvec* v = new hs_ctvec();
+  v->ctx = c;
+  v->n = n;
+  v->d = dmalloc<u64>(std::max<i64>(n, 1) * ct_words(c));
+  return v;
+}
+
+}  // namespace hs
+
+using namespace hs;
+
+extern "C" {
+
+const char* hs_last_error(void) { return hs::last_error_cstr(); }
+
+int hs_ctx_create(const hs_params* params, hs_ctx** out) {
+  return guarded([&] {
+    HS_REQUIRE(params && out, HS_EINVAL, "null argument");
+    *out = nullptr;
+    hs_ctx* c = new hs_ctx();
+    c->prm = *params;
+    try {
+      HS_CHECK_HIP(hipGetDevice(&c->device));
+      build_ctx(c);
+      HS_REQUIRE(c->dec_words <= 16, HS_EPARAM, "modulus too large for the decryption kernel (at most 16 words)");
+      u64 cdt[20];
+      compute_cdt(cdt);
+      upload_cdt(cdt);
+    } catch (...) {
+      free_ctx(c);
+      delete c;
+      throw;
+    }
+    *out = c;
+  });
+}
+
+void hs_ctx_destroy(hs_ctx* c) {
+  if (!c) return;
+  free_ctx(c);
+  delete c;
+}
+
+int hs_ctx_moduli(const hs_ctx* c, uint64_t* out, int cap, int* n) {
+  return guarded([&] {
+    HS_REQUIRE(c && n, HS_EINVAL, "null argument");
+    *n = c->n_mod;
+    HS_REQUIRE(out && cap >= c->n_mod, HS_ECAPACITY, "output too small");
+    for (int i = 0; i < c->n_mod; i++) out[i] = c->mod[i];
+  });
+}
+
+int hs_cdt_table(uint64_t out[20]) {
+  return guarded([&] {
+    HS_REQUIRE(out, HS_EINVAL, "null argument");
+    compute_cdt(out);
+  });
+}
+
+int hs_keygen(hs_ctx* c, uint64_t seed, void* stream, hs_keyset** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && out, HS_EINVAL, "null argument");
+    *out = nullptr;
+    hipStream_t st = S(stream);
+    hs_keyset* ks = new hs_keyset();
+    ks->ctx = c;
+    ks->seed = seed;
+    try {
+      const size_t N = c->N;
+      const int LK = c->L + c->K;
+      ks->ksk_words = 2ULL * c->dnum * LK * N;
+      DBuf scoef(&c->pool, N * sizeof(int));
+      launch_sample_small(c, scoef.as<int>(), 1, (i64)N, seed, P_SK, 0, 1, 0, st);
+      ks->sk = dmalloc<u64>((size_t)c->n_mod * N);
+      launch_sk_ntt(c, ks->sk, scoef.as<int>(), st);
+      // public key: (pk0, pk1) = (e - a s, a) over the data primes
+      ks->pk = dmalloc<u64>(2ULL * c->L * N);
+      DBuf e(&c->pool, N * sizeof(int));
+      launch_sample_small(c, e.as<int>(), 1, (i64)N, seed, P_PK_E, 0, 1, 1, st);
+      std::vector<KskArgs> args;
+      for (int i = 0; i < c->L; i++) {
+        const u64 q = c->mod[i];
+        KskArgs a{};
+        a.b = ks->pk + (size_t)i * N;
+        a.a = ks->pk + ((size_t)c->L + i) * N;
+        a.e_coef = e.as<int>();
+        a.sk = ks->sk + (size_t)i * N;
+        a.mod_index = i;
+        a.seed = seed;
+        a.purpose_a = P_PK_A;
+        a.idx_a = (u64)i;
+        a.sprime_mode = 0;
+        a.pfac = double2{0.0, 0.0};
+        a.r64 = make_const((u64)(((u128)1 << 64) % q), q);
+        args.push_back(a);
+      }
+      DBuf dargs(&c->pool, args.size() * sizeof(KskArgs));
+      h2d(dargs.as<KskArgs>(), args.data(), args.size(), st);
+      launch_ksk_limbs(c, dargs.as<KskArgs>(), (int)args.size(), st);
+      HS_CHECK_HIP(hipStreamSynchronize(st));
+      for (int i = 0; i + 1 < c->logn; i++) ks->gk.push_back(make_ksk(c, ks, (u32)i, 1, (u32)galois_pow2(c, i), st));
+      ks->rk = make_ksk(c, ks, RELIN_ID, 2, 0, st);
+    } catch (...) {
+      hs_keyset_destroy(ks);
+      throw;
+    }
+    *out = ks;
+  });
+}
+
+void hs_keyset_destroy(hs_keyset* ks) {
+  if (!ks) return;
+  if (ks->sk) (void)hipFree(ks->sk);
+  if (ks->pk) (void)hipFree(ks->pk);
+  for (u64* p : ks->gk) (void)hipFree(p);
+  if (ks->rk) (void)hipFree(ks->rk);
+  delete ks;
+}
+
+int hs_keyset_export(const hs_keyset* ks, int which, int index, uint64_t* host_out, int64_t cap) {
+  return guarded([&] {
+    HS_REQUIRE(ks && host_out, HS_EINVAL, "null argument");
+    const hs_ctx* c = ks->ctx;
+    const u64* src = nullptr;
+    size_t n = 0;
+    if (which == 0) { src = ks->sk; n = (size_t)c->n_mod * c->N; }
+    else if (which == 1) { src = ks->pk; n = 2ULL * c->L * c->N; }
+    else if (which == 2) {
+      HS_REQUIRE(index >= 0 && index < (int)ks->gk.size(), HS_EKEY, "no rotation key with that index");
+      src = ks->gk[index]; n = ks->ksk_words;
+    } else if (which == 3) { src = ks->rk; n = ks->ksk_words; }
+    else throw Error{HS_EINVAL, "unknown key kind"};
+    HS_REQUIRE((size_t)cap >= n, HS_ECAPACITY, "output too small");
+    HS_CHECK_HIP(hipMemcpy(host_out, src, n * sizeof(u64), hipMemcpyDeviceToHost));
+  });
+}
+
+int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, const int32_t* col_idx,
+                 const int64_t* vals, int encrypt_values, const hs_keyset* ks, uint64_t seed, void* stream,
+                 hs_matrix** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && out, HS_EINVAL, "null argument");
+    *out = nullptr;
+    HS_REQUIRE(rows >= 0 && cols >= 0 && rows < (1LL << 31) && cols < (1LL << 31), HS_EINVAL, "bad matrix shape");
+    HS_REQUIRE(rows == 0 || row_ptr, HS_EINVAL, "null row_ptr");
+    HS_REQUIRE(!encrypt_values || (ks && ks->ctx == c), HS_EKEY, "encrypted values need the key-set of this context");
+    hipStream_t st = S(stream);
+    const size_t N = c->N;
+    const i64 s = (i64)N / 2;
+    // --- structure on the host: the sparsity pattern is public (Sec. 3.1)
+    std::vector<i64> rp(rows + 1, 0);
+    if (rows) d2h(rp.data(), row_ptr, rows + 1, st);
+    DBuf bad(&c->pool, sizeof(int));
+    HS_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
+    int hbad = 0;
+    HS_CHECK_HIP(hipStreamSynchronize(st));
+    HS_REQUIRE(rp[0] == 0, HS_EINVAL, "row_ptr[0] must be 0");
+    for (i64 i = 0; i < rows; i++) HS_REQUIRE(rp[i + 1] >= rp[i], HS_EINVAL, "row_ptr must be nondecreasing");
+    const i64 nnz = rp[rows];
+    HS_REQUIRE(nnz == 0 || (col_idx && vals), HS_EINVAL, "null col_idx/vals");
+    if (nnz) {
+      launch_csr_check(row_ptr, col_idx, rows, cols, bad.as<int>(), st);
+      d2h(&hbad, bad.as<int>(), 1, st);
+      HS_CHECK_HIP(hipStreamSynchronize(st));
+      HS_REQUIRE(!hbad, HS_EINVAL, "column indices out of range or not strictly ascending within a row");
+    }
+    hs_matrix* M = new hs_matrix();
+    M->ctx = c; M->R = rows; M->C = cols; M->nnz = nnz; M->encrypted = encrypt_values ? 1 : 0;
+    try {
+      std::vector<int> rank(std::max<i64>(rows, 1), 0);
+      std::vector<i64> part_cp_off, part_nnz_off;
+      for (i64 r0 = 0, p = 0; r0 < rows; r0 += s, p++) {
+        hs_part P{};
+        P.row0 = r0;
+        P.rows = std::min(s, rows - r0);
+        std::vector<i64> cnt(P.rows);
+        i64 Lw = 0;
+        for (i64 i = 0; i < P.rows; i++) { cnt[i] = rp[r0 + i + 1] - rp[r0 + i]; Lw = std::max(Lw, cnt[i]); }
+        HS_REQUIRE(Lw <= (1 << 30), HS_ECAPACITY, "row too long");
+        P.Lw = (int)Lw;
+        // stable counting sort by descending count
+        std::vector<i64> hist(Lw + 2, 0);
+        for (i64 i = 0; i < P.rows; i++) hist[cnt[i]]++;
+        std::vector<i64> startpos(Lw + 2, 0);
+        for (i64 v = Lw - 1, acc = hist[Lw]; v >= 0; v--) { startpos[v] = acc; acc += hist[v]; }
+        startpos[Lw] = 0;
+        std::vector<i32> rm(P.rows);
+        for (i64 i = 0; i < P.rows; i++) {
+          const i64 pos = startpos[cnt[i]]++;
+          rm[pos] = (i32)i;
+          rank[r0 + i] = (int)pos;
+        }
+        // CP[j] = sum_{j' < j} #{rows with count > j'}
+        std::vector<i64> cp(Lw + 1, 0);
+        {
+          std::vector<i64> atleast(Lw + 2, 0);  // #rows with count >= v
+          for (i64 v = Lw; v >= 0; v--) atleast[v] = atleast[v + 1] + hist[v];
+          for (i64 j = 0; j < Lw; j++) cp[j + 1] = cp[j] + atleast[j + 1];
+        }
+        P.nz_rows = Lw > 0 ? cp[1] : 0;
+        P.cp_off = (i64)M->h_cp.size();
+        P.nnz_off = rp[r0] - rp[0];
+        P.chunk0 = (int)M->chunks.size();
+        std::vector<hs_chunk> ch = make_chunks(cp, s, c->prm.agg_mode == 1, (int)p);
+        P.nchunks = (int)ch.size();
+        M->chunks.insert(M->chunks.end(), ch.begin(), ch.end());
+        M->h_cp.insert(M->h_cp.end(), cp.begin(), cp.end());
+        M->h_rm.insert(M->h_rm.end(), rm.begin(), rm.end());
+        part_cp_off.push_back(P.cp_off);
+        part_nnz_off.push_back(P.nnz_off);
+        M->parts.push_back(P);
+      }
+      const int G = (int)M->chunks.size();
+      M->d_cp = dmalloc<i64>(M->h_cp.size());
+      M->d_rm = dmalloc<i32>(M->h_rm.size());
+      M->d_va = dmalloc<i64>(nnz);
+      M->d_ci = dmalloc<i32>(nnz);
+      M->d_chunk = dmalloc<i64>(8ULL * std::max(G, 1));
+      h2d(M->d_cp, M->h_cp.data(), M->h_cp.size(), st);
+      h2d(M->d_rm, M->h_rm.data(), M->h_rm.size(), st);
+      std::vector<i64> cd(8ULL * std::max(G, 1), 0);
+      for (int g = 0; g < G; g++) {
+        const hs_chunk& k = M->chunks[g];
+        const hs_part& P = M->parts[k.part];
+        i64* d = &cd[8ULL * g];
+        d[0] = k.start; d[1] = k.c; d[2] = k.h; d[3] = P.cp_off; d[4] = P.nnz_off; d[5] = k.part;
+      }
+      h2d(M->d_chunk, cd.data(), cd.size(), st);
+      if (rows && nnz) {
+        DBuf drank(&c->pool, rows * sizeof(int)), dpco(&c->pool, part_cp_off.size() * sizeof(i64)),
+            dpno(&c->pool, part_nnz_off.size() * sizeof(i64));
+        h2d(drank.as<int>(), rank.data(), rows, st);
+        h2d(dpco.as<i64>(), part_cp_off.data(), part_cp_off.size(), st);
+        h2d(dpno.as<i64>(), part_nnz_off.data(), part_nnz_off.size(), st);
+        launch_cssc_scatter(row_ptr, col_idx, vals, drank.as<int>(), M->d_cp, dpco.as<i64>(), dpno.as<i64>(), rows, s, M->d_va,
+                            M->d_ci, st);
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+      }
+      // --- pack + encode (+ encrypt) every chunk; masks
+      if (G) {
+        DBuf coef(&c->pool, (size_t)G * N * sizeof(u64));
+        PackArgs pa{};
+        pa.va = M->d_va; pa.ci = M->d_ci; pa.v = nullptr; pa.cp = M->d_cp; pa.chunk = M->d_chunk;
+        pa.out = coef.as<u64>(); pa.mode = 0;
+        launch_pack_encode(c, pa, G, st);
+        if (encrypt_values) {
+          M->d_pt = dmalloc<u64>((size_t)G * ct_words(c));
+          DBuf smp(&c->pool, (size_t)G * 3 * N * sizeof(int));
+          launch_sample_small(c, smp.as<int>(), G, 3 * (i64)N, seed, P_ENC_U, 0, 1, 0, st);
+          launch_sample_small(c, smp.as<int>() + N, G, 3 * (i64)N, seed, P_ENC_E0, 0, 1, 1, st);
+          launch_sample_small(c, smp.as<int>() + 2 * N, G, 3 * (i64)N, seed, P_ENC_E1, 0, 1, 1, st);
+          launch_encrypt(c, coef.as<u64>(), smp.as<int>(), ks->pk, M->d_pt, G, st);
+          HS_CHECK_HIP(hipStreamSynchronize(st));
+        } else {
+          M->d_pt = dmalloc<u64>((size_t)G * c->L * N);
+          launch_plain_ntt(c, coef.as<u64>(), M->d_pt, G, st);
+        }
+        if (c->prm.agg_mode == 0) {
+          pa.mode = 2;
+          launch_pack_encode(c, pa, G, st);
+          M->d_mask = dmalloc<u64>((size_t)G * c->L * N);
+          launch_plain_ntt(c, coef.as<u64>(), M->d_mask, G, st);
+        }
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+      }
+    } catch (...) {
+      hs_matrix_destroy(M);
+      throw;
+    }
+    *out = M;
+  });
+}
+
+void hs_matrix_destroy(hs_matrix* m) {
+  if (!m) return;
+  void* ptrs[] = {m->d_cp, m->d_rm, m->d_va, m->d_ci, m->d_chunk, m->d_pt, m->d_mask};
+  for (void* p : ptrs)
+    if (p) (void)hipFree(p);
+  delete m;
+}
+
+int hs_matrix_info(const hs_matrix* m, int64_t* n_parts, int64_t* n_chunks) {
+  return guarded([&] {
+    HS_REQUIRE(m, HS_EINVAL, "null argument");
+    if (n_parts) *n_parts = (int64_t)m->parts.size();
+    if (n_chunks) *n_chunks = (int64_t)m->chunks.size();
+  });
+}
+
+int hs_matrix_chunk(const hs_matrix* m, int64_t k, int64_t out4[4]) {
+  return guarded([&] {
+    HS_REQUIRE(m && out4, HS_EINVAL, "null argument");
+    HS_REQUIRE(k >= 0 && k < (int64_t)m->chunks.size(), HS_EINVAL, "chunk index out of range");
+    const hs_chunk& c = m->chunks[k];
+    out4[0] = c.part; out4[1] = c.start; out4[2] = c.c; out4[3] = c.h;
+  });
+}
+
+int hs_matrix_column_index(const hs_matrix* m, int32_t* host_ci, int64_t cap, int64_t* len) {
+  return guarded([&] {
+    HS_REQUIRE(m && len, HS_EINVAL, "null argument");
+    *len = m->nnz;
+    HS_REQUIRE(host_ci && cap >= m->nnz, HS_ECAPACITY, "output too small");
+    if (m->nnz) HS_CHECK_HIP(hipMemcpy(host_ci, m->d_ci, m->nnz * sizeof(i32), hipMemcpyDeviceToHost));
+  });
+}
+
+int hs_matrix_export(const hs_matrix* m, int which, int64_t k, uint64_t* host_out, int64_t cap) {
+  return guarded([&] {
+    HS_REQUIRE(m && host_out, HS_EINVAL, "null argument");
+    HS_REQUIRE(k >= 0 && k < (int64_t)m->chunks.size(), HS_EINVAL, "chunk index out of range");
+    const hs_ctx* c = m->ctx;
+    const u64* src;
+    size_t n;
+    if (which == 0) {
+      n = m->encrypted ? ct_words(c) : (size_t)c->L * c->N;
+      src = m->d_pt + k * n;
+    } else {
+      HS_REQUIRE(m->d_mask, HS_EINVAL, "no masks (uniform aggregation)");
+      n = (size_t)c->L * c->N;
+      src = m->d_mask + k * n;
+    }
+    HS_REQUIRE((size_t)cap >= n, HS_ECAPACITY, "output too small");
+    HS_CHECK_HIP(hipMemcpy(host_out, src, n * sizeof(u64), hipMemcpyDeviceToHost));
+  });
+}
+
+int hs_encrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const int64_t* v, int64_t len, uint64_t seed,
+               void* stream, hs_ctvec** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks && m && out, HS_EINVAL, "null argument");
+    *out = nullptr;
+    HS_REQUIRE(ks->ctx == c && m->ctx == c, HS_EKEY, "handles from another context");
+    HS_REQUIRE(len == m->C, HS_EINVAL, "vector length must equal the number of matrix columns");
+    HS_REQUIRE(len == 0 || v, HS_EINVAL, "null vector");
+    hipStream_t st = S(stream);
+    const int G = (int)m->chunks.size();
+    const size_t N = c->N;
+    hs_ctvec* x = new_ctvec(c, G);
+    try {
+      if (G) {
+        DBuf coef(&c->pool, (size_t)G * N * sizeof(u64));
+        PackArgs pa{};
+        pa.va = m->d_va; pa.ci = m->d_ci; pa.v = v; pa.cp = m->d_cp; pa.chunk = m->d_chunk;
+        pa.out = coef.as<u64>(); pa.mode = 1;
+        launch_pack_encode(c, pa, G, st);
+        DBuf smp(&c->pool, (size_t)G * 3 * N * sizeof(int));
+        launch_sample_small(c, smp.as<int>(), G, 3 * (i64)N, seed, P_ENC_U, 0, 1, 0, st);
+        launch_sample_small(c, smp.as<int>() + N, G, 3 * (i64)N, seed, P_ENC_E0, 0, 1, 1, st);
+        launch_sample_small(c, smp.as<int>() + 2 * N, G, 3 * (i64)N, seed, P_ENC_E1, 0, 1, 1, st);
+        launch_encrypt(c, coef.as<u64>(), smp.as<int>(), ks->pk, x->d, G, st);
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+      }
+    } catch (...) {
+      hs_ctvec_destroy(x);
+      throw;
+    }
+    *out = x;
+  });
+}
+
+int hs_he_spmv(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* x, void* stream, hs_ctvec** y) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks && m && x && y, HS_EINVAL, "null argument");
+    *y = nullptr;
+    HS_REQUIRE(ks->ctx == c && m->ctx == c && x->ctx == c, HS_EKEY, "handles from another context");
+    HS_REQUIRE(x->n == (i64)m->chunks.size(), HS_EINVAL, "the vector must hold one ciphertext per chunk");
+    HS_REQUIRE(!m->encrypted, HS_EINVAL, "encrypted matrix values: not supported by this build of hs_he_spmv");
+    hipStream_t st = S(stream);
+    for (auto& v : g_counters) v = 0;
+    const int G = (int)m->chunks.size();
+    const int nP = (int)m->parts.size();
+    const size_t CW = ct_words(c);
+    hs_ctvec* res = new_ctvec(c, nP);
+    try {
+      // per chunk: totalSum program and buffers: V (product, contiguous over chunks) and, for
+      // chunks that rotate, WA, WB (accumulators) and TA, TB (intermediate rotations)
+      std::vector<std::vector<MicroOp>> progs(G);
+      int nlog = 0, nwt = 0;
+      std::vector<int> wt_base(G, -1);
+      for (int g = 0; g < G; g++) {
+        progs[g] = total_sum_program(c, m->chunks[g].h, m->chunks[g].c, &nlog);
+        if (progs[g].size() > 1) { wt_base[g] = nwt; nwt += 4; }
+      }
+      DBuf vbuf(&c->pool, (size_t)std::max(G, 1) * CW * sizeof(u64));
+      DBuf wtbuf(&c->pool, (size_t)std::max(nwt, 1) * CW * sizeof(u64));
+      auto buf = [&](int g, int id) -> u64* {
+        return id == 0 ? vbuf.as<u64>() + (size_t)g * CW : wtbuf.as<u64>() + (size_t)(wt_base[g] + id - 1) * CW;
+      };
+      // 1. slot-wise products of all chunks (HE-CMult)
+      launch_mul_plain(c, x->d, m->d_pt, vbuf.as<u64>(), G, c->L, st);
+      g_counters[2]++;
+      g_counters[3] += G;
+      // 2. totalSum, level by level across chunks
+      size_t nlev = 0;
+      for (auto& p : progs) nlev = std::max(nlev, p.size() - 1);
+      std::vector<std::vector<RotItem>> levels(nlev);
+      for (size_t lv = 0; lv < nlev; lv++) {
+        for (int g = 0; g < G; g++) {
+          if (lv + 1 >= progs[g].size()) continue;
+          const MicroOp& op = progs[g][lv];
+          RotItem it{};
+          it.in = buf(g, op.in);
+          it.out = buf(g, op.out);
+          it.addend = op.addend >= 0 ? buf(g, op.addend) : nullptr;
+          it.key = ks->gk[op.pow2];
+          it.galois = (u32)galois_pow2(c, op.pow2);
+          levels[lv].push_back(it);
+        }
+      }
+      run_rotation_levels(c, levels, st);
+      g_counters[1] = nlog;
+      // 3. masks and the per-partition sum
+      std::vector<const u64*> wptr(G);
+      for (int g = 0; g < G; g++) wptr[g] = buf(g, progs[g].back().in);
+      std::vector<int> pc0(nP), pnc(nP);
+      for (int p = 0; p < nP; p++) { pc0[p] = m->parts[p].chunk0; pnc[p] = m->parts[p].nchunks; }
+      DBuf dw(&c->pool, std::max(G, 1) * sizeof(u64*)), dpc0(&c->pool, nP * sizeof(int)), dpnc(&c->pool, nP * sizeof(int));
+      h2d(dw.as<const u64*>(), wptr.data(), G, st);
+      h2d(dpc0.as<int>(), pc0.data(), nP, st);
+      h2d(dpnc.as<int>(), pnc.data(), nP, st);
+      launch_mask_acc(c, dw.as<const u64*>(), c->prm.agg_mode == 0 ? m->d_mask : nullptr, dpc0.as<int>(), dpnc.as<int>(), res->d, nP, st);
+      g_counters[2]++;
+      g_counters[4] += c->prm.agg_mode == 0 ? G : 0;
+      HS_CHECK_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      hs_ctvec_destroy(res);
+      throw;
+    }
+    *y = res;
+  });
+}
+
+int hs_decrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* y, int64_t* out, int64_t rows,
+               void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks && m && y, HS_EINVAL, "null argument");
+    HS_REQUIRE(ks->ctx == c && m->ctx == c && y->ctx == c, HS_EKEY, "handles from another context");
+    HS_REQUIRE(rows == m->R, HS_EINVAL, "rows must equal the matrix row count");
+    HS_REQUIRE(y->n == (i64)m->parts.size(), HS_EINVAL, "one result ciphertext per row partition expected");
+    HS_REQUIRE(rows == 0 || out, HS_EINVAL, "null output");
+    hipStream_t st = S(stream);
+    const int nP = (int)m->parts.size();
+    if (!nP) return;
+    const size_t N = c->N;
+    DBuf X(&c->pool, (size_t)nP * c->L * N * sizeof(u64)), Mc(&c->pool, (size_t)nP * N * sizeof(u64));
+    launch_dec_phase(c, y->d, ks->sk, X.as<u64>(), nP, st);
+    launch_dec_round(c, X.as<u64>(), Mc.as<u64>(), nP, st);
+    std::vector<i64> pinfo(4ULL * nP);
+    i64 rm_off = 0;
+    for (int p = 0; p < nP; p++) {
+      const hs_part& P = m->parts[p];
+      pinfo[4 * p] = P.row0; pinfo[4 * p + 1] = P.rows; pinfo[4 * p + 2] = P.nz_rows; pinfo[4 * p + 3] = rm_off;
+      rm_off += P.rows;
+    }
+    DBuf dp(&c->pool, pinfo.size() * sizeof(i64));
+    h2d(dp.as<i64>(), pinfo.data(), pinfo.size(), st);
+    launch_decode_scatter(c, Mc.as<u64>(), m->d_rm, dp.as<i64>(), out, nP, st);
+    HS_CHECK_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int hs_ctvec_count(const hs_ctvec* v, int64_t* n) {
+  return guarded([&] {
+    HS_REQUIRE(v && n, HS_EINVAL, "null argument");
+    *n = v->n;
+  });
+}
+
+int hs_ct_export(const hs_ctvec* v, int64_t i, uint64_t* host_limbs, int64_t cap) {
+  return guarded([&] {
+    HS_REQUIRE(v && host_limbs, HS_EINVAL, "null argument");
+    HS_REQUIRE(i >= 0 && i < v->n, HS_EINVAL, "ciphertext index out of range");
+    const size_t n = ct_words(v->ctx);
+    HS_REQUIRE((size_t)cap >= n, HS_ECAPACITY, "output too small");
+    HS_CHECK_HIP(hipDeviceSynchronize());
+    HS_CHECK_HIP(hipMemcpy(host_limbs, v->d + i * n, n * sizeof(u64), hipMemcpyDeviceToHost));
+  });
+}
+
+int hs_ctvec_import(hs_ctx* c, const uint64_t* host_limbs, int64_t n, hs_ctvec** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && out && (n == 0 || host_limbs) && n >= 0, HS_EINVAL, "bad argument");
+    *out = nullptr;
+    const size_t CW = ct_words(c);
+    for (int64_t k = 0; k < n; k++)
+      for (int w = 0; w < 2; w++)
+        for (int l = 0; l < c->L; l++)
+          for (size_t i = 0; i < c->N; i++)
+            HS_REQUIRE(host_limbs[k * CW + ((size_t)w * c->L + l) * c->N + i] < c->mod[l], HS_EINVAL, "residue out of range");
+    hs_ctvec* v = new_ctvec(c, n);
+    if (n) {
+      hipError_t e = hipMemcpy(v->d, host_limbs, n * CW * sizeof(u64), hipMemcpyHostToDevice);
+      if (e != hipSuccess) { hs_ctvec_destroy(v); throw Error{HS_EDEVICE, hipGetErrorString(e)}; }
+    }
+    *out = v;
+  });
+}
+
+void hs_ctvec_destroy(hs_ctvec* v) {
+  if (!v) return;
+  if (v->d && v->owned) (void)hipFree(v->d);
+  delete v;
+}
+
+int hs_ntt(hs_ctx* c, uint64_t* d_limbs, int64_t n_polys, int mod0, int n_limbs, int inverse, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(c && (n_polys == 0 || d_limbs), HS_EINVAL, "null argument");
+    HS_REQUIRE(n_polys >= 0 && n_limbs >= 1, HS_EINVAL, "bad counts");
+    int m0 = mod0;
+    if (mod0 < 0) {
+      HS_REQUIRE(n_limbs == 1, HS_EINVAL, "the plaintext modulus is a single limb");
+      m0 = c->n_mod;
+    } else {
+      HS_REQUIRE(mod0 + n_limbs <= c->n_mod, HS_EINVAL, "modulus index out of range");
+    }
+    launch_ntt(c, d_limbs, n_polys * n_limbs, n_limbs, m0, inverse, S(stream));
+  });
+}
+
+int hs_mul_plain(hs_ctx* c, const hs_ctvec* in, const uint64_t* d_pt, void* stream, hs_ctvec** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && in && d_pt && out, HS_EINVAL, "null argument");
+    *out = nullptr;
+    hs_ctvec* r = new_ctvec(c, in->n);
+    launch_mul_plain(c, in->d, d_pt, r->d, in->n, 0, S(stream));
+    *out = r;
+  });
+}
+
+int hs_rotate(hs_ctx* c, const hs_keyset* ks, const hs_ctvec* in, int64_t k, void* stream, hs_ctvec** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks && in && out, HS_EINVAL, "null argument");
+    *out = nullptr;
+    HS_REQUIRE(ks->ctx == c && in->ctx == c, HS_EKEY, "handles from another context");
+    hipStream_t st = S(stream);
+    const size_t CW = ct_words(c);
+    const i64 half = (i64)c->N / 2;
+    const i64 kk = ((k % half) + half) % half;
+    hs_ctvec* r = new_ctvec(c, in->n);
+    try {
+      if (in->n) HS_CHECK_HIP(hipMemcpyAsync(r->d, in->d, in->n * CW * sizeof(u64), hipMemcpyDeviceToDevice, st));
+      DBuf tmp(&c->pool, std::max<i64>(in->n, 1) * CW * sizeof(u64));
+      u64* cur = r->d;
+      u64* other = tmp.as<u64>();
+      std::vector<std::vector<RotItem>> levels;
+      for (int i = 0; i + 1 < c->logn; i++) {
+        if (!((kk >> i) & 1)) continue;
+        std::vector<RotItem> items;
+        for (i64 g = 0; g < in->n; g++) {
+          RotItem it{};
+          it.in = cur + g * CW; it.out = other + g * CW; it.addend = nullptr;
+          it.key = ks->gk[i]; it.galois = (u32)galois_pow2(c, i);
+          items.push_back(it);
+        }
+        levels.push_back(items);
+        std::swap(cur, other);
+      }
+      run_rotation_levels(c, levels, st);
+      if (cur != r->d && in->n) HS_CHECK_HIP(hipMemcpyAsync(r->d, cur, in->n * CW * sizeof(u64), hipMemcpyDeviceToDevice, st));
+      HS_CHECK_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      hs_ctvec_destroy(r);
+      throw;
+    }
+    *out = r;
+  });
+}
+
+int hs_mul_ct(hs_ctx* c, const hs_keyset* ks, const hs_ctvec* a, const hs_ctvec* b, void* stream, hs_ctvec** out) {
+  return guarded([&] {
+    (void)c; (void)ks; (void)a; (void)b; (void)stream;
+    if (out) *out = nullptr;
+    throw Error{HS_EINVAL, "hs_mul_ct: not available in this build"};
+  });
+}
+
+int hs_last_counters(int64_t out[5]) {
+  return guarded([&] {
+    HS_REQUIRE(out, HS_EINVAL, "null argument");
+    for (int i = 0; i < 5; i++) out[i] = g_counters[i];
+  });
+}
+
+}  // extern "C"

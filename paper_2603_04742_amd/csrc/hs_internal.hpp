@@ -1,0 +1,186 @@
+// Internal host-side structures of the encrypted-SpMV library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/hespmv.h"
+
+namespace hs {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+typedef int64_t i64;
+typedef int32_t i32;
+typedef unsigned __int128 u128;
+
+// ------------------------------------------------------------------ errors
+void set_error(const std::string& msg);
+struct Error {
+  int code;
+  std::string msg;
+};
+#define HS_CHECK_HIP(expr)                                                              \
+  do {                                                                                  \
+    hipError_t _e = (expr);                                                             \
+    if (_e != hipSuccess)                                                               \
+      throw ::hs::Error{HS_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(_e)}; \
+  } while (0)
+#define HS_REQUIRE(cond, code, msg) \
+  do {                              \
+    if (!(cond)) throw ::hs::Error{code, msg}; \
+  } while (0)
+
+// ------------------------------------------------------------------ per-modulus device constants
+struct ModTab {
+  double q, qinv;        // modulus and fl(1/q)
+  double2 ninv;          // (N^-1 mod q, quotient)
+  const double2* fw;     // forward twiddles (psi^bitrev(i), fl(./q))
+  const double2* iv;     // inverse twiddles (psi^-bitrev(i), fl(./q))
+};
+
+// pair (w, fl(w/q)) for a constant w in [0, q)
+inline double2 make_const(u64 w, u64 q) { return double2{(double)w, (double)w / (double)q}; }
+
+// Device memory pool: size-bucketed free lists so that steady-state calls do not hipMalloc.
+class Pool {
+ public:
+  void* get(size_t bytes);
+  void put(void* p);
+  void release_all();
+  ~Pool() { release_all(); }
+
+ private:
+  std::mutex mu_;
+  std::multimap<size_t, void*> free_;
+  std::map<void*, size_t> size_of_;
+};
+
+// RAII device buffer from the pool
+struct DBuf {
+  Pool* pool = nullptr;
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() {}
+  DBuf(Pool* pl, size_t b) : pool(pl), p(b ? pl->get(b) : nullptr), bytes(b) {}
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept { *this = std::move(o); }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      reset();
+      pool = o.pool; p = o.p; bytes = o.bytes;
+      o.p = nullptr; o.bytes = 0;
+    }
+    return *this;
+  }
+  void reset() {
+    if (p && pool) pool->put(p);
+    p = nullptr; bytes = 0;
+  }
+  ~DBuf() { reset(); }
+  template <class T> T* as() const { return (T*)p; }
+};
+
+}  // namespace hs
+
+// ------------------------------------------------------------------ opaque handle definitions
+struct hs_ctx {
+  hs_params prm;
+  int logn = 0;
+  hs::u64 N = 0, t = 0;
+  int L = 0, K = 0, alpha = 0, dnum = 0, n_aux = 0, n_mod = 0;
+  int device = 0;
+  std::vector<hs::u64> mod;        // [L data][K special][n_aux tensor] ; index n_mod = t (host copy only)
+  std::vector<hs::u64> psi;        // smallest primitive 2N-th root per modulus (+ t last)
+  hs::ModTab* d_tab = nullptr;     // device [n_mod + 1], entry n_mod = plaintext modulus t
+  std::vector<hs::ModTab> h_tab;
+  double2* d_tw = nullptr;         // twiddle storage
+  hs::u32* d_slot_pos = nullptr;   // slot j -> index of the mod-t NTT output
+  // encryption: floor(Q/t) mod q_i as (w, w/q), Q mod t
+  double2* d_qdt = nullptr;
+  hs::u64 q_mod_t = 0;
+  // key switching: P mod q_i, P^-1 mod q_i (data primes)
+  double2* d_pmod = nullptr;
+  double2* d_pinv = nullptr;
+  // ModUp basis conversion, digit j with source primes D_j (alpha of them):
+  //   d_up_inv[j*alpha + a]             = (Q_j/q_a)^-1 mod q_a
+  //   d_up_hat[(j*alpha + a)*(L+K) + m] = (Q_j/q_a) mod mod[m]
+  double2* d_up_inv = nullptr;
+  double2* d_up_hat = nullptr;
+  // ModDown conversion from the K special primes to data prime i
+  double2* d_dn_inv = nullptr;     // [K]   (P/p_k)^-1 mod p_k
+  double2* d_dn_hat = nullptr;     // [K*L] (P/p_k) mod q_i
+  // decryption: Q-hat_i^-1 mod q_i, Q-hat_i as little-endian 64-bit words, Q, 2Q
+  int dec_words = 0;
+  double2* d_dec_inv = nullptr;
+  hs::u64* d_dec_hat = nullptr;    // [L][dec_words]
+  hs::u64* d_dec_q = nullptr;      // [dec_words] Q
+  hs::Pool pool;
+};
+
+struct hs_keyset {
+  hs_ctx* ctx = nullptr;
+  hs::u64 seed = 0;
+  hs::u64* sk = nullptr;        // [n_mod][N] NTT form, canonical
+  hs::u64* pk = nullptr;        // [2][L][N]
+  std::vector<hs::u64*> gk;     // per power-of-two rotation i: [2][dnum][L+K][N]
+  hs::u64* rk = nullptr;        // relinearisation key, same layout
+  size_t ksk_words = 0;
+};
+
+struct hs_chunk {
+  int part;        // row partition
+  int start, c;    // first CSSC column, number of columns
+  hs::i64 h;       // height (rows); slot k <-> (block k / h, sorted row k % h)
+};
+
+struct hs_part {
+  hs::i64 row0, rows;   // original rows [row0, row0 + rows)
+  int Lw;               // CSSC columns (max nonzeros in a row)
+  hs::i64 nnz_off;      // offset of this partition's VA/CI in the matrix arrays
+  hs::i64 cp_off;       // offset of this partition's CP in the matrix CP array
+  hs::i64 nz_rows;      // rows with at least one nonzero (= NNZ of CSSC column 0)
+  int chunk0, nchunks;
+};
+
+struct hs_matrix {
+  hs_ctx* ctx = nullptr;
+  hs::i64 R = 0, C = 0, nnz = 0;
+  int encrypted = 0;
+  std::vector<hs_part> parts;
+  std::vector<hs_chunk> chunks;
+  std::vector<hs::i64> h_cp;     // all partitions' CP arrays, concatenated
+  std::vector<hs::i32> h_rm;     // row map per partition (local rows), concatenated = R entries
+  hs::i64* d_cp = nullptr;
+  hs::i32* d_rm = nullptr;
+  hs::i64* d_va = nullptr;       // CSSC values (nnz)
+  hs::i32* d_ci = nullptr;       // CSSC column indices (nnz)
+  hs::i64* d_chunk = nullptr;    // per chunk: (start, c, h, cp_off) for device kernels
+  hs::u64* d_pt = nullptr;       // per chunk: plaintext [L][N] or ciphertext [2][L][N]
+  hs::u64* d_mask = nullptr;     // per chunk: mask plaintext [L][N] (paper aggregation)
+};
+
+struct hs_ctvec {
+  hs_ctx* ctx = nullptr;
+  hs::i64 n = 0;                 // ciphertexts
+  hs::u64* d = nullptr;          // [n][2][L][N] NTT form, canonical
+  bool owned = true;
+};
+
+namespace hs {
+// host math (params.cpp)
+bool is_prime_u64(u64 n);
+std::vector<u64> primes_1_mod_2n(u64 N, int bits, int count);
+u64 smallest_root_2n(u64 q, u64 N);
+u64 pow_mod(u64 b, u64 e, u64 m);
+u64 mul_mod(u64 a, u64 b, u64 m);
+u64 inv_mod(u64 a, u64 q);
+void build_ctx(hs_ctx* c);
+void free_ctx(hs_ctx* c);
+size_t ct_words(const hs_ctx* c);
+}  // namespace hs

@@ -1,0 +1,743 @@
+// HIP kernels (gfx950) of the encrypted-SpMV library.
+//
+// Layout in HBM: polynomials limb-major, [poly][limb][N] u64 residues in [0, q) (NTT form unless
+// stated); scratch between kernels of one key switch is held as balanced doubles.  A limb-level
+// transform runs in one workgroup with the whole limb resident in LDS (N <= 16384: 136 KiB with
+// padding) and radix-16 register rounds (hs_device.hpp).
+#include "hs_device.hpp"
+#include "kernels.hpp"
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+
+namespace hs {
+
+__constant__ u64 c_cdt[20];
+
+#define SMEM() extern __shared__ double smem[]
+
+__device__ __forceinline__ ModD mod_of(const ModTab& t) { return ModD{t.q, t.qinv}; }
+
+// Galois automorphism X -> X^g as an index map on NTT-form limbs:
+// NTT(sigma_g a)[k] = NTT(a)[pi(k)], 2 bitrev(pi(k)) + 1 = g (2 bitrev(k) + 1) mod 2N.
+__device__ __forceinline__ u32 galois_index(u32 k, u32 g, int logn) {
+  const u32 n2m = (2u << logn) - 1;
+  const u32 e = 2 * brev_bits(k, logn) + 1;
+  const u32 e2 = (u32)(((u64)g * e) & n2m);
+  return brev_bits((e2 - 1) >> 1, logn);
+}
+
+__device__ __forceinline__ void store_canon(u64* out, const double* s, int n, ModD m, int nt) {
+  for (int i = threadIdx.x; i < n; i += nt) out[i] = d2u(canon(s[lpad(i)], m));
+}
+
+// ------------------------------------------------------------------ standalone NTT
+// One workgroup per limb: poly b / nl, limb b % nl, modulus index mod0 + limb.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_ntt(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  const int n = 1 << logn;
+  const int b = blockIdx.x;
+  const ModTab t = tab[mod0 + b % nl];
+  const ModD m = mod_of(t);
+  u64* p = data + (size_t)b * n;
+  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = u2d(p[i]);
+  __syncthreads();
+  if (inverse) lds_ntt_inv<NT>(smem, logn, t.iv, t.ninv, m);
+  else lds_ntt_fwd<NT>(smem, logn, t.fw, m);
+  store_canon(p, smem, n, m, NT);
+}
+
+// ------------------------------------------------------------------ sampling
+// Small-integer samples (int32) of nobj polynomials: object o uses stream (seed, purpose,
+// index0 + o * index_step) and is written at out + o * obj_stride.  kind 0: ternary, word i -> (w mod 3) - 1.  kind 1: discrete Gaussian by CDT,
+// 64 bits (words 2i, 2i+1) per coefficient: top bit sign, low 63 bits r, |e| = #{k: T[k] <= r}.
+__global__ void k_sample_small(int* out, int nobj, i64 obj_stride, u64 seed, u32 purpose, u64 index0, u64 index_step, int kind, int logn) {
+  const int n = 1 << logn;
+  const int per = kind == 0 ? 16 : 8;
+  const int nblk = n / per;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= nobj * nblk) return;
+  const int o = gid / nblk, blk = gid % nblk;
+  u32 w[16];
+  chacha_block(seed, purpose, index0 + (u64)o * index_step, (u32)blk, w);
+  int* dst = out + (size_t)o * obj_stride + (size_t)blk * per;
+  if (kind == 0) {
+#pragma unroll
+    for (int i = 0; i < 16; i++) dst[i] = (int)(w[i] % 3u) - 1;
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; i++) {
+      const u64 x = (u64)w[2 * i] | ((u64)w[2 * i + 1] << 32);
+      const u64 r = x & 0x7fffffffffffffffULL;
+      int mag = 0;
+#pragma unroll
+      for (int k = 0; k < 20; k++) mag += (c_cdt[k] <= r) ? 1 : 0;
+      dst[i] = (x >> 63) ? -mag : mag;
+    }
+  }
+}
+
+// 128-bit little-endian value (w0..w3) mod q, q < 2^50.
+__device__ __forceinline__ u64 u128_mod(u32 w0, u32 w1, u32 w2, u32 w3, u64 q, double2 r64, ModD m) {
+  const u64 lo = (u64)w0 | ((u64)w1 << 32), hi = (u64)w2 | ((u64)w3 << 32);
+  const double h = u2d(hi % q), l = u2d(lo % q);
+  return d2u(canon(mul_tw(h, r64.x, r64.y, m) + l, m));  // hi * (2^64 mod q) + lo
+}
+
+// ------------------------------------------------------------------ keys
+// Secret key: ternary s (purpose 1, index 0) in NTT form for every modulus of the chain.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_sk_ntt(u64* sk, const int* s_coef, const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  const int n = 1 << logn;
+  const ModTab t = tab[blockIdx.x];
+  const ModD m = mod_of(t);
+  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = (double)s_coef[i];
+  __syncthreads();
+  lds_ntt_fwd<NT>(smem, logn, t.fw, m);
+  store_canon(sk + (size_t)blockIdx.x * n, smem, n, m, NT);
+}
+
+// One limb of a key-switching (or public) key:  b = NTT(e) - a s + [in digit] P s',  a uniform in
+// NTT form from stream (seed, purpose_a, idx_a), e from the Gaussian samples e_coef.
+// s' mode: 0 none (public key), 1 Galois sigma_g(s) (NTT-domain index map), 2 s^2.
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_ksk_limb(const KskArgs* __restrict__ args, const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  const int n = 1 << logn;
+  const KskArgs A = args[blockIdx.x];
+  const ModTab t = tab[A.mod_index];
+  const ModD m = mod_of(t);
+  const u64 q = (u64)t.q;
+  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = (double)A.e_coef[i];
+  __syncthreads();
+  lds_ntt_fwd<NT>(smem, logn, t.fw, m);
+  // each thread draws whole ChaCha blocks: block k gives coefficients 4k .. 4k+3
+  for (int blk = threadIdx.x; blk < n / 4; blk += NT) {
+    u32 w[16];
+    chacha_block(A.seed, A.purpose_a, A.idx_a, (u32)blk, w);
+#pragma unroll
+    for (int c = 0; c < 4; c++) {
+      const int i = blk * 4 + c;
+      const u64 av = u128_mod(w[4 * c], w[4 * c + 1], w[4 * c + 2], w[4 * c + 3], q, A.r64, m);
+      const double ad = u2d(av);
+      const double s = u2d(A.sk[i]);
+      double v = smem[lpad(i)] - mulmod(ad, s, m);
+      if (A.sprime_mode == 1) {
+        const double sp = u2d(A.sk[galois_index((u32)i, A.galois, logn)]);
+        v += mul_tw(sp, A.pfac.x, A.pfac.y, m);
+      } else if (A.sprime_mode == 2) {
+        const double s2 = mulmod(s, s, m);
+        v += mul_tw(s2, A.pfac.x, A.pfac.y, m);
+      }
+      A.b[i] = d2u(canon(v, m));
+      A.a[i] = av;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ slot packing + encoding
+// Builds the slot vector of one plaintext and applies the inverse mod-t NTT (batch encoding):
+// coefficients m in [0, t).  Slot k < h*c of chunk (start, c, h): block b = k / h, sorted row
+// p = k % h; source value at CSSC entry CP[start + b] + p when p < NNZ[start + b], else 0.
+//   mode 0: matrix values va[e];  mode 1: vector values v[ci[e]];  mode 2: mask (1 for k < h).
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_pack_encode(PackArgs A, const u32* __restrict__ slot_pos, const ModTab* __restrict__ tab, int tmod, int logn) {
+  SMEM();
+  const int n = 1 << logn;
+  const int g = blockIdx.x;
+  const i64* cd = A.chunk + 8 * g;  // (start, c, h, cp_off, nnz_off, part, -, -)
+  const i64 start = cd[0], cols = cd[1], h = cd[2], cpo = cd[3], nzo = cd[4];
+  const ModTab t = tab[tmod];
+  const ModD m = mod_of(t);
+  const i64 tq = (i64)t.q;
+  for (int k = threadIdx.x; k < n; k += NT) {
+    i64 val = 0;
+    if (A.mode == 2) {
+      val = (k < h) ? 1 : 0;
+    } else if (k < h * cols && k < n / 2) {
+      {
+        const i64 b = k / h, p = k % h;
+        const i64 c0 = A.cp[cpo + start + b], c1 = A.cp[cpo + start + b + 1];
+        if (p < c1 - c0) {
+          const i64 e = nzo + c0 + p;
+          val = (A.mode == 0) ? A.va[e] : A.v[A.ci[e]];
+        }
+      }
+    }
+    val %= tq;
+    if (val < 0) val += tq;
+    smem[lpad(slot_pos[k])] = (double)val;
+  }
+  __syncthreads();
+  lds_ntt_inv<NT>(smem, logn, t.iv, t.ninv, m);
+  store_canon(A.out + (size_t)g * n, smem, n, m, NT);
+}
+
+// Plaintext for ct x pt: centered lift of the mod-t coefficients (c > (t-1)/2 -> c - t), NTT mod
+// data prime `limb`.  grid = (L, n_plain).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_plain_ntt(const u64* __restrict__ coef, u64* out, int L, u64 t, const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  const int n = 1 << logn;
+  const int l = blockIdx.x, g = blockIdx.y;
+  const ModTab tb = tab[l];
+  const ModD m = mod_of(tb);
+  const u64* c = coef + (size_t)g * n;
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const u64 v = c[i];
+    smem[lpad(i)] = v > (t - 1) / 2 ? (double)v - (double)t : (double)v;
+  }
+  __syncthreads();
+  lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
+  store_canon(out + ((size_t)g * L + l) * n, smem, n, m, NT);
+}
+
+// ------------------------------------------------------------------ encryption
+// c0 = pk0 NTT(u) + NTT(e0 + floor(Q m / t + 1/2)),  c1 = pk1 NTT(u) + NTT(e1), per limb.
+// floor(Q m / t + 1/2) = floor(Q/t) m + floor(((Q mod t) m + floor(t/2)) / t).
+// samples: [n_ct][3][N] int32 (u, e0, e1).  grid = (L, n_ct).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_encrypt(const u64* __restrict__ mcoef, const int* __restrict__ samples, const u64* __restrict__ pk,
+                                                u64* out, int L, u64 t, u64 q_mod_t, const double2* __restrict__ qdt,
+                                                const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  constexpr int PER = 16;  // n / NT <= 16 for every ring size
+  const int n = 1 << logn;
+  const int l = blockIdx.x, g = blockIdx.y;
+  const ModTab tb = tab[l];
+  const ModD m = mod_of(tb);
+  const int* u = samples + (size_t)g * 3 * n;
+  const int* e0 = u + n;
+  const int* e1 = u + 2 * n;
+  const u64* mc = mcoef + (size_t)g * n;
+  u64* c0 = out + ((size_t)g * 2 * L + l) * n;
+  u64* c1 = out + ((size_t)g * 2 * L + L + l) * n;
+  const u64* p0 = pk + (size_t)l * n;
+  const u64* p1 = pk + ((size_t)L + l) * n;
+  double U[PER];
+  // NTT(u)
+  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = (double)u[i];
+  __syncthreads();
+  lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = threadIdx.x + k * NT;
+    if (i < n) U[k] = smem[lpad(i)];
+  }
+  __syncthreads();
+  // c1
+  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = (double)e1[i];
+  __syncthreads();
+  lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = threadIdx.x + k * NT;
+    if (i < n) c1[i] = d2u(canon(mulmod(reduce(U[k], m), u2d(p1[i]), m) + smem[lpad(i)], m));
+  }
+  __syncthreads();
+  // c0
+  const double2 qd = qdt[l];
+  for (int i = threadIdx.x; i < n; i += NT) {
+    const u64 mv = mc[i];
+    const double d1 = mul_tw((double)mv, qd.x, qd.y, m);
+    const double d2 = (double)((q_mod_t * mv + t / 2) / t);
+    smem[lpad(i)] = reduce((double)e0[i] + d1 + d2, m);
+  }
+  __syncthreads();
+  lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = threadIdx.x + k * NT;
+    if (i < n) c0[i] = d2u(canon(mulmod(reduce(U[k], m), u2d(p0[i]), m) + smem[lpad(i)], m));
+  }
+}
+
+// ------------------------------------------------------------------ slot-wise products
+// out[g] = x[g] (.) pt[g], both polynomials; x, out: [n][2][L][N]; pt: [n][L][N].
+__global__ void k_mul_plain(const u64* __restrict__ x, const u64* __restrict__ pt, u64* out, i64 n_ct, int L,
+                            int pt_stride_ct, const ModTab* __restrict__ tab, int logn) {
+  const i64 n = 1 << logn;
+  const i64 total = n_ct * 2 * L * n;
+  for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
+    const i64 k = idx & (n - 1);
+    const i64 r = idx >> logn;         // (g, w, l)
+    const int l = (int)(r % L);
+    const i64 g = r / (2 * L);
+    const ModTab tb = tab[l];
+    const ModD m = mod_of(tb);
+    const double a = u2d(x[idx]);
+    const double b = u2d(pt[(g * pt_stride_ct + l) * n + k]);
+    out[idx] = d2u(canon(mulmod(a, b, m), m));
+  }
+}
+
+// res[P] = sum over the chunks g of partition P of w[g] (.) mask[g]   (mask == nullptr: plain sum)
+__global__ void k_mask_acc(const u64* const* __restrict__ w, const u64* __restrict__ mask, const int* __restrict__ part_chunk0,
+                           const int* __restrict__ part_nchunks, u64* res, int L, const ModTab* __restrict__ tab, int logn) {
+  const int n = 1 << logn;
+  const int P = blockIdx.y;
+  const int per_poly = 2 * L * n;
+  const int g0 = part_chunk0[P], ng = part_nchunks[P];
+  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < per_poly; idx += gridDim.x * blockDim.x) {
+    const int k = idx & (n - 1);
+    const int l = (idx >> logn) % L;
+    const ModTab tb = tab[l];
+    const ModD m = mod_of(tb);
+    double acc = 0.0;
+    for (int g = g0; g < g0 + ng; g++) {
+      double v = u2d(w[g][idx]);
+      if (mask) v = mulmod(v, u2d(mask[((size_t)g * L + l) * n + k]), m);
+      acc = reduce(acc + v, m);
+    }
+    res[(size_t)P * per_poly + idx] = d2u(canon(acc, m));
+  }
+}
+
+// ------------------------------------------------------------------ rotation: key switching
+// Batched power-of-two rotations.  Item b: out = (sigma_g(c0) + ks0, ks1) [+ addend], where
+// (ks0, ks1) = KeySwitch(sigma_g(c1)) under the key for sigma_g(s) -> s.
+//  1. k_rot_intt      sigma_g(c1) limbs (NTT-domain gather) -> coefficient form D[b][l] (u64)
+//  2. k_modup_ip      per target modulus m and digit group: for each digit j,
+//                     ext = (m in D_j) ? sigma_g(c1)_m : NTT_m(Conv_{D_j -> m}(D[b][D_j])),
+//                     acc_w += ext (.) ksk_w[j][m]  -> ACC[b][dg][w][m] (balanced doubles)
+//  3. k_moddown_intt  special limbs of sum_dg ACC -> coefficient form PC[b][w][k]
+//  4. k_moddown_ntt   conv_i = NTT_i(Conv_{P -> q_i}(PC)), out_w,i = (acc_w,i - conv_i) P^-1
+//                     (+ sigma_g(c0)_i for w = 0) (+ addend_w,i)
+template <int NT>
+__global__ void __launch_bounds__(NT) k_rot_intt(const RotItem* __restrict__ items, u64* D, int L, const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  const int n = 1 << logn;
+  const int l = blockIdx.x, b = blockIdx.y;
+  const RotItem it = items[b];
+  const ModTab tb = tab[l];
+  const ModD m = mod_of(tb);
+  const u64* c1 = it.in + ((size_t)L + l) * n;
+  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = u2d(c1[galois_index((u32)i, it.galois, logn)]);
+  __syncthreads();
+  lds_ntt_inv<NT>(smem, logn, tb.iv, tb.ninv, m);
+  store_canon(D + ((size_t)b * L + l) * n, smem, n, m, NT);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict__ D, double* ACC, KsShape S,
+                                                 const double2* __restrict__ up_inv, const double2* __restrict__ up_hat,
+                                                 const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  const int n = 1 << logn;
+  const int mi = blockIdx.x, b = blockIdx.y, dg = blockIdx.z;
+  const int LK = S.L + S.K;
+  const RotItem it = items[b];
+  const ModTab tb = tab[mi];
+  const ModD m = mod_of(tb);
+  const int j0 = dg * S.dpg, j1 = min(S.dnum, j0 + S.dpg);
+  // the accumulators live in the output rows; each element is owned by one thread throughout
+  double* o0 = ACC + ((((size_t)b * S.ndg + dg) * 2 + 0) * LK + mi) * n;
+  double* o1 = ACC + ((((size_t)b * S.ndg + dg) * 2 + 1) * LK + mi) * n;
+  for (int j = j0; j < j1; j++) {
+    const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha);
+    const bool own = (mi >= lo && mi < hi);
+    if (own) {
+      const u64* c1 = it.in + ((size_t)S.L + mi) * n;
+      for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = u2d(c1[galois_index((u32)i, it.galois, logn)]);
+      __syncthreads();
+    } else {
+      // fast basis conversion from the digit's primes to modulus mi
+      for (int i = threadIdx.x; i < n; i += NT) {
+        double acc = 0.0;
+        for (int a = 0; a < hi - lo; a++) {
+          const double x = u2d(D[((size_t)b * S.L + lo + a) * n + i]);
+          if (hi - lo > 1) {
+            const ModTab sa = tab[lo + a];
+            const ModD ms = mod_of(sa);
+            const double2 ci = up_inv[j * S.alpha + a];
+            const double y = canon(mul_tw(x, ci.x, ci.y, ms), ms);
+            const double2 hm = up_hat[((size_t)j * S.alpha + a) * LK + mi];
+            acc = reduce(acc + mul_tw(y, hm.x, hm.y, m), m);
+          } else {
+            acc = reduce(x, m);  // a single source prime: [x]_q as an integer, taken mod mi
+          }
+        }
+        smem[lpad(i)] = acc;
+      }
+      __syncthreads();
+      lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
+    }
+    const u64* kb = it.key + (((size_t)0 * S.dnum + j) * LK + mi) * n;
+    const u64* ka = it.key + (((size_t)1 * S.dnum + j) * LK + mi) * n;
+    const bool first = (j == j0);
+    for (int i = threadIdx.x; i < n; i += NT) {
+      const double e = reduce(smem[lpad(i)], m);
+      double v0 = mulmod(e, u2d(kb[i]), m);
+      double v1 = mulmod(e, u2d(ka[i]), m);
+      if (!first) { v0 = reduce(v0 + o0[i], m); v1 = reduce(v1 + o1[i], m); }
+      o0[i] = v0;
+      o1[i] = v1;
+    }
+    __syncthreads();
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_moddown_intt(const double* __restrict__ ACC, double* PC, KsShape S, const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  const int n = 1 << logn;
+  const int k = blockIdx.x, w = blockIdx.y, b = blockIdx.z;
+  const int LK = S.L + S.K;
+  const int mi = S.L + k;
+  const ModTab tb = tab[mi];
+  const ModD m = mod_of(tb);
+  for (int i = threadIdx.x; i < n; i += NT) {
+    double acc = 0.0;
+    for (int dg = 0; dg < S.ndg; dg++) acc += ACC[((((size_t)b * S.ndg + dg) * 2 + w) * LK + mi) * n + i];
+    smem[lpad(i)] = canon(acc, m);
+  }
+  __syncthreads();
+  lds_ntt_inv<NT>(smem, logn, tb.iv, tb.ninv, m);
+  double* o = PC + (((size_t)b * 2 + w) * S.K + k) * n;
+  for (int i = threadIdx.x; i < n; i += NT) o[i] = canon(smem[lpad(i)], m);
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k_moddown_ntt(const RotItem* __restrict__ items, const double* __restrict__ ACC, const double* __restrict__ PC,
+                                                    KsShape S, const double2* __restrict__ dn_inv, const double2* __restrict__ dn_hat,
+                                                    const double2* __restrict__ pinv, const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  constexpr int PER = 16;
+  const int n = 1 << logn;
+  const int i_l = blockIdx.x, w = blockIdx.y, b = blockIdx.z;
+  const int LK = S.L + S.K;
+  const RotItem it = items[b];
+  const ModTab tb = tab[i_l];
+  const ModD m = mod_of(tb);
+  for (int i = threadIdx.x; i < n; i += NT) {
+    double acc = 0.0;
+    for (int k = 0; k < S.K; k++) {
+      const double x = PC[(((size_t)b * 2 + w) * S.K + k) * n + i];
+      if (S.K == 1) {
+        acc = x;  // [x]_p as an integer in [0, p), taken mod q_i
+      } else {
+        const ModTab sp = tab[S.L + k];
+        const ModD ms = mod_of(sp);
+        const double2 ci = dn_inv[k];
+        const double y = canon(mul_tw(x, ci.x, ci.y, ms), ms);
+        const double2 hm = dn_hat[(size_t)k * S.L + i_l];
+        acc = reduce(acc + mul_tw(y, hm.x, hm.y, m), m);
+      }
+    }
+    smem[lpad(i)] = reduce(acc, m);
+  }
+  __syncthreads();
+  lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
+  const double2 pv = pinv[i_l];
+  const u64* c0 = it.in + (size_t)i_l * n;
+  u64* out = it.out + ((size_t)w * S.L + i_l) * n;
+  const u64* add = it.addend ? it.addend + ((size_t)w * S.L + i_l) * n : nullptr;
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int i = threadIdx.x + k * NT;
+    if (i < n) {
+      double acc = 0.0;
+      for (int dg = 0; dg < S.ndg; dg++) acc += ACC[((((size_t)b * S.ndg + dg) * 2 + w) * LK + i_l) * n + i];
+      double v = mul_tw(reduce(acc - smem[lpad(i)], m), pv.x, pv.y, m);
+      if (w == 0) v += u2d(c0[galois_index((u32)i, it.galois, logn)]);
+      if (add) v += u2d(add[i]);
+      out[i] = d2u(canon(v, m));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ decryption
+// phase x = c0 + c1 s in coefficient form, per limb: X[g][l][N] (u64).  grid = (L, n_ct).
+template <int NT>
+__global__ void __launch_bounds__(NT) k_dec_phase(const u64* __restrict__ ct, const u64* __restrict__ sk, u64* X, int L, const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  const int n = 1 << logn;
+  const int l = blockIdx.x, g = blockIdx.y;
+  const ModTab tb = tab[l];
+  const ModD m = mod_of(tb);
+  const u64* c0 = ct + ((size_t)g * 2 * L + l) * n;
+  const u64* c1 = ct + ((size_t)g * 2 * L + L + l) * n;
+  const u64* s = sk + (size_t)l * n;
+  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = canon(u2d(c0[i]) + mulmod(u2d(c1[i]), u2d(s[i]), m), m);
+  __syncthreads();
+  lds_ntt_inv<NT>(smem, logn, tb.iv, tb.ninv, m);
+  store_canon(X + ((size_t)g * L + l) * n, smem, n, m, NT);
+}
+
+// m = round(t x / Q) mod t from the residues x_i (exact):  with y_i = [x_i Qhat_i^-1]_{q_i},
+// t y_i = a_i q_i + r_i, round(t x / Q) = sum a_i + round(sum_i r_i Qhat_i / Q) (mod t).
+__global__ void k_dec_round(const u64* __restrict__ X, u64* M, int n_ct, int L, u64 t, const double2* __restrict__ dinv,
+                            const u64* __restrict__ dhat, const u64* __restrict__ dq, int W, const ModTab* __restrict__ tab, int logn) {
+  const int n = 1 << logn;
+  const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= n_ct * n) return;
+  const int g = gid / n, k = gid % n;
+  u64 S[16];
+  for (int w = 0; w < W; w++) S[w] = 0;
+  u64 asum = 0;
+  for (int i = 0; i < L; i++) {
+    const ModTab tb = tab[i];
+    const ModD m = mod_of(tb);
+    const u64 q = (u64)tb.q;
+    const double x = u2d(X[((size_t)g * L + i) * n + k]);
+    const u64 y = d2u(canon(mul_tw(x, dinv[i].x, dinv[i].y, m), m));
+    // t*y = a*q + r, 0 <= r < q: estimate a in floating point, fix with exact 64-bit wrap-around
+    u64 a = (u64)((double)y * ((double)t / (double)q));
+    i64 r = (i64)(t * y - a * q);
+    while (r < 0) { r += (i64)q; a--; }
+    while (r >= (i64)q) { r -= (i64)q; a++; }
+    asum += a;
+    // S += r * Qhat_i
+    u64 carry = 0;
+    for (int w = 0; w < W; w++) {
+      const u64 h = dhat[(size_t)i * W + w];
+      const u64 lo = h * (u64)r;
+      const u64 hi = __umul64hi(h, (u64)r);
+      u64 s1 = S[w] + lo;
+      u64 c1 = s1 < lo;
+      u64 s2 = s1 + carry;
+      u64 c2 = s2 < carry;
+      S[w] = s2;
+      carry = hi + c1 + c2;
+    }
+  }
+  // T = 2 S + Q; kq = floor(T / 2Q) by repeated subtraction (kq <= L)
+  u64 T[16], twoq[16];
+  {
+    u64 sh = 0, cadd = 0, shq = 0;
+    for (int w = 0; w < W; w++) {
+      const u64 s2 = (S[w] << 1) | sh;
+      sh = S[w] >> 63;
+      const u64 v = s2 + dq[w];
+      const u64 c1 = v < s2;
+      const u64 v2 = v + cadd;
+      const u64 c2 = v2 < cadd;
+      T[w] = v2;
+      cadd = c1 + c2;
+      twoq[w] = (dq[w] << 1) | shq;
+      shq = dq[w] >> 63;
+    }
+  }
+  u64 kq = 0;
+  for (int guard = 0; guard <= L + 1; guard++) {
+    bool ge = true;
+    for (int w = W - 1; w >= 0; w--) {
+      if (T[w] != twoq[w]) { ge = T[w] > twoq[w]; break; }
+    }
+    if (!ge) break;
+    u64 br = 0;
+    for (int w = 0; w < W; w++) {
+      const u64 a = T[w], bq = twoq[w];
+      const u64 d = a - bq;
+      const u64 b1 = a < bq;
+      const u64 d2 = d - br;
+      const u64 b2 = d < br;
+      T[w] = d2;
+      br = b1 | b2;
+    }
+    kq++;
+  }
+  M[gid] = (asum + kq) % t;
+}
+
+// Decode (forward mod-t NTT), take slot p for the sorted rows of partition P, scatter with the row
+// map.  One workgroup per partition.
+template <int NT>
+__global__ void __launch_bounds__(NT) k_decode_scatter(const u64* __restrict__ M, const u32* __restrict__ slot_pos, const int* __restrict__ rm,
+                                                       const i64* __restrict__ pinfo, i64* y, int tmod, const ModTab* __restrict__ tab, int logn) {
+  SMEM();
+  const int n = 1 << logn;
+  const int P = blockIdx.x;
+  const ModTab tb = tab[tmod];
+  const ModD m = mod_of(tb);
+  const i64 t = (i64)tb.q;
+  const u64* mc = M + (size_t)P * n;
+  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = u2d(mc[i]);
+  __syncthreads();
+  lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
+  const i64 row0 = pinfo[4 * P], rows = pinfo[4 * P + 1], nz = pinfo[4 * P + 2], rm0 = pinfo[4 * P + 3];
+  for (i64 p = threadIdx.x; p < rows; p += NT) {
+    i64 v = 0;
+    if (p < nz) {
+      v = (i64)d2u(canon(smem[lpad(slot_pos[p])], m));
+      if (v > t / 2) v -= t;
+    }
+    y[row0 + rm[rm0 + p]] = v;
+  }
+}
+
+// ------------------------------------------------------------------ CSSC scatter (App. B)
+// Row r (global) of partition P = r / s goes to sorted position rank[r]; its j-th nonzero lands at
+// CSSC entry cp[P][j] + rank[r] of that partition.
+__global__ void k_cssc_scatter(const i64* __restrict__ row_ptr, const int* __restrict__ col, const i64* __restrict__ val,
+                               const int* __restrict__ rank, const i64* __restrict__ cp, const i64* __restrict__ part_cp_off,
+                               const i64* __restrict__ part_nnz_off, i64 R, i64 s, i64* va, int* ci) {
+  const i64 r = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const i64 P = r / s;
+  const i64 k0 = row_ptr[r], k1 = row_ptr[r + 1];
+  const i64 cpo = part_cp_off[P], nzo = part_nnz_off[P];
+  for (i64 k = k0; k < k1; k++) {
+    const i64 pos = nzo + cp[cpo + (k - k0)] + rank[r];
+    va[pos] = val[k];
+    ci[pos] = col[k];
+  }
+}
+
+// CSR validation: col in [0, C) and strictly ascending within each row; sets *bad on violation.
+__global__ void k_csr_check(const i64* __restrict__ row_ptr, const int* __restrict__ col, i64 R, i64 C, int* bad) {
+  const i64 r = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const i64 k0 = row_ptr[r], k1 = row_ptr[r + 1];
+  int prev = -1;
+  for (i64 k = k0; k < k1; k++) {
+    const int c = col[k];
+    if (c < 0 || c >= C || c <= prev) { atomicOr(bad, 1); return; }
+    prev = c;
+  }
+}
+
+// ------------------------------------------------------------------ host launchers
+static int nt_for(int logn) { return logn >= 14 ? 1024 : (logn <= 10 ? 64 : (1 << (logn - 4))); }
+static size_t lds_bytes(int logn) { return (size_t)lds_doubles(1 << logn) * sizeof(double); }
+
+// Dynamic LDS above the default limit needs the attribute once per kernel instantiation.
+static std::mutex g_attr_mu;
+static std::map<const void*, size_t> g_attr_set;
+static void ensure_lds(const void* f, size_t bytes) {
+  std::lock_guard<std::mutex> g(g_attr_mu);
+  auto it = g_attr_set.find(f);
+  if (it != g_attr_set.end() && it->second >= bytes) return;
+  HS_CHECK_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  g_attr_set[f] = bytes;
+}
+
+#define HS_LAUNCH_NT(NTV, KERNEL, GRID, STREAM, ...)                                               \
+  case NTV:                                                                                         \
+    ensure_lds((const void*)KERNEL<NTV>, _lds);                                                     \
+    hipLaunchKernelGGL(KERNEL<NTV>, GRID, dim3(NTV), _lds, STREAM, __VA_ARGS__);                    \
+    break;
+#define HS_DISPATCH_NT(logn, KERNEL, GRID, STREAM, ...)                                             \
+  do {                                                                                              \
+    const size_t _lds = lds_bytes(logn);                                                            \
+    if (_lds > 160 * 1024) throw Error{HS_EPARAM, "ring too large for the LDS-resident transform"}; \
+    switch (nt_for(logn)) {                                                                         \
+      HS_LAUNCH_NT(1024, KERNEL, GRID, STREAM, __VA_ARGS__)                                         \
+      HS_LAUNCH_NT(512, KERNEL, GRID, STREAM, __VA_ARGS__)                                          \
+      HS_LAUNCH_NT(256, KERNEL, GRID, STREAM, __VA_ARGS__)                                          \
+      HS_LAUNCH_NT(128, KERNEL, GRID, STREAM, __VA_ARGS__)                                          \
+      HS_LAUNCH_NT(64, KERNEL, GRID, STREAM, __VA_ARGS__)                                           \
+      default: throw Error{HS_EPARAM, "unsupported ring size"};                                     \
+    }                                                                                               \
+    HS_CHECK_HIP(hipGetLastError());                                                                \
+  } while (0)
+
+void upload_cdt(const u64* tab20) { HS_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_cdt), tab20, 20 * sizeof(u64))); }
+
+void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st) {
+  if (nblocks <= 0) return;
+  HS_DISPATCH_NT(c->logn, k_ntt, dim3((unsigned)nblocks), st, data, nl, mod0, inverse, (const ModTab*)c->d_tab, c->logn);
+}
+
+void launch_sample_small(const hs_ctx* c, int* out, int nobj, i64 obj_stride, u64 seed, u32 purpose, u64 index0, u64 index_step,
+                         int kind, hipStream_t st) {
+  if (nobj <= 0) return;
+  const int per = kind == 0 ? 16 : 8;
+  const i64 threads = (i64)nobj * (c->N / per);
+  hipLaunchKernelGGL(k_sample_small, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, out, nobj, obj_stride, seed, purpose, index0, index_step, kind, c->logn);
+  HS_CHECK_HIP(hipGetLastError());
+}
+
+void launch_sk_ntt(const hs_ctx* c, u64* sk, const int* s_coef, hipStream_t st) {
+  HS_DISPATCH_NT(c->logn, k_sk_ntt, dim3(c->n_mod), st, sk, s_coef, (const ModTab*)c->d_tab, c->logn);
+}
+
+void launch_ksk_limbs(const hs_ctx* c, const KskArgs* d_args, int count, hipStream_t st) {
+  if (count <= 0) return;
+  HS_DISPATCH_NT(c->logn, k_ksk_limb, dim3(count), st, d_args, (const ModTab*)c->d_tab, c->logn);
+}
+
+void launch_pack_encode(const hs_ctx* c, const PackArgs& a, int nchunks, hipStream_t st) {
+  if (nchunks <= 0) return;
+  HS_DISPATCH_NT(c->logn, k_pack_encode, dim3(nchunks), st, a, (const u32*)c->d_slot_pos, (const ModTab*)c->d_tab, c->n_mod, c->logn);
+}
+
+void launch_plain_ntt(const hs_ctx* c, const u64* coef, u64* out, int n_plain, hipStream_t st) {
+  if (n_plain <= 0) return;
+  HS_DISPATCH_NT(c->logn, k_plain_ntt, dim3(c->L, n_plain), st, coef, out, c->L, c->t, (const ModTab*)c->d_tab, c->logn);
+}
+
+void launch_encrypt(const hs_ctx* c, const u64* mcoef, const int* samples, const u64* pk, u64* out, int n_ct, hipStream_t st) {
+  if (n_ct <= 0) return;
+  HS_DISPATCH_NT(c->logn, k_encrypt, dim3(c->L, n_ct), st, mcoef, samples, pk, out, c->L, c->t, c->q_mod_t,
+                 (const double2*)c->d_qdt, (const ModTab*)c->d_tab, c->logn);
+}
+
+void launch_mul_plain(const hs_ctx* c, const u64* x, const u64* pt, u64* out, i64 n_ct, int pt_stride_ct, hipStream_t st) {
+  if (n_ct <= 0) return;
+  const i64 total = n_ct * 2 * c->L * (i64)c->N;
+  const i64 blocks = std::min<i64>((total + 255) / 256, 256 * 64);
+  hipLaunchKernelGGL(k_mul_plain, dim3((unsigned)blocks), dim3(256), 0, st, x, pt, out, n_ct, c->L, pt_stride_ct, (const ModTab*)c->d_tab, c->logn);
+  HS_CHECK_HIP(hipGetLastError());
+}
+
+void launch_mask_acc(const hs_ctx* c, const u64* const* w, const u64* mask, const int* part_chunk0, const int* part_nchunks,
+                     u64* res, int nparts, hipStream_t st) {
+  if (nparts <= 0) return;
+  const int per = 2 * c->L * (int)c->N;
+  const int bx = std::min((per + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_mask_acc, dim3(bx, nparts), dim3(256), 0, st, w, mask, part_chunk0, part_nchunks, res, c->L, (const ModTab*)c->d_tab, c->logn);
+  HS_CHECK_HIP(hipGetLastError());
+}
+
+void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, u64* D, double* ACC, double* PC, hipStream_t st) {
+  if (B <= 0) return;
+  const ModTab* tab = (const ModTab*)c->d_tab;
+  HS_DISPATCH_NT(c->logn, k_rot_intt, dim3(c->L, B), st, d_items, D, c->L, tab, c->logn);
+  HS_DISPATCH_NT(c->logn, k_modup_ip, dim3(c->L + c->K, B, S.ndg), st, d_items, (const u64*)D, ACC, S,
+                 (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, c->logn);
+  HS_DISPATCH_NT(c->logn, k_moddown_intt, dim3(c->K, 2, B), st, (const double*)ACC, PC, S, tab, c->logn);
+  HS_DISPATCH_NT(c->logn, k_moddown_ntt, dim3(c->L, 2, B), st, d_items, (const double*)ACC, (const double*)PC, S,
+                 (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, (const double2*)c->d_pinv, tab, c->logn);
+}
+
+void launch_dec_phase(const hs_ctx* c, const u64* ct, const u64* sk, u64* X, int n_ct, hipStream_t st) {
+  if (n_ct <= 0) return;
+  HS_DISPATCH_NT(c->logn, k_dec_phase, dim3(c->L, n_ct), st, ct, sk, X, c->L, (const ModTab*)c->d_tab, c->logn);
+}
+
+void launch_dec_round(const hs_ctx* c, const u64* X, u64* M, int n_ct, hipStream_t st) {
+  if (n_ct <= 0) return;
+  const i64 total = (i64)n_ct * c->N;
+  hipLaunchKernelGGL(k_dec_round, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, X, M, n_ct, c->L, c->t,
+                     (const double2*)c->d_dec_inv, (const u64*)c->d_dec_hat, (const u64*)c->d_dec_q, c->dec_words,
+                     (const ModTab*)c->d_tab, c->logn);
+  HS_CHECK_HIP(hipGetLastError());
+}
+
+void launch_decode_scatter(const hs_ctx* c, const u64* M, const int* rm, const i64* pinfo, i64* y, int nparts, hipStream_t st) {
+  if (nparts <= 0) return;
+  HS_DISPATCH_NT(c->logn, k_decode_scatter, dim3(nparts), st, M, (const u32*)c->d_slot_pos, rm, pinfo, y, c->n_mod,
+                 (const ModTab*)c->d_tab, c->logn);
+}
+
+void launch_cssc_scatter(const i64* row_ptr, const int* col, const i64* val, const int* rank, const i64* cp, const i64* part_cp_off,
+                         const i64* part_nnz_off, i64 R, i64 s, i64* va, int* ci, hipStream_t st) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(k_cssc_scatter, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, row_ptr, col, val, rank, cp, part_cp_off,
+                     part_nnz_off, R, s, va, ci);
+  HS_CHECK_HIP(hipGetLastError());
+}
+
+void launch_csr_check(const i64* row_ptr, const int* col, i64 R, i64 C, int* bad, hipStream_t st) {
+  if (R <= 0) return;
+  hipLaunchKernelGGL(k_csr_check, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, row_ptr, col, R, C, bad);
+  HS_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace hs

@@ -1,0 +1,61 @@
+// Kernel argument structures and host launchers of the encrypted-SpMV library.
+#pragma once
+#include "hs_internal.hpp"
+
+namespace hs {
+
+// One power-of-two rotation of a batched key switch.
+struct RotItem {
+  const u64* in;      // ciphertext [2][L][N] (NTT form)
+  u64* out;           // result [2][L][N]; must not alias `in`
+  const u64* addend;  // optional ciphertext added to the result (may alias `out`), else nullptr
+  const u64* key;     // key-switching key [2][dnum][L+K][N] for sigma_g(s) -> s
+  u32 galois;         // Galois element g
+  u32 pad;
+};
+
+struct KsShape {
+  int L, K, alpha, dnum;
+  int ndg;   // digit groups (one partial accumulator each)
+  int dpg;   // digits per group
+};
+
+struct KskArgs {
+  u64* b; u64* a;            // outputs [N]
+  const int* e_coef;         // Gaussian coefficients [N]
+  const u64* sk;             // secret key limb (NTT form) of this modulus
+  int mod_index;
+  u64 seed; u32 purpose_a; u64 idx_a;
+  int sprime_mode; u32 galois; double2 pfac;  // s' mode: 0 none, 1 sigma_g(s), 2 s^2; pfac = P mod q or 0
+  double2 r64;               // 2^64 mod q as (w, w/q)
+};
+
+struct PackArgs {
+  const i64* va; const int* ci; const i64* v;
+  const i64* cp;             // CSSC column pointers of the whole matrix
+  const i64* chunk;          // per chunk 8 words: (start, c, h, cp_off, nnz_off, part, 0, 0)
+  u64* out;                  // [nchunks][N] coefficients mod t
+  int mode;                  // 0 matrix values, 1 reorganised vector, 2 mask
+};
+
+void upload_cdt(const u64* tab20);
+void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st);
+void launch_sample_small(const hs_ctx* c, int* out, int nobj, i64 obj_stride, u64 seed, u32 purpose, u64 index0, u64 index_step,
+                         int kind, hipStream_t st);
+void launch_sk_ntt(const hs_ctx* c, u64* sk, const int* s_coef, hipStream_t st);
+void launch_ksk_limbs(const hs_ctx* c, const KskArgs* d_args, int count, hipStream_t st);
+void launch_pack_encode(const hs_ctx* c, const PackArgs& a, int nchunks, hipStream_t st);
+void launch_plain_ntt(const hs_ctx* c, const u64* coef, u64* out, int n_plain, hipStream_t st);
+void launch_encrypt(const hs_ctx* c, const u64* mcoef, const int* samples, const u64* pk, u64* out, int n_ct, hipStream_t st);
+void launch_mul_plain(const hs_ctx* c, const u64* x, const u64* pt, u64* out, i64 n_ct, int pt_stride_ct, hipStream_t st);
+void launch_mask_acc(const hs_ctx* c, const u64* const* w, const u64* mask, const int* part_chunk0, const int* part_nchunks,
+                     u64* res, int nparts, hipStream_t st);
+void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, u64* D, double* ACC, double* PC, hipStream_t st);
+void launch_dec_phase(const hs_ctx* c, const u64* ct, const u64* sk, u64* X, int n_ct, hipStream_t st);
+void launch_dec_round(const hs_ctx* c, const u64* X, u64* M, int n_ct, hipStream_t st);
+void launch_decode_scatter(const hs_ctx* c, const u64* M, const int* rm, const i64* pinfo, i64* y, int nparts, hipStream_t st);
+void launch_cssc_scatter(const i64* row_ptr, const int* col, const i64* val, const int* rank, const i64* cp, const i64* part_cp_off,
+                         const i64* part_nnz_off, i64 R, i64 s, i64* va, int* ci, hipStream_t st);
+void launch_csr_check(const i64* row_ptr, const int* col, i64 R, i64 C, int* bad, hipStream_t st);
+
+}  // namespace hs

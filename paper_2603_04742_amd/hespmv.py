@@ -1,0 +1,283 @@
+"""Encrypted sparse matrix-vector multiplication over the CSSC format on MI355X (gfx950).
+
+Thin ctypes binding of ``libhespmv.so`` (C ABI declared in ``include/hespmv.h``).  Every step of
+the computation runs in the library's HIP kernels; this module only marshals arguments.  Device
+arrays are passed as torch CUDA tensors (torch is used for device memory and streams only).
+The library must have been built (``python -m paper_2603_04742_amd.build`` or
+``__graft_entry__.build()``); importing the binding without it raises ImportError.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhespmv.so")
+
+HS_OK, HS_EINVAL, HS_EPARAM, HS_ECAPACITY, HS_EKEY, HS_ENOMEM, HS_EDEVICE = 0, -1, -2, -3, -4, -5, -6
+
+
+class HespmvError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("hespmv error %d: %s" % (code, msg))
+        self.code = code
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("q_bits", ctypes.c_uint32),
+                ("n_p", ctypes.c_uint32), ("p_bits", ctypes.c_uint32), ("t", ctypes.c_uint64),
+                ("sigma", ctypes.c_double), ("agg_mode", ctypes.c_uint32)]
+
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_u64 = ctypes.c_uint64
+_int = ctypes.c_int
+_pp = ctypes.POINTER(ctypes.c_void_p)
+_u64p = ctypes.POINTER(ctypes.c_uint64)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+
+# name -> (restype, argtypes); the names are those of include/hespmv.h
+SIGNATURES = {
+    "hs_last_error": (ctypes.c_char_p, []),
+    "hs_ctx_create": (_int, [ctypes.POINTER(Params), _pp]),
+    "hs_ctx_destroy": (None, [_vp]),
+    "hs_ctx_moduli": (_int, [_vp, _u64p, _int, ctypes.POINTER(ctypes.c_int)]),
+    "hs_cdt_table": (_int, [_u64p]),
+    "hs_keygen": (_int, [_vp, _u64, _vp, _pp]),
+    "hs_keyset_destroy": (None, [_vp]),
+    "hs_keyset_export": (_int, [_vp, _int, _int, _u64p, _i64]),
+    "hs_cssc_pack": (_int, [_vp, _i64, _i64, _vp, _vp, _vp, _int, _vp, _u64, _vp, _pp]),
+    "hs_matrix_destroy": (None, [_vp]),
+    "hs_matrix_info": (_int, [_vp, _i64p, _i64p]),
+    "hs_matrix_chunk": (_int, [_vp, _i64, _i64p]),
+    "hs_matrix_column_index": (_int, [_vp, _i32p, _i64, _i64p]),
+    "hs_matrix_export": (_int, [_vp, _int, _i64, _u64p, _i64]),
+    "hs_encrypt": (_int, [_vp, _vp, _vp, _vp, _i64, _u64, _vp, _pp]),
+    "hs_he_spmv": (_int, [_vp, _vp, _vp, _vp, _vp, _pp]),
+    "hs_decrypt": (_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp]),
+    "hs_ctvec_count": (_int, [_vp, _i64p]),
+    "hs_ct_export": (_int, [_vp, _i64, _u64p, _i64]),
+    "hs_ctvec_import": (_int, [_vp, _u64p, _i64, _pp]),
+    "hs_ctvec_destroy": (None, [_vp]),
+    "hs_ntt": (_int, [_vp, _vp, _i64, _int, _int, _int, _vp]),
+    "hs_mul_plain": (_int, [_vp, _vp, _vp, _vp, _pp]),
+    "hs_rotate": (_int, [_vp, _vp, _vp, _i64, _vp, _pp]),
+    "hs_mul_ct": (_int, [_vp, _vp, _vp, _vp, _vp, _pp]),
+    "hs_last_counters": (_int, [_i64p]),
+}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libhespmv.so is not built (%s); run paper_2603_04742_amd/build.py" % LIB_PATH)
+lib = ctypes.CDLL(LIB_PATH)
+for _name, (_res, _args) in SIGNATURES.items():
+    _f = getattr(lib, _name)
+    _f.restype = _res
+    _f.argtypes = _args
+
+
+def _check(rc):
+    if rc != HS_OK:
+        msg = lib.hs_last_error()
+        raise HespmvError(rc, msg.decode() if msg else "")
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    """Device address of a contiguous torch CUDA tensor (None for an empty tensor)."""
+    if t is None or t.numel() == 0:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _np(a, dt, ptr):
+    a = np.ascontiguousarray(a, dt)
+    return a, a.ctypes.data_as(ptr)
+
+
+class Context:
+    """hs_ctx: parameter set, primes, tables."""
+
+    def __init__(self, log_n, n_q, q_bits, n_p, t=65537, agg_mode=0, sigma=3.2):
+        self.params = Params(log_n, n_q, q_bits, n_p, q_bits, t, sigma, agg_mode)
+        h = ctypes.c_void_p()
+        _check(lib.hs_ctx_create(ctypes.byref(self.params), ctypes.byref(h)))
+        self.h = h
+        self.N, self.L, self.K, self.t = 1 << log_n, n_q, n_p, t
+        self.dnum = (n_q + n_p - 1) // n_p
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.hs_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def moduli(self):
+        n = ctypes.c_int()
+        buf = np.zeros(256, np.uint64)
+        _check(lib.hs_ctx_moduli(self.h, buf.ctypes.data_as(_u64p), 256, ctypes.byref(n)))
+        return [int(x) for x in buf[:n.value]]
+
+    def ct_words(self):
+        return 2 * self.L * self.N
+
+    def ntt(self, limbs, mod0, n_limbs, inverse=False):
+        """In place on a CUDA uint64 tensor [n_polys][n_limbs][N] (torch int64 dtype)."""
+        n_polys = limbs.numel() // (n_limbs * self.N)
+        _check(lib.hs_ntt(self.h, _dptr(limbs), n_polys, mod0, n_limbs, int(inverse), _stream()))
+
+    def keygen(self, seed):
+        return Keyset(self, seed)
+
+
+def cdt_table():
+    out = np.zeros(20, np.uint64)
+    _check(lib.hs_cdt_table(out.ctypes.data_as(_u64p)))
+    return out
+
+
+class Keyset:
+    def __init__(self, ctx, seed):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib.hs_keygen(ctx.h, seed, _stream(), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.hs_keyset_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def export(self, which, index=0):
+        c = self.ctx
+        n = {0: len(c.moduli()) * c.N, 1: 2 * c.L * c.N}.get(which, 2 * c.dnum * (c.L + c.K) * c.N)
+        out = np.zeros(n, np.uint64)
+        _check(lib.hs_keyset_export(self.h, which, index, out.ctypes.data_as(_u64p), n))
+        return out
+
+
+class CtVec:
+    def __init__(self, ctx, h):
+        self.ctx, self.h = ctx, h
+
+    @classmethod
+    def from_host(cls, ctx, limbs, n):
+        arr, ptr = _np(limbs, np.uint64, _u64p)
+        h = ctypes.c_void_p()
+        _check(lib.hs_ctvec_import(ctx.h, ptr, n, ctypes.byref(h)))
+        return cls(ctx, h)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.hs_ctvec_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def count(self):
+        n = ctypes.c_int64()
+        _check(lib.hs_ctvec_count(self.h, ctypes.byref(n)))
+        return n.value
+
+    def export(self, i):
+        out = np.zeros(self.ctx.ct_words(), np.uint64)
+        _check(lib.hs_ct_export(self.h, i, out.ctypes.data_as(_u64p), out.size))
+        return out
+
+    def export_all(self):
+        return np.concatenate([self.export(i) for i in range(self.count())]) if self.count() else np.zeros(0, np.uint64)
+
+
+class Matrix:
+    """Client A: hs_cssc_pack of a CSR matrix given as CUDA tensors (int64 row_ptr, int32 col,
+    int64 vals)."""
+
+    def __init__(self, ctx, rows, cols, row_ptr, col, val, encrypt_values=False, keyset=None, seed=0):
+        self.ctx, self.R, self.C = ctx, rows, cols
+        h = ctypes.c_void_p()
+        _check(lib.hs_cssc_pack(ctx.h, rows, cols, _dptr(row_ptr), _dptr(col), _dptr(val), int(encrypt_values),
+                                keyset.h if keyset is not None else None, seed, _stream(), ctypes.byref(h)))
+        self.h = h
+        self.encrypted = bool(encrypt_values)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.hs_matrix_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self):
+        p, c = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.hs_matrix_info(self.h, ctypes.byref(p), ctypes.byref(c)))
+        return p.value, c.value
+
+    def chunk(self, k):
+        out = np.zeros(4, np.int64)
+        _check(lib.hs_matrix_chunk(self.h, k, out.ctypes.data_as(_i64p)))
+        return tuple(int(x) for x in out)
+
+    def column_index(self):
+        n = ctypes.c_int64()
+        lib.hs_matrix_column_index(self.h, None, 0, ctypes.byref(n))
+        out = np.zeros(max(n.value, 1), np.int32)
+        _check(lib.hs_matrix_column_index(self.h, out.ctypes.data_as(_i32p), out.size, ctypes.byref(n)))
+        return out[:n.value]
+
+    def export(self, which, k):
+        c = self.ctx
+        n = c.ct_words() if (which == 0 and self.encrypted) else c.L * c.N
+        out = np.zeros(n, np.uint64)
+        _check(lib.hs_matrix_export(self.h, which, k, out.ctypes.data_as(_u64p), n))
+        return out
+
+
+def encrypt(ctx, ks, m, v, seed):
+    """Client B: reorganise, encode and encrypt the CUDA int64 vector v."""
+    h = ctypes.c_void_p()
+    _check(lib.hs_encrypt(ctx.h, ks.h, m.h, _dptr(v), v.numel(), seed, _stream(), ctypes.byref(h)))
+    return CtVec(ctx, h)
+
+
+def he_spmv(ctx, ks, m, x):
+    h = ctypes.c_void_p()
+    _check(lib.hs_he_spmv(ctx.h, ks.h, m.h, x.h, _stream(), ctypes.byref(h)))
+    return CtVec(ctx, h)
+
+
+def decrypt(ctx, ks, m, y, out):
+    """Key holder: decrypt into the CUDA int64 tensor out[rows]."""
+    _check(lib.hs_decrypt(ctx.h, ks.h, m.h, y.h, _dptr(out), m.R, _stream()))
+    return out
+
+
+def mul_plain(ctx, x, pt):
+    h = ctypes.c_void_p()
+    _check(lib.hs_mul_plain(ctx.h, x.h, _dptr(pt), _stream(), ctypes.byref(h)))
+    return CtVec(ctx, h)
+
+
+def rotate(ctx, ks, x, k):
+    h = ctypes.c_void_p()
+    _check(lib.hs_rotate(ctx.h, ks.h, x.h, k, _stream(), ctypes.byref(h)))
+    return CtVec(ctx, h)
+
+
+def last_counters():
+    out = np.zeros(5, np.int64)
+    _check(lib.hs_last_counters(out.ctypes.data_as(_i64p)))
+    return dict(zip(["key_switches", "rotations", "launches", "products", "mask_products"], (int(x) for x in out)))

@@ -1,0 +1,235 @@
+"""GPU parity: every stage of the HIP path against the CPU oracle, bit for bit, through the C ABI.
+
+Inputs come from the seeded generators in paper_2603_04742_amd.workloads; randomness the method
+draws (keys, encryption noise) comes from the same ChaCha20 streams on both sides.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2603_04742_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2603_04742_amd import hespmv as H  # noqa: E402
+
+# (log_n, L, bits, K, agg_mode): the small ring of the 256 x 256 workload, the 16384 ring, and
+# small rings with several partitions and ragged sizes
+SMALL = (12, 2, 30, 1, 1)
+RING16K = (14, 6, 50, 1, 0)
+TINY = (9, 3, 50, 1, 0)
+TINY11 = (11, 3, 50, 1, 0)
+
+
+def dev(a, dtype):
+    a = np.ascontiguousarray(a)
+    if a.dtype == np.uint64:
+        a = a.view(np.int64)
+    npd = {torch.int64: np.int64, torch.int32: np.int32}[dtype]
+    return torch.from_numpy(np.ascontiguousarray(a.astype(npd, copy=False))).cuda()
+
+
+_cache = {}
+
+
+def contexts(p, seed=7):
+    key = (p, seed)
+    if key not in _cache:
+        logn, L, bits, K, agg = p
+        g = H.Context(logn, L, bits, K, agg_mode=agg)
+        o = O.Context(logn, L, bits, K, agg_mode=agg)
+        kg = g.keygen(seed)
+        o.keygen(seed)
+        _cache[key] = (g, kg, o)
+    return _cache[key]
+
+
+@pytest.mark.parametrize("p", [SMALL, RING16K, TINY, (15, 12, 50, 2, 0)])
+def test_moduli_match_oracle(p):
+    logn, L, bits, K, agg = p
+    g = H.Context(logn, L, bits, K, agg_mode=agg)
+    o = O.Context(logn, L, bits, K, agg_mode=agg)
+    assert g.moduli() == o.moduli()
+
+
+@pytest.mark.parametrize("p", [(3, 2, 30, 1, 0), (6, 2, 30, 1, 0), (10, 3, 50, 1, 0), (11, 2, 40, 1, 0), SMALL, (13, 2, 50, 1, 0), RING16K])
+def test_ntt_parity(p):
+    logn, L, bits, K, agg = p
+    g = H.Context(logn, L, bits, K, agg_mode=agg)
+    o = O.Context(logn, L, bits, K, agg_mode=agg)
+    N = 1 << logn
+    mods = o.moduli()[:L + K]
+    rng = np.random.default_rng(logn)
+    npoly = 3
+    x = np.stack([np.stack([rng.integers(0, q, N, dtype=np.uint64) for q in mods]) for _ in range(npoly)])
+    d = dev(x.reshape(-1), torch.int64)
+    g.ntt(d, 0, len(mods), inverse=False)
+    got = d.cpu().numpy().view(np.uint64).reshape(npoly, len(mods), N)
+    for pi in range(npoly):
+        for m in range(len(mods)):
+            assert np.array_equal(got[pi, m], o.ntt(m, x[pi, m])), (p, pi, m)
+    g.ntt(d, 0, len(mods), inverse=True)
+    assert np.array_equal(d.cpu().numpy().view(np.uint64).reshape(x.shape), x)
+    # plaintext modulus t
+    y = rng.integers(0, 65537, N, dtype=np.uint64)
+    dt = dev(y, torch.int64)
+    g.ntt(dt, -1, 1, inverse=True)
+    assert np.array_equal(dt.cpu().numpy().view(np.uint64), o.intt(-1, y))
+
+
+@pytest.mark.parametrize("p", [SMALL, TINY])
+def test_keygen_parity(p):
+    g, kg, o = contexts(p)
+    assert np.array_equal(kg.export(0), o.sk_ntt())
+    assert np.array_equal(kg.export(1), o.pk())
+    for i in range(p[0] - 1):
+        assert np.array_equal(kg.export(2, i), o.ksk(i)), i
+    assert np.array_equal(kg.export(3), o.ksk(-1))
+
+
+def test_keygen_parity_16k():
+    g, kg, o = contexts(RING16K)
+    assert np.array_equal(kg.export(0), o.sk_ntt())
+    assert np.array_equal(kg.export(1), o.pk())
+    for i in (0, 5, 12):
+        assert np.array_equal(kg.export(2, i), o.ksk(i)), i
+    assert np.array_equal(kg.export(3), o.ksk(-1))
+
+
+def gpu_matrix(g, kg, w, encrypted=False, seed=31):
+    return H.Matrix(g, w["R"], w["C"], dev(w["row_ptr"], torch.int64), dev(w["col"], torch.int32),
+                    dev(w["val"], torch.int64), encrypted, kg if encrypted else None, seed)
+
+
+def check_protocol(p, w, mat_seed=31, vec_seed=41):
+    """Every stage of the protocol, GPU vs oracle, bit for bit; returns the decrypted result."""
+    g, kg, o = contexts(p)
+    M = gpu_matrix(g, kg, w, seed=mat_seed)
+    OM = O.Matrix(o, w["R"], w["C"], w["row_ptr"], w["col"], w["val"], False, mat_seed)
+    nparts, nchunks = M.info()
+    assert (nparts, nchunks) == (OM.n_parts(), OM.n_chunks())
+    for k in range(nchunks):
+        assert M.chunk(k) == OM.chunk(k)
+        assert np.array_equal(M.export(0, k), OM.pt(k)), ("plaintext", k)
+        if p[4] == 0:
+            assert np.array_equal(M.export(1, k), OM.mask(k)), ("mask", k)
+    # column index array (Client A -> Client B): the CSSC CI of every partition in order
+    s = (1 << p[0]) // 2
+    ci = []
+    for r0 in range(0, w["R"], s):
+        r1 = min(w["R"], r0 + s)
+        rp = w["row_ptr"][r0:r1 + 1] - w["row_ptr"][r0]
+        sl = slice(w["row_ptr"][r0], w["row_ptr"][r1])
+        _, CI, _, _ = O.cssc(r1 - r0, rp, w["col"][sl], w["val"][sl])
+        ci.append(CI)
+    ci = np.concatenate(ci) if ci else np.zeros(0, np.int32)
+    assert np.array_equal(M.column_index(), ci)
+    x = H.encrypt(g, kg, M, dev(w["v"], torch.int64), vec_seed)
+    ox = OM.encrypt_vector(w["v"], vec_seed)
+    assert np.array_equal(x.export_all(), ox), "encrypted vector"
+    y = H.he_spmv(g, kg, M, x)
+    oy, stats = OM.he_spmv(ox)
+    cnt = H.last_counters()
+    assert cnt["key_switches"] == stats["key_switches"] and cnt["rotations"] == stats["rotations"]
+    assert np.array_equal(y.export_all(), oy), "he_spmv result"
+    out = torch.zeros(w["R"], dtype=torch.int64, device="cuda")
+    H.decrypt(g, kg, M, y, out)
+    res = out.cpu().numpy()
+    assert np.array_equal(res, OM.decrypt_result(oy))
+    assert np.array_equal(res, W.spmv_mod_t(w))
+    return res
+
+
+def test_protocol_small_workload():
+    check_protocol(SMALL, W.small())
+
+
+@pytest.mark.parametrize("case", ["empty", "one", "emptyrows", "rect", "partitions", "dense_row", "ragged"])
+def test_protocol_edge_cases(case):
+    rng = np.random.default_rng(abs(hash(case)) % 1000)
+    p = TINY
+    if case == "empty":
+        R, C, nnz = 10, 10, 0
+    elif case == "one":
+        R, C, nnz = 1, 1, 1
+    elif case == "emptyrows":
+        R, C, nnz = 100, 50, 60
+    elif case == "rect":
+        R, C, nnz = 30, 200, 500
+    elif case == "partitions":
+        R, C, nnz = 700, 300, 2500
+    elif case == "ragged":
+        p = TINY11
+        R, C, nnz = 3000, 1500, 9000   # three partitions of <= 1024 rows, last one ragged
+    else:
+        R, C, nnz = 20, 256, 0
+    if case == "dense_row":
+        rows = np.concatenate([np.zeros(256, np.int64), rng.integers(1, R, 19)])
+        cols = np.concatenate([np.arange(256), rng.integers(0, C, 19)])
+        key = np.unique(rows * C + cols)
+        rows, cols = key // C, key % C
+        rp, col, val = W._csr_from_rows_cols(R, rows, cols, rng.integers(-15, 16, len(rows)))
+    else:
+        rp, col, val = W.uniform_matrix(R, C, nnz, 15, rng)
+    w = dict(R=R, C=C, row_ptr=rp, col=col, val=val, v=rng.integers(-15, 16, C))
+    check_protocol(p, w)
+
+
+def test_rotation_parity():
+    for p in (SMALL, TINY):
+        g, kg, o = contexts(p)
+        N = 1 << p[0]
+        rng = np.random.default_rng(5)
+        m = rng.integers(0, 65537, N).astype(np.uint64)
+        ct = np.concatenate([o.encrypt(m, 9, 0), o.encrypt(m, 9, 1)])
+        x = H.CtVec.from_host(g, ct, 2)
+        for k in (1, 6, 37, N // 2 - 1):
+            r = H.rotate(g, kg, x, k)
+            assert np.array_equal(r.export(0), o.rotate(ct[:o.ct_size()], k)), (p, k)
+            assert np.array_equal(r.export(1), o.rotate(ct[o.ct_size():], k)), (p, k)
+
+
+def test_mul_plain_parity():
+    g, kg, o = contexts(TINY)
+    N = 1 << TINY[0]
+    rng = np.random.default_rng(6)
+    m = rng.integers(0, 65537, N).astype(np.uint64)
+    ct = o.encrypt(m, 3, 0)
+    pt = o.plain_ntt(o.encode(rng.integers(0, 65537, N)))
+    r = H.mul_plain(g, H.CtVec.from_host(g, ct, 1), dev(pt, torch.int64))
+    assert np.array_equal(r.export(0), o.ct_mul_plain(ct, pt))
+
+
+def test_protocol_zipf16k_full_size():
+    """The 16384 x 16384 Zipf workload at full size (two partitions, ~22 chunks, ~56 key
+    switches): every ciphertext limb and the decrypted result against the oracle."""
+    check_protocol(RING16K, W.zipf16k())
+
+
+def test_repeated_runs_are_bit_identical():
+    """A race in the batched kernels would show up as a limb mismatch between runs."""
+    g, kg, o = contexts(SMALL)
+    w = W.small(1)
+    M = gpu_matrix(g, kg, w)
+    x = H.encrypt(g, kg, M, dev(w["v"], torch.int64), 5)
+    a = H.he_spmv(g, kg, M, x).export_all()
+    for _ in range(3):
+        assert np.array_equal(H.he_spmv(g, kg, M, x).export_all(), a)
+
+
+def test_invalid_csr_rejected():
+    g, kg, o = contexts(TINY)
+    rp = np.array([0, 2, 1], np.int64)   # decreasing row pointer
+    with pytest.raises(H.HespmvError) as e:
+        H.Matrix(g, 2, 4, dev(rp, torch.int64), dev(np.array([0, 1], np.int32), torch.int32), dev(np.array([1, 1]), torch.int64))
+    assert e.value.code == H.HS_EINVAL
+    rp = np.array([0, 2], np.int64)       # column out of range
+    with pytest.raises(H.HespmvError):
+        H.Matrix(g, 1, 4, dev(rp, torch.int64), dev(np.array([0, 9], np.int32), torch.int32), dev(np.array([1, 1]), torch.int64))
+    rp = np.array([0, 2], np.int64)       # columns not ascending within the row
+    with pytest.raises(H.HespmvError):
+        H.Matrix(g, 1, 4, dev(rp, torch.int64), dev(np.array([2, 1], np.int32), torch.int32), dev(np.array([1, 1]), torch.int64))
