@@ -1,0 +1,218 @@
+"""Benchmark of encrypted SpMV over CSSC on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload zipf16k|small]
+
+A step is one pass of the whole protocol over one synthetic input, all on the GPU with the CSR
+matrix, the vector and the keys resident in HBM when the timed region starts:
+  Client A  hs_cssc_pack  (CSR -> CSSC, partitions, chunks, slot packing, encoding, masks)
+  Client B  hs_encrypt    (reorganised vector, encoding, public-key encryption)
+  Cloud     hs_he_spmv    (ct x pt products, totalSum rotations with key switching, masks, sums)
+  Holder    hs_decrypt    (decryption, decoding, row-map scatter)
+`value` is steps per second (encrypted SpMVs/s).  The JSON line also carries the server-only
+rate, the per-stage split, the NTT bandwidth of the standalone transform, the roofline of the
+dominant kernel (HIP events on the launch stream during the timed steps) and the CPU oracle
+timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, published
+WORKLOADS = {
+    # name: (generator, log_n, L, bits, K, agg_mode, description)
+    "zipf16k": ("zipf16k", 14, 6, 50, 1, 0,
+                "zipf16k: 16384x16384 int matrix, Zipf(1.2) column degrees, 8 nnz/column (131072 nnz), values and "
+                "vector in [-15,15]; ring N=16384, 6x50-bit data primes + 1 special prime, t=65537; paper aggregation "
+                "(variable chunk heights, masks); power-of-two rotation keys"),
+    "small": ("small", 12, 2, 30, 1, 1,
+              "small: 256x256 int matrix, 2% density uniform, values and vector in [-7,7]; ring N=4096, 2x30-bit + 1 "
+              "special prime, t=65537; uniform aggregation"),
+}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="zipf16k", choices=sorted(WORKLOADS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--profile-only", action="store_true", help="run warmup + steps only (for rocprofv3)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build measures one GPU; the encrypted-SpMV path here has no multi-GPU mode "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2603_04742_amd import hespmv as H
+    from paper_2603_04742_amd import workloads as W
+
+    gen, logn, L, bits, K, agg, desc = WORKLOADS[args.workload]
+    w = getattr(W, gen)()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    ctx = H.Context(logn, L, bits, K, agg_mode=agg)
+    ks = ctx.keygen(0x5EED)
+    rp = torch.from_numpy(w["row_ptr"]).to(dev)
+    col = torch.from_numpy(w["col"].astype(np.int32)).to(dev)
+    val = torch.from_numpy(w["val"].astype(np.int64)).to(dev)
+    v = torch.from_numpy(w["v"].astype(np.int64)).to(dev)
+    out = torch.zeros(w["R"], dtype=torch.int64, device=dev)
+    want = torch.from_numpy(W.spmv_mod_t(w)).to(dev)
+
+    def step(i):
+        m = H.Matrix(ctx, w["R"], w["C"], rp, col, val)
+        x = H.encrypt(ctx, ks, m, v, 1000 + i)
+        y = H.he_spmv(ctx, ks, m, x)
+        H.decrypt(ctx, ks, m, y, out)
+        return m, x, y
+
+    print("bench: workload %s, warmup %d, steps %d" % (args.workload, args.warmup, args.steps), file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    if not torch.equal(out, want):
+        print("bench: decrypted result differs from the integer SpMV", file=sys.stderr)
+        sys.exit(1)
+
+    H.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(args.warmup + i)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = H.profile_summary()
+    H.profile(False)
+    counters = H.last_counters()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    if not torch.equal(out, want):
+        print("bench: decrypted result differs from the integer SpMV", file=sys.stderr)
+        sys.exit(1)
+    print("bench: %.3f ms/step" % ms_per_step, file=sys.stderr, flush=True)
+    if args.profile_only:
+        return
+
+    # per-stage split (separate, synchronised passes; not part of the timed steps)
+    reps = max(3, min(10, args.steps))
+    stage_ms = {"cssc_pack": 0.0, "encrypt": 0.0, "he_spmv": 0.0, "decrypt": 0.0}
+    for i in range(reps):
+        torch.cuda.synchronize(); a = time.perf_counter()
+        m = H.Matrix(ctx, w["R"], w["C"], rp, col, val)
+        torch.cuda.synchronize(); b = time.perf_counter()
+        x = H.encrypt(ctx, ks, m, v, 7 + i)
+        torch.cuda.synchronize(); c = time.perf_counter()
+        y = H.he_spmv(ctx, ks, m, x)
+        torch.cuda.synchronize(); d = time.perf_counter()
+        H.decrypt(ctx, ks, m, y, out)
+        torch.cuda.synchronize(); e = time.perf_counter()
+        for k, dt in zip(stage_ms, (b - a, c - b, d - c, e - d)):
+            stage_ms[k] += dt * 1e3 / reps
+
+    # standalone NTT bandwidth: forward transforms of 64 ciphertext-sized batches of limbs
+    N = 1 << logn
+    nl = L + K
+    npoly = max(1, (256 << 20) // (nl * N * 8))
+    mods = ctx.moduli()[:nl]
+    g = np.random.default_rng(1)
+    limbs = np.stack([np.stack([g.integers(0, q, N, dtype=np.uint64) for q in mods]) for _ in range(4)])
+    buf = torch.from_numpy(np.tile(limbs.view(np.int64), (npoly // 4 + 1, 1, 1))[:npoly].copy()).to(dev)
+    for _ in range(2):
+        ctx.ntt(buf, 0, nl)
+    H.profile(True)
+    torch.cuda.synchronize()
+    ntt_reps = 5
+    for _ in range(ntt_reps):
+        ctx.ntt(buf, 0, nl)
+    torch.cuda.synchronize()
+    nprof = H.profile_summary()
+    H.profile(False)
+    ntt_ms = nprof["k_ntt"][1] / nprof["k_ntt"][0]
+    ntt_bytes = 16.0 * N * nl * npoly
+    ntt_gbps = ntt_bytes / (ntt_ms * 1e-3) / 1e9
+
+    # roofline of the dominant kernel of the timed steps
+    dom, (dcount, dms) = max(prof.items(), key=lambda kv: kv[1][1])
+    avg_ms = dms / dcount
+    LK = L + K
+    dnum = (L + K - 1) // K
+    # algorithmic bytes per launch of the key-switch kernels (per rotation item of the level):
+    # modup+inner product: key 2*dnum*(L+K)*N*8 + digits L*N*8 + rotated c1 own limbs L*N*8
+    #                      + accumulators 2*(L+K)*N*8
+    per_item = {
+        "k_modup_ip": 2 * dnum * LK * N * 8 + 2 * L * N * 8 + 2 * LK * N * 8,
+        "k_rot_intt": 2 * L * N * 8,
+        "k_moddown_ntt": (2 * L * N * 8) * 2 + 2 * L * N * 8 + 2 * K * N * 8,
+        "k_moddown_intt": 2 * K * N * 8 * 2,
+    }
+    rotation_items = counters["key_switches"]
+    launches_per_step = dcount / args.steps
+    roof = None
+    if dom in per_item:
+        items_per_launch = rotation_items / launches_per_step
+        alg = per_item[dom] * items_per_launch
+        achieved = alg / (avg_ms * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
+                "avg_launch_ms": round(avg_ms, 4), "launches_per_step": launches_per_step,
+                "algorithmic_bytes_per_launch": int(alg)}
+    kernel_ms = {k: round(ms / args.steps, 4) for k, (cnt, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+
+    result = {
+        "metric": "encrypted SpMVs/s + NTT GB/s (% HBM peak), batched vs plain; p99 latency",
+        "value": round(1000.0 / ms_per_step, 3),
+        "unit": "SpMV/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": desc, "step": "cssc_pack + encrypt + he_spmv + decrypt"},
+        "server_spmv_per_s": round(1000.0 / stage_ms["he_spmv"], 3),
+        "stage_ms": {k: round(x, 3) for k, x in stage_ms.items()},
+        "ops_per_spmv": counters,
+        "kernel_ms_per_step": kernel_ms,
+        "ntt": {"GBps": round(ntt_gbps, 1), "hbm_frac": round(ntt_gbps / HBM_PEAK_GBPS, 4), "limbs_per_launch": nl * npoly,
+                "avg_launch_ms": round(ntt_ms, 4), "bytes_per_limb": 16 * N},
+        "roofline": roof,
+    }
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(w, logn, L, bits, K, agg)
+    print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(w, logn, L, bits, K, agg):
+    """The CPU oracle (single-threaded C++) on a bounded sample of the same step."""
+    import oracle as O
+    c = O.Context(logn, L, bits, K, agg_mode=agg)
+    c.keygen(0x5EED)
+    reps, t_total, n = 0, 0.0, 0
+    budget = 20.0
+    while t_total < budget / 2 or reps == 0:
+        t0 = time.perf_counter()
+        M = O.Matrix(c, w["R"], w["C"], w["row_ptr"], w["col"], w["val"])
+        x = M.encrypt_vector(w["v"], 1000 + reps)
+        res, _ = M.he_spmv(x)
+        M.decrypt_result(res)
+        t_total += time.perf_counter() - t0
+        reps += 1
+        if reps >= 4:
+            break
+    return {"value": round(reps / t_total, 4), "unit": "SpMV/s", "cores": 1, "kind": "oracle",
+            "sample": "%d full step(s) (pack + encrypt + he_spmv + decrypt) of the same workload, %.1f s" % (reps, t_total)}
+
+
+if __name__ == "__main__":
+    main()

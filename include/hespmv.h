@@ -175,6 +175,13 @@ int hs_rotate(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* in, int64_t k, v
 int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctvec* b,
               void* stream, hs_ctvec** out);
 
+/* Kernel timing: hs_profile(1) clears the records and brackets every subsequent kernel launch with
+   two HIP events on its stream; hs_profile(0) stops.  hs_profile_summary waits for the recorded
+   events and writes one text line per kernel, "name launches total_ms", NUL-terminated, into host
+   `buf` (capacity `cap` bytes; *len receives the length; HS_ECAPACITY if it does not fit). */
+int hs_profile(int enable);
+int hs_profile_summary(char* buf, int64_t cap, int64_t* len);
+
 /* Counters of the calling thread's last hs_he_spmv / hs_he_spmv_batch: [0] key switches,
    [1] logical rotations, [2] kernel launches, [3] slot-wise products, [4] mask products. */
 int hs_last_counters(int64_t out[5]);

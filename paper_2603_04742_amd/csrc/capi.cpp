@@ -815,6 +815,20 @@ int hs_mul_ct(hs_ctx* c, const hs_keyset* ks, const hs_ctvec* a, const hs_ctvec*
   });
 }
 
+int hs_profile(int enable) {
+  return guarded([&] { profile_enable(enable != 0); });
+}
+
+int hs_profile_summary(char* buf, int64_t cap, int64_t* len) {
+  return guarded([&] {
+    HS_REQUIRE(len, HS_EINVAL, "null argument");
+    const std::string s = profile_summary();
+    *len = (int64_t)s.size();
+    HS_REQUIRE(buf && cap > (int64_t)s.size(), HS_ECAPACITY, "output too small");
+    memcpy(buf, s.c_str(), s.size() + 1);
+  });
+}
+
 int hs_last_counters(int64_t out[5]) {
   return guarded([&] {
     HS_REQUIRE(out, HS_EINVAL, "null argument");

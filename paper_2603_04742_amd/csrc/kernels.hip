@@ -624,6 +624,7 @@ static void ensure_lds(const void* f, size_t bytes) {
     break;
 #define HS_DISPATCH_NT(logn, KERNEL, GRID, STREAM, ...)                                             \
   do {                                                                                              \
+    ProfScope _prof(#KERNEL, STREAM);                                                               \
     const size_t _lds = lds_bytes(logn);                                                            \
     if (_lds > 160 * 1024) throw Error{HS_EPARAM, "ring too large for the LDS-resident transform"}; \
     switch (nt_for(logn)) {                                                                         \
@@ -649,6 +650,7 @@ void launch_sample_small(const hs_ctx* c, int* out, int nobj, i64 obj_stride, u6
   if (nobj <= 0) return;
   const int per = kind == 0 ? 16 : 8;
   const i64 threads = (i64)nobj * (c->N / per);
+  ProfScope _prof("k_sample_small", st);
   hipLaunchKernelGGL(k_sample_small, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, out, nobj, obj_stride, seed, purpose, index0, index_step, kind, c->logn);
   HS_CHECK_HIP(hipGetLastError());
 }
@@ -682,6 +684,7 @@ void launch_mul_plain(const hs_ctx* c, const u64* x, const u64* pt, u64* out, i6
   if (n_ct <= 0) return;
   const i64 total = n_ct * 2 * c->L * (i64)c->N;
   const i64 blocks = std::min<i64>((total + 255) / 256, 256 * 64);
+  ProfScope _prof("k_mul_plain", st);
   hipLaunchKernelGGL(k_mul_plain, dim3((unsigned)blocks), dim3(256), 0, st, x, pt, out, n_ct, c->L, pt_stride_ct, (const ModTab*)c->d_tab, c->logn);
   HS_CHECK_HIP(hipGetLastError());
 }
@@ -691,6 +694,7 @@ void launch_mask_acc(const hs_ctx* c, const u64* const* w, const u64* mask, cons
   if (nparts <= 0) return;
   const int per = 2 * c->L * (int)c->N;
   const int bx = std::min((per + 255) / 256, 1024);
+  ProfScope _prof("k_mask_acc", st);
   hipLaunchKernelGGL(k_mask_acc, dim3(bx, nparts), dim3(256), 0, st, w, mask, part_chunk0, part_nchunks, res, c->L, (const ModTab*)c->d_tab, c->logn);
   HS_CHECK_HIP(hipGetLastError());
 }
@@ -714,6 +718,7 @@ void launch_dec_phase(const hs_ctx* c, const u64* ct, const u64* sk, u64* X, int
 void launch_dec_round(const hs_ctx* c, const u64* X, u64* M, int n_ct, hipStream_t st) {
   if (n_ct <= 0) return;
   const i64 total = (i64)n_ct * c->N;
+  ProfScope _prof("k_dec_round", st);
   hipLaunchKernelGGL(k_dec_round, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, X, M, n_ct, c->L, c->t,
                      (const double2*)c->d_dec_inv, (const u64*)c->d_dec_hat, (const u64*)c->d_dec_q, c->dec_words,
                      (const ModTab*)c->d_tab, c->logn);
@@ -729,6 +734,7 @@ void launch_decode_scatter(const hs_ctx* c, const u64* M, const int* rm, const i
 void launch_cssc_scatter(const i64* row_ptr, const int* col, const i64* val, const int* rank, const i64* cp, const i64* part_cp_off,
                          const i64* part_nnz_off, i64 R, i64 s, i64* va, int* ci, hipStream_t st) {
   if (R <= 0) return;
+  ProfScope _prof("k_cssc_scatter", st);
   hipLaunchKernelGGL(k_cssc_scatter, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, row_ptr, col, val, rank, cp, part_cp_off,
                      part_nnz_off, R, s, va, ci);
   HS_CHECK_HIP(hipGetLastError());
@@ -736,6 +742,7 @@ void launch_cssc_scatter(const i64* row_ptr, const int* col, const i64* val, con
 
 void launch_csr_check(const i64* row_ptr, const int* col, i64 R, i64 C, int* bad, hipStream_t st) {
   if (R <= 0) return;
+  ProfScope _prof("k_csr_check", st);
   hipLaunchKernelGGL(k_csr_check, dim3((unsigned)((R + 255) / 256)), dim3(256), 0, st, row_ptr, col, R, C, bad);
   HS_CHECK_HIP(hipGetLastError());
 }

@@ -1,5 +1,7 @@
 // Kernel argument structures and host launchers of the encrypted-SpMV library.
 #pragma once
+#include <string>
+
 #include "hs_internal.hpp"
 
 namespace hs {
@@ -37,6 +39,20 @@ struct PackArgs {
   u64* out;                  // [nchunks][N] coefficients mod t
   int mode;                  // 0 matrix values, 1 reorganised vector, 2 mask
 };
+
+// HIP-event timing of kernel launches (profiler.cpp)
+class ProfScope {
+ public:
+  ProfScope(const char* name, hipStream_t st);
+  ~ProfScope();
+ private:
+  const char* name_;
+  hipStream_t st_;
+  hipEvent_t a_ = nullptr;
+  bool active_ = false;
+};
+void profile_enable(bool on);
+std::string profile_summary();
 
 void upload_cdt(const u64* tab20);
 void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st);

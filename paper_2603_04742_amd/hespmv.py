@@ -66,6 +66,8 @@ SIGNATURES = {
     "hs_rotate": (_int, [_vp, _vp, _vp, _i64, _vp, _pp]),
     "hs_mul_ct": (_int, [_vp, _vp, _vp, _vp, _vp, _pp]),
     "hs_last_counters": (_int, [_i64p]),
+    "hs_profile": (_int, [_int]),
+    "hs_profile_summary": (_int, [ctypes.c_char_p, _i64, _i64p]),
 }
 
 if not os.path.exists(LIB_PATH):
@@ -275,6 +277,24 @@ def rotate(ctx, ks, x, k):
     h = ctypes.c_void_p()
     _check(lib.hs_rotate(ctx.h, ks.h, x.h, k, _stream(), ctypes.byref(h)))
     return CtVec(ctx, h)
+
+
+def profile(enable):
+    """Start (clearing earlier records) or stop HIP-event timing of every kernel launch."""
+    _check(lib.hs_profile(int(bool(enable))))
+
+
+def profile_summary():
+    """{kernel name: (launches, total ms)} of the launches recorded since profile(True)."""
+    n = ctypes.c_int64()
+    lib.hs_profile_summary(None, 0, ctypes.byref(n))
+    buf = ctypes.create_string_buffer(n.value + 1)
+    _check(lib.hs_profile_summary(buf, n.value + 1, ctypes.byref(n)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, cnt, ms = line.split()
+        out[name] = (int(cnt), float(ms))
+    return out
 
 
 def last_counters():
