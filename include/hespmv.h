@@ -175,6 +175,20 @@ int hs_rotate(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* in, int64_t k, v
 int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctvec* b,
               void* stream, hs_ctvec** out);
 
+/* Process-wide execution options (they never change results, only which kernels compute them):
+   HS_OPT_KS_PIPELINE  key switching of a rotation level: 0 = automatic, 1 = one workgroup per limb
+                       transform (least HBM traffic; large batches), 2 = two-pass transforms over
+                       N/2048 workgroups per limb (lowest latency; small batches; always used for
+                       N = 32768, whose limb does not fit in LDS)
+   HS_OPT_NTT_PATH     hs_ntt: 0 = automatic, 1 = one workgroup per limb, 2 = two-pass
+   HS_OPT_KS_THRESHOLD automatic choice: two-pass when (L + K) x items of a level is below this
+                       value (default 512)
+   HS_EINVAL for an unknown key or value. */
+#define HS_OPT_KS_PIPELINE 1
+#define HS_OPT_NTT_PATH 2
+#define HS_OPT_KS_THRESHOLD 3
+int hs_set_option(int key, int64_t value);
+
 /* Kernel timing: hs_profile(1) clears the records and brackets every subsequent kernel launch with
    two HIP events on its stream; hs_profile(0) stops.  hs_profile_summary waits for the recorded
    events and writes one text line per kernel, "name launches total_ms", NUL-terminated, into host

@@ -3,6 +3,7 @@
 #include <cmath>
 #include <cstring>
 #include <numeric>
+#include <atomic>
 #include <stdexcept>
 
 #include "kernels.hpp"
@@ -11,6 +12,11 @@ namespace hs {
 const char* last_error_cstr();
 
 static thread_local int64_t g_counters[5] = {0, 0, 0, 0, 0};
+
+// process-wide options (hs_set_option)
+static std::atomic<int> g_opt_ks{0};    // key-switch pipeline: 0 auto, 1 one workgroup per limb, 2 two-pass
+static std::atomic<int> g_opt_ntt{0};   // hs_ntt path: 0 auto, 1 one workgroup per limb, 2 two-pass
+static std::atomic<int> g_opt_ks_threshold{512};  // auto: two-pass below this many (target x item) pairs
 
 template <class F>
 static int guarded(F&& f) {
@@ -208,6 +214,19 @@ static KsShape ks_shape(const hs_ctx* c, int B) {
 // Levels of batched power-of-two rotations: every item of a level is independent of the others;
 // level k + 1 may read what level k wrote.  All item arrays are uploaded once and the scratch is
 // sized for the widest level, so the launches of all levels are enqueued without host waits.
+static bool lds_limb_fits(const hs_ctx* c) { return c->logn <= 14; }
+
+// Pipeline choice for one level of B rotations: the one-workgroup-per-limb kernels move the least
+// data and win when the level has enough (target modulus x item) pairs to fill the GPU; the
+// two-pass kernels spread each transform over N / 2048 workgroups and win for small levels.
+static bool use_two_pass(const hs_ctx* c, int B) {
+  const int opt = g_opt_ks.load();
+  if (!lds_limb_fits(c)) return true;
+  if (opt == 1) return false;
+  if (opt == 2) return true;
+  return (c->L + c->K) * B < g_opt_ks_threshold.load();
+}
+
 static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels, hipStream_t st) {
   size_t total = 0, widest = 0;
   for (auto& l : levels) { total += l.size(); widest = std::max(widest, l.size()); }
@@ -217,21 +236,42 @@ static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem
   std::vector<RotItem> flat;
   flat.reserve(total);
   for (auto& l : levels) flat.insert(flat.end(), l.begin(), l.end());
+  bool any1 = false, any2 = false;
+  for (auto& l : levels) {
+    if (l.empty()) continue;
+    if (use_two_pass(c, (int)l.size())) any2 = true; else any1 = true;
+  }
   const KsShape Smax = ks_shape(c, 1);  // the most digit groups any level uses
   DBuf ditems(&c->pool, total * sizeof(RotItem));
-  DBuf D(&c->pool, widest * c->L * N * sizeof(u64));
-  DBuf ACC(&c->pool, widest * Smax.ndg * 2 * LK * N * sizeof(double));
-  DBuf PC(&c->pool, widest * 2 * c->K * N * sizeof(double));
+  DBuf D, ACC, PC, T1, E, ACC2, T2, F;
+  if (any1) {
+    D = DBuf(&c->pool, widest * c->L * N * sizeof(u64));
+    ACC = DBuf(&c->pool, widest * Smax.ndg * 2 * LK * N * sizeof(double));
+    PC = DBuf(&c->pool, widest * 2 * c->K * N * sizeof(double));
+  }
+  if (any2) {
+    T1 = DBuf(&c->pool, widest * c->L * N * sizeof(double));
+    E = DBuf(&c->pool, widest * c->dnum * LK * N * sizeof(double));
+    ACC2 = DBuf(&c->pool, widest * 2 * c->L * N * sizeof(double));
+    T2 = DBuf(&c->pool, widest * 2 * c->K * N * sizeof(double));
+    F = DBuf(&c->pool, widest * 2 * c->L * N * sizeof(double));
+  }
   h2d(ditems.as<RotItem>(), flat.data(), flat.size(), st);
   size_t off = 0;
   for (auto& l : levels) {
     const int B = (int)l.size();
     if (!B) continue;
     const KsShape Sh = ks_shape(c, B);
-    launch_rotate_batch(c, ditems.as<RotItem>() + off, B, Sh, D.as<u64>(), ACC.as<double>(), PC.as<double>(), st);
+    if (use_two_pass(c, B)) {
+      launch_rotate_batch2(c, ditems.as<RotItem>() + off, B, Sh, T1.as<double>(), E.as<double>(), ACC2.as<double>(), T2.as<double>(),
+                           F.as<double>(), st);
+      g_counters[2] += 5;
+    } else {
+      launch_rotate_batch(c, ditems.as<RotItem>() + off, B, Sh, D.as<u64>(), ACC.as<double>(), PC.as<double>(), st);
+      g_counters[2] += 4;
+    }
     off += B;
     g_counters[0] += B;
-    g_counters[2] += 4;
   }
   // the item array and scratch return to the pool: wait until the kernels are done with them
   HS_CHECK_HIP(hipStreamSynchronize(st));
@@ -754,7 +794,35 @@ int hs_ntt(hs_ctx* c, uint64_t* d_limbs, int64_t n_polys, int mod0, int n_limbs,
     } else {
       HS_REQUIRE(mod0 + n_limbs <= c->n_mod, HS_EINVAL, "modulus index out of range");
     }
-    launch_ntt(c, d_limbs, n_polys * n_limbs, n_limbs, m0, inverse, S(stream));
+    const bool two = !lds_limb_fits(c) || g_opt_ntt.load() == 2;
+    if (two) {
+      DBuf scratch(&c->pool, (size_t)n_polys * n_limbs * c->N * sizeof(double));
+      launch_ntt2(c, d_limbs, scratch.as<double>(), n_polys * n_limbs, n_limbs, m0, inverse, S(stream));
+      HS_CHECK_HIP(hipStreamSynchronize(S(stream)));
+    } else {
+      launch_ntt(c, d_limbs, n_polys * n_limbs, n_limbs, m0, inverse, S(stream));
+    }
+  });
+}
+
+int hs_set_option(int key, int64_t value) {
+  return guarded([&] {
+    switch (key) {
+      case HS_OPT_KS_PIPELINE:
+        HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "pipeline must be 0, 1 or 2");
+        g_opt_ks = (int)value;
+        break;
+      case HS_OPT_NTT_PATH:
+        HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "path must be 0, 1 or 2");
+        g_opt_ntt = (int)value;
+        break;
+      case HS_OPT_KS_THRESHOLD:
+        HS_REQUIRE(value >= 0 && value < (1 << 30), HS_EINVAL, "bad threshold");
+        g_opt_ks_threshold = (int)value;
+        break;
+      default:
+        throw Error{HS_EINVAL, "unknown option"};
+    }
   });
 }
 

@@ -1,0 +1,240 @@
+// Two-pass (multi-workgroup) negacyclic NTT for gfx950.
+//
+// The stages of a length-N transform split at S = floor(log N / 2): the forward "high" pass runs
+// stages [0, S) (index bits [logn - S, logn)), the forward "low" pass stages [S, logn) (bits
+// [0, logn - S)); the inverse runs the low pass first.  A pass acts on independent groups:
+//   high groups: the elements sharing their low logn - S bits, 2^S of them at stride 2^(logn-S);
+//   low groups : 2^(logn-S) contiguous elements.
+// A workgroup transforms a block of BE = min(N, 2048) elements: GB consecutive groups.  In LDS,
+// element u of group g sits at u * GB + g (high: consecutive g are consecutive addresses in HBM)
+// or g * G + u (low).  Between the passes the data goes through HBM/L2 as balanced doubles.
+// Each kernel pass therefore needs only N / BE workgroups per limb, spreading one transform over
+// many CUs (latency) while fused kernels chain several transforms of the same block.
+#pragma once
+#include "hs_device.hpp"
+
+namespace hs {
+
+static constexpr int kBlockElems = 2048;
+
+struct PassGeom {
+  int logn, S;        // split
+  int BE;             // elements per block
+  int nblk;           // blocks per limb (same for both passes)
+  __host__ __device__ int gb_high() const { return BE >> S; }            // high groups per block
+  __host__ __device__ int gb_low() const { return BE >> (logn - S); }    // low groups per block
+};
+
+__host__ __device__ inline PassGeom make_geom(int logn) {
+  PassGeom g;
+  g.logn = logn;
+  g.S = logn >> 1;
+  g.BE = (1 << logn) < kBlockElems ? (1 << logn) : kBlockElems;
+  g.nblk = (1 << logn) / g.BE;
+  return g;
+}
+
+// Global index of element u of group g in block `blk`.
+__device__ __forceinline__ int gidx_high(const PassGeom& G, int blk, int g, int u) {
+  return (blk * G.gb_high() + g) + (u << (G.logn - G.S));
+}
+__device__ __forceinline__ int gidx_low(const PassGeom& G, int blk, int g, int u) {
+  return ((blk * G.gb_low() + g) << (G.logn - G.S)) + u;
+}
+// LDS address of element u of group g (HIGH: strided layout, LOW: contiguous layout).
+template <bool HIGH>
+__device__ __forceinline__ int laddr(const PassGeom& G, int g, int u) {
+  return HIGH ? u * G.gb_high() + g : g * (1 << (G.logn - G.S)) + u;
+}
+// Block element e (0..BE-1) <-> (g, u) in the LDS order of the layout: LDS address e.
+template <bool HIGH>
+__device__ __forceinline__ int gidx_of_lds(const PassGeom& G, int blk, int e) {
+  if (HIGH) {
+    const int gbh = G.gb_high();
+    return gidx_high(G, blk, e % gbh, e / gbh);
+  } else {
+    const int gl = 1 << (G.logn - G.S);
+    return gidx_low(G, blk, e / gl, e % gl);
+  }
+}
+
+// ---- twiddles of one pass, staged in LDS
+// High passes (forward stages [0, S), inverse stages [logn - S, logn)) use table entries [1, 2^S):
+// copied to LDS at the same indices.  Low passes use, per stage, one contiguous range of the table
+// that depends on the block:
+//   forward stage st in [S, logn): entries 2^st + blk GB 2^(st-S) + [0, GB 2^(st-S)),
+//                                   LDS offset GB (2^(st-S) - 1)
+//   inverse stage st in [0, logn-S): with d = logn - S - st - 1, entries N/2^(st+1) + blk GB 2^d +
+//                                   [0, GB 2^d), LDS offset GB (2^(logn-S) - 2^(d+1))
+// Each range has at most BE/2 entries and all ranges of a pass at most BE.
+__host__ __device__ constexpr int tw_lds_entries(int BE) { return BE; }
+
+template <bool HIGH, bool FWD>
+__device__ __forceinline__ int tw_lds_index(const PassGeom& G, int blk, int st, int gtw) {
+  if (HIGH) return gtw;
+  const int GB = G.gb_low();
+  const int nl = G.logn - G.S;
+  if (FWD) {
+    const int e = st - G.S;
+    return GB * ((1 << e) - 1) + (gtw - (1 << st) - ((blk * GB) << e));
+  } else {
+    const int d = nl - st - 1;
+    return GB * ((1 << nl) - (2 << d)) + (gtw - ((1 << G.logn) >> (st + 1)) - ((blk * GB) << d));
+  }
+}
+
+// Copy the pass's twiddles to twl (cooperative; the caller synchronises afterwards).
+template <int NT, bool HIGH, bool FWD>
+__device__ __forceinline__ void stage_twiddles(double2* twl, const PassGeom& G, int blk, const double2* __restrict__ tw) {
+  if (HIGH) {
+    for (int i = threadIdx.x; i < (1 << G.S); i += NT) twl[i] = tw[i];
+    return;
+  }
+  const int GB = G.gb_low();
+  const int nl = G.logn - G.S;
+  for (int k = 0; k < nl; k++) {
+    int st, base, cnt, off;
+    if (FWD) {
+      st = G.S + k;
+      cnt = GB << k;
+      base = (1 << st) + ((blk * GB) << k);
+      off = GB * ((1 << k) - 1);
+    } else {
+      st = k;
+      const int d = nl - st - 1;
+      cnt = GB << d;
+      base = ((1 << G.logn) >> (st + 1)) + ((blk * GB) << d);
+      off = GB * ((1 << nl) - (2 << d));
+    }
+    for (int i = threadIdx.x; i < cnt; i += NT) twl[off + i] = tw[base + i];
+  }
+}
+
+// One register round of a group transform: group bits [lo, lo + nb) of the global index (lo = 0
+// for low groups, logn - S for high groups); the round covers local bits [lb, lb + R).
+// Forward: stage k pairs global bit lo + lb + R - 1 - k (global stage logn - lo - lb - R + k).
+// Inverse: stage k pairs global bit lo + lb + k.
+template <int R, int NT, bool FWD, bool HIGH>
+__device__ __forceinline__ void pass_round(double* s, const PassGeom& G, int blk, int lb, int lazy, bool scale,
+                                           const double2* twl, double2 ninv, ModD m) {
+  const int n = 1 << G.logn;
+  const int nb = HIGH ? G.S : G.logn - G.S;
+  const int lo = HIGH ? G.logn - G.S : 0;
+  const int GB = HIGH ? G.gb_high() : G.gb_low();
+  const int per_group = 1 << (nb - R);
+  for (int sg = threadIdx.x; sg < GB * per_group; sg += NT) {
+    const int g = sg / per_group, r = sg % per_group;
+    const int base_u = ((r >> lb) << (lb + R)) | (r & ((1 << lb) - 1));
+    const int gb = HIGH ? gidx_high(G, blk, g, base_u) : gidx_low(G, blk, g, base_u);
+    const int hb = gb >> (lo + lb + R);
+    const int l0 = laddr<HIGH>(G, g, base_u);
+    const int ls = HIGH ? (GB << lb) : (1 << lb);
+    double x[1 << R];
+#pragma unroll
+    for (int v = 0; v < (1 << R); v++) x[v] = s[lpad(l0 + v * ls)];
+    if (FWD) {
+      int lz = lazy;
+#pragma unroll
+      for (int k = 0; k < R; k++) {
+        if (lz >= 2) {
+#pragma unroll
+          for (int v = 0; v < (1 << R); v++) x[v] = reduce(x[v], m);
+          lz = 0;
+        }
+        const int st = G.logn - lo - lb - R + k;
+        const double2* twk = twl + tw_lds_index<HIGH, true>(G, blk, st, (1 << st) + (hb << k));
+#pragma unroll
+        for (int j = 0; j < (1 << k); j++) {
+          const double2 w = twk[j];
+#pragma unroll
+          for (int v = 0; v < (1 << (R - 1 - k)); v++) {
+            const int u = (j << (R - k)) | v;
+            const int u2 = u | (1 << (R - 1 - k));
+            const double t = mul_tw(x[u2], w.x, w.y, m);
+            x[u2] = x[u] - t;
+            x[u] = x[u] + t;
+          }
+        }
+        lz++;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < R; k++) {
+        const int st = lo + lb + k;
+        const double2* twk = twl + tw_lds_index<HIGH, false>(G, blk, st, (n >> (st + 1)) + (hb << (R - 1 - k)));
+#pragma unroll
+        for (int j = 0; j < (1 << (R - 1 - k)); j++) {
+          const double2 w = twk[j];
+#pragma unroll
+          for (int v = 0; v < (1 << k); v++) {
+            const int u = (j << (k + 1)) | v;
+            const int u2 = u | (1 << k);
+            const double a = x[u], b = x[u2];
+            x[u] = reduce(a + b, m);
+            x[u2] = mul_tw(a - b, w.x, w.y, m);
+          }
+        }
+      }
+      if (scale) {
+#pragma unroll
+        for (int v = 0; v < (1 << R); v++) x[v] = mul_tw(x[v], ninv.x, ninv.y, m);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < (1 << R); v++) s[lpad(l0 + v * ls)] = x[v];
+  }
+}
+
+// Forward pass on the block in LDS (inputs |x| <= q); ends with every element reduced to
+// |x| <= q/2 + 1 and a barrier.  twl: LDS scratch of tw_lds_entries(BE) double2 for the staged
+// twiddles (must not be in use by other threads).  The caller synchronises before.
+template <int NT, bool HIGH>
+__device__ void pass_fwd(double* s, double2* twl, const PassGeom& G, int blk, const double2* __restrict__ tw, ModD m,
+                         bool stage = true) {
+  const int nb = HIGH ? G.S : G.logn - G.S;
+  if (stage) {
+    stage_twiddles<NT, HIGH, true>(twl, G, blk, tw);
+    __syncthreads();
+  }
+  int done = 0, lazy = 0;
+  while (done < nb) {
+    const int R = min(HS_NTT_RADIX_BITS, nb - done);
+    const int lb = nb - done - R;  // forward: from the top local bits down
+    switch (R) {
+      case 3: pass_round<3, NT, true, HIGH>(s, G, blk, lb, lazy, false, twl, double2{0, 0}, m); break;
+      case 2: pass_round<2, NT, true, HIGH>(s, G, blk, lb, lazy, false, twl, double2{0, 0}, m); break;
+      default: pass_round<1, NT, true, HIGH>(s, G, blk, lb, lazy, false, twl, double2{0, 0}, m); break;
+    }
+    for (int k = 0; k < R; k++) { if (lazy >= 2) lazy = 0; lazy++; }
+    done += R;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < G.BE; e += NT) s[lpad(e)] = reduce(s[lpad(e)], m);
+  __syncthreads();
+}
+
+// Inverse pass on the block in LDS (inputs |x| <= q, outputs |x| <= 0.625 q); `scale` multiplies
+// by N^-1 (the last inverse pass).  Ends with a barrier.
+template <int NT, bool HIGH>
+__device__ void pass_inv(double* s, double2* twl, const PassGeom& G, int blk, bool scale, const double2* __restrict__ tw, double2 ninv, ModD m,
+                         bool stage = true) {
+  const int nb = HIGH ? G.S : G.logn - G.S;
+  if (stage) {
+    stage_twiddles<NT, HIGH, false>(twl, G, blk, tw);
+    __syncthreads();
+  }
+  int done = 0;
+  while (done < nb) {
+    const int R = min(HS_NTT_RADIX_BITS, nb - done);
+    const bool last = scale && (done + R == nb);
+    switch (R) {
+      case 3: pass_round<3, NT, false, HIGH>(s, G, blk, done, 0, last, twl, ninv, m); break;
+      case 2: pass_round<2, NT, false, HIGH>(s, G, blk, done, 0, last, twl, ninv, m); break;
+      default: pass_round<1, NT, false, HIGH>(s, G, blk, done, 0, last, twl, ninv, m); break;
+    }
+    done += R;
+    __syncthreads();
+  }
+}
+
+}  // namespace hs

@@ -67,6 +67,11 @@ void launch_mul_plain(const hs_ctx* c, const u64* x, const u64* pt, u64* out, i6
 void launch_mask_acc(const hs_ctx* c, const u64* const* w, const u64* mask, const int* part_chunk0, const int* part_nchunks,
                      u64* res, int nparts, hipStream_t st);
 void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, u64* D, double* ACC, double* PC, hipStream_t st);
+// two-pass (multi-workgroup) transforms and key switching (ks2.hip)
+void launch_ntt2(const hs_ctx* c, u64* data, double* scratch, i64 rows, int nl, int mod0, int inverse, hipStream_t st);
+void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, double* T1, double* E, double* ACC, double* T2,
+                          double* F, hipStream_t st);
+
 void launch_dec_phase(const hs_ctx* c, const u64* ct, const u64* sk, u64* X, int n_ct, hipStream_t st);
 void launch_dec_round(const hs_ctx* c, const u64* X, u64* M, int n_ct, hipStream_t st);
 void launch_decode_scatter(const hs_ctx* c, const u64* M, const int* rm, const i64* pinfo, i64* y, int nparts, hipStream_t st);

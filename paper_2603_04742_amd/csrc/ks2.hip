@@ -1,0 +1,390 @@
+// Two-pass key switching and two-pass NTT kernels (multi-workgroup transforms, hs_pass.hpp).
+//
+// One batched power-of-two rotation level runs as five kernels; every workgroup owns one block of
+// BE elements of one limb, so a level has (limbs x blocks x items) workgroups:
+//  K1 k2_rot_intt_low   sigma_g(c1) (NTT-domain gather), inverse low pass            -> T1
+//  K2 k2_modup_high     inverse high pass (coefficients), ModUp conversion of the digit to every
+//                       other modulus, forward high pass                              -> E
+//  K3 k2_ip_low         forward low pass of each digit's extension (own limb: sigma_g(c1)), key
+//                       inner product over the digits; special limbs also get the inverse low pass
+//                                                                                     -> ACC, T2
+//  K4 k2_moddown_high   inverse high pass of the special limbs, conversion P -> q_i, forward high
+//                       pass                                                          -> F
+//  K5 k2_final_low      forward low pass, out = (ACC - F) P^-1 + sigma_g(c0) (+ addend)
+// Intermediates are balanced doubles in HBM (mostly served from the 256 MB Infinity Cache).
+#include <algorithm>
+#include <map>
+#include <mutex>
+
+#include "hs_pass.hpp"
+#include "kernels.hpp"
+
+namespace hs {
+
+#define SMEM() extern __shared__ double smem_raw[]
+// LDS layout of every two-pass kernel: [staged twiddles: BE double2][data buffers of lds_doubles(BE)]
+#define SMEM2_N(G, TWN)                           \
+  SMEM();                                         \
+  double2* twl = (double2*)smem_raw;              \
+  double* smem = smem_raw + 2 * (TWN)
+#define SMEM2(G) SMEM2_N(G, (G).BE)
+// kernels that only run high passes stage 2^S twiddles
+#define SMEM2_HIGH(G) SMEM2_N(G, 1 << (G).S)
+
+__device__ __forceinline__ ModD mod_of2(const ModTab& t) { return ModD{t.q, t.qinv}; }
+
+__device__ __forceinline__ u32 galois_index2(u32 k, u32 g, int logn) {
+  const u32 n2m = (2u << logn) - 1;
+  const u32 e = 2 * brev_bits(k, logn) + 1;
+  const u32 e2 = (u32)(((u64)g * e) & n2m);
+  return brev_bits((e2 - 1) >> 1, logn);
+}
+
+// ------------------------------------------------------------------ standalone two-pass NTT
+// One pass over `nl`-limb polynomials: grid (nblk, n_polys * nl).  in/out either u64 canonical
+// residues or balanced doubles (in place allowed).
+template <int NT, bool HIGH, bool FWD>
+__device__ __forceinline__ void ntt_pass_body(double* smem, double2* twl, const void* in, int in_u64, void* out, int out_u64, int nl, int mod0,
+                                              int scale, const ModTab* __restrict__ tab, PassGeom G) {
+  const int n = 1 << G.logn;
+  const int blk = blockIdx.x, row = blockIdx.y;
+  const ModTab tb = tab[mod0 + row % nl];
+  const ModD m = mod_of2(tb);
+  const size_t base = (size_t)row * n;
+  for (int e = threadIdx.x; e < G.BE; e += NT) {
+    const int gi = gidx_of_lds<HIGH>(G, blk, e);
+    smem[lpad(e)] = in_u64 ? u2d(((const u64*)in)[base + gi]) : ((const double*)in)[base + gi];
+  }
+  __syncthreads();
+  if (FWD) pass_fwd<NT, HIGH>(smem, twl, G, blk, tb.fw, m);
+  else pass_inv<NT, HIGH>(smem, twl, G, blk, scale != 0, tb.iv, tb.ninv, m);
+  for (int e = threadIdx.x; e < G.BE; e += NT) {
+    const int gi = gidx_of_lds<HIGH>(G, blk, e);
+    if (out_u64) ((u64*)out)[base + gi] = d2u(canon(smem[lpad(e)], m));
+    else ((double*)out)[base + gi] = smem[lpad(e)];
+  }
+}
+
+#define HS2_PASS_KERNEL(NAME, HIGH, FWD)                                                                      \
+  template <int NT>                                                                                           \
+  __global__ void __launch_bounds__(NT) NAME(const void* in, int in_u64, void* out, int out_u64, int nl,      \
+                                             int mod0, int scale, const ModTab* __restrict__ tab, PassGeom G) { \
+    SMEM2(G);                                                                                                 \
+    ntt_pass_body<NT, HIGH, FWD>(smem, twl, in, in_u64, out, out_u64, nl, mod0, scale, tab, G);               \
+  }
+HS2_PASS_KERNEL(k2_ntt_pass_hf, true, true)
+HS2_PASS_KERNEL(k2_ntt_pass_lf, false, true)
+HS2_PASS_KERNEL(k2_ntt_pass_li, false, false)
+HS2_PASS_KERNEL(k2_ntt_pass_hi, true, false)
+
+// ------------------------------------------------------------------ key switching, K1..K5
+template <int NT>
+__global__ void __launch_bounds__(NT) k2_rot_intt_low(const RotItem* __restrict__ items, double* T1, int L, const ModTab* __restrict__ tab, PassGeom G) {
+  SMEM2(G);
+  const int n = 1 << G.logn;
+  const int blk = blockIdx.x, l = blockIdx.y, b = blockIdx.z;
+  const RotItem it = items[b];
+  const ModTab tb = tab[l];
+  const ModD m = mod_of2(tb);
+  const u64* c1 = it.in + ((size_t)L + l) * n;
+  for (int e = threadIdx.x; e < G.BE; e += NT) {
+    const int gi = gidx_of_lds<false>(G, blk, e);
+    smem[lpad(e)] = u2d(c1[galois_index2((u32)gi, it.galois, G.logn)]);
+  }
+  __syncthreads();
+  pass_inv<NT, false>(smem, twl, G, blk, false, tb.iv, tb.ninv, m);
+  double* o = T1 + ((size_t)b * L + l) * n;
+  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<false>(G, blk, e)] = smem[lpad(e)];
+}
+
+// grid (nblk, dnum * (L + K), B): digit j = y / (L+K), target modulus mi = y % (L+K) (own limbs of
+// the digit exit at once).  The digit's inverse high pass is recomputed by each target's
+// workgroup: two passes per workgroup instead of a chain of L + K.
+template <int NT>
+__global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T1, double* E, KsShape S, const double2* __restrict__ up_inv,
+                                                    const double2* __restrict__ up_hat, const ModTab* __restrict__ tab, PassGeom G) {
+  SMEM2_HIGH(G);
+  const int n = 1 << G.logn;
+  const int LK = S.L + S.K;
+  const int blk = blockIdx.x, j = blockIdx.y / LK, mi = blockIdx.y % LK, b = blockIdx.z;
+  const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha), na = hi - lo;
+  if (mi >= lo && mi < hi) return;
+  const int LB = lds_doubles(G.BE);
+  double* work = smem + (size_t)na * LB;
+  for (int a = 0; a < na; a++) {
+    double* buf = smem + (size_t)a * LB;
+    const double* src = T1 + ((size_t)b * S.L + lo + a) * n;
+    for (int e = threadIdx.x; e < G.BE; e += NT) buf[lpad(e)] = src[gidx_of_lds<true>(G, blk, e)];
+  }
+  __syncthreads();
+  for (int a = 0; a < na; a++) {
+    const ModTab ta = tab[lo + a];
+    const ModD ma = mod_of2(ta);
+    double* buf = smem + (size_t)a * LB;
+    pass_inv<NT, true>(buf, twl, G, blk, true, ta.iv, ta.ninv, ma);
+    for (int e = threadIdx.x; e < G.BE; e += NT) {
+      double x = canon(buf[lpad(e)], ma);
+      if (na > 1) {
+        const double2 ci = up_inv[j * S.alpha + a];
+        x = canon(mul_tw(x, ci.x, ci.y, ma), ma);   // [x (Q_j/q_a)^-1]_{q_a}
+      }
+      buf[lpad(e)] = x;
+    }
+  }
+  __syncthreads();
+  const ModTab tm = tab[mi];
+  const ModD mm = mod_of2(tm);
+  for (int e = threadIdx.x; e < G.BE; e += NT) {
+    double acc = 0.0;
+    for (int a = 0; a < na; a++) {
+      const double y = smem[(size_t)a * LB + lpad(e)];
+      if (na > 1) {
+        const double2 hm = up_hat[((size_t)j * S.alpha + a) * LK + mi];
+        acc = reduce(acc + mul_tw(y, hm.x, hm.y, mm), mm);
+      } else {
+        acc = reduce(y, mm);   // one source prime: [x]_q as an integer, taken mod mi
+      }
+    }
+    work[lpad(e)] = acc;
+  }
+  __syncthreads();
+  pass_fwd<NT, true>(work, twl, G, blk, tm.fw, mm);
+  double* o = E + (((size_t)b * S.dnum + j) * LK + mi) * n;
+  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<true>(G, blk, e)] = work[lpad(e)];
+}
+
+// grid (nblk, L + K, B).  The next digit's block is loaded into registers while the current one
+// is transformed (its twiddles are staged once: every digit uses modulus mi).
+template <int NT>
+__global__ void __launch_bounds__(NT) k2_ip_low(const RotItem* __restrict__ items, const double* __restrict__ E, double* ACC, double* T2, KsShape S,
+                                                const ModTab* __restrict__ tab, PassGeom G) {
+  SMEM2(G);
+  constexpr int PER = kBlockElems / NT > 0 ? kBlockElems / NT : 1;
+  const int n = 1 << G.logn;
+  const int blk = blockIdx.x, mi = blockIdx.y, b = blockIdx.z;
+  const int LK = S.L + S.K;
+  const RotItem it = items[b];
+  const ModTab tm = tab[mi];
+  const ModD m = mod_of2(tm);
+  double a0[PER], a1[PER], nx[PER];
+#pragma unroll
+  for (int k = 0; k < PER; k++) { a0[k] = 0.0; a1[k] = 0.0; }
+  auto load_digit = [&](int j) {
+    const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha);
+    if (mi >= lo && mi < hi) {
+      const u64* c1 = it.in + ((size_t)S.L + mi) * n;
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int e = threadIdx.x + k * NT;
+        if (e < G.BE) nx[k] = u2d(c1[galois_index2((u32)gidx_of_lds<false>(G, blk, e), it.galois, G.logn)]);
+      }
+    } else {
+      const double* src = E + (((size_t)b * S.dnum + j) * LK + mi) * n;
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int e = threadIdx.x + k * NT;
+        if (e < G.BE) nx[k] = src[gidx_of_lds<false>(G, blk, e)];
+      }
+    }
+  };
+  stage_twiddles<NT, false, true>(twl, G, blk, tm.fw);
+  load_digit(0);
+  for (int j = 0; j < S.dnum; j++) {
+    const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha);
+    const bool own = (mi >= lo && mi < hi);
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int e = threadIdx.x + k * NT;
+      if (e < G.BE) smem[lpad(e)] = nx[k];
+    }
+    if (j + 1 < S.dnum) load_digit(j + 1);
+    __syncthreads();
+    if (!own) pass_fwd<NT, false>(smem, twl, G, blk, tm.fw, m, false);
+    const u64* kb = it.key + (((size_t)0 * S.dnum + j) * LK + mi) * n;
+    const u64* ka = it.key + (((size_t)1 * S.dnum + j) * LK + mi) * n;
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int e = threadIdx.x + k * NT;
+      if (e < G.BE) {
+        const int gi = gidx_of_lds<false>(G, blk, e);
+        const double x = smem[lpad(e)];
+        a0[k] += mulmod(x, u2d(kb[gi]), m);
+        a1[k] += mulmod(x, u2d(ka[gi]), m);
+      }
+    }
+    if ((j & 3) == 3) {
+#pragma unroll
+      for (int k = 0; k < PER; k++) { a0[k] = reduce(a0[k], m); a1[k] = reduce(a1[k], m); }
+    }
+    __syncthreads();
+  }
+  if (mi < S.L) {
+    double* o0 = ACC + (((size_t)b * 2 + 0) * S.L + mi) * n;
+    double* o1 = ACC + (((size_t)b * 2 + 1) * S.L + mi) * n;
+#pragma unroll
+    for (int k = 0; k < PER; k++) {
+      const int e = threadIdx.x + k * NT;
+      if (e < G.BE) {
+        const int gi = gidx_of_lds<false>(G, blk, e);
+        o0[gi] = reduce(a0[k], m);
+        o1[gi] = reduce(a1[k], m);
+      }
+    }
+  } else {
+    stage_twiddles<NT, false, false>(twl, G, blk, tm.iv);
+    for (int w = 0; w < 2; w++) {
+#pragma unroll
+      for (int k = 0; k < PER; k++) {
+        const int e = threadIdx.x + k * NT;
+        if (e < G.BE) smem[lpad(e)] = canon(w == 0 ? a0[k] : a1[k], m);
+      }
+      __syncthreads();
+      pass_inv<NT, false>(smem, twl, G, blk, false, tm.iv, tm.ninv, m, false);
+      double* o = T2 + (((size_t)b * 2 + w) * S.K + (mi - S.L)) * n;
+      for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<false>(G, blk, e)] = smem[lpad(e)];
+      __syncthreads();
+    }
+  }
+}
+
+// grid (nblk, 2 L, B): polynomial w = y / L, data prime i = y % L.  The special limbs' inverse
+// high pass is recomputed per target.
+template <int NT>
+__global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__ T2, double* F, KsShape S, const double2* __restrict__ dn_inv,
+                                                      const double2* __restrict__ dn_hat, const ModTab* __restrict__ tab, PassGeom G) {
+  SMEM2_HIGH(G);
+  const int n = 1 << G.logn;
+  const int blk = blockIdx.x, w = blockIdx.y / S.L, i = blockIdx.y % S.L, b = blockIdx.z;
+  const int LB = lds_doubles(G.BE);
+  double* work = smem + (size_t)S.K * LB;
+  for (int k = 0; k < S.K; k++) {
+    double* buf = smem + (size_t)k * LB;
+    const double* src = T2 + (((size_t)b * 2 + w) * S.K + k) * n;
+    for (int e = threadIdx.x; e < G.BE; e += NT) buf[lpad(e)] = src[gidx_of_lds<true>(G, blk, e)];
+  }
+  __syncthreads();
+  for (int k = 0; k < S.K; k++) {
+    const ModTab tp = tab[S.L + k];
+    const ModD mp = mod_of2(tp);
+    double* buf = smem + (size_t)k * LB;
+    pass_inv<NT, true>(buf, twl, G, blk, true, tp.iv, tp.ninv, mp);
+    for (int e = threadIdx.x; e < G.BE; e += NT) {
+      double x = canon(buf[lpad(e)], mp);
+      if (S.K > 1) {
+        const double2 ci = dn_inv[k];
+        x = canon(mul_tw(x, ci.x, ci.y, mp), mp);
+      }
+      buf[lpad(e)] = x;
+    }
+  }
+  __syncthreads();
+  const ModTab tq = tab[i];
+  const ModD mq = mod_of2(tq);
+  for (int e = threadIdx.x; e < G.BE; e += NT) {
+    double acc = 0.0;
+    for (int k = 0; k < S.K; k++) {
+      const double y = smem[(size_t)k * LB + lpad(e)];
+      if (S.K > 1) {
+        const double2 hm = dn_hat[(size_t)k * S.L + i];
+        acc = reduce(acc + mul_tw(y, hm.x, hm.y, mq), mq);
+      } else {
+        acc = reduce(y, mq);
+      }
+    }
+    work[lpad(e)] = acc;
+  }
+  __syncthreads();
+  pass_fwd<NT, true>(work, twl, G, blk, tq.fw, mq);
+  double* o = F + (((size_t)b * 2 + w) * S.L + i) * n;
+  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<true>(G, blk, e)] = work[lpad(e)];
+}
+
+template <int NT>
+__global__ void __launch_bounds__(NT) k2_final_low(const RotItem* __restrict__ items, const double* __restrict__ F, const double* __restrict__ ACC,
+                                                   const double2* __restrict__ pinv, KsShape S, const ModTab* __restrict__ tab, PassGeom G) {
+  SMEM2(G);
+  const int n = 1 << G.logn;
+  const int blk = blockIdx.x, wi = blockIdx.y, b = blockIdx.z;
+  const int w = wi / S.L, i = wi % S.L;
+  const RotItem it = items[b];
+  const ModTab tq = tab[i];
+  const ModD m = mod_of2(tq);
+  const double* src = F + (((size_t)b * 2 + w) * S.L + i) * n;
+  for (int e = threadIdx.x; e < G.BE; e += NT) smem[lpad(e)] = src[gidx_of_lds<false>(G, blk, e)];
+  __syncthreads();
+  pass_fwd<NT, false>(smem, twl, G, blk, tq.fw, m);
+  const double2 pv = pinv[i];
+  const double* acc = ACC + (((size_t)b * 2 + w) * S.L + i) * n;
+  const u64* c0 = it.in + (size_t)i * n;
+  u64* out = it.out + ((size_t)w * S.L + i) * n;
+  const u64* add = it.addend ? it.addend + ((size_t)w * S.L + i) * n : nullptr;
+  for (int e = threadIdx.x; e < G.BE; e += NT) {
+    const int gi = gidx_of_lds<false>(G, blk, e);
+    double v = mul_tw(reduce(acc[gi] - smem[lpad(e)], m), pv.x, pv.y, m);
+    if (w == 0) v += u2d(c0[galois_index2((u32)gi, it.galois, G.logn)]);
+    if (add) v += u2d(add[gi]);
+    out[gi] = d2u(canon(v, m));
+  }
+}
+
+// ------------------------------------------------------------------ launchers
+static std::mutex g2_mu;
+static std::map<const void*, size_t> g2_set;
+static void ensure_lds2(const void* f, size_t bytes) {
+  std::lock_guard<std::mutex> g(g2_mu);
+  auto it = g2_set.find(f);
+  if (it != g2_set.end() && it->second >= bytes) return;
+  HS_CHECK_HIP(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+  g2_set[f] = bytes;
+}
+
+static int nt2(const PassGeom& G) { return G.BE >= 2048 ? 256 : 64; }
+
+#define HS2_LAUNCH(KERNEL, GRID, LDS, STREAM, ...)                                                  \
+  do {                                                                                              \
+    ProfScope _prof(#KERNEL, STREAM);                                                               \
+    if (nt2(G) == 256) {                                                                            \
+      ensure_lds2((const void*)KERNEL<256>, LDS);                                                   \
+      hipLaunchKernelGGL(KERNEL<256>, GRID, dim3(256), LDS, STREAM, __VA_ARGS__);                   \
+    } else {                                                                                        \
+      ensure_lds2((const void*)KERNEL<64>, LDS);                                                    \
+      hipLaunchKernelGGL(KERNEL<64>, GRID, dim3(64), LDS, STREAM, __VA_ARGS__);                     \
+    }                                                                                               \
+    HS_CHECK_HIP(hipGetLastError());                                                                \
+  } while (0)
+
+void launch_ntt2(const hs_ctx* c, u64* data, double* scratch, i64 rows, int nl, int mod0, int inverse, hipStream_t st) {
+  if (rows <= 0) return;
+  const PassGeom G = make_geom(c->logn);
+  const size_t lds = (size_t)(lds_doubles(G.BE) + 2 * G.BE) * sizeof(double);
+  const ModTab* tab = (const ModTab*)c->d_tab;
+  const dim3 grid(G.nblk, (unsigned)rows);
+  if (!inverse) {
+    HS2_LAUNCH(k2_ntt_pass_hf, grid, lds, st, data, 1, scratch, 0, nl, mod0, 0, tab, G);
+    HS2_LAUNCH(k2_ntt_pass_lf, grid, lds, st, scratch, 0, data, 1, nl, mod0, 0, tab, G);
+  } else {
+    HS2_LAUNCH(k2_ntt_pass_li, grid, lds, st, data, 1, scratch, 0, nl, mod0, 0, tab, G);
+    HS2_LAUNCH(k2_ntt_pass_hi, grid, lds, st, scratch, 0, data, 1, nl, mod0, 1, tab, G);
+  }
+}
+
+void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, double* T1, double* E, double* ACC, double* T2,
+                          double* F, hipStream_t st) {
+  if (B <= 0) return;
+  const PassGeom G = make_geom(c->logn);
+  const size_t LB = (size_t)lds_doubles(G.BE) * sizeof(double);
+  const size_t TW = (size_t)2 * G.BE * sizeof(double);
+  const size_t TWH = (size_t)2 * (1 << G.S) * sizeof(double);
+  const ModTab* tab = (const ModTab*)c->d_tab;
+  const int LK = c->L + c->K;
+  HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B), TW + LB, st, d_items, T1, c->L, tab, G);
+  HS2_LAUNCH(k2_modup_high, dim3(G.nblk, c->dnum * LK, B), TWH + LB * (c->alpha + 1), st, (const double*)T1, E, S,
+             (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
+  HS2_LAUNCH(k2_ip_low, dim3(G.nblk, LK, B), TW + LB, st, d_items, (const double*)E, ACC, T2, S, tab, G);
+  HS2_LAUNCH(k2_moddown_high, dim3(G.nblk, 2 * c->L, B), TWH + LB * (c->K + 1), st, (const double*)T2, F, S, (const double2*)c->d_dn_inv,
+             (const double2*)c->d_dn_hat, tab, G);
+  HS2_LAUNCH(k2_final_low, dim3(G.nblk, 2 * c->L, B), TW + LB, st, d_items, (const double*)F, (const double*)ACC, (const double2*)c->d_pinv, S,
+             tab, G);
+}
+
+}  // namespace hs

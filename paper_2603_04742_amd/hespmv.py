@@ -67,6 +67,7 @@ SIGNATURES = {
     "hs_mul_ct": (_int, [_vp, _vp, _vp, _vp, _vp, _pp]),
     "hs_last_counters": (_int, [_i64p]),
     "hs_profile": (_int, [_int]),
+    "hs_set_option": (_int, [_int, _i64]),
     "hs_profile_summary": (_int, [ctypes.c_char_p, _i64, _i64p]),
 }
 
@@ -277,6 +278,13 @@ def rotate(ctx, ks, x, k):
     h = ctypes.c_void_p()
     _check(lib.hs_rotate(ctx.h, ks.h, x.h, k, _stream(), ctypes.byref(h)))
     return CtVec(ctx, h)
+
+
+OPT_KS_PIPELINE, OPT_NTT_PATH, OPT_KS_THRESHOLD = 1, 2, 3
+
+
+def set_option(key, value):
+    _check(lib.hs_set_option(key, value))
 
 
 def profile(enable):

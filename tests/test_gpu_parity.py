@@ -36,6 +36,14 @@ def dev(a, dtype):
 _cache = {}
 
 
+@pytest.fixture(params=[1, 2], ids=["ks_limb", "ks_2pass"])
+def pipeline(request):
+    """Run the test under both key-switch pipelines (results must be identical)."""
+    H.set_option(H.OPT_KS_PIPELINE, request.param)
+    yield request.param
+    H.set_option(H.OPT_KS_PIPELINE, 0)
+
+
 def contexts(p, seed=7):
     key = (p, seed)
     if key not in _cache:
@@ -56,8 +64,15 @@ def test_moduli_match_oracle(p):
     assert g.moduli() == o.moduli()
 
 
+@pytest.fixture(params=[1, 2], ids=["ntt_limb", "ntt_2pass"])
+def ntt_path(request):
+    H.set_option(H.OPT_NTT_PATH, request.param)
+    yield request.param
+    H.set_option(H.OPT_NTT_PATH, 0)
+
+
 @pytest.mark.parametrize("p", [(3, 2, 30, 1, 0), (6, 2, 30, 1, 0), (10, 3, 50, 1, 0), (11, 2, 40, 1, 0), SMALL, (13, 2, 50, 1, 0), RING16K])
-def test_ntt_parity(p):
+def test_ntt_parity(p, ntt_path):
     logn, L, bits, K, agg = p
     g = H.Context(logn, L, bits, K, agg_mode=agg)
     o = O.Context(logn, L, bits, K, agg_mode=agg)
@@ -144,12 +159,12 @@ def check_protocol(p, w, mat_seed=31, vec_seed=41):
     return res
 
 
-def test_protocol_small_workload():
+def test_protocol_small_workload(pipeline):
     check_protocol(SMALL, W.small())
 
 
 @pytest.mark.parametrize("case", ["empty", "one", "emptyrows", "rect", "partitions", "dense_row", "ragged"])
-def test_protocol_edge_cases(case):
+def test_protocol_edge_cases(case, pipeline):
     rng = np.random.default_rng(abs(hash(case)) % 1000)
     p = TINY
     if case == "empty":
@@ -179,7 +194,7 @@ def test_protocol_edge_cases(case):
     check_protocol(p, w)
 
 
-def test_rotation_parity():
+def test_rotation_parity(pipeline):
     for p in (SMALL, TINY):
         g, kg, o = contexts(p)
         N = 1 << p[0]
@@ -204,13 +219,13 @@ def test_mul_plain_parity():
     assert np.array_equal(r.export(0), o.ct_mul_plain(ct, pt))
 
 
-def test_protocol_zipf16k_full_size():
+def test_protocol_zipf16k_full_size(pipeline):
     """The 16384 x 16384 Zipf workload at full size (two partitions, ~22 chunks, ~56 key
     switches): every ciphertext limb and the decrypted result against the oracle."""
     check_protocol(RING16K, W.zipf16k())
 
 
-def test_repeated_runs_are_bit_identical():
+def test_repeated_runs_are_bit_identical(pipeline):
     """A race in the batched kernels would show up as a limb mismatch between runs."""
     g, kg, o = contexts(SMALL)
     w = W.small(1)
@@ -219,6 +234,29 @@ def test_repeated_runs_are_bit_identical():
     a = H.he_spmv(g, kg, M, x).export_all()
     for _ in range(3):
         assert np.array_equal(H.he_spmv(g, kg, M, x).export_all(), a)
+
+
+def test_ntt_32768_two_pass():
+    """N = 32768 (limb larger than LDS) always takes the two-pass transform."""
+    g = H.Context(15, 2, 50, 1)
+    o = O.Context(15, 2, 50, 1)
+    rng = np.random.default_rng(15)
+    mods = o.moduli()[:3]
+    x = np.stack([rng.integers(0, q, 1 << 15, dtype=np.uint64) for q in mods])
+    d = dev(x.reshape(-1), torch.int64)
+    g.ntt(d, 0, 3)
+    got = d.cpu().numpy().view(np.uint64).reshape(3, -1)
+    for m in range(3):
+        assert np.array_equal(got[m], o.ntt(m, x[m]))
+    g.ntt(d, 0, 3, inverse=True)
+    assert np.array_equal(d.cpu().numpy().view(np.uint64).reshape(3, -1), x)
+
+
+def test_options_rejected():
+    with pytest.raises(H.HespmvError):
+        H.set_option(99, 1)
+    with pytest.raises(H.HespmvError):
+        H.set_option(H.OPT_KS_PIPELINE, 7)
 
 
 def test_invalid_csr_rejected():
