@@ -44,6 +44,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="zipf16k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batched-vs-plain measurement")
     ap.add_argument("--profile-only", action="store_true", help="run warmup + steps only (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -188,9 +189,54 @@ def main():
                 "avg_launch_ms": round(ntt_ms, 4), "bytes_per_limb": 16 * N},
         "roofline": roof,
     }
+    if args.workload == "zipf16k" and not args.no_batch:
+        result["batched_vs_plain"] = batched_vs_plain(H, W, torch, dev)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, logn, L, bits, K, agg)
     print(json.dumps(result), flush=True)
+
+
+def batched_vs_plain(H, W, torch, dev, reps=3):
+    """The 64-matrix batch (rows log-uniform in [512, 16384], densities log-uniform in [0.05%, 1%],
+    values in [-7, 7]; ring N=16384, 6x50-bit + 1): 64 sequential hs_he_spmv calls against one
+    hs_he_spmv_batch call, matrices packed and vectors encrypted beforehand."""
+    ctx = H.Context(14, 6, 50, 1, agg_mode=0)
+    ks = ctx.keygen(0xBA7C)
+    ws = W.batch64()
+    ms, xs = [], []
+    for i, w in enumerate(ws):
+        m = H.Matrix(ctx, w["R"], w["C"], torch.from_numpy(w["row_ptr"]).to(dev),
+                     torch.from_numpy(w["col"].astype(np.int32)).to(dev), torch.from_numpy(w["val"]).to(dev))
+        ms.append(m)
+        xs.append(H.encrypt(ctx, ks, m, torch.from_numpy(w["v"]).to(dev), 50 + i))
+    H.he_spmv_batch(ctx, [ks] * len(ms), ms, xs)  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ys = H.he_spmv_batch(ctx, [ks] * len(ms), ms, xs)
+    torch.cuda.synchronize()
+    t_batch = (time.perf_counter() - t0) / reps
+    counters = H.last_counters()
+    for m, x in zip(ms, xs):
+        H.he_spmv(ctx, ks, m, x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        for m, x in zip(ms, xs):
+            H.he_spmv(ctx, ks, m, x)
+    torch.cuda.synchronize()
+    t_plain = (time.perf_counter() - t0) / reps
+    ok = True
+    for w, m, y in zip(ws[:8], ms[:8], ys[:8]):
+        out = torch.zeros(w["R"], dtype=torch.int64, device=dev)
+        H.decrypt(ctx, ks, m, y, out)
+        ok &= bool(torch.equal(out.cpu(), torch.from_numpy(W.spmv_mod_t(w))))
+    return {"workload": "batch64: 64 matrices, rows log-uniform [512,16384], density log-uniform [0.05%%,1%%], "
+                        "%d nnz, %d chunks, %d key switches; ring N=16384 6x50-bit + 1" %
+                        (sum(int(w["row_ptr"][-1]) for w in ws), sum(m.info()[1] for m in ms), counters["key_switches"]),
+            "batched_spmv_per_s": round(len(ms) / t_batch, 2), "plain_spmv_per_s": round(len(ms) / t_plain, 2),
+            "batched_ms": round(t_batch * 1e3, 2), "plain_ms": round(t_plain * 1e3, 2),
+            "speedup": round(t_plain / t_batch, 2), "decrypt_check": ok}
 
 
 def cpu_baseline(w, logn, L, bits, K, agg):

@@ -141,6 +141,13 @@ int hs_encrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const int64
 int hs_he_spmv(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* x,
                void* stream, hs_ctvec** y);
 
+/* Batched form: n independent encrypted SpMVs (request r: key-set ks[r], matrix m[r], vector
+   x[r]; the same context) in one call.  The totalSum rotations of all requests are merged level by
+   level into batched key switches, so small requests share launches and key reads; every result
+   is identical to the request's own hs_he_spmv.  y[r] receives request r's result. */
+int hs_he_spmv_batch(hs_ctx* ctx, int n, const hs_keyset* const* ks, const hs_matrix* const* m,
+                     const hs_ctvec* const* x, void* stream, hs_ctvec** y);
+
 /* ---------------------------------------------------------------- key holder */
 /* Decrypt the per-partition results and scatter them with the row map: out (device int64[rows])
    receives y = A v reduced into (-t/2, t/2]; rows without nonzeros receive 0. */

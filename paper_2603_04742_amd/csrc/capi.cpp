@@ -639,75 +639,122 @@ int hs_encrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const int64_t
   });
 }
 
+}  // extern "C"
+
+namespace hs {
+// Encrypted SpMV of n independent requests (matrix, encrypted vector, key-set): the slot-wise
+// products, then every request's chunk programs (totalSum rotations) merged level by level into
+// batched rotations, then the masks and per-partition sums.  Results: one vector per request.
+static void spmv_many(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_matrix* const* m, const hs_ctvec* const* x,
+                      hipStream_t st, hs_ctvec** y) {
+  for (auto& v : g_counters) v = 0;
+  const size_t CW = ct_words(c);
+  struct Req {
+    int G, nP;
+    std::vector<std::vector<MicroOp>> progs;
+    std::vector<int> wt_base;
+    int nwt = 0;
+    DBuf vbuf, wtbuf;
+  };
+  std::vector<Req> rq(n);
+  int nlog = 0;
+  for (int r = 0; r < n; r++) {
+    Req& q = rq[r];
+    q.G = (int)m[r]->chunks.size();
+    q.nP = (int)m[r]->parts.size();
+    q.progs.resize(q.G);
+    q.wt_base.assign(q.G, -1);
+    for (int g = 0; g < q.G; g++) {
+      q.progs[g] = total_sum_program(c, m[r]->chunks[g].h, m[r]->chunks[g].c, &nlog);
+      if (q.progs[g].size() > 1) { q.wt_base[g] = q.nwt; q.nwt += 4; }
+    }
+    q.vbuf = DBuf(&c->pool, (size_t)std::max(q.G, 1) * CW * sizeof(u64));
+    q.wtbuf = DBuf(&c->pool, (size_t)std::max(q.nwt, 1) * CW * sizeof(u64));
+  }
+  auto buf = [&](int r, int g, int id) -> u64* {
+    Req& q = rq[r];
+    return id == 0 ? q.vbuf.as<u64>() + (size_t)g * CW : q.wtbuf.as<u64>() + (size_t)(q.wt_base[g] + id - 1) * CW;
+  };
+  // 1. slot-wise products (HE-CMult) of every chunk
+  for (int r = 0; r < n; r++) {
+    if (!rq[r].G) continue;
+    launch_mul_plain(c, x[r]->d, m[r]->d_pt, rq[r].vbuf.as<u64>(), rq[r].G, c->L, st);
+    g_counters[2]++;
+    g_counters[3] += rq[r].G;
+  }
+  // 2. totalSum of all chunks of all requests, level by level
+  size_t nlev = 0;
+  for (auto& q : rq)
+    for (auto& p : q.progs) nlev = std::max(nlev, p.size() - 1);
+  std::vector<std::vector<RotItem>> levels(nlev);
+  for (size_t lv = 0; lv < nlev; lv++)
+    for (int r = 0; r < n; r++)
+      for (int g = 0; g < rq[r].G; g++) {
+        const auto& prog = rq[r].progs[g];
+        if (lv + 1 >= prog.size()) continue;
+        const MicroOp& op = prog[lv];
+        RotItem it{};
+        it.in = buf(r, g, op.in);
+        it.out = buf(r, g, op.out);
+        it.addend = op.addend >= 0 ? buf(r, g, op.addend) : nullptr;
+        it.key = ks[r]->gk[op.pow2];
+        it.galois = (u32)galois_pow2(c, op.pow2);
+        levels[lv].push_back(it);
+      }
+  run_rotation_levels(c, levels, st);
+  g_counters[1] = nlog;
+  // 3. masks and the per-partition sums
+  std::vector<const u64*> wptr;
+  std::vector<DBuf> keep;
+  for (int r = 0; r < n; r++) {
+    Req& q = rq[r];
+    if (!q.nP) continue;
+    std::vector<const u64*> wp(std::max(q.G, 1), nullptr);
+    for (int g = 0; g < q.G; g++) wp[g] = buf(r, g, q.progs[g].back().in);
+    std::vector<int> pc0(q.nP), pnc(q.nP);
+    for (int p = 0; p < q.nP; p++) { pc0[p] = m[r]->parts[p].chunk0; pnc[p] = m[r]->parts[p].nchunks; }
+    keep.emplace_back(&c->pool, wp.size() * sizeof(u64*));
+    h2d(keep.back().as<const u64*>(), wp.data(), wp.size(), st);
+    keep.emplace_back(&c->pool, q.nP * sizeof(int));
+    h2d(keep.back().as<int>(), pc0.data(), q.nP, st);
+    const int* dpc0 = keep.back().as<int>();
+    keep.emplace_back(&c->pool, q.nP * sizeof(int));
+    h2d(keep.back().as<int>(), pnc.data(), q.nP, st);
+    const int* dpnc = keep.back().as<int>();
+    launch_mask_acc(c, keep[keep.size() - 3].as<const u64*>(), c->prm.agg_mode == 0 ? m[r]->d_mask : nullptr, dpc0, dpnc, y[r]->d, q.nP, st);
+    g_counters[2]++;
+    g_counters[4] += c->prm.agg_mode == 0 ? q.G : 0;
+  }
+  HS_CHECK_HIP(hipStreamSynchronize(st));
+}
+}  // namespace hs
+
+extern "C" {
+
 int hs_he_spmv(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* x, void* stream, hs_ctvec** y) {
+  return hs_he_spmv_batch(c, 1, &ks, &m, &x, stream, y);
+}
+
+int hs_he_spmv_batch(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_matrix* const* m, const hs_ctvec* const* x,
+                     void* stream, hs_ctvec** y) {
   return guarded([&] {
-    HS_REQUIRE(c && ks && m && x && y, HS_EINVAL, "null argument");
-    *y = nullptr;
-    HS_REQUIRE(ks->ctx == c && m->ctx == c && x->ctx == c, HS_EKEY, "handles from another context");
-    HS_REQUIRE(x->n == (i64)m->chunks.size(), HS_EINVAL, "the vector must hold one ciphertext per chunk");
-    HS_REQUIRE(!m->encrypted, HS_EINVAL, "encrypted matrix values: not supported by this build of hs_he_spmv");
-    hipStream_t st = S(stream);
-    for (auto& v : g_counters) v = 0;
-    const int G = (int)m->chunks.size();
-    const int nP = (int)m->parts.size();
-    const size_t CW = ct_words(c);
-    hs_ctvec* res = new_ctvec(c, nP);
+    HS_REQUIRE(c && n >= 0 && (n == 0 || (ks && m && x && y)), HS_EINVAL, "null argument");
+    for (int r = 0; r < n; r++) {
+      y[r] = nullptr;
+      HS_REQUIRE(ks[r] && m[r] && x[r], HS_EINVAL, "null handle in the batch");
+      HS_REQUIRE(ks[r]->ctx == c && m[r]->ctx == c && x[r]->ctx == c, HS_EKEY, "handles from another context");
+      HS_REQUIRE(x[r]->n == (i64)m[r]->chunks.size(), HS_EINVAL, "the vector must hold one ciphertext per chunk");
+      HS_REQUIRE(!m[r]->encrypted, HS_EINVAL, "encrypted matrix values: not supported by this build of hs_he_spmv");
+    }
+    std::vector<hs_ctvec*> out(n, nullptr);
     try {
-      // per chunk: totalSum program and buffers: V (product, contiguous over chunks) and, for
-      // chunks that rotate, WA, WB (accumulators) and TA, TB (intermediate rotations)
-      std::vector<std::vector<MicroOp>> progs(G);
-      int nlog = 0, nwt = 0;
-      std::vector<int> wt_base(G, -1);
-      for (int g = 0; g < G; g++) {
-        progs[g] = total_sum_program(c, m->chunks[g].h, m->chunks[g].c, &nlog);
-        if (progs[g].size() > 1) { wt_base[g] = nwt; nwt += 4; }
-      }
-      DBuf vbuf(&c->pool, (size_t)std::max(G, 1) * CW * sizeof(u64));
-      DBuf wtbuf(&c->pool, (size_t)std::max(nwt, 1) * CW * sizeof(u64));
-      auto buf = [&](int g, int id) -> u64* {
-        return id == 0 ? vbuf.as<u64>() + (size_t)g * CW : wtbuf.as<u64>() + (size_t)(wt_base[g] + id - 1) * CW;
-      };
-      // 1. slot-wise products of all chunks (HE-CMult)
-      launch_mul_plain(c, x->d, m->d_pt, vbuf.as<u64>(), G, c->L, st);
-      g_counters[2]++;
-      g_counters[3] += G;
-      // 2. totalSum, level by level across chunks
-      size_t nlev = 0;
-      for (auto& p : progs) nlev = std::max(nlev, p.size() - 1);
-      std::vector<std::vector<RotItem>> levels(nlev);
-      for (size_t lv = 0; lv < nlev; lv++) {
-        for (int g = 0; g < G; g++) {
-          if (lv + 1 >= progs[g].size()) continue;
-          const MicroOp& op = progs[g][lv];
-          RotItem it{};
-          it.in = buf(g, op.in);
-          it.out = buf(g, op.out);
-          it.addend = op.addend >= 0 ? buf(g, op.addend) : nullptr;
-          it.key = ks->gk[op.pow2];
-          it.galois = (u32)galois_pow2(c, op.pow2);
-          levels[lv].push_back(it);
-        }
-      }
-      run_rotation_levels(c, levels, st);
-      g_counters[1] = nlog;
-      // 3. masks and the per-partition sum
-      std::vector<const u64*> wptr(G);
-      for (int g = 0; g < G; g++) wptr[g] = buf(g, progs[g].back().in);
-      std::vector<int> pc0(nP), pnc(nP);
-      for (int p = 0; p < nP; p++) { pc0[p] = m->parts[p].chunk0; pnc[p] = m->parts[p].nchunks; }
-      DBuf dw(&c->pool, std::max(G, 1) * sizeof(u64*)), dpc0(&c->pool, nP * sizeof(int)), dpnc(&c->pool, nP * sizeof(int));
-      h2d(dw.as<const u64*>(), wptr.data(), G, st);
-      h2d(dpc0.as<int>(), pc0.data(), nP, st);
-      h2d(dpnc.as<int>(), pnc.data(), nP, st);
-      launch_mask_acc(c, dw.as<const u64*>(), c->prm.agg_mode == 0 ? m->d_mask : nullptr, dpc0.as<int>(), dpnc.as<int>(), res->d, nP, st);
-      g_counters[2]++;
-      g_counters[4] += c->prm.agg_mode == 0 ? G : 0;
-      HS_CHECK_HIP(hipStreamSynchronize(st));
+      for (int r = 0; r < n; r++) out[r] = new_ctvec(c, (i64)m[r]->parts.size());
+      spmv_many(c, n, ks, m, x, S(stream), out.data());
     } catch (...) {
-      hs_ctvec_destroy(res);
+      for (hs_ctvec* v : out) hs_ctvec_destroy(v);
       throw;
     }
-    *y = res;
+    for (int r = 0; r < n; r++) y[r] = out[r];
   });
 }
 

@@ -56,6 +56,7 @@ SIGNATURES = {
     "hs_matrix_export": (_int, [_vp, _int, _i64, _u64p, _i64]),
     "hs_encrypt": (_int, [_vp, _vp, _vp, _vp, _i64, _u64, _vp, _pp]),
     "hs_he_spmv": (_int, [_vp, _vp, _vp, _vp, _vp, _pp]),
+    "hs_he_spmv_batch": (_int, [_vp, _int, _pp, _pp, _pp, _vp, _pp]),
     "hs_decrypt": (_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp]),
     "hs_ctvec_count": (_int, [_vp, _i64p]),
     "hs_ct_export": (_int, [_vp, _i64, _u64p, _i64]),
@@ -260,6 +261,15 @@ def he_spmv(ctx, ks, m, x):
     h = ctypes.c_void_p()
     _check(lib.hs_he_spmv(ctx.h, ks.h, m.h, x.h, _stream(), ctypes.byref(h)))
     return CtVec(ctx, h)
+
+
+def he_spmv_batch(ctx, kss, ms, xs):
+    """n independent encrypted SpMVs in one call (rotations merged into shared batched launches)."""
+    n = len(ms)
+    arr = lambda hs: (ctypes.c_void_p * max(n, 1))(*[h.h for h in hs])
+    ys = (ctypes.c_void_p * max(n, 1))()
+    _check(lib.hs_he_spmv_batch(ctx.h, n, arr(kss), arr(ms), arr(xs), _stream(), ys))
+    return [CtVec(ctx, ctypes.c_void_p(ys[i])) for i in range(n)]
 
 
 def decrypt(ctx, ks, m, y, out):

@@ -271,3 +271,47 @@ def test_invalid_csr_rejected():
     rp = np.array([0, 2], np.int64)       # columns not ascending within the row
     with pytest.raises(H.HespmvError):
         H.Matrix(g, 1, 4, dev(rp, torch.int64), dev(np.array([2, 1], np.int32), torch.int32), dev(np.array([1, 1]), torch.int64))
+
+
+def _pack_and_encrypt(g, kg, w, seed):
+    M = gpu_matrix(g, kg, w)
+    x = H.encrypt(g, kg, M, dev(w["v"], torch.int64), seed)
+    return M, x
+
+
+@pytest.mark.parametrize("n_keysets", [1, 2])
+def test_batch_equals_individual_calls(pipeline, n_keysets):
+    """hs_he_spmv_batch over requests of mixed sizes (including an empty matrix and several
+    partitions) and key-sets returns, per request, exactly its own hs_he_spmv result."""
+    p = TINY
+    g, kg0, o = contexts(p)
+    kgs = [kg0] + ([g.keygen(8)] if n_keysets == 2 else [])
+    rng = np.random.default_rng(21)
+    reqs = []
+    for i, (R, C, nnz) in enumerate([(40, 30, 200), (10, 10, 0), (300, 300, 1500), (700, 200, 2000), (5, 80, 60), (256, 256, 2500)]):
+        rp, col, val = W.uniform_matrix(R, C, nnz, 7, rng)
+        w = dict(R=R, C=C, row_ptr=rp, col=col, val=val, v=rng.integers(-7, 8, C))
+        ks = kgs[i % len(kgs)]
+        M, x = _pack_and_encrypt(g, ks, w, 100 + i)
+        reqs.append((w, ks, M, x))
+    ys = H.he_spmv_batch(g, [r[1] for r in reqs], [r[2] for r in reqs], [r[3] for r in reqs])
+    for (w, ks, M, x), y in zip(reqs, ys):
+        solo = H.he_spmv(g, ks, M, x)
+        assert np.array_equal(y.export_all(), solo.export_all())
+        out = torch.zeros(w["R"], dtype=torch.int64, device="cuda")
+        H.decrypt(g, ks, M, y, out)
+        assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
+
+
+def test_batch64_workload_sample():
+    """Eight matrices of the 64-matrix batch generator on the 16384 ring: batch == individual,
+    and the decrypted results equal the integer SpMV."""
+    g, kg, o = contexts(RING16K)
+    ws = W.batch64(count=8, rmax=4096)
+    pairs = [_pack_and_encrypt(g, kg, w, 7 + i) for i, w in enumerate(ws)]
+    ys = H.he_spmv_batch(g, [kg] * len(ws), [p[0] for p in pairs], [p[1] for p in pairs])
+    for w, (M, x), y in zip(ws, pairs, ys):
+        assert np.array_equal(y.export_all(), H.he_spmv(g, kg, M, x).export_all())
+        out = torch.zeros(w["R"], dtype=torch.int64, device="cuda")
+        H.decrypt(g, kg, M, y, out)
+        assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
