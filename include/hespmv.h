@@ -190,10 +190,14 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
    HS_OPT_NTT_PATH     hs_ntt: 0 = automatic, 1 = one workgroup per limb, 2 = two-pass
    HS_OPT_KS_THRESHOLD automatic choice: two-pass when (L + K) x items of a level is below this
                        value (default 512)
+   HS_OPT_AUX_PATH     keygen, encoding, encryption, decryption: 0 = automatic, 1 = fused kernels
+                       with the limb in LDS, 2 = elementwise kernels around batched transforms
+                       (always used for N = 32768)
    HS_EINVAL for an unknown key or value. */
 #define HS_OPT_KS_PIPELINE 1
 #define HS_OPT_NTT_PATH 2
 #define HS_OPT_KS_THRESHOLD 3
+#define HS_OPT_AUX_PATH 4
 int hs_set_option(int key, int64_t value);
 
 /* Kernel timing: hs_profile(1) clears the records and brackets every subsequent kernel launch with

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhespmv.so")
-SOURCES = ["kernels.hip", "ks2.hip", "params.cpp", "capi.cpp", "profiler.cpp"]
+SOURCES = ["kernels.hip", "ks2.hip", "aux2.hip", "tensor.hip", "params.cpp", "capi.cpp", "profiler.cpp"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
     "-ffp-contract=off",                      # the FP64 modular products rely on unfused rounding

@@ -17,6 +17,7 @@ static thread_local int64_t g_counters[5] = {0, 0, 0, 0, 0};
 static std::atomic<int> g_opt_ks{0};    // key-switch pipeline: 0 auto, 1 one workgroup per limb, 2 two-pass
 static std::atomic<int> g_opt_ntt{0};   // hs_ntt path: 0 auto, 1 one workgroup per limb, 2 two-pass
 static std::atomic<int> g_opt_ks_threshold{512};  // auto: two-pass below this many (target x item) pairs
+static std::atomic<int> g_opt_aux{0};   // keygen/encode/encrypt/decrypt: 0 auto, 1 fused kernels, 2 split path
 
 template <class F>
 static int guarded(F&& f) {
@@ -103,6 +104,9 @@ static const u32 RELIN_ID = 255;
 static u64 galois_pow2(const hs_ctx* c, int i) { return pow_mod(3, 1ULL << i, 2 * c->N); }
 
 // ------------------------------------------------------------------ key generation
+static bool use_split(const hs_ctx* c);
+static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int inverse, hipStream_t st, std::vector<DBuf>& hold);
+
 static u64* make_ksk(hs_ctx* c, hs_keyset* ks, u32 key_id, int sprime_mode, u32 galois, hipStream_t st) {
   const int LK = c->L + c->K;
   const size_t N = c->N;
@@ -136,8 +140,18 @@ static u64* make_ksk(hs_ctx* c, hs_keyset* ks, u32 key_id, int sprime_mode, u32 
   }
   DBuf dargs(&c->pool, args.size() * sizeof(KskArgs));
   h2d(dargs.as<KskArgs>(), args.data(), args.size(), st);
-  launch_ksk_limbs(c, dargs.as<KskArgs>(), (int)args.size(), st);
-  HS_CHECK_HIP(hipStreamSynchronize(st));
+  if (use_split(c)) {
+    // e_j reduced to every modulus, transformed, then combined with a, s and s'
+    std::vector<DBuf> hold;
+    DBuf en(&c->pool, (size_t)c->dnum * LK * N * sizeof(u64));
+    launch_ints_to_limbs(c, e.as<int>(), (i64)N, c->dnum, en.as<u64>(), LK, 0, st);
+    ntt_any(c, en.as<u64>(), (i64)c->dnum * LK, LK, 0, 0, st, hold);
+    launch_ksk_combine(c, dargs.as<KskArgs>(), en.as<u64>(), (int)args.size(), st);
+    HS_CHECK_HIP(hipStreamSynchronize(st));
+  } else {
+    launch_ksk_limbs(c, dargs.as<KskArgs>(), (int)args.size(), st);
+    HS_CHECK_HIP(hipStreamSynchronize(st));
+  }
   return key;
 }
 
@@ -277,6 +291,98 @@ static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem
   HS_CHECK_HIP(hipStreamSynchronize(st));
 }
 
+// Transform helper: one-workgroup-per-limb kernels when the limb fits in LDS (unless the two-pass
+// path is requested), else the two-pass kernels with a scratch buffer kept in `hold` until the
+// caller synchronises.
+static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int inverse, hipStream_t st, std::vector<DBuf>& hold) {
+  if (rows <= 0) return;
+  if (!lds_limb_fits(c) || g_opt_ntt.load() == 2) {
+    hold.emplace_back(&c->pool, (size_t)rows * c->N * sizeof(double));
+    launch_ntt2(c, data, hold.back().as<double>(), rows, nl, mod0, inverse, st);
+  } else {
+    launch_ntt(c, data, rows, nl, mod0, inverse, st);
+  }
+}
+
+// keygen / encoding / encryption / decryption as elementwise kernels around batched transforms
+static bool use_split(const hs_ctx* c) { return !lds_limb_fits(c) || g_opt_aux.load() == 2; }
+
+// Exact ciphertext products a_i x b_i (NTT form [2][L][N] each) with relinearisation: n items,
+// keys[i] = the relinearisation key of item i.
+static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const* b, u64* const* out, const u64* const* rkeys,
+                         hipStream_t st) {
+  if (n <= 0) return;
+  HS_REQUIRE(c->has_tensor, HS_EPARAM, "parameters too large for the exact ciphertext product");
+  const size_t N = c->N;
+  const int L = c->L, T = c->n_mod;
+  const size_t LN = (size_t)L * N;
+  std::vector<DBuf> hold;
+  DBuf X(&c->pool, (size_t)n * 4 * LN * sizeof(u64));
+  for (int i = 0; i < n; i++) {
+    HS_CHECK_HIP(hipMemcpyAsync(X.as<u64>() + (size_t)i * 4 * LN, a[i], 2 * LN * sizeof(u64), hipMemcpyDeviceToDevice, st));
+    HS_CHECK_HIP(hipMemcpyAsync(X.as<u64>() + (size_t)i * 4 * LN + 2 * LN, b[i], 2 * LN * sizeof(u64), hipMemcpyDeviceToDevice, st));
+  }
+  ntt_any(c, X.as<u64>(), (i64)n * 4 * L, L, 0, 1, st, hold);
+  TensorConst C{};
+  C.qhat_inv = (const double2*)c->d_dec_inv; C.qhat = c->d_dec_hat; C.Q = c->d_dec_q; C.halfQ = c->d_t_halfq; C.WQ = c->tq_words;
+  C.mhat_inv = (const double2*)c->d_t_mhat_inv; C.mhat = c->d_t_mhat; C.M = c->d_t_m; C.halfM = c->d_t_halfm; C.WM = c->tm_words;
+  C.D = c->d_t_d; C.WD = c->td_words; C.mu = c->d_t_mu; C.WMU = c->tmu_words; C.WA = c->ta_words;
+  C.r64 = (const double2*)c->d_t_r64; C.T = T; C.L = L; C.t = c->t;
+  DBuf LIFT(&c->pool, (size_t)n * 4 * T * N * sizeof(u64));
+  launch_crt_lift(c, C, X.as<u64>(), LIFT.as<u64>(), n * 4, st);
+  ntt_any(c, LIFT.as<u64>(), (i64)n * 4 * T, T, 0, 0, st, hold);
+  DBuf PROD(&c->pool, (size_t)n * 3 * T * N * sizeof(u64));
+  launch_tensor(c, LIFT.as<u64>(), PROD.as<u64>(), n, T, st);
+  ntt_any(c, PROD.as<u64>(), (i64)n * 3 * T, T, 0, 1, st, hold);
+  DBuf D4(&c->pool, (size_t)n * 4 * LN * sizeof(u64));
+  launch_scale_round(c, C, PROD.as<u64>(), D4.as<u64>(), n, st);
+  ntt_any(c, D4.as<u64>(), (i64)n * 4 * L, L, 0, 0, st, hold);
+  std::vector<std::vector<RotItem>> lv(1);
+  for (int i = 0; i < n; i++) {
+    RotItem it{};
+    it.in = D4.as<u64>() + (size_t)i * 4 * LN;            // (d0, d2)
+    it.addend = D4.as<u64>() + (size_t)i * 4 * LN + 2 * LN;  // (0, d1)
+    it.out = out[i];
+    it.key = rkeys[i];
+    it.galois = 1;  // identity automorphism: a plain key switch of d2 under s^2 -> s
+    lv[0].push_back(it);
+  }
+  run_rotation_levels(c, lv, st);
+  g_counters[0] -= n;  // relinearisations are not rotations; counted separately below
+}
+
+// Pack + encode G chunks (mode 0 matrix values, 1 vector, 2 mask) into mod-t coefficients.
+static void pack_encode(hs_ctx* c, PackArgs pa, int G, hipStream_t st, std::vector<DBuf>& hold) {
+  if (use_split(c)) {
+    launch_pack_slots(c, pa, G, st);
+    ntt_any(c, pa.out, G, 1, c->n_mod, 1, st, hold);
+  } else {
+    launch_pack_encode(c, pa, G, st);
+  }
+}
+// Mod-t coefficients -> NTT-form plaintexts over the data primes.
+static void plain_ntt(hs_ctx* c, const u64* coef, u64* out, int G, hipStream_t st, std::vector<DBuf>& hold) {
+  if (use_split(c)) {
+    launch_lift_plain(c, coef, G, out, st);
+    ntt_any(c, out, (i64)G * c->L, c->L, 0, 0, st, hold);
+  } else {
+    launch_plain_ntt(c, coef, out, G, st);
+  }
+}
+// Public-key encryption of G encoded plaintexts (samples [G][3][N]: u, e0, e1).
+static void encrypt_coefs(hs_ctx* c, const u64* coef, const int* samples, const u64* pk, u64* out, int G, hipStream_t st,
+                          std::vector<DBuf>& hold) {
+  if (use_split(c)) {
+    hold.emplace_back(&c->pool, (size_t)G * 3 * c->L * c->N * sizeof(u64));
+    u64* prep = hold.back().as<u64>();
+    launch_enc_prep(c, coef, samples, G, prep, st);
+    ntt_any(c, prep, (i64)G * 3 * c->L, c->L, 0, 0, st, hold);
+    launch_enc_combine(c, prep, pk, out, G, st);
+  } else {
+    launch_encrypt(c, coef, samples, pk, out, G, st);
+  }
+}
+
 static hs_ctvec* new_ctvec(hs_ctx* c, i64 n) {
   hs_ctvec* v = new hs_ctvec();
   v->ctx = c;
@@ -352,7 +458,13 @@ int hs_keygen(hs_ctx* c, uint64_t seed, void* stream, hs_keyset** out) {
       DBuf scoef(&c->pool, N * sizeof(int));
       launch_sample_small(c, scoef.as<int>(), 1, (i64)N, seed, P_SK, 0, 1, 0, st);
       ks->sk = dmalloc<u64>((size_t)c->n_mod * N);
-      launch_sk_ntt(c, ks->sk, scoef.as<int>(), st);
+      std::vector<DBuf> hold;
+      if (use_split(c)) {
+        launch_ints_to_limbs(c, scoef.as<int>(), (i64)N, 1, ks->sk, c->n_mod, 0, st);
+        ntt_any(c, ks->sk, c->n_mod, c->n_mod, 0, 0, st, hold);
+      } else {
+        launch_sk_ntt(c, ks->sk, scoef.as<int>(), st);
+      }
       // public key: (pk0, pk1) = (e - a s, a) over the data primes
       ks->pk = dmalloc<u64>(2ULL * c->L * N);
       DBuf e(&c->pool, N * sizeof(int));
@@ -376,7 +488,15 @@ int hs_keygen(hs_ctx* c, uint64_t seed, void* stream, hs_keyset** out) {
       }
       DBuf dargs(&c->pool, args.size() * sizeof(KskArgs));
       h2d(dargs.as<KskArgs>(), args.data(), args.size(), st);
-      launch_ksk_limbs(c, dargs.as<KskArgs>(), (int)args.size(), st);
+      if (use_split(c)) {
+        DBuf en(&c->pool, (size_t)c->L * N * sizeof(u64));
+        launch_ints_to_limbs(c, e.as<int>(), (i64)N, 1, en.as<u64>(), c->L, 0, st);
+        ntt_any(c, en.as<u64>(), c->L, c->L, 0, 0, st, hold);
+        launch_ksk_combine(c, dargs.as<KskArgs>(), en.as<u64>(), (int)args.size(), st);
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+      } else {
+        launch_ksk_limbs(c, dargs.as<KskArgs>(), (int)args.size(), st);
+      }
       HS_CHECK_HIP(hipStreamSynchronize(st));
       for (int i = 0; i + 1 < c->logn; i++) ks->gk.push_back(make_ksk(c, ks, (u32)i, 1, (u32)galois_pow2(c, i), st));
       ks->rk = make_ksk(c, ks, RELIN_ID, 2, 0, st);
@@ -518,28 +638,30 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
       }
       // --- pack + encode (+ encrypt) every chunk; masks
       if (G) {
+        std::vector<DBuf> hold;
         DBuf coef(&c->pool, (size_t)G * N * sizeof(u64));
         PackArgs pa{};
         pa.va = M->d_va; pa.ci = M->d_ci; pa.v = nullptr; pa.cp = M->d_cp; pa.chunk = M->d_chunk;
         pa.out = coef.as<u64>(); pa.mode = 0;
-        launch_pack_encode(c, pa, G, st);
+        pack_encode(c, pa, G, st, hold);
         if (encrypt_values) {
           M->d_pt = dmalloc<u64>((size_t)G * ct_words(c));
           DBuf smp(&c->pool, (size_t)G * 3 * N * sizeof(int));
           launch_sample_small(c, smp.as<int>(), G, 3 * (i64)N, seed, P_ENC_U, 0, 1, 0, st);
           launch_sample_small(c, smp.as<int>() + N, G, 3 * (i64)N, seed, P_ENC_E0, 0, 1, 1, st);
           launch_sample_small(c, smp.as<int>() + 2 * N, G, 3 * (i64)N, seed, P_ENC_E1, 0, 1, 1, st);
-          launch_encrypt(c, coef.as<u64>(), smp.as<int>(), ks->pk, M->d_pt, G, st);
+          encrypt_coefs(c, coef.as<u64>(), smp.as<int>(), ks->pk, M->d_pt, G, st, hold);
           HS_CHECK_HIP(hipStreamSynchronize(st));
         } else {
           M->d_pt = dmalloc<u64>((size_t)G * c->L * N);
-          launch_plain_ntt(c, coef.as<u64>(), M->d_pt, G, st);
+          plain_ntt(c, coef.as<u64>(), M->d_pt, G, st, hold);
         }
         if (c->prm.agg_mode == 0) {
+          HS_CHECK_HIP(hipStreamSynchronize(st));
           pa.mode = 2;
-          launch_pack_encode(c, pa, G, st);
+          pack_encode(c, pa, G, st, hold);
           M->d_mask = dmalloc<u64>((size_t)G * c->L * N);
-          launch_plain_ntt(c, coef.as<u64>(), M->d_mask, G, st);
+          plain_ntt(c, coef.as<u64>(), M->d_mask, G, st, hold);
         }
         HS_CHECK_HIP(hipStreamSynchronize(st));
       }
@@ -619,16 +741,17 @@ int hs_encrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const int64_t
     hs_ctvec* x = new_ctvec(c, G);
     try {
       if (G) {
+        std::vector<DBuf> hold;
         DBuf coef(&c->pool, (size_t)G * N * sizeof(u64));
         PackArgs pa{};
         pa.va = m->d_va; pa.ci = m->d_ci; pa.v = v; pa.cp = m->d_cp; pa.chunk = m->d_chunk;
         pa.out = coef.as<u64>(); pa.mode = 1;
-        launch_pack_encode(c, pa, G, st);
+        pack_encode(c, pa, G, st, hold);
         DBuf smp(&c->pool, (size_t)G * 3 * N * sizeof(int));
         launch_sample_small(c, smp.as<int>(), G, 3 * (i64)N, seed, P_ENC_U, 0, 1, 0, st);
         launch_sample_small(c, smp.as<int>() + N, G, 3 * (i64)N, seed, P_ENC_E0, 0, 1, 1, st);
         launch_sample_small(c, smp.as<int>() + 2 * N, G, 3 * (i64)N, seed, P_ENC_E1, 0, 1, 1, st);
-        launch_encrypt(c, coef.as<u64>(), smp.as<int>(), ks->pk, x->d, G, st);
+        encrypt_coefs(c, coef.as<u64>(), smp.as<int>(), ks->pk, x->d, G, st, hold);
         HS_CHECK_HIP(hipStreamSynchronize(st));
       }
     } catch (...) {
@@ -675,13 +798,26 @@ static void spmv_many(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_mat
     Req& q = rq[r];
     return id == 0 ? q.vbuf.as<u64>() + (size_t)g * CW : q.wtbuf.as<u64>() + (size_t)(q.wt_base[g] + id - 1) * CW;
   };
-  // 1. slot-wise products (HE-CMult) of every chunk
+  // 1. slot-wise products of every chunk: HE-CMult, or HE-Mult + relinearisation when the matrix
+  //    values are encrypted (all such products of the batch in one exact-product call)
+  std::vector<const u64*> pa, pb, rk;
+  std::vector<u64*> po;
   for (int r = 0; r < n; r++) {
     if (!rq[r].G) continue;
-    launch_mul_plain(c, x[r]->d, m[r]->d_pt, rq[r].vbuf.as<u64>(), rq[r].G, c->L, st);
-    g_counters[2]++;
+    if (m[r]->encrypted) {
+      for (int g = 0; g < rq[r].G; g++) {
+        pa.push_back(m[r]->d_pt + (size_t)g * CW);
+        pb.push_back(x[r]->d + (size_t)g * CW);
+        po.push_back(rq[r].vbuf.as<u64>() + (size_t)g * CW);
+        rk.push_back(ks[r]->rk);
+      }
+    } else {
+      launch_mul_plain(c, x[r]->d, m[r]->d_pt, rq[r].vbuf.as<u64>(), rq[r].G, c->L, st);
+      g_counters[2]++;
+    }
     g_counters[3] += rq[r].G;
   }
+  if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), st);
   // 2. totalSum of all chunks of all requests, level by level
   size_t nlev = 0;
   for (auto& q : rq)
@@ -744,7 +880,6 @@ int hs_he_spmv_batch(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_matr
       HS_REQUIRE(ks[r] && m[r] && x[r], HS_EINVAL, "null handle in the batch");
       HS_REQUIRE(ks[r]->ctx == c && m[r]->ctx == c && x[r]->ctx == c, HS_EKEY, "handles from another context");
       HS_REQUIRE(x[r]->n == (i64)m[r]->chunks.size(), HS_EINVAL, "the vector must hold one ciphertext per chunk");
-      HS_REQUIRE(!m[r]->encrypted, HS_EINVAL, "encrypted matrix values: not supported by this build of hs_he_spmv");
     }
     std::vector<hs_ctvec*> out(n, nullptr);
     try {
@@ -771,7 +906,14 @@ int hs_decrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const hs_ctve
     if (!nP) return;
     const size_t N = c->N;
     DBuf X(&c->pool, (size_t)nP * c->L * N * sizeof(u64)), Mc(&c->pool, (size_t)nP * N * sizeof(u64));
-    launch_dec_phase(c, y->d, ks->sk, X.as<u64>(), nP, st);
+    std::vector<DBuf> hold;
+    const bool split = use_split(c);
+    if (split) {
+      launch_dec_prep(c, y->d, ks->sk, X.as<u64>(), nP, st);
+      ntt_any(c, X.as<u64>(), (i64)nP * c->L, c->L, 0, 1, st, hold);
+    } else {
+      launch_dec_phase(c, y->d, ks->sk, X.as<u64>(), nP, st);
+    }
     launch_dec_round(c, X.as<u64>(), Mc.as<u64>(), nP, st);
     std::vector<i64> pinfo(4ULL * nP);
     i64 rm_off = 0;
@@ -782,7 +924,12 @@ int hs_decrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const hs_ctve
     }
     DBuf dp(&c->pool, pinfo.size() * sizeof(i64));
     h2d(dp.as<i64>(), pinfo.data(), pinfo.size(), st);
-    launch_decode_scatter(c, Mc.as<u64>(), m->d_rm, dp.as<i64>(), out, nP, st);
+    if (split) {
+      ntt_any(c, Mc.as<u64>(), nP, 1, c->n_mod, 0, st, hold);
+      launch_slots_scatter(c, Mc.as<u64>(), m->d_rm, dp.as<i64>(), nP, out, st);
+    } else {
+      launch_decode_scatter(c, Mc.as<u64>(), m->d_rm, dp.as<i64>(), out, nP, st);
+    }
     HS_CHECK_HIP(hipStreamSynchronize(st));
   });
 }
@@ -855,6 +1002,10 @@ int hs_ntt(hs_ctx* c, uint64_t* d_limbs, int64_t n_polys, int mod0, int n_limbs,
 int hs_set_option(int key, int64_t value) {
   return guarded([&] {
     switch (key) {
+      case HS_OPT_AUX_PATH:
+        HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "path must be 0, 1 or 2");
+        g_opt_aux = (int)value;
+        break;
       case HS_OPT_KS_PIPELINE:
         HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "pipeline must be 0, 1 or 2");
         g_opt_ks = (int)value;
@@ -924,9 +1075,27 @@ int hs_rotate(hs_ctx* c, const hs_keyset* ks, const hs_ctvec* in, int64_t k, voi
 
 int hs_mul_ct(hs_ctx* c, const hs_keyset* ks, const hs_ctvec* a, const hs_ctvec* b, void* stream, hs_ctvec** out) {
   return guarded([&] {
-    (void)c; (void)ks; (void)a; (void)b; (void)stream;
-    if (out) *out = nullptr;
-    throw Error{HS_EINVAL, "hs_mul_ct: not available in this build"};
+    HS_REQUIRE(c && ks && a && b && out, HS_EINVAL, "null argument");
+    *out = nullptr;
+    HS_REQUIRE(ks->ctx == c && a->ctx == c && b->ctx == c, HS_EKEY, "handles from another context");
+    HS_REQUIRE(a->n == b->n, HS_EINVAL, "vectors of different lengths");
+    const size_t CW = ct_words(c);
+    hs_ctvec* r = new_ctvec(c, a->n);
+    try {
+      std::vector<const u64*> pa, pb, rk;
+      std::vector<u64*> po;
+      for (i64 i = 0; i < a->n; i++) {
+        pa.push_back(a->d + i * CW);
+        pb.push_back(b->d + i * CW);
+        po.push_back(r->d + i * CW);
+        rk.push_back(ks->rk);
+      }
+      mul_ct_batch(c, (int)a->n, pa.data(), pb.data(), po.data(), rk.data(), S(stream));
+    } catch (...) {
+      hs_ctvec_destroy(r);
+      throw;
+    }
+    *out = r;
   });
 }
 

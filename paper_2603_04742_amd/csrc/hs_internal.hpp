@@ -120,6 +120,17 @@ struct hs_ctx {
   double2* d_dec_inv = nullptr;
   hs::u64* d_dec_hat = nullptr;    // [L][dec_words]
   hs::u64* d_dec_q = nullptr;      // [dec_words] Q
+  // exact ciphertext product over the tensor basis (all n_mod moduli)
+  bool has_tensor = false;
+  int tq_words = 0, tm_words = 0, td_words = 0, tmu_words = 0, ta_words = 0;
+  hs::u64* d_t_halfq = nullptr;
+  double2* d_t_mhat_inv = nullptr;
+  hs::u64* d_t_mhat = nullptr;
+  hs::u64* d_t_m = nullptr;
+  hs::u64* d_t_halfm = nullptr;
+  hs::u64* d_t_d = nullptr;
+  hs::u64* d_t_mu = nullptr;
+  double2* d_t_r64 = nullptr;
   hs::Pool pool;
 };
 

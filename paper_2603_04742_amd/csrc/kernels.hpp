@@ -40,6 +40,27 @@ struct PackArgs {
   int mode;                  // 0 matrix values, 1 reorganised vector, 2 mask
 };
 
+// Constants of the exact ciphertext product (tensor.hip); device pointers.
+struct TensorConst {
+  const double2* qhat_inv;  // [L]  (Q/q_i)^-1 mod q_i
+  const u64* qhat;          // [L][WQ] Q/q_i
+  const u64* Q;             // [WQ]
+  const u64* halfQ;         // [WQ] floor(Q/2)
+  int WQ;
+  const double2* mhat_inv;  // [T]  (M/m)^-1 mod m
+  const u64* mhat;          // [T][WM] M/m
+  const u64* M;             // [WM + 1]
+  const u64* halfM;         // [WM] floor(M/2)
+  int WM;
+  const u64* D;             // [WD] 2Q
+  int WD;
+  const u64* mu;            // [WMU] floor(2^(64 WA) / 2Q)
+  int WMU, WA;
+  const double2* r64;       // [T] 2^64 mod m
+  int T, L;
+  u64 t;
+};
+
 // HIP-event timing of kernel launches (profiler.cpp)
 class ProfScope {
  public:
@@ -71,6 +92,20 @@ void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const K
 void launch_ntt2(const hs_ctx* c, u64* data, double* scratch, i64 rows, int nl, int mod0, int inverse, hipStream_t st);
 void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, double* T1, double* E, double* ACC, double* T2,
                           double* F, hipStream_t st);
+
+// split path (aux2.hip): elementwise prologues / epilogues around batched transforms
+void launch_ints_to_limbs(const hs_ctx* c, const int* src, i64 src_stride, int nobj, u64* out, int nl, int mod0, hipStream_t st);
+void launch_ksk_combine(const hs_ctx* c, const KskArgs* d_args, const u64* e_ntt, int count, hipStream_t st);
+void launch_pack_slots(const hs_ctx* c, const PackArgs& a, int nchunks, hipStream_t st);
+void launch_lift_plain(const hs_ctx* c, const u64* coef, int n_plain, u64* out, hipStream_t st);
+void launch_enc_prep(const hs_ctx* c, const u64* mcoef, const int* samples, int n_ct, u64* out, hipStream_t st);
+void launch_enc_combine(const hs_ctx* c, const u64* prep, const u64* pk, u64* out, int n_ct, hipStream_t st);
+void launch_dec_prep(const hs_ctx* c, const u64* ct, const u64* sk, u64* X, int n_ct, hipStream_t st);
+void launch_slots_scatter(const hs_ctx* c, const u64* Mntt, const int* rm, const i64* pinfo, int nparts, i64* y, hipStream_t st);
+// exact ciphertext product (tensor.hip)
+void launch_crt_lift(const hs_ctx* c, const TensorConst& C, const u64* x, u64* out, int rows, hipStream_t st);
+void launch_tensor(const hs_ctx* c, const u64* lift, u64* prod, int items, int T, hipStream_t st);
+void launch_scale_round(const hs_ctx* c, const TensorConst& C, const u64* prod, u64* out, int items, hipStream_t st);
 
 void launch_dec_phase(const hs_ctx* c, const u64* ct, const u64* sk, u64* X, int n_ct, hipStream_t st);
 void launch_dec_round(const hs_ctx* c, const u64* X, u64* M, int n_ct, hipStream_t st);

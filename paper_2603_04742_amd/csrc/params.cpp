@@ -103,6 +103,71 @@ static u64 words_mod(const Words& a, u64 m) {
   for (size_t i = a.size(); i-- > 0;) r = ((r << 64) | a[i]) % m;
   return (u64)r;
 }
+static Words words_shl1(const Words& a, u64 bit_in) {
+  Words r(a.size() + 1, 0);
+  u64 carry = bit_in;
+  for (size_t i = 0; i < a.size(); i++) {
+    r[i] = (a[i] << 1) | carry;
+    carry = a[i] >> 63;
+  }
+  r[a.size()] = carry;
+  while (r.size() > 1 && r.back() == 0) r.pop_back();
+  return r;
+}
+static Words words_sub(const Words& a, const Words& b) {  // a >= b
+  Words r(a.size(), 0);
+  u64 br = 0;
+  for (size_t i = 0; i < a.size(); i++) {
+    const u64 y = i < b.size() ? b[i] : 0;
+    const u64 d = a[i] - y;
+    const u64 b1 = a[i] < y;
+    r[i] = d - br;
+    const u64 b2 = d < br;
+    br = b1 | b2;
+  }
+  while (r.size() > 1 && r.back() == 0) r.pop_back();
+  return r;
+}
+static Words words_add(const Words& a, const Words& b) {
+  Words r(std::max(a.size(), b.size()) + 1, 0);
+  u64 c = 0;
+  for (size_t i = 0; i + 1 < r.size(); i++) {
+    const u64 x = i < a.size() ? a[i] : 0, y = i < b.size() ? b[i] : 0;
+    const u64 s = x + y;
+    const u64 c1 = s < x;
+    r[i] = s + c;
+    const u64 c2 = r[i] < s;
+    c = c1 | c2;
+  }
+  r.back() = c;
+  while (r.size() > 1 && r.back() == 0) r.pop_back();
+  return r;
+}
+static Words words_shr1(const Words& a) {
+  Words r(a.size(), 0);
+  for (size_t i = 0; i < a.size(); i++) r[i] = (a[i] >> 1) | (i + 1 < a.size() ? a[i + 1] << 63 : 0);
+  while (r.size() > 1 && r.back() == 0) r.pop_back();
+  return r;
+}
+// floor(2^s / d) by binary long division
+static Words words_pow2_div(int s, const Words& d) {
+  Words q(s / 64 + 1, 0), r{0};
+  for (int bit = s; bit >= 0; bit--) {
+    r = words_shl1(r, bit == s ? 1 : 0);
+    if (words_cmp(r, d) >= 0) {
+      r = words_sub(r, d);
+      q[bit / 64] |= 1ULL << (bit % 64);
+    }
+  }
+  while (q.size() > 1 && q.back() == 0) q.pop_back();
+  return q;
+}
+static std::vector<u64> padded(const Words& w, int n) {
+  std::vector<u64> r(n, 0);
+  for (size_t i = 0; i < w.size() && (int)i < n; i++) r[i] = w[i];
+  return r;
+}
+
 static u64 product_mod(const std::vector<u64>& ms, u64 m) {
   u64 r = 1 % m;
   for (u64 x : ms) r = mul_mod(r, x % m, m);
@@ -266,11 +331,51 @@ void build_ctx(hs_ctx* c) {
   c->d_dec_inv = upload(dinv);
   c->d_dec_hat = upload(dhat);
   c->d_dec_q = upload(dq);
+
+  // exact ciphertext product: CRT over all n_mod moduli (M > 4 N Q^2), Barrett division by 2Q
+  {
+    const int T = c->n_mod;
+    const Words M = words_product(c->mod);
+    const int WQ = c->dec_words;
+    const int WM = (int)M.size() + 1;
+    Words tM = words_mul_small(M, c->t);
+    const Words A_max = words_add(tM, Q);
+    const int WA = (int)A_max.size() + 1;
+    const Words D = words_shl1(Q, 0);
+    const int WD = (int)D.size();
+    const Words mu = words_pow2_div(64 * WA, D);
+    const int WMU = (int)mu.size();
+    const int kMaxW = 24;
+    if (WM + 1 <= kMaxW && WA <= kMaxW && WMU + 1 <= kMaxW && WQ + 1 <= kMaxW) {
+      std::vector<double2> minv(T), r64(T);
+      std::vector<u64> mhat((size_t)T * WM, 0);
+      for (int i = 0; i < T; i++) {
+        std::vector<u64> others;
+        for (int j = 0; j < T; j++)
+          if (j != i) others.push_back(c->mod[j]);
+        const Words h = words_product(others);
+        minv[i] = make_const(inv_mod(words_mod(h, c->mod[i]), c->mod[i]), c->mod[i]);
+        for (size_t w = 0; w < h.size(); w++) mhat[(size_t)i * WM + w] = h[w];
+        r64[i] = make_const((u64)(((u128)1 << 64) % c->mod[i]), c->mod[i]);
+      }
+      c->tq_words = WQ; c->tm_words = WM; c->td_words = WD; c->tmu_words = WMU; c->ta_words = WA;
+      c->d_t_halfq = upload(padded(words_shr1(Q), WQ));
+      c->d_t_mhat_inv = upload(minv);
+      c->d_t_mhat = upload(mhat);
+      c->d_t_m = upload(padded(M, WM + 1));
+      c->d_t_halfm = upload(padded(words_shr1(M), WM));
+      c->d_t_d = upload(padded(D, WD));
+      c->d_t_mu = upload(padded(mu, WMU + 1));
+      c->d_t_r64 = upload(r64);
+      c->has_tensor = true;
+    }
+  }
 }
 
 void free_ctx(hs_ctx* c) {
   void* ptrs[] = {c->d_tab, c->d_tw, c->d_slot_pos, c->d_qdt, c->d_pmod, c->d_pinv, c->d_up_inv,
-                  c->d_up_hat, c->d_dn_inv, c->d_dn_hat, c->d_dec_inv, c->d_dec_hat, c->d_dec_q};
+                  c->d_up_hat, c->d_dn_inv, c->d_dn_hat, c->d_dec_inv, c->d_dec_hat, c->d_dec_q,
+                  c->d_t_halfq, c->d_t_mhat_inv, c->d_t_mhat, c->d_t_m, c->d_t_halfm, c->d_t_d, c->d_t_mu, c->d_t_r64};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   c->pool.release_all();

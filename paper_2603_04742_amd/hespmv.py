@@ -290,7 +290,7 @@ def rotate(ctx, ks, x, k):
     return CtVec(ctx, h)
 
 
-OPT_KS_PIPELINE, OPT_NTT_PATH, OPT_KS_THRESHOLD = 1, 2, 3
+OPT_KS_PIPELINE, OPT_NTT_PATH, OPT_KS_THRESHOLD, OPT_AUX_PATH = 1, 2, 3, 4
 
 
 def set_option(key, value):
@@ -313,6 +313,13 @@ def profile_summary():
         name, cnt, ms = line.split()
         out[name] = (int(cnt), float(ms))
     return out
+
+
+def mul_ct(ctx, ks, a, b):
+    """Slot-wise product of two ciphertext vectors (exact scaled tensor + relinearisation)."""
+    h = ctypes.c_void_p()
+    _check(lib.hs_mul_ct(ctx.h, ks.h, a.h, b.h, _stream(), ctypes.byref(h)))
+    return CtVec(ctx, h)
 
 
 def last_counters():

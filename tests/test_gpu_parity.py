@@ -315,3 +315,137 @@ def test_batch64_workload_sample():
         out = torch.zeros(w["R"], dtype=torch.int64, device="cuda")
         H.decrypt(g, kg, M, y, out)
         assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
+
+
+@pytest.fixture
+def split_path():
+    """Force keygen/encoding/encryption/decryption onto the elementwise + two-pass-NTT path (the
+    path every N = 32768 ring takes), at ring sizes the oracle handles quickly."""
+    H.set_option(H.OPT_AUX_PATH, 2)
+    H.set_option(H.OPT_NTT_PATH, 2)
+    yield
+    H.set_option(H.OPT_AUX_PATH, 0)
+    H.set_option(H.OPT_NTT_PATH, 0)
+
+
+@pytest.mark.parametrize("p", [SMALL, TINY, (10, 3, 50, 2, 0)])
+def test_split_path_keygen_and_protocol(p, split_path, pipeline):
+    g = H.Context(*p[:4], agg_mode=p[4])
+    o = O.Context(*p[:4], agg_mode=p[4])
+    kg = g.keygen(19)
+    o.keygen(19)
+    assert np.array_equal(kg.export(0), o.sk_ntt())
+    assert np.array_equal(kg.export(1), o.pk())
+    for i in (0, p[0] - 2):
+        assert np.array_equal(kg.export(2, i), o.ksk(i))
+    assert np.array_equal(kg.export(3), o.ksk(-1))
+    _cache[(p, 19)] = (g, kg, o)
+    rng = np.random.default_rng(3)
+    R = 3 * (1 << p[0]) // 4
+    rp, col, val = W.uniform_matrix(R, R, 6 * R, 7, rng)
+    check_protocol_seeded(p, 19, dict(R=R, C=R, row_ptr=rp, col=col, val=val, v=rng.integers(-7, 8, R)))
+
+
+def check_protocol_seeded(p, seed, w):
+    saved = _cache.get((p, 7))
+    _cache[(p, 7)] = _cache[(p, seed)]
+    try:
+        check_protocol(p, w)
+    finally:
+        if saved is None:
+            del _cache[(p, 7)]
+        else:
+            _cache[(p, 7)] = saved
+
+
+@pytest.mark.parametrize("p", [(6, 3, 50, 1, 0), (8, 4, 40, 2, 0), (10, 3, 50, 2, 0)])
+def test_mul_ct_parity(p):
+    """Exact scaled tensor + relinearisation against the oracle, bit for bit (K = 1 and K = 2
+    digits), and the product decrypts to the slot-wise product."""
+    logn, L, bits, K, agg = p
+    g = H.Context(logn, L, bits, K, agg_mode=agg)
+    o = O.Context(logn, L, bits, K, agg_mode=agg)
+    assert g.moduli() == o.moduli()
+    kg = g.keygen(5)
+    o.keygen(5)
+    N = 1 << logn
+    rng = np.random.default_rng(logn)
+    x, y = rng.integers(-40, 40, N), rng.integers(-40, 40, N)
+    ca = np.concatenate([o.encrypt(o.encode(x), 1, i) for i in range(2)])
+    cb = np.concatenate([o.encrypt(o.encode(y), 2, i) for i in range(2)])
+    r = H.mul_ct(g, kg, H.CtVec.from_host(g, ca, 2), H.CtVec.from_host(g, cb, 2))
+    cs = o.ct_size()
+    for i in range(2):
+        want = o.ct_mul_ct(ca[i * cs:(i + 1) * cs], cb[i * cs:(i + 1) * cs])
+        assert np.array_equal(r.export(i), want), i
+    assert np.array_equal(o.decode(o.decrypt(r.export(0))), (x * y) % 65537)
+
+
+@pytest.mark.parametrize("p", [(10, 3, 50, 1, 0), (10, 4, 50, 2, 0)])
+def test_protocol_both_encrypted(p, pipeline):
+    """Matrix values encrypted too (HE-Mult + relinearisation, then masks): every stage bit for
+    bit against the oracle, on a small 5-point Laplacian."""
+    g = H.Context(*p[:4], agg_mode=p[4])
+    o = O.Context(*p[:4], agg_mode=p[4])
+    kg = g.keygen(23)
+    o.keygen(23)
+    w = W.laplace256(n=30)   # 900 rows: two partitions of <= 512
+    M = H.Matrix(g, w["R"], w["C"], dev(w["row_ptr"], torch.int64), dev(w["col"], torch.int32), dev(w["val"], torch.int64), True, kg, 31)
+    OM = O.Matrix(o, w["R"], w["C"], w["row_ptr"], w["col"], w["val"], True, 31)
+    assert M.info() == (OM.n_parts(), OM.n_chunks())
+    for k in range(M.info()[1]):
+        assert np.array_equal(M.export(0, k), OM.pt(k, encrypted=True))
+    x = H.encrypt(g, kg, M, dev(w["v"], torch.int64), 41)
+    ox = OM.encrypt_vector(w["v"], 41)
+    assert np.array_equal(x.export_all(), ox)
+    y = H.he_spmv(g, kg, M, x)
+    oy, _ = OM.he_spmv(ox)
+    assert np.array_equal(y.export_all(), oy)
+    out = torch.zeros(w["R"], dtype=torch.int64, device="cuda")
+    H.decrypt(g, kg, M, y, out)
+    assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
+
+
+def test_laplace256_full_size():
+    """The both-encrypted 5-point Laplacian on a 256 x 256 grid at N = 32768 (12 x 50-bit data
+    primes, 2 special): keys sampled against the oracle, the decrypted result equal to the
+    integer SpMV, and the first chunk's encryption and exact product + relinearisation against
+    the oracle, limb for limb."""
+    p = (15, 12, 50, 2, 0)
+    g = H.Context(*p[:4], agg_mode=0)
+    o = O.Context(*p[:4], agg_mode=0)
+    assert g.moduli() == o.moduli()
+    kg = g.keygen(29)
+    o.keygen(29)
+    assert np.array_equal(kg.export(0), o.sk_ntt())
+    assert np.array_equal(kg.export(2, 3), o.ksk(3))
+    assert np.array_equal(kg.export(3), o.ksk(-1))
+    w = W.laplace256()
+    M = H.Matrix(g, w["R"], w["C"], dev(w["row_ptr"], torch.int64), dev(w["col"], torch.int32), dev(w["val"], torch.int64), True, kg, 31)
+    nparts, nchunks = M.info()
+    assert nparts == 4
+    x = H.encrypt(g, kg, M, dev(w["v"], torch.int64), 41)
+    y = H.he_spmv(g, kg, M, x)
+    out = torch.zeros(w["R"], dtype=torch.int64, device="cuda")
+    H.decrypt(g, kg, M, y, out)
+    assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
+    # sampled limb parity: chunk 0 of partition 0 (matrix ciphertext, vector ciphertext, product)
+    s = (1 << 15) // 2
+    rp = w["row_ptr"][:s + 1]
+    VA, CI, RM, CP = O.cssc(s, rp, w["col"][:rp[-1]], w["val"][:rp[-1]])
+    ch = O.chunks(CP, s)
+    start, c, h = ch[0]
+    assert M.chunk(0) == (0, start, c, h)
+    slots_a = np.zeros(1 << 15, np.int64)
+    slots_v = np.zeros(1 << 15, np.int64)
+    for b in range(c):
+        col_ = start + b
+        cnt = min(CP[col_ + 1] - CP[col_], h)
+        slots_a[b * h:b * h + cnt] = VA[CP[col_]:CP[col_] + cnt]
+        slots_v[b * h:b * h + cnt] = w["v"][CI[CP[col_]:CP[col_] + cnt]]
+    ca = o.encrypt(o.encode(slots_a), 31, 0)
+    cv = o.encrypt(o.encode(slots_v), 41, 0)
+    assert np.array_equal(M.export(0, 0), ca)
+    assert np.array_equal(x.export(0), cv)
+    got = H.mul_ct(g, kg, H.CtVec.from_host(g, ca, 1), H.CtVec.from_host(g, cv, 1)).export(0)
+    assert np.array_equal(got, o.ct_mul_ct(ca, cv))
