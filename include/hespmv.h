@@ -148,6 +148,27 @@ int hs_he_spmv(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ct
 int hs_he_spmv_batch(hs_ctx* ctx, int n, const hs_keyset* const* ks, const hs_matrix* const* m,
                      const hs_ctvec* const* x, void* stream, hs_ctvec** y);
 
+/* ---------------------------------------------------------------- serving (continuous batching) */
+typedef struct hs_server hs_server;
+/* Start a server on `stream` (its own worker thread).  Engine ticks admit queued requests while
+   the device footprint of the active ones (product, accumulator and rotation buffers, results)
+   stays within hbm_budget_bytes (one request is always admitted) and at most max_active run; each
+   tick advances every active request by one power-of-two rotation, all in one batched level, so
+   requests that arrive while others run share their launches.  Every result is identical to the
+   request's own hs_he_spmv. */
+int hs_server_create(hs_ctx* ctx, int64_t hbm_budget_bytes, int max_active, void* stream, hs_server** out);
+/* Queue one request; the handles must stay alive until hs_server_wait returns for it.  *id
+   receives the request id. */
+int hs_server_submit(hs_server* s, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* x, int64_t* id);
+/* Block until request `id` is done; *y receives its result (caller owns it).  times (optional,
+   host): submit, admission and completion time in seconds since the server started. */
+int hs_server_wait(hs_server* s, int64_t id, hs_ctvec** y, double times[3]);
+/* out = [ticks, most requests active at once, admitted, completed, bytes in use]; *now (optional)
+   = seconds since the server started. */
+int hs_server_stats(hs_server* s, int64_t out[5], double* now);
+/* Drain the queue, stop the worker and free the server (results not yet collected are freed). */
+void hs_server_destroy(hs_server* s);
+
 /* ---------------------------------------------------------------- key holder */
 /* Decrypt the per-partition results and scatter them with the row map: out (device int64[rows])
    receives y = A v reduced into (-t/2, t/2]; rows without nonzeros receive 0. */

@@ -4,7 +4,13 @@
 #include <cstring>
 #include <numeric>
 #include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <memory>
 #include <stdexcept>
+#include <thread>
+#include <unordered_map>
 
 #include "kernels.hpp"
 
@@ -1118,6 +1124,273 @@ int hs_last_counters(int64_t out[5]) {
     HS_REQUIRE(out, HS_EINVAL, "null argument");
     for (int i = 0; i < 5; i++) out[i] = g_counters[i];
   });
+}
+
+}  // extern "C"
+
+// ====================================================================== continuous-batching server
+// Requests (key-set, packed matrix, encrypted vector) are queued by hs_server_submit.  A worker
+// thread runs engine ticks: it admits queued requests while their device footprint fits the
+// budget, launches the slot-wise products of the newly admitted ones, advances every active
+// request's chunk programs by one power-of-two rotation in a single batched rotation level, and
+// retires the requests whose programs have finished (mask products and per-partition sums).
+// Requests that arrive while others run join at the next tick, so their rotations share launches.
+namespace hs {
+struct SrvReq {
+  i64 id = 0;
+  const hs_keyset* ks = nullptr;
+  const hs_matrix* m = nullptr;
+  const hs_ctvec* x = nullptr;
+  hs_ctvec* y = nullptr;
+  std::vector<std::vector<MicroOp>> progs;
+  std::vector<size_t> pc;
+  std::vector<int> wt_base;
+  DBuf vbuf, wtbuf;
+  size_t footprint = 0;
+  double t_submit = 0, t_admit = 0, t_done = 0;
+  int status = 0;  // 0 queued, 1 active, 2 done, <0 error code
+  std::string err;
+};
+}  // namespace hs
+
+struct hs_server {
+  hs_ctx* ctx = nullptr;
+  hipStream_t st = nullptr;
+  size_t budget = 0, used = 0;
+  int max_active = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<std::shared_ptr<hs::SrvReq>> queue;
+  std::vector<std::shared_ptr<hs::SrvReq>> active;
+  std::unordered_map<hs::i64, std::shared_ptr<hs::SrvReq>> all;
+  hs::i64 next_id = 1;
+  bool stop = false;
+  std::thread worker;
+  std::chrono::steady_clock::time_point t0;
+  hs::i64 ticks = 0, max_conc = 0, admitted = 0, completed = 0;
+  double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
+};
+
+namespace hs {
+static size_t request_footprint(const hs_ctx* c, const hs_matrix* m, int* nwt_out) {
+  const size_t CW = ct_words(c) * sizeof(u64);
+  int nwt = 0;
+  for (const hs_chunk& ch : m->chunks)
+    if (ch.c > 1) nwt += 4;
+  if (nwt_out) *nwt_out = nwt;
+  return ((size_t)m->chunks.size() + nwt + m->parts.size()) * CW;
+}
+
+static void server_tick(hs_server* S) {
+  hs_ctx* c = S->ctx;
+  const size_t CW = ct_words(c);
+  std::vector<std::shared_ptr<SrvReq>> fresh;
+  {
+    std::unique_lock<std::mutex> lk(S->mu);
+    while (!S->queue.empty() && (int)S->active.size() < S->max_active) {
+      auto& r = S->queue.front();
+      if (!S->active.empty() && S->used + r->footprint > S->budget) break;  // admission by footprint
+      S->used += r->footprint;
+      r->status = 1;
+      r->t_admit = S->now();
+      S->active.push_back(r);
+      fresh.push_back(r);
+      S->queue.pop_front();
+      S->admitted++;
+    }
+    S->max_conc = std::max<i64>(S->max_conc, (i64)S->active.size());
+  }
+  // set up and launch the products of the newly admitted requests
+  std::vector<const u64*> pa, pb, rk;
+  std::vector<u64*> po;
+  for (auto& r : fresh) {
+    const hs_matrix* m = r->m;
+    const int G = (int)m->chunks.size();
+    r->progs.resize(G);
+    r->pc.assign(G, 0);
+    r->wt_base.assign(G, -1);
+    int nwt = 0;
+    for (int g = 0; g < G; g++) {
+      r->progs[g] = total_sum_program(c, m->chunks[g].h, m->chunks[g].c, nullptr);
+      if (r->progs[g].size() > 1) { r->wt_base[g] = nwt; nwt += 4; }
+    }
+    r->vbuf = DBuf(&c->pool, (size_t)std::max(G, 1) * CW * sizeof(u64));
+    r->wtbuf = DBuf(&c->pool, (size_t)std::max(nwt, 1) * CW * sizeof(u64));
+    r->y = new_ctvec(c, (i64)m->parts.size());
+    if (!G) continue;
+    if (m->encrypted) {
+      for (int g = 0; g < G; g++) {
+        pa.push_back(m->d_pt + (size_t)g * CW);
+        pb.push_back(r->x->d + (size_t)g * CW);
+        po.push_back(r->vbuf.as<u64>() + (size_t)g * CW);
+        rk.push_back(r->ks->rk);
+      }
+    } else {
+      launch_mul_plain(c, r->x->d, m->d_pt, r->vbuf.as<u64>(), G, c->L, S->st);
+    }
+  }
+  if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), S->st);
+  // one rotation level across every active request
+  auto buf = [&](SrvReq* r, int g, int id) -> u64* {
+    return id == 0 ? r->vbuf.as<u64>() + (size_t)g * CW : r->wtbuf.as<u64>() + (size_t)(r->wt_base[g] + id - 1) * CW;
+  };
+  std::vector<std::vector<RotItem>> level(1);
+  for (auto& r : S->active)
+    for (size_t g = 0; g < r->progs.size(); g++) {
+      auto& prog = r->progs[g];
+      if (r->pc[g] + 1 >= prog.size()) continue;
+      const MicroOp& op = prog[r->pc[g]++];
+      RotItem it{};
+      it.in = buf(r.get(), (int)g, op.in);
+      it.out = buf(r.get(), (int)g, op.out);
+      it.addend = op.addend >= 0 ? buf(r.get(), (int)g, op.addend) : nullptr;
+      it.key = r->ks->gk[op.pow2];
+      it.galois = (u32)galois_pow2(c, op.pow2);
+      level[0].push_back(it);
+    }
+  if (!level[0].empty()) run_rotation_levels(c, level, S->st);
+  // retire finished requests
+  std::vector<std::shared_ptr<SrvReq>> done;
+  std::vector<DBuf> keep;
+  for (auto& r : S->active) {
+    bool fin = true;
+    for (size_t g = 0; g < r->progs.size(); g++) fin &= (r->pc[g] + 1 >= r->progs[g].size());
+    if (!fin) continue;
+    const hs_matrix* m = r->m;
+    const int G = (int)m->chunks.size(), nP = (int)m->parts.size();
+    if (nP) {
+      std::vector<const u64*> wp(std::max(G, 1), nullptr);
+      for (int g = 0; g < G; g++) wp[g] = buf(r.get(), g, r->progs[g].back().in);
+      std::vector<int> pc0(nP), pnc(nP);
+      for (int p = 0; p < nP; p++) { pc0[p] = m->parts[p].chunk0; pnc[p] = m->parts[p].nchunks; }
+      keep.emplace_back(&c->pool, wp.size() * sizeof(u64*));
+      const u64* const* dw = keep.back().as<const u64*>();
+      h2d(keep.back().as<const u64*>(), wp.data(), wp.size(), S->st);
+      keep.emplace_back(&c->pool, nP * sizeof(int));
+      int* dpc0 = keep.back().as<int>();
+      h2d(dpc0, pc0.data(), nP, S->st);
+      keep.emplace_back(&c->pool, nP * sizeof(int));
+      int* dpnc = keep.back().as<int>();
+      h2d(dpnc, pnc.data(), nP, S->st);
+      launch_mask_acc(c, dw, c->prm.agg_mode == 0 ? m->d_mask : nullptr, dpc0, dpnc, r->y->d, nP, S->st);
+    }
+    done.push_back(r);
+  }
+  HS_CHECK_HIP(hipStreamSynchronize(S->st));
+  const double t = S->now();
+  std::lock_guard<std::mutex> lk(S->mu);
+  for (auto& r : done) {
+    r->vbuf.reset();
+    r->wtbuf.reset();
+    r->t_done = t;
+    r->status = 2;
+    S->used -= r->footprint;
+    S->completed++;
+    S->active.erase(std::find(S->active.begin(), S->active.end(), r));
+  }
+  S->ticks++;
+  if (!done.empty()) S->cv_done.notify_all();
+}
+
+static void server_loop(hs_server* S) {
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      S->cv_work.wait(lk, [&] { return S->stop || !S->queue.empty() || !S->active.empty(); });
+      if (S->stop && S->queue.empty() && S->active.empty()) return;
+    }
+    try {
+      server_tick(S);
+    } catch (const Error& e) {
+      std::lock_guard<std::mutex> lk(S->mu);
+      for (auto& r : S->active) { r->status = e.code; r->err = e.msg; S->used -= r->footprint; }
+      for (auto& r : S->queue) { r->status = e.code; r->err = e.msg; }
+      S->active.clear();
+      S->queue.clear();
+      S->cv_done.notify_all();
+    }
+  }
+}
+}  // namespace hs
+
+extern "C" {
+
+int hs_server_create(hs_ctx* c, int64_t hbm_budget_bytes, int max_active, void* stream, hs_server** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && out && hbm_budget_bytes > 0 && max_active > 0, HS_EINVAL, "bad argument");
+    *out = nullptr;
+    hs_server* srv = new hs_server();
+    srv->ctx = c;
+    srv->st = (hipStream_t)stream;
+    srv->budget = (size_t)hbm_budget_bytes;
+    srv->max_active = max_active;
+    srv->t0 = std::chrono::steady_clock::now();
+    srv->worker = std::thread([srv] {
+      (void)hipSetDevice(srv->ctx->device);
+      server_loop(srv);
+    });
+    *out = srv;
+  });
+}
+
+int hs_server_submit(hs_server* S, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* x, int64_t* id) {
+  return guarded([&] {
+    HS_REQUIRE(S && ks && m && x && id, HS_EINVAL, "null argument");
+    HS_REQUIRE(ks->ctx == S->ctx && m->ctx == S->ctx && x->ctx == S->ctx, HS_EKEY, "handles from another context");
+    HS_REQUIRE(x->n == (i64)m->chunks.size(), HS_EINVAL, "the vector must hold one ciphertext per chunk");
+    auto r = std::make_shared<SrvReq>();
+    r->ks = ks; r->m = m; r->x = x;
+    r->footprint = request_footprint(S->ctx, m, nullptr);
+    std::lock_guard<std::mutex> lk(S->mu);
+    HS_REQUIRE(!S->stop, HS_EINVAL, "server is shutting down");
+    r->id = S->next_id++;
+    r->t_submit = S->now();
+    S->queue.push_back(r);
+    S->all[r->id] = r;
+    *id = r->id;
+    S->cv_work.notify_one();
+  });
+}
+
+int hs_server_wait(hs_server* S, int64_t id, hs_ctvec** y, double times[3]) {
+  return guarded([&] {
+    HS_REQUIRE(S && y, HS_EINVAL, "null argument");
+    *y = nullptr;
+    std::unique_lock<std::mutex> lk(S->mu);
+    auto it = S->all.find(id);
+    HS_REQUIRE(it != S->all.end(), HS_EINVAL, "unknown request id");
+    auto r = it->second;
+    S->cv_done.wait(lk, [&] { return r->status == 2 || r->status < 0; });
+    S->all.erase(it);
+    if (r->status < 0) {
+      if (r->y) hs_ctvec_destroy(r->y);
+      throw Error{r->status, r->err};
+    }
+    *y = r->y;
+    if (times) { times[0] = r->t_submit; times[1] = r->t_admit; times[2] = r->t_done; }
+  });
+}
+
+int hs_server_stats(hs_server* S, int64_t out[5], double* now) {
+  return guarded([&] {
+    HS_REQUIRE(S && out, HS_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(S->mu);
+    out[0] = S->ticks; out[1] = S->max_conc; out[2] = S->admitted; out[3] = S->completed; out[4] = (int64_t)S->used;
+    if (now) *now = S->now();
+  });
+}
+
+void hs_server_destroy(hs_server* S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+    S->cv_work.notify_all();
+  }
+  if (S->worker.joinable()) S->worker.join();
+  for (auto& kv : S->all)
+    if (kv.second->y) hs_ctvec_destroy(kv.second->y);
+  delete S;
 }
 
 }  // extern "C"

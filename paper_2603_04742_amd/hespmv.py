@@ -69,6 +69,11 @@ SIGNATURES = {
     "hs_last_counters": (_int, [_i64p]),
     "hs_profile": (_int, [_int]),
     "hs_set_option": (_int, [_int, _i64]),
+    "hs_server_create": (_int, [_vp, _i64, _int, _vp, _pp]),
+    "hs_server_submit": (_int, [_vp, _vp, _vp, _vp, _i64p]),
+    "hs_server_wait": (_int, [_vp, _i64, _pp, ctypes.POINTER(ctypes.c_double)]),
+    "hs_server_stats": (_int, [_vp, _i64p, ctypes.POINTER(ctypes.c_double)]),
+    "hs_server_destroy": (None, [_vp]),
     "hs_profile_summary": (_int, [ctypes.c_char_p, _i64, _i64p]),
 }
 
@@ -320,6 +325,47 @@ def mul_ct(ctx, ks, a, b):
     h = ctypes.c_void_p()
     _check(lib.hs_mul_ct(ctx.h, ks.h, a.h, b.h, _stream(), ctypes.byref(h)))
     return CtVec(ctx, h)
+
+
+class Server:
+    """Continuous-batching server (hs_server_*): submit() queues a request, wait() returns its
+    result and (submit, admit, done) times."""
+
+    def __init__(self, ctx, hbm_budget_bytes=64 << 30, max_active=256):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib.hs_server_create(ctx.h, hbm_budget_bytes, max_active, _stream(), ctypes.byref(h)))
+        self.h = h
+        self._keep = {}
+
+    def submit(self, ks, m, x):
+        rid = ctypes.c_int64()
+        _check(lib.hs_server_submit(self.h, ks.h, m.h, x.h, ctypes.byref(rid)))
+        self._keep[rid.value] = (ks, m, x)
+        return rid.value
+
+    def wait(self, rid):
+        y = ctypes.c_void_p()
+        t = (ctypes.c_double * 3)()
+        try:
+            _check(lib.hs_server_wait(self.h, rid, ctypes.byref(y), t))
+        finally:
+            self._keep.pop(rid, None)
+        return CtVec(self.ctx, y), (t[0], t[1], t[2])
+
+    def stats(self):
+        out = np.zeros(5, np.int64)
+        now = ctypes.c_double()
+        _check(lib.hs_server_stats(self.h, out.ctypes.data_as(_i64p), ctypes.byref(now)))
+        return dict(zip(["ticks", "max_active", "admitted", "completed", "bytes_in_use"], (int(v) for v in out)), now=now.value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib.hs_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def last_counters():

@@ -449,3 +449,52 @@ def test_laplace256_full_size():
     assert np.array_equal(x.export(0), cv)
     got = H.mul_ct(g, kg, H.CtVec.from_host(g, ca, 1), H.CtVec.from_host(g, cv, 1)).export(0)
     assert np.array_equal(got, o.ct_mul_ct(ca, cv))
+
+
+def _serve_mix(budget, max_active, stagger_s):
+    import time as _t
+    p = TINY
+    g, kg0, o = contexts(p)
+    kgs = [kg0, g.keygen(9)]
+    rng = np.random.default_rng(77)
+    reqs = []
+    for i, (R, nnz) in enumerate([(200, 900), (600, 3000), (50, 100), (300, 2000), (1000, 3000), (90, 400), (256, 2500), (700, 1400)]):
+        rp, col, val = W.uniform_matrix(R, R, nnz, 15, rng)
+        w = dict(R=R, C=R, row_ptr=rp, col=col, val=val, v=rng.integers(-15, 16, R))
+        ks = kgs[i % 2]
+        M, x = _pack_and_encrypt(g, ks, w, 300 + i)
+        reqs.append((w, ks, M, x))
+    srv = H.Server(g, budget, max_active)
+    ids = []
+    for w, ks, M, x in reqs:
+        ids.append(srv.submit(ks, M, x))
+        _t.sleep(stagger_s)
+    outs = [srv.wait(i) for i in ids]
+    stats = srv.stats()
+    srv.close()
+    for (w, ks, M, x), (y, times) in zip(reqs, outs):
+        assert times[0] <= times[1] <= times[2]
+        solo = H.he_spmv(g, ks, M, x)
+        assert np.array_equal(y.export_all(), solo.export_all())
+        out = torch.zeros(w["R"], dtype=torch.int64, device="cuda")
+        H.decrypt(g, ks, M, y, out)
+        assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
+    return stats
+
+
+def test_server_results_equal_solo_in_the_mix():
+    """Continuous batching: requests arriving while others run are admitted at the next tick and
+    share rotation launches; each result equals the request's own hs_he_spmv, bit for bit."""
+    stats = _serve_mix(64 << 30, 64, 0.0)
+    assert stats["completed"] == 8 and stats["max_active"] >= 2
+
+
+def test_server_staggered_arrivals():
+    stats = _serve_mix(64 << 30, 64, 0.001)
+    assert stats["completed"] == 8
+
+
+def test_server_admission_by_footprint():
+    """A budget below any two requests' footprint admits one request at a time."""
+    stats = _serve_mix(1, 64, 0.0)
+    assert stats["completed"] == 8 and stats["max_active"] == 1
