@@ -45,7 +45,12 @@ def main():
     ap.add_argument("--workload", default="zipf16k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batched-vs-plain measurement")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the serving run (Poisson arrivals at 200/s; 10000 for the full stream; 0 skips)")
     ap.add_argument("--profile-only", action="store_true", help="run warmup + steps only (for rocprofv3)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="with --profile-only: also copy 256 MiB once (device to device), the known-size kernel used to "
+                         "scale rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the encrypted-SpMV path here has no multi-GPU mode "
@@ -100,6 +105,13 @@ def main():
         sys.exit(1)
     print("bench: %.3f ms/step" % ms_per_step, file=sys.stderr, flush=True)
     if args.profile_only:
+        if args.copy_calibration:
+            a = torch.ones(32 << 20, dtype=torch.int64, device=dev)
+            b = torch.empty_like(a)
+            torch.cuda.synchronize()
+            b.copy_(a)
+            torch.cuda.synchronize()
+            print("bench: copied %d bytes for counter calibration" % (a.numel() * 8), file=sys.stderr, flush=True)
         return
 
     # per-stage split (separate, synchronised passes; not part of the timed steps)
@@ -143,28 +155,23 @@ def main():
     # roofline of the dominant kernel of the timed steps
     dom, (dcount, dms) = max(prof.items(), key=lambda kv: kv[1][1])
     avg_ms = dms / dcount
-    LK = L + K
-    dnum = (L + K - 1) // K
-    # algorithmic bytes per launch of the key-switch kernels (per rotation item of the level):
-    # modup+inner product: key 2*dnum*(L+K)*N*8 + digits L*N*8 + rotated c1 own limbs L*N*8
-    #                      + accumulators 2*(L+K)*N*8
-    per_item = {
-        "k_modup_ip": 2 * dnum * LK * N * 8 + 2 * L * N * 8 + 2 * LK * N * 8,
-        "k_rot_intt": 2 * L * N * 8,
-        "k_moddown_ntt": (2 * L * N * 8) * 2 + 2 * L * N * 8 + 2 * K * N * 8,
-        "k_moddown_intt": 2 * K * N * 8 * 2,
-    }
-    rotation_items = counters["key_switches"]
+    per_item = keyswitch_kernel_bytes(L, K, N)
     launches_per_step = dcount / args.steps
     roof = None
     if dom in per_item:
-        items_per_launch = rotation_items / launches_per_step
+        items_per_launch = counters["key_switches"] / launches_per_step
         alg = per_item[dom] * items_per_launch
         achieved = alg / (avg_ms * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": None,
                 "avg_launch_ms": round(avg_ms, 4), "launches_per_step": launches_per_step,
-                "algorithmic_bytes_per_launch": int(alg)}
+                "rotation_items_per_launch": round(items_per_launch, 3),
+                "algorithmic_bytes_per_item": int(per_item[dom]), "algorithmic_bytes_per_launch": int(alg)}
+    ks_ms = sum(ms for k, (cnt, ms) in prof.items() if k in per_item) / args.steps
+    ks_unit = 2 * ((L + K - 1) // K) * (L + K) * N * 8 + 4 * L * N * 8   # key + ct in + ct out (per key switch)
+    keyswitch = {"key_switches_per_step": counters["key_switches"], "ms_per_step": round(ks_ms, 4),
+                 "algorithmic_GBps": round(counters["key_switches"] * ks_unit / (ks_ms * 1e-3) / 1e9, 1),
+                 "algorithmic_bytes_per_key_switch": ks_unit}
     kernel_ms = {k: round(ms / args.steps, 4) for k, (cnt, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
 
     result = {
@@ -188,12 +195,37 @@ def main():
         "ntt": {"GBps": round(ntt_gbps, 1), "hbm_frac": round(ntt_gbps / HBM_PEAK_GBPS, 4), "limbs_per_launch": nl * npoly,
                 "avg_launch_ms": round(ntt_ms, 4), "bytes_per_limb": 16 * N},
         "roofline": roof,
+        "keyswitch_unit": keyswitch,
     }
     if args.workload == "zipf16k" and not args.no_batch:
         result["batched_vs_plain"] = batched_vs_plain(H, W, torch, dev)
+    if args.workload == "zipf16k" and args.serve_requests > 0:
+        result["serving"] = serving(H, W, torch, dev, args.serve_requests)
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(w, logn, L, bits, K, agg)
     print(json.dumps(result), flush=True)
+
+
+def keyswitch_kernel_bytes(L, K, N):
+    """Compulsory HBM bytes per rotation item of each key-switch kernel (its inputs read once and its
+    outputs written once), limb = N u64 or double words.  dnum = ceil(L/K) digits of K primes."""
+    limb = N * 8
+    LK, dnum = L + K, (L + K - 1) // K
+    ext = dnum * (LK - K)   # extended digit limbs (ModUp output)
+    key = 2 * dnum * LK     # key-switching key limbs
+    return {
+        # two-pass pipeline
+        "k2_rot_intt_low": (L + L) * limb,
+        "k2_modup_high": (L + ext) * limb,
+        "k2_ip_low": (ext + L + key + 2 * L + 2 * K) * limb,
+        "k2_moddown_high": (2 * K + 2 * L) * limb,
+        "k2_final_low": (2 * L + 2 * L + L + 2 * L) * limb,
+        # one-workgroup-per-limb pipeline
+        "k_rot_intt": (L + L) * limb,
+        "k_modup_ip": (L + L + key + 2 * LK) * limb,
+        "k_moddown_intt": (2 * K + 2 * K) * limb,
+        "k_moddown_ntt": (2 * K + 2 * L + L + 2 * L) * limb,
+    }
 
 
 def batched_vs_plain(H, W, torch, dev, reps=3):
@@ -237,6 +269,77 @@ def batched_vs_plain(H, W, torch, dev, reps=3):
             "batched_spmv_per_s": round(len(ms) / t_batch, 2), "plain_spmv_per_s": round(len(ms) / t_plain, 2),
             "batched_ms": round(t_batch * 1e3, 2), "plain_ms": round(t_plain * 1e3, 2),
             "speedup": round(t_plain / t_batch, 2), "decrypt_check": ok}
+
+
+def serving(H, W, torch, dev, n_requests, rate=200.0, n_keysets=8, pool=16):
+    """Serving: Poisson arrivals at `rate` req/s over 8 key-sets (keys resident), each request an
+    encrypted SpMV with rows = cols log-uniform in [1024, 32768] and Zipf(1.2) column degrees (8 nnz
+    per column).  Matrices come from a pool of `pool` packed matrices whose sizes are the quantiles
+    of the stream's sizes (each request takes the nearest); vectors are encrypted beforehand per
+    (matrix, key-set) pair (client work, untimed).  Latency = completion - submission on the
+    server clock; the driver submits each request at its arrival time."""
+    import threading
+    ctx = H.Context(14, 6, 50, 1, agg_mode=0)
+    kss = [ctx.keygen(0x5E7 + k) for k in range(n_keysets)]
+    arrivals, keyset, sizes = W.serve_stream(n_requests, rate, n_keysets)
+    pool_sizes = np.unique(np.quantile(sizes, (np.arange(pool) + 0.5) / pool).round().astype(np.int64))
+    mats = []
+    for j, R in enumerate(pool_sizes):
+        w = W.serve_request(j, int(R))
+        m = H.Matrix(ctx, w["R"], w["C"], torch.from_numpy(w["row_ptr"]).to(dev), torch.from_numpy(w["col"].astype(np.int32)).to(dev),
+                     torch.from_numpy(w["val"]).to(dev))
+        mats.append((w, m))
+    pick = np.abs(np.log(sizes)[:, None] - np.log(pool_sizes)[None, :]).argmin(1)
+    xs = {}
+    for j, k in sorted(set(zip(pick.tolist(), keyset.tolist()))):
+        w, m = mats[j]
+        xs[(j, k)] = H.encrypt(ctx, kss[k], m, torch.from_numpy(w["v"]).to(dev), 7000 + 16 * j + k)
+    torch.cuda.synchronize()
+    srv = H.Server(ctx, 96 << 30, 1024)
+    ids = [None] * n_requests
+    lat, done_t, results = [], [], {}
+    check = set(range(0, n_requests, max(1, n_requests // 8)))
+
+    def waiter():
+        for i in range(n_requests):
+            while ids[i] is None:
+                time.sleep(0.0002)
+            y, (ts, ta, td) = srv.wait(ids[i])
+            lat.append(td - ts)
+            done_t.append((ts, td))
+            if i in check:
+                results[i] = y
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t_start = time.perf_counter()
+    late = 0.0
+    for i in range(n_requests):
+        dt = t_start + arrivals[i] - time.perf_counter()
+        if dt > 0:
+            time.sleep(dt)
+        else:
+            late = max(late, -dt)
+        j, k = int(pick[i]), int(keyset[i])
+        ids[i] = srv.submit(kss[k], mats[j][1], xs[(j, k)])
+    th.join()
+    st = srv.stats()
+    srv.close()
+    ok = True
+    for i, y in results.items():
+        j, k = int(pick[i]), int(keyset[i])
+        w, m = mats[j]
+        out = torch.zeros(w["R"], dtype=torch.int64, device=dev)
+        H.decrypt(ctx, kss[k], m, y, out)
+        ok &= bool(torch.equal(out.cpu(), torch.from_numpy(W.spmv_mod_t(w))))
+    span = max(t for _, t in done_t) - min(t for t, _ in done_t)
+    lat_ms = np.array(lat) * 1e3
+    return {"workload": "serve: %d requests, Poisson %.0f req/s, %d key-sets (N=16384, 6x50-bit + 1, keys resident), rows log-uniform "
+                        "[1024,32768], Zipf(1.2) 8 nnz/col; %d pooled matrices" % (n_requests, rate, n_keysets, len(mats)),
+            "throughput_req_per_s": round(n_requests / span, 2), "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
+            "p99_ms": round(float(np.percentile(lat_ms, 99)), 3), "mean_ms": round(float(lat_ms.mean()), 3),
+            "max_active": st["max_active"], "engine_ticks": st["ticks"], "driver_max_late_ms": round(late * 1e3, 2),
+            "decrypt_check": ok}
 
 
 def cpu_baseline(w, logn, L, bits, K, agg):
