@@ -66,8 +66,22 @@ __device__ __forceinline__ double canon(double x, ModD m) {
   return r < 0.0 ? r + m.q : r;
 }
 
-__device__ __forceinline__ double u2d(u64 x) { return (double)x; }           // x < 2^53
-__device__ __forceinline__ u64 d2u(double x) { return (u64)x; }              // 0 <= x < 2^53
+// Residue <-> double for integers in [0, 2^52): the integer is the mantissa of 2^52 + x, so
+// each direction is one integer and one floating-point operation.
+__device__ __forceinline__ double u2d(u64 x) {
+  return __longlong_as_double((long long)(x | 0x4330000000000000ULL)) - 4503599627370496.0;
+}
+__device__ __forceinline__ u64 d2u(double x) {
+  return (u64)__double_as_longlong(x + 4503599627370496.0) ^ 0x4330000000000000ULL;
+}
+
+// Twiddle tables are global memory; loading through an address-space-1 pointer gives global
+// (not flat) loads, which do not hold up the LDS wait counter.
+typedef const double __attribute__((address_space(1)))* gdbl_ptr;
+__device__ __forceinline__ double2 ldtw(const double2* p, int i) {
+  const gdbl_ptr g = (gdbl_ptr)(const double*)(p + i);
+  return double2{g[0], g[1]};
+}
 
 __device__ __forceinline__ u32 brev_bits(u32 x, int bits) { return __brev(x) >> (32 - bits); }
 
@@ -202,6 +216,375 @@ __device__ void lds_ntt_inv(double* s, int logn, const double2* __restrict__ tw,
     __syncthreads();
   }
 }
+
+// ---------------------------------------------------------------- compile-time transforms
+// For the ring sizes that fill a workgroup (N = 16 NT) every round parameter is a constant:
+// element offsets become immediates, the loops unroll fully and the data source of the first round
+// and the sink of the last round can be global memory, saving two LDS passes.  Rounds split LOGN
+// into ceil(LOGN / 4) near-equal parts (14 -> 4,4,3,3).
+//
+// Forward reductions run before global stages 2, 5, 8, 11 (inputs |x| <= q): a stage adds at most
+// 0.625 q, so twiddle operands stay <= 1.75 q < 2^51 and outputs are |x| <= 2.375 q + 1.
+
+__host__ __device__ constexpr int ilog2c(int x) { return x <= 1 ? 0 : 1 + ilog2c(x >> 1); }
+__host__ __device__ constexpr int st_rounds(int logn) { return (logn + 3) / 4; }
+__host__ __device__ constexpr int st_rbits(int logn, int r) {  // bits of round r
+  return logn / st_rounds(logn) + (r < logn % st_rounds(logn) ? 1 : 0);
+}
+__host__ __device__ constexpr int st_first(int logn, int r) {  // first stage of round r (forward)
+  return r == 0 ? 0 : st_first(logn, r - 1) + st_rbits(logn, r - 1);
+}
+__host__ __device__ constexpr bool fwd_reduces_before(int st) { return st >= 2 && (st - 2) % 3 == 0; }
+
+// Element access of a round: element base | (u << LO) for u < 2^R, base with zero bits [LO, LO+R).
+// In LDS with one pad per 16 doubles the offset of u is the constant X + (X >> 4), X = u << LO.
+struct LdsIO {
+  double* s;
+  template <int R, int LO>
+  __device__ __forceinline__ void get(double (&x)[1 << R], int base) const {
+    const double* p = s + lpad(base);
+#pragma unroll
+    for (int u = 0; u < (1 << R); u++) x[u] = p[(u << LO) + ((u << LO) >> 4)];
+  }
+  template <int R, int LO>
+  __device__ __forceinline__ void put(const double (&x)[1 << R], int base) const {
+    double* p = s + lpad(base);
+#pragma unroll
+    for (int u = 0; u < (1 << R); u++) p[(u << LO) + ((u << LO) >> 4)] = x[u];
+  }
+};
+// Canonical u64 residues in global memory.
+struct U64In {
+  const u64* g;
+  template <int R, int LO>
+  __device__ __forceinline__ void get(double (&x)[1 << R], int base) const {
+#pragma unroll
+    for (int u = 0; u < (1 << R); u++) x[u] = u2d(g[base + (u << LO)]);
+  }
+};
+struct U64Out {
+  u64* g;
+  ModD m;
+  template <int R, int LO>
+  __device__ __forceinline__ void put(const double (&x)[1 << R], int base) const {
+#pragma unroll
+    for (int u = 0; u < (1 << R); u++) g[base + (u << LO)] = d2u(canon(x[u], m));
+  }
+};
+
+// Stages [ST0, ST0 + R) of the forward transform on one register group (hb = base >> (LO + R)).
+template <int R, int ST0>
+__device__ __forceinline__ void ct_group(double (&x)[1 << R], int hb, const double2* __restrict__ tw, ModD m) {
+#pragma unroll
+  for (int k = 0; k < R; k++) {
+    if (fwd_reduces_before(ST0 + k)) {
+#pragma unroll
+      for (int u = 0; u < (1 << R); u++) x[u] = reduce(x[u], m);
+    }
+    const double2* twk = tw + (1 << (ST0 + k)) + (hb << k);
+#pragma unroll
+    for (int j = 0; j < (1 << k); j++) {
+      const double2 w = ldtw(twk, j);
+#pragma unroll
+      for (int v = 0; v < (1 << (R - 1 - k)); v++) {
+        const int u = (j << (R - k)) | v;
+        const int u2 = u | (1 << (R - 1 - k));
+        const double t = mul_tw(x[u2], w.x, w.y, m);
+        x[u2] = x[u] - t;
+        x[u] = x[u] + t;
+      }
+    }
+  }
+}
+
+// Stages [ST0, ST0 + R) of the inverse transform (Gentleman-Sande, stage s pairs bit s).
+template <int R, int ST0, int LOGN, bool LAST>
+__device__ __forceinline__ void gs_group(double (&x)[1 << R], int hb, const double2* __restrict__ tw, double2 ninv, ModD m) {
+#pragma unroll
+  for (int k = 0; k < R; k++) {
+    const double2* twk = tw + ((1 << LOGN) >> (ST0 + k + 1)) + (hb << (R - 1 - k));
+#pragma unroll
+    for (int j = 0; j < (1 << (R - 1 - k)); j++) {
+      const double2 w = ldtw(twk, j);
+#pragma unroll
+      for (int v = 0; v < (1 << k); v++) {
+        const int u = (j << (k + 1)) | v;
+        const int u2 = u | (1 << k);
+        const double a = x[u], b = x[u2];
+        x[u] = reduce(a + b, m);
+        x[u2] = mul_tw(a - b, w.x, w.y, m);
+      }
+    }
+  }
+  if (LAST) {
+#pragma unroll
+    for (int u = 0; u < (1 << R); u++) x[u] = mul_tw(x[u], ninv.x, ninv.y, m);
+  }
+}
+
+// Forward stages [ST0, ST0 + R) over TPT tasks per thread starting at task sg0 (a task is the
+// register group of element base | (u << LO), LO = LOGN - ST0 - R).
+template <int LOGN, int NT, int ST0, int R, int TPT, class In, class Out>
+__device__ __forceinline__ void fwd_round_g(const In& in, const Out& out, const double2* __restrict__ tw, ModD m, int sg0, int tid) {
+  constexpr int LO = LOGN - ST0 - R;
+#pragma unroll
+  for (int it = 0; it < TPT; it++) {
+    const int sg = sg0 + tid + it * NT;
+    const int base = ((sg >> LO) << (LO + R)) | (sg & ((1 << LO) - 1));
+    double x[1 << R];
+    in.template get<R, LO>(x, base);
+    ct_group<R, ST0>(x, sg >> LO, tw, m);
+    out.template put<R, LO>(x, base);
+  }
+}
+
+// Inverse stages [ST0, ST0 + R) (stage s pairs bit s, so LO = ST0), same task scheme.
+template <int LOGN, int NT, int ST0, int R, int TPT, bool LAST, class In, class Out>
+__device__ __forceinline__ void inv_round_g(const In& in, const Out& out, const double2* __restrict__ tw, double2 ninv, ModD m, int sg0, int tid) {
+  constexpr int LO = ST0;
+#pragma unroll
+  for (int it = 0; it < TPT; it++) {
+    const int sg = sg0 + tid + it * NT;
+    const int base = ((sg >> LO) << (LO + R)) | (sg & ((1 << LO) - 1));
+    double x[1 << R];
+    in.template get<R, LO>(x, base);
+    gs_group<R, LO, LOGN, LAST>(x, sg >> LO, tw, ninv, m);
+    out.template put<R, LO>(x, base);
+  }
+}
+
+// Round r of the whole-limb schedule.
+template <int LOGN, int NT, int RD, class In, class Out>
+__device__ __forceinline__ void fwd_round_c(const In& in, const Out& out, const double2* __restrict__ tw, ModD m, int tid) {
+  constexpr int R = st_rbits(LOGN, RD);
+  static_assert((1 << (LOGN - R)) % NT == 0, "round does not tile the workgroup");
+  fwd_round_g<LOGN, NT, st_first(LOGN, RD), R, (1 << (LOGN - R)) / NT>(in, out, tw, m, 0, tid);
+}
+template <int LOGN, int NT, int RD, class In, class Out>
+__device__ __forceinline__ void inv_round_c(const In& in, const Out& out, const double2* __restrict__ tw, double2 ninv, ModD m, int tid) {
+  constexpr int R = st_rbits(LOGN, RD);
+  static_assert((1 << (LOGN - R)) % NT == 0, "round does not tile the workgroup");
+  inv_round_g<LOGN, NT, st_first(LOGN, RD), R, (1 << (LOGN - R)) / NT, RD == st_rounds(LOGN) - 1>(in, out, tw, ninv, m, 0, tid);
+}
+
+template <int LOGN, int NT, int RD, class In, class Out>
+__device__ __forceinline__ void fwd_rounds_from(const In& in, const Out& out, double* s, const double2* __restrict__ tw, ModD m, int tid) {
+  constexpr int NR = st_rounds(LOGN);
+  if constexpr (NR == 1) {
+    fwd_round_c<LOGN, NT, 0>(in, out, tw, m, tid);
+  } else if constexpr (RD == 0) {
+    fwd_round_c<LOGN, NT, 0>(in, LdsIO{s}, tw, m, tid);
+    __syncthreads();
+    fwd_rounds_from<LOGN, NT, 1>(in, out, s, tw, m, tid);
+  } else if constexpr (RD == NR - 1) {
+    fwd_round_c<LOGN, NT, RD>(LdsIO{s}, out, tw, m, tid);
+  } else {
+    fwd_round_c<LOGN, NT, RD>(LdsIO{s}, LdsIO{s}, tw, m, tid);
+    __syncthreads();
+    fwd_rounds_from<LOGN, NT, RD + 1>(in, out, s, tw, m, tid);
+  }
+}
+
+template <int LOGN, int NT, int RD, class In, class Out>
+__device__ __forceinline__ void inv_rounds_from(const In& in, const Out& out, double* s, const double2* __restrict__ tw, double2 ninv,
+                                                ModD m, int tid) {
+  constexpr int NR = st_rounds(LOGN);
+  if constexpr (NR == 1) {
+    inv_round_c<LOGN, NT, 0>(in, out, tw, ninv, m, tid);
+  } else if constexpr (RD == 0) {
+    inv_round_c<LOGN, NT, 0>(in, LdsIO{s}, tw, ninv, m, tid);
+    __syncthreads();
+    inv_rounds_from<LOGN, NT, 1>(in, out, s, tw, ninv, m, tid);
+  } else if constexpr (RD == NR - 1) {
+    inv_round_c<LOGN, NT, RD>(LdsIO{s}, out, tw, ninv, m, tid);
+  } else {
+    inv_round_c<LOGN, NT, RD>(LdsIO{s}, LdsIO{s}, tw, ninv, m, tid);
+    __syncthreads();
+    inv_rounds_from<LOGN, NT, RD + 1>(in, out, s, tw, ninv, m, tid);
+  }
+}
+
+// Whole transforms, s = LDS of lds_doubles(2^LOGN) doubles.  `tid` is the thread index; a kernel
+// running several transforms in a loop passes a copy it has made opaque to the optimiser, so that
+// per-thread address arithmetic is recomputed per transform rather than hoisted and held in
+// registers across the loop.  The first round reads `in`, the last writes `out` (either may be LdsIO{s}: then the caller synchronises before / after as with the
+// runtime-size functions).  No barrier at the end: `out` of the last round is written by the
+// thread that computed it.
+template <int LOGN, int NT, class In, class Out>
+__device__ __forceinline__ void ntt_fwd_c(const In& in, const Out& out, double* s, const double2* __restrict__ tw, ModD m,
+                                          int tid = threadIdx.x) {
+  fwd_rounds_from<LOGN, NT, 0>(in, out, s, tw, m, tid);
+}
+template <int LOGN, int NT, class In, class Out>
+__device__ __forceinline__ void ntt_inv_c(const In& in, const Out& out, double* s, const double2* __restrict__ tw, double2 ninv, ModD m,
+                                          int tid = threadIdx.x) {
+  inv_rounds_from<LOGN, NT, 0>(in, out, s, tw, ninv, m, tid);
+}
+
+// Element-wise sources and sinks: f(e) -> double (|x| <= q), g(e, x).
+template <class F>
+struct ElemIn {
+  F f;
+  template <int R, int LO>
+  __device__ __forceinline__ void get(double (&x)[1 << R], int base) const {
+#pragma unroll
+    for (int u = 0; u < (1 << R); u++) x[u] = f(base + (u << LO));
+  }
+};
+template <class G>
+struct ElemOut {
+  G g;
+  template <int R, int LO>
+  __device__ __forceinline__ void put(const double (&x)[1 << R], int base) const {
+#pragma unroll
+    for (int u = 0; u < (1 << R); u++) g(base + (u << LO), x[u]);
+  }
+};
+template <class F> __device__ __forceinline__ ElemIn<F> elem_in(F f) { return ElemIn<F>{f}; }
+template <class G> __device__ __forceinline__ ElemOut<G> elem_out(G g) { return ElemOut<G>{g}; }
+
+// LDS holding one half of a limb (elements with a fixed top index bit, HB = log2 of the half).
+template <int HB>
+struct LdsHalf {
+  double* s;
+  template <int R, int LO>
+  __device__ __forceinline__ void get(double (&x)[1 << R], int base) const { LdsIO{s}.template get<R, LO>(x, base & ((1 << HB) - 1)); }
+  template <int R, int LO>
+  __device__ __forceinline__ void put(const double (&x)[1 << R], int base) const { LdsIO{s}.template put<R, LO>(x, base & ((1 << HB) - 1)); }
+};
+
+// ---- N = 2^14 with half-limb LDS (68 KiB, two workgroups per CU, NT = 512)
+// Forward: stage 0 pairs e with e + 2^13 and is done in registers as the limb is read; the two
+// halves are then independent 13-stage problems.  Each thread owns elements tid + 512 k of both
+// halves, which is exactly its register group of stages 1..4 (LO = 9), so that round needs no LDS.
+// The second half waits in registers while the first runs stages 5..13 through LDS
+// (rounds 3,3,3 with two tasks per thread).  Inverse: the mirror image (stages 0..12 per half,
+// stage 13 and the 1/N scaling in registers at the end).
+static constexpr int kSplitLogn = 14, kSplitNT = 512;
+__host__ __device__ constexpr int split_lds_doubles() { return lds_doubles(1 << (kSplitLogn - 1)); }
+
+template <class In, class Out>
+__device__ __forceinline__ void ntt_fwd_split(const In& in, const Out& out, double* s, const double2* __restrict__ tw, ModD m,
+                                              int tid = threadIdx.x) {
+  constexpr int LOGN = kSplitLogn, NT = kSplitNT, H = 1 << (LOGN - 1), EH = H / NT;
+  static_assert(EH == 16, "split layout assumes 16 elements per thread and half");
+  double a[EH], b[EH];
+  const double2 w1 = ldtw(tw, 1);
+#pragma unroll
+  for (int k = 0; k < EH; k++) {
+    const int e = tid + k * NT;
+    a[k] = in(e);
+    b[k] = in(e + H);
+  }
+#pragma unroll
+  for (int k = 0; k < EH; k++) {
+    const double t = mul_tw(b[k], w1.x, w1.y, m);
+    b[k] = a[k] - t;
+    a[k] = a[k] + t;
+  }
+  ct_group<4, 1>(a, 0, tw, m);
+  LdsHalf<LOGN - 1>{s}.template put<4, 9>(a, tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 5, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, m, 0, tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 8, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, m, 0, tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 11, 3, 2>(LdsHalf<LOGN - 1>{s}, elem_out(out), tw, m, 0, tid);
+  __syncthreads();
+  ct_group<4, 1>(b, 1, tw, m);
+  LdsHalf<LOGN - 1>{s}.template put<4, 9>(b, H + tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 5, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, m, 1 << 10, tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 8, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, m, 1 << 10, tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 11, 3, 2>(LdsHalf<LOGN - 1>{s}, elem_out(out), tw, m, 1 << 10, tid);
+}
+
+// As ntt_fwd_split, but each half's result stays in LDS and seg(base, count) is called (after a
+// barrier) to consume elements base .. base + count - 1, element base + e at s[lpad(e)]; for
+// epilogues too heavy to inline into the last round.  Ends with a barrier.
+template <class In, class Seg>
+__device__ __forceinline__ void ntt_fwd_split_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, ModD m,
+                                                  int tid = threadIdx.x) {
+  constexpr int LOGN = kSplitLogn, NT = kSplitNT, H = 1 << (LOGN - 1), EH = H / NT;
+  double a[EH], b[EH];
+  const double2 w1 = ldtw(tw, 1);
+#pragma unroll
+  for (int k = 0; k < EH; k++) {
+    const int e = tid + k * NT;
+    a[k] = in(e);
+    b[k] = in(e + H);
+  }
+#pragma unroll
+  for (int k = 0; k < EH; k++) {
+    const double t = mul_tw(b[k], w1.x, w1.y, m);
+    b[k] = a[k] - t;
+    a[k] = a[k] + t;
+  }
+  const LdsHalf<LOGN - 1> L{s};
+  ct_group<4, 1>(a, 0, tw, m);
+  L.template put<4, 9>(a, tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 5, 3, 2>(L, L, tw, m, 0, tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 8, 3, 2>(L, L, tw, m, 0, tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 11, 3, 2>(L, L, tw, m, 0, tid);
+  __syncthreads();
+  seg(0, H);
+  __syncthreads();
+  ct_group<4, 1>(b, 1, tw, m);
+  L.template put<4, 9>(b, H + tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 5, 3, 2>(L, L, tw, m, 1 << 10, tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 8, 3, 2>(L, L, tw, m, 1 << 10, tid);
+  __syncthreads();
+  fwd_round_g<LOGN, NT, 11, 3, 2>(L, L, tw, m, 1 << 10, tid);
+  __syncthreads();
+  seg(H, H);
+  __syncthreads();
+}
+
+template <class In, class Out>
+__device__ __forceinline__ void ntt_inv_split(const In& in, const Out& out, double* s, const double2* __restrict__ tw, double2 ninv, ModD m,
+                                              int tid = threadIdx.x) {
+  constexpr int LOGN = kSplitLogn, NT = kSplitNT, H = 1 << (LOGN - 1), EH = H / NT;
+  static_assert(EH == 16, "split layout assumes 16 elements per thread and half");
+  double a[EH], b[EH];
+  inv_round_g<LOGN, NT, 0, 3, 2, false>(elem_in(in), LdsHalf<LOGN - 1>{s}, tw, ninv, m, 0, tid);
+  __syncthreads();
+  inv_round_g<LOGN, NT, 3, 3, 2, false>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, ninv, m, 0, tid);
+  __syncthreads();
+  inv_round_g<LOGN, NT, 6, 3, 2, false>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, ninv, m, 0, tid);
+  __syncthreads();
+  LdsHalf<LOGN - 1>{s}.template get<4, 9>(a, tid);
+  gs_group<4, 9, LOGN, false>(a, 0, tw, ninv, m);
+  __syncthreads();
+  inv_round_g<LOGN, NT, 0, 3, 2, false>(elem_in(in), LdsHalf<LOGN - 1>{s}, tw, ninv, m, 1 << 10, tid);
+  __syncthreads();
+  inv_round_g<LOGN, NT, 3, 3, 2, false>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, ninv, m, 1 << 10, tid);
+  __syncthreads();
+  inv_round_g<LOGN, NT, 6, 3, 2, false>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, ninv, m, 1 << 10, tid);
+  __syncthreads();
+  LdsHalf<LOGN - 1>{s}.template get<4, 9>(b, H + tid);
+  gs_group<4, 9, LOGN, false>(b, 1, tw, ninv, m);
+  // stage 13 with the scaling merged into its twiddle: w' = w / N mod q
+  const double2 w = ldtw(tw, 1);
+  const double wn = canon(mul_tw(w.x, ninv.x, ninv.y, m), m);
+  const double wnq = wn / m.q;
+#pragma unroll
+  for (int k = 0; k < EH; k++) {
+    const int e = tid + k * NT;
+    const double x = a[k], y = b[k];
+    out(e, mul_tw(x + y, ninv.x, ninv.y, m));
+    out(e + H, mul_tw(x - y, wn, wnq, m));
+  }
+}
+
+// Ring size handled by the compile-time path for a workgroup of NT threads (0: runtime path).
+__host__ __device__ constexpr int static_logn(int nt) { return nt >= 128 ? ilog2c(nt) + 4 : 0; }
 
 // ---------------------------------------------------------------- ChaCha20 (RFC 8439)
 __device__ __forceinline__ u32 rotl32(u32 v, int c) { return (v << c) | (v >> (32 - c)); }

@@ -2,8 +2,9 @@
 //
 // Layout in HBM: polynomials limb-major, [poly][limb][N] u64 residues in [0, q) (NTT form unless
 // stated); scratch between kernels of one key switch is held as balanced doubles.  A limb-level
-// transform runs in one workgroup with the whole limb resident in LDS (N <= 16384: 136 KiB with
-// padding) and radix-16 register rounds (hs_device.hpp).
+// transform runs in one workgroup (the transform policies below): N = 16384 keeps half a limb in
+// LDS (68 KiB, two workgroups per CU), smaller rings the whole limb, with compile-time register
+// rounds whose first and last rounds read and write global memory directly.
 #include "hs_device.hpp"
 #include "kernels.hpp"
 
@@ -32,21 +33,97 @@ __device__ __forceinline__ void store_canon(u64* out, const double* s, int n, Mo
   for (int i = threadIdx.x; i < n; i += nt) out[i] = d2u(canon(s[lpad(i)], m));
 }
 
+// ------------------------------------------------------------------ limb-transform policies
+// How a workgroup of XF::NT threads runs one length-N transform from an element source in(e)
+// (|x| <= q) to an element sink out(e, x) (balanced x, |x| <= 2.375 q + 1 forward, 0.625 q
+// inverse).  Every element is read once and written once, each by one thread; the functions end
+// without a barrier, so a caller that reuses LDS synchronises first.  fwd_seg leaves the result
+// in LDS and hands it to seg(base, count) in one or two segments (element base + e at
+// s[lpad(e)]), ending with a barrier.
+//   XfRuntime<NT>: any N <= 16 NT, limb in LDS, runtime log N (small rings)
+//   XfStatic<NT> : N = 16 NT, compile-time rounds, first/last round on the source/sink directly
+//   XfSplit      : N = 16384 with 512 threads and half-limb LDS (two workgroups per CU)
+template <int NT_>
+struct XfRuntime {
+  static constexpr int NT = NT_;
+  int logn;
+  template <class In, class Out>
+  __device__ __forceinline__ void fwd(const In& in, const Out& out, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
+    const int n = 1 << logn;
+    for (int i = threadIdx.x; i < n; i += NT) s[lpad(i)] = in(i);
+    __syncthreads();
+    lds_ntt_fwd<NT>(s, logn, tw, m);
+    for (int i = threadIdx.x; i < n; i += NT) out(i, s[lpad(i)]);
+  }
+  template <class In, class Seg>
+  __device__ __forceinline__ void fwd_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
+    const int n = 1 << logn;
+    for (int i = threadIdx.x; i < n; i += NT) s[lpad(i)] = in(i);
+    __syncthreads();
+    lds_ntt_fwd<NT>(s, logn, tw, m);
+    seg(0, n);
+    __syncthreads();
+  }
+  template <class In, class Out>
+  __device__ __forceinline__ void inv(const In& in, const Out& out, double* s, const double2* __restrict__ tw, double2 ninv, ModD m, int tid = threadIdx.x) const {
+    const int n = 1 << logn;
+    for (int i = threadIdx.x; i < n; i += NT) s[lpad(i)] = in(i);
+    __syncthreads();
+    lds_ntt_inv<NT>(s, logn, tw, ninv, m);
+    for (int i = threadIdx.x; i < n; i += NT) out(i, s[lpad(i)]);
+  }
+};
+template <int NT_>
+struct XfStatic {
+  static constexpr int NT = NT_;
+  static constexpr int LOGN = static_logn(NT_);
+  template <class In, class Out>
+  __device__ __forceinline__ void fwd(const In& in, const Out& out, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
+    ntt_fwd_c<LOGN, NT>(elem_in(in), elem_out(out), s, tw, m, tid);
+  }
+  template <class In, class Seg>
+  __device__ __forceinline__ void fwd_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
+    ntt_fwd_c<LOGN, NT>(elem_in(in), LdsIO{s}, s, tw, m, tid);
+    __syncthreads();
+    seg(0, 1 << LOGN);
+    __syncthreads();
+  }
+  template <class In, class Out>
+  __device__ __forceinline__ void inv(const In& in, const Out& out, double* s, const double2* __restrict__ tw, double2 ninv, ModD m, int tid = threadIdx.x) const {
+    ntt_inv_c<LOGN, NT>(elem_in(in), elem_out(out), s, tw, ninv, m, tid);
+  }
+};
+struct XfSplit {
+  static constexpr int NT = kSplitNT;
+  template <class In, class Out>
+  __device__ __forceinline__ void fwd(const In& in, const Out& out, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
+    ntt_fwd_split(in, out, s, tw, m, tid);
+  }
+  template <class In, class Seg>
+  __device__ __forceinline__ void fwd_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
+    ntt_fwd_split_seg(in, seg, s, tw, m, tid);
+  }
+  template <class In, class Out>
+  __device__ __forceinline__ void inv(const In& in, const Out& out, double* s, const double2* __restrict__ tw, double2 ninv, ModD m, int tid = threadIdx.x) const {
+    ntt_inv_split(in, out, s, tw, ninv, m, tid);
+  }
+};
+// Kernels on these policies keep to 128 VGPRs so that the split form fits two workgroups per CU.
+#define HS_XF_KERNEL template <class XF> __global__ void __launch_bounds__(XF::NT) __attribute__((amdgpu_waves_per_eu(4)))
+
 // ------------------------------------------------------------------ standalone NTT
-// One workgroup per limb: poly b / nl, limb b % nl, modulus index mod0 + limb.
-template <int NT>
-__global__ void __launch_bounds__(NT) k_ntt(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab, int logn) {
+// One workgroup per limb: poly b / nl, limb b % nl, modulus index mod0 + limb (in place).
+HS_XF_KERNEL k_ntt(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab, int logn, XF xf) {
   SMEM();
   const int n = 1 << logn;
   const int b = blockIdx.x;
   const ModTab t = tab[mod0 + b % nl];
   const ModD m = mod_of(t);
   u64* p = data + (size_t)b * n;
-  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = u2d(p[i]);
-  __syncthreads();
-  if (inverse) lds_ntt_inv<NT>(smem, logn, t.iv, t.ninv, m);
-  else lds_ntt_fwd<NT>(smem, logn, t.fw, m);
-  store_canon(p, smem, n, m, NT);
+  auto in = [p](int i) { return u2d(p[i]); };
+  auto out = [p, m](int i, double x) { p[i] = d2u(canon(x, m)); };
+  if (inverse) xf.inv(in, out, smem, t.iv, t.ninv, m);
+  else xf.fwd(in, out, smem, t.fw, m);
 }
 
 // ------------------------------------------------------------------ sampling
@@ -180,21 +257,20 @@ __global__ void __launch_bounds__(NT) k_pack_encode(PackArgs A, const u32* __res
 
 // Plaintext for ct x pt: centered lift of the mod-t coefficients (c > (t-1)/2 -> c - t), NTT mod
 // data prime `limb`.  grid = (L, n_plain).
-template <int NT>
-__global__ void __launch_bounds__(NT) k_plain_ntt(const u64* __restrict__ coef, u64* out, int L, u64 t, const ModTab* __restrict__ tab, int logn) {
+HS_XF_KERNEL k_plain_ntt(const u64* __restrict__ coef, u64* out, int L, u64 t, const ModTab* __restrict__ tab, int logn, XF xf) {
   SMEM();
   const int n = 1 << logn;
   const int l = blockIdx.x, g = blockIdx.y;
   const ModTab tb = tab[l];
   const ModD m = mod_of(tb);
   const u64* c = coef + (size_t)g * n;
-  for (int i = threadIdx.x; i < n; i += NT) {
+  u64* o = out + ((size_t)g * L + l) * n;
+  auto in = [c, t](int i) {
     const u64 v = c[i];
-    smem[lpad(i)] = v > (t - 1) / 2 ? (double)v - (double)t : (double)v;
-  }
-  __syncthreads();
-  lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
-  store_canon(out + ((size_t)g * L + l) * n, smem, n, m, NT);
+    return v > (t - 1) / 2 ? (double)v - (double)t : (double)v;
+  };
+  auto sink = [o, m](int i, double x) { o[i] = d2u(canon(x, m)); };
+  xf.fwd(in, sink, smem, tb.fw, m);
 }
 
 // ------------------------------------------------------------------ encryption
@@ -308,8 +384,7 @@ __global__ void k_mask_acc(const u64* const* __restrict__ w, const u64* __restri
 //  3. k_moddown_intt  special limbs of sum_dg ACC -> coefficient form PC[b][w][k]
 //  4. k_moddown_ntt   conv_i = NTT_i(Conv_{P -> q_i}(PC)), out_w,i = (acc_w,i - conv_i) P^-1
 //                     (+ sigma_g(c0)_i for w = 0) (+ addend_w,i)
-template <int NT>
-__global__ void __launch_bounds__(NT) k_rot_intt(const RotItem* __restrict__ items, u64* D, int L, const ModTab* __restrict__ tab, int logn) {
+HS_XF_KERNEL k_rot_intt(const RotItem* __restrict__ items, u64* D, int L, const ModTab* __restrict__ tab, int logn, XF xf) {
   SMEM();
   const int n = 1 << logn;
   const int l = blockIdx.x, b = blockIdx.y;
@@ -317,17 +392,20 @@ __global__ void __launch_bounds__(NT) k_rot_intt(const RotItem* __restrict__ ite
   const ModTab tb = tab[l];
   const ModD m = mod_of(tb);
   const u64* c1 = it.in + ((size_t)L + l) * n;
-  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = u2d(c1[galois_index((u32)i, it.galois, logn)]);
-  __syncthreads();
-  lds_ntt_inv<NT>(smem, logn, tb.iv, tb.ninv, m);
-  store_canon(D + ((size_t)b * L + l) * n, smem, n, m, NT);
+  const u32 gal = it.galois;
+  u64* o = D + ((size_t)b * L + l) * n;
+  auto in = [c1, gal, logn](int i) { return u2d(c1[galois_index((u32)i, gal, logn)]); };
+  auto sink = [o, m](int i, double x) { o[i] = d2u(canon(x, m)); };
+  xf.inv(in, sink, smem, tb.iv, tb.ninv, m);
 }
 
-template <int NT>
-__global__ void __launch_bounds__(NT) k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict__ D, double* ACC, KsShape S,
-                                                 const double2* __restrict__ up_inv, const double2* __restrict__ up_hat,
-                                                 const ModTab* __restrict__ tab, int logn) {
+// Accumulators live in the output rows ACC; a barrier separates the digits (element ownership
+// differs between the transform's sink and the own-limb loop).
+HS_XF_KERNEL k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict__ D, double* ACC, KsShape S,
+                        const double2* __restrict__ up_inv, const double2* __restrict__ up_hat, const ModTab* __restrict__ tab,
+                        int logn, XF xf) {
   SMEM();
+  constexpr int NT = XF::NT;
   const int n = 1 << logn;
   const int mi = blockIdx.x, b = blockIdx.y, dg = blockIdx.z;
   const int LK = S.L + S.K;
@@ -335,55 +413,62 @@ __global__ void __launch_bounds__(NT) k_modup_ip(const RotItem* __restrict__ ite
   const ModTab tb = tab[mi];
   const ModD m = mod_of(tb);
   const int j0 = dg * S.dpg, j1 = min(S.dnum, j0 + S.dpg);
-  // the accumulators live in the output rows; each element is owned by one thread throughout
   double* o0 = ACC + ((((size_t)b * S.ndg + dg) * 2 + 0) * LK + mi) * n;
   double* o1 = ACC + ((((size_t)b * S.ndg + dg) * 2 + 1) * LK + mi) * n;
   for (int j = j0; j < j1; j++) {
+    // the transform's per-thread address arithmetic (and twiddle base) is recomputed per digit
+    // instead of being hoisted out of the loop and held in registers across it
+    int tid = threadIdx.x;
+    const double2* tw = tb.fw;
+    asm volatile("" : "+v"(tid), "+s"(tw));
     const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha);
     const bool own = (mi >= lo && mi < hi);
-    if (own) {
-      const u64* c1 = it.in + ((size_t)S.L + mi) * n;
-      for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = u2d(c1[galois_index((u32)i, it.galois, logn)]);
-      __syncthreads();
-    } else {
-      // fast basis conversion from the digit's primes to modulus mi
-      for (int i = threadIdx.x; i < n; i += NT) {
-        double acc = 0.0;
-        for (int a = 0; a < hi - lo; a++) {
-          const double x = u2d(D[((size_t)b * S.L + lo + a) * n + i]);
-          if (hi - lo > 1) {
-            const ModTab sa = tab[lo + a];
-            const ModD ms = mod_of(sa);
-            const double2 ci = up_inv[j * S.alpha + a];
-            const double y = canon(mul_tw(x, ci.x, ci.y, ms), ms);
-            const double2 hm = up_hat[((size_t)j * S.alpha + a) * LK + mi];
-            acc = reduce(acc + mul_tw(y, hm.x, hm.y, m), m);
-          } else {
-            acc = reduce(x, m);  // a single source prime: [x]_q as an integer, taken mod mi
-          }
-        }
-        smem[lpad(i)] = acc;
-      }
-      __syncthreads();
-      lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
-    }
+    const bool first = (j == j0);
     const u64* kb = it.key + (((size_t)0 * S.dnum + j) * LK + mi) * n;
     const u64* ka = it.key + (((size_t)1 * S.dnum + j) * LK + mi) * n;
-    const bool first = (j == j0);
-    for (int i = threadIdx.x; i < n; i += NT) {
-      const double e = reduce(smem[lpad(i)], m);
+    auto sink = [=](int i, double x) {
+      const double e = reduce(x, m);
       double v0 = mulmod(e, u2d(kb[i]), m);
       double v1 = mulmod(e, u2d(ka[i]), m);
       if (!first) { v0 = reduce(v0 + o0[i], m); v1 = reduce(v1 + o1[i], m); }
       o0[i] = v0;
       o1[i] = v1;
+    };
+    if (own) {
+      const u64* c1 = it.in + ((size_t)S.L + mi) * n;
+      for (int i = threadIdx.x; i < n; i += NT) sink(i, u2d(c1[galois_index((u32)i, it.galois, logn)]));
+    } else {
+      const u64* Dj = D + ((size_t)b * S.L + lo) * n;
+      const int na = hi - lo;
+      auto seg = [&](int base, int cnt) {
+        for (int e = threadIdx.x; e < cnt; e += NT) sink(base + e, smem[lpad(e)]);
+      };
+      if (na == 1) {
+        // one source prime (alpha = 1): [x]_q as an integer, taken mod mi
+        xf.fwd_seg([=](int i) { return reduce(u2d(Dj[i]), m); }, seg, smem, tw, m, tid);
+      } else {
+        // fast basis conversion from the digit's primes to modulus mi
+        const double2* cinv = up_inv + j * S.alpha;
+        const double2* chat = up_hat + (size_t)j * S.alpha * LK + mi;
+        auto src = [=](int i) {
+          double acc = 0.0;
+          for (int a = 0; a < na; a++) {
+            const ModTab sa = tab[lo + a];
+            const ModD ms = mod_of(sa);
+            const double y = canon(mul_tw(u2d(Dj[(size_t)a * n + i]), cinv[a].x, cinv[a].y, ms), ms);
+            const double2 hm = chat[(size_t)a * LK];
+            acc = reduce(acc + mul_tw(y, hm.x, hm.y, m), m);
+          }
+          return acc;
+        };
+        xf.fwd_seg(src, seg, smem, tw, m, tid);
+      }
     }
     __syncthreads();
   }
 }
 
-template <int NT>
-__global__ void __launch_bounds__(NT) k_moddown_intt(const double* __restrict__ ACC, double* PC, KsShape S, const ModTab* __restrict__ tab, int logn) {
+HS_XF_KERNEL k_moddown_intt(const double* __restrict__ ACC, double* PC, KsShape S, const ModTab* __restrict__ tab, int logn, XF xf) {
   SMEM();
   const int n = 1 << logn;
   const int k = blockIdx.x, w = blockIdx.y, b = blockIdx.z;
@@ -391,34 +476,36 @@ __global__ void __launch_bounds__(NT) k_moddown_intt(const double* __restrict__ 
   const int mi = S.L + k;
   const ModTab tb = tab[mi];
   const ModD m = mod_of(tb);
-  for (int i = threadIdx.x; i < n; i += NT) {
-    double acc = 0.0;
-    for (int dg = 0; dg < S.ndg; dg++) acc += ACC[((((size_t)b * S.ndg + dg) * 2 + w) * LK + mi) * n + i];
-    smem[lpad(i)] = canon(acc, m);
-  }
-  __syncthreads();
-  lds_ntt_inv<NT>(smem, logn, tb.iv, tb.ninv, m);
+  const int ndg = S.ndg;
+  const double* a0 = ACC + (((size_t)b * ndg * 2 + w) * LK + mi) * n;
+  const size_t dstride = (size_t)2 * LK * n;
   double* o = PC + (((size_t)b * 2 + w) * S.K + k) * n;
-  for (int i = threadIdx.x; i < n; i += NT) o[i] = canon(smem[lpad(i)], m);
+  auto in = [a0, dstride, ndg, m](int i) {
+    double acc = 0.0;
+    for (int dg = 0; dg < ndg; dg++) acc += a0[dg * dstride + i];
+    return canon(acc, m);
+  };
+  auto sink = [o, m](int i, double x) { o[i] = canon(x, m); };
+  xf.inv(in, sink, smem, tb.iv, tb.ninv, m);
 }
 
-template <int NT>
-__global__ void __launch_bounds__(NT) k_moddown_ntt(const RotItem* __restrict__ items, const double* __restrict__ ACC, const double* __restrict__ PC,
-                                                    KsShape S, const double2* __restrict__ dn_inv, const double2* __restrict__ dn_hat,
-                                                    const double2* __restrict__ pinv, const ModTab* __restrict__ tab, int logn) {
+HS_XF_KERNEL k_moddown_ntt(const RotItem* __restrict__ items, const double* __restrict__ ACC, const double* __restrict__ PC, KsShape S,
+                           const double2* __restrict__ dn_inv, const double2* __restrict__ dn_hat, const double2* __restrict__ pinv,
+                           const ModTab* __restrict__ tab, int logn, XF xf) {
   SMEM();
-  constexpr int PER = 16;
   const int n = 1 << logn;
   const int i_l = blockIdx.x, w = blockIdx.y, b = blockIdx.z;
   const int LK = S.L + S.K;
   const RotItem it = items[b];
   const ModTab tb = tab[i_l];
   const ModD m = mod_of(tb);
-  for (int i = threadIdx.x; i < n; i += NT) {
+  const double* pc = PC + ((size_t)b * 2 + w) * S.K * n;
+  const int K = S.K;
+  auto src = [=](int i) {
     double acc = 0.0;
-    for (int k = 0; k < S.K; k++) {
-      const double x = PC[(((size_t)b * 2 + w) * S.K + k) * n + i];
-      if (S.K == 1) {
+    for (int k = 0; k < K; k++) {
+      const double x = pc[(size_t)k * n + i];
+      if (K == 1) {
         acc = x;  // [x]_p as an integer in [0, p), taken mod q_i
       } else {
         const ModTab sp = tab[S.L + k];
@@ -429,32 +516,33 @@ __global__ void __launch_bounds__(NT) k_moddown_ntt(const RotItem* __restrict__ 
         acc = reduce(acc + mul_tw(y, hm.x, hm.y, m), m);
       }
     }
-    smem[lpad(i)] = reduce(acc, m);
-  }
-  __syncthreads();
-  lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
+    return reduce(acc, m);
+  };
   const double2 pv = pinv[i_l];
   const u64* c0 = it.in + (size_t)i_l * n;
+  const u32 gal = it.galois;
   u64* out = it.out + ((size_t)w * S.L + i_l) * n;
   const u64* add = it.addend ? it.addend + ((size_t)w * S.L + i_l) * n : nullptr;
-#pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int i = threadIdx.x + k * NT;
-    if (i < n) {
-      double acc = 0.0;
-      for (int dg = 0; dg < S.ndg; dg++) acc += ACC[((((size_t)b * S.ndg + dg) * 2 + w) * LK + i_l) * n + i];
-      double v = mul_tw(reduce(acc - smem[lpad(i)], m), pv.x, pv.y, m);
-      if (w == 0) v += u2d(c0[galois_index((u32)i, it.galois, logn)]);
-      if (add) v += u2d(add[i]);
-      out[i] = d2u(canon(v, m));
-    }
-  }
+  const int ndg = S.ndg;
+  const double* a0 = ACC + (((size_t)b * ndg * 2 + w) * LK + i_l) * n;
+  const size_t dstride = (size_t)2 * LK * n;
+  auto sink = [=](int i, double x) {
+    double acc = 0.0;
+    for (int dg = 0; dg < ndg; dg++) acc += a0[dg * dstride + i];
+    double v = mul_tw(reduce(acc - x, m), pv.x, pv.y, m);
+    if (w == 0) v += u2d(c0[galois_index((u32)i, gal, logn)]);
+    if (add) v += u2d(add[i]);
+    out[i] = d2u(canon(v, m));
+  };
+  auto seg = [&](int base, int cnt) {
+    for (int e = threadIdx.x; e < cnt; e += XF::NT) sink(base + e, smem[lpad(e)]);
+  };
+  xf.fwd_seg(src, seg, smem, tb.fw, m);
 }
 
 // ------------------------------------------------------------------ decryption
 // phase x = c0 + c1 s in coefficient form, per limb: X[g][l][N] (u64).  grid = (L, n_ct).
-template <int NT>
-__global__ void __launch_bounds__(NT) k_dec_phase(const u64* __restrict__ ct, const u64* __restrict__ sk, u64* X, int L, const ModTab* __restrict__ tab, int logn) {
+HS_XF_KERNEL k_dec_phase(const u64* __restrict__ ct, const u64* __restrict__ sk, u64* X, int L, const ModTab* __restrict__ tab, int logn, XF xf) {
   SMEM();
   const int n = 1 << logn;
   const int l = blockIdx.x, g = blockIdx.y;
@@ -462,11 +550,11 @@ __global__ void __launch_bounds__(NT) k_dec_phase(const u64* __restrict__ ct, co
   const ModD m = mod_of(tb);
   const u64* c0 = ct + ((size_t)g * 2 * L + l) * n;
   const u64* c1 = ct + ((size_t)g * 2 * L + L + l) * n;
-  const u64* s = sk + (size_t)l * n;
-  for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = canon(u2d(c0[i]) + mulmod(u2d(c1[i]), u2d(s[i]), m), m);
-  __syncthreads();
-  lds_ntt_inv<NT>(smem, logn, tb.iv, tb.ninv, m);
-  store_canon(X + ((size_t)g * L + l) * n, smem, n, m, NT);
+  const u64* sl = sk + (size_t)l * n;
+  u64* o = X + ((size_t)g * L + l) * n;
+  auto in = [=](int i) { return canon(u2d(c0[i]) + mulmod(u2d(c1[i]), u2d(sl[i]), m), m); };
+  auto sink = [o, m](int i, double x) { o[i] = d2u(canon(x, m)); };
+  xf.inv(in, sink, smem, tb.iv, tb.ninv, m);
 }
 
 // m = round(t x / Q) mod t from the residues x_i (exact):  with y_i = [x_i Qhat_i^-1]_{q_i},
@@ -638,11 +726,34 @@ static void ensure_lds(const void* f, size_t bytes) {
     HS_CHECK_HIP(hipGetLastError());                                                                \
   } while (0)
 
+static size_t split_lds_bytes() { return (size_t)split_lds_doubles() * sizeof(double); }
+
+#define HS_LAUNCH_XF(XFT, XFV, LDSB, KERNEL, GRID, STREAM, ...)                              \
+  do {                                                                                         \
+    ensure_lds((const void*)KERNEL<XFT>, LDSB);                                                \
+    hipLaunchKernelGGL(KERNEL<XFT>, GRID, dim3(XFT::NT), LDSB, STREAM, __VA_ARGS__, XFV);     \
+  } while (0)
+// Ring size -> transform policy: 2^14 split, 2^11..2^13 compile-time, smaller runtime (64 threads).
+#define HS_DISPATCH_XF(logn, KERNEL, GRID, STREAM, ...)                                                  \
+  do {                                                                                                   \
+    ProfScope _prof(#KERNEL, STREAM);                                                                    \
+    switch (logn) {                                                                                      \
+      case 14: HS_LAUNCH_XF(XfSplit, XfSplit{}, split_lds_bytes(), KERNEL, GRID, STREAM, __VA_ARGS__); break; \
+      case 13: HS_LAUNCH_XF(XfStatic<512>, XfStatic<512>{}, lds_bytes(13), KERNEL, GRID, STREAM, __VA_ARGS__); break; \
+      case 12: HS_LAUNCH_XF(XfStatic<256>, XfStatic<256>{}, lds_bytes(12), KERNEL, GRID, STREAM, __VA_ARGS__); break; \
+      case 11: HS_LAUNCH_XF(XfStatic<128>, XfStatic<128>{}, lds_bytes(11), KERNEL, GRID, STREAM, __VA_ARGS__); break; \
+      default:                                                                                           \
+        if ((logn) < 1 || (logn) > 10) throw Error{HS_EPARAM, "ring too large for the LDS-resident transform"}; \
+        HS_LAUNCH_XF(XfRuntime<64>, XfRuntime<64>{logn}, lds_bytes(logn), KERNEL, GRID, STREAM, __VA_ARGS__); \
+    }                                                                                                    \
+    HS_CHECK_HIP(hipGetLastError());                                                                     \
+  } while (0)
+
 void upload_cdt(const u64* tab20) { HS_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_cdt), tab20, 20 * sizeof(u64))); }
 
 void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st) {
   if (nblocks <= 0) return;
-  HS_DISPATCH_NT(c->logn, k_ntt, dim3((unsigned)nblocks), st, data, nl, mod0, inverse, (const ModTab*)c->d_tab, c->logn);
+  HS_DISPATCH_XF(c->logn, k_ntt, dim3((unsigned)nblocks), st, data, nl, mod0, inverse, (const ModTab*)c->d_tab, c->logn);
 }
 
 void launch_sample_small(const hs_ctx* c, int* out, int nobj, i64 obj_stride, u64 seed, u32 purpose, u64 index0, u64 index_step,
@@ -671,7 +782,7 @@ void launch_pack_encode(const hs_ctx* c, const PackArgs& a, int nchunks, hipStre
 
 void launch_plain_ntt(const hs_ctx* c, const u64* coef, u64* out, int n_plain, hipStream_t st) {
   if (n_plain <= 0) return;
-  HS_DISPATCH_NT(c->logn, k_plain_ntt, dim3(c->L, n_plain), st, coef, out, c->L, c->t, (const ModTab*)c->d_tab, c->logn);
+  HS_DISPATCH_XF(c->logn, k_plain_ntt, dim3(c->L, n_plain), st, coef, out, c->L, c->t, (const ModTab*)c->d_tab, c->logn);
 }
 
 void launch_encrypt(const hs_ctx* c, const u64* mcoef, const int* samples, const u64* pk, u64* out, int n_ct, hipStream_t st) {
@@ -702,17 +813,17 @@ void launch_mask_acc(const hs_ctx* c, const u64* const* w, const u64* mask, cons
 void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, u64* D, double* ACC, double* PC, hipStream_t st) {
   if (B <= 0) return;
   const ModTab* tab = (const ModTab*)c->d_tab;
-  HS_DISPATCH_NT(c->logn, k_rot_intt, dim3(c->L, B), st, d_items, D, c->L, tab, c->logn);
-  HS_DISPATCH_NT(c->logn, k_modup_ip, dim3(c->L + c->K, B, S.ndg), st, d_items, (const u64*)D, ACC, S,
+  HS_DISPATCH_XF(c->logn, k_rot_intt, dim3(c->L, B), st, d_items, D, c->L, tab, c->logn);
+  HS_DISPATCH_XF(c->logn, k_modup_ip, dim3(c->L + c->K, B, S.ndg), st, d_items, (const u64*)D, ACC, S,
                  (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, c->logn);
-  HS_DISPATCH_NT(c->logn, k_moddown_intt, dim3(c->K, 2, B), st, (const double*)ACC, PC, S, tab, c->logn);
-  HS_DISPATCH_NT(c->logn, k_moddown_ntt, dim3(c->L, 2, B), st, d_items, (const double*)ACC, (const double*)PC, S,
+  HS_DISPATCH_XF(c->logn, k_moddown_intt, dim3(c->K, 2, B), st, (const double*)ACC, PC, S, tab, c->logn);
+  HS_DISPATCH_XF(c->logn, k_moddown_ntt, dim3(c->L, 2, B), st, d_items, (const double*)ACC, (const double*)PC, S,
                  (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, (const double2*)c->d_pinv, tab, c->logn);
 }
 
 void launch_dec_phase(const hs_ctx* c, const u64* ct, const u64* sk, u64* X, int n_ct, hipStream_t st) {
   if (n_ct <= 0) return;
-  HS_DISPATCH_NT(c->logn, k_dec_phase, dim3(c->L, n_ct), st, ct, sk, X, c->L, (const ModTab*)c->d_tab, c->logn);
+  HS_DISPATCH_XF(c->logn, k_dec_phase, dim3(c->L, n_ct), st, ct, sk, X, c->L, (const ModTab*)c->d_tab, c->logn);
 }
 
 void launch_dec_round(const hs_ctx* c, const u64* X, u64* M, int n_ct, hipStream_t st) {

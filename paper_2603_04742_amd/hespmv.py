@@ -123,7 +123,7 @@ class Context:
         self.dnum = (n_q + n_p - 1) // n_p
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:  # lib is None during interpreter shutdown
             lib.hs_ctx_destroy(self.h)
             self.h = None
 
@@ -162,7 +162,7 @@ class Keyset:
         self.h = h
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:  # lib is None during interpreter shutdown
             lib.hs_keyset_destroy(self.h)
             self.h = None
 
@@ -189,7 +189,7 @@ class CtVec:
         return cls(ctx, h)
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:  # lib is None during interpreter shutdown
             lib.hs_ctvec_destroy(self.h)
             self.h = None
 
@@ -223,7 +223,7 @@ class Matrix:
         self.encrypted = bool(encrypt_values)
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:  # lib is None during interpreter shutdown
             lib.hs_matrix_destroy(self.h)
             self.h = None
 
@@ -360,7 +360,7 @@ class Server:
         return dict(zip(["ticks", "max_active", "admitted", "completed", "bytes_in_use"], (int(v) for v in out)), now=now.value)
 
     def close(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:  # lib is None during interpreter shutdown
             lib.hs_server_destroy(self.h)
             self.h = None
 
