@@ -218,6 +218,7 @@ def keyswitch_kernel_bytes(L, K, N):
         "k2_rot_intt_low": (L + L) * limb,
         "k2_modup_high": (L + ext) * limb,
         "k2_ip_low": (ext + L + key + 2 * L + 2 * K) * limb,
+        "k2_ip_par": (ext + L + key + 2 * L + 2 * K) * limb,
         "k2_moddown_high": (2 * K + 2 * L) * limb,
         "k2_final_low": (2 * L + 2 * L + L + 2 * L) * limb,
         # one-workgroup-per-limb pipeline

@@ -20,9 +20,12 @@ static constexpr int kBlockElems = 2048;
 struct PassGeom {
   int logn, S;        // split
   int BE;             // elements per block
+  int lbe;            // log2 BE
   int nblk;           // blocks per limb (same for both passes)
   __host__ __device__ int gb_high() const { return BE >> S; }            // high groups per block
   __host__ __device__ int gb_low() const { return BE >> (logn - S); }    // low groups per block
+  __host__ __device__ int lgb_high() const { return lbe - S; }           // their log2 (all index
+  __host__ __device__ int lgb_low() const { return lbe - (logn - S); }   // arithmetic is shifts)
 };
 
 __host__ __device__ inline PassGeom make_geom(int logn) {
@@ -30,31 +33,33 @@ __host__ __device__ inline PassGeom make_geom(int logn) {
   g.logn = logn;
   g.S = logn >> 1;
   g.BE = (1 << logn) < kBlockElems ? (1 << logn) : kBlockElems;
+  g.lbe = 0;
+  while ((1 << g.lbe) < g.BE) g.lbe++;
   g.nblk = (1 << logn) / g.BE;
   return g;
 }
 
 // Global index of element u of group g in block `blk`.
 __device__ __forceinline__ int gidx_high(const PassGeom& G, int blk, int g, int u) {
-  return (blk * G.gb_high() + g) + (u << (G.logn - G.S));
+  return ((blk << G.lgb_high()) + g) + (u << (G.logn - G.S));
 }
 __device__ __forceinline__ int gidx_low(const PassGeom& G, int blk, int g, int u) {
-  return ((blk * G.gb_low() + g) << (G.logn - G.S)) + u;
+  return (((blk << G.lgb_low()) + g) << (G.logn - G.S)) + u;
 }
 // LDS address of element u of group g (HIGH: strided layout, LOW: contiguous layout).
 template <bool HIGH>
 __device__ __forceinline__ int laddr(const PassGeom& G, int g, int u) {
-  return HIGH ? u * G.gb_high() + g : g * (1 << (G.logn - G.S)) + u;
+  return HIGH ? (u << G.lgb_high()) + g : (g << (G.logn - G.S)) + u;
 }
 // Block element e (0..BE-1) <-> (g, u) in the LDS order of the layout: LDS address e.
 template <bool HIGH>
 __device__ __forceinline__ int gidx_of_lds(const PassGeom& G, int blk, int e) {
   if (HIGH) {
-    const int gbh = G.gb_high();
-    return gidx_high(G, blk, e % gbh, e / gbh);
+    const int l = G.lgb_high();
+    return gidx_high(G, blk, e & ((1 << l) - 1), e >> l);
   } else {
-    const int gl = 1 << (G.logn - G.S);
-    return gidx_low(G, blk, e / gl, e % gl);
+    const int l = G.logn - G.S;
+    return gidx_low(G, blk, e >> l, e & ((1 << l) - 1));
   }
 }
 
@@ -72,14 +77,14 @@ __host__ __device__ constexpr int tw_lds_entries(int BE) { return BE; }
 template <bool HIGH, bool FWD>
 __device__ __forceinline__ int tw_lds_index(const PassGeom& G, int blk, int st, int gtw) {
   if (HIGH) return gtw;
-  const int GB = G.gb_low();
+  const int lgb = G.lgb_low();
   const int nl = G.logn - G.S;
   if (FWD) {
     const int e = st - G.S;
-    return GB * ((1 << e) - 1) + (gtw - (1 << st) - ((blk * GB) << e));
+    return (((1 << e) - 1) << lgb) + (gtw - (1 << st) - (blk << (lgb + e)));
   } else {
     const int d = nl - st - 1;
-    return GB * ((1 << nl) - (2 << d)) + (gtw - ((1 << G.logn) >> (st + 1)) - ((blk * GB) << d));
+    return (((1 << nl) - (2 << d)) << lgb) + (gtw - ((1 << G.logn) >> (st + 1)) - (blk << (lgb + d)));
   }
 }
 
@@ -90,21 +95,21 @@ __device__ __forceinline__ void stage_twiddles(double2* twl, const PassGeom& G, 
     for (int i = threadIdx.x; i < (1 << G.S); i += NT) twl[i] = tw[i];
     return;
   }
-  const int GB = G.gb_low();
+  const int lgb = G.lgb_low();
   const int nl = G.logn - G.S;
   for (int k = 0; k < nl; k++) {
     int st, base, cnt, off;
     if (FWD) {
       st = G.S + k;
-      cnt = GB << k;
-      base = (1 << st) + ((blk * GB) << k);
-      off = GB * ((1 << k) - 1);
+      cnt = 1 << (lgb + k);
+      base = (1 << st) + (blk << (lgb + k));
+      off = ((1 << k) - 1) << lgb;
     } else {
       st = k;
       const int d = nl - st - 1;
-      cnt = GB << d;
-      base = ((1 << G.logn) >> (st + 1)) + ((blk * GB) << d);
-      off = GB * ((1 << nl) - (2 << d));
+      cnt = 1 << (lgb + d);
+      base = ((1 << G.logn) >> (st + 1)) + (blk << (lgb + d));
+      off = ((1 << nl) - (2 << d)) << lgb;
     }
     for (int i = threadIdx.x; i < cnt; i += NT) twl[off + i] = tw[base + i];
   }
@@ -121,9 +126,9 @@ __device__ __forceinline__ void pass_round(double* s, const PassGeom& G, int blk
   const int nb = HIGH ? G.S : G.logn - G.S;
   const int lo = HIGH ? G.logn - G.S : 0;
   const int GB = HIGH ? G.gb_high() : G.gb_low();
-  const int per_group = 1 << (nb - R);
-  for (int sg = threadIdx.x; sg < GB * per_group; sg += NT) {
-    const int g = sg / per_group, r = sg % per_group;
+  const int lpg = nb - R;  // log2 of the register groups per transform group
+  for (int sg = threadIdx.x; sg < (GB << lpg); sg += NT) {
+    const int g = sg >> lpg, r = sg & ((1 << lpg) - 1);
     const int base_u = ((r >> lb) << (lb + R)) | (r & ((1 << lb) - 1));
     const int gb = HIGH ? gidx_high(G, blk, g, base_u) : gidx_low(G, blk, g, base_u);
     const int hb = gb >> (lo + lb + R);
@@ -231,6 +236,129 @@ __device__ void pass_inv(double* s, double2* twl, const PassGeom& G, int blk, bo
       case 3: pass_round<3, NT, false, HIGH>(s, G, blk, done, 0, last, twl, ninv, m); break;
       case 2: pass_round<2, NT, false, HIGH>(s, G, blk, done, 0, last, twl, ninv, m); break;
       default: pass_round<1, NT, false, HIGH>(s, G, blk, done, 0, last, twl, ninv, m); break;
+    }
+    done += R;
+    __syncthreads();
+  }
+}
+
+// ---- several blocks of the same pass at once (same modulus and block position, so the staged
+// twiddles are shared): block j at s + j * LB, skipped when bit j of `skip` is set.  Spreads the
+// register groups of all blocks over the workgroup, so NB independent transforms run
+// concurrently instead of one after another.
+template <int R, int NT, bool FWD, bool HIGH>
+__device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsigned skip, const PassGeom& G, int blk, int lb, int lazy,
+                                                 bool scale, const double2* twl, double2 ninv, ModD m) {
+  const int nb = HIGH ? G.S : G.logn - G.S;
+  const int GB = HIGH ? G.gb_high() : G.gb_low();
+  const int lpg = nb - R;
+  const int lpb = (HIGH ? G.lgb_high() : G.lgb_low()) + lpg;  // log2 register groups per block
+  for (int t = threadIdx.x; t < (NB << lpb); t += NT) {
+    const int j = t >> lpb;
+    if ((skip >> j) & 1u) continue;
+    const int sg = t & ((1 << lpb) - 1);
+    const int g = sg >> lpg, r = sg & ((1 << lpg) - 1);
+    const int n = 1 << G.logn;
+    const int lo = HIGH ? G.logn - G.S : 0;
+    const int base_u = ((r >> lb) << (lb + R)) | (r & ((1 << lb) - 1));
+    const int gb = HIGH ? gidx_high(G, blk, g, base_u) : gidx_low(G, blk, g, base_u);
+    const int hb = gb >> (lo + lb + R);
+    double* sj = s + (size_t)j * LB;
+    const int l0 = laddr<HIGH>(G, g, base_u);
+    const int ls = HIGH ? (GB << lb) : (1 << lb);
+    double x[1 << R];
+#pragma unroll
+    for (int v = 0; v < (1 << R); v++) x[v] = sj[lpad(l0 + v * ls)];
+    if (FWD) {
+      int lz = lazy;
+#pragma unroll
+      for (int k = 0; k < R; k++) {
+        if (lz >= 2) {
+#pragma unroll
+          for (int v = 0; v < (1 << R); v++) x[v] = reduce(x[v], m);
+          lz = 0;
+        }
+        const int st = G.logn - lo - lb - R + k;
+        const double2* twk = twl + tw_lds_index<HIGH, true>(G, blk, st, (1 << st) + (hb << k));
+#pragma unroll
+        for (int jj = 0; jj < (1 << k); jj++) {
+          const double2 w = twk[jj];
+#pragma unroll
+          for (int v = 0; v < (1 << (R - 1 - k)); v++) {
+            const int u = (jj << (R - k)) | v;
+            const int u2 = u | (1 << (R - 1 - k));
+            const double tt = mul_tw(x[u2], w.x, w.y, m);
+            x[u2] = x[u] - tt;
+            x[u] = x[u] + tt;
+          }
+        }
+        lz++;
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < R; k++) {
+        const int st = lo + lb + k;
+        const double2* twk = twl + tw_lds_index<HIGH, false>(G, blk, st, (n >> (st + 1)) + (hb << (R - 1 - k)));
+#pragma unroll
+        for (int jj = 0; jj < (1 << (R - 1 - k)); jj++) {
+          const double2 w = twk[jj];
+#pragma unroll
+          for (int v = 0; v < (1 << k); v++) {
+            const int u = (jj << (k + 1)) | v;
+            const int u2 = u | (1 << k);
+            const double a = x[u], bb = x[u2];
+            x[u] = reduce(a + bb, m);
+            x[u2] = mul_tw(a - bb, w.x, w.y, m);
+          }
+        }
+      }
+      if (scale) {
+#pragma unroll
+        for (int v = 0; v < (1 << R); v++) x[v] = mul_tw(x[v], ninv.x, ninv.y, m);
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < (1 << R); v++) sj[lpad(l0 + v * ls)] = x[v];
+  }
+}
+
+// Forward pass on NB blocks (twiddles already staged; inputs |x| <= q; outputs |x| <= q/2 + 1).
+// Starts with no barrier of its own (the caller synchronises after staging) and ends with one.
+template <int NT, bool HIGH>
+__device__ void pass_fwd_multi(double* s, int LB, int NB, unsigned skip, const double2* twl, const PassGeom& G, int blk, ModD m) {
+  const int nb = HIGH ? G.S : G.logn - G.S;
+  int done = 0, lazy = 0;
+  while (done < nb) {
+    const int R = min(HS_NTT_RADIX_BITS, nb - done);
+    const int lb = nb - done - R;
+    switch (R) {
+      case 3: pass_round_multi<3, NT, true, HIGH>(s, LB, NB, skip, G, blk, lb, lazy, false, twl, double2{0, 0}, m); break;
+      case 2: pass_round_multi<2, NT, true, HIGH>(s, LB, NB, skip, G, blk, lb, lazy, false, twl, double2{0, 0}, m); break;
+      default: pass_round_multi<1, NT, true, HIGH>(s, LB, NB, skip, G, blk, lb, lazy, false, twl, double2{0, 0}, m); break;
+    }
+    for (int k = 0; k < R; k++) { if (lazy >= 2) lazy = 0; lazy++; }
+    done += R;
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < (NB << G.lbe); t += NT) {
+    const int j = t >> G.lbe, e = t & (G.BE - 1);
+    if (!((skip >> j) & 1u)) s[(size_t)j * LB + lpad(e)] = reduce(s[(size_t)j * LB + lpad(e)], m);
+  }
+  __syncthreads();
+}
+
+// Inverse pass on NB blocks (twiddles already staged; inputs |x| <= q, outputs |x| <= 0.625 q).
+template <int NT, bool HIGH>
+__device__ void pass_inv_multi(double* s, int LB, int NB, bool scale, const double2* twl, double2 ninv, const PassGeom& G, int blk, ModD m) {
+  const int nb = HIGH ? G.S : G.logn - G.S;
+  int done = 0;
+  while (done < nb) {
+    const int R = min(HS_NTT_RADIX_BITS, nb - done);
+    const bool last = scale && (done + R == nb);
+    switch (R) {
+      case 3: pass_round_multi<3, NT, false, HIGH>(s, LB, NB, 0u, G, blk, done, 0, last, twl, ninv, m); break;
+      case 2: pass_round_multi<2, NT, false, HIGH>(s, LB, NB, 0u, G, blk, done, 0, last, twl, ninv, m); break;
+      default: pass_round_multi<1, NT, false, HIGH>(s, LB, NB, 0u, G, blk, done, 0, last, twl, ninv, m); break;
     }
     done += R;
     __syncthreads();

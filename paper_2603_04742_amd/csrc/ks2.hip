@@ -247,6 +247,96 @@ __global__ void __launch_bounds__(NT) k2_ip_low(const RotItem* __restrict__ item
   }
 }
 
+// K3 with every digit resident at once: the digit blocks (own limb: sigma_g(c1)) sit side by side
+// in LDS and one workgroup of NT threads transforms all of them concurrently, then forms the inner
+// product per element.  LDS [staged twiddles: BE double2][dnum blocks of lds_doubles(BE)].
+// grid (nblk, L + K, B).
+template <int NT, int DMAX>
+__global__ void __launch_bounds__(NT) k2_ip_par(const RotItem* __restrict__ items, const double* __restrict__ E, double* ACC, double* T2, KsShape S,
+                                                const ModTab* __restrict__ tab, PassGeom G) {
+  SMEM2(G);
+  constexpr int PER = kBlockElems / NT > 0 ? kBlockElems / NT : 1;
+  const int n = 1 << G.logn;
+  const int blk = blockIdx.x, mi = blockIdx.y, b = blockIdx.z;
+  const int LK = S.L + S.K;
+  const int LB = lds_doubles(G.BE);
+  const RotItem it = items[b];
+  const ModTab tm = tab[mi];
+  const ModD m = mod_of2(tm);
+  const int jown = mi < S.L ? mi / S.alpha : -1;
+  // the key-switching key words of this thread's elements are loaded first: their latency then
+  // overlaps the staging and the transforms
+  u64 kbv[PER][DMAX], kav[PER][DMAX];
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int e = threadIdx.x + k * NT;
+    const int gi = e < G.BE ? gidx_of_lds<false>(G, blk, e) : 0;
+#pragma unroll
+    for (int j = 0; j < DMAX; j++) {
+      kbv[k][j] = 0;
+      kav[k][j] = 0;
+      if (j < S.dnum && e < G.BE) {
+        kbv[k][j] = it.key[(((size_t)0 * S.dnum + j) * LK + mi) * n + gi];
+        kav[k][j] = it.key[(((size_t)1 * S.dnum + j) * LK + mi) * n + gi];
+      }
+    }
+  }
+  stage_twiddles<NT, false, true>(twl, G, blk, tm.fw);
+  const u64* c1 = it.in + ((size_t)S.L + mi) * n;
+  for (int t = threadIdx.x; t < (S.dnum << G.lbe); t += NT) {
+    const int j = t >> G.lbe, e = t & (G.BE - 1);
+    const int gi = gidx_of_lds<false>(G, blk, e);
+    smem[(size_t)j * LB + lpad(e)] = (j == jown) ? u2d(c1[galois_index2((u32)gi, it.galois, G.logn)])
+                                                 : E[(((size_t)b * S.dnum + j) * LK + mi) * n + gi];
+  }
+  __syncthreads();
+  pass_fwd_multi<NT, false>(smem, LB, S.dnum, jown >= 0 ? (1u << jown) : 0u, twl, G, blk, m);
+  double r0[PER], r1[PER];
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int e = threadIdx.x + k * NT;
+    r0[k] = 0.0;
+    r1[k] = 0.0;
+    if (e < G.BE) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < DMAX; j++) {
+        if (j < S.dnum) {
+          const double x = smem[(size_t)j * LB + lpad(e)];
+          a0 += mulmod(x, u2d(kbv[k][j]), m);
+          a1 += mulmod(x, u2d(kav[k][j]), m);
+          if ((j & 3) == 3) { a0 = reduce(a0, m); a1 = reduce(a1, m); }
+        }
+      }
+      r0[k] = reduce(a0, m);
+      r1[k] = reduce(a1, m);
+      if (mi < S.L) {
+        const int gi = gidx_of_lds<false>(G, blk, e);
+        ACC[(((size_t)b * 2 + 0) * S.L + mi) * n + gi] = r0[k];
+        ACC[(((size_t)b * 2 + 1) * S.L + mi) * n + gi] = r1[k];
+      }
+    }
+  }
+  if (mi < S.L) return;
+  // special limb: inverse low pass of both accumulators (two blocks at once)
+  __syncthreads();
+  stage_twiddles<NT, false, false>(twl, G, blk, tm.iv);
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int e = threadIdx.x + k * NT;
+    if (e < G.BE) {
+      smem[lpad(e)] = canon(r0[k], m);
+      smem[(size_t)LB + lpad(e)] = canon(r1[k], m);
+    }
+  }
+  __syncthreads();
+  pass_inv_multi<NT, false>(smem, LB, 2, false, twl, tm.ninv, G, blk, m);
+  for (int t = threadIdx.x; t < (2 << G.lbe); t += NT) {
+    const int w = t >> G.lbe, e = t & (G.BE - 1);
+    T2[(((size_t)b * 2 + w) * S.K + (mi - S.L)) * n + gidx_of_lds<false>(G, blk, e)] = smem[(size_t)w * LB + lpad(e)];
+  }
+}
+
 // grid (nblk, 2 L, B): polynomial w = y / L, data prime i = y % L.  The special limbs' inverse
 // high pass is recomputed per target.
 template <int NT>
@@ -380,7 +470,14 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
   HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B), TW + LB, st, d_items, T1, c->L, tab, G);
   HS2_LAUNCH(k2_modup_high, dim3(G.nblk, c->dnum * LK, B), TWH + LB * (c->alpha + 1), st, (const double*)T1, E, S,
              (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
-  HS2_LAUNCH(k2_ip_low, dim3(G.nblk, LK, B), TW + LB, st, d_items, (const double*)E, ACC, T2, S, tab, G);
+  if (TW + LB * c->dnum <= (size_t)160 * 1024 && G.BE >= 1024 && c->dnum <= 6) {
+    ProfScope _prof("k2_ip_par", st);
+    ensure_lds2((const void*)k2_ip_par<1024, 6>, TW + LB * c->dnum);
+    hipLaunchKernelGGL((k2_ip_par<1024, 6>), dim3(G.nblk, LK, B), dim3(1024), TW + LB * c->dnum, st, d_items, (const double*)E, ACC, T2, S, tab, G);
+    HS_CHECK_HIP(hipGetLastError());
+  } else {
+    HS2_LAUNCH(k2_ip_low, dim3(G.nblk, LK, B), TW + LB, st, d_items, (const double*)E, ACC, T2, S, tab, G);
+  }
   HS2_LAUNCH(k2_moddown_high, dim3(G.nblk, 2 * c->L, B), TWH + LB * (c->K + 1), st, (const double*)T2, F, S, (const double2*)c->d_dn_inv,
              (const double2*)c->d_dn_hat, tab, G);
   HS2_LAUNCH(k2_final_low, dim3(G.nblk, 2 * c->L, B), TW + LB, st, d_items, (const double*)F, (const double*)ACC, (const double2*)c->d_pinv, S,
