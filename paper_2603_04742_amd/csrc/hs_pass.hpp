@@ -39,21 +39,39 @@ __host__ __device__ inline PassGeom make_geom(int logn) {
   return g;
 }
 
+// The same geometry as compile-time constants (ring sizes of the two-pass path): every shift and
+// loop bound of the pass code folds, as with the whole-limb transforms.
+__host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
+__host__ __device__ constexpr int clog2(int x) { return x <= 1 ? 0 : 1 + clog2(x >> 1); }
+template <int LOGN>
+struct PassGeomC {
+  static constexpr int logn = LOGN, S = LOGN >> 1;
+  static constexpr int BE = cmin(1 << LOGN, kBlockElems);
+  static constexpr int lbe = clog2(BE);
+  static constexpr int nblk = (1 << LOGN) / BE;
+  __host__ __device__ static constexpr int gb_high() { return BE >> S; }
+  __host__ __device__ static constexpr int gb_low() { return BE >> (logn - S); }
+  __host__ __device__ static constexpr int lgb_high() { return lbe - S; }
+  __host__ __device__ static constexpr int lgb_low() { return lbe - (logn - S); }
+};
+
 // Global index of element u of group g in block `blk`.
-__device__ __forceinline__ int gidx_high(const PassGeom& G, int blk, int g, int u) {
+template <class GT>
+__device__ __forceinline__ int gidx_high(const GT& G, int blk, int g, int u) {
   return ((blk << G.lgb_high()) + g) + (u << (G.logn - G.S));
 }
-__device__ __forceinline__ int gidx_low(const PassGeom& G, int blk, int g, int u) {
+template <class GT>
+__device__ __forceinline__ int gidx_low(const GT& G, int blk, int g, int u) {
   return (((blk << G.lgb_low()) + g) << (G.logn - G.S)) + u;
 }
 // LDS address of element u of group g (HIGH: strided layout, LOW: contiguous layout).
-template <bool HIGH>
-__device__ __forceinline__ int laddr(const PassGeom& G, int g, int u) {
+template <bool HIGH, class GT>
+__device__ __forceinline__ int laddr(const GT& G, int g, int u) {
   return HIGH ? (u << G.lgb_high()) + g : (g << (G.logn - G.S)) + u;
 }
 // Block element e (0..BE-1) <-> (g, u) in the LDS order of the layout: LDS address e.
-template <bool HIGH>
-__device__ __forceinline__ int gidx_of_lds(const PassGeom& G, int blk, int e) {
+template <bool HIGH, class GT>
+__device__ __forceinline__ int gidx_of_lds(const GT& G, int blk, int e) {
   if (HIGH) {
     const int l = G.lgb_high();
     return gidx_high(G, blk, e & ((1 << l) - 1), e >> l);
@@ -74,8 +92,8 @@ __device__ __forceinline__ int gidx_of_lds(const PassGeom& G, int blk, int e) {
 // Each range has at most BE/2 entries and all ranges of a pass at most BE.
 __host__ __device__ constexpr int tw_lds_entries(int BE) { return BE; }
 
-template <bool HIGH, bool FWD>
-__device__ __forceinline__ int tw_lds_index(const PassGeom& G, int blk, int st, int gtw) {
+template <bool HIGH, bool FWD, class GT>
+__device__ __forceinline__ int tw_lds_index(const GT& G, int blk, int st, int gtw) {
   if (HIGH) return gtw;
   const int lgb = G.lgb_low();
   const int nl = G.logn - G.S;
@@ -89,8 +107,8 @@ __device__ __forceinline__ int tw_lds_index(const PassGeom& G, int blk, int st, 
 }
 
 // Copy the pass's twiddles to twl (cooperative; the caller synchronises afterwards).
-template <int NT, bool HIGH, bool FWD>
-__device__ __forceinline__ void stage_twiddles(double2* twl, const PassGeom& G, int blk, const double2* __restrict__ tw) {
+template <int NT, bool HIGH, bool FWD, class GT>
+__device__ __forceinline__ void stage_twiddles(double2* twl, const GT& G, int blk, const double2* __restrict__ tw) {
   if (HIGH) {
     for (int i = threadIdx.x; i < (1 << G.S); i += NT) twl[i] = tw[i];
     return;
@@ -119,8 +137,8 @@ __device__ __forceinline__ void stage_twiddles(double2* twl, const PassGeom& G, 
 // for low groups, logn - S for high groups); the round covers local bits [lb, lb + R).
 // Forward: stage k pairs global bit lo + lb + R - 1 - k (global stage logn - lo - lb - R + k).
 // Inverse: stage k pairs global bit lo + lb + k.
-template <int R, int NT, bool FWD, bool HIGH>
-__device__ __forceinline__ void pass_round(double* s, const PassGeom& G, int blk, int lb, int lazy, bool scale,
+template <int R, int NT, bool FWD, bool HIGH, class GT>
+__device__ __forceinline__ void pass_round(double* s, const GT& G, int blk, int lb, int lazy, bool scale,
                                            const double2* twl, double2 ninv, ModD m) {
   const int n = 1 << G.logn;
   const int nb = HIGH ? G.S : G.logn - G.S;
@@ -193,8 +211,8 @@ __device__ __forceinline__ void pass_round(double* s, const PassGeom& G, int blk
 // Forward pass on the block in LDS (inputs |x| <= q); ends with every element reduced to
 // |x| <= q/2 + 1 and a barrier.  twl: LDS scratch of tw_lds_entries(BE) double2 for the staged
 // twiddles (must not be in use by other threads).  The caller synchronises before.
-template <int NT, bool HIGH>
-__device__ void pass_fwd(double* s, double2* twl, const PassGeom& G, int blk, const double2* __restrict__ tw, ModD m,
+template <int NT, bool HIGH, class GT>
+__device__ void pass_fwd(double* s, double2* twl, const GT& G, int blk, const double2* __restrict__ tw, ModD m,
                          bool stage = true) {
   const int nb = HIGH ? G.S : G.logn - G.S;
   if (stage) {
@@ -220,8 +238,8 @@ __device__ void pass_fwd(double* s, double2* twl, const PassGeom& G, int blk, co
 
 // Inverse pass on the block in LDS (inputs |x| <= q, outputs |x| <= 0.625 q); `scale` multiplies
 // by N^-1 (the last inverse pass).  Ends with a barrier.
-template <int NT, bool HIGH>
-__device__ void pass_inv(double* s, double2* twl, const PassGeom& G, int blk, bool scale, const double2* __restrict__ tw, double2 ninv, ModD m,
+template <int NT, bool HIGH, class GT>
+__device__ void pass_inv(double* s, double2* twl, const GT& G, int blk, bool scale, const double2* __restrict__ tw, double2 ninv, ModD m,
                          bool stage = true) {
   const int nb = HIGH ? G.S : G.logn - G.S;
   if (stage) {
@@ -246,8 +264,8 @@ __device__ void pass_inv(double* s, double2* twl, const PassGeom& G, int blk, bo
 // twiddles are shared): block j at s + j * LB, skipped when bit j of `skip` is set.  Spreads the
 // register groups of all blocks over the workgroup, so NB independent transforms run
 // concurrently instead of one after another.
-template <int R, int NT, bool FWD, bool HIGH>
-__device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsigned skip, const PassGeom& G, int blk, int lb, int lazy,
+template <int R, int NT, bool FWD, bool HIGH, class GT>
+__device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsigned skip, const GT& G, int blk, int lb, int lazy,
                                                  bool scale, const double2* twl, double2 ninv, ModD m) {
   const int nb = HIGH ? G.S : G.logn - G.S;
   const int GB = HIGH ? G.gb_high() : G.gb_low();
@@ -324,8 +342,8 @@ __device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsi
 
 // Forward pass on NB blocks (twiddles already staged; inputs |x| <= q; outputs |x| <= q/2 + 1).
 // Starts with no barrier of its own (the caller synchronises after staging) and ends with one.
-template <int NT, bool HIGH>
-__device__ void pass_fwd_multi(double* s, int LB, int NB, unsigned skip, const double2* twl, const PassGeom& G, int blk, ModD m) {
+template <int NT, bool HIGH, class GT>
+__device__ void pass_fwd_multi(double* s, int LB, int NB, unsigned skip, const double2* twl, const GT& G, int blk, ModD m) {
   const int nb = HIGH ? G.S : G.logn - G.S;
   int done = 0, lazy = 0;
   while (done < nb) {
@@ -348,8 +366,8 @@ __device__ void pass_fwd_multi(double* s, int LB, int NB, unsigned skip, const d
 }
 
 // Inverse pass on NB blocks (twiddles already staged; inputs |x| <= q, outputs |x| <= 0.625 q).
-template <int NT, bool HIGH>
-__device__ void pass_inv_multi(double* s, int LB, int NB, bool scale, const double2* twl, double2 ninv, const PassGeom& G, int blk, ModD m) {
+template <int NT, bool HIGH, class GT>
+__device__ void pass_inv_multi(double* s, int LB, int NB, bool scale, const double2* twl, double2 ninv, const GT& G, int blk, ModD m) {
   const int nb = HIGH ? G.S : G.logn - G.S;
   int done = 0;
   while (done < nb) {

@@ -43,9 +43,9 @@ __device__ __forceinline__ u32 galois_index2(u32 k, u32 g, int logn) {
 // ------------------------------------------------------------------ standalone two-pass NTT
 // One pass over `nl`-limb polynomials: grid (nblk, n_polys * nl).  in/out either u64 canonical
 // residues or balanced doubles (in place allowed).
-template <int NT, bool HIGH, bool FWD>
+template <int NT, bool HIGH, bool FWD, class GT>
 __device__ __forceinline__ void ntt_pass_body(double* smem, double2* twl, const void* in, int in_u64, void* out, int out_u64, int nl, int mod0,
-                                              int scale, const ModTab* __restrict__ tab, PassGeom G) {
+                                              int scale, const ModTab* __restrict__ tab, GT G) {
   const int n = 1 << G.logn;
   const int blk = blockIdx.x, row = blockIdx.y;
   const ModTab tb = tab[mod0 + row % nl];
@@ -66,11 +66,11 @@ __device__ __forceinline__ void ntt_pass_body(double* smem, double2* twl, const 
 }
 
 #define HS2_PASS_KERNEL(NAME, HIGH, FWD)                                                                      \
-  template <int NT>                                                                                           \
+  template <int NT, class GT>                                                                                         \
   __global__ void __launch_bounds__(NT) NAME(const void* in, int in_u64, void* out, int out_u64, int nl,      \
-                                             int mod0, int scale, const ModTab* __restrict__ tab, PassGeom G) { \
+                                             int mod0, int scale, const ModTab* __restrict__ tab, GT G) { \
     SMEM2(G);                                                                                                 \
-    ntt_pass_body<NT, HIGH, FWD>(smem, twl, in, in_u64, out, out_u64, nl, mod0, scale, tab, G);               \
+    ntt_pass_body<NT, HIGH, FWD, GT>(smem, twl, in, in_u64, out, out_u64, nl, mod0, scale, tab, G);               \
   }
 HS2_PASS_KERNEL(k2_ntt_pass_hf, true, true)
 HS2_PASS_KERNEL(k2_ntt_pass_lf, false, true)
@@ -78,8 +78,8 @@ HS2_PASS_KERNEL(k2_ntt_pass_li, false, false)
 HS2_PASS_KERNEL(k2_ntt_pass_hi, true, false)
 
 // ------------------------------------------------------------------ key switching, K1..K5
-template <int NT>
-__global__ void __launch_bounds__(NT) k2_rot_intt_low(const RotItem* __restrict__ items, double* T1, int L, const ModTab* __restrict__ tab, PassGeom G) {
+template <int NT, class GT>
+__global__ void __launch_bounds__(NT) k2_rot_intt_low(const RotItem* __restrict__ items, double* T1, int L, const ModTab* __restrict__ tab, GT G) {
   SMEM2(G);
   const int n = 1 << G.logn;
   const int blk = blockIdx.x, l = blockIdx.y, b = blockIdx.z;
@@ -100,9 +100,9 @@ __global__ void __launch_bounds__(NT) k2_rot_intt_low(const RotItem* __restrict_
 // grid (nblk, dnum * (L + K), B): digit j = y / (L+K), target modulus mi = y % (L+K) (own limbs of
 // the digit exit at once).  The digit's inverse high pass is recomputed by each target's
 // workgroup: two passes per workgroup instead of a chain of L + K.
-template <int NT>
+template <int NT, class GT>
 __global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T1, double* E, KsShape S, const double2* __restrict__ up_inv,
-                                                    const double2* __restrict__ up_hat, const ModTab* __restrict__ tab, PassGeom G) {
+                                                    const double2* __restrict__ up_hat, const ModTab* __restrict__ tab, GT G) {
   SMEM2_HIGH(G);
   const int n = 1 << G.logn;
   const int LK = S.L + S.K;
@@ -155,9 +155,9 @@ __global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T
 
 // grid (nblk, L + K, B).  The next digit's block is loaded into registers while the current one
 // is transformed (its twiddles are staged once: every digit uses modulus mi).
-template <int NT>
+template <int NT, class GT>
 __global__ void __launch_bounds__(NT) k2_ip_low(const RotItem* __restrict__ items, const double* __restrict__ E, double* ACC, double* T2, KsShape S,
-                                                const ModTab* __restrict__ tab, PassGeom G) {
+                                                const ModTab* __restrict__ tab, GT G) {
   SMEM2(G);
   constexpr int PER = kBlockElems / NT > 0 ? kBlockElems / NT : 1;
   const int n = 1 << G.logn;
@@ -251,9 +251,9 @@ __global__ void __launch_bounds__(NT) k2_ip_low(const RotItem* __restrict__ item
 // in LDS and one workgroup of NT threads transforms all of them concurrently, then forms the inner
 // product per element.  LDS [staged twiddles: BE double2][dnum blocks of lds_doubles(BE)].
 // grid (nblk, L + K, B).
-template <int NT, int DMAX>
+template <int NT, int DMAX, class GT>
 __global__ void __launch_bounds__(NT) k2_ip_par(const RotItem* __restrict__ items, const double* __restrict__ E, double* ACC, double* T2, KsShape S,
-                                                const ModTab* __restrict__ tab, PassGeom G) {
+                                                const ModTab* __restrict__ tab, GT G) {
   SMEM2(G);
   constexpr int PER = kBlockElems / NT > 0 ? kBlockElems / NT : 1;
   const int n = 1 << G.logn;
@@ -339,9 +339,9 @@ __global__ void __launch_bounds__(NT) k2_ip_par(const RotItem* __restrict__ item
 
 // grid (nblk, 2 L, B): polynomial w = y / L, data prime i = y % L.  The special limbs' inverse
 // high pass is recomputed per target.
-template <int NT>
+template <int NT, class GT>
 __global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__ T2, double* F, KsShape S, const double2* __restrict__ dn_inv,
-                                                      const double2* __restrict__ dn_hat, const ModTab* __restrict__ tab, PassGeom G) {
+                                                      const double2* __restrict__ dn_hat, const ModTab* __restrict__ tab, GT G) {
   SMEM2_HIGH(G);
   const int n = 1 << G.logn;
   const int blk = blockIdx.x, w = blockIdx.y / S.L, i = blockIdx.y % S.L, b = blockIdx.z;
@@ -389,9 +389,9 @@ __global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__
   for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<true>(G, blk, e)] = work[lpad(e)];
 }
 
-template <int NT>
+template <int NT, class GT>
 __global__ void __launch_bounds__(NT) k2_final_low(const RotItem* __restrict__ items, const double* __restrict__ F, const double* __restrict__ ACC,
-                                                   const double2* __restrict__ pinv, KsShape S, const ModTab* __restrict__ tab, PassGeom G) {
+                                                   const double2* __restrict__ pinv, KsShape S, const ModTab* __restrict__ tab, GT G) {
   SMEM2(G);
   const int n = 1 << G.logn;
   const int blk = blockIdx.x, wi = blockIdx.y, b = blockIdx.z;
@@ -428,60 +428,79 @@ static void ensure_lds2(const void* f, size_t bytes) {
   g2_set[f] = bytes;
 }
 
-static int nt2(const PassGeom& G) { return G.BE >= 2048 ? 256 : 64; }
+template <class GT>
+static int nt2(const GT& G) { return G.BE >= 2048 ? 256 : 64; }
 
+// Launch KERNEL<NT, GT> (GT = the geometry type in scope) with 256 or 64 threads.
 #define HS2_LAUNCH(KERNEL, GRID, LDS, STREAM, ...)                                                  \
   do {                                                                                              \
     ProfScope _prof(#KERNEL, STREAM);                                                               \
     if (nt2(G) == 256) {                                                                            \
-      ensure_lds2((const void*)KERNEL<256>, LDS);                                                   \
-      hipLaunchKernelGGL(KERNEL<256>, GRID, dim3(256), LDS, STREAM, __VA_ARGS__);                   \
+      ensure_lds2((const void*)KERNEL<256, GT>, LDS);                                               \
+      hipLaunchKernelGGL((KERNEL<256, GT>), GRID, dim3(256), LDS, STREAM, __VA_ARGS__);             \
     } else {                                                                                        \
-      ensure_lds2((const void*)KERNEL<64>, LDS);                                                    \
-      hipLaunchKernelGGL(KERNEL<64>, GRID, dim3(64), LDS, STREAM, __VA_ARGS__);                     \
+      ensure_lds2((const void*)KERNEL<64, GT>, LDS);                                                \
+      hipLaunchKernelGGL((KERNEL<64, GT>), GRID, dim3(64), LDS, STREAM, __VA_ARGS__);               \
     }                                                                                               \
     HS_CHECK_HIP(hipGetLastError());                                                                \
   } while (0)
 
+// Calls f(geometry): compile-time for the ring sizes this path serves, runtime otherwise.
+template <class F>
+static void with_geom(int logn, F&& f) {
+  switch (logn) {
+    case 12: f(PassGeomC<12>{}); break;
+    case 13: f(PassGeomC<13>{}); break;
+    case 14: f(PassGeomC<14>{}); break;
+    case 15: f(PassGeomC<15>{}); break;
+    default: f(make_geom(logn)); break;
+  }
+}
+
 void launch_ntt2(const hs_ctx* c, u64* data, double* scratch, i64 rows, int nl, int mod0, int inverse, hipStream_t st) {
   if (rows <= 0) return;
-  const PassGeom G = make_geom(c->logn);
-  const size_t lds = (size_t)(lds_doubles(G.BE) + 2 * G.BE) * sizeof(double);
-  const ModTab* tab = (const ModTab*)c->d_tab;
-  const dim3 grid(G.nblk, (unsigned)rows);
-  if (!inverse) {
-    HS2_LAUNCH(k2_ntt_pass_hf, grid, lds, st, data, 1, scratch, 0, nl, mod0, 0, tab, G);
-    HS2_LAUNCH(k2_ntt_pass_lf, grid, lds, st, scratch, 0, data, 1, nl, mod0, 0, tab, G);
-  } else {
-    HS2_LAUNCH(k2_ntt_pass_li, grid, lds, st, data, 1, scratch, 0, nl, mod0, 0, tab, G);
-    HS2_LAUNCH(k2_ntt_pass_hi, grid, lds, st, scratch, 0, data, 1, nl, mod0, 1, tab, G);
-  }
+  with_geom(c->logn, [&](auto G) {
+    using GT = decltype(G);
+    const size_t lds = (size_t)(lds_doubles(G.BE) + 2 * G.BE) * sizeof(double);
+    const ModTab* tab = (const ModTab*)c->d_tab;
+    const dim3 grid(G.nblk, (unsigned)rows);
+    if (!inverse) {
+      HS2_LAUNCH(k2_ntt_pass_hf, grid, lds, st, data, 1, scratch, 0, nl, mod0, 0, tab, G);
+      HS2_LAUNCH(k2_ntt_pass_lf, grid, lds, st, scratch, 0, data, 1, nl, mod0, 0, tab, G);
+    } else {
+      HS2_LAUNCH(k2_ntt_pass_li, grid, lds, st, data, 1, scratch, 0, nl, mod0, 0, tab, G);
+      HS2_LAUNCH(k2_ntt_pass_hi, grid, lds, st, scratch, 0, data, 1, nl, mod0, 1, tab, G);
+    }
+  });
 }
 
 void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, double* T1, double* E, double* ACC, double* T2,
                           double* F, hipStream_t st) {
   if (B <= 0) return;
-  const PassGeom G = make_geom(c->logn);
-  const size_t LB = (size_t)lds_doubles(G.BE) * sizeof(double);
-  const size_t TW = (size_t)2 * G.BE * sizeof(double);
-  const size_t TWH = (size_t)2 * (1 << G.S) * sizeof(double);
-  const ModTab* tab = (const ModTab*)c->d_tab;
-  const int LK = c->L + c->K;
-  HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B), TW + LB, st, d_items, T1, c->L, tab, G);
-  HS2_LAUNCH(k2_modup_high, dim3(G.nblk, c->dnum * LK, B), TWH + LB * (c->alpha + 1), st, (const double*)T1, E, S,
-             (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
-  if (TW + LB * c->dnum <= (size_t)160 * 1024 && G.BE >= 1024 && c->dnum <= 6) {
-    ProfScope _prof("k2_ip_par", st);
-    ensure_lds2((const void*)k2_ip_par<1024, 6>, TW + LB * c->dnum);
-    hipLaunchKernelGGL((k2_ip_par<1024, 6>), dim3(G.nblk, LK, B), dim3(1024), TW + LB * c->dnum, st, d_items, (const double*)E, ACC, T2, S, tab, G);
-    HS_CHECK_HIP(hipGetLastError());
-  } else {
-    HS2_LAUNCH(k2_ip_low, dim3(G.nblk, LK, B), TW + LB, st, d_items, (const double*)E, ACC, T2, S, tab, G);
-  }
-  HS2_LAUNCH(k2_moddown_high, dim3(G.nblk, 2 * c->L, B), TWH + LB * (c->K + 1), st, (const double*)T2, F, S, (const double2*)c->d_dn_inv,
-             (const double2*)c->d_dn_hat, tab, G);
-  HS2_LAUNCH(k2_final_low, dim3(G.nblk, 2 * c->L, B), TW + LB, st, d_items, (const double*)F, (const double*)ACC, (const double2*)c->d_pinv, S,
-             tab, G);
+  with_geom(c->logn, [&](auto G) {
+    using GT = decltype(G);
+    const size_t LB = (size_t)lds_doubles(G.BE) * sizeof(double);
+    const size_t TW = (size_t)2 * G.BE * sizeof(double);
+    const size_t TWH = (size_t)2 * (1 << G.S) * sizeof(double);
+    const ModTab* tab = (const ModTab*)c->d_tab;
+    const int LK = c->L + c->K;
+    HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B), TW + LB, st, d_items, T1, c->L, tab, G);
+    HS2_LAUNCH(k2_modup_high, dim3(G.nblk, c->dnum * LK, B), TWH + LB * (c->alpha + 1), st, (const double*)T1, E, S,
+               (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
+    if (TW + LB * c->dnum <= (size_t)160 * 1024 && G.BE >= 1024 && c->dnum <= 6) {
+      ProfScope _prof("k2_ip_par", st);
+      ensure_lds2((const void*)k2_ip_par<1024, 6, GT>, TW + LB * c->dnum);
+      hipLaunchKernelGGL((k2_ip_par<1024, 6, GT>), dim3(G.nblk, LK, B), dim3(1024), TW + LB * c->dnum, st, d_items, (const double*)E, ACC,
+                         T2, S, tab, G);
+      HS_CHECK_HIP(hipGetLastError());
+    } else {
+      HS2_LAUNCH(k2_ip_low, dim3(G.nblk, LK, B), TW + LB, st, d_items, (const double*)E, ACC, T2, S, tab, G);
+    }
+    HS2_LAUNCH(k2_moddown_high, dim3(G.nblk, 2 * c->L, B), TWH + LB * (c->K + 1), st, (const double*)T2, F, S,
+               (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, tab, G);
+    HS2_LAUNCH(k2_final_low, dim3(G.nblk, 2 * c->L, B), TW + LB, st, d_items, (const double*)F, (const double*)ACC,
+               (const double2*)c->d_pinv, S, tab, G);
+  });
 }
 
 }  // namespace hs
