@@ -52,6 +52,17 @@ template <class T>
 static void d2h(T* h, const T* d, size_t n, hipStream_t st) {
   if (n) HS_CHECK_HIP(hipMemcpyAsync(h, d, n * sizeof(T), hipMemcpyDeviceToHost, st));
 }
+// Matrices and ciphertext vectors take their device memory from the context's pool (returned on
+// destroy): hipMalloc/hipFree per object cost tens of microseconds each and hipFree waits for the
+// device.  Every API call that writes such an object synchronises its stream before returning,
+// so memory handed back on destroy is idle.
+template <class T>
+static T* pmalloc(hs_ctx* c, size_t n) {
+  return (T*)c->pool.get((n ? n : 1) * sizeof(T));
+}
+static void pfree(hs_ctx* c, void* p) {
+  if (p) c->pool.put(p);
+}
 template <class T>
 static T* dmalloc(size_t n) {
   T* p = nullptr;
@@ -393,7 +404,7 @@ static hs_ctvec* new_ctvec(hs_ctx* c, i64 n) {
   hs_ctvec* v = new hs_ctvec();
   v->ctx = c;
   v->n = n;
-  v->d = dmalloc<u64>(std::max<i64>(n, 1) * ct_words(c));
+  v->d = pmalloc<u64>(c, std::max<i64>(n, 1) * ct_words(c));
   return v;
 }
 
@@ -564,11 +575,11 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
     for (i64 i = 0; i < rows; i++) HS_REQUIRE(rp[i + 1] >= rp[i], HS_EINVAL, "row_ptr must be nondecreasing");
     const i64 nnz = rp[rows];
     HS_REQUIRE(nnz == 0 || (col_idx && vals), HS_EINVAL, "null col_idx/vals");
+    // the column check runs on the device and is read back with the final synchronisation (no
+    // kernel below uses a column index as an address)
     if (nnz) {
       launch_csr_check(row_ptr, col_idx, rows, cols, bad.as<int>(), st);
       d2h(&hbad, bad.as<int>(), 1, st);
-      HS_CHECK_HIP(hipStreamSynchronize(st));
-      HS_REQUIRE(!hbad, HS_EINVAL, "column indices out of range or not strictly ascending within a row");
     }
     hs_matrix* M = new hs_matrix();
     M->ctx = c; M->R = rows; M->C = cols; M->nnz = nnz; M->encrypted = encrypt_values ? 1 : 0;
@@ -617,11 +628,11 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         M->parts.push_back(P);
       }
       const int G = (int)M->chunks.size();
-      M->d_cp = dmalloc<i64>(M->h_cp.size());
-      M->d_rm = dmalloc<i32>(M->h_rm.size());
-      M->d_va = dmalloc<i64>(nnz);
-      M->d_ci = dmalloc<i32>(nnz);
-      M->d_chunk = dmalloc<i64>(8ULL * std::max(G, 1));
+      M->d_cp = pmalloc<i64>(c, M->h_cp.size());
+      M->d_rm = pmalloc<i32>(c, M->h_rm.size());
+      M->d_va = pmalloc<i64>(c, nnz);
+      M->d_ci = pmalloc<i32>(c, nnz);
+      M->d_chunk = pmalloc<i64>(c, 8ULL * std::max(G, 1));
       h2d(M->d_cp, M->h_cp.data(), M->h_cp.size(), st);
       h2d(M->d_rm, M->h_rm.data(), M->h_rm.size(), st);
       std::vector<i64> cd(8ULL * std::max(G, 1), 0);
@@ -632,46 +643,51 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         d[0] = k.start; d[1] = k.c; d[2] = k.h; d[3] = P.cp_off; d[4] = P.nnz_off; d[5] = k.part;
       }
       h2d(M->d_chunk, cd.data(), cd.size(), st);
+      std::vector<DBuf> keep;  // scratch released only after the final synchronisation
+      keep.reserve(8);         // references into it stay valid
       if (rows && nnz) {
-        DBuf drank(&c->pool, rows * sizeof(int)), dpco(&c->pool, part_cp_off.size() * sizeof(i64)),
-            dpno(&c->pool, part_nnz_off.size() * sizeof(i64));
+        keep.emplace_back(&c->pool, rows * sizeof(int));
+        keep.emplace_back(&c->pool, part_cp_off.size() * sizeof(i64));
+        keep.emplace_back(&c->pool, part_nnz_off.size() * sizeof(i64));
+        DBuf &drank = keep[0], &dpco = keep[1], &dpno = keep[2];
         h2d(drank.as<int>(), rank.data(), rows, st);
         h2d(dpco.as<i64>(), part_cp_off.data(), part_cp_off.size(), st);
         h2d(dpno.as<i64>(), part_nnz_off.data(), part_nnz_off.size(), st);
         launch_cssc_scatter(row_ptr, col_idx, vals, drank.as<int>(), M->d_cp, dpco.as<i64>(), dpno.as<i64>(), rows, s, M->d_va,
                             M->d_ci, st);
-        HS_CHECK_HIP(hipStreamSynchronize(st));
       }
       // --- pack + encode (+ encrypt) every chunk; masks
+      std::vector<DBuf> hold;
       if (G) {
-        std::vector<DBuf> hold;
-        DBuf coef(&c->pool, (size_t)G * N * sizeof(u64));
+        keep.emplace_back(&c->pool, (size_t)G * N * sizeof(u64));
+        DBuf& coef = keep.back();
         PackArgs pa{};
         pa.va = M->d_va; pa.ci = M->d_ci; pa.v = nullptr; pa.cp = M->d_cp; pa.chunk = M->d_chunk;
         pa.out = coef.as<u64>(); pa.mode = 0;
         pack_encode(c, pa, G, st, hold);
         if (encrypt_values) {
-          M->d_pt = dmalloc<u64>((size_t)G * ct_words(c));
-          DBuf smp(&c->pool, (size_t)G * 3 * N * sizeof(int));
+          M->d_pt = pmalloc<u64>(c, (size_t)G * ct_words(c));
+          keep.emplace_back(&c->pool, (size_t)G * 3 * N * sizeof(int));
+          DBuf& smp = keep.back();
           launch_sample_small(c, smp.as<int>(), G, 3 * (i64)N, seed, P_ENC_U, 0, 1, 0, st);
           launch_sample_small(c, smp.as<int>() + N, G, 3 * (i64)N, seed, P_ENC_E0, 0, 1, 1, st);
           launch_sample_small(c, smp.as<int>() + 2 * N, G, 3 * (i64)N, seed, P_ENC_E1, 0, 1, 1, st);
           encrypt_coefs(c, coef.as<u64>(), smp.as<int>(), ks->pk, M->d_pt, G, st, hold);
-          HS_CHECK_HIP(hipStreamSynchronize(st));
         } else {
-          M->d_pt = dmalloc<u64>((size_t)G * c->L * N);
+          M->d_pt = pmalloc<u64>(c, (size_t)G * c->L * N);
           plain_ntt(c, coef.as<u64>(), M->d_pt, G, st, hold);
         }
         if (c->prm.agg_mode == 0) {
-          HS_CHECK_HIP(hipStreamSynchronize(st));
           pa.mode = 2;
           pack_encode(c, pa, G, st, hold);
-          M->d_mask = dmalloc<u64>((size_t)G * c->L * N);
+          M->d_mask = pmalloc<u64>(c, (size_t)G * c->L * N);
           plain_ntt(c, coef.as<u64>(), M->d_mask, G, st, hold);
         }
-        HS_CHECK_HIP(hipStreamSynchronize(st));
       }
+      HS_CHECK_HIP(hipStreamSynchronize(st));
+      HS_REQUIRE(!hbad, HS_EINVAL, "column indices out of range or not strictly ascending within a row");
     } catch (...) {
+      (void)hipStreamSynchronize(st);  // nothing in flight may still use the pooled memory
       hs_matrix_destroy(M);
       throw;
     }
@@ -682,8 +698,7 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
 void hs_matrix_destroy(hs_matrix* m) {
   if (!m) return;
   void* ptrs[] = {m->d_cp, m->d_rm, m->d_va, m->d_ci, m->d_chunk, m->d_pt, m->d_mask};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  for (void* p : ptrs) pfree(m->ctx, p);
   delete m;
 }
 
@@ -761,6 +776,7 @@ int hs_encrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const int64_t
         HS_CHECK_HIP(hipStreamSynchronize(st));
       }
     } catch (...) {
+      (void)hipStreamSynchronize(st);  // nothing in flight may still use the pooled memory
       hs_ctvec_destroy(x);
       throw;
     }
@@ -979,7 +995,7 @@ int hs_ctvec_import(hs_ctx* c, const uint64_t* host_limbs, int64_t n, hs_ctvec**
 
 void hs_ctvec_destroy(hs_ctvec* v) {
   if (!v) return;
-  if (v->d && v->owned) (void)hipFree(v->d);
+  if (v->d && v->owned) pfree(v->ctx, v->d);
   delete v;
 }
 
