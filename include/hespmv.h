@@ -148,6 +148,25 @@ int hs_he_spmv(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ct
 int hs_he_spmv_batch(hs_ctx* ctx, int n, const hs_keyset* const* ks, const hs_matrix* const* m,
                      const hs_ctvec* const* x, void* stream, hs_ctvec** y);
 
+/* Batched form recorded as a HIP graph, for a batch that is run repeatedly with new vector
+   contents (same handles): hs_batch_plan_create does all host work of hs_he_spmv_batch once (chunk
+   programs, rotation levels, item arrays, scratch and the result vectors), runs the batch once,
+   then records its kernel sequence into a graph; hs_batch_plan_run replays it on `stream`
+   (asynchronous; it reads the vectors x[r] as they are at replay time and overwrites the results).
+   Results equal hs_he_spmv_batch's.  The plan borrows ks, m and x (they must outlive it) and owns
+   its results: hs_batch_plan_output gives a borrowed handle, valid until the plan is destroyed
+   (do not destroy it).  Plaintext matrices only (HS_EINVAL for encrypted values).
+   hs_batch_plan_destroy waits for the plan's last replay. */
+/* Copy the ciphertexts of src into dst (same context and count), asynchronously on `stream`:
+   the way to give a graph plan new input vectors. */
+int hs_ctvec_copy(hs_ctvec* dst, const hs_ctvec* src, void* stream);
+typedef struct hs_batch_plan hs_batch_plan;
+int hs_batch_plan_create(hs_ctx* ctx, int n, const hs_keyset* const* ks, const hs_matrix* const* m,
+                         const hs_ctvec* const* x, void* stream, hs_batch_plan** out);
+int hs_batch_plan_run(hs_batch_plan* plan, void* stream);
+int hs_batch_plan_output(const hs_batch_plan* plan, int i, const hs_ctvec** y);
+void hs_batch_plan_destroy(hs_batch_plan* plan);
+
 /* ---------------------------------------------------------------- serving (continuous batching) */
 typedef struct hs_server hs_server;
 /* Start a server on `stream` (its own worker thread).  Engine ticks admit queued requests while
@@ -220,6 +239,22 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
 #define HS_OPT_KS_THRESHOLD 3
 #define HS_OPT_AUX_PATH 4
 int hs_set_option(int key, int64_t value);
+
+/* Autotuner.  Times, on synthetic operands and the key-switching key of `ks`, (1) the two variants
+   of the one-workgroup-per-limb transforms (N = 2^14: half-limb LDS with 512 threads vs whole limb
+   with 1024; N = 2^11..2^13: compile-time radix-16 rounds vs runtime radix-8 rounds) on a 32-item
+   rotation level, and (2) the two key-switch pipelines (two-pass vs one workgroup per limb) on
+   levels of B = 1, 2, 4, ..., 64 items, and stores the faster choice in the context; later calls
+   use it (results never depend on these choices; HS_OPT_KS_PIPELINE still forces a pipeline).
+   Report (host `report`, capacity `cap` doubles; *len receives the count, 24): [variant chosen,
+   ms variant 0, ms variant 1], then per B: [B, ms one-workgroup, ms two-pass] (0 when a variant
+   does not exist for the ring).  Not thread-safe against concurrent calls on the context. */
+int hs_autotune(hs_ctx* ctx, const hs_keyset* ks, void* stream, double* report, int cap, int* len);
+/* The context's launch choices: out[0] transform variant (0/1), out[1 + b] key-switch pipeline for
+   levels of 2^(b-1) < B <= 2^b items (b = 7: larger): 1 two-pass, 0 one workgroup per limb, -1 the
+   fixed threshold rule (HS_OPT_KS_THRESHOLD).  hs_set_tuning installs such a table. */
+int hs_tuning(const hs_ctx* ctx, int64_t out[9]);
+int hs_set_tuning(hs_ctx* ctx, const int64_t in[9]);
 
 /* Kernel timing: hs_profile(1) clears the records and brackets every subsequent kernel launch with
    two HIP events on its stream; hs_profile(0) stops.  hs_profile_summary waits for the recorded

@@ -250,15 +250,34 @@ static bool lds_limb_fits(const hs_ctx* c) { return c->logn <= 14; }
 // Pipeline choice for one level of B rotations: the one-workgroup-per-limb kernels move the least
 // data and win when the level has enough (target modulus x item) pairs to fill the GPU; the
 // two-pass kernels spread each transform over N / 2048 workgroups and win for small levels.
+// Batch-size bucket of the tuned pipeline table: B = 1 -> 0, 2 -> 1, 3..4 -> 2, ..., > 64 -> 7.
+static int ks_bucket(int B) {
+  int b = 0;
+  while ((1 << b) < B && b < 7) b++;
+  return b;
+}
+
 static bool use_two_pass(const hs_ctx* c, int B) {
   const int opt = g_opt_ks.load();
   if (!lds_limb_fits(c)) return true;
   if (opt == 1) return false;
   if (opt == 2) return true;
+  const int pick = c->ks_pick[ks_bucket(B)];
+  if (pick >= 0) return pick == 1;
   return (c->L + c->K) * B < g_opt_ks_threshold.load();
 }
 
-static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels, hipStream_t st) {
+// Scratch, item arrays and per-level shapes of a sequence of rotation levels (prepared on the
+// host, then enqueued without host waits; the enqueue step alone can be captured into a graph).
+struct LevelPlan {
+  std::vector<int> B;
+  std::vector<KsShape> shape;
+  std::vector<char> two;
+  DBuf ditems, D, ACC, PC, T1, E, ACC2, T2, F;
+  int64_t key_switches = 0, launches = 0;
+};
+
+static void prepare_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels, hipStream_t st, LevelPlan& P) {
   size_t total = 0, widest = 0;
   for (auto& l : levels) { total += l.size(); widest = std::max(widest, l.size()); }
   if (!total) return;
@@ -270,40 +289,52 @@ static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem
   bool any1 = false, any2 = false;
   for (auto& l : levels) {
     if (l.empty()) continue;
-    if (use_two_pass(c, (int)l.size())) any2 = true; else any1 = true;
+    const bool t = use_two_pass(c, (int)l.size());
+    P.B.push_back((int)l.size());
+    P.shape.push_back(ks_shape(c, (int)l.size()));
+    P.two.push_back(t ? 1 : 0);
+    if (t) any2 = true; else any1 = true;
+    P.key_switches += (int64_t)l.size();
+    P.launches += t ? 5 : 4;
   }
   const KsShape Smax = ks_shape(c, 1);  // the most digit groups any level uses
-  DBuf ditems(&c->pool, total * sizeof(RotItem));
-  DBuf D, ACC, PC, T1, E, ACC2, T2, F;
+  P.ditems = DBuf(&c->pool, total * sizeof(RotItem));
   if (any1) {
-    D = DBuf(&c->pool, widest * c->L * N * sizeof(u64));
-    ACC = DBuf(&c->pool, widest * Smax.ndg * 2 * LK * N * sizeof(double));
-    PC = DBuf(&c->pool, widest * 2 * c->K * N * sizeof(double));
+    P.D = DBuf(&c->pool, widest * c->L * N * sizeof(u64));
+    P.ACC = DBuf(&c->pool, widest * Smax.ndg * 2 * LK * N * sizeof(double));
+    P.PC = DBuf(&c->pool, widest * 2 * c->K * N * sizeof(double));
   }
   if (any2) {
-    T1 = DBuf(&c->pool, widest * c->L * N * sizeof(double));
-    E = DBuf(&c->pool, widest * c->dnum * LK * N * sizeof(double));
-    ACC2 = DBuf(&c->pool, widest * 2 * c->L * N * sizeof(double));
-    T2 = DBuf(&c->pool, widest * 2 * c->K * N * sizeof(double));
-    F = DBuf(&c->pool, widest * 2 * c->L * N * sizeof(double));
+    P.T1 = DBuf(&c->pool, widest * c->L * N * sizeof(double));
+    P.E = DBuf(&c->pool, widest * c->dnum * LK * N * sizeof(double));
+    P.ACC2 = DBuf(&c->pool, widest * 2 * c->L * N * sizeof(double));
+    P.T2 = DBuf(&c->pool, widest * 2 * c->K * N * sizeof(double));
+    P.F = DBuf(&c->pool, widest * 2 * c->L * N * sizeof(double));
   }
-  h2d(ditems.as<RotItem>(), flat.data(), flat.size(), st);
+  h2d(P.ditems.as<RotItem>(), flat.data(), flat.size(), st);
+}
+
+static void enqueue_levels(hs_ctx* c, const LevelPlan& P, hipStream_t st) {
   size_t off = 0;
-  for (auto& l : levels) {
-    const int B = (int)l.size();
-    if (!B) continue;
-    const KsShape Sh = ks_shape(c, B);
-    if (use_two_pass(c, B)) {
-      launch_rotate_batch2(c, ditems.as<RotItem>() + off, B, Sh, T1.as<double>(), E.as<double>(), ACC2.as<double>(), T2.as<double>(),
-                           F.as<double>(), st);
-      g_counters[2] += 5;
+  for (size_t lv = 0; lv < P.B.size(); lv++) {
+    const int B = P.B[lv];
+    const RotItem* items = P.ditems.as<RotItem>() + off;
+    if (P.two[lv]) {
+      launch_rotate_batch2(c, items, B, P.shape[lv], P.T1.as<double>(), P.E.as<double>(), P.ACC2.as<double>(), P.T2.as<double>(),
+                           P.F.as<double>(), st);
     } else {
-      launch_rotate_batch(c, ditems.as<RotItem>() + off, B, Sh, D.as<u64>(), ACC.as<double>(), PC.as<double>(), st);
-      g_counters[2] += 4;
+      launch_rotate_batch(c, items, B, P.shape[lv], P.D.as<u64>(), P.ACC.as<double>(), P.PC.as<double>(), st);
     }
     off += B;
-    g_counters[0] += B;
   }
+}
+
+static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels, hipStream_t st) {
+  LevelPlan P;
+  prepare_levels(c, levels, st, P);
+  enqueue_levels(c, P, st);
+  g_counters[0] += P.key_switches;
+  g_counters[2] += P.launches;
   // the item array and scratch return to the pool: wait until the kernels are done with them
   HS_CHECK_HIP(hipStreamSynchronize(st));
 }
@@ -790,99 +821,130 @@ namespace hs {
 // Encrypted SpMV of n independent requests (matrix, encrypted vector, key-set): the slot-wise
 // products, then every request's chunk programs (totalSum rotations) merged level by level into
 // batched rotations, then the masks and per-partition sums.  Results: one vector per request.
+// prepare() does all host work, allocation and uploads; enqueue() only launches kernels (no host
+// waits, copies or allocations), so it can be recorded into a graph and replayed.
+struct BatchWork {
+  struct Prod { const u64* x; const u64* pt; u64* out; int G; };
+  struct Mask { const u64* const* wp; const u64* mask; const int* pc0; const int* pnc; u64* y; int nP; };
+  std::vector<Prod> prods;
+  std::vector<const u64*> pa, pb, rk;   // exact ct x ct products (encrypted matrices)
+  std::vector<u64*> po;
+  LevelPlan levels;
+  std::vector<Mask> masks;
+  std::vector<DBuf> keep;
+  int64_t counters[5] = {0, 0, 0, 0, 0};
+
+  void prepare(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_matrix* const* m, const hs_ctvec* const* x, hipStream_t st,
+               hs_ctvec** y) {
+    const size_t CW = ct_words(c);
+    struct Req {
+      int G, nP;
+      std::vector<std::vector<MicroOp>> progs;
+      std::vector<int> wt_base;
+      int nwt = 0;
+      u64* vbuf = nullptr;
+      u64* wtbuf = nullptr;
+    };
+    std::vector<Req> rq(n);
+    int nlog = 0;
+    keep.reserve(2 * (size_t)n + 3 * (size_t)n + 1);
+    for (int r = 0; r < n; r++) {
+      Req& q = rq[r];
+      q.G = (int)m[r]->chunks.size();
+      q.nP = (int)m[r]->parts.size();
+      q.progs.resize(q.G);
+      q.wt_base.assign(q.G, -1);
+      for (int g = 0; g < q.G; g++) {
+        q.progs[g] = total_sum_program(c, m[r]->chunks[g].h, m[r]->chunks[g].c, &nlog);
+        if (q.progs[g].size() > 1) { q.wt_base[g] = q.nwt; q.nwt += 4; }
+      }
+      keep.emplace_back(&c->pool, (size_t)std::max(q.G, 1) * CW * sizeof(u64));
+      q.vbuf = keep.back().as<u64>();
+      keep.emplace_back(&c->pool, (size_t)std::max(q.nwt, 1) * CW * sizeof(u64));
+      q.wtbuf = keep.back().as<u64>();
+    }
+    auto buf = [&](int r, int g, int id) -> u64* {
+      Req& q = rq[r];
+      return id == 0 ? q.vbuf + (size_t)g * CW : q.wtbuf + (size_t)(q.wt_base[g] + id - 1) * CW;
+    };
+    // 1. slot-wise products: HE-CMult, or HE-Mult + relinearisation for encrypted matrix values
+    for (int r = 0; r < n; r++) {
+      if (!rq[r].G) continue;
+      if (m[r]->encrypted) {
+        for (int g = 0; g < rq[r].G; g++) {
+          pa.push_back(m[r]->d_pt + (size_t)g * CW);
+          pb.push_back(x[r]->d + (size_t)g * CW);
+          po.push_back(rq[r].vbuf + (size_t)g * CW);
+          rk.push_back(ks[r]->rk);
+        }
+      } else {
+        prods.push_back(Prod{x[r]->d, m[r]->d_pt, rq[r].vbuf, rq[r].G});
+        counters[2]++;
+      }
+      counters[3] += rq[r].G;
+    }
+    // 2. totalSum of all chunks of all requests, level by level
+    size_t nlev = 0;
+    for (auto& q : rq)
+      for (auto& p : q.progs) nlev = std::max(nlev, p.size() - 1);
+    std::vector<std::vector<RotItem>> lv_items(nlev);
+    for (size_t lv = 0; lv < nlev; lv++)
+      for (int r = 0; r < n; r++)
+        for (int g = 0; g < rq[r].G; g++) {
+          const auto& prog = rq[r].progs[g];
+          if (lv + 1 >= prog.size()) continue;
+          const MicroOp& op = prog[lv];
+          RotItem it{};
+          it.in = buf(r, g, op.in);
+          it.out = buf(r, g, op.out);
+          it.addend = op.addend >= 0 ? buf(r, g, op.addend) : nullptr;
+          it.key = ks[r]->gk[op.pow2];
+          it.galois = (u32)galois_pow2(c, op.pow2);
+          lv_items[lv].push_back(it);
+        }
+    prepare_levels(c, lv_items, st, levels);
+    counters[0] += levels.key_switches;
+    counters[2] += levels.launches;
+    counters[1] = nlog;
+    // 3. masks and the per-partition sums
+    for (int r = 0; r < n; r++) {
+      Req& q = rq[r];
+      if (!q.nP) continue;
+      std::vector<const u64*> wp(std::max(q.G, 1), nullptr);
+      for (int g = 0; g < q.G; g++) wp[g] = buf(r, g, q.progs[g].back().in);
+      std::vector<int> pc0(q.nP), pnc(q.nP);
+      for (int p = 0; p < q.nP; p++) { pc0[p] = m[r]->parts[p].chunk0; pnc[p] = m[r]->parts[p].nchunks; }
+      keep.emplace_back(&c->pool, wp.size() * sizeof(u64*));
+      const u64* const* dwp = keep.back().as<const u64*>();
+      h2d(keep.back().as<const u64*>(), wp.data(), wp.size(), st);
+      keep.emplace_back(&c->pool, q.nP * sizeof(int));
+      const int* dpc0 = keep.back().as<int>();
+      h2d(keep.back().as<int>(), pc0.data(), q.nP, st);
+      keep.emplace_back(&c->pool, q.nP * sizeof(int));
+      const int* dpnc = keep.back().as<int>();
+      h2d(keep.back().as<int>(), pnc.data(), q.nP, st);
+      masks.push_back(Mask{dwp, c->prm.agg_mode == 0 ? m[r]->d_mask : nullptr, dpc0, dpnc, y[r]->d, q.nP});
+      counters[2]++;
+      counters[4] += c->prm.agg_mode == 0 ? q.G : 0;
+    }
+  }
+
+  bool capturable() const { return pa.empty(); }
+
+  void enqueue(hs_ctx* c, hipStream_t st) const {
+    for (const Prod& p : prods) launch_mul_plain(c, p.x, p.pt, p.out, p.G, c->L, st);
+    if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), st);
+    enqueue_levels(c, levels, st);
+    for (const Mask& k : masks) launch_mask_acc(c, k.wp, k.mask, k.pc0, k.pnc, k.y, k.nP, st);
+  }
+};
+
 static void spmv_many(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_matrix* const* m, const hs_ctvec* const* x,
                       hipStream_t st, hs_ctvec** y) {
-  for (auto& v : g_counters) v = 0;
-  const size_t CW = ct_words(c);
-  struct Req {
-    int G, nP;
-    std::vector<std::vector<MicroOp>> progs;
-    std::vector<int> wt_base;
-    int nwt = 0;
-    DBuf vbuf, wtbuf;
-  };
-  std::vector<Req> rq(n);
-  int nlog = 0;
-  for (int r = 0; r < n; r++) {
-    Req& q = rq[r];
-    q.G = (int)m[r]->chunks.size();
-    q.nP = (int)m[r]->parts.size();
-    q.progs.resize(q.G);
-    q.wt_base.assign(q.G, -1);
-    for (int g = 0; g < q.G; g++) {
-      q.progs[g] = total_sum_program(c, m[r]->chunks[g].h, m[r]->chunks[g].c, &nlog);
-      if (q.progs[g].size() > 1) { q.wt_base[g] = q.nwt; q.nwt += 4; }
-    }
-    q.vbuf = DBuf(&c->pool, (size_t)std::max(q.G, 1) * CW * sizeof(u64));
-    q.wtbuf = DBuf(&c->pool, (size_t)std::max(q.nwt, 1) * CW * sizeof(u64));
-  }
-  auto buf = [&](int r, int g, int id) -> u64* {
-    Req& q = rq[r];
-    return id == 0 ? q.vbuf.as<u64>() + (size_t)g * CW : q.wtbuf.as<u64>() + (size_t)(q.wt_base[g] + id - 1) * CW;
-  };
-  // 1. slot-wise products of every chunk: HE-CMult, or HE-Mult + relinearisation when the matrix
-  //    values are encrypted (all such products of the batch in one exact-product call)
-  std::vector<const u64*> pa, pb, rk;
-  std::vector<u64*> po;
-  for (int r = 0; r < n; r++) {
-    if (!rq[r].G) continue;
-    if (m[r]->encrypted) {
-      for (int g = 0; g < rq[r].G; g++) {
-        pa.push_back(m[r]->d_pt + (size_t)g * CW);
-        pb.push_back(x[r]->d + (size_t)g * CW);
-        po.push_back(rq[r].vbuf.as<u64>() + (size_t)g * CW);
-        rk.push_back(ks[r]->rk);
-      }
-    } else {
-      launch_mul_plain(c, x[r]->d, m[r]->d_pt, rq[r].vbuf.as<u64>(), rq[r].G, c->L, st);
-      g_counters[2]++;
-    }
-    g_counters[3] += rq[r].G;
-  }
-  if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), st);
-  // 2. totalSum of all chunks of all requests, level by level
-  size_t nlev = 0;
-  for (auto& q : rq)
-    for (auto& p : q.progs) nlev = std::max(nlev, p.size() - 1);
-  std::vector<std::vector<RotItem>> levels(nlev);
-  for (size_t lv = 0; lv < nlev; lv++)
-    for (int r = 0; r < n; r++)
-      for (int g = 0; g < rq[r].G; g++) {
-        const auto& prog = rq[r].progs[g];
-        if (lv + 1 >= prog.size()) continue;
-        const MicroOp& op = prog[lv];
-        RotItem it{};
-        it.in = buf(r, g, op.in);
-        it.out = buf(r, g, op.out);
-        it.addend = op.addend >= 0 ? buf(r, g, op.addend) : nullptr;
-        it.key = ks[r]->gk[op.pow2];
-        it.galois = (u32)galois_pow2(c, op.pow2);
-        levels[lv].push_back(it);
-      }
-  run_rotation_levels(c, levels, st);
-  g_counters[1] = nlog;
-  // 3. masks and the per-partition sums
-  std::vector<const u64*> wptr;
-  std::vector<DBuf> keep;
-  for (int r = 0; r < n; r++) {
-    Req& q = rq[r];
-    if (!q.nP) continue;
-    std::vector<const u64*> wp(std::max(q.G, 1), nullptr);
-    for (int g = 0; g < q.G; g++) wp[g] = buf(r, g, q.progs[g].back().in);
-    std::vector<int> pc0(q.nP), pnc(q.nP);
-    for (int p = 0; p < q.nP; p++) { pc0[p] = m[r]->parts[p].chunk0; pnc[p] = m[r]->parts[p].nchunks; }
-    keep.emplace_back(&c->pool, wp.size() * sizeof(u64*));
-    h2d(keep.back().as<const u64*>(), wp.data(), wp.size(), st);
-    keep.emplace_back(&c->pool, q.nP * sizeof(int));
-    h2d(keep.back().as<int>(), pc0.data(), q.nP, st);
-    const int* dpc0 = keep.back().as<int>();
-    keep.emplace_back(&c->pool, q.nP * sizeof(int));
-    h2d(keep.back().as<int>(), pnc.data(), q.nP, st);
-    const int* dpnc = keep.back().as<int>();
-    launch_mask_acc(c, keep[keep.size() - 3].as<const u64*>(), c->prm.agg_mode == 0 ? m[r]->d_mask : nullptr, dpc0, dpnc, y[r]->d, q.nP, st);
-    g_counters[2]++;
-    g_counters[4] += c->prm.agg_mode == 0 ? q.G : 0;
-  }
+  BatchWork w;
+  w.prepare(c, n, ks, m, x, st, y);
+  for (int i = 0; i < 5; i++) g_counters[i] = w.counters[i];  // the relinearisations add theirs
+  w.enqueue(c, st);
   HS_CHECK_HIP(hipStreamSynchronize(st));
 }
 }  // namespace hs
@@ -913,6 +975,229 @@ int hs_he_spmv_batch(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_matr
     }
     for (int r = 0; r < n; r++) y[r] = out[r];
   });
+}
+
+}  // extern "C"
+
+struct hs_batch_plan {
+  hs_ctx* ctx = nullptr;
+  std::vector<hs_ctvec*> y;
+  hs::BatchWork work;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last = nullptr;  // stream of the last replay
+  bool ran = false;
+};
+
+extern "C" {
+
+int hs_ctvec_copy(hs_ctvec* dst, const hs_ctvec* src, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(dst && src && dst->ctx == src->ctx, HS_EINVAL, "vectors of one context required");
+    HS_REQUIRE(dst->n == src->n, HS_EINVAL, "ciphertext counts differ");
+    if (dst->n && dst->d != src->d)
+      HS_CHECK_HIP(hipMemcpyAsync(dst->d, src->d, (size_t)src->n * ct_words(src->ctx) * sizeof(u64), hipMemcpyDeviceToDevice, S(stream)));
+  });
+}
+
+int hs_autotune(hs_ctx* c, const hs_keyset* ks, void* stream, double* report, int cap, int* len) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks && ks->ctx == c && !ks->gk.empty(), HS_EINVAL, "autotuning needs a key-set of this context");
+    hipStream_t st = S(stream);
+    const size_t N = c->N, CW = ct_words(c);
+    const int LK = c->L + c->K;
+    constexpr int kBmax = 64, kIn = 4;
+    // synthetic operands: canonical residues (their values do not affect the timing)
+    std::vector<u64> host((size_t)kIn * CW);
+    u64 z = 0x9E3779B97F4A7C15ULL;
+    for (int i = 0; i < kIn; i++)
+      for (int l = 0; l < 2 * c->L; l++)
+        for (size_t k = 0; k < N; k++) {
+          z ^= z << 13; z ^= z >> 7; z ^= z << 17;
+          host[(size_t)i * CW + (size_t)l * N + k] = z % c->mod[l % c->L];
+        }
+    DBuf in(&c->pool, host.size() * sizeof(u64)), outb(&c->pool, (size_t)kBmax * CW * sizeof(u64));
+    h2d(in.as<u64>(), host.data(), host.size(), st);
+    std::vector<RotItem> items(kBmax);
+    for (int i = 0; i < kBmax; i++) {
+      items[i] = RotItem{};
+      items[i].in = in.as<u64>() + (size_t)(i % kIn) * CW;
+      items[i].out = outb.as<u64>() + (size_t)i * CW;
+      items[i].key = ks->gk[0];
+      items[i].galois = (u32)galois_pow2(c, 0);
+    }
+    DBuf ditems(&c->pool, items.size() * sizeof(RotItem));
+    h2d(ditems.as<RotItem>(), items.data(), items.size(), st);
+    const bool one_ok = lds_limb_fits(c);
+    const KsShape Smax = ks_shape(c, 1);
+    DBuf D, ACC, PC;
+    if (one_ok) {
+      D = DBuf(&c->pool, (size_t)kBmax * c->L * N * sizeof(u64));
+      ACC = DBuf(&c->pool, (size_t)kBmax * Smax.ndg * 2 * LK * N * sizeof(double));
+      PC = DBuf(&c->pool, (size_t)kBmax * 2 * c->K * N * sizeof(double));
+    }
+    DBuf T1(&c->pool, (size_t)kBmax * c->L * N * sizeof(double)), E(&c->pool, (size_t)kBmax * c->dnum * LK * N * sizeof(double)),
+        ACC2(&c->pool, (size_t)kBmax * 2 * c->L * N * sizeof(double)), T2(&c->pool, (size_t)kBmax * 2 * c->K * N * sizeof(double)),
+        F(&c->pool, (size_t)kBmax * 2 * c->L * N * sizeof(double));
+    hipEvent_t ea, eb;
+    HS_CHECK_HIP(hipEventCreate(&ea));
+    HS_CHECK_HIP(hipEventCreate(&eb));
+    auto level = [&](bool two, int B) {
+      const KsShape Sh = ks_shape(c, B);
+      if (two) launch_rotate_batch2(c, ditems.as<RotItem>(), B, Sh, T1.as<double>(), E.as<double>(), ACC2.as<double>(), T2.as<double>(),
+                                    F.as<double>(), st);
+      else launch_rotate_batch(c, ditems.as<RotItem>(), B, Sh, D.as<u64>(), ACC.as<double>(), PC.as<double>(), st);
+    };
+    auto time_ms = [&](bool two, int B) {
+      level(two, B);  // warm-up
+      const int reps = B <= 8 ? 5 : 3;
+      HS_CHECK_HIP(hipEventRecord(ea, st));
+      for (int r = 0; r < reps; r++) level(two, B);
+      HS_CHECK_HIP(hipEventRecord(eb, st));
+      HS_CHECK_HIP(hipEventSynchronize(eb));
+      float ms = 0;
+      HS_CHECK_HIP(hipEventElapsedTime(&ms, ea, eb));
+      return (double)ms / reps;
+    };
+    std::vector<double> rep;
+    try {
+      // 1. limb-transform variant of the one-workgroup-per-limb kernels, timed on a 32-item level
+      double tv[2] = {0, 0};
+      const bool has_alt = one_ok && c->logn >= 11;
+      if (has_alt) {
+        for (int v = 0; v < 2; v++) {
+          c->xf_variant = v;
+          tv[v] = time_ms(false, 32);
+        }
+        c->xf_variant = tv[1] < tv[0] ? 1 : 0;
+      } else {
+        c->xf_variant = 0;
+      }
+      rep.push_back(c->xf_variant);
+      rep.push_back(tv[0]);
+      rep.push_back(tv[1]);
+      // 2. key-switch pipeline per batch-size bucket
+      for (int b = 0; b < 7; b++) {
+        const int B = 1 << b;
+        const double t1 = one_ok ? time_ms(false, B) : 0.0;
+        const double t2 = time_ms(true, B);
+        c->ks_pick[b] = (!one_ok || t2 <= t1) ? 1 : 0;
+        rep.push_back(B);
+        rep.push_back(t1);
+        rep.push_back(t2);
+      }
+      c->ks_pick[7] = c->ks_pick[6];
+      HS_CHECK_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      (void)hipEventDestroy(ea);
+      (void)hipEventDestroy(eb);
+      throw;
+    }
+    (void)hipEventDestroy(ea);
+    (void)hipEventDestroy(eb);
+    if (len) *len = (int)rep.size();
+    if (report) {
+      HS_REQUIRE(cap >= (int)rep.size(), HS_ECAPACITY, "report buffer too small");
+      std::copy(rep.begin(), rep.end(), report);
+    }
+  });
+}
+
+int hs_tuning(const hs_ctx* c, int64_t out[9]) {
+  return guarded([&] {
+    HS_REQUIRE(c && out, HS_EINVAL, "null argument");
+    out[0] = c->xf_variant;
+    for (int b = 0; b < 8; b++) out[1 + b] = c->ks_pick[b];
+  });
+}
+
+int hs_set_tuning(hs_ctx* c, const int64_t in[9]) {
+  return guarded([&] {
+    HS_REQUIRE(c && in, HS_EINVAL, "null argument");
+    HS_REQUIRE(in[0] == 0 || in[0] == 1, HS_EINVAL, "transform variant must be 0 or 1");
+    for (int b = 0; b < 8; b++) HS_REQUIRE(in[1 + b] >= -1 && in[1 + b] <= 1, HS_EINVAL, "pipeline pick must be -1, 0 or 1");
+    c->xf_variant = (int)in[0];
+    for (int b = 0; b < 8; b++) c->ks_pick[b] = (signed char)in[1 + b];
+  });
+}
+
+int hs_batch_plan_create(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_matrix* const* m, const hs_ctvec* const* x,
+                         void* stream, hs_batch_plan** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && out && n >= 1 && ks && m && x, HS_EINVAL, "null argument or empty batch");
+    *out = nullptr;
+    for (int r = 0; r < n; r++) {
+      HS_REQUIRE(ks[r] && m[r] && x[r], HS_EINVAL, "null handle in the batch");
+      HS_REQUIRE(ks[r]->ctx == c && m[r]->ctx == c && x[r]->ctx == c, HS_EKEY, "handles from another context");
+      HS_REQUIRE(x[r]->n == (i64)m[r]->chunks.size(), HS_EINVAL, "the vector must hold one ciphertext per chunk");
+      HS_REQUIRE(!m[r]->encrypted, HS_EINVAL, "graph plans take plaintext matrices");
+    }
+    hipStream_t st = S(stream);
+    hs_batch_plan* P = new hs_batch_plan();
+    P->ctx = c;
+    hipStream_t cs = nullptr;
+    try {
+      for (int r = 0; r < n; r++) P->y.push_back(new_ctvec(c, (i64)m[r]->parts.size()));
+      P->work.prepare(c, n, ks, m, x, st, P->y.data());
+      // one eager pass: the results are valid at once, and every kernel attribute is set before
+      // recording (no runtime configuration calls inside the captured region)
+      P->work.enqueue(c, st);
+      HS_CHECK_HIP(hipStreamSynchronize(st));
+      HS_CHECK_HIP(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+      profile_capturing(true);
+      hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+      if (e == hipSuccess) {
+        try {
+          P->work.enqueue(c, cs);
+        } catch (...) {
+          hipGraph_t g = nullptr;
+          (void)hipStreamEndCapture(cs, &g);
+          if (g) (void)hipGraphDestroy(g);
+          throw;
+        }
+        e = hipStreamEndCapture(cs, &P->graph);
+      }
+      profile_capturing(false);
+      HS_CHECK_HIP(e);
+      HS_CHECK_HIP(hipGraphInstantiate(&P->exec, P->graph, nullptr, nullptr, 0));
+      HS_CHECK_HIP(hipStreamDestroy(cs));
+      cs = nullptr;
+    } catch (...) {
+      profile_capturing(false);
+      if (cs) (void)hipStreamDestroy(cs);
+      (void)hipStreamSynchronize(st);
+      hs_batch_plan_destroy(P);
+      throw;
+    }
+    *out = P;
+  });
+}
+
+int hs_batch_plan_run(hs_batch_plan* P, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(P && P->exec, HS_EINVAL, "null plan");
+    hipStream_t st = S(stream);
+    HS_CHECK_HIP(hipGraphLaunch(P->exec, st));
+    P->last = st;
+    P->ran = true;
+  });
+}
+
+int hs_batch_plan_output(const hs_batch_plan* P, int i, const hs_ctvec** y) {
+  return guarded([&] {
+    HS_REQUIRE(P && y && i >= 0 && i < (int)P->y.size(), HS_EINVAL, "bad plan output index");
+    *y = P->y[i];
+  });
+}
+
+void hs_batch_plan_destroy(hs_batch_plan* P) {
+  if (!P) return;
+  if (P->ran) (void)hipStreamSynchronize(P->last);
+  if (P->exec) (void)hipGraphExecDestroy(P->exec);
+  if (P->graph) (void)hipGraphDestroy(P->graph);
+  for (hs_ctvec* v : P->y) hs_ctvec_destroy(v);
+  delete P;
 }
 
 int hs_decrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* y, int64_t* out, int64_t rows,

@@ -132,6 +132,12 @@ struct hs_ctx {
   hs::u64* d_t_mu = nullptr;
   double2* d_t_r64 = nullptr;
   hs::Pool pool;
+  // launch choices set by hs_autotune (results do not depend on them):
+  //   xf_variant 0: compile-time / half-limb transforms, 1: runtime radix-8 / whole-limb;
+  //   ks_pick[b]: key-switch pipeline for levels of 2^(b-1) < B <= 2^b items (b = 7: larger),
+  //   1 two-pass, 0 one workgroup per limb, -1 the fixed threshold rule.
+  int xf_variant = 0;
+  signed char ks_pick[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
 };
 
 struct hs_keyset {

@@ -73,6 +73,7 @@ class ProfScope {
   bool active_ = false;
 };
 void profile_enable(bool on);
+void profile_capturing(bool on);  // calling thread is recording a graph: no timing events
 std::string profile_summary();
 
 void upload_cdt(const u64* tab20);

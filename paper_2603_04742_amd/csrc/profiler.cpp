@@ -32,7 +32,12 @@ hipEvent_t take_event() {
 }
 }  // namespace
 
+// Launches recorded into a graph are not timed (their events would become graph nodes).
+static thread_local bool t_capturing = false;
+void profile_capturing(bool on) { t_capturing = on; }
+
 ProfScope::ProfScope(const char* name, hipStream_t st) : name_(name), st_(st) {
+  if (t_capturing) return;
   std::lock_guard<std::mutex> g(g_mu);
   if (!g_on) return;
   a_ = take_event();

@@ -75,6 +75,14 @@ SIGNATURES = {
     "hs_server_stats": (_int, [_vp, _i64p, ctypes.POINTER(ctypes.c_double)]),
     "hs_server_destroy": (None, [_vp]),
     "hs_profile_summary": (_int, [ctypes.c_char_p, _i64, _i64p]),
+    "hs_batch_plan_create": (_int, [_vp, _int, _pp, _pp, _pp, _vp, _pp]),
+    "hs_batch_plan_run": (_int, [_vp, _vp]),
+    "hs_batch_plan_output": (_int, [_vp, _int, _pp]),
+    "hs_batch_plan_destroy": (None, [_vp]),
+    "hs_ctvec_copy": (_int, [_vp, _vp, _vp]),
+    "hs_autotune": (_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _int, ctypes.POINTER(ctypes.c_int)]),
+    "hs_tuning": (_int, [_vp, _i64p]),
+    "hs_set_tuning": (_int, [_vp, _i64p]),
 }
 
 if not os.path.exists(LIB_PATH):
@@ -178,8 +186,9 @@ class Keyset:
 
 
 class CtVec:
-    def __init__(self, ctx, h):
-        self.ctx, self.h = ctx, h
+    def __init__(self, ctx, h, owner=None):
+        # owner: the object that owns a borrowed handle (a BatchPlan); such a vector is not destroyed
+        self.ctx, self.h, self.owner = ctx, h, owner
 
     @classmethod
     def from_host(cls, ctx, limbs, n):
@@ -189,12 +198,16 @@ class CtVec:
         return cls(ctx, h)
 
     def close(self):
-        if getattr(self, "h", None) and lib is not None:  # lib is None during interpreter shutdown
+        if getattr(self, "h", None) and lib is not None and getattr(self, "owner", None) is None:  # lib: None at shutdown
             lib.hs_ctvec_destroy(self.h)
-            self.h = None
+        self.h = None
 
     def __del__(self):
         self.close()
+
+    def copy_from(self, src):
+        """Overwrite this vector's ciphertexts with src's (same count), on the current stream."""
+        _check(lib.hs_ctvec_copy(self.h, src.h, _stream()))
 
     def count(self):
         n = ctypes.c_int64()
@@ -275,6 +288,60 @@ def he_spmv_batch(ctx, kss, ms, xs):
     ys = (ctypes.c_void_p * max(n, 1))()
     _check(lib.hs_he_spmv_batch(ctx.h, n, arr(kss), arr(ms), arr(xs), _stream(), ys))
     return [CtVec(ctx, ctypes.c_void_p(ys[i])) for i in range(n)]
+
+
+def autotune(ctx, ks):
+    """Time the launch variants on this context and keep the faster ones; returns the report:
+    {"variant": v, "variant_ms": [v0, v1], "pipelines": [(B, ms one-workgroup, ms two-pass), ...]}."""
+    buf = (ctypes.c_double * 64)()
+    n = ctypes.c_int()
+    _check(lib.hs_autotune(ctx.h, ks.h, _stream(), buf, 64, ctypes.byref(n)))
+    r = list(buf[:n.value])
+    return {"variant": int(r[0]), "variant_ms": r[1:3],
+            "pipelines": [(int(r[3 + 3 * i]), r[4 + 3 * i], r[5 + 3 * i]) for i in range((len(r) - 3) // 3)]}
+
+
+def tuning(ctx):
+    out = (ctypes.c_int64 * 9)()
+    _check(lib.hs_tuning(ctx.h, out))
+    return list(out)
+
+
+def set_tuning(ctx, table):
+    arr = (ctypes.c_int64 * 9)(*[int(v) for v in table])
+    _check(lib.hs_set_tuning(ctx.h, arr))
+
+
+class BatchPlan:
+    """hs_he_spmv_batch recorded as a HIP graph: built (and run once) at construction, replayed by
+    run() on the current stream.  outputs() are borrowed from the plan."""
+
+    def __init__(self, ctx, kss, ms, xs):
+        self.ctx, self._refs = ctx, (list(kss), list(ms), list(xs))
+        n = len(ms)
+        arr = lambda hs: (ctypes.c_void_p * max(n, 1))(*[h.h for h in hs])
+        h = ctypes.c_void_p()
+        _check(lib.hs_batch_plan_create(ctx.h, n, arr(kss), arr(ms), arr(xs), _stream(), ctypes.byref(h)))
+        self.h, self.n = h, n
+
+    def run(self):
+        _check(lib.hs_batch_plan_run(self.h, _stream()))
+
+    def outputs(self):
+        out = []
+        for i in range(self.n):
+            y = ctypes.c_void_p()
+            _check(lib.hs_batch_plan_output(self.h, i, ctypes.byref(y)))
+            out.append(CtVec(self.ctx, y, owner=self))
+        return out
+
+    def close(self):
+        if getattr(self, "h", None) and lib is not None:
+            lib.hs_batch_plan_destroy(self.h)
+        self.h = None
+
+    def __del__(self):
+        self.close()
 
 
 def decrypt(ctx, ks, m, y, out):
