@@ -67,6 +67,7 @@ def main():
     torch.cuda.set_device(dev)
     ctx = H.Context(logn, L, bits, K, agg_mode=agg)
     ks = ctx.keygen(0x5EED)
+    tune = H.autotune(ctx, ks)  # launch variants for this context (untimed, once)
     rp = torch.from_numpy(w["row_ptr"]).to(dev)
     col = torch.from_numpy(w["col"].astype(np.int32)).to(dev)
     val = torch.from_numpy(w["val"].astype(np.int64)).to(dev)
@@ -196,6 +197,9 @@ def main():
                 "avg_launch_ms": round(ntt_ms, 4), "bytes_per_limb": 16 * N},
         "roofline": roof,
         "keyswitch_unit": keyswitch,
+        "autotune": {"keyswitch_transform_variant": tune["variant"], "ntt_transform_variant": tune["ntt_variant"],
+                     "tuning_table": H.tuning(ctx),
+                     "level_ms_by_B": {str(b): [round(t1, 4), round(t2, 4)] for b, t1, t2 in tune["pipelines"]}},
     }
     if args.workload == "zipf16k" and not args.no_batch:
         result["batched_vs_plain"] = batched_vs_plain(H, W, torch, dev)
@@ -232,9 +236,12 @@ def keyswitch_kernel_bytes(L, K, N):
 def batched_vs_plain(H, W, torch, dev, reps=3):
     """The 64-matrix batch (rows log-uniform in [512, 16384], densities log-uniform in [0.05%, 1%],
     values in [-7, 7]; ring N=16384, 6x50-bit + 1): 64 sequential hs_he_spmv calls against one
-    hs_he_spmv_batch call, matrices packed and vectors encrypted beforehand."""
+    hs_he_spmv_batch call and against replays of the batch recorded as a HIP graph; matrices packed
+    and vectors encrypted beforehand, launch variants chosen by the autotuner (untimed, once per
+    context)."""
     ctx = H.Context(14, 6, 50, 1, agg_mode=0)
     ks = ctx.keygen(0xBA7C)
+    tune = H.autotune(ctx, ks)
     ws = W.batch64()
     ms, xs = [], []
     for i, w in enumerate(ws):
@@ -250,6 +257,17 @@ def batched_vs_plain(H, W, torch, dev, reps=3):
     torch.cuda.synchronize()
     t_batch = (time.perf_counter() - t0) / reps
     counters = H.last_counters()
+    # graph replays (the plan's construction does the host work and one eager run: untimed)
+    plan = H.BatchPlan(ctx, [ks] * len(ms), ms, xs)
+    plan.run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.run()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    graph_same = all(np.array_equal(a.export_all(), b.export_all()) for a, b in zip(plan.outputs()[:8], ys[:8]))
+    plan.close()
     for m, x in zip(ms, xs):
         H.he_spmv(ctx, ks, m, x)
     torch.cuda.synchronize()
@@ -259,7 +277,7 @@ def batched_vs_plain(H, W, torch, dev, reps=3):
             H.he_spmv(ctx, ks, m, x)
     torch.cuda.synchronize()
     t_plain = (time.perf_counter() - t0) / reps
-    ok = True
+    ok = graph_same
     for w, m, y in zip(ws[:8], ms[:8], ys[:8]):
         out = torch.zeros(w["R"], dtype=torch.int64, device=dev)
         H.decrypt(ctx, ks, m, y, out)
@@ -267,9 +285,12 @@ def batched_vs_plain(H, W, torch, dev, reps=3):
     return {"workload": "batch64: 64 matrices, rows log-uniform [512,16384], density log-uniform [0.05%%,1%%], "
                         "%d nnz, %d chunks, %d key switches; ring N=16384 6x50-bit + 1" %
                         (sum(int(w["row_ptr"][-1]) for w in ws), sum(m.info()[1] for m in ms), counters["key_switches"]),
-            "batched_spmv_per_s": round(len(ms) / t_batch, 2), "plain_spmv_per_s": round(len(ms) / t_plain, 2),
-            "batched_ms": round(t_batch * 1e3, 2), "plain_ms": round(t_plain * 1e3, 2),
-            "speedup": round(t_plain / t_batch, 2), "decrypt_check": ok}
+            "batched_spmv_per_s": round(len(ms) / t_batch, 2), "graph_spmv_per_s": round(len(ms) / t_graph, 2),
+            "plain_spmv_per_s": round(len(ms) / t_plain, 2),
+            "batched_ms": round(t_batch * 1e3, 2), "graph_ms": round(t_graph * 1e3, 2), "plain_ms": round(t_plain * 1e3, 2),
+            "speedup": round(t_plain / t_batch, 2), "graph_speedup": round(t_plain / t_graph, 2), "decrypt_check": ok,
+            "autotune": {"keyswitch_transform_variant": tune["variant"], "pipeline_two_pass_by_B": {str(b): int(t2 <= t1 or t1 == 0)
+                                                                                          for b, t1, t2 in tune["pipelines"]}}}
 
 
 def serving(H, W, torch, dev, n_requests, rate=200.0, n_keysets=8, pool=16):
@@ -282,6 +303,7 @@ def serving(H, W, torch, dev, n_requests, rate=200.0, n_keysets=8, pool=16):
     import threading
     ctx = H.Context(14, 6, 50, 1, agg_mode=0)
     kss = [ctx.keygen(0x5E7 + k) for k in range(n_keysets)]
+    H.autotune(ctx, kss[0])
     arrivals, keyset, sizes = W.serve_stream(n_requests, rate, n_keysets)
     pool_sizes = np.unique(np.quantile(sizes, (np.arange(pool) + 0.5) / pool).round().astype(np.int64))
     mats = []

@@ -242,19 +242,22 @@ int hs_set_option(int key, int64_t value);
 
 /* Autotuner.  Times, on synthetic operands and the key-switching key of `ks`, (1) the two variants
    of the one-workgroup-per-limb transforms (N = 2^14: half-limb LDS with 512 threads vs whole limb
-   with 1024; N = 2^11..2^13: compile-time radix-16 rounds vs runtime radix-8 rounds) on a 32-item
-   rotation level, and (2) the two key-switch pipelines (two-pass vs one workgroup per limb) on
-   levels of B = 1, 2, 4, ..., 64 items, and stores the faster choice in the context; later calls
-   use it (results never depend on these choices; HS_OPT_KS_PIPELINE still forces a pipeline).
-   Report (host `report`, capacity `cap` doubles; *len receives the count, 24): [variant chosen,
-   ms variant 0, ms variant 1], then per B: [B, ms one-workgroup, ms two-pass] (0 when a variant
-   does not exist for the ring).  Not thread-safe against concurrent calls on the context. */
+   with 1024; N = 2^11..2^13: compile-time radix-16 rounds vs runtime radix-8 rounds), once inside
+   the key-switch kernels on a 32-item rotation level and once in the plain transform kernels on
+   64 polynomials of L + K limbs (forward + inverse), and (2) the two key-switch pipelines
+   (two-pass vs one workgroup per limb) on levels of B = 1, 2, 4, ..., 64 items, and stores the
+   faster choices in the context; later calls use them (results never depend on these choices;
+   HS_OPT_KS_PIPELINE still forces a pipeline).  Report (host `report`, capacity `cap` doubles;
+   *len receives the count, 27): [key-switch variant, ms variant 0, ms variant 1, transform variant,
+   ms variant 0, ms variant 1], then per B: [B, ms one workgroup per limb, ms two-pass] (0 where a
+   variant does not exist for the ring).  Not thread-safe against concurrent calls on the context. */
 int hs_autotune(hs_ctx* ctx, const hs_keyset* ks, void* stream, double* report, int cap, int* len);
-/* The context's launch choices: out[0] transform variant (0/1), out[1 + b] key-switch pipeline for
-   levels of 2^(b-1) < B <= 2^b items (b = 7: larger): 1 two-pass, 0 one workgroup per limb, -1 the
-   fixed threshold rule (HS_OPT_KS_THRESHOLD).  hs_set_tuning installs such a table. */
-int hs_tuning(const hs_ctx* ctx, int64_t out[9]);
-int hs_set_tuning(hs_ctx* ctx, const int64_t in[9]);
+/* The context's launch choices: out[0] key-switch transform variant, out[1] plain transform
+   variant (0/1 as above), out[2 + b] key-switch pipeline for levels of 2^(b-1) < B <= 2^b items
+   (b = 7: larger): 1 two-pass, 0 one workgroup per limb, -1 the fixed threshold rule
+   (HS_OPT_KS_THRESHOLD).  hs_set_tuning installs such a table. */
+int hs_tuning(const hs_ctx* ctx, int64_t out[10]);
+int hs_set_tuning(hs_ctx* ctx, const int64_t in[10]);
 
 /* Kernel timing: hs_profile(1) clears the records and brackets every subsequent kernel launch with
    two HIP events on its stream; hs_profile(0) stops.  hs_profile_summary waits for the recorded

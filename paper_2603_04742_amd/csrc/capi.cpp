@@ -1076,6 +1076,40 @@ int hs_autotune(hs_ctx* c, const hs_keyset* ks, void* stream, double* report, in
       rep.push_back(c->xf_variant);
       rep.push_back(tv[0]);
       rep.push_back(tv[1]);
+      // 1b. the same choice for the plain transform kernels, timed on forward + inverse transforms
+      //     of 64 polynomials of L + K limbs
+      double tn[2] = {0, 0};
+      if (has_alt) {
+        const int rows = 64 * LK;
+        DBuf lim(&c->pool, (size_t)rows * N * sizeof(u64));
+        HS_CHECK_HIP(hipMemcpyAsync(lim.as<u64>(), in.as<u64>(), std::min((size_t)rows * N, (size_t)kIn * CW) * sizeof(u64),
+                                    hipMemcpyDeviceToDevice, st));
+        if ((size_t)rows * N > (size_t)kIn * CW)  // the rest: valid residues of the first limbs, repeated
+          for (size_t o = (size_t)kIn * CW; o < (size_t)rows * N; o += (size_t)kIn * CW)
+            HS_CHECK_HIP(hipMemcpyAsync(lim.as<u64>() + o, in.as<u64>(), std::min((size_t)kIn * CW, (size_t)rows * N - o) * sizeof(u64),
+                                        hipMemcpyDeviceToDevice, st));
+        for (int v = 0; v < 2; v++) {
+          c->xf_variant_ntt = v;
+          auto pass = [&] {
+            launch_ntt(c, lim.as<u64>(), rows, LK, 0, 0, st);
+            launch_ntt(c, lim.as<u64>(), rows, LK, 0, 1, st);
+          };
+          pass();
+          HS_CHECK_HIP(hipEventRecord(ea, st));
+          for (int r = 0; r < 3; r++) pass();
+          HS_CHECK_HIP(hipEventRecord(eb, st));
+          HS_CHECK_HIP(hipEventSynchronize(eb));
+          float ms = 0;
+          HS_CHECK_HIP(hipEventElapsedTime(&ms, ea, eb));
+          tn[v] = ms / 3.0;
+        }
+        c->xf_variant_ntt = tn[1] < tn[0] ? 1 : 0;
+      } else {
+        c->xf_variant_ntt = 0;
+      }
+      rep.push_back(c->xf_variant_ntt);
+      rep.push_back(tn[0]);
+      rep.push_back(tn[1]);
       // 2. key-switch pipeline per batch-size bucket
       for (int b = 0; b < 7; b++) {
         const int B = 1 << b;
@@ -1104,21 +1138,23 @@ int hs_autotune(hs_ctx* c, const hs_keyset* ks, void* stream, double* report, in
   });
 }
 
-int hs_tuning(const hs_ctx* c, int64_t out[9]) {
+int hs_tuning(const hs_ctx* c, int64_t out[10]) {
   return guarded([&] {
     HS_REQUIRE(c && out, HS_EINVAL, "null argument");
     out[0] = c->xf_variant;
-    for (int b = 0; b < 8; b++) out[1 + b] = c->ks_pick[b];
+    out[1] = c->xf_variant_ntt;
+    for (int b = 0; b < 8; b++) out[2 + b] = c->ks_pick[b];
   });
 }
 
-int hs_set_tuning(hs_ctx* c, const int64_t in[9]) {
+int hs_set_tuning(hs_ctx* c, const int64_t in[10]) {
   return guarded([&] {
     HS_REQUIRE(c && in, HS_EINVAL, "null argument");
-    HS_REQUIRE(in[0] == 0 || in[0] == 1, HS_EINVAL, "transform variant must be 0 or 1");
-    for (int b = 0; b < 8; b++) HS_REQUIRE(in[1 + b] >= -1 && in[1 + b] <= 1, HS_EINVAL, "pipeline pick must be -1, 0 or 1");
+    HS_REQUIRE((in[0] == 0 || in[0] == 1) && (in[1] == 0 || in[1] == 1), HS_EINVAL, "transform variants must be 0 or 1");
+    for (int b = 0; b < 8; b++) HS_REQUIRE(in[2 + b] >= -1 && in[2 + b] <= 1, HS_EINVAL, "pipeline pick must be -1, 0 or 1");
     c->xf_variant = (int)in[0];
-    for (int b = 0; b < 8; b++) c->ks_pick[b] = (signed char)in[1 + b];
+    c->xf_variant_ntt = (int)in[1];
+    for (int b = 0; b < 8; b++) c->ks_pick[b] = (signed char)in[2 + b];
   });
 }
 

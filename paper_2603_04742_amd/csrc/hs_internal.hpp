@@ -133,10 +133,13 @@ struct hs_ctx {
   double2* d_t_r64 = nullptr;
   hs::Pool pool;
   // launch choices set by hs_autotune (results do not depend on them):
-  //   xf_variant 0: compile-time / half-limb transforms, 1: runtime radix-8 / whole-limb;
+  //   xf_variant 0: compile-time / half-limb transforms, 1: runtime radix-8 / whole-limb, for the
+  //   key-switch kernels; xf_variant_ntt the same for the plain transform kernels (NTT, plaintext
+  //   encoding, decryption phase);
   //   ks_pick[b]: key-switch pipeline for levels of 2^(b-1) < B <= 2^b items (b = 7: larger),
   //   1 two-pass, 0 one workgroup per limb, -1 the fixed threshold rule.
   int xf_variant = 0;
+  int xf_variant_ntt = 0;
   signed char ks_pick[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
 };
 

@@ -735,11 +735,11 @@ static size_t split_lds_bytes() { return (size_t)split_lds_doubles() * sizeof(do
   } while (0)
 // Ring size (and the context's tuned variant) -> transform policy: 2^14 half-limb or whole-limb,
 // 2^11..2^13 compile-time (radix 16) or runtime (radix 8), smaller rings runtime with 64 threads.
-#define HS_DISPATCH_XF(C, KERNEL, GRID, STREAM, ...)                                                     \
+#define HS_DISPATCH_XF(VARIANT, C, KERNEL, GRID, STREAM, ...)                                            \
   do {                                                                                                   \
     ProfScope _prof(#KERNEL, STREAM);                                                                    \
     const int _logn = (C)->logn;                                                                         \
-    const bool _alt = (C)->xf_variant == 1;                                                              \
+    const bool _alt = (VARIANT) == 1;                                                                    \
     switch (_logn) {                                                                                     \
       case 14:                                                                                           \
         if (_alt) HS_LAUNCH_XF(XfStatic<1024>, XfStatic<1024>{}, lds_bytes(14), KERNEL, GRID, STREAM, __VA_ARGS__); \
@@ -768,7 +768,7 @@ void upload_cdt(const u64* tab20) { HS_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_
 
 void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st) {
   if (nblocks <= 0) return;
-  HS_DISPATCH_XF(c, k_ntt, dim3((unsigned)nblocks), st, data, nl, mod0, inverse, (const ModTab*)c->d_tab, c->logn);
+  HS_DISPATCH_XF(c->xf_variant_ntt, c, k_ntt, dim3((unsigned)nblocks), st, data, nl, mod0, inverse, (const ModTab*)c->d_tab, c->logn);
 }
 
 void launch_sample_small(const hs_ctx* c, int* out, int nobj, i64 obj_stride, u64 seed, u32 purpose, u64 index0, u64 index_step,
@@ -797,7 +797,7 @@ void launch_pack_encode(const hs_ctx* c, const PackArgs& a, int nchunks, hipStre
 
 void launch_plain_ntt(const hs_ctx* c, const u64* coef, u64* out, int n_plain, hipStream_t st) {
   if (n_plain <= 0) return;
-  HS_DISPATCH_XF(c, k_plain_ntt, dim3(c->L, n_plain), st, coef, out, c->L, c->t, (const ModTab*)c->d_tab, c->logn);
+  HS_DISPATCH_XF(c->xf_variant_ntt, c, k_plain_ntt, dim3(c->L, n_plain), st, coef, out, c->L, c->t, (const ModTab*)c->d_tab, c->logn);
 }
 
 void launch_encrypt(const hs_ctx* c, const u64* mcoef, const int* samples, const u64* pk, u64* out, int n_ct, hipStream_t st) {
@@ -828,17 +828,17 @@ void launch_mask_acc(const hs_ctx* c, const u64* const* w, const u64* mask, cons
 void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, u64* D, double* ACC, double* PC, hipStream_t st) {
   if (B <= 0) return;
   const ModTab* tab = (const ModTab*)c->d_tab;
-  HS_DISPATCH_XF(c, k_rot_intt, dim3(c->L, B), st, d_items, D, c->L, tab, c->logn);
-  HS_DISPATCH_XF(c, k_modup_ip, dim3(c->L + c->K, B, S.ndg), st, d_items, (const u64*)D, ACC, S,
+  HS_DISPATCH_XF(c->xf_variant, c, k_rot_intt, dim3(c->L, B), st, d_items, D, c->L, tab, c->logn);
+  HS_DISPATCH_XF(c->xf_variant, c, k_modup_ip, dim3(c->L + c->K, B, S.ndg), st, d_items, (const u64*)D, ACC, S,
                  (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, c->logn);
-  HS_DISPATCH_XF(c, k_moddown_intt, dim3(c->K, 2, B), st, (const double*)ACC, PC, S, tab, c->logn);
-  HS_DISPATCH_XF(c, k_moddown_ntt, dim3(c->L, 2, B), st, d_items, (const double*)ACC, (const double*)PC, S,
+  HS_DISPATCH_XF(c->xf_variant, c, k_moddown_intt, dim3(c->K, 2, B), st, (const double*)ACC, PC, S, tab, c->logn);
+  HS_DISPATCH_XF(c->xf_variant, c, k_moddown_ntt, dim3(c->L, 2, B), st, d_items, (const double*)ACC, (const double*)PC, S,
                  (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, (const double2*)c->d_pinv, tab, c->logn);
 }
 
 void launch_dec_phase(const hs_ctx* c, const u64* ct, const u64* sk, u64* X, int n_ct, hipStream_t st) {
   if (n_ct <= 0) return;
-  HS_DISPATCH_XF(c, k_dec_phase, dim3(c->L, n_ct), st, ct, sk, X, c->L, (const ModTab*)c->d_tab, c->logn);
+  HS_DISPATCH_XF(c->xf_variant_ntt, c, k_dec_phase, dim3(c->L, n_ct), st, ct, sk, X, c->L, (const ModTab*)c->d_tab, c->logn);
 }
 
 void launch_dec_round(const hs_ctx* c, const u64* X, u64* M, int n_ct, hipStream_t st) {

@@ -292,23 +292,25 @@ def he_spmv_batch(ctx, kss, ms, xs):
 
 def autotune(ctx, ks):
     """Time the launch variants on this context and keep the faster ones; returns the report:
-    {"variant": v, "variant_ms": [v0, v1], "pipelines": [(B, ms one-workgroup, ms two-pass), ...]}."""
+    {"variant": v, "variant_ms": [v0, v1], "ntt_variant": v, "ntt_variant_ms": [v0, v1],
+     "pipelines": [(B, ms one-workgroup, ms two-pass), ...]}."""
     buf = (ctypes.c_double * 64)()
     n = ctypes.c_int()
     _check(lib.hs_autotune(ctx.h, ks.h, _stream(), buf, 64, ctypes.byref(n)))
     r = list(buf[:n.value])
-    return {"variant": int(r[0]), "variant_ms": r[1:3],
-            "pipelines": [(int(r[3 + 3 * i]), r[4 + 3 * i], r[5 + 3 * i]) for i in range((len(r) - 3) // 3)]}
+    return {"variant": int(r[0]), "variant_ms": r[1:3], "ntt_variant": int(r[3]), "ntt_variant_ms": r[4:6],
+            "pipelines": [(int(r[6 + 3 * i]), r[7 + 3 * i], r[8 + 3 * i]) for i in range((len(r) - 6) // 3)]}
 
 
 def tuning(ctx):
-    out = (ctypes.c_int64 * 9)()
+    """[key-switch transform variant, plain transform variant, pipeline pick per batch bucket x 8]."""
+    out = (ctypes.c_int64 * 10)()
     _check(lib.hs_tuning(ctx.h, out))
     return list(out)
 
 
 def set_tuning(ctx, table):
-    arr = (ctypes.c_int64 * 9)(*[int(v) for v in table])
+    arr = (ctypes.c_int64 * 10)(*[int(v) for v in table])
     _check(lib.hs_set_tuning(ctx.h, arr))
 
 

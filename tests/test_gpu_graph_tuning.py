@@ -117,12 +117,12 @@ def test_autotune_and_every_tuning_give_identical_limbs(p):
     assert [b for b, _, _ in rep["pipelines"]] == [1, 2, 4, 8, 16, 32, 64]
     assert all(t2 > 0 for _, _, t2 in rep["pipelines"])
     tab = H.tuning(g)
-    assert tab[0] == rep["variant"] and all(v in (0, 1) for v in tab[1:])
+    assert tab[0] == rep["variant"] and tab[1] == rep["ntt_variant"] and all(v in (0, 1) for v in tab[2:])
     for y, e in zip(H.he_spmv_batch(g, kss, ms, xs), ref):
         assert np.array_equal(y.export_all(), e)
     for variant in (0, 1):
         for pick in (0, 1):
-            H.set_tuning(g, [variant] + [pick] * 8)
+            H.set_tuning(g, [variant, 1 - variant] + [pick] * 8)
             for y, e in zip(H.he_spmv_batch(g, kss, ms, xs), ref):
                 assert np.array_equal(y.export_all(), e), "variant %d pipeline %d" % (variant, pick)
             # the standalone transform under this variant round-trips
@@ -133,4 +133,4 @@ def test_autotune_and_every_tuning_give_identical_limbs(p):
             assert torch.equal(back, lim)
     check_decrypt(g, reqs, H.he_spmv_batch(g, kss, ms, xs))
     with pytest.raises(H.HespmvError):
-        H.set_tuning(g, [2] + [0] * 8)
+        H.set_tuning(g, [2, 0] + [0] * 8)
