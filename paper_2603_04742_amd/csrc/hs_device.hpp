@@ -143,7 +143,7 @@ __device__ __forceinline__ void fwd_round(double* s, int logn, int stage, int la
 // below 1.625 q < 2^51.  The caller synchronises before (data in LDS) and the function ends with
 // a barrier.
 template <int NT>
-__device__ void lds_ntt_fwd(double* s, int logn, const double2* __restrict__ tw, ModD m) {
+__device__ __forceinline__ void lds_ntt_fwd(double* s, int logn, const double2* __restrict__ tw, ModD m) {
   int stage = 0, lazy = 0;
   while (stage < logn) {
     const int R = min(HS_NTT_RADIX_BITS, logn - stage);
@@ -201,7 +201,7 @@ __device__ __forceinline__ void inv_round(double* s, int logn, int stage, bool l
 // Inverse negacyclic NTT of one limb in LDS, including the 1/N scaling: inputs |x| <= q, outputs
 // |x| <= 0.625 q.  Stage s pairs indices differing in bit s; X' = reduce(X + Y), Y' = (X - Y) w.
 template <int NT>
-__device__ void lds_ntt_inv(double* s, int logn, const double2* __restrict__ tw, double2 ninv, ModD m) {
+__device__ __forceinline__ void lds_ntt_inv(double* s, int logn, const double2* __restrict__ tw, double2 ninv, ModD m) {
   int stage = 0;
   while (stage < logn) {
     const int R = min(HS_NTT_RADIX_BITS, logn - stage);

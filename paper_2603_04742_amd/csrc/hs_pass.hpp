@@ -55,6 +55,13 @@ struct PassGeomC {
   __host__ __device__ static constexpr int lgb_low() { return lbe - (logn - S); }
 };
 
+// LDS padding of a pass layout.  Low layout: one pad double per 16.  High layout: one per 32 --
+// its first round reads elements 8 rows (8 x 16 doubles) apart across lanes, which one pad per 16
+// maps onto a quarter of the banks (4-way conflicts); one per 32 halves that and keeps the
+// unit-stride rounds conflict-free.
+template <bool HIGH>
+__device__ __forceinline__ int lpadx(int i) { return HIGH ? i + (i >> 5) : i + (i >> 4); }
+
 // Global index of element u of group g in block `blk`.
 template <class GT>
 __device__ __forceinline__ int gidx_high(const GT& G, int blk, int g, int u) {
@@ -154,7 +161,7 @@ __device__ __forceinline__ void pass_round(double* s, const GT& G, int blk, int 
     const int ls = HIGH ? (GB << lb) : (1 << lb);
     double x[1 << R];
 #pragma unroll
-    for (int v = 0; v < (1 << R); v++) x[v] = s[lpad(l0 + v * ls)];
+    for (int v = 0; v < (1 << R); v++) x[v] = s[lpadx<HIGH>(l0 + v * ls)];
     if (FWD) {
       int lz = lazy;
 #pragma unroll
@@ -204,7 +211,7 @@ __device__ __forceinline__ void pass_round(double* s, const GT& G, int blk, int 
       }
     }
 #pragma unroll
-    for (int v = 0; v < (1 << R); v++) s[lpad(l0 + v * ls)] = x[v];
+    for (int v = 0; v < (1 << R); v++) s[lpadx<HIGH>(l0 + v * ls)] = x[v];
   }
 }
 
@@ -212,7 +219,7 @@ __device__ __forceinline__ void pass_round(double* s, const GT& G, int blk, int 
 // |x| <= q/2 + 1 and a barrier.  twl: LDS scratch of tw_lds_entries(BE) double2 for the staged
 // twiddles (must not be in use by other threads).  The caller synchronises before.
 template <int NT, bool HIGH, class GT>
-__device__ void pass_fwd(double* s, double2* twl, const GT& G, int blk, const double2* __restrict__ tw, ModD m,
+__device__ __forceinline__ void pass_fwd(double* s, double2* twl, const GT& G, int blk, const double2* __restrict__ tw, ModD m,
                          bool stage = true) {
   const int nb = HIGH ? G.S : G.logn - G.S;
   if (stage) {
@@ -232,14 +239,14 @@ __device__ void pass_fwd(double* s, double2* twl, const GT& G, int blk, const do
     done += R;
     __syncthreads();
   }
-  for (int e = threadIdx.x; e < G.BE; e += NT) s[lpad(e)] = reduce(s[lpad(e)], m);
+  for (int e = threadIdx.x; e < G.BE; e += NT) s[lpadx<HIGH>(e)] = reduce(s[lpadx<HIGH>(e)], m);
   __syncthreads();
 }
 
 // Inverse pass on the block in LDS (inputs |x| <= q, outputs |x| <= 0.625 q); `scale` multiplies
 // by N^-1 (the last inverse pass).  Ends with a barrier.
 template <int NT, bool HIGH, class GT>
-__device__ void pass_inv(double* s, double2* twl, const GT& G, int blk, bool scale, const double2* __restrict__ tw, double2 ninv, ModD m,
+__device__ __forceinline__ void pass_inv(double* s, double2* twl, const GT& G, int blk, bool scale, const double2* __restrict__ tw, double2 ninv, ModD m,
                          bool stage = true) {
   const int nb = HIGH ? G.S : G.logn - G.S;
   if (stage) {
@@ -286,7 +293,7 @@ __device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsi
     const int ls = HIGH ? (GB << lb) : (1 << lb);
     double x[1 << R];
 #pragma unroll
-    for (int v = 0; v < (1 << R); v++) x[v] = sj[lpad(l0 + v * ls)];
+    for (int v = 0; v < (1 << R); v++) x[v] = sj[lpadx<HIGH>(l0 + v * ls)];
     if (FWD) {
       int lz = lazy;
 #pragma unroll
@@ -336,14 +343,14 @@ __device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsi
       }
     }
 #pragma unroll
-    for (int v = 0; v < (1 << R); v++) sj[lpad(l0 + v * ls)] = x[v];
+    for (int v = 0; v < (1 << R); v++) sj[lpadx<HIGH>(l0 + v * ls)] = x[v];
   }
 }
 
 // Forward pass on NB blocks (twiddles already staged; inputs |x| <= q; outputs |x| <= q/2 + 1).
 // Starts with no barrier of its own (the caller synchronises after staging) and ends with one.
 template <int NT, bool HIGH, class GT>
-__device__ void pass_fwd_multi(double* s, int LB, int NB, unsigned skip, const double2* twl, const GT& G, int blk, ModD m) {
+__device__ __forceinline__ void pass_fwd_multi(double* s, int LB, int NB, unsigned skip, const double2* twl, const GT& G, int blk, ModD m) {
   const int nb = HIGH ? G.S : G.logn - G.S;
   int done = 0, lazy = 0;
   while (done < nb) {
@@ -360,14 +367,14 @@ __device__ void pass_fwd_multi(double* s, int LB, int NB, unsigned skip, const d
   }
   for (int t = threadIdx.x; t < (NB << G.lbe); t += NT) {
     const int j = t >> G.lbe, e = t & (G.BE - 1);
-    if (!((skip >> j) & 1u)) s[(size_t)j * LB + lpad(e)] = reduce(s[(size_t)j * LB + lpad(e)], m);
+    if (!((skip >> j) & 1u)) s[(size_t)j * LB + lpadx<HIGH>(e)] = reduce(s[(size_t)j * LB + lpadx<HIGH>(e)], m);
   }
   __syncthreads();
 }
 
 // Inverse pass on NB blocks (twiddles already staged; inputs |x| <= q, outputs |x| <= 0.625 q).
 template <int NT, bool HIGH, class GT>
-__device__ void pass_inv_multi(double* s, int LB, int NB, bool scale, const double2* twl, double2 ninv, const GT& G, int blk, ModD m) {
+__device__ __forceinline__ void pass_inv_multi(double* s, int LB, int NB, bool scale, const double2* twl, double2 ninv, const GT& G, int blk, ModD m) {
   const int nb = HIGH ? G.S : G.logn - G.S;
   int done = 0;
   while (done < nb) {

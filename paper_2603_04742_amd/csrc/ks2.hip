@@ -53,15 +53,15 @@ __device__ __forceinline__ void ntt_pass_body(double* smem, double2* twl, const 
   const size_t base = (size_t)row * n;
   for (int e = threadIdx.x; e < G.BE; e += NT) {
     const int gi = gidx_of_lds<HIGH>(G, blk, e);
-    smem[lpad(e)] = in_u64 ? u2d(((const u64*)in)[base + gi]) : ((const double*)in)[base + gi];
+    smem[lpadx<HIGH>(e)] = in_u64 ? u2d(((const u64*)in)[base + gi]) : ((const double*)in)[base + gi];
   }
   __syncthreads();
   if (FWD) pass_fwd<NT, HIGH>(smem, twl, G, blk, tb.fw, m);
   else pass_inv<NT, HIGH>(smem, twl, G, blk, scale != 0, tb.iv, tb.ninv, m);
   for (int e = threadIdx.x; e < G.BE; e += NT) {
     const int gi = gidx_of_lds<HIGH>(G, blk, e);
-    if (out_u64) ((u64*)out)[base + gi] = d2u(canon(smem[lpad(e)], m));
-    else ((double*)out)[base + gi] = smem[lpad(e)];
+    if (out_u64) ((u64*)out)[base + gi] = d2u(canon(smem[lpadx<HIGH>(e)], m));
+    else ((double*)out)[base + gi] = smem[lpadx<HIGH>(e)];
   }
 }
 
@@ -114,7 +114,7 @@ __global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T
   for (int a = 0; a < na; a++) {
     double* buf = smem + (size_t)a * LB;
     const double* src = T1 + ((size_t)b * S.L + lo + a) * n;
-    for (int e = threadIdx.x; e < G.BE; e += NT) buf[lpad(e)] = src[gidx_of_lds<true>(G, blk, e)];
+    for (int e = threadIdx.x; e < G.BE; e += NT) buf[lpadx<true>(e)] = src[gidx_of_lds<true>(G, blk, e)];
   }
   __syncthreads();
   for (int a = 0; a < na; a++) {
@@ -123,12 +123,12 @@ __global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T
     double* buf = smem + (size_t)a * LB;
     pass_inv<NT, true>(buf, twl, G, blk, true, ta.iv, ta.ninv, ma);
     for (int e = threadIdx.x; e < G.BE; e += NT) {
-      double x = canon(buf[lpad(e)], ma);
+      double x = canon(buf[lpadx<true>(e)], ma);
       if (na > 1) {
         const double2 ci = up_inv[j * S.alpha + a];
         x = canon(mul_tw(x, ci.x, ci.y, ma), ma);   // [x (Q_j/q_a)^-1]_{q_a}
       }
-      buf[lpad(e)] = x;
+      buf[lpadx<true>(e)] = x;
     }
   }
   __syncthreads();
@@ -137,7 +137,7 @@ __global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T
   for (int e = threadIdx.x; e < G.BE; e += NT) {
     double acc = 0.0;
     for (int a = 0; a < na; a++) {
-      const double y = smem[(size_t)a * LB + lpad(e)];
+      const double y = smem[(size_t)a * LB + lpadx<true>(e)];
       if (na > 1) {
         const double2 hm = up_hat[((size_t)j * S.alpha + a) * LK + mi];
         acc = reduce(acc + mul_tw(y, hm.x, hm.y, mm), mm);
@@ -145,12 +145,12 @@ __global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T
         acc = reduce(y, mm);   // one source prime: [x]_q as an integer, taken mod mi
       }
     }
-    work[lpad(e)] = acc;
+    work[lpadx<true>(e)] = acc;
   }
   __syncthreads();
   pass_fwd<NT, true>(work, twl, G, blk, tm.fw, mm);
   double* o = E + (((size_t)b * S.dnum + j) * LK + mi) * n;
-  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<true>(G, blk, e)] = work[lpad(e)];
+  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<true>(G, blk, e)] = work[lpadx<true>(e)];
 }
 
 // grid (nblk, L + K, B).  The next digit's block is loaded into registers while the current one
@@ -250,22 +250,28 @@ __global__ void __launch_bounds__(NT) k2_ip_low(const RotItem* __restrict__ item
 // K3 with every digit resident at once: the digit blocks (own limb: sigma_g(c1)) sit side by side
 // in LDS and one workgroup of NT threads transforms all of them concurrently, then forms the inner
 // product per element.  LDS [staged twiddles: BE double2][dnum blocks of lds_doubles(BE)].
-// grid (nblk, L + K, B).
+// grid (nblk, L + 2K, B): y < L is data prime y (both accumulators); y >= L is special prime
+// L + (y - L) / 2 and accumulator (y - L) % 2 only, whose workgroup also runs that accumulator's
+// inverse low pass (splitting the special limbs this way keeps every workgroup's work close to
+// that of a data-prime workgroup, which sets the kernel's duration).
 template <int NT, int DMAX, class GT>
 __global__ void __launch_bounds__(NT) k2_ip_par(const RotItem* __restrict__ items, const double* __restrict__ E, double* ACC, double* T2, KsShape S,
                                                 const ModTab* __restrict__ tab, GT G) {
   SMEM2(G);
   constexpr int PER = kBlockElems / NT > 0 ? kBlockElems / NT : 1;
   const int n = 1 << G.logn;
-  const int blk = blockIdx.x, mi = blockIdx.y, b = blockIdx.z;
+  const int blk = blockIdx.x, y = blockIdx.y, b = blockIdx.z;
+  const bool special = y >= S.L;
+  const int mi = special ? S.L + ((y - S.L) >> 1) : y;
+  const int wsel = special ? ((y - S.L) & 1) : 0;
   const int LK = S.L + S.K;
   const int LB = lds_doubles(G.BE);
   const RotItem it = items[b];
   const ModTab tm = tab[mi];
   const ModD m = mod_of2(tm);
-  const int jown = mi < S.L ? mi / S.alpha : -1;
+  const int jown = special ? -1 : mi / S.alpha;
   // the key-switching key words of this thread's elements are loaded first: their latency then
-  // overlaps the staging and the transforms
+  // overlaps the staging and the transforms (a special-prime workgroup needs one key part)
   u64 kbv[PER][DMAX], kav[PER][DMAX];
 #pragma unroll
   for (int k = 0; k < PER; k++) {
@@ -276,8 +282,8 @@ __global__ void __launch_bounds__(NT) k2_ip_par(const RotItem* __restrict__ item
       kbv[k][j] = 0;
       kav[k][j] = 0;
       if (j < S.dnum && e < G.BE) {
-        kbv[k][j] = it.key[(((size_t)0 * S.dnum + j) * LK + mi) * n + gi];
-        kav[k][j] = it.key[(((size_t)1 * S.dnum + j) * LK + mi) * n + gi];
+        if (!special || wsel == 0) kbv[k][j] = it.key[(((size_t)0 * S.dnum + j) * LK + mi) * n + gi];
+        if (!special || wsel == 1) kav[k][j] = it.key[(((size_t)1 * S.dnum + j) * LK + mi) * n + gi];
       }
     }
   }
@@ -303,38 +309,33 @@ __global__ void __launch_bounds__(NT) k2_ip_par(const RotItem* __restrict__ item
       for (int j = 0; j < DMAX; j++) {
         if (j < S.dnum) {
           const double x = smem[(size_t)j * LB + lpad(e)];
-          a0 += mulmod(x, u2d(kbv[k][j]), m);
-          a1 += mulmod(x, u2d(kav[k][j]), m);
+          if (!special || wsel == 0) a0 += mulmod(x, u2d(kbv[k][j]), m);
+          if (!special || wsel == 1) a1 += mulmod(x, u2d(kav[k][j]), m);
           if ((j & 3) == 3) { a0 = reduce(a0, m); a1 = reduce(a1, m); }
         }
       }
       r0[k] = reduce(a0, m);
       r1[k] = reduce(a1, m);
-      if (mi < S.L) {
+      if (!special) {
         const int gi = gidx_of_lds<false>(G, blk, e);
         ACC[(((size_t)b * 2 + 0) * S.L + mi) * n + gi] = r0[k];
         ACC[(((size_t)b * 2 + 1) * S.L + mi) * n + gi] = r1[k];
       }
     }
   }
-  if (mi < S.L) return;
-  // special limb: inverse low pass of both accumulators (two blocks at once)
+  if (!special) return;
+  // special prime: inverse low pass of the selected accumulator
   __syncthreads();
   stage_twiddles<NT, false, false>(twl, G, blk, tm.iv);
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int e = threadIdx.x + k * NT;
-    if (e < G.BE) {
-      smem[lpad(e)] = canon(r0[k], m);
-      smem[(size_t)LB + lpad(e)] = canon(r1[k], m);
-    }
+    if (e < G.BE) smem[lpad(e)] = canon(wsel == 0 ? r0[k] : r1[k], m);
   }
   __syncthreads();
-  pass_inv_multi<NT, false>(smem, LB, 2, false, twl, tm.ninv, G, blk, m);
-  for (int t = threadIdx.x; t < (2 << G.lbe); t += NT) {
-    const int w = t >> G.lbe, e = t & (G.BE - 1);
-    T2[(((size_t)b * 2 + w) * S.K + (mi - S.L)) * n + gidx_of_lds<false>(G, blk, e)] = smem[(size_t)w * LB + lpad(e)];
-  }
+  pass_inv_multi<NT, false>(smem, LB, 1, false, twl, tm.ninv, G, blk, m);
+  double* o = T2 + (((size_t)b * 2 + wsel) * S.K + (mi - S.L)) * n;
+  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<false>(G, blk, e)] = smem[lpad(e)];
 }
 
 // grid (nblk, 2 L, B): polynomial w = y / L, data prime i = y % L.  The special limbs' inverse
@@ -350,7 +351,7 @@ __global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__
   for (int k = 0; k < S.K; k++) {
     double* buf = smem + (size_t)k * LB;
     const double* src = T2 + (((size_t)b * 2 + w) * S.K + k) * n;
-    for (int e = threadIdx.x; e < G.BE; e += NT) buf[lpad(e)] = src[gidx_of_lds<true>(G, blk, e)];
+    for (int e = threadIdx.x; e < G.BE; e += NT) buf[lpadx<true>(e)] = src[gidx_of_lds<true>(G, blk, e)];
   }
   __syncthreads();
   for (int k = 0; k < S.K; k++) {
@@ -359,12 +360,12 @@ __global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__
     double* buf = smem + (size_t)k * LB;
     pass_inv<NT, true>(buf, twl, G, blk, true, tp.iv, tp.ninv, mp);
     for (int e = threadIdx.x; e < G.BE; e += NT) {
-      double x = canon(buf[lpad(e)], mp);
+      double x = canon(buf[lpadx<true>(e)], mp);
       if (S.K > 1) {
         const double2 ci = dn_inv[k];
         x = canon(mul_tw(x, ci.x, ci.y, mp), mp);
       }
-      buf[lpad(e)] = x;
+      buf[lpadx<true>(e)] = x;
     }
   }
   __syncthreads();
@@ -373,7 +374,7 @@ __global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__
   for (int e = threadIdx.x; e < G.BE; e += NT) {
     double acc = 0.0;
     for (int k = 0; k < S.K; k++) {
-      const double y = smem[(size_t)k * LB + lpad(e)];
+      const double y = smem[(size_t)k * LB + lpadx<true>(e)];
       if (S.K > 1) {
         const double2 hm = dn_hat[(size_t)k * S.L + i];
         acc = reduce(acc + mul_tw(y, hm.x, hm.y, mq), mq);
@@ -381,12 +382,12 @@ __global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__
         acc = reduce(y, mq);
       }
     }
-    work[lpad(e)] = acc;
+    work[lpadx<true>(e)] = acc;
   }
   __syncthreads();
   pass_fwd<NT, true>(work, twl, G, blk, tq.fw, mq);
   double* o = F + (((size_t)b * 2 + w) * S.L + i) * n;
-  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<true>(G, blk, e)] = work[lpad(e)];
+  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<true>(G, blk, e)] = work[lpadx<true>(e)];
 }
 
 template <int NT, class GT>
@@ -490,7 +491,7 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     if (TW + LB * c->dnum <= (size_t)160 * 1024 && G.BE >= 1024 && c->dnum <= 6) {
       ProfScope _prof("k2_ip_par", st);
       ensure_lds2((const void*)k2_ip_par<1024, 6, GT>, TW + LB * c->dnum);
-      hipLaunchKernelGGL((k2_ip_par<1024, 6, GT>), dim3(G.nblk, LK, B), dim3(1024), TW + LB * c->dnum, st, d_items, (const double*)E, ACC,
+      hipLaunchKernelGGL((k2_ip_par<1024, 6, GT>), dim3(G.nblk, c->L + 2 * c->K, B), dim3(1024), TW + LB * c->dnum, st, d_items, (const double*)E, ACC,
                          T2, S, tab, G);
       HS_CHECK_HIP(hipGetLastError());
     } else {
