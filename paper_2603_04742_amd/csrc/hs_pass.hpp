@@ -18,6 +18,7 @@ namespace hs {
 static constexpr int kBlockElems = 2048;
 
 struct PassGeom {
+  static constexpr int kMaxBE = kBlockElems;  // bound for per-thread register arrays
   int logn, S;        // split
   int BE;             // elements per block
   int lbe;            // log2 BE
@@ -43,10 +44,11 @@ __host__ __device__ inline PassGeom make_geom(int logn) {
 // loop bound of the pass code folds, as with the whole-limb transforms.
 __host__ __device__ constexpr int cmin(int a, int b) { return a < b ? a : b; }
 __host__ __device__ constexpr int clog2(int x) { return x <= 1 ? 0 : 1 + clog2(x >> 1); }
-template <int LOGN>
+template <int LOGN, int LBE = 11>
 struct PassGeomC {
   static constexpr int logn = LOGN, S = LOGN >> 1;
-  static constexpr int BE = cmin(1 << LOGN, kBlockElems);
+  static constexpr int BE = cmin(1 << LOGN, 1 << LBE);
+  static constexpr int kMaxBE = BE;  // bound for per-thread register arrays
   static constexpr int lbe = clog2(BE);
   static constexpr int nblk = (1 << LOGN) / BE;
   __host__ __device__ static constexpr int gb_high() { return BE >> S; }
@@ -61,6 +63,11 @@ struct PassGeomC {
 // unit-stride rounds conflict-free.
 template <bool HIGH>
 __device__ __forceinline__ int lpadx(int i) { return HIGH ? i + (i >> 5) : i + (i >> 4); }
+
+// The same ring with half-size blocks (1024 elements): kernels whose workgroups hold several blocks
+// use it to double their grid and halve each workgroup's serial work.  Runtime geometry: unchanged.
+template <class GT> struct HalfBlocks { using type = GT; };
+template <int LOGN> struct HalfBlocks<PassGeomC<LOGN, 11>> { using type = PassGeomC<LOGN, 10>; };
 
 // Global index of element u of group g in block `blk`.
 template <class GT>

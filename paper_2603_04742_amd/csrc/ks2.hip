@@ -258,7 +258,7 @@ template <int NT, int DMAX, class GT>
 __global__ void __launch_bounds__(NT) k2_ip_par(const RotItem* __restrict__ items, const double* __restrict__ E, double* ACC, double* T2, KsShape S,
                                                 const ModTab* __restrict__ tab, GT G) {
   SMEM2(G);
-  constexpr int PER = kBlockElems / NT > 0 ? kBlockElems / NT : 1;
+  constexpr int PER = GT::kMaxBE / NT > 0 ? GT::kMaxBE / NT : 1;
   const int n = 1 << G.logn;
   const int blk = blockIdx.x, y = blockIdx.y, b = blockIdx.z;
   const bool special = y >= S.L;
@@ -488,11 +488,17 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B), TW + LB, st, d_items, T1, c->L, tab, G);
     HS2_LAUNCH(k2_modup_high, dim3(G.nblk, c->dnum * LK, B), TWH + LB * (c->alpha + 1), st, (const double*)T1, E, S,
                (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
-    if (TW + LB * c->dnum <= (size_t)160 * 1024 && G.BE >= 1024 && c->dnum <= 6) {
+    // the all-digit inner product on half-size blocks where the geometry is compile-time (twice
+    // the workgroups, each with half the serial work; two fit a CU)
+    using G3T = typename HalfBlocks<GT>::type;
+    const G3T G3{};
+    constexpr int NT3 = G3T::kMaxBE >= 2048 ? 1024 : 512;
+    const size_t LB3 = (size_t)lds_doubles(G3.BE) * sizeof(double), TW3 = (size_t)2 * G3.BE * sizeof(double);
+    if (TW3 + LB3 * c->dnum <= (size_t)160 * 1024 && G3.BE >= 1024 && c->dnum <= 6) {
       ProfScope _prof("k2_ip_par", st);
-      ensure_lds2((const void*)k2_ip_par<1024, 6, GT>, TW + LB * c->dnum);
-      hipLaunchKernelGGL((k2_ip_par<1024, 6, GT>), dim3(G.nblk, c->L + 2 * c->K, B), dim3(1024), TW + LB * c->dnum, st, d_items, (const double*)E, ACC,
-                         T2, S, tab, G);
+      ensure_lds2((const void*)k2_ip_par<NT3, 6, G3T>, TW3 + LB3 * c->dnum);
+      hipLaunchKernelGGL((k2_ip_par<NT3, 6, G3T>), dim3(G3.nblk, c->L + 2 * c->K, B), dim3(NT3), TW3 + LB3 * c->dnum, st, d_items, (const double*)E,
+                         ACC, T2, S, tab, G3);
       HS_CHECK_HIP(hipGetLastError());
     } else {
       HS2_LAUNCH(k2_ip_low, dim3(G.nblk, LK, B), TW + LB, st, d_items, (const double*)E, ACC, T2, S, tab, G);
