@@ -1567,25 +1567,44 @@ static void server_tick(hs_server* S) {
     }
   }
   if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), S->st);
-  // one rotation level across every active request
+  // rotation levels across every active request: one when requests wait for admission, else as
+  // many as every active request still has (at most 4), enqueued without host waits in between, so
+  // no request finishes in the middle of a tick and admission stays responsive
   auto buf = [&](SrvReq* r, int g, int id) -> u64* {
     return id == 0 ? r->vbuf.as<u64>() + (size_t)g * CW : r->wtbuf.as<u64>() + (size_t)(r->wt_base[g] + id - 1) * CW;
   };
-  std::vector<std::vector<RotItem>> level(1);
-  for (auto& r : S->active)
-    for (size_t g = 0; g < r->progs.size(); g++) {
-      auto& prog = r->progs[g];
-      if (r->pc[g] + 1 >= prog.size()) continue;
-      const MicroOp& op = prog[r->pc[g]++];
-      RotItem it{};
-      it.in = buf(r.get(), (int)g, op.in);
-      it.out = buf(r.get(), (int)g, op.out);
-      it.addend = op.addend >= 0 ? buf(r.get(), (int)g, op.addend) : nullptr;
-      it.key = r->ks->gk[op.pow2];
-      it.galois = (u32)galois_pow2(c, op.pow2);
-      level[0].push_back(it);
+  int nlev = 1;
+  bool waiting;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    waiting = !S->queue.empty();
+  }
+  if (!waiting) {
+    int minrem = 0;
+    for (auto& r : S->active) {
+      int rem = 0;
+      for (size_t g = 0; g < r->progs.size(); g++) rem = std::max(rem, (int)r->progs[g].size() - 1 - (int)r->pc[g]);
+      if (rem > 0) minrem = minrem == 0 ? rem : std::min(minrem, rem);
     }
-  if (!level[0].empty()) run_rotation_levels(c, level, S->st);
+    nlev = std::max(1, std::min(minrem, 4));
+  }
+  std::vector<std::vector<RotItem>> levels(nlev);
+  for (int lv = 0; lv < nlev; lv++)
+    for (auto& r : S->active)
+      for (size_t g = 0; g < r->progs.size(); g++) {
+        auto& prog = r->progs[g];
+        if ((size_t)r->pc[g] + 1 >= prog.size()) continue;
+        const MicroOp& op = prog[r->pc[g]++];
+        RotItem it{};
+        it.in = buf(r.get(), (int)g, op.in);
+        it.out = buf(r.get(), (int)g, op.out);
+        it.addend = op.addend >= 0 ? buf(r.get(), (int)g, op.addend) : nullptr;
+        it.key = r->ks->gk[op.pow2];
+        it.galois = (u32)galois_pow2(c, op.pow2);
+        levels[lv].push_back(it);
+      }
+  while (!levels.empty() && levels.back().empty()) levels.pop_back();
+  if (!levels.empty()) run_rotation_levels(c, levels, S->st);
   // retire finished requests
   std::vector<std::shared_ptr<SrvReq>> done;
   std::vector<DBuf> keep;
