@@ -114,6 +114,9 @@ int hs_keyset_export(const hs_keyset* ks, int which, int index, uint64_t* host_o
 int hs_cssc_pack(hs_ctx* ctx, int64_t rows, int64_t cols, const int64_t* row_ptr,
                  const int32_t* col_idx, const int64_t* vals, int encrypt_values,
                  const hs_keyset* ks, uint64_t seed, void* stream, hs_matrix** out);
+/* Matrices and ciphertext vectors take their device memory from the context's pool; their destroy
+   functions wait for the device (hipDeviceSynchronize) before handing it back, and must be called
+   before the context's hs_ctx_destroy. */
 void hs_matrix_destroy(hs_matrix* m);
 int hs_matrix_info(const hs_matrix* m, int64_t* n_parts, int64_t* n_chunks);
 /* Chunk k (global numbering over partitions): out4 = (partition, first CSSC column, columns c,

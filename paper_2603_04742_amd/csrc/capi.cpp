@@ -728,6 +728,9 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
 
 void hs_matrix_destroy(hs_matrix* m) {
   if (!m) return;
+  // the memory returns to the context's pool, from which work on any stream may take it next:
+  // wait for the device so no operation still in flight (an asynchronous call) uses it
+  (void)hipDeviceSynchronize();
   void* ptrs[] = {m->d_cp, m->d_rm, m->d_va, m->d_ci, m->d_chunk, m->d_pt, m->d_mask};
   for (void* p : ptrs) pfree(m->ctx, p);
   delete m;
@@ -1316,7 +1319,10 @@ int hs_ctvec_import(hs_ctx* c, const uint64_t* host_limbs, int64_t n, hs_ctvec**
 
 void hs_ctvec_destroy(hs_ctvec* v) {
   if (!v) return;
-  if (v->d && v->owned) pfree(v->ctx, v->d);
+  if (v->d && v->owned) {
+    (void)hipDeviceSynchronize();  // as for matrices: nothing in flight may still use the memory
+    pfree(v->ctx, v->d);
+  }
   delete v;
 }
 
