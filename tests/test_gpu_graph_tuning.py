@@ -18,6 +18,7 @@ if not torch.cuda.is_available():
 
 from paper_2603_04742_amd import hespmv as H  # noqa: E402
 
+SMALL = (12, 2, 30, 1, 1)  # the ring of the 256 x 256 workload: uniform aggregation, 30-bit primes
 TINY = (9, 3, 50, 1, 0)
 TINY11 = (11, 3, 50, 1, 0)
 RING16K = (14, 6, 50, 1, 0)
@@ -57,7 +58,7 @@ def check_decrypt(g, reqs, ys):
         assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
 
 
-@pytest.mark.parametrize("p", [TINY, RING16K], ids=["tiny", "ring16k"])
+@pytest.mark.parametrize("p", [TINY, SMALL, RING16K], ids=["tiny", "ring4096", "ring16k"])
 def test_batch_plan_replays_match_eager(p):
     g, kg = fresh(p)
     kg2 = g.keygen(12)
@@ -105,10 +106,10 @@ def test_batch_plan_rejects_encrypted_matrix():
         H.BatchPlan(g, [kg], [M], [x])
 
 
-@pytest.mark.parametrize("p", [TINY11, RING16K], ids=["ring2048", "ring16k"])
+@pytest.mark.parametrize("p", [TINY11, SMALL, RING16K], ids=["ring2048", "ring4096", "ring16k"])
 def test_autotune_and_every_tuning_give_identical_limbs(p):
     g, kg = fresh(p)
-    shapes = [(300, 300, 1500), (700, 200, 2000)] if p == TINY11 else [(9000, 4000, 20000), (64, 64, 300)]
+    shapes = [(9000, 4000, 20000), (64, 64, 300)] if p == RING16K else [(300, 300, 1500), (700, 200, 2000)]
     reqs = requests(g, [kg], shapes, 8)
     kss, ms, xs = [r[1] for r in reqs], [r[2] for r in reqs], [r[3] for r in reqs]
     ref = [y.export_all() for y in H.he_spmv_batch(g, kss, ms, xs)]
@@ -126,7 +127,7 @@ def test_autotune_and_every_tuning_give_identical_limbs(p):
             for y, e in zip(H.he_spmv_batch(g, kss, ms, xs), ref):
                 assert np.array_equal(y.export_all(), e), "variant %d pipeline %d" % (variant, pick)
             # the standalone transform under this variant round-trips
-            lim = torch.randint(0, 1 << 40, (3, p[1], 1 << p[0]), dtype=torch.int64, device="cuda")
+            lim = torch.randint(0, min(g.moduli()[: p[1]]), (3, p[1], 1 << p[0]), dtype=torch.int64, device="cuda")
             back = lim.clone()
             g.ntt(back, 0, p[1])
             g.ntt(back, 0, p[1], inverse=True)
