@@ -68,6 +68,9 @@ def lib():
             "orc_keyswitch": (None, [vp, u64p, ctypes.c_int, u64p]),
             "orc_automorph_ntt": (None, [vp, u64p, ctypes.c_uint64, u64p]),
             "orc_rotate": (None, [vp, u64p, ctypes.c_uint64, u64p]),
+            "orc_add_step_keys": (None, [vp, i64p, ctypes.c_int64]),
+            "orc_export_step_key": (ctypes.c_int, [vp, ctypes.c_uint64, u64p]),
+            "orc_total_sum_steps": (ctypes.c_int, [vp, ctypes.c_int64, ctypes.c_int64, u64p]),
             "orc_total_sum": (None, [vp, u64p, ctypes.c_int64, ctypes.c_int64, u64p]),
             "orc_cssc_lw": (ctypes.c_int, [ctypes.c_int64, i64p]),
             "orc_cssc": (None, [ctypes.c_int64, i64p, i32p, i64p, i64p, i32p, i32p, i64p]),
@@ -230,6 +233,21 @@ class Context:
         out = np.zeros(2 * self.dnum * (self.L + self.K) * self.N, np.uint64)
         lib().orc_export_ksk(self.h, key_id, _p(out, u64p))
         return out
+
+    def add_step_keys(self, steps):
+        """Rotation keys for left rotations by exactly these steps (mod N/2); powers of two and
+        steps already held are skipped."""
+        st = np.ascontiguousarray(np.asarray(steps, np.int64).reshape(-1))
+        lib().orc_add_step_keys(self.h, _p(st, i64p), len(st))
+
+    def step_key(self, k):
+        out = np.zeros(2 * self.dnum * (self.L + self.K) * self.N, np.uint64)
+        return out if lib().orc_export_step_key(self.h, k, _p(out, u64p)) else None
+
+    def total_sum_steps(self, r, c):
+        out = np.zeros(128, np.uint64)
+        n = lib().orc_total_sum_steps(self.h, r, c, _p(out, u64p))
+        return [int(x) for x in out[:n]]
 
     # --- HE ops (ciphertexts: flat uint64 [2][L][N], NTT form)
     def ct_size(self):

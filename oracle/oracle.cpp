@@ -30,6 +30,7 @@
 #include <cstring>
 #include <vector>
 #include <algorithm>
+#include <map>
 
 #include "cdt_sigma3p2.h"
 
@@ -395,6 +396,7 @@ struct Ctx {
   std::vector<u64> s_ntt;        /* [L+K+n_aux][N] */
   std::vector<u64> pk0, pk1;     /* [L][N] */
   std::vector<std::vector<u64>> gk; /* per power-of-two rotation: [2][dnum][L+K][N] (b then a) */
+  std::map<u64, std::vector<u64>> gk_step; /* optional exact-step rotation keys, by step k */
   std::vector<u64> rk;           /* relinearisation key, same layout */
   u64 keyseed = 0;
 };
@@ -403,6 +405,12 @@ u64* limb(std::vector<u64>& v, u64 N, int i) { return v.data() + (u64)i * N; }
 
 /* Rotation key id i rotates the slots left by 2^i; its Galois element is 3^(2^i) mod 2N. */
 u64 galois_elt_pow2(const Ctx& c, int i) { return powmod(3, 1ULL << i, 2 * c.N); }
+/* A left rotation by k slots within each slot row has Galois element 3^k mod 2N (Sec. 2.1,
+   HE-Rot; 3 generates the slot-row rotations of the power-of-two cyclotomic ring). */
+u64 galois_elt_step(const Ctx& c, u64 k) { return powmod(3, k, 2 * c.N); }
+/* Sampling id of an exact-step rotation key: above the power-of-two ids (< 64) and the
+   relinearisation id (255), one per step. */
+u32 step_key_id(u64 k) { return 256u + (u32)k; }
 
 /* Coefficient-domain automorphism a(X) -> a(X^g) mod (X^N + 1) over Z_m. */
 std::vector<u64> automorph_coeff(const std::vector<u64>& a, u64 g, u64 N, u64 m) {
@@ -556,6 +564,7 @@ void keygen(Ctx& c, u64 seed) {
     }
   }
   c.gk.clear();
+  c.gk_step.clear();
   for (int i = 0; i + 1 < c.logn; i++) {
     std::vector<i64> sg = automorph_int(c.s, galois_elt_pow2(c, i), N);
     c.gk.push_back(make_ksk(c, sg, (u32)i));
@@ -788,13 +797,14 @@ std::vector<u64> automorph_poly_ntt(const Ctx& c, const std::vector<u64>& a, u64
   return r;
 }
 
-/* One key-switched rotation by 2^i slots (left): (sigma(c0) + ks0, ks1), ks = KS(sigma(c1)). */
-std::vector<u64> rotate_pow2(const Ctx& c, const std::vector<u64>& ct, int i) {
-  u64 g = galois_elt_pow2(c, i), LN = (u64)c.L * c.N;
+/* One key-switched automorphism (left rotation): (sigma_g(c0) + ks0, ks1), ks = KS(sigma_g(c1))
+   with the key for sigma_g(s) -> s. */
+std::vector<u64> rotate_with_key(const Ctx& c, const std::vector<u64>& ct, u64 g, const std::vector<u64>& key) {
+  u64 LN = (u64)c.L * c.N;
   std::vector<u64> c0(ct.begin(), ct.begin() + LN), c1(ct.begin() + LN, ct.end());
   std::vector<u64> a0 = automorph_poly_ntt(c, c0, g, c.L), a1 = automorph_poly_ntt(c, c1, g, c.L);
   std::vector<u64> k0, k1;
-  keyswitch(c, a1, c.gk[i], k0, k1);
+  keyswitch(c, a1, key, k0, k1);
   std::vector<u64> r(2 * LN);
   for (int l = 0; l < c.L; l++)
     for (u64 k = 0; k < c.N; k++) {
@@ -804,14 +814,33 @@ std::vector<u64> rotate_pow2(const Ctx& c, const std::vector<u64>& ct, int i) {
     }
   return r;
 }
-/* HE-Rot by k slots (left, within each row of N/2 slots): the binary digits of k in ascending
-   order, each one power-of-two rotation with its own key. */
+std::vector<u64> rotate_pow2(const Ctx& c, const std::vector<u64>& ct, int i) {
+  return rotate_with_key(c, ct, galois_elt_pow2(c, i), c.gk[i]);
+}
+/* HE-Rot by k slots (left, within each row of N/2 slots).  With a rotation key for exactly k,
+   one key switch with it; otherwise the binary digits of k in ascending order, each one
+   power-of-two rotation with its own key.  Both decrypt to the same rotated slots; their noise
+   (and so their limbs) differ. */
 std::vector<u64> rotate(const Ctx& c, const std::vector<u64>& ct, u64 k, int* nks) {
   std::vector<u64> r(ct);
   k %= c.N / 2;
+  auto it = c.gk_step.find(k);
+  if (it != c.gk_step.end()) {
+    if (nks) (*nks)++;
+    return rotate_with_key(c, r, galois_elt_step(c, k), it->second);
+  }
   for (int i = 0; i + 1 < c.logn; i++)
     if ((k >> i) & 1) { r = rotate_pow2(c, r, i); if (nks) (*nks)++; }
   return r;
+}
+
+/* Adds a rotation key for a left rotation by exactly k slots (k mod N/2; nothing for 0, for a
+   power of two, which the power-of-two key already covers, or for a step already held). */
+void add_step_key(Ctx& c, u64 k) {
+  k %= c.N / 2;
+  if (k == 0 || (k & (k - 1)) == 0 || c.gk_step.count(k)) return;
+  std::vector<i64> sg = automorph_int(c.s, galois_elt_step(c, k), c.N);
+  c.gk_step[k] = make_ksk(c, sg, step_key_id(k));
 }
 
 /* HE-Mult (both operands encrypted): the exact scaled tensor
@@ -969,6 +998,20 @@ std::vector<u64> total_sum(const Ctx& c, const std::vector<u64>& ctV, i64 r, i64
   return w;
 }
 
+/* The rotation amounts (mod N/2) that total_sum applies to a chunk of height r and ccols
+   columns, in the order it applies them. */
+std::vector<u64> total_sum_steps(const Ctx& c, i64 r, i64 ccols) {
+  std::vector<u64> out;
+  u64 e = 1, half = c.N / 2;
+  int nb = (int)num_bits((u64)ccols);
+  for (int j = nb - 2; j >= 0; j--) {
+    out.push_back((e * (u64)r) % half);
+    e *= 2;
+    if (((u64)ccols >> j) & 1) { out.push_back((u64)r % half); e += 1; }
+  }
+  return out;
+}
+
 struct Partition { i64 row0, rows; Cssc m; std::vector<Chunk> chunks; };
 struct Matrix {
   i64 R = 0, C = 0; int encrypted = 0;
@@ -1058,6 +1101,23 @@ void orc_keyswitch(void* h, const u64* d, int key_id, u64* out) {
 void orc_automorph_ntt(void* h, const u64* a, u64 g, u64* out) {
   Ctx* c = (Ctx*)h; std::vector<u64> x(a, a + (u64)c->L * c->N); auto r = automorph_poly_ntt(*c, x, g, c->L);
   memcpy(out, r.data(), r.size() * 8);
+}
+void orc_add_step_keys(void* h, const i64* steps, i64 n) {
+  Ctx* c = (Ctx*)h; i64 half = (i64)c->N / 2;
+  for (i64 i = 0; i < n; i++) add_step_key(*c, (u64)(((steps[i] % half) + half) % half));
+}
+/* Exact-step rotation key for k, layout [2][dnum][L+K][N]; returns 0 when none is held. */
+int orc_export_step_key(void* h, u64 k, u64* out) {
+  Ctx* c = (Ctx*)h; auto it = c->gk_step.find(k % (c->N / 2));
+  if (it == c->gk_step.end()) return 0;
+  memcpy(out, it->second.data(), it->second.size() * 8);
+  return 1;
+}
+/* Rotation amounts of one chunk's totalSum (at most 2 log2 N of them); returns the count. */
+int orc_total_sum_steps(void* h, i64 r, i64 cc, u64* out) {
+  auto v = total_sum_steps(*(Ctx*)h, r, cc);
+  for (size_t i = 0; i < v.size(); i++) out[i] = v[i];
+  return (int)v.size();
 }
 void orc_rotate(void* h, const u64* ct, u64 k, u64* out) {
   Ctx* c = (Ctx*)h; u64 n = 2ULL * c->L * c->N; std::vector<u64> x(ct, ct + n);

@@ -317,6 +317,54 @@ def test_homomorphic_add_cmult_rotate_keyswitch():
     assert np.array_equal(out, c.rotate(cx, 4))
 
 
+def test_exact_step_rotation_keys():
+    """Sec. 2.1 HE-Rot with a key for the whole step: one key switch whose key satisfies
+    b + a s = e + P sigma_g(s) on its digit (g = 3^k mod 2N, e small), and whose rotation decrypts
+    to the slot rows rotated left by k; power-of-two steps and 0 get no extra key."""
+    c = small_ctx(logn=6, L=2, bits=30, K=1)
+    N, h, L, K = c.N, c.N // 2, c.L, c.K
+    c.add_step_keys([3, 5, -1, 4, 0, 3, h + 6])
+    assert c.step_key(4) is None and c.step_key(0) is None and c.step_key(7) is None
+    mods = c.moduli()
+    P = math.prod(mods[L:L + K])
+    s = [int(v) for v in c.sk()]
+    for k in (3, 5, h - 1, 6):
+        key = c.step_key(k).reshape(2, c.dnum, L + K, N)
+        sp = coeff_automorph(s, pow(3, k, 2 * N), 2 ** 62)
+        sp = [v - 2 ** 62 if v > 2 ** 61 else v for v in sp]
+        for j in range(c.dnum):
+            for m in range(L + K):
+                q = mods[m]
+                b = [int(v) for v in c.intt(m, key[0, j, m].copy())]
+                a = [int(v) for v in c.intt(m, key[1, j, m].copy())]
+                e = [(x + y) % q for x, y in zip(b, negacyclic(a, [v % q for v in s], q))]
+                if m < L and m // K == j:  # digits of K data primes
+                    e = [(x - P * v) % q for x, v in zip(e, sp)]
+                e = [v - q if v > q // 2 else v for v in e]
+                assert max(abs(v) for v in e) <= 19, (k, j, m)
+    g = np.random.default_rng(21)
+    x = g.integers(0, T, N)
+    cx = c.encrypt(c.encode(x), 8, 0)
+    for k in (3, 5, h - 1, 6, 7):
+        want = np.concatenate([np.roll(x[:h], -k), np.roll(x[h:], -k)])
+        assert np.array_equal(c.decode(c.decrypt(c.rotate(cx, k))), want), k
+
+
+def test_total_sum_steps_follow_the_recurrence():
+    c = small_ctx(logn=8)
+    h = c.N // 2
+    for r, cc in ((5, 6), (3, 1), (7, 13), (1, 16), (40, 5)):
+        steps, e = [], 1
+        for j in range(cc.bit_length() - 2, -1, -1):
+            steps.append(e * r % h)
+            e *= 2
+            if (cc >> j) & 1:
+                steps.append(r % h)
+                e += 1
+        assert c.total_sum_steps(r, cc) == steps
+    assert c.total_sum_steps(5, 6) == [5, 5, 15]
+
+
 def test_ct_times_ct_with_relinearisation():
     c = small_ctx(logn=6, L=3, bits=50, K=1)
     g = np.random.default_rng(8)
@@ -567,6 +615,28 @@ def test_spmv_small_workload_uniform_aggregation():
     cs = [M.chunk(k)[2] for k in range(n_ct)]
     assert stats["rotations"] == sum((x.bit_length() - 1) + (bin(x).count("1") - 1) for x in cs)
     assert stats["rotations"] <= 2 * n_ct * math.log2(max(cs))
+
+
+def test_spmv_with_exact_step_keys_one_key_switch_per_rotation():
+    """With a key for every totalSum step the decrypted product is unchanged and every logical
+    rotation costs one key switch instead of one per binary digit of its step."""
+    g = np.random.default_rng(17)
+    rp, col, val = W.uniform_matrix(300, 200, 1200, 15, g)
+    w = dict(R=300, C=200, row_ptr=rp, col=col, val=val, v=g.integers(-15, 16, 200))
+    res = []
+    for steps in (False, True):
+        c = O.Context(9, 3, 50, 1, agg_mode=0)   # s = 256: two row partitions, several chunks
+        c.keygen(101)
+        M = O.Matrix(c, w["R"], w["C"], w["row_ptr"], w["col"], w["val"], False, 31)
+        if steps:
+            need = sorted({k for g in range(M.n_chunks()) for k in c.total_sum_steps(M.chunk(g)[3], M.chunk(g)[2])})
+            c.add_step_keys(need)
+        x = M.encrypt_vector(w["v"], 41)
+        out, stats = M.he_spmv(x)
+        assert np.array_equal(M.decrypt_result(out), W.spmv_mod_t(w))
+        res.append(stats)
+    assert res[1]["rotations"] == res[0]["rotations"] == res[1]["key_switches"]
+    assert res[0]["key_switches"] > res[0]["rotations"]
 
 
 @pytest.mark.parametrize("case", ["empty", "one", "emptyrows", "rect", "partitions", "dense_row"])
