@@ -98,8 +98,20 @@ int hs_keygen(hs_ctx* ctx, uint64_t seed, void* stream, hs_keyset** out);
 void hs_keyset_destroy(hs_keyset* ks);
 /* Copy key material to host memory, for verification.  which: 0 = secret key, NTT form
    [n_moduli][N]; 1 = public key [2][L][N]; 2 = rotation key `index` [2][dnum][L+K][N]
-   (b then a); 3 = relinearisation key, same layout.  cap in u64 words; HS_ECAPACITY if short. */
+   (b then a); 3 = relinearisation key, same layout; 4 = exact-step rotation key for the step
+   `index` (HS_EKEY if the key-set holds none).  cap in u64 words; HS_ECAPACITY if short. */
 int hs_keyset_export(const hs_keyset* ks, int which, int index, uint64_t* host_out, int64_t cap);
+/* Add rotation keys for left rotations by exactly steps[i] slots (Sec. 2.1, HE-Rot with Galois
+   element 3^k mod 2N; each step taken mod N/2).  Steps that are 0 or a power of two, and steps
+   the key-set already holds, are skipped.  Afterwards every rotation by a held step -- in
+   hs_rotate and in the totalSum of hs_he_spmv, its batched forms and the server -- is one key
+   switch instead of one per binary digit: the decrypted results are the same, the ciphertext
+   limbs (their noise) differ.  Keys are [2][dnum][L+K][N] each (10.5 MiB at N = 16384 with
+   6 + 1 primes), sampled from the key-set's seed with a stream id of their own.  Must not run
+   concurrently with other calls that use the key-set; batch plans keep the keys they were
+   recorded with.  Synchronises `stream`. */
+int hs_keyset_add_rotation_keys(hs_ctx* ctx, hs_keyset* ks, const int64_t* host_steps, int64_t n,
+                                void* stream);
 
 /* ---------------------------------------------------------------- Client A: matrix */
 /* Pack an R x C integer matrix given in CSR form (device arrays: row_ptr int64[R+1] with
@@ -125,6 +137,11 @@ int hs_matrix_chunk(const hs_matrix* m, int64_t k, int64_t out4[4]);
 /* The CSSC column-index array (all partitions, concatenated) that Client A sends to Client B
    (Alg. "Sparse Matrix-Vector Multiplication"), into host memory. *len receives nnz. */
 int hs_matrix_column_index(const hs_matrix* m, int32_t* host_ci, int64_t cap, int64_t* len);
+/* The distinct rotation steps (mod N/2, ascending) of the totalSum of every chunk of the matrix
+   (Alg. Aggregation: e r and r for the chunk height r), into host memory; *len receives the count
+   (HS_ECAPACITY if cap is short).  The layout is public, so a key holder can add exactly these
+   keys with hs_keyset_add_rotation_keys. */
+int hs_matrix_rotation_steps(const hs_matrix* m, int64_t* host_steps, int64_t cap, int64_t* len);
 /* Encoded (NTT-form [L][N]) or encrypted ([2][L][N]) chunk k, or its mask (which = 1), to host. */
 int hs_matrix_export(const hs_matrix* m, int which, int64_t k, uint64_t* host_out, int64_t cap);
 
@@ -216,8 +233,10 @@ int hs_ntt(hs_ctx* ctx, uint64_t* d_limbs, int64_t n_polys, int mod0, int n_limb
 /* Slot-wise product of every ciphertext of `in` with the NTT-form plaintext pt (device u64
    [L][N]) (HE-CMult). */
 int hs_mul_plain(hs_ctx* ctx, const hs_ctvec* in, const uint64_t* d_pt, void* stream, hs_ctvec** out);
-/* Left rotation of every ciphertext of `in` by k slots within each slot row (HE-Rot): the binary
-   digits of k mod N/2 in ascending order, each a Galois automorphism 3^(2^i) plus a key switch. */
+/* Left rotation of every ciphertext of `in` by k slots within each slot row (HE-Rot): one Galois
+   automorphism 3^k plus a key switch when the key-set holds an exact-step key for k mod N/2, else
+   the binary digits of k mod N/2 in ascending order, each a Galois automorphism 3^(2^i) plus a key
+   switch. */
 int hs_rotate(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* in, int64_t k, void* stream,
               hs_ctvec** out);
 /* Slot-wise product of two ciphertexts (HE-Mult): exact scaled tensor round(t/Q * (a (x) b)) of the

@@ -119,6 +119,18 @@ enum : u32 { P_SK = 1, P_PK_A = 2, P_PK_E = 3, P_KSK_A = 4, P_KSK_E = 5, P_ENC_U
 static const u32 RELIN_ID = 255;
 
 static u64 galois_pow2(const hs_ctx* c, int i) { return pow_mod(3, 1ULL << i, 2 * c->N); }
+// Left rotation by k slots within each slot row: Galois element 3^k mod 2N (Sec. 2.1, HE-Rot).
+static u64 galois_step(const hs_ctx* c, i64 k) { return pow_mod(3, (u64)k, 2 * c->N); }
+// Sampling id of the exact-step rotation key for k: above the power-of-two ids and RELIN_ID.
+static u32 step_key_id(i64 k) { return 256u + (u32)k; }
+static bool is_pow2(i64 k) { return k > 0 && (k & (k - 1)) == 0; }
+// Key of a rotation micro-op: a power-of-two key, or the exact-step key for k.
+static const u64* rotation_key(const hs_keyset* ks, i64 step) {
+  if (is_pow2(step)) return ks->gk[__builtin_ctzll((unsigned long long)step)];
+  auto it = ks->step_keys.find(step);
+  if (it == ks->step_keys.end()) throw Error{HS_EKEY, "internal: no rotation key for a planned step"};
+  return it->second;
+}
 
 // ------------------------------------------------------------------ key generation
 static bool use_split(const hs_ctx* c);
@@ -187,25 +199,42 @@ static std::vector<hs_chunk> make_chunks(const std::vector<i64>& cp, i64 s, int 
 }
 
 // ------------------------------------------------------------------ he_spmv plan
-// Micro-op of a chunk's totalSum: one power-of-two rotation, in -> out (+ addend).
+// Micro-op of a chunk's totalSum: one key-switched rotation by `step` slots, in -> out (+ addend).
 struct MicroOp {
   int in, out, addend;  // buffer ids per chunk: 0 = V (product), 1 = WA, 2 = WB, 3 = TA, 4 = TB; -1 none
-  int pow2;
+  i64 step;             // a power of two, or a step the key-set holds an exact key for
 };
 
-static std::vector<MicroOp> total_sum_program(const hs_ctx* c, i64 r, int cols, int* n_logical) {
+// The rotation amounts (mod N/2) of one chunk's totalSum, in the order it applies them.
+static std::vector<i64> total_sum_steps(const hs_ctx* c, i64 r, int cols) {
+  std::vector<i64> out;
+  const i64 half = (i64)c->N / 2;
+  i64 e = 1;
+  const int nb = 32 - __builtin_clz((unsigned)cols);
+  for (int j = nb - 2; j >= 0; j--) {
+    out.push_back((e * r) % half);
+    e *= 2;
+    if ((cols >> j) & 1) { out.push_back(r % half); e += 1; }
+  }
+  return out;
+}
+
+static std::vector<MicroOp> total_sum_program(const hs_ctx* c, const hs_keyset* ks, i64 r, int cols, int* n_logical) {
   std::vector<MicroOp> prog;
   int w = 0;  // current accumulator buffer
   i64 e = 1;
   const int nb = 32 - __builtin_clz((unsigned)cols);
   const i64 half = (i64)c->N / 2;
   auto rotate_into = [&](int src, i64 amount, int addend) {
-    // rotation by `amount` applied as its binary digits (ascending), last one lands in the W
-    // buffer that is not the current accumulator, plus `addend`
+    // rotation by `amount` as one key switch when the key-set holds a key for the whole step,
+    // else as its binary digits (ascending); the last one lands in the W buffer that is not the
+    // current accumulator, plus `addend`
     const i64 k = amount % half;
-    std::vector<int> bits;
-    for (int i = 0; i + 1 < c->logn; i++)
-      if ((k >> i) & 1) bits.push_back(i);
+    std::vector<i64> bits;
+    if (!is_pow2(k) && ks->step_keys.count(k)) bits.push_back(k);
+    else
+      for (int i = 0; i + 1 < c->logn; i++)
+        if ((k >> i) & 1) bits.push_back(1LL << i);
     if (bits.empty()) throw Error{HS_EINVAL, "internal: zero rotation in totalSum"};
     const int dst_w = (w == 1) ? 2 : 1;
     int cur = src;
@@ -561,6 +590,7 @@ void hs_keyset_destroy(hs_keyset* ks) {
   if (ks->sk) (void)hipFree(ks->sk);
   if (ks->pk) (void)hipFree(ks->pk);
   for (u64* p : ks->gk) (void)hipFree(p);
+  for (auto& kv : ks->step_keys) (void)hipFree(kv.second);
   if (ks->rk) (void)hipFree(ks->rk);
   delete ks;
 }
@@ -577,9 +607,43 @@ int hs_keyset_export(const hs_keyset* ks, int which, int index, uint64_t* host_o
       HS_REQUIRE(index >= 0 && index < (int)ks->gk.size(), HS_EKEY, "no rotation key with that index");
       src = ks->gk[index]; n = ks->ksk_words;
     } else if (which == 3) { src = ks->rk; n = ks->ksk_words; }
-    else throw Error{HS_EINVAL, "unknown key kind"};
+    else if (which == 4) {
+      auto it = ks->step_keys.find(index);
+      HS_REQUIRE(it != ks->step_keys.end(), HS_EKEY, "no exact-step rotation key for that step");
+      src = it->second; n = ks->ksk_words;
+    } else throw Error{HS_EINVAL, "unknown key kind"};
     HS_REQUIRE((size_t)cap >= n, HS_ECAPACITY, "output too small");
     HS_CHECK_HIP(hipMemcpy(host_out, src, n * sizeof(u64), hipMemcpyDeviceToHost));
+  });
+}
+
+int hs_keyset_add_rotation_keys(hs_ctx* c, hs_keyset* ks, const int64_t* steps, int64_t n, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks && (n == 0 || steps), HS_EINVAL, "null argument");
+    HS_REQUIRE(n >= 0, HS_EINVAL, "negative count");
+    HS_REQUIRE(ks->ctx == c, HS_EKEY, "key-set from another context");
+    hipStream_t st = S(stream);
+    const i64 half = (i64)c->N / 2;
+    for (i64 i = 0; i < n; i++) {
+      const i64 k = ((steps[i] % half) + half) % half;
+      if (k == 0 || is_pow2(k) || ks->step_keys.count(k)) continue;
+      u64* key = make_ksk(c, ks, step_key_id(k), 1, (u32)galois_step(c, k), st);
+      ks->step_keys[k] = key;
+    }
+  });
+}
+
+int hs_matrix_rotation_steps(const hs_matrix* m, int64_t* out, int64_t cap, int64_t* len) {
+  return guarded([&] {
+    HS_REQUIRE(m && len && (cap == 0 || out), HS_EINVAL, "null argument");
+    std::vector<i64> all;
+    for (const hs_chunk& ch : m->chunks)
+      for (i64 k : total_sum_steps(m->ctx, ch.h, ch.c)) all.push_back(k);
+    std::sort(all.begin(), all.end());
+    all.erase(std::unique(all.begin(), all.end()), all.end());
+    *len = (int64_t)all.size();
+    HS_REQUIRE(cap >= (int64_t)all.size(), HS_ECAPACITY, "output too small");
+    for (size_t i = 0; i < all.size(); i++) out[i] = all[i];
   });
 }
 
@@ -858,7 +922,7 @@ struct BatchWork {
       q.progs.resize(q.G);
       q.wt_base.assign(q.G, -1);
       for (int g = 0; g < q.G; g++) {
-        q.progs[g] = total_sum_program(c, m[r]->chunks[g].h, m[r]->chunks[g].c, &nlog);
+        q.progs[g] = total_sum_program(c, ks[r], m[r]->chunks[g].h, m[r]->chunks[g].c, &nlog);
         if (q.progs[g].size() > 1) { q.wt_base[g] = q.nwt; q.nwt += 4; }
       }
       keep.emplace_back(&c->pool, (size_t)std::max(q.G, 1) * CW * sizeof(u64));
@@ -901,8 +965,8 @@ struct BatchWork {
           it.in = buf(r, g, op.in);
           it.out = buf(r, g, op.out);
           it.addend = op.addend >= 0 ? buf(r, g, op.addend) : nullptr;
-          it.key = ks[r]->gk[op.pow2];
-          it.galois = (u32)galois_pow2(c, op.pow2);
+          it.key = rotation_key(ks[r], op.step);
+          it.galois = (u32)galois_step(c, op.step);
           lv_items[lv].push_back(it);
         }
     prepare_levels(c, lv_items, st, levels);
@@ -1399,13 +1463,17 @@ int hs_rotate(hs_ctx* c, const hs_keyset* ks, const hs_ctvec* in, int64_t k, voi
       u64* cur = r->d;
       u64* other = tmp.as<u64>();
       std::vector<std::vector<RotItem>> levels;
-      for (int i = 0; i + 1 < c->logn; i++) {
-        if (!((kk >> i) & 1)) continue;
+      std::vector<i64> steps;  // one exact-step key switch, or the binary digits of kk
+      if (!is_pow2(kk) && ks->step_keys.count(kk)) steps.push_back(kk);
+      else
+        for (int i = 0; i + 1 < c->logn; i++)
+          if ((kk >> i) & 1) steps.push_back(1LL << i);
+      for (i64 step : steps) {
         std::vector<RotItem> items;
         for (i64 g = 0; g < in->n; g++) {
           RotItem it{};
           it.in = cur + g * CW; it.out = other + g * CW; it.addend = nullptr;
-          it.key = ks->gk[i]; it.galois = (u32)galois_pow2(c, i);
+          it.key = rotation_key(ks, step); it.galois = (u32)galois_step(c, step);
           items.push_back(it);
         }
         levels.push_back(items);
@@ -1554,7 +1622,7 @@ static void server_tick(hs_server* S) {
     r->wt_base.assign(G, -1);
     int nwt = 0;
     for (int g = 0; g < G; g++) {
-      r->progs[g] = total_sum_program(c, m->chunks[g].h, m->chunks[g].c, nullptr);
+      r->progs[g] = total_sum_program(c, r->ks, m->chunks[g].h, m->chunks[g].c, nullptr);
       if (r->progs[g].size() > 1) { r->wt_base[g] = nwt; nwt += 4; }
     }
     r->vbuf = DBuf(&c->pool, (size_t)std::max(G, 1) * CW * sizeof(u64));
@@ -1605,8 +1673,8 @@ static void server_tick(hs_server* S) {
         it.in = buf(r.get(), (int)g, op.in);
         it.out = buf(r.get(), (int)g, op.out);
         it.addend = op.addend >= 0 ? buf(r.get(), (int)g, op.addend) : nullptr;
-        it.key = r->ks->gk[op.pow2];
-        it.galois = (u32)galois_pow2(c, op.pow2);
+        it.key = rotation_key(r->ks, op.step);
+        it.galois = (u32)galois_step(c, op.step);
         levels[lv].push_back(it);
       }
   while (!levels.empty() && levels.back().empty()) levels.pop_back();

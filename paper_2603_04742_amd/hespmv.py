@@ -48,6 +48,8 @@ SIGNATURES = {
     "hs_keygen": (_int, [_vp, _u64, _vp, _pp]),
     "hs_keyset_destroy": (None, [_vp]),
     "hs_keyset_export": (_int, [_vp, _int, _int, _u64p, _i64]),
+    "hs_keyset_add_rotation_keys": (_int, [_vp, _vp, _i64p, _i64, _vp]),
+    "hs_matrix_rotation_steps": (_int, [_vp, _i64p, _i64, _i64p]),
     "hs_cssc_pack": (_int, [_vp, _i64, _i64, _vp, _vp, _vp, _int, _vp, _u64, _vp, _pp]),
     "hs_matrix_destroy": (None, [_vp]),
     "hs_matrix_info": (_int, [_vp, _i64p, _i64p]),
@@ -184,6 +186,11 @@ class Keyset:
         _check(lib.hs_keyset_export(self.h, which, index, out.ctypes.data_as(_u64p), n))
         return out
 
+    def add_rotation_keys(self, steps):
+        """hs_keyset_add_rotation_keys: exact-step rotation keys for these steps (host ints)."""
+        st = np.ascontiguousarray(np.asarray(steps, np.int64).reshape(-1))
+        _check(lib.hs_keyset_add_rotation_keys(self.ctx.h, self.h, st.ctypes.data_as(_i64p), st.size, _stream()))
+
 
 class CtVec:
     def __init__(self, ctx, h, owner=None):
@@ -252,6 +259,13 @@ class Matrix:
         out = np.zeros(4, np.int64)
         _check(lib.hs_matrix_chunk(self.h, k, out.ctypes.data_as(_i64p)))
         return tuple(int(x) for x in out)
+
+    def rotation_steps(self):
+        n = ctypes.c_int64()
+        lib.hs_matrix_rotation_steps(self.h, None, 0, ctypes.byref(n))
+        out = np.zeros(max(n.value, 1), np.int64)
+        _check(lib.hs_matrix_rotation_steps(self.h, out.ctypes.data_as(_i64p), out.size, ctypes.byref(n)))
+        return [int(x) for x in out[:n.value]]
 
     def column_index(self):
         n = ctypes.c_int64()
