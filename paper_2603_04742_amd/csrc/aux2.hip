@@ -72,17 +72,18 @@ __global__ void k_pack_slots(PackArgs A, int nchunks, const u32* __restrict__ sl
   for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
     const int g = (int)(idx >> logn);
     const i64 k = idx & (n - 1);
-    const i64* cd = A.chunk + 8 * g;
+    const int mode = A.mode == 3 ? (g < A.nG ? 0 : 2) : A.mode;
+    const i64* cd = A.chunk + 8 * (A.mode == 3 && g >= A.nG ? g - A.nG : g);
     const i64 start = cd[0], cols = cd[1], h = cd[2], cpo = cd[3], nzo = cd[4];
     i64 val = 0;
-    if (A.mode == 2) {
+    if (mode == 2) {
       val = (k < h) ? 1 : 0;
     } else if (k < h * cols && k < n / 2) {
       const i64 b = k / h, p = k % h;
       const i64 c0 = A.cp[cpo + start + b], c1 = A.cp[cpo + start + b + 1];
       if (p < c1 - c0) {
         const i64 e = nzo + c0 + p;
-        val = (A.mode == 0) ? A.va[e] : A.v[A.ci[e]];
+        val = (mode == 0) ? A.va[e] : A.v[A.ci[e]];
       }
     }
     A.out[(size_t)g * n + slot_pos[k]] = smod_i64(val, t);

@@ -55,7 +55,8 @@ static void d2h(T* h, const T* d, size_t n, hipStream_t st) {
 // Matrices and ciphertext vectors take their device memory from the context's pool (returned on
 // destroy): hipMalloc/hipFree per object cost tens of microseconds each and hipFree waits for the
 // device.  Every API call that writes such an object synchronises its stream before returning,
-// so memory handed back on destroy is idle.
+// except the plaintext encoding of hs_cssc_pack, which finishes on the context's side stream
+// (M->ready); destroy waits for the whole device, so memory handed back on destroy is idle.
 template <class T>
 static T* pmalloc(hs_ctx* c, size_t n) {
   return (T*)c->pool.get((n ? n : 1) * sizeof(T));
@@ -63,6 +64,27 @@ static T* pmalloc(hs_ctx* c, size_t n) {
 static void pfree(hs_ctx* c, void* p) {
   if (p) c->pool.put(p);
 }
+// Pinned host staging per thread for the structure copies of hs_cssc_pack (pageable copies cost
+// a driver-side staging copy and a wait each).  Every call that uses it synchronises its stream
+// before returning, so a thread's buffer is never in use by two copies at once.  The buffers live
+// until the process ends (freeing pinned memory from thread-exit handlers can run after the HIP
+// runtime has shut down).
+struct PinnedStage {
+  void* p = nullptr;
+  size_t bytes = 0;
+  void* get(size_t n) {
+    if (n > bytes) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      bytes = 0;
+      const size_t want = std::max<size_t>(n + n / 2, 1 << 16);
+      if (hipHostMalloc(&p, want, hipHostMallocDefault) != hipSuccess) throw Error{HS_ENOMEM, "pinned host allocation failed"};
+      bytes = want;
+    }
+    return p;
+  }
+};
+static thread_local PinnedStage t_stage_down, t_stage_up;
 template <class T>
 static T* dmalloc(size_t n) {
   T* p = nullptr;
@@ -446,10 +468,12 @@ static void plain_ntt(hs_ctx* c, const u64* coef, u64* out, int G, hipStream_t s
     launch_plain_ntt(c, coef, out, G, st);
   }
 }
-// Public-key encryption of G encoded plaintexts (samples [G][3][N]: u, e0, e1).
+// Public-key encryption of G encoded plaintexts (samples [G][3][N]: u, e0, e1).  From N = 16384 on
+// the split form (elementwise kernels around one batched transform of all 3 L G limbs) beats the
+// fused kernel, whose workgroups run three whole-limb transforms one after another.
 static void encrypt_coefs(hs_ctx* c, const u64* coef, const int* samples, const u64* pk, u64* out, int G, hipStream_t st,
                           std::vector<DBuf>& hold) {
-  if (use_split(c)) {
+  if (use_split(c) || (c->logn >= 14 && g_opt_aux.load() == 0)) {
     hold.emplace_back(&c->pool, (size_t)G * 3 * c->L * c->N * sizeof(u64));
     u64* prep = hold.back().as<u64>();
     launch_enc_prep(c, coef, samples, G, prep, st);
@@ -484,6 +508,7 @@ int hs_ctx_create(const hs_params* params, hs_ctx** out) {
     c->prm = *params;
     try {
       HS_CHECK_HIP(hipGetDevice(&c->device));
+      HS_CHECK_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
       build_ctx(c);
       HS_REQUIRE(c->dec_words <= 16, HS_EPARAM, "modulus too large for the decryption kernel (at most 16 words)");
       u64 cdt[20];
@@ -660,22 +685,19 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
     const size_t N = c->N;
     const i64 s = (i64)N / 2;
     // --- structure on the host: the sparsity pattern is public (Sec. 3.1)
-    std::vector<i64> rp(rows + 1, 0);
-    if (rows) d2h(rp.data(), row_ptr, rows + 1, st);
-    DBuf bad(&c->pool, sizeof(int));
-    HS_CHECK_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), st));
-    int hbad = 0;
-    HS_CHECK_HIP(hipStreamSynchronize(st));
+    PinnedStage& down = t_stage_down;
+    i64* rp = (i64*)down.get((size_t)(rows + 1) * sizeof(i64) + 256);
+    int* hbad_p = (int*)((char*)rp + (((size_t)(rows + 1) * sizeof(i64) + 255) & ~(size_t)255));
+    *hbad_p = 0;
+    rp[0] = 0;
+    if (rows) {
+      d2h(rp, row_ptr, rows + 1, st);
+      HS_CHECK_HIP(hipStreamSynchronize(st));
+    }
     HS_REQUIRE(rp[0] == 0, HS_EINVAL, "row_ptr[0] must be 0");
     for (i64 i = 0; i < rows; i++) HS_REQUIRE(rp[i + 1] >= rp[i], HS_EINVAL, "row_ptr must be nondecreasing");
     const i64 nnz = rp[rows];
     HS_REQUIRE(nnz == 0 || (col_idx && vals), HS_EINVAL, "null col_idx/vals");
-    // the column check runs on the device and is read back with the final synchronisation (no
-    // kernel below uses a column index as an address)
-    if (nnz) {
-      launch_csr_check(row_ptr, col_idx, rows, cols, bad.as<int>(), st);
-      d2h(&hbad, bad.as<int>(), 1, st);
-    }
     hs_matrix* M = new hs_matrix();
     M->ctx = c; M->R = rows; M->C = cols; M->nnz = nnz; M->encrypted = encrypt_values ? 1 : 0;
     try {
@@ -723,13 +745,10 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         M->parts.push_back(P);
       }
       const int G = (int)M->chunks.size();
-      M->d_cp = pmalloc<i64>(c, M->h_cp.size());
-      M->d_rm = pmalloc<i32>(c, M->h_rm.size());
-      M->d_va = pmalloc<i64>(c, nnz);
-      M->d_ci = pmalloc<i32>(c, nnz);
-      M->d_chunk = pmalloc<i64>(c, 8ULL * std::max(G, 1));
-      h2d(M->d_cp, M->h_cp.data(), M->h_cp.size(), st);
-      h2d(M->d_rm, M->h_rm.data(), M->h_rm.size(), st);
+      const int nP = (int)M->parts.size();
+      // one upload of every structure array (pinned staging, one device allocation):
+      //   cp | rm | chunk table | partition info (row0, rows, nz rows, rm offset) | rank | cp and
+      //   nnz offsets per partition | the column-check flag
       std::vector<i64> cd(8ULL * std::max(G, 1), 0);
       for (int g = 0; g < G; g++) {
         const hs_chunk& k = M->chunks[g];
@@ -737,28 +756,75 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         i64* d = &cd[8ULL * g];
         d[0] = k.start; d[1] = k.c; d[2] = k.h; d[3] = P.cp_off; d[4] = P.nnz_off; d[5] = k.part;
       }
-      h2d(M->d_chunk, cd.data(), cd.size(), st);
+      std::vector<i64> pinfo(4ULL * std::max(nP, 1), 0);
+      for (int p = 0, rm_off = 0; p < nP; p++) {
+        const hs_part& P = M->parts[p];
+        pinfo[4 * p] = P.row0; pinfo[4 * p + 1] = P.rows; pinfo[4 * p + 2] = P.nz_rows; pinfo[4 * p + 3] = rm_off;
+        rm_off += (int)P.rows;
+      }
+      auto seg = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
+      const size_t o_cp = 0, o_rm = o_cp + seg(M->h_cp.size() * 8), o_ch = o_rm + seg(M->h_rm.size() * 4 + 4),
+                   o_pi = o_ch + seg(cd.size() * 8), o_rk = o_pi + seg(pinfo.size() * 8), o_po = o_rk + seg(rank.size() * 4),
+                   o_no = o_po + seg(part_cp_off.size() * 8 + 8), o_bad = o_no + seg(part_nnz_off.size() * 8 + 8),
+                   total = o_bad + 256;
+      char* up = (char*)t_stage_up.get(total);
+      auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(up + off, src, bytes); };
+      put(o_cp, M->h_cp.data(), M->h_cp.size() * 8);
+      put(o_rm, M->h_rm.data(), M->h_rm.size() * 4);
+      put(o_ch, cd.data(), cd.size() * 8);
+      put(o_pi, pinfo.data(), pinfo.size() * 8);
+      put(o_rk, rank.data(), rank.size() * 4);
+      put(o_po, part_cp_off.data(), part_cp_off.size() * 8);
+      put(o_no, part_nnz_off.data(), part_nnz_off.size() * 8);
+      std::memset(up + o_bad, 0, 256);
+      M->d_struct = pmalloc<char>(c, total);
+      HS_CHECK_HIP(hipMemcpyAsync(M->d_struct, up, total, hipMemcpyHostToDevice, st));
+      M->d_cp = (i64*)(M->d_struct + o_cp);
+      M->d_rm = (i32*)(M->d_struct + o_rm);
+      M->d_chunk = (i64*)(M->d_struct + o_ch);
+      M->d_pinfo = (i64*)(M->d_struct + o_pi);
+      int* dbad = (int*)(M->d_struct + o_bad);
+      M->d_va = pmalloc<i64>(c, nnz);
+      M->d_ci = pmalloc<i32>(c, nnz);
+      // the column check runs on the device and is read back with the final synchronisation (no
+      // kernel below uses a column index as an address)
+      if (nnz) {
+        launch_csr_check(row_ptr, col_idx, rows, cols, dbad, st);
+        d2h(hbad_p, dbad, 1, st);
+      }
+      if (rows && nnz)
+        launch_cssc_scatter(row_ptr, col_idx, vals, (const int*)(M->d_struct + o_rk), M->d_cp, (const i64*)(M->d_struct + o_po),
+                            (const i64*)(M->d_struct + o_no), rows, s, M->d_va, M->d_ci, st);
       std::vector<DBuf> keep;  // scratch released only after the final synchronisation
       keep.reserve(8);         // references into it stay valid
-      if (rows && nnz) {
-        keep.emplace_back(&c->pool, rows * sizeof(int));
-        keep.emplace_back(&c->pool, part_cp_off.size() * sizeof(i64));
-        keep.emplace_back(&c->pool, part_nnz_off.size() * sizeof(i64));
-        DBuf &drank = keep[0], &dpco = keep[1], &dpno = keep[2];
-        h2d(drank.as<int>(), rank.data(), rows, st);
-        h2d(dpco.as<i64>(), part_cp_off.data(), part_cp_off.size(), st);
-        h2d(dpno.as<i64>(), part_nnz_off.data(), part_nnz_off.size(), st);
-        launch_cssc_scatter(row_ptr, col_idx, vals, drank.as<int>(), M->d_cp, dpco.as<i64>(), dpno.as<i64>(), rows, s, M->d_va,
-                            M->d_ci, st);
-      }
+      const int hbad_dummy = 0;
+      const int& hbad = nnz ? *hbad_p : hbad_dummy;
       // --- pack + encode (+ encrypt) every chunk; masks
       std::vector<DBuf> hold;
-      if (G) {
+      const bool masks = c->prm.agg_mode == 0;
+      if (G && !encrypt_values && !use_split(c)) {
+        // plaintexts and masks in one pass each, on the side stream after the structure is final:
+        // the encoding overlaps the caller's next work (the vector's encryption); consumers wait
+        // for M->ready.  Every buffer it touches belongs to M until hs_matrix_destroy.
+        const int np = masks ? 2 * G : G;
+        M->d_coef = pmalloc<u64>(c, (size_t)np * N);
+        M->d_pt = pmalloc<u64>(c, (size_t)np * c->L * N);
+        if (masks) { M->d_mask = M->d_pt + (size_t)G * c->L * N; M->mask_in_pt = true; }
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+        HS_REQUIRE(!hbad, HS_EINVAL, "column indices out of range or not strictly ascending within a row");
+        HS_CHECK_HIP(hipEventCreateWithFlags(&M->ready, hipEventDisableTiming));
+        PackArgs pa{};
+        pa.va = M->d_va; pa.ci = M->d_ci; pa.v = nullptr; pa.cp = M->d_cp; pa.chunk = M->d_chunk;
+        pa.out = M->d_coef; pa.mode = masks ? 3 : 0; pa.nG = G;
+        launch_pack_encode(c, pa, np, c->side);
+        launch_plain_ntt(c, M->d_coef, M->d_pt, np, c->side);
+        HS_CHECK_HIP(hipEventRecord(M->ready, c->side));
+      } else if (G) {
         keep.emplace_back(&c->pool, (size_t)G * N * sizeof(u64));
         DBuf& coef = keep.back();
         PackArgs pa{};
         pa.va = M->d_va; pa.ci = M->d_ci; pa.v = nullptr; pa.cp = M->d_cp; pa.chunk = M->d_chunk;
-        pa.out = coef.as<u64>(); pa.mode = 0;
+        pa.out = coef.as<u64>(); pa.mode = 0; pa.nG = G;
         pack_encode(c, pa, G, st, hold);
         if (encrypt_values) {
           M->d_pt = pmalloc<u64>(c, (size_t)G * ct_words(c));
@@ -772,7 +838,7 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
           M->d_pt = pmalloc<u64>(c, (size_t)G * c->L * N);
           plain_ntt(c, coef.as<u64>(), M->d_pt, G, st, hold);
         }
-        if (c->prm.agg_mode == 0) {
+        if (masks) {
           pa.mode = 2;
           pack_encode(c, pa, G, st, hold);
           M->d_mask = pmalloc<u64>(c, (size_t)G * c->L * N);
@@ -795,8 +861,9 @@ void hs_matrix_destroy(hs_matrix* m) {
   // the memory returns to the context's pool, from which work on any stream may take it next:
   // wait for the device so no operation still in flight (an asynchronous call) uses it
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {m->d_cp, m->d_rm, m->d_va, m->d_ci, m->d_chunk, m->d_pt, m->d_mask};
+  void* ptrs[] = {m->d_struct, m->d_va, m->d_ci, m->d_pt, m->mask_in_pt ? nullptr : m->d_mask, m->d_coef};
   for (void* p : ptrs) pfree(m->ctx, p);
+  if (m->ready) (void)hipEventDestroy(m->ready);
   delete m;
 }
 
@@ -842,6 +909,7 @@ int hs_matrix_export(const hs_matrix* m, int which, int64_t k, uint64_t* host_ou
       src = m->d_mask + k * n;
     }
     HS_REQUIRE((size_t)cap >= n, HS_ECAPACITY, "output too small");
+    if (m->ready) HS_CHECK_HIP(hipEventSynchronize(m->ready));
     HS_CHECK_HIP(hipMemcpy(host_out, src, n * sizeof(u64), hipMemcpyDeviceToHost));
   });
 }
@@ -915,6 +983,8 @@ struct BatchWork {
     std::vector<Req> rq(n);
     int nlog = 0;
     keep.reserve(2 * (size_t)n + 3 * (size_t)n + 1);
+    for (int r = 0; r < n; r++)  // plaintexts still being encoded on the side stream
+      if (m[r]->ready) HS_CHECK_HIP(hipStreamWaitEvent(st, m[r]->ready, 0));
     for (int r = 0; r < n; r++) {
       Req& q = rq[r];
       q.G = (int)m[r]->chunks.size();
@@ -1325,20 +1395,11 @@ int hs_decrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const hs_ctve
       launch_dec_phase(c, y->d, ks->sk, X.as<u64>(), nP, st);
     }
     launch_dec_round(c, X.as<u64>(), Mc.as<u64>(), nP, st);
-    std::vector<i64> pinfo(4ULL * nP);
-    i64 rm_off = 0;
-    for (int p = 0; p < nP; p++) {
-      const hs_part& P = m->parts[p];
-      pinfo[4 * p] = P.row0; pinfo[4 * p + 1] = P.rows; pinfo[4 * p + 2] = P.nz_rows; pinfo[4 * p + 3] = rm_off;
-      rm_off += P.rows;
-    }
-    DBuf dp(&c->pool, pinfo.size() * sizeof(i64));
-    h2d(dp.as<i64>(), pinfo.data(), pinfo.size(), st);
     if (split) {
       ntt_any(c, Mc.as<u64>(), nP, 1, c->n_mod, 0, st, hold);
-      launch_slots_scatter(c, Mc.as<u64>(), m->d_rm, dp.as<i64>(), nP, out, st);
+      launch_slots_scatter(c, Mc.as<u64>(), m->d_rm, m->d_pinfo, nP, out, st);
     } else {
-      launch_decode_scatter(c, Mc.as<u64>(), m->d_rm, dp.as<i64>(), out, nP, st);
+      launch_decode_scatter(c, Mc.as<u64>(), m->d_rm, m->d_pinfo, out, nP, st);
     }
     HS_CHECK_HIP(hipStreamSynchronize(st));
   });
@@ -1629,6 +1690,7 @@ static void server_tick(hs_server* S) {
     r->wtbuf = DBuf(&c->pool, (size_t)std::max(nwt, 1) * CW * sizeof(u64));
     r->y = new_ctvec(c, (i64)m->parts.size());
     if (!G) continue;
+    if (m->ready) HS_CHECK_HIP(hipStreamWaitEvent(S->st, m->ready, 0));
     if (m->encrypted) {
       for (int g = 0; g < G; g++) {
         pa.push_back(m->d_pt + (size_t)g * CW);

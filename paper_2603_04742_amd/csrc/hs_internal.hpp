@@ -132,6 +132,9 @@ struct hs_ctx {
   hs::u64* d_t_mu = nullptr;
   double2* d_t_r64 = nullptr;
   hs::Pool pool;
+  // stream of the matrix plaintext encoding, which runs after hs_cssc_pack returns (default
+  // priority, non-blocking); each matrix records an event on it when its plaintexts are ready
+  hipStream_t side = nullptr;
   // launch choices set by hs_autotune (results do not depend on them):
   //   xf_variant 0: compile-time / half-limb transforms, 1: runtime radix-8 / whole-limb, for the
   //   key-switch kernels; xf_variant_ntt the same for the plain transform kernels (NTT, plaintext
@@ -177,13 +180,18 @@ struct hs_matrix {
   std::vector<hs_chunk> chunks;
   std::vector<hs::i64> h_cp;     // all partitions' CP arrays, concatenated
   std::vector<hs::i32> h_rm;     // row map per partition (local rows), concatenated = R entries
+  char* d_struct = nullptr;      // one allocation: d_cp, d_rm, d_chunk, d_pinfo and upload scratch
   hs::i64* d_cp = nullptr;
   hs::i32* d_rm = nullptr;
+  hs::i64* d_pinfo = nullptr;    // per partition: (row0, rows, nonzero rows, row-map offset)
   hs::i64* d_va = nullptr;       // CSSC values (nnz)
   hs::i32* d_ci = nullptr;       // CSSC column indices (nnz)
   hs::i64* d_chunk = nullptr;    // per chunk: (start, c, h, cp_off) for device kernels
   hs::u64* d_pt = nullptr;       // per chunk: plaintext [L][N] or ciphertext [2][L][N]
   hs::u64* d_mask = nullptr;     // per chunk: mask plaintext [L][N] (paper aggregation)
+  bool mask_in_pt = false;       // d_mask points into the d_pt allocation
+  hs::u64* d_coef = nullptr;     // mod-t coefficients of the deferred encoding (kept until destroy)
+  hipEvent_t ready = nullptr;    // recorded on the context's side stream when d_pt/d_mask are final
 };
 
 struct hs_ctvec {

@@ -227,14 +227,15 @@ __global__ void __launch_bounds__(NT) k_pack_encode(PackArgs A, const u32* __res
   SMEM();
   const int n = 1 << logn;
   const int g = blockIdx.x;
-  const i64* cd = A.chunk + 8 * g;  // (start, c, h, cp_off, nnz_off, part, -, -)
+  const int mode = A.mode == 3 ? (g < A.nG ? 0 : 2) : A.mode;
+  const i64* cd = A.chunk + 8 * (A.mode == 3 && g >= A.nG ? g - A.nG : g);  // (start, c, h, cp_off, nnz_off, part, -, -)
   const i64 start = cd[0], cols = cd[1], h = cd[2], cpo = cd[3], nzo = cd[4];
   const ModTab t = tab[tmod];
   const ModD m = mod_of(t);
   const i64 tq = (i64)t.q;
   for (int k = threadIdx.x; k < n; k += NT) {
     i64 val = 0;
-    if (A.mode == 2) {
+    if (mode == 2) {
       val = (k < h) ? 1 : 0;
     } else if (k < h * cols && k < n / 2) {
       {
@@ -242,7 +243,7 @@ __global__ void __launch_bounds__(NT) k_pack_encode(PackArgs A, const u32* __res
         const i64 c0 = A.cp[cpo + start + b], c1 = A.cp[cpo + start + b + 1];
         if (p < c1 - c0) {
           const i64 e = nzo + c0 + p;
-          val = (A.mode == 0) ? A.va[e] : A.v[A.ci[e]];
+          val = (mode == 0) ? A.va[e] : A.v[A.ci[e]];
         }
       }
     }

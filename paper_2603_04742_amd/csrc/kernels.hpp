@@ -37,7 +37,9 @@ struct PackArgs {
   const i64* cp;             // CSSC column pointers of the whole matrix
   const i64* chunk;          // per chunk 8 words: (start, c, h, cp_off, nnz_off, part, 0, 0)
   u64* out;                  // [nchunks][N] coefficients mod t
-  int mode;                  // 0 matrix values, 1 reorganised vector, 2 mask
+  int mode;                  // 0 matrix values, 1 reorganised vector, 2 mask,
+                             // 3 matrix values for plaintexts g < nG, mask of chunk g - nG after
+  int nG;                    // chunks (mode 3)
 };
 
 // Constants of the exact ciphertext product (tensor.hip); device pointers.

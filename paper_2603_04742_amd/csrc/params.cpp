@@ -378,6 +378,11 @@ void free_ctx(hs_ctx* c) {
                   c->d_t_halfq, c->d_t_mhat_inv, c->d_t_mhat, c->d_t_m, c->d_t_halfm, c->d_t_d, c->d_t_mu, c->d_t_r64};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+    c->side = nullptr;
+  }
   c->pool.release_all();
 }
 
