@@ -1043,26 +1043,35 @@ struct BatchWork {
     counters[0] += levels.key_switches;
     counters[2] += levels.launches;
     counters[1] = nlog;
-    // 3. masks and the per-partition sums
+    // 3. masks and the per-partition sums; the argument arrays of every request in one upload:
+    //    per request [chunk result pointers (G, at least 1)][first chunk per partition][chunks
+    //    per partition], 8-byte words
+    std::vector<u64> words;
+    std::vector<size_t> at(n, 0);
     for (int r = 0; r < n; r++) {
       Req& q = rq[r];
+      at[r] = words.size();
       if (!q.nP) continue;
-      std::vector<const u64*> wp(std::max(q.G, 1), nullptr);
-      for (int g = 0; g < q.G; g++) wp[g] = buf(r, g, q.progs[g].back().in);
-      std::vector<int> pc0(q.nP), pnc(q.nP);
-      for (int p = 0; p < q.nP; p++) { pc0[p] = m[r]->parts[p].chunk0; pnc[p] = m[r]->parts[p].nchunks; }
-      keep.emplace_back(&c->pool, wp.size() * sizeof(u64*));
-      const u64* const* dwp = keep.back().as<const u64*>();
-      h2d(keep.back().as<const u64*>(), wp.data(), wp.size(), st);
-      keep.emplace_back(&c->pool, q.nP * sizeof(int));
-      const int* dpc0 = keep.back().as<int>();
-      h2d(keep.back().as<int>(), pc0.data(), q.nP, st);
-      keep.emplace_back(&c->pool, q.nP * sizeof(int));
-      const int* dpnc = keep.back().as<int>();
-      h2d(keep.back().as<int>(), pnc.data(), q.nP, st);
-      masks.push_back(Mask{dwp, c->prm.agg_mode == 0 ? m[r]->d_mask : nullptr, dpc0, dpnc, y[r]->d, q.nP});
-      counters[2]++;
-      counters[4] += c->prm.agg_mode == 0 ? q.G : 0;
+      for (int g = 0; g < std::max(q.G, 1); g++) words.push_back(g < q.G ? (u64)(uintptr_t)buf(r, g, q.progs[g].back().in) : 0);
+      std::vector<int> pcn(2 * (size_t)q.nP);
+      for (int p = 0; p < q.nP; p++) { pcn[p] = m[r]->parts[p].chunk0; pcn[q.nP + p] = m[r]->parts[p].nchunks; }
+      const size_t w0 = words.size();
+      words.resize(w0 + (pcn.size() * sizeof(int) + 7) / 8, 0);
+      std::memcpy(words.data() + w0, pcn.data(), pcn.size() * sizeof(int));
+    }
+    if (!words.empty()) {
+      keep.emplace_back(&c->pool, words.size() * sizeof(u64));
+      u64* dw = keep.back().as<u64>();
+      h2d(dw, words.data(), words.size(), st);
+      for (int r = 0; r < n; r++) {
+        Req& q = rq[r];
+        if (!q.nP) continue;
+        const u64* const* dwp = (const u64* const*)(dw + at[r]);
+        const int* dpc0 = (const int*)(dw + at[r] + std::max(q.G, 1));
+        masks.push_back(Mask{dwp, c->prm.agg_mode == 0 ? m[r]->d_mask : nullptr, dpc0, dpc0 + q.nP, y[r]->d, q.nP});
+        counters[2]++;
+        counters[4] += c->prm.agg_mode == 0 ? q.G : 0;
+      }
     }
   }
 
