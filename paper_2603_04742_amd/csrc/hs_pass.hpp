@@ -120,31 +120,67 @@ __device__ __forceinline__ int tw_lds_index(const GT& G, int blk, int st, int gt
   }
 }
 
+// Global memory through address-space-1 pointers: such a load cannot alias LDS, so the compiler
+// issues a workgroup's loads together ahead of the LDS stores that consume them instead of
+// waiting for each one in turn (a flat pointer could point into LDS).
+template <class T>
+__device__ __forceinline__ T gld(const T* p) { return *(const T __attribute__((address_space(1)))*)p; }
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v) { *(T __attribute__((address_space(1)))*)p = v; }
+
+// LDS twiddle slots of a pass: high passes use slots [0, 2^S) = table entries [0, 2^S); the
+// stage ranges of a low pass are adjacent, [(2^k - 1) GB, (2^(k+1) - 1) GB) for forward stage
+// S + k and [(2^nl - 2^(d+1)) GB, (2^nl - 2^d) GB) for inverse stage nl - 1 - d (nl = logn - S).
+template <bool HIGH, class GT>
+__host__ __device__ inline int tw_slots(const GT& G) {
+  return HIGH ? (1 << G.S) : (((1 << (G.logn - G.S)) - 1) << G.lgb_low());
+}
+// Table index of slot L (the inverse of tw_lds_index over the slots in use).
+template <bool HIGH, bool FWD, class GT>
+__host__ __device__ inline int tw_src_index(const GT& G, int blk, int L) {
+  if (HIGH) return L;
+  const int lgb = G.lgb_low(), nl = G.logn - G.S;
+  const int q = L >> lgb;
+  if (FWD) {
+    const int k = 31 - __builtin_clz((unsigned)(q + 1));
+    return (1 << (G.S + k)) + (blk << (lgb + k)) + (L - (((1 << k) - 1) << lgb));
+  }
+  const int d = 31 - __builtin_clz((unsigned)((1 << nl) - q - 1));
+  const int st = nl - 1 - d;
+  return ((1 << G.logn) >> (st + 1)) + (blk << (lgb + d)) + (L - (((1 << nl) - (2 << d)) << lgb));
+}
+
+// A pass's twiddles held in registers: load() issues every global load at once (early in a
+// kernel, so their latency overlaps the data loads), store() writes them to the LDS slots.
+template <int NT, bool HIGH, bool FWD, class GT>
+struct TwPre {
+  static constexpr int kSlotsMax = HIGH ? cmin(GT::kMaxBE, 256) : GT::kMaxBE;  // 2^S <= 256 for logn <= 16
+  static constexpr int kPer = (kSlotsMax + NT - 1) / NT;
+  double2 v[kPer];
+  __device__ __forceinline__ void load(const GT& G, int blk, const double2* __restrict__ tw) {
+    const int total = tw_slots<HIGH>(G);
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+      const int L = threadIdx.x + r * NT;
+      if (L < total) v[r] = ldtw(tw, tw_src_index<HIGH, FWD>(G, blk, L));
+    }
+  }
+  __device__ __forceinline__ void store(double2* twl, const GT& G) const {
+    const int total = tw_slots<HIGH>(G);
+#pragma unroll
+    for (int r = 0; r < kPer; r++) {
+      const int L = threadIdx.x + r * NT;
+      if (L < total) twl[L] = v[r];
+    }
+  }
+};
+
 // Copy the pass's twiddles to twl (cooperative; the caller synchronises afterwards).
 template <int NT, bool HIGH, bool FWD, class GT>
 __device__ __forceinline__ void stage_twiddles(double2* twl, const GT& G, int blk, const double2* __restrict__ tw) {
-  if (HIGH) {
-    for (int i = threadIdx.x; i < (1 << G.S); i += NT) twl[i] = tw[i];
-    return;
-  }
-  const int lgb = G.lgb_low();
-  const int nl = G.logn - G.S;
-  for (int k = 0; k < nl; k++) {
-    int st, base, cnt, off;
-    if (FWD) {
-      st = G.S + k;
-      cnt = 1 << (lgb + k);
-      base = (1 << st) + (blk << (lgb + k));
-      off = ((1 << k) - 1) << lgb;
-    } else {
-      st = k;
-      const int d = nl - st - 1;
-      cnt = 1 << (lgb + d);
-      base = ((1 << G.logn) >> (st + 1)) + (blk << (lgb + d));
-      off = ((1 << nl) - (2 << d)) << lgb;
-    }
-    for (int i = threadIdx.x; i < cnt; i += NT) twl[off + i] = tw[base + i];
-  }
+  TwPre<NT, HIGH, FWD, GT> p;
+  p.load(G, blk, tw);
+  p.store(twl, G);
 }
 
 // One register round of a group transform: group bits [lo, lo + nb) of the global index (lo = 0

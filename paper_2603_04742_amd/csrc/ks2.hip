@@ -28,8 +28,6 @@ namespace hs {
   double2* twl = (double2*)smem_raw;              \
   double* smem = smem_raw + 2 * (TWN)
 #define SMEM2(G) SMEM2_N(G, (G).BE)
-// kernels that only run high passes stage 2^S twiddles
-#define SMEM2_HIGH(G) SMEM2_N(G, 1 << (G).S)
 
 __device__ __forceinline__ ModD mod_of2(const ModTab& t) { return ModD{t.q, t.qinv}; }
 
@@ -46,22 +44,37 @@ __device__ __forceinline__ u32 galois_index2(u32 k, u32 g, int logn) {
 template <int NT, bool HIGH, bool FWD, class GT>
 __device__ __forceinline__ void ntt_pass_body(double* smem, double2* twl, const void* in, int in_u64, void* out, int out_u64, int nl, int mod0,
                                               int scale, const ModTab* __restrict__ tab, GT G) {
+  constexpr int PER = (GT::kMaxBE + NT - 1) / NT;
   const int n = 1 << G.logn;
   const int blk = blockIdx.x, row = blockIdx.y;
   const ModTab tb = tab[mod0 + row % nl];
   const ModD m = mod_of2(tb);
   const size_t base = (size_t)row * n;
-  for (int e = threadIdx.x; e < G.BE; e += NT) {
-    const int gi = gidx_of_lds<HIGH>(G, blk, e);
-    smem[lpadx<HIGH>(e)] = in_u64 ? u2d(((const u64*)in)[base + gi]) : ((const double*)in)[base + gi];
+  // every global load first (twiddles and the block), then the LDS stores
+  TwPre<NT, HIGH, FWD, GT> tw;
+  tw.load(G, blk, FWD ? tb.fw : tb.iv);
+  double x[PER];
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    const int e = threadIdx.x + r * NT;
+    if (e < G.BE) {
+      const int gi = gidx_of_lds<HIGH>(G, blk, e);
+      x[r] = in_u64 ? u2d(gld((const u64*)in + base + gi)) : gld((const double*)in + base + gi);
+    }
+  }
+  tw.store(twl, G);
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    const int e = threadIdx.x + r * NT;
+    if (e < G.BE) smem[lpadx<HIGH>(e)] = x[r];
   }
   __syncthreads();
-  if (FWD) pass_fwd<NT, HIGH>(smem, twl, G, blk, tb.fw, m);
-  else pass_inv<NT, HIGH>(smem, twl, G, blk, scale != 0, tb.iv, tb.ninv, m);
+  if (FWD) pass_fwd<NT, HIGH>(smem, twl, G, blk, tb.fw, m, false);
+  else pass_inv<NT, HIGH>(smem, twl, G, blk, scale != 0, tb.iv, tb.ninv, m, false);
   for (int e = threadIdx.x; e < G.BE; e += NT) {
     const int gi = gidx_of_lds<HIGH>(G, blk, e);
-    if (out_u64) ((u64*)out)[base + gi] = d2u(canon(smem[lpadx<HIGH>(e)], m));
-    else ((double*)out)[base + gi] = smem[lpadx<HIGH>(e)];
+    if (out_u64) gst((u64*)out + base + gi, d2u(canon(smem[lpadx<HIGH>(e)], m)));
+    else gst((double*)out + base + gi, smem[lpadx<HIGH>(e)]);
   }
 }
 
@@ -81,20 +94,32 @@ HS2_PASS_KERNEL(k2_ntt_pass_hi, true, false)
 template <int NT, class GT>
 __global__ void __launch_bounds__(NT) k2_rot_intt_low(const RotItem* __restrict__ items, double* T1, int L, const ModTab* __restrict__ tab, GT G) {
   SMEM2(G);
+  constexpr int PER = (GT::kMaxBE + NT - 1) / NT;
   const int n = 1 << G.logn;
   const int blk = blockIdx.x, l = blockIdx.y, b = blockIdx.z;
   const RotItem it = items[b];
   const ModTab tb = tab[l];
   const ModD m = mod_of2(tb);
+  // every global load first (twiddles and the gathered block), then the LDS stores
+  TwPre<NT, false, false, GT> tw;
+  tw.load(G, blk, tb.iv);
   const u64* c1 = it.in + ((size_t)L + l) * n;
-  for (int e = threadIdx.x; e < G.BE; e += NT) {
-    const int gi = gidx_of_lds<false>(G, blk, e);
-    smem[lpad(e)] = u2d(c1[galois_index2((u32)gi, it.galois, G.logn)]);
+  u64 x[PER];
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    const int e = threadIdx.x + r * NT;
+    if (e < G.BE) x[r] = gld(c1 + galois_index2((u32)gidx_of_lds<false>(G, blk, e), it.galois, G.logn));
+  }
+  tw.store(twl, G);
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    const int e = threadIdx.x + r * NT;
+    if (e < G.BE) smem[lpad(e)] = u2d(x[r]);
   }
   __syncthreads();
-  pass_inv<NT, false>(smem, twl, G, blk, false, tb.iv, tb.ninv, m);
+  pass_inv<NT, false>(smem, twl, G, blk, false, tb.iv, tb.ninv, m, false);
   double* o = T1 + ((size_t)b * L + l) * n;
-  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<false>(G, blk, e)] = smem[lpad(e)];
+  for (int e = threadIdx.x; e < G.BE; e += NT) gst(o + gidx_of_lds<false>(G, blk, e), smem[lpad(e)]);
 }
 
 // grid (nblk, dnum * (L + K), B): digit j = y / (L+K), target modulus mi = y % (L+K) (own limbs of
@@ -103,25 +128,55 @@ __global__ void __launch_bounds__(NT) k2_rot_intt_low(const RotItem* __restrict_
 template <int NT, class GT>
 __global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T1, double* E, KsShape S, const double2* __restrict__ up_inv,
                                                     const double2* __restrict__ up_hat, const ModTab* __restrict__ tab, GT G) {
-  SMEM2_HIGH(G);
+  SMEM();
+  constexpr int AMAX = 4;  // source primes per digit whose twiddles are prefetched (more: staged late)
+  constexpr int PER = (GT::kMaxBE + NT - 1) / NT;
   const int n = 1 << G.logn;
   const int LK = S.L + S.K;
   const int blk = blockIdx.x, j = blockIdx.y / LK, mi = blockIdx.y % LK, b = blockIdx.z;
   const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha), na = hi - lo;
   if (mi >= lo && mi < hi) return;
+  // LDS: [alpha + 1 twiddle tables of 2^S][alpha + 1 blocks]: table a < na inverts source a, table
+  // alpha is the target's forward pass; block a holds source a, block alpha the target
+  const int TWH = 1 << G.S;
+  double2* twl = (double2*)smem_raw;
+  double* smem = smem_raw + 2 * (size_t)(S.alpha + 1) * TWH;
   const int LB = lds_doubles(G.BE);
-  double* work = smem + (size_t)na * LB;
+  double* work = smem + (size_t)S.alpha * LB;
+  const ModTab tm = tab[mi];
+  const ModD mm = mod_of2(tm);
+  TwPre<NT, true, true, GT> twf;
+  twf.load(G, blk, tm.fw);
+  TwPre<NT, true, false, GT> twi[AMAX];
+#pragma unroll
+  for (int a = 0; a < AMAX; a++)
+    if (a < na) twi[a].load(G, blk, tab[lo + a].iv);
   for (int a = 0; a < na; a++) {
-    double* buf = smem + (size_t)a * LB;
     const double* src = T1 + ((size_t)b * S.L + lo + a) * n;
-    for (int e = threadIdx.x; e < G.BE; e += NT) buf[lpadx<true>(e)] = src[gidx_of_lds<true>(G, blk, e)];
+    double x[PER];
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+      const int e = threadIdx.x + r * NT;
+      if (e < G.BE) x[r] = gld(src + gidx_of_lds<true>(G, blk, e));
+    }
+    double* buf = smem + (size_t)a * LB;
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+      const int e = threadIdx.x + r * NT;
+      if (e < G.BE) buf[lpadx<true>(e)] = x[r];
+    }
   }
+  twf.store(twl + (size_t)S.alpha * TWH, G);
+#pragma unroll
+  for (int a = 0; a < AMAX; a++)
+    if (a < na) twi[a].store(twl + (size_t)a * TWH, G);
+  for (int a = AMAX; a < na; a++) stage_twiddles<NT, true, false>(twl + (size_t)a * TWH, G, blk, tab[lo + a].iv);
   __syncthreads();
   for (int a = 0; a < na; a++) {
     const ModTab ta = tab[lo + a];
     const ModD ma = mod_of2(ta);
     double* buf = smem + (size_t)a * LB;
-    pass_inv<NT, true>(buf, twl, G, blk, true, ta.iv, ta.ninv, ma);
+    pass_inv<NT, true>(buf, twl + (size_t)a * TWH, G, blk, true, ta.iv, ta.ninv, ma, false);
     for (int e = threadIdx.x; e < G.BE; e += NT) {
       double x = canon(buf[lpadx<true>(e)], ma);
       if (na > 1) {
@@ -132,8 +187,6 @@ __global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T
     }
   }
   __syncthreads();
-  const ModTab tm = tab[mi];
-  const ModD mm = mod_of2(tm);
   for (int e = threadIdx.x; e < G.BE; e += NT) {
     double acc = 0.0;
     for (int a = 0; a < na; a++) {
@@ -148,9 +201,9 @@ __global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T
     work[lpadx<true>(e)] = acc;
   }
   __syncthreads();
-  pass_fwd<NT, true>(work, twl, G, blk, tm.fw, mm);
+  pass_fwd<NT, true>(work, twl + (size_t)S.alpha * TWH, G, blk, tm.fw, mm, false);
   double* o = E + (((size_t)b * S.dnum + j) * LK + mi) * n;
-  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<true>(G, blk, e)] = work[lpadx<true>(e)];
+  for (int e = threadIdx.x; e < G.BE; e += NT) gst(o + gidx_of_lds<true>(G, blk, e), work[lpadx<true>(e)]);
 }
 
 // grid (nblk, L + K, B).  The next digit's block is loaded into registers while the current one
@@ -270,30 +323,38 @@ __global__ void __launch_bounds__(NT) k2_ip_par(const RotItem* __restrict__ item
   const ModTab tm = tab[mi];
   const ModD m = mod_of2(tm);
   const int jown = special ? -1 : mi / S.alpha;
-  // the key-switching key words of this thread's elements are loaded first: their latency then
-  // overlaps the staging and the transforms (a special-prime workgroup needs one key part)
-  u64 kbv[PER][DMAX], kav[PER][DMAX];
+  // Every global load is issued before the first wait, without branches: the key words (a
+  // special-prime workgroup reads its one key part into both sets), the digit blocks and the
+  // twiddles of the forward (and, for the special primes, inverse) low pass.  Digits beyond dnum
+  // and elements beyond the block (runtime geometry) read valid words that are ignored.
+  const int p0 = special ? wsel : 0, p1 = special ? wsel : 1;
+  TwPre<NT, false, true, GT> twf;
+  twf.load(G, blk, tm.fw);
+  u64 kbv[PER][DMAX], kav[PER][DMAX], xv[PER][DMAX];  // raw words: converted after the loads
+  const u64* c1 = it.in + ((size_t)S.L + mi) * n;
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int e = threadIdx.x + k * NT;
-    const int gi = e < G.BE ? gidx_of_lds<false>(G, blk, e) : 0;
+    const int gi = gidx_of_lds<false>(G, blk, e < G.BE ? e : 0);
 #pragma unroll
     for (int j = 0; j < DMAX; j++) {
-      kbv[k][j] = 0;
-      kav[k][j] = 0;
-      if (j < S.dnum && e < G.BE) {
-        if (!special || wsel == 0) kbv[k][j] = it.key[(((size_t)0 * S.dnum + j) * LK + mi) * n + gi];
-        if (!special || wsel == 1) kav[k][j] = it.key[(((size_t)1 * S.dnum + j) * LK + mi) * n + gi];
-      }
+      const int jj = j < S.dnum ? j : 0;
+      kbv[k][j] = gld(it.key + (((size_t)p0 * S.dnum + jj) * LK + mi) * n + gi);
+      kav[k][j] = gld(it.key + (((size_t)p1 * S.dnum + jj) * LK + mi) * n + gi);
+      const u64* src = (jj == jown) ? c1 + galois_index2((u32)gi, it.galois, G.logn)
+                                    : (const u64*)(E + (((size_t)b * S.dnum + jj) * LK + mi) * n + gi);
+      xv[k][j] = gld(src);
     }
   }
-  stage_twiddles<NT, false, true>(twl, G, blk, tm.fw);
-  const u64* c1 = it.in + ((size_t)S.L + mi) * n;
-  for (int t = threadIdx.x; t < (S.dnum << G.lbe); t += NT) {
-    const int j = t >> G.lbe, e = t & (G.BE - 1);
-    const int gi = gidx_of_lds<false>(G, blk, e);
-    smem[(size_t)j * LB + lpad(e)] = (j == jown) ? u2d(c1[galois_index2((u32)gi, it.galois, G.logn)])
-                                                 : E[(((size_t)b * S.dnum + j) * LK + mi) * n + gi];
+  TwPre<NT, false, false, GT> twi;
+  if (special) twi.load(G, blk, tm.iv);
+  twf.store(twl, G);
+#pragma unroll
+  for (int k = 0; k < PER; k++) {
+    const int e = threadIdx.x + k * NT;
+#pragma unroll
+    for (int j = 0; j < DMAX; j++)
+      if (j < S.dnum && e < G.BE) smem[(size_t)j * LB + lpad(e)] = (j == jown) ? u2d(xv[k][j]) : __longlong_as_double((long long)xv[k][j]);
   }
   __syncthreads();
   pass_fwd_multi<NT, false>(smem, LB, S.dnum, jown >= 0 ? (1u << jown) : 0u, twl, G, blk, m);
@@ -301,41 +362,35 @@ __global__ void __launch_bounds__(NT) k2_ip_par(const RotItem* __restrict__ item
 #pragma unroll
   for (int k = 0; k < PER; k++) {
     const int e = threadIdx.x + k * NT;
-    r0[k] = 0.0;
-    r1[k] = 0.0;
-    if (e < G.BE) {
-      double a0 = 0.0, a1 = 0.0;
+    double a0 = 0.0, a1 = 0.0;
 #pragma unroll
-      for (int j = 0; j < DMAX; j++) {
-        if (j < S.dnum) {
-          const double x = smem[(size_t)j * LB + lpad(e)];
-          if (!special || wsel == 0) a0 += mulmod(x, u2d(kbv[k][j]), m);
-          if (!special || wsel == 1) a1 += mulmod(x, u2d(kav[k][j]), m);
-          if ((j & 3) == 3) { a0 = reduce(a0, m); a1 = reduce(a1, m); }
-        }
+    for (int j = 0; j < DMAX; j++) {
+      if (j < S.dnum && e < G.BE) {
+        const double x = smem[(size_t)j * LB + lpad(e)];
+        a0 += mulmod(x, u2d(kbv[k][j]), m);
+        a1 += mulmod(x, u2d(kav[k][j]), m);
+        if ((j & 3) == 3) { a0 = reduce(a0, m); a1 = reduce(a1, m); }
       }
-      r0[k] = reduce(a0, m);
-      r1[k] = reduce(a1, m);
-      if (!special) {
-        const int gi = gidx_of_lds<false>(G, blk, e);
-        ACC[(((size_t)b * 2 + 0) * S.L + mi) * n + gi] = r0[k];
-        ACC[(((size_t)b * 2 + 1) * S.L + mi) * n + gi] = r1[k];
-      }
+    }
+    r0[k] = reduce(a0, m);
+    r1[k] = reduce(a1, m);
+    if (!special && e < G.BE) {
+      const int gi = gidx_of_lds<false>(G, blk, e);
+      gst(ACC + (((size_t)b * 2 + 0) * S.L + mi) * n + gi, r0[k]);
+      gst(ACC + (((size_t)b * 2 + 1) * S.L + mi) * n + gi, r1[k]);
     }
   }
   if (!special) return;
-  // special prime: inverse low pass of the selected accumulator
+  // special prime: inverse low pass of the selected accumulator (r0 = r1 here)
   __syncthreads();
-  stage_twiddles<NT, false, false>(twl, G, blk, tm.iv);
+  twi.store(twl, G);
 #pragma unroll
-  for (int k = 0; k < PER; k++) {
-    const int e = threadIdx.x + k * NT;
-    if (e < G.BE) smem[lpad(e)] = canon(wsel == 0 ? r0[k] : r1[k], m);
-  }
+  for (int k = 0; k < PER; k++)
+    if (threadIdx.x + k * NT < G.BE) smem[lpad(threadIdx.x + k * NT)] = canon(r0[k], m);
   __syncthreads();
   pass_inv_multi<NT, false>(smem, LB, 1, false, twl, tm.ninv, G, blk, m);
   double* o = T2 + (((size_t)b * 2 + wsel) * S.K + (mi - S.L)) * n;
-  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<false>(G, blk, e)] = smem[lpad(e)];
+  for (int e = threadIdx.x; e < G.BE; e += NT) gst(o + gidx_of_lds<false>(G, blk, e), smem[lpad(e)]);
 }
 
 // grid (nblk, 2 L, B): polynomial w = y / L, data prime i = y % L.  The special limbs' inverse
@@ -343,22 +398,52 @@ __global__ void __launch_bounds__(NT) k2_ip_par(const RotItem* __restrict__ item
 template <int NT, class GT>
 __global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__ T2, double* F, KsShape S, const double2* __restrict__ dn_inv,
                                                       const double2* __restrict__ dn_hat, const ModTab* __restrict__ tab, GT G) {
-  SMEM2_HIGH(G);
+  SMEM();
+  constexpr int KMAX = 4;  // special primes whose twiddles are prefetched (more: staged late)
+  constexpr int PER = (GT::kMaxBE + NT - 1) / NT;
   const int n = 1 << G.logn;
   const int blk = blockIdx.x, w = blockIdx.y / S.L, i = blockIdx.y % S.L, b = blockIdx.z;
+  // LDS: [K + 1 twiddle tables of 2^S][K + 1 blocks]: table k < K inverts special prime k, table K
+  // is the target's forward pass; block k holds special limb k, block K the target
+  const int TWH = 1 << G.S;
+  double2* twl = (double2*)smem_raw;
+  double* smem = smem_raw + 2 * (size_t)(S.K + 1) * TWH;
   const int LB = lds_doubles(G.BE);
   double* work = smem + (size_t)S.K * LB;
+  const ModTab tq = tab[i];
+  const ModD mq = mod_of2(tq);
+  TwPre<NT, true, true, GT> twf;
+  twf.load(G, blk, tq.fw);
+  TwPre<NT, true, false, GT> twi[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; k++)
+    if (k < S.K) twi[k].load(G, blk, tab[S.L + k].iv);
   for (int k = 0; k < S.K; k++) {
-    double* buf = smem + (size_t)k * LB;
     const double* src = T2 + (((size_t)b * 2 + w) * S.K + k) * n;
-    for (int e = threadIdx.x; e < G.BE; e += NT) buf[lpadx<true>(e)] = src[gidx_of_lds<true>(G, blk, e)];
+    double x[PER];
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+      const int e = threadIdx.x + r * NT;
+      if (e < G.BE) x[r] = gld(src + gidx_of_lds<true>(G, blk, e));
+    }
+    double* buf = smem + (size_t)k * LB;
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+      const int e = threadIdx.x + r * NT;
+      if (e < G.BE) buf[lpadx<true>(e)] = x[r];
+    }
   }
+  twf.store(twl + (size_t)S.K * TWH, G);
+#pragma unroll
+  for (int k = 0; k < KMAX; k++)
+    if (k < S.K) twi[k].store(twl + (size_t)k * TWH, G);
+  for (int k = KMAX; k < S.K; k++) stage_twiddles<NT, true, false>(twl + (size_t)k * TWH, G, blk, tab[S.L + k].iv);
   __syncthreads();
   for (int k = 0; k < S.K; k++) {
     const ModTab tp = tab[S.L + k];
     const ModD mp = mod_of2(tp);
     double* buf = smem + (size_t)k * LB;
-    pass_inv<NT, true>(buf, twl, G, blk, true, tp.iv, tp.ninv, mp);
+    pass_inv<NT, true>(buf, twl + (size_t)k * TWH, G, blk, true, tp.iv, tp.ninv, mp, false);
     for (int e = threadIdx.x; e < G.BE; e += NT) {
       double x = canon(buf[lpadx<true>(e)], mp);
       if (S.K > 1) {
@@ -369,8 +454,6 @@ __global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__
     }
   }
   __syncthreads();
-  const ModTab tq = tab[i];
-  const ModD mq = mod_of2(tq);
   for (int e = threadIdx.x; e < G.BE; e += NT) {
     double acc = 0.0;
     for (int k = 0; k < S.K; k++) {
@@ -385,36 +468,61 @@ __global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__
     work[lpadx<true>(e)] = acc;
   }
   __syncthreads();
-  pass_fwd<NT, true>(work, twl, G, blk, tq.fw, mq);
+  pass_fwd<NT, true>(work, twl + (size_t)S.K * TWH, G, blk, tq.fw, mq, false);
   double* o = F + (((size_t)b * 2 + w) * S.L + i) * n;
-  for (int e = threadIdx.x; e < G.BE; e += NT) o[gidx_of_lds<true>(G, blk, e)] = work[lpadx<true>(e)];
+  for (int e = threadIdx.x; e < G.BE; e += NT) gst(o + gidx_of_lds<true>(G, blk, e), work[lpadx<true>(e)]);
 }
 
+// The epilogue's operands (accumulator, sigma_g(c0), addend) are loaded with the block, before
+// the pass, so their latency hides behind it.
 template <int NT, class GT>
 __global__ void __launch_bounds__(NT) k2_final_low(const RotItem* __restrict__ items, const double* __restrict__ F, const double* __restrict__ ACC,
                                                    const double2* __restrict__ pinv, KsShape S, const ModTab* __restrict__ tab, GT G) {
   SMEM2(G);
+  constexpr int PER = (GT::kMaxBE + NT - 1) / NT;
   const int n = 1 << G.logn;
   const int blk = blockIdx.x, wi = blockIdx.y, b = blockIdx.z;
   const int w = wi / S.L, i = wi % S.L;
   const RotItem it = items[b];
   const ModTab tq = tab[i];
   const ModD m = mod_of2(tq);
+  TwPre<NT, false, true, GT> tw;
+  tw.load(G, blk, tq.fw);
   const double* src = F + (((size_t)b * 2 + w) * S.L + i) * n;
-  for (int e = threadIdx.x; e < G.BE; e += NT) smem[lpad(e)] = src[gidx_of_lds<false>(G, blk, e)];
-  __syncthreads();
-  pass_fwd<NT, false>(smem, twl, G, blk, tq.fw, m);
-  const double2 pv = pinv[i];
   const double* acc = ACC + (((size_t)b * 2 + w) * S.L + i) * n;
   const u64* c0 = it.in + (size_t)i * n;
-  u64* out = it.out + ((size_t)w * S.L + i) * n;
   const u64* add = it.addend ? it.addend + ((size_t)w * S.L + i) * n : nullptr;
-  for (int e = threadIdx.x; e < G.BE; e += NT) {
-    const int gi = gidx_of_lds<false>(G, blk, e);
-    double v = mul_tw(reduce(acc[gi] - smem[lpad(e)], m), pv.x, pv.y, m);
-    if (w == 0) v += u2d(c0[galois_index2((u32)gi, it.galois, G.logn)]);
-    if (add) v += u2d(add[gi]);
-    out[gi] = d2u(canon(v, m));
+  double x[PER], av[PER];
+  u64 c0w[PER], adw[PER];  // raw words, converted after the pass (branch-free loads)
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    const int e = threadIdx.x + r * NT;
+    const int gi = gidx_of_lds<false>(G, blk, e < G.BE ? e : 0);
+    x[r] = gld(src + gi);
+    av[r] = gld(acc + gi);
+    const u64* c0p = c0 + galois_index2((u32)gi, it.galois, G.logn);
+    c0w[r] = gld(c0p);
+    adw[r] = gld(add ? add + gi : c0p);
+  }
+  tw.store(twl, G);
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    const int e = threadIdx.x + r * NT;
+    if (e < G.BE) smem[lpad(e)] = x[r];
+  }
+  __syncthreads();
+  pass_fwd<NT, false>(smem, twl, G, blk, tq.fw, m, false);
+  const double2 pv = pinv[i];
+  u64* out = it.out + ((size_t)w * S.L + i) * n;
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    const int e = threadIdx.x + r * NT;
+    if (e < G.BE) {
+      const int gi = gidx_of_lds<false>(G, blk, e);
+      const double cv = (w == 0 ? u2d(c0w[r]) : 0.0) + (add ? u2d(adw[r]) : 0.0);
+      const double v = mul_tw(reduce(av[r] - smem[lpad(e)], m), pv.x, pv.y, m) + cv;
+      gst(out + gi, d2u(canon(v, m)));
+    }
   }
 }
 
@@ -486,7 +594,7 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     const ModTab* tab = (const ModTab*)c->d_tab;
     const int LK = c->L + c->K;
     HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B), TW + LB, st, d_items, T1, c->L, tab, G);
-    HS2_LAUNCH(k2_modup_high, dim3(G.nblk, c->dnum * LK, B), TWH + LB * (c->alpha + 1), st, (const double*)T1, E, S,
+    HS2_LAUNCH(k2_modup_high, dim3(G.nblk, c->dnum * LK, B), (TWH + LB) * (c->alpha + 1), st, (const double*)T1, E, S,
                (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
     // the all-digit inner product on half-size blocks where the geometry is compile-time (twice
     // the workgroups, each with half the serial work; two fit a CU)
@@ -503,7 +611,7 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     } else {
       HS2_LAUNCH(k2_ip_low, dim3(G.nblk, LK, B), TW + LB, st, d_items, (const double*)E, ACC, T2, S, tab, G);
     }
-    HS2_LAUNCH(k2_moddown_high, dim3(G.nblk, 2 * c->L, B), TWH + LB * (c->K + 1), st, (const double*)T2, F, S,
+    HS2_LAUNCH(k2_moddown_high, dim3(G.nblk, 2 * c->L, B), (TWH + LB) * (c->K + 1), st, (const double*)T2, F, S,
                (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, tab, G);
     HS2_LAUNCH(k2_final_low, dim3(G.nblk, 2 * c->L, B), TW + LB, st, d_items, (const double*)F, (const double*)ACC,
                (const double2*)c->d_pinv, S, tab, G);
