@@ -205,6 +205,7 @@ def main():
                      "tuning_table": H.tuning(ctx),
                      "level_ms_by_B": {str(b): [round(t1, 4), round(t2, 4)] for b, t1, t2 in tune["pipelines"]}},
     }
+    result["keyswitch_saturated"] = keyswitch_saturated(H, torch, ctx, ks, L, K, 1 << logn)
     result["exact_step_keys"] = exact_step_keys(H, torch, ctx, w, (rp, col, val, v), out, want, args.steps)
     if args.workload == "zipf16k" and not args.no_batch:
         result["batched_vs_plain"] = batched_vs_plain(H, W, torch, dev)
@@ -278,6 +279,42 @@ def ntt_bandwidth(H, torch, dev, ctx, logn, L, K, reps=5):
     nprof = H.profile_summary()
     H.profile(False)
     return nprof["k_ntt"][1] / nprof["k_ntt"][0], 16.0 * N * nl * npoly, nl * npoly
+
+
+def keyswitch_saturated(H, torch, ctx, ks, L, K, N, B=128, reps=5):
+    """One level of B independent rotations by one slot (B ciphertexts of random residues, one
+    hs_rotate call = one batched key switch per ciphertext), so every key-switch kernel has the
+    whole GPU: the key-switch throughput and the HBM fraction of its dominant kernel when the
+    device is full, beside the latency-bound single-SpMV levels of the timed step."""
+    g = np.random.default_rng(5)
+    mods = ctx.moduli()[:L]
+    one = np.concatenate([g.integers(0, q, N, dtype=np.uint64) for q in mods] * 2)
+    x = H.CtVec.from_host(ctx, np.tile(one, B), B)
+    for _ in range(2):
+        H.rotate(ctx, ks, x, 1)
+    H.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        H.rotate(ctx, ks, x, 1)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) * 1e3 / reps
+    prof = H.profile_summary()
+    H.profile(False)
+    per_item = keyswitch_kernel_bytes(L, K, N)
+    ks_prof = {k: v for k, v in prof.items() if k in per_item}
+    ks_ms = sum(ms for _, ms in ks_prof.values()) / reps
+    dom, (cnt, dms) = max(ks_prof.items(), key=lambda kv: kv[1][1])
+    avg = dms / cnt
+    alg = per_item[dom] * B   # one launch of each kernel per level
+    ach = alg / (avg * 1e-3) / 1e9
+    unit = 2 * ((L + K - 1) // K) * (L + K) * N * 8 + 4 * L * N * 8
+    return {"items_per_level": B, "kernel_ms_per_level": round(ks_ms, 4), "wall_ms_per_call": round(wall, 4),
+            "key_switches_per_s": round(B / (ks_ms * 1e-3), 1),
+            "algorithmic_GBps": round(B * unit / (ks_ms * 1e-3) / 1e9, 1),
+            "dominant": {"kernel": dom, "avg_launch_ms": round(avg, 4), "algorithmic_bytes_per_launch": int(alg),
+                         "achieved_GBps": round(ach, 1), "frac": round(ach / HBM_PEAK_GBPS, 4)},
+            "kernel_ms": {k: round(ms / reps, 4) for k, (c, ms) in sorted(ks_prof.items(), key=lambda kv: -kv[1][1])}}
 
 
 def measured_traffic(kernel):

@@ -83,6 +83,15 @@ __device__ __forceinline__ double2 ldtw(const double2* p, int i) {
   return double2{g[0], g[1]};
 }
 
+// Global memory through address-space-1 pointers: such a load cannot alias LDS, so the compiler
+// issues a workgroup's loads together ahead of the LDS stores that consume them instead of
+// waiting for each one in turn (a flat pointer could point into LDS), and it does not hold up the
+// LDS wait counter.
+template <class T>
+__device__ __forceinline__ T gld(const T* p) { return *(const T __attribute__((address_space(1)))*)p; }
+template <class T>
+__device__ __forceinline__ void gst(T* p, T v) { *(T __attribute__((address_space(1)))*)p = v; }
+
 __device__ __forceinline__ u32 brev_bits(u32 x, int bits) { return __brev(x) >> (32 - bits); }
 
 // LDS layout with one pad double every 16, so that power-of-two strides spread over the banks.

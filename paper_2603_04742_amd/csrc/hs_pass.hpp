@@ -120,14 +120,6 @@ __device__ __forceinline__ int tw_lds_index(const GT& G, int blk, int st, int gt
   }
 }
 
-// Global memory through address-space-1 pointers: such a load cannot alias LDS, so the compiler
-// issues a workgroup's loads together ahead of the LDS stores that consume them instead of
-// waiting for each one in turn (a flat pointer could point into LDS).
-template <class T>
-__device__ __forceinline__ T gld(const T* p) { return *(const T __attribute__((address_space(1)))*)p; }
-template <class T>
-__device__ __forceinline__ void gst(T* p, T v) { *(T __attribute__((address_space(1)))*)p = v; }
-
 // LDS twiddle slots of a pass: high passes use slots [0, 2^S) = table entries [0, 2^S); the
 // stage ranges of a low pass are adjacent, [(2^k - 1) GB, (2^(k+1) - 1) GB) for forward stage
 // S + k and [(2^nl - 2^(d+1)) GB, (2^nl - 2^d) GB) for inverse stage nl - 1 - d (nl = logn - S).

@@ -401,12 +401,19 @@ HS_XF_KERNEL k_rot_intt(const RotItem* __restrict__ items, u64* D, int L, const 
 }
 
 // Accumulators live in the output rows ACC; a barrier separates the digits (element ownership
-// differs between the transform's sink and the own-limb loop).
+// differs between the transform's sink and the own-limb loop).  The accumulate step takes a
+// thread's elements KB at a time with every load of the batch (key words, accumulators, the
+// own limb's gathered words) issued before the first use, instead of one element's round trip
+// after another.  The half-limb form holds the other half in registers during its first segment,
+// so it batches fewer elements (within its 128 VGPRs).
+template <class XF> struct KsBatch { static constexpr int value = 8; };
+template <> struct KsBatch<XfSplit> { static constexpr int value = 2; };
 HS_XF_KERNEL k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict__ D, double* ACC, KsShape S,
                         const double2* __restrict__ up_inv, const double2* __restrict__ up_hat, const ModTab* __restrict__ tab,
                         int logn, XF xf) {
   SMEM();
   constexpr int NT = XF::NT;
+  constexpr int KB = KsBatch<XF>::value;
   const int n = 1 << logn;
   const int mi = blockIdx.x, b = blockIdx.y, dg = blockIdx.z;
   const int LK = S.L + S.K;
@@ -427,22 +434,48 @@ HS_XF_KERNEL k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict
     const bool first = (j == j0);
     const u64* kb = it.key + (((size_t)0 * S.dnum + j) * LK + mi) * n;
     const u64* ka = it.key + (((size_t)1 * S.dnum + j) * LK + mi) * n;
-    auto sink = [=](int i, double x) {
-      const double e = reduce(x, m);
-      double v0 = mulmod(e, u2d(kb[i]), m);
-      double v1 = mulmod(e, u2d(ka[i]), m);
-      if (!first) { v0 = reduce(v0 + o0[i], m); v1 = reduce(v1 + o1[i], m); }
-      o0[i] = v0;
-      o1[i] = v1;
+    // elements base + e, e = e0 + c NT < cnt; value(c, e) reads the digit element (LDS or gathered)
+    auto accumulate = [&](int base, int cnt, int e0, auto&& value) {
+      u64 wb[KB], wa[KB];
+      double a0[KB], a1[KB];
+#pragma unroll
+      for (int c = 0; c < KB; c++) {
+        const int e = e0 + c * NT;
+        const int i = base + (e < cnt ? e : e0);
+        wb[c] = gld(kb + i);
+        wa[c] = gld(ka + i);
+        a0[c] = gld(o0 + i);  // read also for the first digit (ignored): no branch around the load
+        a1[c] = gld(o1 + i);
+      }
+#pragma unroll
+      for (int c = 0; c < KB; c++) {
+        const int e = e0 + c * NT;
+        if (e < cnt) {
+          const double x = reduce(value(c, e), m);
+          double v0 = mulmod(x, u2d(wb[c]), m);
+          double v1 = mulmod(x, u2d(wa[c]), m);
+          if (!first) { v0 = reduce(v0 + a0[c], m); v1 = reduce(v1 + a1[c], m); }
+          gst(o0 + base + e, v0);
+          gst(o1 + base + e, v1);
+        }
+      }
     };
     if (own) {
       const u64* c1 = it.in + ((size_t)S.L + mi) * n;
-      for (int i = threadIdx.x; i < n; i += NT) sink(i, u2d(c1[galois_index((u32)i, it.galois, logn)]));
+      for (int e0 = threadIdx.x; e0 < n; e0 += KB * NT) {
+        u64 cw[KB];
+#pragma unroll
+        for (int c = 0; c < KB; c++) {
+          const int e = e0 + c * NT;
+          cw[c] = gld(c1 + galois_index((u32)(e < n ? e : e0), it.galois, logn));
+        }
+        accumulate(0, n, e0, [&](int c, int) { return u2d(cw[c]); });
+      }
     } else {
       const u64* Dj = D + ((size_t)b * S.L + lo) * n;
       const int na = hi - lo;
       auto seg = [&](int base, int cnt) {
-        for (int e = threadIdx.x; e < cnt; e += NT) sink(base + e, smem[lpad(e)]);
+        for (int e0 = threadIdx.x; e0 < cnt; e0 += KB * NT) accumulate(base, cnt, e0, [&](int, int e) { return smem[lpad(e)]; });
       };
       if (na == 1) {
         // one source prime (alpha = 1): [x]_q as an integer, taken mod mi
@@ -527,16 +560,35 @@ HS_XF_KERNEL k_moddown_ntt(const RotItem* __restrict__ items, const double* __re
   const int ndg = S.ndg;
   const double* a0 = ACC + (((size_t)b * ndg * 2 + w) * LK + i_l) * n;
   const size_t dstride = (size_t)2 * LK * n;
-  auto sink = [=](int i, double x) {
-    double acc = 0.0;
-    for (int dg = 0; dg < ndg; dg++) acc += a0[dg * dstride + i];
-    double v = mul_tw(reduce(acc - x, m), pv.x, pv.y, m);
-    if (w == 0) v += u2d(c0[galois_index((u32)i, gal, logn)]);
-    if (add) v += u2d(add[i]);
-    out[i] = d2u(canon(v, m));
-  };
+  // the epilogue's loads (accumulators, sigma_g(c0), addend) KB elements at a time, all in
+  // flight together, with branch-free addresses (unused words are read and ignored)
+  constexpr int KB = KsBatch<XF>::value;
   auto seg = [&](int base, int cnt) {
-    for (int e = threadIdx.x; e < cnt; e += XF::NT) sink(base + e, smem[lpad(e)]);
+    for (int e0 = threadIdx.x; e0 < cnt; e0 += KB * XF::NT) {
+      double ac[KB];
+      u64 cw[KB], aw[KB];
+#pragma unroll
+      for (int c = 0; c < KB; c++) {
+        const int e = e0 + c * XF::NT;
+        const int i = base + (e < cnt ? e : e0);
+        double acc = 0.0;
+        for (int dg = 0; dg < ndg; dg++) acc += gld(a0 + dg * dstride + i);
+        ac[c] = acc;
+        const u64* cp = c0 + galois_index((u32)i, gal, logn);
+        cw[c] = gld(cp);
+        aw[c] = gld(add ? add + i : cp);
+      }
+#pragma unroll
+      for (int c = 0; c < KB; c++) {
+        const int e = e0 + c * XF::NT;
+        if (e < cnt) {
+          double v = mul_tw(reduce(ac[c] - smem[lpad(e)], m), pv.x, pv.y, m);
+          if (w == 0) v += u2d(cw[c]);
+          if (add) v += u2d(aw[c]);
+          gst(out + base + e, d2u(canon(v, m)));
+        }
+      }
+    }
   };
   xf.fwd_seg(src, seg, smem, tb.fw, m);
 }
