@@ -1497,6 +1497,10 @@ int hs_set_option(int key, int64_t value) {
         HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "path must be 0, 1 or 2");
         g_opt_ntt = (int)value;
         break;
+      case HS_OPT_MODUP_GROUP:
+        HS_REQUIRE(value >= 0 && value <= 3, HS_EINVAL, "group must be 0, 1, 2 or 3");
+        set_modup_group((int)value);
+        break;
       case HS_OPT_KS_THRESHOLD:
         HS_REQUIRE(value >= 0 && value < (1 << 30), HS_EINVAL, "bad threshold");
         g_opt_ks_threshold = (int)value;

@@ -306,9 +306,10 @@ __device__ __forceinline__ void pass_inv(double* s, double2* twl, const GT& G, i
 // twiddles are shared): block j at s + j * LB, skipped when bit j of `skip` is set.  Spreads the
 // register groups of all blocks over the workgroup, so NB independent transforms run
 // concurrently instead of one after another.
-template <int R, int NT, bool FWD, bool HIGH, class GT>
+template <int R, int NT, bool FWD, bool HIGH, class GT, bool PM = false>
 __device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsigned skip, const GT& G, int blk, int lb, int lazy,
-                                                 bool scale, const double2* twl, double2 ninv, ModD m) {
+                                                 bool scale, const double2* twl, double2 ninv, ModD m, int twstride = 0,
+                                                 const double2* mods = nullptr) {
   const int nb = HIGH ? G.S : G.logn - G.S;
   const int GB = HIGH ? G.gb_high() : G.gb_low();
   const int lpg = nb - R;
@@ -316,6 +317,14 @@ __device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsi
   for (int t = threadIdx.x; t < (NB << lpb); t += NT) {
     const int j = t >> lpb;
     if ((skip >> j) & 1u) continue;
+    // PM: block j has its own modulus (mods[j] = (q, fl(1/q)) in LDS) and twiddle table
+    ModD mj = m;
+    const double2* twj = twl;
+    if (PM) {
+      const double2 mq = mods[j];
+      mj = ModD{mq.x, mq.y};
+      twj = twl + (size_t)j * twstride;
+    }
     const int sg = t & ((1 << lpb) - 1);
     const int g = sg >> lpg, r = sg & ((1 << lpg) - 1);
     const int n = 1 << G.logn;
@@ -335,11 +344,11 @@ __device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsi
       for (int k = 0; k < R; k++) {
         if (lz >= 2) {
 #pragma unroll
-          for (int v = 0; v < (1 << R); v++) x[v] = reduce(x[v], m);
+          for (int v = 0; v < (1 << R); v++) x[v] = reduce(x[v], mj);
           lz = 0;
         }
         const int st = G.logn - lo - lb - R + k;
-        const double2* twk = twl + tw_lds_index<HIGH, true>(G, blk, st, (1 << st) + (hb << k));
+        const double2* twk = twj + tw_lds_index<HIGH, true>(G, blk, st, (1 << st) + (hb << k));
 #pragma unroll
         for (int jj = 0; jj < (1 << k); jj++) {
           const double2 w = twk[jj];
@@ -347,7 +356,7 @@ __device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsi
           for (int v = 0; v < (1 << (R - 1 - k)); v++) {
             const int u = (jj << (R - k)) | v;
             const int u2 = u | (1 << (R - 1 - k));
-            const double tt = mul_tw(x[u2], w.x, w.y, m);
+            const double tt = mul_tw(x[u2], w.x, w.y, mj);
             x[u2] = x[u] - tt;
             x[u] = x[u] + tt;
           }
@@ -358,7 +367,7 @@ __device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsi
 #pragma unroll
       for (int k = 0; k < R; k++) {
         const int st = lo + lb + k;
-        const double2* twk = twl + tw_lds_index<HIGH, false>(G, blk, st, (n >> (st + 1)) + (hb << (R - 1 - k)));
+        const double2* twk = twj + tw_lds_index<HIGH, false>(G, blk, st, (n >> (st + 1)) + (hb << (R - 1 - k)));
 #pragma unroll
         for (int jj = 0; jj < (1 << (R - 1 - k)); jj++) {
           const double2 w = twk[jj];
@@ -367,14 +376,14 @@ __device__ __forceinline__ void pass_round_multi(double* s, int LB, int NB, unsi
             const int u = (jj << (k + 1)) | v;
             const int u2 = u | (1 << k);
             const double a = x[u], bb = x[u2];
-            x[u] = reduce(a + bb, m);
-            x[u2] = mul_tw(a - bb, w.x, w.y, m);
+            x[u] = reduce(a + bb, mj);
+            x[u2] = mul_tw(a - bb, w.x, w.y, mj);
           }
         }
       }
       if (scale) {
 #pragma unroll
-        for (int v = 0; v < (1 << R); v++) x[v] = mul_tw(x[v], ninv.x, ninv.y, m);
+        for (int v = 0; v < (1 << R); v++) x[v] = mul_tw(x[v], ninv.x, ninv.y, mj);
       }
     }
 #pragma unroll
@@ -403,6 +412,34 @@ __device__ __forceinline__ void pass_fwd_multi(double* s, int LB, int NB, unsign
   for (int t = threadIdx.x; t < (NB << G.lbe); t += NT) {
     const int j = t >> G.lbe, e = t & (G.BE - 1);
     if (!((skip >> j) & 1u)) s[(size_t)j * LB + lpadx<HIGH>(e)] = reduce(s[(size_t)j * LB + lpadx<HIGH>(e)], m);
+  }
+  __syncthreads();
+}
+
+// Forward pass on NB blocks of different moduli: block j uses twiddle table twl + j * twstride and
+// modulus mods[j] (LDS).  Same contract as pass_fwd_multi otherwise.
+template <int NT, bool HIGH, class GT>
+__device__ __forceinline__ void pass_fwd_multi_mod(double* s, int LB, int NB, const double2* twl, int twstride, const double2* mods, const GT& G,
+                                                   int blk) {
+  const int nb = HIGH ? G.S : G.logn - G.S;
+  const ModD m0{0.0, 0.0};
+  int done = 0, lazy = 0;
+  while (done < nb) {
+    const int R = min(HS_NTT_RADIX_BITS, nb - done);
+    const int lb = nb - done - R;
+    switch (R) {
+      case 3: pass_round_multi<3, NT, true, HIGH, GT, true>(s, LB, NB, 0u, G, blk, lb, lazy, false, twl, double2{0, 0}, m0, twstride, mods); break;
+      case 2: pass_round_multi<2, NT, true, HIGH, GT, true>(s, LB, NB, 0u, G, blk, lb, lazy, false, twl, double2{0, 0}, m0, twstride, mods); break;
+      default: pass_round_multi<1, NT, true, HIGH, GT, true>(s, LB, NB, 0u, G, blk, lb, lazy, false, twl, double2{0, 0}, m0, twstride, mods); break;
+    }
+    for (int k = 0; k < R; k++) { if (lazy >= 2) lazy = 0; lazy++; }
+    done += R;
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < (NB << G.lbe); t += NT) {
+    const int j = t >> G.lbe, e = t & (G.BE - 1);
+    const ModD mj{mods[j].x, mods[j].y};
+    s[(size_t)j * LB + lpadx<HIGH>(e)] = reduce(s[(size_t)j * LB + lpadx<HIGH>(e)], mj);
   }
   __syncthreads();
 }

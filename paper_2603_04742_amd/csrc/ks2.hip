@@ -13,6 +13,7 @@
 //  K5 k2_final_low      forward low pass, out = (ACC - F) P^-1 + sigma_g(c0) (+ addend)
 // Intermediates are balanced doubles in HBM (mostly served from the 256 MB Infinity Cache).
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 
@@ -204,6 +205,111 @@ __global__ void __launch_bounds__(NT) k2_modup_high(const double* __restrict__ T
   pass_fwd<NT, true>(work, twl + (size_t)S.alpha * TWH, G, blk, tm.fw, mm, false);
   double* o = E + (((size_t)b * S.dnum + j) * LK + mi) * n;
   for (int e = threadIdx.x; e < G.BE; e += NT) gst(o + gidx_of_lds<true>(G, blk, e), work[lpadx<true>(e)]);
+}
+
+// K2 with TG targets per workgroup: the digit's inverse high pass runs once for TG targets, whose
+// forward high passes then run concurrently (one modulus and twiddle table per block).  grid
+// (nblk, dnum * ngrp, B), ngrp = ceil((L + K - na_min) / TG) with na_min the primes of the last
+// (smallest) digit; target t of digit j is modulus t (t < lo) or t + na, skipping the digit's own
+// primes; groups past a digit's targets exit.
+template <int NT, int TG, class GT>
+__global__ void __launch_bounds__(NT) k2_modup_grp(const double* __restrict__ T1, double* E, KsShape S, int ngrp,
+                                                   const double2* __restrict__ up_inv, const double2* __restrict__ up_hat,
+                                                   const ModTab* __restrict__ tab, GT G) {
+  SMEM();
+  constexpr int AMAX = 4;
+  constexpr int PER = (GT::kMaxBE + NT - 1) / NT;
+  const int n = 1 << G.logn;
+  const int LK = S.L + S.K;
+  const int blk = blockIdx.x, j = blockIdx.y / ngrp, g = blockIdx.y % ngrp, b = blockIdx.z;
+  const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha), na = hi - lo;
+  const int t0 = g * TG, nt = min(TG, LK - na - t0);
+  if (nt <= 0) return;
+  // LDS: [alpha + TG twiddle tables of 2^S][TG moduli (q, 1/q)][alpha + TG blocks]
+  const int TWH = 1 << G.S;
+  double2* twl = (double2*)smem_raw;
+  double2* mods = twl + (size_t)(S.alpha + TG) * TWH;
+  double* smem = (double*)(mods + TG);
+  const int LB = lds_doubles(G.BE);
+  double* work = smem + (size_t)S.alpha * LB;
+  int mis[TG];
+#pragma unroll
+  for (int tt = 0; tt < TG; tt++) {
+    const int t = t0 + (tt < nt ? tt : 0);
+    mis[tt] = t < lo ? t : t + na;
+  }
+  TwPre<NT, true, true, GT> twf[TG];
+#pragma unroll
+  for (int tt = 0; tt < TG; tt++) twf[tt].load(G, blk, tab[mis[tt]].fw);
+  TwPre<NT, true, false, GT> twi[AMAX];
+#pragma unroll
+  for (int a = 0; a < AMAX; a++)
+    if (a < na) twi[a].load(G, blk, tab[lo + a].iv);
+  for (int a = 0; a < na; a++) {
+    const double* src = T1 + ((size_t)b * S.L + lo + a) * n;
+    double x[PER];
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+      const int e = threadIdx.x + r * NT;
+      if (e < G.BE) x[r] = gld(src + gidx_of_lds<true>(G, blk, e));
+    }
+    double* buf = smem + (size_t)a * LB;
+#pragma unroll
+    for (int r = 0; r < PER; r++) {
+      const int e = threadIdx.x + r * NT;
+      if (e < G.BE) buf[lpadx<true>(e)] = x[r];
+    }
+  }
+#pragma unroll
+  for (int tt = 0; tt < TG; tt++) twf[tt].store(twl + (size_t)(S.alpha + tt) * TWH, G);
+  if (threadIdx.x < TG) {
+    const ModTab tq = tab[mis[threadIdx.x]];
+    mods[threadIdx.x] = double2{tq.q, tq.qinv};
+  }
+#pragma unroll
+  for (int a = 0; a < AMAX; a++)
+    if (a < na) twi[a].store(twl + (size_t)a * TWH, G);
+  for (int a = AMAX; a < na; a++) stage_twiddles<NT, true, false>(twl + (size_t)a * TWH, G, blk, tab[lo + a].iv);
+  __syncthreads();
+  for (int a = 0; a < na; a++) {
+    const ModTab ta = tab[lo + a];
+    const ModD ma = mod_of2(ta);
+    double* buf = smem + (size_t)a * LB;
+    pass_inv<NT, true>(buf, twl + (size_t)a * TWH, G, blk, true, ta.iv, ta.ninv, ma, false);
+    for (int e = threadIdx.x; e < G.BE; e += NT) {
+      double x = canon(buf[lpadx<true>(e)], ma);
+      if (na > 1) {
+        const double2 ci = up_inv[j * S.alpha + a];
+        x = canon(mul_tw(x, ci.x, ci.y, ma), ma);   // [x (Q_j/q_a)^-1]_{q_a}
+      }
+      buf[lpadx<true>(e)] = x;
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < (nt << G.lbe); t += NT) {
+    const int tt = t >> G.lbe, e = t & (G.BE - 1);
+    const ModD mm{mods[tt].x, mods[tt].y};
+    double acc = 0.0;
+    for (int a = 0; a < na; a++) {
+      const double y = smem[(size_t)a * LB + lpadx<true>(e)];
+      if (na > 1) {
+        const int t_mod = (t0 + tt) < lo ? (t0 + tt) : (t0 + tt + na);
+        const double2 hm = up_hat[((size_t)j * S.alpha + a) * LK + t_mod];
+        acc = reduce(acc + mul_tw(y, hm.x, hm.y, mm), mm);
+      } else {
+        acc = reduce(y, mm);   // one source prime: [x]_q as an integer, taken mod the target
+      }
+    }
+    work[(size_t)tt * LB + lpadx<true>(e)] = acc;
+  }
+  __syncthreads();
+  pass_fwd_multi_mod<NT, true>(work, LB, nt, twl + (size_t)S.alpha * TWH, TWH, mods, G, blk);
+  for (int t = threadIdx.x; t < (nt << G.lbe); t += NT) {
+    const int tt = t >> G.lbe, e = t & (G.BE - 1);
+    const int t_mod = (t0 + tt) < lo ? (t0 + tt) : (t0 + tt + na);
+    double* o = E + (((size_t)b * S.dnum + j) * LK + t_mod) * n;
+    gst(o + gidx_of_lds<true>(G, blk, e), work[(size_t)tt * LB + lpadx<true>(e)]);
+  }
 }
 
 // grid (nblk, L + K, B).  The next digit's block is loaded into registers while the current one
@@ -527,6 +633,11 @@ __global__ void __launch_bounds__(NT) k2_final_low(const RotItem* __restrict__ i
 }
 
 // ------------------------------------------------------------------ launchers
+// ModUp targets per workgroup of K2: 1 = k2_modup_high, 2 or 3 = k2_modup_grp, 0 = by level size
+// (measured at N = 16384: two below 5 items, three from 5 on; the shared inverse pass saves work
+// while fewer, longer workgroups cost latency).
+static std::atomic<int> g_modup_tg{0};
+void set_modup_group(int tg) { g_modup_tg = tg; }
 static std::mutex g2_mu;
 static std::map<const void*, size_t> g2_set;
 static void ensure_lds2(const void* f, size_t bytes) {
@@ -594,8 +705,27 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     const ModTab* tab = (const ModTab*)c->d_tab;
     const int LK = c->L + c->K;
     HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B), TW + LB, st, d_items, T1, c->L, tab, G);
-    HS2_LAUNCH(k2_modup_high, dim3(G.nblk, c->dnum * LK, B), (TWH + LB) * (c->alpha + 1), st, (const double*)T1, E, S,
-               (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
+    const int tg = g_modup_tg.load() > 0 ? g_modup_tg.load() : (B >= 5 ? 3 : 2);
+    if (tg <= 1) {
+      HS2_LAUNCH(k2_modup_high, dim3(G.nblk, c->dnum * LK, B), (TWH + LB) * (c->alpha + 1), st, (const double*)T1, E, S,
+                 (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
+    } else {
+      // enough groups for the digit with the fewest primes (the last one), which has the most targets
+      const int na_min = c->L - (c->dnum - 1) * c->alpha;
+      const int ngrp = (LK - na_min + tg - 1) / tg;
+      const size_t lds = (TWH + LB) * (c->alpha + tg) + 16 * (size_t)tg;
+      ProfScope _prof("k2_modup_high", st);
+      if (tg == 2) {
+        ensure_lds2((const void*)k2_modup_grp<512, 2, GT>, lds);
+        hipLaunchKernelGGL((k2_modup_grp<512, 2, GT>), dim3(G.nblk, c->dnum * ngrp, B), dim3(512), lds, st, (const double*)T1, E, S, ngrp,
+                           (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
+      } else {
+        ensure_lds2((const void*)k2_modup_grp<512, 3, GT>, lds);
+        hipLaunchKernelGGL((k2_modup_grp<512, 3, GT>), dim3(G.nblk, c->dnum * ngrp, B), dim3(512), lds, st, (const double*)T1, E, S, ngrp,
+                           (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
+      }
+      HS_CHECK_HIP(hipGetLastError());
+    }
     // the all-digit inner product on half-size blocks where the geometry is compile-time (twice
     // the workgroups, each with half the serial work; two fit a CU)
     using G3T = typename HalfBlocks<GT>::type;

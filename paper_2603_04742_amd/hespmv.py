@@ -378,7 +378,7 @@ def rotate(ctx, ks, x, k):
     return CtVec(ctx, h)
 
 
-OPT_KS_PIPELINE, OPT_NTT_PATH, OPT_KS_THRESHOLD, OPT_AUX_PATH = 1, 2, 3, 4
+OPT_KS_PIPELINE, OPT_NTT_PATH, OPT_KS_THRESHOLD, OPT_AUX_PATH, OPT_MODUP_GROUP = 1, 2, 3, 4, 5
 
 
 def set_option(key, value):

@@ -135,3 +135,23 @@ def test_autotune_and_every_tuning_give_identical_limbs(p):
     check_decrypt(g, reqs, H.he_spmv_batch(g, kss, ms, xs))
     with pytest.raises(H.HespmvError):
         H.set_tuning(g, [2, 0] + [0] * 8)
+
+
+@pytest.mark.parametrize("p", [TINY11, SMALL, RING16K, (10, 3, 50, 2, 0)], ids=["ring2048", "ring4096", "ring16k", "two_prime_digits"])
+def test_modup_grouping_gives_identical_limbs(p):
+    """The two-pass ModUp with one, two or three targets per workgroup computes the same limbs."""
+    g, kg = fresh(p)
+    shapes = [(9000, 4000, 20000), (64, 64, 300)] if p == RING16K else [(300, 300, 1500), (700, 200, 2000)]
+    reqs = requests(g, [kg], shapes, 9)
+    kss, ms, xs = [r[1] for r in reqs], [r[2] for r in reqs], [r[3] for r in reqs]
+    H.set_option(H.OPT_KS_PIPELINE, 2)
+    try:
+        ref = [y.export_all() for y in H.he_spmv_batch(g, kss, ms, xs)]
+        for tg in (2, 3, 1, 0):
+            H.set_option(H.OPT_MODUP_GROUP, tg)
+            for y, e in zip(H.he_spmv_batch(g, kss, ms, xs), ref):
+                assert np.array_equal(y.export_all(), e), "targets per workgroup %d" % tg
+        check_decrypt(g, reqs, H.he_spmv_batch(g, kss, ms, xs))
+    finally:
+        H.set_option(H.OPT_MODUP_GROUP, 0)
+        H.set_option(H.OPT_KS_PIPELINE, 0)
