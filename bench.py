@@ -326,16 +326,16 @@ def measured_traffic(kernel):
         text = open(os.path.join(here, "profiles", "zipf16k_keyswitch_traffic.md")).read()
     except OSError:
         return None
-    line = [l for l in text.splitlines() if l.startswith("machine-readable:")]
-    if not line:
-        return None
-    kv = dict(f.split("=", 1) for f in line[0].split()[1:])
     h = hashlib.sha256()
     for f in ["ks2.hip", "hs_pass.hpp", "hs_device.hpp", "kernels.hpp"]:
         h.update(open(os.path.join(here, "paper_2603_04742_amd", "csrc", f), "rb").read())
-    if kv.get("kernel") != kernel or kv.get("sources_sha256") != h.hexdigest()[:16]:
-        return None
-    return int(kv["traffic_bytes_per_launch"])
+    for line in text.splitlines():
+        if not line.startswith("machine-readable:"):
+            continue
+        kv = dict(f.split("=", 1) for f in line.split()[1:])
+        if kv.get("kernel") == kernel and kv.get("sources_sha256") == h.hexdigest()[:16]:
+            return int(kv["traffic_bytes_per_launch"])
+    return None
 
 
 def keyswitch_kernel_bytes(L, K, N):
@@ -349,6 +349,7 @@ def keyswitch_kernel_bytes(L, K, N):
         # two-pass pipeline
         "k2_rot_intt_low": (L + L) * limb,
         "k2_modup_high": (L + ext) * limb,
+        "k2_modup_grp": (L + ext) * limb,
         "k2_ip_low": (ext + L + key + 2 * L + 2 * K) * limb,
         "k2_ip_par": (ext + L + key + 2 * L + 2 * K) * limb,
         "k2_moddown_high": (2 * K + 2 * L) * limb,

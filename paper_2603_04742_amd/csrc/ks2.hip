@@ -714,7 +714,7 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
       const int na_min = c->L - (c->dnum - 1) * c->alpha;
       const int ngrp = (LK - na_min + tg - 1) / tg;
       const size_t lds = (TWH + LB) * (c->alpha + tg) + 16 * (size_t)tg;
-      ProfScope _prof("k2_modup_high", st);
+      ProfScope _prof("k2_modup_grp", st);
       if (tg == 2) {
         ensure_lds2((const void*)k2_modup_grp<512, 2, GT>, lds);
         hipLaunchKernelGGL((k2_modup_grp<512, 2, GT>), dim3(G.nblk, c->dnum * ngrp, B), dim3(512), lds, st, (const double*)T1, E, S, ngrp,
