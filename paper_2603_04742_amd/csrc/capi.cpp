@@ -393,9 +393,14 @@ static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem
 // Transform helper: one-workgroup-per-limb kernels when the limb fits in LDS (unless the two-pass
 // path is requested), else the two-pass kernels with a scratch buffer kept in `hold` until the
 // caller synchronises.
+// Batched transform of `rows` limbs: one workgroup per limb, or the two-pass form (N / 2048
+// workgroups per limb) for limbs larger than LDS and, automatically, for a handful of limbs, whose
+// one-workgroup transforms would occupy a few CUs for a whole transform's latency.
+static constexpr i64 kTwoPassMaxRows = 16;
 static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int inverse, hipStream_t st, std::vector<DBuf>& hold) {
   if (rows <= 0) return;
-  if (!lds_limb_fits(c) || g_opt_ntt.load() == 2) {
+  const int opt = g_opt_ntt.load();
+  if (!lds_limb_fits(c) || opt == 2 || (opt == 0 && c->logn >= 12 && rows <= kTwoPassMaxRows)) {
     hold.emplace_back(&c->pool, (size_t)rows * c->N * sizeof(double));
     launch_ntt2(c, data, hold.back().as<double>(), rows, nl, mod0, inverse, st);
   } else {
@@ -405,6 +410,10 @@ static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int invers
 
 // keygen / encoding / encryption / decryption as elementwise kernels around batched transforms
 static bool use_split(const hs_ctx* c) { return !lds_limb_fits(c) || g_opt_aux.load() == 2; }
+// The same choice for the vector's encoding and encryption and for decryption: from N = 16384 on
+// the split form wins (measured: its batched transforms spread a limb over two or more workgroups),
+// while the matrix's encoding keeps the fused kernels, which run on the side stream.
+static bool use_split_client(const hs_ctx* c) { return use_split(c) || (c->logn >= 14 && g_opt_aux.load() == 0); }
 
 // Exact ciphertext products a_i x b_i (NTT form [2][L][N] each) with relinearisation: n items,
 // keys[i] = the relinearisation key of item i.
@@ -451,8 +460,8 @@ static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const
 }
 
 // Pack + encode G chunks (mode 0 matrix values, 1 vector, 2 mask) into mod-t coefficients.
-static void pack_encode(hs_ctx* c, PackArgs pa, int G, hipStream_t st, std::vector<DBuf>& hold) {
-  if (use_split(c)) {
+static void pack_encode(hs_ctx* c, PackArgs pa, int G, hipStream_t st, std::vector<DBuf>& hold, bool split) {
+  if (split) {
     launch_pack_slots(c, pa, G, st);
     ntt_any(c, pa.out, G, 1, c->n_mod, 1, st, hold);
   } else {
@@ -473,7 +482,7 @@ static void plain_ntt(hs_ctx* c, const u64* coef, u64* out, int G, hipStream_t s
 // fused kernel, whose workgroups run three whole-limb transforms one after another.
 static void encrypt_coefs(hs_ctx* c, const u64* coef, const int* samples, const u64* pk, u64* out, int G, hipStream_t st,
                           std::vector<DBuf>& hold) {
-  if (use_split(c) || (c->logn >= 14 && g_opt_aux.load() == 0)) {
+  if (use_split_client(c)) {
     hold.emplace_back(&c->pool, (size_t)G * 3 * c->L * c->N * sizeof(u64));
     u64* prep = hold.back().as<u64>();
     launch_enc_prep(c, coef, samples, G, prep, st);
@@ -825,7 +834,7 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         PackArgs pa{};
         pa.va = M->d_va; pa.ci = M->d_ci; pa.v = nullptr; pa.cp = M->d_cp; pa.chunk = M->d_chunk;
         pa.out = coef.as<u64>(); pa.mode = 0; pa.nG = G;
-        pack_encode(c, pa, G, st, hold);
+        pack_encode(c, pa, G, st, hold, use_split(c));
         if (encrypt_values) {
           M->d_pt = pmalloc<u64>(c, (size_t)G * ct_words(c));
           keep.emplace_back(&c->pool, (size_t)G * 3 * N * sizeof(int));
@@ -840,7 +849,7 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         }
         if (masks) {
           pa.mode = 2;
-          pack_encode(c, pa, G, st, hold);
+          pack_encode(c, pa, G, st, hold, use_split(c));
           M->d_mask = pmalloc<u64>(c, (size_t)G * c->L * N);
           plain_ntt(c, coef.as<u64>(), M->d_mask, G, st, hold);
         }
@@ -933,7 +942,7 @@ int hs_encrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const int64_t
         PackArgs pa{};
         pa.va = m->d_va; pa.ci = m->d_ci; pa.v = v; pa.cp = m->d_cp; pa.chunk = m->d_chunk;
         pa.out = coef.as<u64>(); pa.mode = 1;
-        pack_encode(c, pa, G, st, hold);
+        pack_encode(c, pa, G, st, hold, use_split_client(c));
         DBuf smp(&c->pool, (size_t)G * 3 * N * sizeof(int));
         launch_sample_small(c, smp.as<int>(), G, 3 * (i64)N, seed, P_ENC_U, 0, 1, 0, st);
         launch_sample_small(c, smp.as<int>() + N, G, 3 * (i64)N, seed, P_ENC_E0, 0, 1, 1, st);
@@ -1396,7 +1405,7 @@ int hs_decrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const hs_ctve
     const size_t N = c->N;
     DBuf X(&c->pool, (size_t)nP * c->L * N * sizeof(u64)), Mc(&c->pool, (size_t)nP * N * sizeof(u64));
     std::vector<DBuf> hold;
-    const bool split = use_split(c);
+    const bool split = use_split_client(c);
     if (split) {
       launch_dec_prep(c, y->d, ks->sk, X.as<u64>(), nP, st);
       ntt_any(c, X.as<u64>(), (i64)nP * c->L, c->L, 0, 1, st, hold);
