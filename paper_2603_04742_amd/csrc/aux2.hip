@@ -21,6 +21,16 @@ __device__ __forceinline__ u64 smod_i64(i64 v, u64 q) {
   i64 r = v % (i64)q;
   return (u64)(r < 0 ? r + (i64)q : r);
 }
+// The same for |v| < q (samples, centered plaintext coefficients): no division.
+__device__ __forceinline__ u64 smod_small(i64 v, u64 q) { return (u64)(v < 0 ? v + (i64)q : v); }
+
+// Row-wise elementwise kernels: grid (N / (256 ROW_EPT), rows) with rows looped over gridDim.y, so a
+// block's row (and with it the modulus) is uniform and no per-element division is needed.
+static constexpr int ROW_EPT = 4;
+#define ROW_LOOP(ROWS)                                                                   \
+  for (int row = blockIdx.y; row < (ROWS); row += gridDim.y)                             \
+    for (int e_ = 0; e_ < ROW_EPT; e_++)                                                 \
+      if (const i64 k = ((i64)blockIdx.x * ROW_EPT + e_) * blockDim.x + threadIdx.x; k < n)
 
 // out[o][l][k] = src[o][k] mod modulus (mod0 + l), for small signed integers.
 __global__ void k_ints_to_limbs(const int* __restrict__ src, i64 src_stride, int nobj, u64* out, int nl, int mod0,
@@ -93,14 +103,11 @@ __global__ void k_pack_slots(PackArgs A, int nchunks, const u32* __restrict__ sl
 // Centered lift of mod-t coefficients to every data prime: out[g][l][k].
 __global__ void k_lift_plain(const u64* __restrict__ coef, int n_plain, u64* out, int L, u64 t, const ModTab* __restrict__ tab, int logn) {
   const i64 n = 1 << logn;
-  const i64 total = (i64)n_plain * L * n;
-  for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
-    const i64 k = idx & (n - 1);
-    const i64 r = idx >> logn;
-    const int l = (int)(r % L), g = (int)(r / L);
+  ROW_LOOP(n_plain * L) {
+    const int l = row % L, g = row / L;
     const u64 v = coef[(size_t)g * n + k];
     const i64 c = v > (t - 1) / 2 ? (i64)v - (i64)t : (i64)v;
-    out[idx] = smod_i64(c, (u64)tab[l].q);
+    out[(size_t)row * n + k] = smod_small(c, (u64)tab[l].q);
   }
 }
 
@@ -109,21 +116,20 @@ __global__ void k_lift_plain(const u64* __restrict__ coef, int n_plain, u64* out
 __global__ void k_enc_prep(const u64* __restrict__ mcoef, const int* __restrict__ samples, int n_ct, u64* out, int L, u64 t, u64 q_mod_t,
                            const double2* __restrict__ qdt, const ModTab* __restrict__ tab, int logn) {
   const i64 n = 1 << logn;
-  const i64 total = (i64)n_ct * L * n;
-  for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
-    const i64 k = idx & (n - 1);
-    const i64 r = idx >> logn;
-    const int l = (int)(r % L), g = (int)(r / L);
+  ROW_LOOP(n_ct * L) {
+    const int l = row % L, g = row / L;
     const ModTab tb = tab[l];
     const ModD m = modx(tb);
     const u64 q = (u64)tb.q;
     const int* u = samples + (size_t)g * 3 * n;
     const u64 mv = mcoef[(size_t)g * n + k];
     const double d1 = mul_tw((double)mv, qdt[l].x, qdt[l].y, m);
-    const double d2 = (double)((q_mod_t * mv + t / 2) / t);
+    // floor(((Q mod t) m + floor(t/2)) / t): the numerator is below 2^34, so the quotient of the
+    // exactly represented doubles rounds to within 2^-18 of the true one and floor is exact
+    const double d2 = floor(((double)(q_mod_t * mv) + (double)(t / 2)) / (double)t);
     u64* o = out + ((size_t)g * 3 * L) * n;
-    o[((size_t)0 * L + l) * n + k] = smod_i64(u[k], q);
-    o[((size_t)1 * L + l) * n + k] = smod_i64(u[2 * n + k], q);
+    o[((size_t)0 * L + l) * n + k] = smod_small(u[k], q);
+    o[((size_t)1 * L + l) * n + k] = smod_small(u[2 * n + k], q);
     o[((size_t)2 * L + l) * n + k] = d2u(canon(reduce((double)u[n + k] + d1 + d2, m), m));
   }
 }
@@ -132,11 +138,8 @@ __global__ void k_enc_prep(const u64* __restrict__ mcoef, const int* __restrict_
 __global__ void k_enc_combine(const u64* __restrict__ prep, const u64* __restrict__ pk, u64* out, int n_ct, int L, const ModTab* __restrict__ tab,
                               int logn) {
   const i64 n = 1 << logn;
-  const i64 total = (i64)n_ct * L * n;
-  for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
-    const i64 k = idx & (n - 1);
-    const i64 r = idx >> logn;
-    const int l = (int)(r % L), g = (int)(r / L);
+  ROW_LOOP(n_ct * L) {
+    const int l = row % L, g = row / L;
     const ModD m = modx(tab[l]);
     const u64* p = prep + ((size_t)g * 3 * L) * n;
     const double U = u2d(p[((size_t)0 * L + l) * n + k]);
@@ -150,14 +153,11 @@ __global__ void k_enc_combine(const u64* __restrict__ prep, const u64* __restric
 // Decryption prologue (NTT domain): x = c0 + c1 s per limb.
 __global__ void k_dec_prep(const u64* __restrict__ ct, const u64* __restrict__ sk, u64* X, int n_ct, int L, const ModTab* __restrict__ tab, int logn) {
   const i64 n = 1 << logn;
-  const i64 total = (i64)n_ct * L * n;
-  for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
-    const i64 k = idx & (n - 1);
-    const i64 r = idx >> logn;
-    const int l = (int)(r % L), g = (int)(r / L);
+  ROW_LOOP(n_ct * L) {
+    const int l = row % L, g = row / L;
     const ModD m = modx(tab[l]);
     const double c0 = u2d(ct[((size_t)g * 2 * L + l) * n + k]), c1 = u2d(ct[((size_t)g * 2 * L + L + l) * n + k]);
-    X[idx] = d2u(canon(c0 + mulmod(c1, u2d(sk[(size_t)l * n + k]), m), m));
+    X[(size_t)row * n + k] = d2u(canon(c0 + mulmod(c1, u2d(sk[(size_t)l * n + k]), m), m));
   }
 }
 
@@ -180,6 +180,9 @@ __global__ void k_slots_scatter(const u64* __restrict__ Mntt, const u32* __restr
 
 // ------------------------------------------------------------------ launchers
 static dim3 grid_for(i64 total) { return dim3((unsigned)std::min<i64>((total + 255) / 256, 256 * 64)); }
+static dim3 grid_rows(i64 rows, i64 n) {
+  return dim3((unsigned)std::max<i64>(1, (n + 256 * ROW_EPT - 1) / (256 * ROW_EPT)), (unsigned)std::min<i64>(std::max<i64>(rows, 1), 65535));
+}
 
 #define HSX_LAUNCH(KERNEL, GRID, STREAM, ...)                                  \
   do {                                                                         \
@@ -204,20 +207,20 @@ void launch_pack_slots(const hs_ctx* c, const PackArgs& a, int nchunks, hipStrea
 }
 void launch_lift_plain(const hs_ctx* c, const u64* coef, int n_plain, u64* out, hipStream_t st) {
   if (n_plain <= 0) return;
-  HSX_LAUNCH(k_lift_plain, grid_for((i64)n_plain * c->L * c->N), st, coef, n_plain, out, c->L, c->t, (const ModTab*)c->d_tab, c->logn);
+  HSX_LAUNCH(k_lift_plain, grid_rows((i64)n_plain * c->L, c->N), st, coef, n_plain, out, c->L, c->t, (const ModTab*)c->d_tab, c->logn);
 }
 void launch_enc_prep(const hs_ctx* c, const u64* mcoef, const int* samples, int n_ct, u64* out, hipStream_t st) {
   if (n_ct <= 0) return;
-  HSX_LAUNCH(k_enc_prep, grid_for((i64)n_ct * c->L * c->N), st, mcoef, samples, n_ct, out, c->L, c->t, c->q_mod_t, (const double2*)c->d_qdt,
+  HSX_LAUNCH(k_enc_prep, grid_rows((i64)n_ct * c->L, c->N), st, mcoef, samples, n_ct, out, c->L, c->t, c->q_mod_t, (const double2*)c->d_qdt,
              (const ModTab*)c->d_tab, c->logn);
 }
 void launch_enc_combine(const hs_ctx* c, const u64* prep, const u64* pk, u64* out, int n_ct, hipStream_t st) {
   if (n_ct <= 0) return;
-  HSX_LAUNCH(k_enc_combine, grid_for((i64)n_ct * c->L * c->N), st, prep, pk, out, n_ct, c->L, (const ModTab*)c->d_tab, c->logn);
+  HSX_LAUNCH(k_enc_combine, grid_rows((i64)n_ct * c->L, c->N), st, prep, pk, out, n_ct, c->L, (const ModTab*)c->d_tab, c->logn);
 }
 void launch_dec_prep(const hs_ctx* c, const u64* ct, const u64* sk, u64* X, int n_ct, hipStream_t st) {
   if (n_ct <= 0) return;
-  HSX_LAUNCH(k_dec_prep, grid_for((i64)n_ct * c->L * c->N), st, ct, sk, X, n_ct, c->L, (const ModTab*)c->d_tab, c->logn);
+  HSX_LAUNCH(k_dec_prep, grid_rows((i64)n_ct * c->L, c->N), st, ct, sk, X, n_ct, c->L, (const ModTab*)c->d_tab, c->logn);
 }
 void launch_slots_scatter(const hs_ctx* c, const u64* Mntt, const int* rm, const i64* pinfo, int nparts, i64* y, hipStream_t st) {
   if (nparts <= 0) return;

@@ -336,43 +336,45 @@ __global__ void __launch_bounds__(NT) k_encrypt(const u64* __restrict__ mcoef, c
 
 // ------------------------------------------------------------------ slot-wise products
 // out[g] = x[g] (.) pt[g], both polynomials; x, out: [n][2][L][N]; pt: [n][L][N].
+// grid (N / (256 EW_EPT), rows): a block's row (g, w, l) is uniform; rows loop over gridDim.y.
+static constexpr int EW_EPT = 4;
 __global__ void k_mul_plain(const u64* __restrict__ x, const u64* __restrict__ pt, u64* out, i64 n_ct, int L,
                             int pt_stride_ct, const ModTab* __restrict__ tab, int logn) {
   const i64 n = 1 << logn;
-  const i64 total = n_ct * 2 * L * n;
-  for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
-    const i64 k = idx & (n - 1);
-    const i64 r = idx >> logn;         // (g, w, l)
-    const int l = (int)(r % L);
-    const i64 g = r / (2 * L);
-    const ModTab tb = tab[l];
-    const ModD m = mod_of(tb);
-    const double a = u2d(x[idx]);
-    const double b = u2d(pt[(g * pt_stride_ct + l) * n + k]);
-    out[idx] = d2u(canon(mulmod(a, b, m), m));
+  for (i64 row = blockIdx.y; row < n_ct * 2 * L; row += gridDim.y) {
+    const int l = (int)(row % L);
+    const i64 g = row / (2 * L);
+    const ModD m = mod_of(tab[l]);
+    const u64* xr = x + row * n;
+    const u64* pr = pt + (g * pt_stride_ct + l) * n;
+    u64* orow = out + row * n;
+#pragma unroll
+    for (int e = 0; e < EW_EPT; e++) {
+      const i64 k = ((i64)blockIdx.x * EW_EPT + e) * blockDim.x + threadIdx.x;
+      if (k < n) orow[k] = d2u(canon(mulmod(u2d(xr[k]), u2d(pr[k]), m), m));
+    }
   }
 }
 
 // res[P] = sum over the chunks g of partition P of w[g] (.) mask[g]   (mask == nullptr: plain sum)
+// grid (N / 256, 2 L, partitions): a block's row (w, l) is uniform; one element per thread, so that
+// the chain over the partition's chunks (a pointer, then the words) runs in many threads at once.
 __global__ void k_mask_acc(const u64* const* __restrict__ w, const u64* __restrict__ mask, const int* __restrict__ part_chunk0,
                            const int* __restrict__ part_nchunks, u64* res, int L, const ModTab* __restrict__ tab, int logn) {
   const int n = 1 << logn;
-  const int P = blockIdx.y;
-  const int per_poly = 2 * L * n;
+  const int P = blockIdx.z, row = blockIdx.y;   // row = w L + l
+  const int l = row % L;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
   const int g0 = part_chunk0[P], ng = part_nchunks[P];
-  for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < per_poly; idx += gridDim.x * blockDim.x) {
-    const int k = idx & (n - 1);
-    const int l = (idx >> logn) % L;
-    const ModTab tb = tab[l];
-    const ModD m = mod_of(tb);
-    double acc = 0.0;
-    for (int g = g0; g < g0 + ng; g++) {
-      double v = u2d(w[g][idx]);
-      if (mask) v = mulmod(v, u2d(mask[((size_t)g * L + l) * n + k]), m);
-      acc = reduce(acc + v, m);
-    }
-    res[(size_t)P * per_poly + idx] = d2u(canon(acc, m));
+  const ModD m = mod_of(tab[l]);
+  double acc = 0.0;
+  for (int g = g0; g < g0 + ng; g++) {
+    double v = u2d(w[g][(size_t)row * n + k]);
+    if (mask) v = mulmod(v, u2d(mask[((size_t)g * L + l) * n + k]), m);
+    acc = reduce(acc + v, m);
   }
+  res[((size_t)P * 2 * L + row) * n + k] = d2u(canon(acc, m));
 }
 
 // ------------------------------------------------------------------ rotation: key switching
@@ -617,7 +619,7 @@ __global__ void k_dec_round(const u64* __restrict__ X, u64* M, int n_ct, int L, 
   const int n = 1 << logn;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= n_ct * n) return;
-  const int g = gid / n, k = gid % n;
+  const int g = gid >> logn, k = gid & (n - 1);
   u64 S[16];
   for (int w = 0; w < W; w++) S[w] = 0;
   u64 asum = 0;
@@ -683,7 +685,8 @@ __global__ void k_dec_round(const u64* __restrict__ X, u64* M, int n_ct, int L, 
     }
     kq++;
   }
-  M[gid] = (asum + kq) % t;
+  // asum + kq < (L + 2) t: a 32-bit remainder when that stays below 2^32 (t < 2^26, L < 62)
+  M[gid] = (t < (1ull << 26) && L < 62) ? (u64)((u32)(asum + kq) % (u32)t) : (asum + kq) % t;
 }
 
 // Decode (forward mod-t NTT), take slot p for the sorted rows of partition P, scatter with the row
@@ -861,20 +864,19 @@ void launch_encrypt(const hs_ctx* c, const u64* mcoef, const int* samples, const
 
 void launch_mul_plain(const hs_ctx* c, const u64* x, const u64* pt, u64* out, i64 n_ct, int pt_stride_ct, hipStream_t st) {
   if (n_ct <= 0) return;
-  const i64 total = n_ct * 2 * c->L * (i64)c->N;
-  const i64 blocks = std::min<i64>((total + 255) / 256, 256 * 64);
+  const i64 rows = n_ct * 2 * c->L;
+  const dim3 grid((unsigned)std::max<i64>(1, ((i64)c->N + 256 * EW_EPT - 1) / (256 * EW_EPT)), (unsigned)std::min<i64>(rows, 65535));
   ProfScope _prof("k_mul_plain", st);
-  hipLaunchKernelGGL(k_mul_plain, dim3((unsigned)blocks), dim3(256), 0, st, x, pt, out, n_ct, c->L, pt_stride_ct, (const ModTab*)c->d_tab, c->logn);
+  hipLaunchKernelGGL(k_mul_plain, grid, dim3(256), 0, st, x, pt, out, n_ct, c->L, pt_stride_ct, (const ModTab*)c->d_tab, c->logn);
   HS_CHECK_HIP(hipGetLastError());
 }
 
 void launch_mask_acc(const hs_ctx* c, const u64* const* w, const u64* mask, const int* part_chunk0, const int* part_nchunks,
                      u64* res, int nparts, hipStream_t st) {
   if (nparts <= 0) return;
-  const int per = 2 * c->L * (int)c->N;
-  const int bx = std::min((per + 255) / 256, 1024);
+  const dim3 grid((unsigned)std::max<i64>(1, ((i64)c->N + 255) / 256), (unsigned)(2 * c->L), (unsigned)nparts);
   ProfScope _prof("k_mask_acc", st);
-  hipLaunchKernelGGL(k_mask_acc, dim3(bx, nparts), dim3(256), 0, st, w, mask, part_chunk0, part_nchunks, res, c->L, (const ModTab*)c->d_tab, c->logn);
+  hipLaunchKernelGGL(k_mask_acc, grid, dim3(256), 0, st, w, mask, part_chunk0, part_nchunks, res, c->L, (const ModTab*)c->d_tab, c->logn);
   HS_CHECK_HIP(hipGetLastError());
 }
 
