@@ -37,7 +37,7 @@ def lib():
         build()
         L = ctypes.CDLL(_SO)
         sig = {
-            "orc_ctx_new": (vp, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int]),
+            "orc_ctx_new": (vp, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]),
             "orc_ctx_free": (None, [vp]),
             "orc_n_moduli": (ctypes.c_int, [vp]),
             "orc_n_aux": (ctypes.c_int, [vp]),
@@ -78,6 +78,7 @@ def lib():
             "orc_matrix_new": (vp, [vp, ctypes.c_int64, ctypes.c_int64, i64p, i32p, i64p, ctypes.c_int, ctypes.c_uint64]),
             "orc_matrix_free": (None, [vp]),
             "orc_matrix_n_parts": (ctypes.c_int, [vp]),
+            "orc_matrix_n_groups": (ctypes.c_int, [vp]),
             "orc_matrix_n_chunks": (ctypes.c_int, [vp]),
             "orc_matrix_chunk": (None, [vp, ctypes.c_int, i64p]),
             "orc_matrix_pt": (None, [vp, ctypes.c_int, u64p]),
@@ -148,9 +149,10 @@ def chunks(CP, s, uniform=False):
 class Context:
     """Scheme parameters + keys (single key-set)."""
 
-    def __init__(self, logn, L, qbits, K, pbits=None, t=65537, agg_mode=0):
+    def __init__(self, logn, L, qbits, K, pbits=None, t=65537, agg_mode=0, slot_rows=1):
         self.logn, self.N, self.L, self.K, self.t = logn, 1 << logn, L, K, t
-        self.h = lib().orc_ctx_new(logn, L, qbits, K, pbits or qbits, t, agg_mode)
+        self.slot_rows = slot_rows
+        self.h = lib().orc_ctx_new(logn, L, qbits, K, pbits or qbits, t, agg_mode, slot_rows)
         if not self.h:
             raise ValueError("oracle: unsupported parameters")
         self.agg_mode = agg_mode
@@ -330,6 +332,10 @@ class Matrix:
     def n_chunks(self):
         return lib().orc_matrix_n_chunks(self.h)
 
+    def n_groups(self):
+        """Result ciphertexts: one per row partition, or per pair of partitions (two slot rows)."""
+        return lib().orc_matrix_n_groups(self.h)
+
     def chunk(self, k):
         out = np.zeros(4, np.int64)
         lib().orc_matrix_chunk(self.h, k, _p(out, i64p))
@@ -354,7 +360,7 @@ class Matrix:
 
     def he_spmv(self, x):
         x = np.ascontiguousarray(x, np.uint64)
-        out = np.zeros(self.n_parts() * self.ctx.ct_size(), np.uint64)
+        out = np.zeros(self.n_groups() * self.ctx.ct_size(), np.uint64)
         stats = np.zeros(2, np.int64)
         lib().orc_he_spmv(self.ctx.h, self.h, _p(x, u64p), _p(out, u64p), _p(stats, i64p))
         return out, {"key_switches": int(stats[0]), "rotations": int(stats[1])}

@@ -381,6 +381,7 @@ std::vector<u64> sample_uniform(u64 seed, u32 purpose, u64 index, u64 q, u64 N) 
 struct Ctx {
   int logn = 0; u64 N = 0; u64 t = 0;
   int L = 0, K = 0, alpha = 0, dnum = 0, qbits = 0, pbits = 0, agg_mode = 0;
+  int slot_rows = 1;             /* 1: data in slot row 0 only; 2: two row partitions per ciphertext */
   int n_aux = 0;                 /* extra primes for the exact ct x ct tensor */
   std::vector<u64> mod;          /* [L data primes][K special primes][n_aux tensor primes] */
   std::vector<NttTable> tab;
@@ -439,9 +440,11 @@ std::vector<u64> ntt_of_int(const Ctx& c, const std::vector<i64>& a, int m) {
   return r;
 }
 
-bool ctx_init(Ctx& c, int logn, int L, int qbits, int K, int pbits, u64 t, int agg_mode) {
+bool ctx_init(Ctx& c, int logn, int L, int qbits, int K, int pbits, u64 t, int agg_mode, int slot_rows = 1) {
   c.logn = logn; c.N = 1ULL << logn; c.t = t; c.L = L; c.K = K; c.qbits = qbits; c.pbits = pbits;
   c.agg_mode = agg_mode;
+  if (slot_rows != 1 && slot_rows != 2) return false;
+  c.slot_rows = slot_rows;
   c.alpha = K; c.dnum = (L + K - 1) / K;
   if (t % (2 * c.N) != 1 || !is_prime(t)) return false;
   /* Prime choice: the primes q = 1 mod 2N below 2^b in decreasing order; the first K are the
@@ -966,14 +969,32 @@ std::vector<Chunk> make_chunks(const Cssc& m, i64 s, int uniform) {
 /* Slot k of chunk: block b = k div h, sorted row p = k mod h; value of CSSC column start+b at
    row p when present, else padding. get(idx) maps a CSSC entry index to the slot value. */
 template <class F>
-std::vector<u64> chunk_slots(const Cssc& m, const Chunk& ch, u64 N, u64 t, F get) {
-  std::vector<u64> slots(N, 0);
+void chunk_slots_into(std::vector<u64>& slots, u64 off, const Cssc& m, const Chunk& ch, u64 t, F get) {
   for (i64 b = 0; b < ch.c; b++) {
     int col = ch.start + (int)b;
+    if (col >= m.Lw) break;   /* a joint chunk may reach past this partition's columns */
     i64 nn = m.CP[col + 1] - m.CP[col];
-    for (i64 p = 0; p < std::min(nn, ch.h); p++) slots[b * ch.h + p] = smod(get(m.CP[col] + p), t);
+    for (i64 p = 0; p < std::min(nn, ch.h); p++) slots[off + b * ch.h + p] = smod(get(m.CP[col] + p), t);
   }
+}
+template <class F>
+std::vector<u64> chunk_slots(const Cssc& m, const Chunk& ch, u64 N, u64 t, F get) {
+  std::vector<u64> slots(N, 0);
+  chunk_slots_into(slots, 0, m, ch, t, get);
   return slots;
+}
+
+/* The joint column profile of two row partitions packed into one ciphertext (slot row 0 and slot
+   row 1): column j has height max(NNZ_A[j], NNZ_B[j]) (heights past a partition's last column are
+   0), so generateChunk on it gives chunks that fit both rows with the same rotation schedule. */
+Cssc joint_profile(const Cssc& a, const Cssc& b) {
+  Cssc j; j.Lw = std::max(a.Lw, b.Lw);
+  j.CP.assign(j.Lw + 1, 0);
+  for (int c = 0; c < j.Lw; c++) {
+    i64 na = c < a.Lw ? a.CP[c + 1] - a.CP[c] : 0, nb = c < b.Lw ? b.CP[c + 1] - b.CP[c] : 0;
+    j.CP[c + 1] = j.CP[c] + std::max(na, nb);
+  }
+  return j;
 }
 
 u64 num_bits(u64 c) { u64 n = 0; while (c) { n++; c >>= 1; } return n; }
@@ -1012,10 +1033,14 @@ std::vector<u64> total_sum_steps(const Ctx& c, i64 r, i64 ccols) {
   return out;
 }
 
-struct Partition { i64 row0, rows; Cssc m; std::vector<Chunk> chunks; };
+struct Partition { i64 row0, rows; Cssc m; };
+/* One result ciphertext: partition pa in slot row 0 and, with two slot rows, partition pb (or -1)
+   in slot row 1, sharing the chunks. */
+struct Group { int pa, pb; std::vector<Chunk> chunks; };
 struct Matrix {
   i64 R = 0, C = 0; int encrypted = 0;
   std::vector<Partition> parts;
+  std::vector<Group> groups;
   std::vector<std::vector<u64>> pts;  /* per chunk: NTT-form plaintext [L][N] or ciphertext */
   std::vector<std::vector<u64>> masks; /* per chunk: mask plaintext (paper mode) */
 };
@@ -1025,9 +1050,9 @@ struct Matrix {
 /* ====================================================================== C API (for tests) */
 extern "C" {
 
-void* orc_ctx_new(int logn, int L, int qbits, int K, int pbits, u64 t, int agg_mode) {
+void* orc_ctx_new(int logn, int L, int qbits, int K, int pbits, u64 t, int agg_mode, int slot_rows) {
   Ctx* c = new Ctx();
-  if (!ctx_init(*c, logn, L, qbits, K, pbits, t, agg_mode)) { delete c; return nullptr; }
+  if (!ctx_init(*c, logn, L, qbits, K, pbits, t, agg_mode, slot_rows)) { delete c; return nullptr; }
   return c;
 }
 void orc_ctx_free(void* h) { delete (Ctx*)h; }
@@ -1160,32 +1185,48 @@ void* orc_matrix_new(void* h, i64 R, i64 C, const i64* row_ptr, const i32* col, 
     std::vector<i64> rp(P.rows + 1);
     for (i64 i = 0; i <= P.rows; i++) rp[i] = row_ptr[r0 + i] - row_ptr[r0];
     P.m = csr_to_cssc(P.rows, rp.data(), col + row_ptr[r0], val + row_ptr[r0]);
-    P.chunks = make_chunks(P.m, s, c->agg_mode == 1);
-    for (const Chunk& ch : P.chunks) {
-      const Cssc& m = P.m;
-      std::vector<u64> slots = chunk_slots(m, ch, c->N, c->t, [&](i64 k) { return m.VA[k]; });
+    M->parts.push_back(P);
+  }
+  const int nP = (int)M->parts.size();
+  for (int p = 0; p < nP; p += c->slot_rows) {
+    Group G; G.pa = p; G.pb = (c->slot_rows == 2 && p + 1 < nP) ? p + 1 : -1;
+    G.chunks = G.pb < 0 ? make_chunks(M->parts[p].m, s, c->agg_mode == 1)
+                        : make_chunks(joint_profile(M->parts[p].m, M->parts[G.pb].m), s, c->agg_mode == 1);
+    for (const Chunk& ch : G.chunks) {
+      std::vector<u64> slots(c->N, 0);
+      const Cssc& ma = M->parts[G.pa].m;
+      chunk_slots_into(slots, 0, ma, ch, c->t, [&](i64 k) { return ma.VA[k]; });
+      if (G.pb >= 0) {
+        const Cssc& mb = M->parts[G.pb].m;
+        chunk_slots_into(slots, c->N / 2, mb, ch, c->t, [&](i64 k) { return mb.VA[k]; });
+      }
       std::vector<u64> mcoef = encode(*c, slots);
       if (encrypted) M->pts.push_back(encrypt(*c, mcoef, mat_seed, ct_idx));
       else M->pts.push_back(plain_ntt(*c, mcoef));
       ct_idx++;
       if (c->agg_mode == 0) {
         std::vector<u64> ms(c->N, 0);
-        for (i64 p = 0; p < ch.h; p++) ms[p] = 1;
+        for (i64 p2 = 0; p2 < ch.h; p2++) {
+          ms[p2] = 1;
+          if (G.pb >= 0) ms[c->N / 2 + p2] = 1;
+        }
         M->masks.push_back(plain_ntt(*c, encode(*c, ms)));
       }
     }
-    M->parts.push_back(P);
+    M->groups.push_back(G);
   }
   return M;
 }
 void orc_matrix_free(void* m) { delete (Matrix*)m; }
 int orc_matrix_n_parts(void* m) { return (int)((Matrix*)m)->parts.size(); }
+int orc_matrix_n_groups(void* m) { return (int)((Matrix*)m)->groups.size(); }
 int orc_matrix_n_chunks(void* m) { return (int)((Matrix*)m)->pts.size(); }
-/* chunk k (global numbering): out = (partition, start, c, h) */
+/* chunk k (global numbering): out = (group = result ciphertext, start, c, h); with one slot row a
+   group is a partition */
 void orc_matrix_chunk(void* m, int k, i64* out4) {
   Matrix* M = (Matrix*)m; int g = 0;
-  for (size_t p = 0; p < M->parts.size(); p++)
-    for (const Chunk& ch : M->parts[p].chunks) {
+  for (size_t p = 0; p < M->groups.size(); p++)
+    for (const Chunk& ch : M->groups[p].chunks) {
       if (g == k) { out4[0] = (i64)p; out4[1] = ch.start; out4[2] = ch.c; out4[3] = ch.h; return; }
       g++;
     }
@@ -1197,24 +1238,30 @@ void orc_matrix_mask(void* m, int k, u64* out) { Matrix* M = (Matrix*)m; memcpy(
    index = global chunk number.  out: [n_chunks][2][L][N]. */
 void orc_encrypt_vector(void* h, void* m, const i64* v, u64 seed, u64* out) {
   Ctx* c = (Ctx*)h; Matrix* M = (Matrix*)m; u64 ctsz = 2ULL * c->L * c->N; u64 g = 0;
-  for (const Partition& P : M->parts)
-    for (const Chunk& ch : P.chunks) {
-      const Cssc& mm = P.m;
-      std::vector<u64> slots = chunk_slots(mm, ch, c->N, c->t, [&](i64 k) { return v[mm.CI[k]]; });
+  for (const Group& G : M->groups)
+    for (const Chunk& ch : G.chunks) {
+      std::vector<u64> slots(c->N, 0);
+      const Cssc& ma = M->parts[G.pa].m;
+      chunk_slots_into(slots, 0, ma, ch, c->t, [&](i64 k) { return v[ma.CI[k]]; });
+      if (G.pb >= 0) {
+        const Cssc& mb = M->parts[G.pb].m;
+        chunk_slots_into(slots, c->N / 2, mb, ch, c->t, [&](i64 k) { return v[mb.CI[k]]; });
+      }
       auto ct = encrypt(*c, encode(*c, slots), seed, g);
       memcpy(out + g * ctsz, ct.data(), ctsz * 8);
       g++;
     }
 }
 
-/* Cloud: per chunk HE product, totalSum, mask (paper mode), sum per partition.
-   x: [n_chunks][2][L][N]; out: [n_parts][2][L][N].  stats (optional): [key switches, rotations]. */
+/* Cloud: per chunk HE product, totalSum, mask (paper mode), sum per group (partition, or pair of
+   partitions with two slot rows).  x: [n_chunks][2][L][N]; out: [n_groups][2][L][N].  stats
+   (optional): [key switches, rotations]. */
 void orc_he_spmv(void* h, void* m, const u64* x, u64* out, i64* stats) {
   Ctx* c = (Ctx*)h; Matrix* M = (Matrix*)m; u64 ctsz = 2ULL * c->L * c->N;
   int g = 0, nks = 0, nrot = 0;
-  for (size_t p = 0; p < M->parts.size(); p++) {
+  for (size_t p = 0; p < M->groups.size(); p++) {
     std::vector<u64> res(ctsz, 0);
-    for (const Chunk& ch : M->parts[p].chunks) {
+    for (const Chunk& ch : M->groups[p].chunks) {
       std::vector<u64> xv(x + (u64)g * ctsz, x + (u64)(g + 1) * ctsz);
       std::vector<u64> prod = M->encrypted ? ct_mul_ct(*c, M->pts[g], xv) : ct_mul_plain(*c, xv, M->pts[g]);
       std::vector<u64> w = total_sum(*c, prod, ch.h, ch.c, &nks, &nrot);
@@ -1231,15 +1278,21 @@ void orc_he_spmv(void* h, void* m, const u64* x, u64* out, i64* stats) {
    nonzeros get 0.  y: [R], centered in (-t/2, t/2]. */
 void orc_decrypt_result(void* h, void* m, const u64* res, i64* y) {
   Ctx* c = (Ctx*)h; Matrix* M = (Matrix*)m; u64 ctsz = 2ULL * c->L * c->N;
-  for (size_t p = 0; p < M->parts.size(); p++) {
-    const Partition& P = M->parts[p];
-    std::vector<u64> ct(res + p * ctsz, res + (p + 1) * ctsz);
+  for (size_t gi = 0; gi < M->groups.size(); gi++) {
+    const Group& G = M->groups[gi];
+    std::vector<u64> ct(res + gi * ctsz, res + (gi + 1) * ctsz);
     std::vector<u64> slots = decode(*c, decrypt(*c, ct));
-    i64 nz = P.m.Lw > 0 ? P.m.CP[1] - P.m.CP[0] : 0;
-    for (i64 q = 0; q < P.rows; q++) {
-      i64 row = P.row0 + P.m.RM[q];
-      if (q < nz) { u64 s = slots[q]; y[row] = s > c->t / 2 ? (i64)s - (i64)c->t : (i64)s; }
-      else y[row] = 0;
+    for (int half = 0; half < 2; half++) {
+      const int pi = half == 0 ? G.pa : G.pb;
+      if (pi < 0) continue;
+      const Partition& P = M->parts[pi];
+      const u64 off = half == 0 ? 0 : c->N / 2;
+      i64 nz = P.m.Lw > 0 ? P.m.CP[1] - P.m.CP[0] : 0;
+      for (i64 q = 0; q < P.rows; q++) {
+        i64 row = P.row0 + P.m.RM[q];
+        if (q < nz) { u64 s = slots[off + q]; y[row] = s > c->t / 2 ? (i64)s - (i64)c->t : (i64)s; }
+        else y[row] = 0;
+      }
     }
   }
 }

@@ -639,6 +639,63 @@ def test_spmv_with_exact_step_keys_one_key_switch_per_rotation():
     assert res[0]["key_switches"] > res[0]["rotations"]
 
 
+def joint_chunks_python(cssc_a, cssc_b, s, uniform):
+    """generateChunk (padded fit rule) on the column heights max(NNZ_A[j], NNZ_B[j])."""
+    def heights(cp):
+        return [cp[j + 1] - cp[j] for j in range(len(cp) - 1)]
+    ha, hb = heights(cssc_a[3]), heights(cssc_b[3])
+    nc = max(len(ha), len(hb))
+    hj = [max(ha[j] if j < len(ha) else 0, hb[j] if j < len(hb) else 0) for j in range(nc)]
+    out, i = [], 0
+    while i < nc:
+        start, h = i, (hj[0] if uniform else hj[i])
+        while i < nc and h * (i - start + 1) <= s:
+            i += 1
+        out.append((start, i - start, h))
+    return out
+
+
+@pytest.mark.parametrize("agg,R,C,nnz", [(0, 700, 300, 2500), (0, 512, 400, 1800), (1, 600, 200, 1500), (0, 300, 300, 600)])
+def test_two_slot_rows_protocol(agg, R, C, nnz):
+    """Two row partitions per ciphertext (slot rows 0 and 1, joint chunks): the decrypted product is
+    the integer SpMV, with one result ciphertext per pair of partitions and no more chunks than the
+    one-row layout needs."""
+    g = np.random.default_rng(R + C + agg)
+    rp, col, val = W.uniform_matrix(R, C, nnz, 15, g)
+    if R == 300:   # second partition without nonzeros: rows 256.. empty
+        keep = np.repeat(np.arange(R), np.diff(rp)) < 256
+        rows = np.repeat(np.arange(R), np.diff(rp))[keep]
+        rp, col, val = W._csr_from_rows_cols(R, rows, col[keep], val[keep])
+    w = dict(R=R, C=C, row_ptr=rp, col=col, val=val, v=g.integers(-15, 16, C))
+    res = {}
+    for rows_ in (1, 2):
+        c = O.Context(9, 3, 50, 1, agg_mode=agg, slot_rows=rows_)
+        c.keygen(5)
+        M = O.Matrix(c, R, C, rp, col, val, False, 31)
+        x = M.encrypt_vector(w["v"], 41)
+        out, stats = M.he_spmv(x)
+        assert np.array_equal(M.decrypt_result(out), W.spmv_mod_t(w)), rows_
+        res[rows_] = (M.n_parts(), M.n_groups(), M.n_chunks(), stats)
+        if rows_ == 2:
+            s = c.N // 2
+            parts = []
+            for r0 in range(0, R, s):
+                r1 = min(R, r0 + s)
+                prp = rp[r0:r1 + 1] - rp[r0]
+                sl = slice(rp[r0], rp[r1])
+                parts.append(O.cssc(r1 - r0, prp, col[sl], val[sl]))
+            want = []
+            for p in range(0, len(parts), 2):
+                if p + 1 < len(parts):
+                    want += [(p // 2,) + ch for ch in joint_chunks_python(parts[p], parts[p + 1], s, agg == 1)]
+                else:
+                    want += [(p // 2,) + tuple(ch) for ch in O.chunks(parts[p][3], s, agg == 1)]
+            assert [M.chunk(k) for k in range(M.n_chunks())] == want
+    (p1, g1, n1, s1), (p2, g2, n2, s2) = res[1], res[2]
+    assert p1 == p2 and g1 == p1 and g2 == (p1 + 1) // 2
+    assert n2 <= n1 and s2["rotations"] <= s1["rotations"]
+
+
 @pytest.mark.parametrize("case", ["empty", "one", "emptyrows", "rect", "partitions", "dense_row"])
 def test_spmv_edge_cases_paper_aggregation(case):
     c = O.Context(9, 3, 50, 1, agg_mode=0)   # s = 256 slots per chunk
