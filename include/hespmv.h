@@ -67,6 +67,13 @@ typedef struct hs_params {
   uint32_t agg_mode; /* 0 = paper aggregation: chunk heights NNZ[start] and masks (Alg. Aggregation);
                         1 = uniform heights NNZ[0] in a partition and no masks (one fewer ct x pt,
                             needed when Q/t leaves too little noise room for the mask product) */
+  uint32_t slot_rows; /* 0 or 1 = the paper's layout: a partition's chunks in slot row 0, row 1 zero;
+                         2 = two row partitions per ciphertext: partition 2g in slot row 0 and
+                             2g + 1 in slot row 1, chunks generated on the joint column heights
+                             max(NNZ_2g[j], NNZ_2g+1[j]) so that one rotation schedule serves both
+                             rows (a rotation turns each slot row on its own); half the chunks,
+                             products and rotations for matrices of two or more partitions, one
+                             result ciphertext per pair.  Decrypted results are the same. */
 } hs_params;
 
 typedef struct hs_ctx hs_ctx;
@@ -135,8 +142,11 @@ int hs_cssc_pack(hs_ctx* ctx, int64_t rows, int64_t cols, const int64_t* row_ptr
    before the context's hs_ctx_destroy. */
 void hs_matrix_destroy(hs_matrix* m);
 int hs_matrix_info(const hs_matrix* m, int64_t* n_parts, int64_t* n_chunks);
-/* Chunk k (global numbering over partitions): out4 = (partition, first CSSC column, columns c,
-   height h). */
+/* Result ciphertexts of hs_he_spmv for this matrix: the row partitions (slot_rows <= 1) or pairs of
+   them (slot_rows = 2). */
+int hs_matrix_groups(const hs_matrix* m, int64_t* n_groups);
+/* Chunk k (global numbering over groups): out4 = (group = result ciphertext, first CSSC column,
+   columns c, height h); a group is a row partition unless slot_rows = 2. */
 int hs_matrix_chunk(const hs_matrix* m, int64_t k, int64_t out4[4]);
 /* The CSSC column-index array (all partitions, concatenated) that Client A sends to Client B
    (Alg. "Sparse Matrix-Vector Multiplication"), into host memory. *len receives nnz. */
@@ -160,8 +170,9 @@ int hs_encrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const int64
 /* Encrypted SpMV: for each chunk the slot-wise product with the encrypted vector (HE-CMult, or
    HE-Mult + relinearisation for an encrypted matrix), the intra-chunk totalSum by rotations of
    e*h slots (Alg. Aggregation; each rotation applied as its binary digits in ascending order, one
-   key switch per digit), the mask product (agg_mode 0), and the sum over the chunks of each
-   partition.  *y receives one ciphertext per row partition. */
+   key switch per digit, or as one key switch with an exact-step key), the mask product
+   (agg_mode 0), and the sum over the chunks of each group.  *y receives one ciphertext per group
+   (hs_matrix_groups: a row partition, or a pair of them with slot_rows = 2). */
 int hs_he_spmv(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* x,
                void* stream, hs_ctvec** y);
 
@@ -213,8 +224,9 @@ int hs_server_stats(hs_server* s, int64_t out[5], double* now);
 void hs_server_destroy(hs_server* s);
 
 /* ---------------------------------------------------------------- key holder */
-/* Decrypt the per-partition results and scatter them with the row map: out (device int64[rows])
-   receives y = A v reduced into (-t/2, t/2]; rows without nonzeros receive 0. */
+/* Decrypt the per-group results and scatter each partition's slot row with its row map: out
+   (device int64[rows]) receives y = A v reduced into (-t/2, t/2]; rows without nonzeros receive
+   0. */
 int hs_decrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* y,
                int64_t* out, int64_t rows, void* stream);
 

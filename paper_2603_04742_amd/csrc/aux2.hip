@@ -84,12 +84,17 @@ __global__ void k_pack_slots(PackArgs A, int nchunks, const u32* __restrict__ sl
     const i64 k = idx & (n - 1);
     const int mode = A.mode == 3 ? (g < A.nG ? 0 : 2) : A.mode;
     const i64* cd = A.chunk + 8 * (A.mode == 3 && g >= A.nG ? g - A.nG : g);
-    const i64 start = cd[0], cols = cd[1], h = cd[2], cpo = cd[3], nzo = cd[4];
+    const i64 start = cd[0], cols = cd[1], h = cd[2];
+    const int srow = k >= n / 2;
+    const i64 kk = k - srow * (n / 2);
+    const i64 cpo = srow ? cd[6] : cd[3], nzo = srow ? cd[7] : cd[4];
     i64 val = 0;
-    if (mode == 2) {
-      val = (k < h) ? 1 : 0;
-    } else if (k < h * cols && k < n / 2) {
-      const i64 b = k / h, p = k % h;
+    if (cpo < 0) {
+      val = 0;   // no partition in this slot row
+    } else if (mode == 2) {
+      val = (kk < h) ? 1 : 0;
+    } else if (kk < h * cols) {
+      const i64 b = kk / h, p = kk % h;
       const i64 c0 = A.cp[cpo + start + b], c1 = A.cp[cpo + start + b + 1];
       if (p < c1 - c0) {
         const i64 e = nzo + c0 + p;
@@ -167,11 +172,13 @@ __global__ void k_slots_scatter(const u64* __restrict__ Mntt, const u32* __restr
   const i64 n = 1 << logn;
   const int P = blockIdx.y;
   if (P >= nparts) return;
-  const i64 row0 = pinfo[4 * P], rows = pinfo[4 * P + 1], nz = pinfo[4 * P + 2], rm0 = pinfo[4 * P + 3];
+  // pinfo per partition: (row0, rows, nonzero rows, row-map offset, group, slot offset)
+  const i64* pi = pinfo + 6 * P;
+  const i64 row0 = pi[0], rows = pi[1], nz = pi[2], rm0 = pi[3], grp = pi[4], off = pi[5];
   for (i64 p = blockIdx.x * (i64)blockDim.x + threadIdx.x; p < rows; p += (i64)gridDim.x * blockDim.x) {
     i64 v = 0;
     if (p < nz) {
-      v = (i64)Mntt[(size_t)P * n + slot_pos[p]];
+      v = (i64)Mntt[(size_t)grp * n + slot_pos[off + p]];
       if (v > (i64)(t / 2)) v -= (i64)t;
     }
     y[row0 + rm[rm0 + p]] = v;

@@ -712,6 +712,7 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
     try {
       std::vector<int> rank(std::max<i64>(rows, 1), 0);
       std::vector<i64> part_cp_off, part_nnz_off;
+      std::vector<std::vector<i64>> cps;
       for (i64 r0 = 0, p = 0; r0 < rows; r0 += s, p++) {
         hs_part P{};
         P.row0 = r0;
@@ -741,34 +742,62 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
           for (i64 j = 0; j < Lw; j++) cp[j + 1] = cp[j] + atleast[j + 1];
         }
         P.nz_rows = Lw > 0 ? cp[1] : 0;
-        P.cp_off = (i64)M->h_cp.size();
         P.nnz_off = rp[r0] - rp[0];
-        P.chunk0 = (int)M->chunks.size();
-        std::vector<hs_chunk> ch = make_chunks(cp, s, c->prm.agg_mode == 1, (int)p);
-        P.nchunks = (int)ch.size();
-        M->chunks.insert(M->chunks.end(), ch.begin(), ch.end());
-        M->h_cp.insert(M->h_cp.end(), cp.begin(), cp.end());
         M->h_rm.insert(M->h_rm.end(), rm.begin(), rm.end());
-        part_cp_off.push_back(P.cp_off);
-        part_nnz_off.push_back(P.nnz_off);
+        cps.push_back(std::move(cp));
         M->parts.push_back(P);
       }
-      const int G = (int)M->chunks.size();
       const int nP = (int)M->parts.size();
+      // result ciphertexts: one per partition, or (two slot rows) per pair of partitions whose
+      // chunks follow the joint column profile max(NNZ_A[j], NNZ_B[j]); each partition's CP is then
+      // padded to the joint width (columns past its own have no entries)
+      const int srows = c->prm.slot_rows == 2 ? 2 : 1;
+      for (int p = 0; p < nP; p += srows) {
+        hs_group Gr{p, (srows == 2 && p + 1 < nP) ? p + 1 : -1, (int)M->chunks.size(), 0};
+        std::vector<i64> jcp;
+        if (Gr.pb >= 0) {
+          std::vector<i64>& a = cps[p];
+          std::vector<i64>& bb = cps[Gr.pb];
+          const size_t W = std::max(a.size(), bb.size());
+          jcp.assign(W, 0);
+          for (size_t j = 0; j + 1 < W; j++) {
+            const i64 na = j + 1 < a.size() ? a[j + 1] - a[j] : 0, nb = j + 1 < bb.size() ? bb[j + 1] - bb[j] : 0;
+            jcp[j + 1] = jcp[j] + std::max(na, nb);
+          }
+          a.resize(W, a.back());
+          bb.resize(W, bb.back());
+        }
+        std::vector<hs_chunk> ch = make_chunks(Gr.pb >= 0 ? jcp : cps[p], s, c->prm.agg_mode == 1, (int)M->groups.size());
+        Gr.nchunks = (int)ch.size();
+        M->chunks.insert(M->chunks.end(), ch.begin(), ch.end());
+        M->groups.push_back(Gr);
+      }
+      for (int p = 0; p < nP; p++) {
+        hs_part& P = M->parts[p];
+        P.cp_off = (i64)M->h_cp.size();
+        M->h_cp.insert(M->h_cp.end(), cps[p].begin(), cps[p].end());
+        part_cp_off.push_back(P.cp_off);
+        part_nnz_off.push_back(P.nnz_off);
+      }
+      const int G = (int)M->chunks.size();
       // one upload of every structure array (pinned staging, one device allocation):
-      //   cp | rm | chunk table | partition info (row0, rows, nz rows, rm offset) | rank | cp and
-      //   nnz offsets per partition | the column-check flag
+      //   cp | rm | chunk table | partition info (row0, rows, nz rows, rm offset, group, slot
+      //   offset) | rank | cp and nnz offsets per partition | the column-check flag
       std::vector<i64> cd(8ULL * std::max(G, 1), 0);
       for (int g = 0; g < G; g++) {
         const hs_chunk& k = M->chunks[g];
-        const hs_part& P = M->parts[k.part];
+        const hs_group& Gr = M->groups[k.part];
+        const hs_part& PA = M->parts[Gr.pa];
         i64* d = &cd[8ULL * g];
-        d[0] = k.start; d[1] = k.c; d[2] = k.h; d[3] = P.cp_off; d[4] = P.nnz_off; d[5] = k.part;
+        d[0] = k.start; d[1] = k.c; d[2] = k.h; d[3] = PA.cp_off; d[4] = PA.nnz_off; d[5] = k.part;
+        d[6] = Gr.pb >= 0 ? M->parts[Gr.pb].cp_off : -1;
+        d[7] = Gr.pb >= 0 ? M->parts[Gr.pb].nnz_off : 0;
       }
-      std::vector<i64> pinfo(4ULL * std::max(nP, 1), 0);
+      std::vector<i64> pinfo(6ULL * std::max(nP, 1), 0);
       for (int p = 0, rm_off = 0; p < nP; p++) {
         const hs_part& P = M->parts[p];
-        pinfo[4 * p] = P.row0; pinfo[4 * p + 1] = P.rows; pinfo[4 * p + 2] = P.nz_rows; pinfo[4 * p + 3] = rm_off;
+        i64* q = &pinfo[6ULL * p];
+        q[0] = P.row0; q[1] = P.rows; q[2] = P.nz_rows; q[3] = rm_off; q[4] = p / srows; q[5] = (p % srows) * s;
         rm_off += (int)P.rows;
       }
       auto seg = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
@@ -874,6 +903,13 @@ void hs_matrix_destroy(hs_matrix* m) {
   for (void* p : ptrs) pfree(m->ctx, p);
   if (m->ready) (void)hipEventDestroy(m->ready);
   delete m;
+}
+
+int hs_matrix_groups(const hs_matrix* m, int64_t* n_groups) {
+  return guarded([&] {
+    HS_REQUIRE(m && n_groups, HS_EINVAL, "null argument");
+    *n_groups = (int64_t)m->groups.size();
+  });
 }
 
 int hs_matrix_info(const hs_matrix* m, int64_t* n_parts, int64_t* n_chunks) {
@@ -997,7 +1033,7 @@ struct BatchWork {
     for (int r = 0; r < n; r++) {
       Req& q = rq[r];
       q.G = (int)m[r]->chunks.size();
-      q.nP = (int)m[r]->parts.size();
+      q.nP = (int)m[r]->groups.size();
       q.progs.resize(q.G);
       q.wt_base.assign(q.G, -1);
       for (int g = 0; g < q.G; g++) {
@@ -1063,7 +1099,7 @@ struct BatchWork {
       if (!q.nP) continue;
       for (int g = 0; g < std::max(q.G, 1); g++) words.push_back(g < q.G ? (u64)(uintptr_t)buf(r, g, q.progs[g].back().in) : 0);
       std::vector<int> pcn(2 * (size_t)q.nP);
-      for (int p = 0; p < q.nP; p++) { pcn[p] = m[r]->parts[p].chunk0; pcn[q.nP + p] = m[r]->parts[p].nchunks; }
+      for (int p = 0; p < q.nP; p++) { pcn[p] = m[r]->groups[p].chunk0; pcn[q.nP + p] = m[r]->groups[p].nchunks; }
       const size_t w0 = words.size();
       words.resize(w0 + (pcn.size() * sizeof(int) + 7) / 8, 0);
       std::memcpy(words.data() + w0, pcn.data(), pcn.size() * sizeof(int));
@@ -1122,7 +1158,7 @@ int hs_he_spmv_batch(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_matr
     }
     std::vector<hs_ctvec*> out(n, nullptr);
     try {
-      for (int r = 0; r < n; r++) out[r] = new_ctvec(c, (i64)m[r]->parts.size());
+      for (int r = 0; r < n; r++) out[r] = new_ctvec(c, (i64)m[r]->groups.size());
       spmv_many(c, n, ks, m, x, S(stream), out.data());
     } catch (...) {
       for (hs_ctvec* v : out) hs_ctvec_destroy(v);
@@ -1329,7 +1365,7 @@ int hs_batch_plan_create(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_
     P->ctx = c;
     hipStream_t cs = nullptr;
     try {
-      for (int r = 0; r < n; r++) P->y.push_back(new_ctvec(c, (i64)m[r]->parts.size()));
+      for (int r = 0; r < n; r++) P->y.push_back(new_ctvec(c, (i64)m[r]->groups.size()));
       P->work.prepare(c, n, ks, m, x, st, P->y.data());
       // one eager pass: the results are valid at once, and every kernel attribute is set before
       // recording (no runtime configuration calls inside the captured region)
@@ -1397,24 +1433,25 @@ int hs_decrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const hs_ctve
     HS_REQUIRE(c && ks && m && y, HS_EINVAL, "null argument");
     HS_REQUIRE(ks->ctx == c && m->ctx == c && y->ctx == c, HS_EKEY, "handles from another context");
     HS_REQUIRE(rows == m->R, HS_EINVAL, "rows must equal the matrix row count");
-    HS_REQUIRE(y->n == (i64)m->parts.size(), HS_EINVAL, "one result ciphertext per row partition expected");
+    HS_REQUIRE(y->n == (i64)m->groups.size(), HS_EINVAL, "one result ciphertext per partition group expected");
     HS_REQUIRE(rows == 0 || out, HS_EINVAL, "null output");
     hipStream_t st = S(stream);
-    const int nP = (int)m->parts.size();
+    const int nP = (int)m->parts.size(), nG = (int)m->groups.size();
     if (!nP) return;
     const size_t N = c->N;
-    DBuf X(&c->pool, (size_t)nP * c->L * N * sizeof(u64)), Mc(&c->pool, (size_t)nP * N * sizeof(u64));
+    DBuf X(&c->pool, (size_t)nG * c->L * N * sizeof(u64)), Mc(&c->pool, (size_t)nG * N * sizeof(u64));
     std::vector<DBuf> hold;
     const bool split = use_split_client(c);
     if (split) {
-      launch_dec_prep(c, y->d, ks->sk, X.as<u64>(), nP, st);
-      ntt_any(c, X.as<u64>(), (i64)nP * c->L, c->L, 0, 1, st, hold);
+      launch_dec_prep(c, y->d, ks->sk, X.as<u64>(), nG, st);
+      ntt_any(c, X.as<u64>(), (i64)nG * c->L, c->L, 0, 1, st, hold);
     } else {
-      launch_dec_phase(c, y->d, ks->sk, X.as<u64>(), nP, st);
+      launch_dec_phase(c, y->d, ks->sk, X.as<u64>(), nG, st);
     }
-    launch_dec_round(c, X.as<u64>(), Mc.as<u64>(), nP, st);
-    if (split) {
-      ntt_any(c, Mc.as<u64>(), nP, 1, c->n_mod, 0, st, hold);
+    launch_dec_round(c, X.as<u64>(), Mc.as<u64>(), nG, st);
+    // decode per result ciphertext, scatter per partition (slot row 0 or 1 of its group's ciphertext)
+    if (split || nG != nP) {
+      ntt_any(c, Mc.as<u64>(), nG, 1, c->n_mod, 0, st, hold);
       launch_slots_scatter(c, Mc.as<u64>(), m->d_rm, m->d_pinfo, nP, out, st);
     } else {
       launch_decode_scatter(c, Mc.as<u64>(), m->d_rm, m->d_pinfo, out, nP, st);
@@ -1672,7 +1709,7 @@ static size_t request_footprint(const hs_ctx* c, const hs_matrix* m, int* nwt_ou
   for (const hs_chunk& ch : m->chunks)
     if (ch.c > 1) nwt += 4;
   if (nwt_out) *nwt_out = nwt;
-  return ((size_t)m->chunks.size() + nwt + m->parts.size()) * CW;
+  return ((size_t)m->chunks.size() + nwt + m->groups.size()) * CW;
 }
 
 static void server_tick(hs_server* S) {
@@ -1710,7 +1747,7 @@ static void server_tick(hs_server* S) {
     }
     r->vbuf = DBuf(&c->pool, (size_t)std::max(G, 1) * CW * sizeof(u64));
     r->wtbuf = DBuf(&c->pool, (size_t)std::max(nwt, 1) * CW * sizeof(u64));
-    r->y = new_ctvec(c, (i64)m->parts.size());
+    r->y = new_ctvec(c, (i64)m->groups.size());
     if (!G) continue;
     if (m->ready) HS_CHECK_HIP(hipStreamWaitEvent(S->st, m->ready, 0));
     if (m->encrypted) {
@@ -1771,12 +1808,12 @@ static void server_tick(hs_server* S) {
     for (size_t g = 0; g < r->progs.size(); g++) fin &= (r->pc[g] + 1 >= r->progs[g].size());
     if (!fin) continue;
     const hs_matrix* m = r->m;
-    const int G = (int)m->chunks.size(), nP = (int)m->parts.size();
+    const int G = (int)m->chunks.size(), nP = (int)m->groups.size();
     if (nP) {
       std::vector<const u64*> wp(std::max(G, 1), nullptr);
       for (int g = 0; g < G; g++) wp[g] = buf(r.get(), g, r->progs[g].back().in);
       std::vector<int> pc0(nP), pnc(nP);
-      for (int p = 0; p < nP; p++) { pc0[p] = m->parts[p].chunk0; pnc[p] = m->parts[p].nchunks; }
+      for (int p = 0; p < nP; p++) { pc0[p] = m->groups[p].chunk0; pnc[p] = m->groups[p].nchunks; }
       keep.emplace_back(&c->pool, wp.size() * sizeof(u64*));
       const u64* const* dw = keep.back().as<const u64*>();
       h2d(keep.back().as<const u64*>(), wp.data(), wp.size(), S->st);

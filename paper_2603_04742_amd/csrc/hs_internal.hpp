@@ -158,7 +158,7 @@ struct hs_keyset {
 };
 
 struct hs_chunk {
-  int part;        // row partition
+  int part;        // group (result ciphertext): a row partition, or a pair with two slot rows
   int start, c;    // first CSSC column, number of columns
   hs::i64 h;       // height (rows); slot k <-> (block k / h, sorted row k % h)
 };
@@ -169,6 +169,12 @@ struct hs_part {
   hs::i64 nnz_off;      // offset of this partition's VA/CI in the matrix arrays
   hs::i64 cp_off;       // offset of this partition's CP in the matrix CP array
   hs::i64 nz_rows;      // rows with at least one nonzero (= NNZ of CSSC column 0)
+};
+
+// One result ciphertext: partition pa in slot row 0 and, with two slot rows, partition pb (or -1)
+// in slot row 1; its chunks are chunks[chunk0, chunk0 + nchunks).
+struct hs_group {
+  int pa, pb;
   int chunk0, nchunks;
 };
 
@@ -177,13 +183,14 @@ struct hs_matrix {
   hs::i64 R = 0, C = 0, nnz = 0;
   int encrypted = 0;
   std::vector<hs_part> parts;
+  std::vector<hs_group> groups;
   std::vector<hs_chunk> chunks;
   std::vector<hs::i64> h_cp;     // all partitions' CP arrays, concatenated
   std::vector<hs::i32> h_rm;     // row map per partition (local rows), concatenated = R entries
   char* d_struct = nullptr;      // one allocation: d_cp, d_rm, d_chunk, d_pinfo and upload scratch
   hs::i64* d_cp = nullptr;
   hs::i32* d_rm = nullptr;
-  hs::i64* d_pinfo = nullptr;    // per partition: (row0, rows, nonzero rows, row-map offset)
+  hs::i64* d_pinfo = nullptr;    // per partition: (row0, rows, nonzero rows, row-map offset, group, slot offset)
   hs::i64* d_va = nullptr;       // CSSC values (nnz)
   hs::i32* d_ci = nullptr;       // CSSC column indices (nnz)
   hs::i64* d_chunk = nullptr;    // per chunk: (start, c, h, cp_off) for device kernels

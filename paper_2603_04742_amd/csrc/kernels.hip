@@ -228,23 +228,27 @@ __global__ void __launch_bounds__(NT) k_pack_encode(PackArgs A, const u32* __res
   const int n = 1 << logn;
   const int g = blockIdx.x;
   const int mode = A.mode == 3 ? (g < A.nG ? 0 : 2) : A.mode;
-  const i64* cd = A.chunk + 8 * (A.mode == 3 && g >= A.nG ? g - A.nG : g);  // (start, c, h, cp_off, nnz_off, part, -, -)
-  const i64 start = cd[0], cols = cd[1], h = cd[2], cpo = cd[3], nzo = cd[4];
+  // (start, c, h, cp_off, nnz_off, group, cp_off of slot row 1 or -1, nnz_off of slot row 1)
+  const i64* cd = A.chunk + 8 * (A.mode == 3 && g >= A.nG ? g - A.nG : g);
+  const i64 start = cd[0], cols = cd[1], h = cd[2];
   const ModTab t = tab[tmod];
   const ModD m = mod_of(t);
   const i64 tq = (i64)t.q;
   for (int k = threadIdx.x; k < n; k += NT) {
+    const int srow = k >= n / 2;
+    const i64 kk = k - srow * (n / 2);
+    const i64 cpo = srow ? cd[6] : cd[3], nzo = srow ? cd[7] : cd[4];
     i64 val = 0;
-    if (mode == 2) {
-      val = (k < h) ? 1 : 0;
-    } else if (k < h * cols && k < n / 2) {
-      {
-        const i64 b = k / h, p = k % h;
-        const i64 c0 = A.cp[cpo + start + b], c1 = A.cp[cpo + start + b + 1];
-        if (p < c1 - c0) {
-          const i64 e = nzo + c0 + p;
-          val = (mode == 0) ? A.va[e] : A.v[A.ci[e]];
-        }
+    if (cpo < 0) {
+      val = 0;   // no partition in this slot row
+    } else if (mode == 2) {
+      val = (kk < h) ? 1 : 0;
+    } else if (kk < h * cols) {
+      const i64 b = kk / h, p = kk % h;
+      const i64 c0 = A.cp[cpo + start + b], c1 = A.cp[cpo + start + b + 1];
+      if (p < c1 - c0) {
+        const i64 e = nzo + c0 + p;
+        val = (mode == 0) ? A.va[e] : A.v[A.ci[e]];
       }
     }
     val %= tq;
@@ -700,15 +704,17 @@ __global__ void __launch_bounds__(NT) k_decode_scatter(const u64* __restrict__ M
   const ModTab tb = tab[tmod];
   const ModD m = mod_of(tb);
   const i64 t = (i64)tb.q;
-  const u64* mc = M + (size_t)P * n;
+  // pinfo per partition: (row0, rows, nonzero rows, row-map offset, group, slot offset)
+  const i64* pi = pinfo + 6 * P;
+  const i64 row0 = pi[0], rows = pi[1], nz = pi[2], rm0 = pi[3], grp = pi[4], off = pi[5];
+  const u64* mc = M + (size_t)grp * n;
   for (int i = threadIdx.x; i < n; i += NT) smem[lpad(i)] = u2d(mc[i]);
   __syncthreads();
   lds_ntt_fwd<NT>(smem, logn, tb.fw, m);
-  const i64 row0 = pinfo[4 * P], rows = pinfo[4 * P + 1], nz = pinfo[4 * P + 2], rm0 = pinfo[4 * P + 3];
   for (i64 p = threadIdx.x; p < rows; p += NT) {
     i64 v = 0;
     if (p < nz) {
-      v = (i64)d2u(canon(smem[lpad(slot_pos[p])], m));
+      v = (i64)d2u(canon(smem[lpad(slot_pos[off + p])], m));
       if (v > t / 2) v -= t;
     }
     y[row0 + rm[rm0 + p]] = v;

@@ -197,6 +197,7 @@ void build_ctx(hs_ctx* c) {
   HS_REQUIRE(is_prime_u64(c->t) && c->t % (2 * c->N) == 1 && c->t < (1ULL << 50), HS_EPARAM,
              "t must be a prime < 2^50 with t = 1 mod 2N");
   HS_REQUIRE(p.agg_mode <= 1, HS_EPARAM, "agg_mode must be 0 or 1");
+  HS_REQUIRE(p.slot_rows <= 2, HS_EPARAM, "slot_rows must be 0, 1 or 2");
   c->L = (int)p.n_q;
   c->K = (int)p.n_p;
   c->alpha = c->K;

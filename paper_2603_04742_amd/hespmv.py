@@ -26,7 +26,7 @@ class HespmvError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("q_bits", ctypes.c_uint32),
                 ("n_p", ctypes.c_uint32), ("p_bits", ctypes.c_uint32), ("t", ctypes.c_uint64),
-                ("sigma", ctypes.c_double), ("agg_mode", ctypes.c_uint32)]
+                ("sigma", ctypes.c_double), ("agg_mode", ctypes.c_uint32), ("slot_rows", ctypes.c_uint32)]
 
 
 _vp = ctypes.c_void_p
@@ -55,6 +55,7 @@ SIGNATURES = {
     "hs_matrix_info": (_int, [_vp, _i64p, _i64p]),
     "hs_matrix_chunk": (_int, [_vp, _i64, _i64p]),
     "hs_matrix_column_index": (_int, [_vp, _i32p, _i64, _i64p]),
+    "hs_matrix_groups": (_int, [_vp, _i64p]),
     "hs_matrix_export": (_int, [_vp, _int, _i64, _u64p, _i64]),
     "hs_encrypt": (_int, [_vp, _vp, _vp, _vp, _i64, _u64, _vp, _pp]),
     "hs_he_spmv": (_int, [_vp, _vp, _vp, _vp, _vp, _pp]),
@@ -124,8 +125,8 @@ def _np(a, dt, ptr):
 class Context:
     """hs_ctx: parameter set, primes, tables."""
 
-    def __init__(self, log_n, n_q, q_bits, n_p, t=65537, agg_mode=0, sigma=3.2):
-        self.params = Params(log_n, n_q, q_bits, n_p, q_bits, t, sigma, agg_mode)
+    def __init__(self, log_n, n_q, q_bits, n_p, t=65537, agg_mode=0, sigma=3.2, slot_rows=1):
+        self.params = Params(log_n, n_q, q_bits, n_p, q_bits, t, sigma, agg_mode, slot_rows)
         h = ctypes.c_void_p()
         _check(lib.hs_ctx_create(ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h
@@ -254,6 +255,11 @@ class Matrix:
         p, c = ctypes.c_int64(), ctypes.c_int64()
         _check(lib.hs_matrix_info(self.h, ctypes.byref(p), ctypes.byref(c)))
         return p.value, c.value
+
+    def groups(self):
+        n = ctypes.c_int64()
+        _check(lib.hs_matrix_groups(self.h, ctypes.byref(n)))
+        return n.value
 
     def chunk(self, k):
         out = np.zeros(4, np.int64)
