@@ -206,7 +206,14 @@ def main():
                      "level_ms_by_B": {str(b): [round(t1, 4), round(t2, 4)] for b, t1, t2 in tune["pipelines"]}},
     }
     result["keyswitch_saturated"] = keyswitch_saturated(H, torch, ctx, ks, L, K, 1 << logn)
-    result["exact_step_keys"] = exact_step_keys(H, torch, ctx, w, (rp, col, val, v), out, want, args.steps)
+    tens = (rp, col, val, v)
+    result["exact_step_keys"] = layout_variant(H, torch, ctx, w, tens, out, want, args.steps, True, "exact-step keys")
+    ctx2 = H.Context(logn, L, bits, K, agg_mode=agg, slot_rows=2)
+    H.autotune(ctx2, ctx2.keygen(0x5EED + 2))
+    result["two_slot_rows"] = layout_variant(H, torch, ctx2, w, tens, out, want, args.steps, False, "two slot rows")
+    result["two_slot_rows_exact_step_keys"] = layout_variant(H, torch, ctx2, w, tens, out, want, args.steps, True,
+                                                             "two slot rows + exact-step keys")
+    ctx2.close()
     if args.workload == "zipf16k" and not args.no_batch:
         result["batched_vs_plain"] = batched_vs_plain(H, W, torch, dev)
     if args.workload == "zipf16k" and args.serve_requests > 0:
@@ -216,15 +223,18 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def exact_step_keys(H, torch, ctx, w, tensors, out, want, n_steps):
-    """The same protocol step with a key-set that also holds a rotation key for every totalSum step
-    of the matrix (one key switch per logical rotation instead of one per binary digit of its
-    step).  The decrypted product is the same; the keys are generated once, before timing."""
+def layout_variant(H, torch, ctx, w, tensors, out, want, n_steps, exact_keys, label):
+    """The same protocol step under a variant that leaves the decrypted product unchanged:
+    exact_keys adds a rotation key for every totalSum step of the matrix (one key switch per
+    logical rotation instead of one per binary digit of its step; the keys are generated once,
+    before timing); a context made with slot_rows = 2 packs two row partitions per ciphertext."""
     rp, col, val, v = tensors
     ks2 = ctx.keygen(0x5EED + 1)
     steps = H.Matrix(ctx, w["R"], w["C"], rp, col, val).rotation_steps()
-    ks2.add_rotation_keys(steps)
-    n_new = sum(1 for k in steps if k & (k - 1))
+    n_new = 0
+    if exact_keys:
+        ks2.add_rotation_keys(steps)
+        n_new = sum(1 for k in steps if k & (k - 1))
 
     def step(i):
         m = H.Matrix(ctx, w["R"], w["C"], rp, col, val)
@@ -243,7 +253,7 @@ def exact_step_keys(H, torch, ctx, w, tensors, out, want, n_steps):
     ms = (time.perf_counter() - t0) * 1e3 / n_steps
     counters = H.last_counters()
     if not torch.equal(out, want):
-        raise RuntimeError("exact-step keys: decrypted result differs from the integer SpMV")
+        raise RuntimeError(label + ": decrypted result differs from the integer SpMV")
     m = H.Matrix(ctx, w["R"], w["C"], rp, col, val)
     x = H.encrypt(ctx, ks2, m, v, 9)
     reps, he_ms = 5, 0.0
@@ -252,10 +262,12 @@ def exact_step_keys(H, torch, ctx, w, tensors, out, want, n_steps):
         H.he_spmv(ctx, ks2, m, x)
         torch.cuda.synchronize(); he_ms += (time.perf_counter() - a) * 1e3 / reps
     key_bytes = 2 * ctx.dnum * (ctx.L + ctx.K) * ctx.N * 8
-    return {"value": round(1000.0 / ms, 3), "unit": "SpMV/s", "ms_per_step": round(ms, 3),
-            "he_spmv_ms": round(he_ms, 3), "key_switches_per_spmv": counters["key_switches"],
-            "rotations_per_spmv": counters["rotations"], "rotation_steps": steps,
-            "extra_keys": n_new, "extra_key_bytes": n_new * key_bytes}
+    r = {"value": round(1000.0 / ms, 3), "unit": "SpMV/s", "ms_per_step": round(ms, 3),
+         "he_spmv_ms": round(he_ms, 3), "chunk_ciphertexts": m.info()[1], "result_ciphertexts": m.groups(),
+         "key_switches_per_spmv": counters["key_switches"], "rotations_per_spmv": counters["rotations"]}
+    if exact_keys:
+        r.update({"rotation_steps": steps, "extra_keys": n_new, "extra_key_bytes": n_new * key_bytes})
+    return r
 
 
 def ntt_bandwidth(H, torch, dev, ctx, logn, L, K, reps=5):
