@@ -86,6 +86,15 @@ def lib():
             "orc_encrypt_vector": (None, [vp, vp, i64p, ctypes.c_uint64, u64p]),
             "orc_he_spmv": (None, [vp, vp, u64p, u64p, i64p]),
             "orc_decrypt_result": (None, [vp, vp, u64p, i64p]),
+            "orc_diag_new": (vp, [vp, ctypes.c_int64, ctypes.c_int64, i64p, i32p, i64p]),
+            "orc_diag_free": (None, [vp]),
+            "orc_diag_count": (ctypes.c_int, [vp]),
+            "orc_diag_info": (None, [vp, i64p]),
+            "orc_diag_key": (None, [vp, ctypes.c_int, i64p]),
+            "orc_diag_pt": (None, [vp, ctypes.c_int, u64p]),
+            "orc_diag_encrypt_vector": (None, [vp, vp, i64p, ctypes.c_uint64, u64p]),
+            "orc_diag_spmv": (None, [vp, vp, u64p, u64p, i64p]),
+            "orc_diag_decrypt": (None, [vp, vp, u64p, i64p]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -369,4 +378,54 @@ class Matrix:
         res = np.ascontiguousarray(res, np.uint64)
         y = np.zeros(self.R, np.int64)
         lib().orc_decrypt_result(self.ctx.h, self.h, _p(res, u64p), _p(y, i64p))
+        return y
+
+
+class DiagMatrix:
+    """The paper's diagonal baseline: generalised diagonals of B x B blocks as plaintexts."""
+
+    def __init__(self, ctx, R, C, row_ptr, col, val):
+        self.ctx, self.R, self.C = ctx, R, C
+        self.row_ptr = np.ascontiguousarray(row_ptr, np.int64)
+        self.col = np.ascontiguousarray(col, np.int32)
+        self.val = np.ascontiguousarray(val, np.int64)
+        self.h = lib().orc_diag_new(ctx.h, R, C, _p(self.row_ptr, i64p), _p(self.col, i32p), _p(self.val, i64p))
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().orc_diag_free(self.h)
+            self.h = None
+
+    def info(self):
+        out = np.zeros(5, np.int64)
+        lib().orc_diag_info(self.h, _p(out, i64p))
+        return dict(B=int(out[0]), row_blocks=int(out[1]), col_blocks=int(out[2]), diagonals=int(out[3]))
+
+    def key(self, k):
+        out = np.zeros(3, np.int64)
+        lib().orc_diag_key(self.h, k, _p(out, i64p))
+        return tuple(int(x) for x in out)
+
+    def pt(self, k):
+        out = np.zeros(self.ctx.L * self.ctx.N, np.uint64)
+        lib().orc_diag_pt(self.h, k, _p(out, u64p))
+        return out
+
+    def encrypt_vector(self, v, seed):
+        v = np.ascontiguousarray(v, np.int64)
+        out = np.zeros(self.info()["col_blocks"] * self.ctx.ct_size(), np.uint64)
+        lib().orc_diag_encrypt_vector(self.ctx.h, self.h, _p(v, i64p), seed, _p(out, u64p))
+        return out
+
+    def spmv(self, x):
+        x = np.ascontiguousarray(x, np.uint64)
+        out = np.zeros(self.info()["row_blocks"] * self.ctx.ct_size(), np.uint64)
+        stats = np.zeros(1, np.int64)
+        lib().orc_diag_spmv(self.ctx.h, self.h, _p(x, u64p), _p(out, u64p), _p(stats, i64p))
+        return out
+
+    def decrypt_result(self, res):
+        res = np.ascontiguousarray(res, np.uint64)
+        y = np.zeros(self.R, np.int64)
+        lib().orc_diag_decrypt(self.ctx.h, self.h, _p(res, u64p), _p(y, i64p))
         return y

@@ -31,6 +31,7 @@
 #include <vector>
 #include <algorithm>
 #include <map>
+#include <array>
 
 #include "cdt_sigma3p2.h"
 
@@ -1293,6 +1294,94 @@ void orc_decrypt_result(void* h, void* m, const u64* res, i64* y) {
         if (q < nz) { u64 s = slots[off + q]; y[row] = s > c->t / 2 ? (i64)s - (i64)c->t : (i64)s; }
         else y[row] = 0;
       }
+    }
+  }
+}
+
+/* ---- the paper's diagonal baseline (Sec. 5, baseline approaches; the diagonal-method figure) ----
+ * The matrix is cut into square blocks of side B = min(N/4, max(R, C)) (zero padded at the right
+ * and bottom edges).  Block (bi, bj) keeps its non-zero generalised diagonals d:
+ * diag[i] = A[bi B + i][bj B + (i + d) mod B], each encoded as one plaintext (slots [0, B) of row
+ * 0).  Vector block bj is encrypted twice over (x_bj || x_bj in slots [0, 2B)), so a left rotation
+ * by d puts x_bj[(i + d) mod B] in slot i.  Result block bi = sum over its diagonals (bj, d) of
+ * diag (.) Rot(x_bj, d), in (bj, d) order; the product of block row bi lies in slots [0, B). */
+struct DiagM {
+  i64 R = 0, C = 0, B = 0; int nrb = 0, ncb = 0;
+  std::vector<i64> key;                 /* per diagonal: bi, bj, d (3 words), sorted */
+  std::vector<std::vector<u64>> pts;    /* NTT-form plaintexts */
+};
+void* orc_diag_new(void* h, i64 R, i64 C, const i64* row_ptr, const i32* col, const i64* val) {
+  Ctx* c = (Ctx*)h;
+  DiagM* D = new DiagM(); D->R = R; D->C = C;
+  D->B = std::min<i64>((i64)c->N / 4, std::max<i64>(std::max<i64>(R, C), 1));
+  D->nrb = (int)((R + D->B - 1) / D->B); D->ncb = (int)((C + D->B - 1) / D->B);
+  std::map<std::array<i64, 3>, std::vector<i64>> diags;
+  for (i64 r = 0; r < R; r++)
+    for (i64 k = row_ptr[r]; k < row_ptr[r + 1]; k++) {
+      i64 cc = col[k], bi = r / D->B, bj = cc / D->B, i = r % D->B, j = cc % D->B;
+      i64 d = ((j - i) % D->B + D->B) % D->B;
+      auto& v = diags[{bi, bj, d}];
+      if (v.empty()) v.assign(D->B, 0);
+      v[i] = val[k];
+    }
+  for (auto& kv : diags) {
+    std::vector<u64> slots(c->N, 0);
+    for (i64 i = 0; i < D->B; i++) slots[i] = smod(kv.second[i], c->t);
+    D->pts.push_back(plain_ntt(*c, encode(*c, slots)));
+    for (int q = 0; q < 3; q++) D->key.push_back(kv.first[q]);
+  }
+  return D;
+}
+void orc_diag_free(void* d) { delete (DiagM*)d; }
+int orc_diag_count(void* d) { return (int)((DiagM*)d)->pts.size(); }
+void orc_diag_info(void* d, i64* out5) {
+  DiagM* D = (DiagM*)d; out5[0] = D->B; out5[1] = D->nrb; out5[2] = D->ncb; out5[3] = (i64)D->pts.size(); out5[4] = 0;
+}
+void orc_diag_key(void* d, int k, i64* out3) { DiagM* D = (DiagM*)d; for (int q = 0; q < 3; q++) out3[q] = D->key[3 * (size_t)k + q]; }
+void orc_diag_pt(void* d, int k, u64* out) { DiagM* D = (DiagM*)d; memcpy(out, D->pts[k].data(), D->pts[k].size() * 8); }
+/* vector blocks, each x_bj || x_bj, encrypted with (seed, index bj): out [ncb][2][L][N] */
+void orc_diag_encrypt_vector(void* h, void* d, const i64* v, u64 seed, u64* out) {
+  Ctx* c = (Ctx*)h; DiagM* D = (DiagM*)d; u64 ctsz = 2ULL * c->L * c->N;
+  for (int bj = 0; bj < D->ncb; bj++) {
+    std::vector<u64> slots(c->N, 0);
+    for (i64 j = 0; j < D->B; j++) {
+      i64 cc = bj * D->B + j;
+      u64 x = cc < D->C ? smod(v[cc], c->t) : 0;
+      slots[j] = x; slots[D->B + j] = x;
+    }
+    auto ct = encrypt(*c, encode(*c, slots), seed, (u64)bj);
+    memcpy(out + bj * ctsz, ct.data(), ctsz * 8);
+  }
+}
+/* out [nrb][2][L][N]; stats (optional): [diagonal products] */
+void orc_diag_spmv(void* h, void* d, const u64* x, u64* out, i64* stats) {
+  Ctx* c = (Ctx*)h; DiagM* D = (DiagM*)d; u64 ctsz = 2ULL * c->L * c->N;
+  std::map<std::pair<i64, i64>, std::vector<u64>> rot;   /* (bj, d) -> Rot(x_bj, d) */
+  for (int bi = 0; bi < D->nrb; bi++) {
+    std::vector<u64> res(ctsz, 0);
+    for (size_t k = 0; k < D->pts.size(); k++) {
+      if (D->key[3 * k] != bi) continue;
+      i64 bj = D->key[3 * k + 1], dd = D->key[3 * k + 2];
+      auto it = rot.find({bj, dd});
+      if (it == rot.end()) {
+        std::vector<u64> xb(x + bj * ctsz, x + (bj + 1) * ctsz);
+        it = rot.emplace(std::make_pair(bj, dd), dd ? rotate(*c, xb, (u64)dd, nullptr) : xb).first;
+      }
+      ct_add(*c, res, ct_mul_plain(*c, it->second, D->pts[k]));
+    }
+    memcpy(out + bi * ctsz, res.data(), ctsz * 8);
+  }
+  if (stats) stats[0] = (i64)D->pts.size();
+}
+/* y [R] centered: row bi B + i from slot i of result block bi */
+void orc_diag_decrypt(void* h, void* d, const u64* res, i64* y) {
+  Ctx* c = (Ctx*)h; DiagM* D = (DiagM*)d; u64 ctsz = 2ULL * c->L * c->N;
+  for (int bi = 0; bi < D->nrb; bi++) {
+    std::vector<u64> ct(res + bi * ctsz, res + (bi + 1) * ctsz);
+    std::vector<u64> slots = decode(*c, decrypt(*c, ct));
+    for (i64 i = 0; i < D->B && bi * D->B + i < D->R; i++) {
+      u64 sv = slots[i];
+      y[bi * D->B + i] = sv > c->t / 2 ? (i64)sv - (i64)c->t : (i64)sv;
     }
   }
 }

@@ -696,6 +696,39 @@ def test_two_slot_rows_protocol(agg, R, C, nnz):
     assert n2 <= n1 and s2["rotations"] <= s1["rotations"]
 
 
+@pytest.mark.parametrize("R,C,nnz", [(100, 100, 400), (200, 150, 600), (64, 300, 500), (1, 1, 1)])
+def test_diagonal_baseline(R, C, nnz):
+    """The diagonal method (the paper's baseline): the plaintext diagonals rebuild the dense matrix
+    (decoded slot by slot), and the decrypted product is the integer SpMV."""
+    c = O.Context(9, 3, 50, 1)
+    c.keygen(3)
+    g = np.random.default_rng(R * 7 + C)
+    rp, col, val = W.uniform_matrix(R, C, nnz, 15, g)
+    w = dict(R=R, C=C, row_ptr=rp, col=col, val=val, v=g.integers(-15, 16, C))
+    D = O.DiagMatrix(c, R, C, rp, col, val)
+    inf = D.info()
+    B = inf["B"]
+    assert B == min(c.N // 4, max(R, C))
+    dense = np.zeros((inf["row_blocks"] * B, inf["col_blocks"] * B), np.int64)
+    q0 = c.moduli()[0]
+    for k in range(inf["diagonals"]):
+        bi, bj, d = D.key(k)
+        coef = c.intt(0, D.pt(k)[:c.N].copy()).astype(object)
+        m = np.array([(int(x) - q0 if int(x) > q0 // 2 else int(x)) % T for x in coef], np.uint64)
+        sl = c.decode(m).astype(np.int64)
+        sl = np.where(sl > T // 2, sl - T, sl)
+        assert not sl[B:].any()
+        for i in range(B):
+            dense[bi * B + i, bj * B + (i + d) % B] += sl[i]
+    want = np.zeros_like(dense)
+    for r in range(R):
+        for k in range(rp[r], rp[r + 1]):
+            want[r, col[k]] = ((int(val[k]) + T // 2) % T) - T // 2
+    assert np.array_equal(dense, want)
+    y = D.decrypt_result(D.spmv(D.encrypt_vector(w["v"], 7)))
+    assert np.array_equal(y, W.spmv_mod_t(w))
+
+
 @pytest.mark.parametrize("case", ["empty", "one", "emptyrows", "rect", "partitions", "dense_row"])
 def test_spmv_edge_cases_paper_aggregation(case):
     c = O.Context(9, 3, 50, 1, agg_mode=0)   # s = 256 slots per chunk
