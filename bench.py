@@ -47,6 +47,9 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batched-vs-plain measurement")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving run (Poisson arrivals at 200/s; 10000 for the full stream; 0 skips)")
+    ap.add_argument("--no-diagonal", action="store_true", help="skip the diagonal-method comparison")
+    ap.add_argument("--diagonal-zipf16k", action="store_true",
+                    help="also run the diagonal method on the 16384 x 16384 Zipf workload (tens of GB of plaintexts)")
     ap.add_argument("--profile-only", action="store_true", help="run warmup + steps only (for rocprofv3)")
     ap.add_argument("--profile-ntt", action="store_true",
                     help="with --profile-only: also run the standalone NTT measurement (256 MiB of limbs, 5 launches)")
@@ -214,6 +217,10 @@ def main():
     result["two_slot_rows_exact_step_keys"] = layout_variant(H, torch, ctx2, w, tens, out, want, args.steps, True,
                                                              "two slot rows + exact-step keys")
     ctx2.close()
+    if not args.no_diagonal:
+        result["diagonal_baseline"] = {"small": diagonal_baseline(H, W, torch, dev, "small", reps=10)}
+        if args.diagonal_zipf16k:
+            result["diagonal_baseline"]["zipf16k"] = diagonal_baseline(H, W, torch, dev, "zipf16k", reps=2)
     if args.workload == "zipf16k" and not args.no_batch:
         result["batched_vs_plain"] = batched_vs_plain(H, W, torch, dev)
     if args.workload == "zipf16k" and args.serve_requests > 0:
@@ -267,6 +274,68 @@ def layout_variant(H, torch, ctx, w, tensors, out, want, n_steps, exact_keys, la
          "key_switches_per_spmv": counters["key_switches"], "rotations_per_spmv": counters["rotations"]}
     if exact_keys:
         r.update({"rotation_steps": steps, "extra_keys": n_new, "extra_key_bytes": n_new * key_bytes})
+    return r
+
+
+def diagonal_baseline(H, W, torch, dev, name, reps):
+    """The paper's diagonal-method baseline against CSSC on the same workload, ring and keys: the
+    whole protocol step (pack + encrypt + SpMV + decrypt) and the server-side SpMV alone, each
+    timed as the mean of `reps` synchronised runs after one warm-up; both decrypt to the integer
+    SpMV."""
+    gen, logn, L, bits, K, agg, desc = WORKLOADS[name]
+    w = getattr(W, gen)()
+    ctx = H.Context(logn, L, bits, K, agg_mode=agg)
+    ks = ctx.keygen(0x5EED + 3)
+    rp = torch.from_numpy(w["row_ptr"]).to(dev)
+    col = torch.from_numpy(w["col"].astype(np.int32)).to(dev)
+    val = torch.from_numpy(w["val"].astype(np.int64)).to(dev)
+    v = torch.from_numpy(w["v"].astype(np.int64)).to(dev)
+    out = torch.zeros(w["R"], dtype=torch.int64, device=dev)
+    want = torch.from_numpy(W.spmv_mod_t(w)).to(dev)
+    methods = {
+        "cssc": (lambda: H.Matrix(ctx, w["R"], w["C"], rp, col, val), H.encrypt, H.he_spmv, H.decrypt),
+        "diagonal": (lambda: H.DiagMatrix(ctx, w["R"], w["C"], rp, col, val), H.diag_encrypt, H.diag_spmv, H.diag_decrypt),
+    }
+    r = {"workload": desc}
+    for label, (pack, enc, spmv, dec) in methods.items():
+        def step(i):
+            m = pack()
+            x = enc(ctx, ks, m, v, 300 + i)
+            y = spmv(ctx, ks, m, x)
+            dec(ctx, ks, m, y, out)
+            return m, x, y
+
+        m, x, y = step(0)
+        torch.cuda.synchronize()
+        if not torch.equal(out, want):
+            raise RuntimeError(label + ": decrypted result differs from the integer SpMV")
+        del m, x, y
+        torch.cuda.synchronize(); t0 = time.perf_counter()
+        for i in range(reps):
+            step(1 + i)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3 / reps
+        m = pack()
+        x = enc(ctx, ks, m, v, 9)
+        spmv(ctx, ks, m, x)
+        torch.cuda.synchronize(); t0 = time.perf_counter()
+        for i in range(reps):
+            spmv(ctx, ks, m, x)
+        torch.cuda.synchronize()
+        spmv_ms = (time.perf_counter() - t0) * 1e3 / reps
+        cnt = H.last_counters()
+        r[label] = {"step_ms": round(step_ms, 3), "spmv_ms": round(spmv_ms, 3), "key_switches": cnt["key_switches"],
+                    "products": cnt["products"]}
+        if label == "diagonal":
+            B, nrb, ncb, nd = m.info()
+            r[label].update({"block": B, "block_rows": nrb, "block_columns": ncb, "diagonals": nd})
+        else:
+            r[label]["chunk_ciphertexts"] = m.info()[1]
+        del m, x
+    r["speedup_step"] = round(r["diagonal"]["step_ms"] / r["cssc"]["step_ms"], 2)
+    r["speedup_spmv"] = round(r["diagonal"]["spmv_ms"] / r["cssc"]["spmv_ms"], 2)
+    ks.close()
+    ctx.close()
     return r
 
 

@@ -80,6 +80,7 @@ typedef struct hs_ctx hs_ctx;
 typedef struct hs_keyset hs_keyset;
 typedef struct hs_matrix hs_matrix;
 typedef struct hs_ctvec hs_ctvec;
+typedef struct hs_diag hs_diag;
 
 /* Create a context: prime selection (the largest primes q < 2^q_bits with q = 1 mod 2N, first K
    special, next L data primes, then tensor primes for exact ct x ct), NTT tables, constants.
@@ -229,6 +230,44 @@ void hs_server_destroy(hs_server* s);
    0. */
 int hs_decrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* y,
                int64_t* out, int64_t rows, void* stream);
+
+/* ---------------------------------------------------------------- the diagonal method
+   The paper's baseline (Sec. 5, baseline approaches, and its diagonal-method figure), run on the
+   same primitives so that the two methods are compared on one GPU.  The matrix is cut into square
+   blocks of side B = min(N/4, max(rows, cols)), zero padded at the right and bottom edges.  Block
+   (bi, bj) keeps each generalised diagonal d (0 <= d < B) that holds a stored entry:
+   diag[i] = A[bi B + i][bj B + (i + d) mod B], encoded into slots [0, B) of slot row 0 as one
+   NTT-form plaintext.  Diagonals are ordered by (bi, bj, d).  The vector block bj is encrypted
+   twice over (slots j and B + j hold v[bj B + j]), so a left rotation by d puts
+   v[bj B + (i + d) mod B] in slot i.  Result block bi = sum over its diagonals of
+   diag (.) Rot(x_bj, d); its slots [0, B) hold rows bi B .. bi B + B - 1 of A v mod t. */
+/* Client A: CSR (device row_ptr int64[rows+1], col_idx int32[nnz], vals int64[nnz], columns
+   strictly ascending within a row) -> the diagonal plaintexts.  HS_EINVAL for malformed CSR. */
+int hs_diag_pack(hs_ctx* ctx, int64_t rows, int64_t cols, const int64_t* row_ptr,
+                 const int32_t* col_idx, const int64_t* vals, void* stream, hs_diag** out);
+void hs_diag_destroy(hs_diag* d);
+/* out4 = (B, block rows, block columns, diagonals). */
+int hs_diag_info(const hs_diag* d, int64_t out4[4]);
+/* The diagonals' (bi, bj, d) triples in their order, into host int64[3 * diagonals]. */
+int hs_diag_keys(const hs_diag* d, int64_t* host_out, int64_t cap);
+/* Diagonal k's plaintext, [L][N] NTT form, into host memory. */
+int hs_diag_export(const hs_diag* d, int64_t k, uint64_t* host_out, int64_t cap);
+/* The distinct non-zero rotation steps d of the diagonals, ascending (for
+   hs_keyset_add_rotation_keys); *len receives the count, HS_ECAPACITY if cap is smaller. */
+int hs_diag_rotation_steps(const hs_diag* d, int64_t* host_steps, int64_t cap, int64_t* len);
+/* Client B: the vector (device int64[len], len = cols) as one ciphertext per block column, each
+   x_bj || x_bj, encrypted with the sampling index bj. */
+int hs_diag_encrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_diag* d, const int64_t* v,
+                    int64_t len, uint64_t seed, void* stream, hs_ctvec** out);
+/* Cloud: one result ciphertext per block row.  Rot(x_bj, d) uses one exact-step key switch when
+   the key-set holds a key for d, else the binary digits of d in ascending order (each partial
+   rotation computed once per block column).  hs_last_counters then reports [0] key switches,
+   [1] distinct rotated blocks, [2] kernel launches, [3] diagonal products. */
+int hs_diag_spmv(hs_ctx* ctx, const hs_keyset* ks, const hs_diag* d, const hs_ctvec* x,
+                 void* stream, hs_ctvec** y);
+/* Key holder: out (device int64[rows]) = A v reduced into (-t/2, t/2]. */
+int hs_diag_decrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_diag* d, const hs_ctvec* y,
+                    int64_t* out, int64_t rows, void* stream);
 
 /* ---------------------------------------------------------------- ciphertext vectors */
 int hs_ctvec_count(const hs_ctvec* v, int64_t* n);

@@ -5,6 +5,7 @@
 // oracle at sizes the oracle handles quickly.
 #include "hs_device.hpp"
 #include "kernels.hpp"
+#include "diag.hpp"
 
 namespace hs {
 
@@ -185,6 +186,57 @@ __global__ void k_slots_scatter(const u64* __restrict__ Mntt, const u32* __restr
   }
 }
 
+// The diagonal method's packing.  A block diagonal is named by id = (bi ncb + bj) B + d with
+// d = (j - i) mod B for the entry (bi B + i, bj B + j); ids ascend in (bi, bj, d) order.
+// One thread per matrix row: flag every id that holds a stored entry (entries with an invalid
+// column are skipped here and reported by the column check).
+__global__ void k_diag_mark(const i64* __restrict__ row_ptr, const int* __restrict__ col, i64 R, i64 C, i64 B, i64 ncb, unsigned char* flags) {
+  const i64 r = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const i64 bi = r / B, i = r - bi * B;
+  for (i64 k = row_ptr[r]; k < row_ptr[r + 1]; k++) {
+    const i64 c = col[k];
+    if (c < 0 || c >= C) continue;
+    const i64 bj = c / B, j = c - bj * B;
+    flags[(bi * ncb + bj) * B + (j - i + B) % B] = 1;
+  }
+}
+
+// Slot i of diagonal (bi, bj, d) receives A[bi B + i][bj B + (i + d) mod B] mod t at position
+// slot_pos[i] of that diagonal's row (then the inverse mod-t NTT).  The diagonal's row is found by
+// binary search in the ascending id list.  The column check has passed before this runs.
+__global__ void k_diag_place(const i64* __restrict__ row_ptr, const int* __restrict__ col, const i64* __restrict__ val, i64 R, i64 B, i64 ncb,
+                             const i64* __restrict__ ids, int nd, u64* out, const u32* __restrict__ slot_pos, u64 t, int logn) {
+  const i64 r = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const i64 bi = r / B, i = r - bi * B;
+  const u32 pos = slot_pos[i];
+  for (i64 k = row_ptr[r]; k < row_ptr[r + 1]; k++) {
+    const i64 c = col[k], bj = c / B, j = c - bj * B;
+    const i64 id = (bi * ncb + bj) * B + (j - i + B) % B;
+    int lo = 0, hi = nd - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (ids[mid] < id) lo = mid + 1; else hi = mid;
+    }
+    out[((size_t)lo << logn) + pos] = smod_i64(val[k], t);
+  }
+}
+
+// Vector block bj, twice over: slots j and B + j hold v[bj B + j] mod t (0 past the last column),
+// every other slot 0; written at slot_pos order (then the inverse mod-t NTT).
+__global__ void k_diag_vector(const i64* __restrict__ v, i64 C, i64 B, int ncb, u64* out, const u32* __restrict__ slot_pos, u64 t, int logn) {
+  const i64 n = 1 << logn;
+  const i64 total = (i64)ncb * n;
+  for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
+    const i64 bj = idx >> logn, k = idx & (n - 1);
+    const i64 j = k < B ? k : (k < 2 * B ? k - B : -1);
+    const i64 cc = bj * B + j;
+    const u64 x = (j >= 0 && cc < C) ? smod_i64(v[cc], t) : 0;
+    out[(size_t)bj * n + slot_pos[k]] = x;
+  }
+}
+
 // ------------------------------------------------------------------ launchers
 static dim3 grid_for(i64 total) { return dim3((unsigned)std::min<i64>((total + 255) / 256, 256 * 64)); }
 static dim3 grid_rows(i64 rows, i64 n) {
@@ -234,6 +286,21 @@ void launch_slots_scatter(const hs_ctx* c, const u64* Mntt, const int* rm, const
   hipLaunchKernelGGL(k_slots_scatter, dim3(std::max<int>(1, (int)((c->N / 2 + 255) / 256)), nparts), dim3(256), 0, st, Mntt,
                      (const u32*)c->d_slot_pos, rm, pinfo, nparts, y, c->t, c->logn);
   HS_CHECK_HIP(hipGetLastError());
+}
+
+void launch_diag_mark(const i64* row_ptr, const int* col, i64 R, i64 C, i64 B, i64 ncb, unsigned char* flags, hipStream_t st) {
+  if (R <= 0) return;
+  HSX_LAUNCH(k_diag_mark, dim3((unsigned)((R + 255) / 256)), st, row_ptr, col, R, C, B, ncb, flags);
+}
+void launch_diag_place(const hs_ctx* c, const i64* row_ptr, const int* col, const i64* val, i64 R, i64 B, i64 ncb, const i64* ids, int nd,
+                       u64* out, hipStream_t st) {
+  if (R <= 0 || nd <= 0) return;
+  HSX_LAUNCH(k_diag_place, dim3((unsigned)((R + 255) / 256)), st, row_ptr, col, val, R, B, ncb, ids, nd, out, (const u32*)c->d_slot_pos, c->t,
+             c->logn);
+}
+void launch_diag_vector(const hs_ctx* c, const i64* v, i64 C, i64 B, int ncb, u64* out, hipStream_t st) {
+  if (ncb <= 0) return;
+  HSX_LAUNCH(k_diag_vector, grid_for((i64)ncb * c->N), st, v, C, B, ncb, out, (const u32*)c->d_slot_pos, c->t, c->logn);
 }
 
 }  // namespace hs

@@ -13,6 +13,7 @@
 #include <unordered_map>
 
 #include "kernels.hpp"
+#include "diag.hpp"
 
 namespace hs {
 const char* last_error_cstr();
@@ -1633,6 +1634,308 @@ int hs_mul_ct(hs_ctx* c, const hs_keyset* ks, const hs_ctvec* a, const hs_ctvec*
       throw;
     }
     *out = r;
+  });
+}
+
+// ---------------------------------------------------------------- the diagonal method
+// The paper's baseline (Sec. 5, baseline approaches; the diagonal-method figure): square blocks of
+// side B = min(N/4, max(R, C)), one plaintext per non-empty generalised block diagonal, the vector
+// block encrypted twice over, and per block row the sum of diagonal (.) Rot(x_bj, d).
+int hs_diag_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, const int32_t* col_idx, const int64_t* vals,
+                 void* stream, hs_diag** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && out, HS_EINVAL, "null argument");
+    *out = nullptr;
+    HS_REQUIRE(rows >= 0 && cols >= 0 && rows < (1LL << 31) && cols < (1LL << 31), HS_EINVAL, "bad matrix shape");
+    HS_REQUIRE(rows == 0 || row_ptr, HS_EINVAL, "null row_ptr");
+    hipStream_t st = S(stream);
+    const size_t N = c->N;
+    std::vector<i64> rp(rows + 1, 0);
+    if (rows) {
+      d2h(rp.data(), row_ptr, rows + 1, st);
+      HS_CHECK_HIP(hipStreamSynchronize(st));
+    }
+    HS_REQUIRE(rp[0] == 0, HS_EINVAL, "row_ptr[0] must be 0");
+    for (i64 i = 0; i < rows; i++) HS_REQUIRE(rp[i + 1] >= rp[i], HS_EINVAL, "row_ptr must be nondecreasing");
+    const i64 nnz = rp[rows];
+    HS_REQUIRE(nnz == 0 || (col_idx && vals), HS_EINVAL, "null col_idx/vals");
+    hs_diag* D = new hs_diag();
+    D->ctx = c; D->R = rows; D->C = cols;
+    D->B = std::min<i64>((i64)N / 4, std::max<i64>(std::max<i64>(rows, cols), 1));
+    D->nrb = (int)((rows + D->B - 1) / D->B);
+    D->ncb = (int)((cols + D->B - 1) / D->B);
+    try {
+      const i64 B = D->B, nids = (i64)D->nrb * D->ncb * B;
+      HS_REQUIRE(nids < (1LL << 33), HS_ECAPACITY, "too many block diagonals for the diagonal method");
+      // non-empty diagonals: flagged on the device, listed in ascending id order on the host
+      std::vector<i64> ids;
+      if (nnz) {
+        const size_t fbytes = ((size_t)nids + 255) & ~(size_t)255;
+        DBuf flags(&c->pool, fbytes + 256);
+        unsigned char* fl = flags.as<unsigned char>();
+        int* dbad = (int*)(fl + fbytes);
+        HS_CHECK_HIP(hipMemsetAsync(fl, 0, fbytes + 256, st));
+        launch_csr_check(row_ptr, col_idx, rows, cols, dbad, st);
+        launch_diag_mark(row_ptr, col_idx, rows, cols, B, D->ncb, fl, st);
+        std::vector<unsigned char> h(fbytes + 256);
+        d2h(h.data(), fl, h.size(), st);
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+        int bad = 0;
+        std::memcpy(&bad, h.data() + fbytes, sizeof(int));
+        HS_REQUIRE(!bad, HS_EINVAL, "column indices out of range or not strictly ascending within a row");
+        for (i64 id = 0; id < nids; id++)
+          if (h[id]) ids.push_back(id);
+      }
+      const i64 nd = (i64)ids.size();
+      HS_REQUIRE(nd < (1LL << 31), HS_ECAPACITY, "too many diagonals");
+      D->row0.assign(D->nrb, 0);
+      D->rown.assign(D->nrb, 0);
+      for (i64 k = 0; k < nd; k++) {
+        const i64 bi = ids[k] / ((i64)D->ncb * B), rem = ids[k] % ((i64)D->ncb * B);
+        D->key.insert(D->key.end(), {bi, rem / B, rem % B});
+        if (!D->rown[bi]) D->row0[bi] = (int)k;
+        D->rown[bi]++;
+      }
+      // identity row map [B] | per block row (row0, rows, rows, 0, block row, 0) | diagonal ids
+      std::vector<i32> rm(B);
+      std::iota(rm.begin(), rm.end(), 0);
+      std::vector<i64> pinfo(6ULL * std::max(D->nrb, 1), 0);
+      for (int bi = 0; bi < D->nrb; bi++) {
+        i64* q = &pinfo[6ULL * bi];
+        q[0] = bi * B; q[1] = std::min(B, rows - bi * B); q[2] = q[1]; q[3] = 0; q[4] = bi; q[5] = 0;
+      }
+      auto seg = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
+      const size_t o_rm = 0, o_pi = seg(rm.size() * 4), o_id = o_pi + seg(pinfo.size() * 8), total = o_id + seg(ids.size() * 8 + 8);
+      char* up = (char*)t_stage_up.get(total);
+      std::memcpy(up + o_rm, rm.data(), rm.size() * 4);
+      std::memcpy(up + o_pi, pinfo.data(), pinfo.size() * 8);
+      if (nd) std::memcpy(up + o_id, ids.data(), ids.size() * 8);
+      D->d_struct = pmalloc<char>(c, total);
+      HS_CHECK_HIP(hipMemcpyAsync(D->d_struct, up, total, hipMemcpyHostToDevice, st));
+      D->d_rm = (i32*)(D->d_struct + o_rm);
+      D->d_pinfo = (i64*)(D->d_struct + o_pi);
+      std::vector<DBuf> hold;
+      if (nd) {
+        DBuf coef(&c->pool, (size_t)nd * N * sizeof(u64));
+        HS_CHECK_HIP(hipMemsetAsync(coef.p, 0, coef.bytes, st));
+        launch_diag_place(c, row_ptr, col_idx, vals, rows, B, D->ncb, (const i64*)(D->d_struct + o_id), (int)nd, coef.as<u64>(), st);
+        ntt_any(c, coef.as<u64>(), nd, 1, c->n_mod, 1, st, hold);
+        D->d_pt = pmalloc<u64>(c, (size_t)nd * c->L * N);
+        plain_ntt(c, coef.as<u64>(), D->d_pt, (int)nd, st, hold);
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+      } else {
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+      }
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      hs_diag_destroy(D);
+      throw;
+    }
+    *out = D;
+  });
+}
+
+void hs_diag_destroy(hs_diag* D) {
+  if (!D) return;
+  (void)hipDeviceSynchronize();
+  pfree(D->ctx, D->d_struct);
+  pfree(D->ctx, D->d_pt);
+  delete D;
+}
+
+int hs_diag_info(const hs_diag* D, int64_t out4[4]) {
+  return guarded([&] {
+    HS_REQUIRE(D && out4, HS_EINVAL, "null argument");
+    out4[0] = D->B; out4[1] = D->nrb; out4[2] = D->ncb; out4[3] = (int64_t)D->key.size() / 3;
+  });
+}
+
+int hs_diag_keys(const hs_diag* D, int64_t* host_out, int64_t cap) {
+  return guarded([&] {
+    HS_REQUIRE(D, HS_EINVAL, "null argument");
+    HS_REQUIRE(cap >= (int64_t)D->key.size() && (host_out || D->key.empty()), HS_ECAPACITY, "output too small");
+    if (!D->key.empty()) std::memcpy(host_out, D->key.data(), D->key.size() * sizeof(i64));
+  });
+}
+
+int hs_diag_export(const hs_diag* D, int64_t k, uint64_t* host_out, int64_t cap) {
+  return guarded([&] {
+    HS_REQUIRE(D && host_out, HS_EINVAL, "null argument");
+    HS_REQUIRE(k >= 0 && k < (int64_t)D->key.size() / 3, HS_EINVAL, "diagonal index out of range");
+    const size_t n = (size_t)D->ctx->L * D->ctx->N;
+    HS_REQUIRE((size_t)cap >= n, HS_ECAPACITY, "output too small");
+    HS_CHECK_HIP(hipMemcpy(host_out, D->d_pt + k * n, n * sizeof(u64), hipMemcpyDeviceToHost));
+  });
+}
+
+int hs_diag_rotation_steps(const hs_diag* D, int64_t* out, int64_t cap, int64_t* len) {
+  return guarded([&] {
+    HS_REQUIRE(D && len, HS_EINVAL, "null argument");
+    std::vector<char> used(D->B, 0);
+    for (size_t k = 0; k < D->key.size(); k += 3) used[D->key[k + 2]] = 1;
+    std::vector<i64> steps;
+    for (i64 d = 1; d < D->B; d++)
+      if (used[d]) steps.push_back(d);
+    *len = (int64_t)steps.size();
+    HS_REQUIRE(cap >= *len && (out || steps.empty()), HS_ECAPACITY, "output too small");
+    if (!steps.empty()) std::memcpy(out, steps.data(), steps.size() * sizeof(i64));
+  });
+}
+
+int hs_diag_encrypt(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const int64_t* v, int64_t len, uint64_t seed, void* stream,
+                    hs_ctvec** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks && D && out, HS_EINVAL, "null argument");
+    *out = nullptr;
+    HS_REQUIRE(ks->ctx == c && D->ctx == c, HS_EKEY, "handles from another context");
+    HS_REQUIRE(len == D->C, HS_EINVAL, "vector length must equal the number of matrix columns");
+    HS_REQUIRE(len == 0 || v, HS_EINVAL, "null vector");
+    hipStream_t st = S(stream);
+    const int G = D->ncb;
+    const size_t N = c->N;
+    hs_ctvec* x = new_ctvec(c, G);
+    try {
+      if (G) {
+        std::vector<DBuf> hold;
+        DBuf coef(&c->pool, (size_t)G * N * sizeof(u64));
+        launch_diag_vector(c, v, D->C, D->B, G, coef.as<u64>(), st);
+        ntt_any(c, coef.as<u64>(), G, 1, c->n_mod, 1, st, hold);
+        DBuf smp(&c->pool, (size_t)G * 3 * N * sizeof(int));
+        launch_sample_small(c, smp.as<int>(), G, 3 * (i64)N, seed, P_ENC_U, 0, 1, 0, st);
+        launch_sample_small(c, smp.as<int>() + N, G, 3 * (i64)N, seed, P_ENC_E0, 0, 1, 1, st);
+        launch_sample_small(c, smp.as<int>() + 2 * N, G, 3 * (i64)N, seed, P_ENC_E1, 0, 1, 1, st);
+        encrypt_coefs(c, coef.as<u64>(), smp.as<int>(), ks->pk, x->d, G, st, hold);
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+      }
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      hs_ctvec_destroy(x);
+      throw;
+    }
+    *out = x;
+  });
+}
+
+// Rotations of the vector blocks: Rot(x_bj, d) for every (bj, d) a diagonal needs.  With an
+// exact-step key for d, one key switch from x_bj; otherwise the binary digits of d in ascending
+// order, so Rot(x_bj, d) = Rot_{2^h}(Rot(x_bj, d - 2^h)) with h the top bit of d: every such
+// partial rotation is computed once per block column and shared.  Level h holds the partial
+// rotations whose top bit is h (the exact-step ones go to level 0); levels are cut into batches of
+// at most kDiagBatch key switches.
+static constexpr size_t kDiagBatch = 256;
+int hs_diag_spmv(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const hs_ctvec* x, void* stream, hs_ctvec** y) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks && D && x && y, HS_EINVAL, "null argument");
+    *y = nullptr;
+    HS_REQUIRE(ks->ctx == c && D->ctx == c && x->ctx == c, HS_EKEY, "handles from another context");
+    HS_REQUIRE(x->n == D->ncb, HS_EINVAL, "one encrypted vector block per block column expected");
+    hipStream_t st = S(stream);
+    const size_t CW = ct_words(c);
+    const i64 B = D->B, nd = (i64)D->key.size() / 3;
+    hs_ctvec* r = new_ctvec(c, D->nrb);
+    try {
+      // per block column: slot of each partial (digit) rotation and each exact-step rotation
+      // (a step with an exact key may also be a partial rotation of another step's digits: the
+      // two are different ciphertexts and both are kept)
+      std::vector<std::vector<int>> tree(D->ncb, std::vector<int>(B, -1)), direct(D->ncb, std::vector<int>(B, -1));
+      std::vector<std::vector<char>> seen(D->ncb, std::vector<char>(B, 0));
+      int nbuf = 0, nlog = 0;
+      for (i64 k = 0; k < nd; k++) {
+        const i64 bj = D->key[3 * k + 1], d = D->key[3 * k + 2];
+        if (!d || seen[bj][d]) continue;
+        seen[bj][d] = 1;
+        nlog++;
+        if (!is_pow2(d) && ks->step_keys.count(d)) { direct[bj][d] = nbuf++; continue; }
+        for (i64 p = d; p && tree[bj][p] < 0; p &= ~(1LL << (63 - __builtin_clzll((u64)p)))) tree[bj][p] = nbuf++;
+      }
+      DBuf rot(&c->pool, (size_t)std::max(nbuf, 1) * CW * sizeof(u64));
+      auto at = [&](int idx) { return rot.as<u64>() + (size_t)idx * CW; };
+      int top = 0;
+      while ((2LL << top) < B) top++;
+      std::vector<std::vector<RotItem>> levels;
+      auto push = [&](std::vector<RotItem>& lv, const RotItem& it) {
+        lv.push_back(it);
+        if (lv.size() == kDiagBatch) { levels.push_back(lv); lv.clear(); }
+      };
+      for (int h = 0; h <= top; h++) {
+        std::vector<RotItem> lv;
+        for (int bj = 0; bj < D->ncb; bj++) {
+          const u64* xb = x->d + (size_t)bj * CW;
+          if (h == 0)
+            for (i64 d = 1; d < B; d++)
+              if (direct[bj][d] >= 0) {
+                RotItem it{};
+                it.in = xb; it.out = at(direct[bj][d]); it.addend = nullptr;
+                it.key = rotation_key(ks, d); it.galois = (u32)galois_step(c, d);
+                push(lv, it);
+              }
+          for (i64 d = 1LL << h; d < std::min<i64>(2LL << h, B); d++)
+            if (tree[bj][d] >= 0) {
+              const i64 p = d - (1LL << h);
+              RotItem it{};
+              it.in = p ? at(tree[bj][p]) : xb; it.out = at(tree[bj][d]); it.addend = nullptr;
+              it.key = rotation_key(ks, 1LL << h); it.galois = (u32)galois_step(c, 1LL << h);
+              push(lv, it);
+            }
+        }
+        if (!lv.empty()) levels.push_back(lv);
+      }
+      for (int i = 0; i < 5; i++) g_counters[i] = 0;
+      run_rotation_levels(c, levels, st);
+      g_counters[1] = nlog;
+      // per block row: sum over its diagonals of plaintext (.) rotated block (one pass, the
+      // masked-sum kernel with the diagonals as masks)
+      if (D->nrb) {
+        std::vector<u64> words(std::max<i64>(nd, 1), 0);
+        for (i64 k = 0; k < nd; k++) {
+          const i64 bj = D->key[3 * k + 1], d = D->key[3 * k + 2];
+          const u64* src = !d ? x->d + (size_t)bj * CW : at(direct[bj][d] >= 0 ? direct[bj][d] : tree[bj][d]);
+          words[k] = (u64)(uintptr_t)src;
+        }
+        const size_t w0 = words.size();
+        words.resize(w0 + ((size_t)2 * D->nrb * sizeof(int) + 7) / 8, 0);
+        std::memcpy(words.data() + w0, D->row0.data(), D->nrb * sizeof(int));
+        std::memcpy((char*)(words.data() + w0) + D->nrb * sizeof(int), D->rown.data(), D->nrb * sizeof(int));
+        DBuf dw(&c->pool, words.size() * sizeof(u64));
+        h2d(dw.as<u64>(), words.data(), words.size(), st);
+        const int* pc0 = (const int*)(dw.as<u64>() + w0);
+        launch_mask_acc(c, (const u64* const*)dw.as<u64>(), D->d_pt, pc0, pc0 + D->nrb, r->d, D->nrb, st);
+        g_counters[2] += 1;
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+      }
+      g_counters[3] = nd;
+    } catch (...) {
+      (void)hipStreamSynchronize(st);
+      hs_ctvec_destroy(r);
+      throw;
+    }
+    *y = r;
+  });
+}
+
+int hs_diag_decrypt(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const hs_ctvec* y, int64_t* out, int64_t rows, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks && D && y, HS_EINVAL, "null argument");
+    HS_REQUIRE(ks->ctx == c && D->ctx == c && y->ctx == c, HS_EKEY, "handles from another context");
+    HS_REQUIRE(rows == D->R, HS_EINVAL, "rows must equal the matrix row count");
+    HS_REQUIRE(y->n == D->nrb, HS_EINVAL, "one result ciphertext per block row expected");
+    HS_REQUIRE(rows == 0 || out, HS_EINVAL, "null output");
+    const int nb = D->nrb;
+    if (!nb) return;
+    hipStream_t st = S(stream);
+    const size_t N = c->N;
+    DBuf X(&c->pool, (size_t)nb * c->L * N * sizeof(u64)), Mc(&c->pool, (size_t)nb * N * sizeof(u64));
+    std::vector<DBuf> hold;
+    if (use_split_client(c)) {
+      launch_dec_prep(c, y->d, ks->sk, X.as<u64>(), nb, st);
+      ntt_any(c, X.as<u64>(), (i64)nb * c->L, c->L, 0, 1, st, hold);
+    } else {
+      launch_dec_phase(c, y->d, ks->sk, X.as<u64>(), nb, st);
+    }
+    launch_dec_round(c, X.as<u64>(), Mc.as<u64>(), nb, st);
+    ntt_any(c, Mc.as<u64>(), nb, 1, c->n_mod, 0, st, hold);
+    launch_slots_scatter(c, Mc.as<u64>(), D->d_rm, D->d_pinfo, nb, out, st);
+    HS_CHECK_HIP(hipStreamSynchronize(st));
   });
 }
 

@@ -1,0 +1,10 @@
+// Launchers of the diagonal method's packing kernels (defined in aux2.hip).
+#pragma once
+#include "hs_internal.hpp"
+
+namespace hs {
+void launch_diag_mark(const i64* row_ptr, const int* col, i64 R, i64 C, i64 B, i64 ncb, unsigned char* flags, hipStream_t st);
+void launch_diag_place(const hs_ctx* c, const i64* row_ptr, const int* col, const i64* val, i64 R, i64 B, i64 ncb, const i64* ids, int nd,
+                       u64* out, hipStream_t st);
+void launch_diag_vector(const hs_ctx* c, const i64* v, i64 C, i64 B, int ncb, u64* out, hipStream_t st);
+}  // namespace hs

@@ -201,6 +201,20 @@ struct hs_matrix {
   hipEvent_t ready = nullptr;    // recorded on the context's side stream when d_pt/d_mask are final
 };
 
+// The diagonal method (the paper's baseline): square blocks of side B; per block its non-empty
+// generalised diagonals, each one NTT-form plaintext, sorted by (block row, block column, d).
+struct hs_diag {
+  hs_ctx* ctx = nullptr;
+  hs::i64 R = 0, C = 0, B = 0;
+  int nrb = 0, ncb = 0;              // block rows, block columns
+  std::vector<hs::i64> key;          // per diagonal: (bi, bj, d)
+  std::vector<int> row0, rown;       // per block row: first diagonal, number of diagonals
+  char* d_struct = nullptr;          // identity row map [B] (i32) | per block row 6-word scatter info
+  hs::i32* d_rm = nullptr;
+  hs::i64* d_pinfo = nullptr;
+  hs::u64* d_pt = nullptr;           // [n diagonals][L][N]
+};
+
 struct hs_ctvec {
   hs_ctx* ctx = nullptr;
   hs::i64 n = 0;                 // ciphertexts

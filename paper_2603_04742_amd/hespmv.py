@@ -85,6 +85,15 @@ SIGNATURES = {
     "hs_ctvec_copy": (_int, [_vp, _vp, _vp]),
     "hs_autotune": (_int, [_vp, _vp, _vp, ctypes.POINTER(ctypes.c_double), _int, ctypes.POINTER(ctypes.c_int)]),
     "hs_tuning": (_int, [_vp, _i64p]),
+    "hs_diag_pack": (_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp, _pp]),
+    "hs_diag_destroy": (None, [_vp]),
+    "hs_diag_info": (_int, [_vp, _i64p]),
+    "hs_diag_keys": (_int, [_vp, _i64p, _i64]),
+    "hs_diag_export": (_int, [_vp, _i64, _u64p, _i64]),
+    "hs_diag_rotation_steps": (_int, [_vp, _i64p, _i64, _i64p]),
+    "hs_diag_encrypt": (_int, [_vp, _vp, _vp, _vp, _i64, _u64, _vp, _pp]),
+    "hs_diag_spmv": (_int, [_vp, _vp, _vp, _vp, _vp, _pp]),
+    "hs_diag_decrypt": (_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp]),
     "hs_set_tuning": (_int, [_vp, _i64p]),
 }
 
@@ -286,6 +295,68 @@ class Matrix:
         out = np.zeros(n, np.uint64)
         _check(lib.hs_matrix_export(self.h, which, k, out.ctypes.data_as(_u64p), n))
         return out
+
+
+class DiagMatrix:
+    """The diagonal method (the paper's baseline): hs_diag_pack of a CSR matrix given as CUDA
+    tensors (int64 row_ptr, int32 col, int64 vals)."""
+
+    def __init__(self, ctx, rows, cols, row_ptr, col, val):
+        self.ctx, self.R, self.C = ctx, rows, cols
+        h = ctypes.c_void_p()
+        _check(lib.hs_diag_pack(ctx.h, rows, cols, _dptr(row_ptr), _dptr(col), _dptr(val), _stream(), ctypes.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None) and lib is not None:
+            lib.hs_diag_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def info(self):
+        """(B, block rows, block columns, diagonals)."""
+        out = np.zeros(4, np.int64)
+        _check(lib.hs_diag_info(self.h, out.ctypes.data_as(_i64p)))
+        return tuple(int(x) for x in out)
+
+    def keys(self):
+        n = self.info()[3]
+        out = np.zeros(max(3 * n, 1), np.int64)
+        _check(lib.hs_diag_keys(self.h, out.ctypes.data_as(_i64p), out.size))
+        return out[:3 * n].reshape(n, 3)
+
+    def export(self, k):
+        c = self.ctx
+        out = np.zeros(c.L * c.N, np.uint64)
+        _check(lib.hs_diag_export(self.h, k, out.ctypes.data_as(_u64p), out.size))
+        return out
+
+    def rotation_steps(self):
+        n = ctypes.c_int64()
+        lib.hs_diag_rotation_steps(self.h, None, 0, ctypes.byref(n))
+        out = np.zeros(max(n.value, 1), np.int64)
+        _check(lib.hs_diag_rotation_steps(self.h, out.ctypes.data_as(_i64p), out.size, ctypes.byref(n)))
+        return [int(x) for x in out[:n.value]]
+
+
+def diag_encrypt(ctx, ks, d, v, seed):
+    """Client B of the diagonal method: one ciphertext per block column (CUDA int64 vector v)."""
+    h = ctypes.c_void_p()
+    _check(lib.hs_diag_encrypt(ctx.h, ks.h, d.h, _dptr(v), v.numel(), seed, _stream(), ctypes.byref(h)))
+    return CtVec(ctx, h)
+
+
+def diag_spmv(ctx, ks, d, x):
+    h = ctypes.c_void_p()
+    _check(lib.hs_diag_spmv(ctx.h, ks.h, d.h, x.h, _stream(), ctypes.byref(h)))
+    return CtVec(ctx, h)
+
+
+def diag_decrypt(ctx, ks, d, y, out):
+    _check(lib.hs_diag_decrypt(ctx.h, ks.h, d.h, y.h, _dptr(out), d.R, _stream()))
+    return out
 
 
 def encrypt(ctx, ks, m, v, seed):

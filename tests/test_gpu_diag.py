@@ -1,0 +1,142 @@
+"""GPU: the diagonal method (the paper's baseline, Sec. 5 and its diagonal-method figure) against
+the oracle, bit for bit, through the C ABI.
+
+Every diagonal plaintext, the diagonal keys, the encrypted vector blocks, every result limb and the
+decrypted product must equal the oracle's; with exact-step keys for some of the steps, rotations
+by those steps take one key switch and the rest keep the binary digits, as in the oracle.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2603_04742_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2603_04742_amd import hespmv as H  # noqa: E402
+
+TINY = (9, 3, 50, 1, 0)
+TINY11 = (11, 3, 50, 1, 0)
+SMALL = (12, 2, 30, 1, 1)
+
+
+def dev(a, dtype):
+    npd = {torch.int64: np.int64, torch.int32: np.int32}[dtype]
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(a).astype(npd, copy=False))).cuda()
+
+
+def fresh(p, seed=8):
+    logn, L, bits, K, agg = p
+    g = H.Context(logn, L, bits, K, agg_mode=agg)
+    o = O.Context(logn, L, bits, K, agg_mode=agg)
+    kg = g.keygen(seed)
+    o.keygen(seed)
+    return g, kg, o
+
+
+def workload(case):
+    if case == "small":
+        return SMALL, W.small()
+    rng = np.random.default_rng({"tiny": 31, "ragged": 32, "rect": 33, "tall": 34, "empty": 35, "one": 36,
+                                 "nocols": 37, "emptyrows": 38}[case])
+    p, (R, C, nnz) = {
+        "tiny": (TINY, (300, 200, 1200)),      # B = 128: 3 x 2 blocks, ragged at both edges
+        "ragged": (TINY11, (1000, 700, 3000)),  # B = 512: 2 x 2 blocks
+        "rect": (TINY, (40, 300, 500)),        # B = 128: one block row, 3 block columns
+        "tall": (TINY, (300, 40, 400)),        # B = 128: 3 block rows, one block column
+        "empty": (TINY, (10, 10, 0)),
+        "one": (TINY, (1, 1, 1)),
+        "nocols": (TINY, (5, 0, 0)),
+        "emptyrows": (TINY, (200, 100, 50)),
+    }[case]
+    rp, col, val = W.uniform_matrix(R, C, nnz, 15, rng)
+    return p, dict(R=R, C=C, row_ptr=rp, col=col, val=val, v=rng.integers(-15, 16, C))
+
+
+def check(p, w, step_keys=None, seed=41):
+    g, kg, o = fresh(p)
+    D = H.DiagMatrix(g, w["R"], w["C"], dev(w["row_ptr"], torch.int64), dev(w["col"], torch.int32), dev(w["val"], torch.int64))
+    OD = O.DiagMatrix(o, w["R"], w["C"], w["row_ptr"], w["col"], w["val"])
+    B, nrb, ncb, nd = D.info()
+    oi = OD.info()
+    assert (B, nrb, ncb, nd) == (oi["B"], oi["row_blocks"], oi["col_blocks"], oi["diagonals"])
+    keys = D.keys()
+    assert [tuple(int(x) for x in keys[k]) for k in range(nd)] == [OD.key(k) for k in range(nd)]
+    for k in range(nd):
+        assert np.array_equal(D.export(k), OD.pt(k)), k
+    steps = D.rotation_steps()
+    assert steps == sorted({int(keys[k][2]) for k in range(nd)} - {0})
+    if step_keys is not None:
+        held = step_keys(steps)
+        kg.add_rotation_keys(held)
+        o.add_step_keys(held)
+    x = H.diag_encrypt(g, kg, D, dev(w["v"], torch.int64), seed)
+    ox = OD.encrypt_vector(w["v"], seed)
+    assert x.count() == ncb
+    assert np.array_equal(x.export_all(), ox)
+    y = H.diag_spmv(g, kg, D, x)
+    cnt = H.last_counters()
+    oy = OD.spmv(ox)
+    assert y.count() == nrb
+    assert np.array_equal(y.export_all(), oy)
+    assert cnt["products"] == nd
+    out = torch.full((w["R"],), 12345, dtype=torch.int64, device="cuda")
+    H.diag_decrypt(g, kg, D, y, out)
+    assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
+    assert np.array_equal(out.cpu().numpy(), OD.decrypt_result(oy))
+    return D, cnt
+
+
+def expected_key_switches(D, held=()):
+    """One per partial rotation of the binary-digit tree per block column, plus one per step
+    rotated with its exact key."""
+    keys = D.keys()
+    want = 0
+    for bj in range(D.info()[2]):
+        nodes = set()
+        for d in {int(k[2]) for k in keys if k[1] == bj} - {0}:
+            if d in held:
+                want += 1
+                continue
+            while d:
+                nodes.add(d)
+                d &= ~(1 << (d.bit_length() - 1))
+        want += len(nodes)
+    return want
+
+
+@pytest.mark.parametrize("case", ["tiny", "ragged", "small", "rect", "tall"])
+def test_diagonal_method_matches_oracle(case):
+    p, w = workload(case)
+    D, cnt = check(p, w)
+    assert cnt["key_switches"] == expected_key_switches(D)
+
+
+@pytest.mark.parametrize("case", ["empty", "one", "nocols", "emptyrows"])
+def test_diagonal_method_edge_cases(case):
+    p, w = workload(case)
+    check(p, w)
+
+
+def test_diagonal_method_with_exact_step_keys():
+    """Exact keys for every third non-power-of-two step: those rotations take one key switch
+    from the vector block, the others keep the digit tree (whose partial rotations may be steps
+    that also have an exact key, computed both ways as the oracle does)."""
+    p, w = workload("tiny")
+    pick = []
+    D, cnt = check(p, w, step_keys=lambda steps: pick.extend([s for s in steps if s & (s - 1)][::3]) or pick)
+    assert any(d in pick for d in (3, 5, 6, 7, 9, 10, 11)), "no exact-step key on a partial rotation"
+    assert cnt["key_switches"] == expected_key_switches(D, set(pick))
+
+
+def test_diagonal_pack_rejects_bad_columns():
+    g, kg, o = fresh(TINY)
+    rp = np.array([0, 2, 3], np.int64)
+    for col in ([0, 5], [1, 0, 2], [-1, 1, 2]):   # out of range, unsorted, negative
+        c = np.array(col + [0] * (3 - len(col)), np.int32)
+        with pytest.raises(H.HespmvError):
+            H.DiagMatrix(g, 2, 4, dev(rp, torch.int64), dev(c, torch.int32), dev(np.ones(3, np.int64), torch.int64))
