@@ -50,6 +50,9 @@ def main():
     ap.add_argument("--no-diagonal", action="store_true", help="skip the diagonal-method comparison")
     ap.add_argument("--diagonal-zipf16k", action="store_true",
                     help="also run the diagonal method on the 16384 x 16384 Zipf workload (tens of GB of plaintexts)")
+    ap.add_argument("--lazy-relin-laplace256", action="store_true",
+                    help="also time the both-encrypted 256 x 256-grid Laplacian (N = 32768) with relinearisation after "
+                         "every product and with lazy relinearisation")
     ap.add_argument("--profile-only", action="store_true", help="run warmup + steps only (for rocprofv3)")
     ap.add_argument("--profile-ntt", action="store_true",
                     help="with --profile-only: also run the standalone NTT measurement (256 MiB of limbs, 5 launches)")
@@ -221,6 +224,8 @@ def main():
         result["diagonal_baseline"] = {"small": diagonal_baseline(H, W, torch, dev, "small", reps=10)}
         if args.diagonal_zipf16k:
             result["diagonal_baseline"]["zipf16k"] = diagonal_baseline(H, W, torch, dev, "zipf16k", reps=2)
+    if args.lazy_relin_laplace256:
+        result["lazy_relin_laplace256"] = lazy_relin_laplace256(H, W, torch, dev)
     if args.workload == "zipf16k" and not args.no_batch:
         result["batched_vs_plain"] = batched_vs_plain(H, W, torch, dev)
     if args.workload == "zipf16k" and args.serve_requests > 0:
@@ -274,6 +279,54 @@ def layout_variant(H, torch, ctx, w, tensors, out, want, n_steps, exact_keys, la
          "key_switches_per_spmv": counters["key_switches"], "rotations_per_spmv": counters["rotations"]}
     if exact_keys:
         r.update({"rotation_steps": steps, "extra_keys": n_new, "extra_key_bytes": n_new * key_bytes})
+    return r
+
+
+def lazy_relin_laplace256(H, W, torch, dev, reps=3):
+    """The both-encrypted 5-point Laplacian on a 256 x 256 grid (N = 32768, 12 x 50-bit data primes,
+    2 special primes, matrix values and vector encrypted): the protocol step and the server-side
+    SpMV with relinearisation after every ct x ct product and with lazy relinearisation (one per
+    result ciphertext); both decrypt to the integer SpMV."""
+    w = W.laplace256()
+    rp = torch.from_numpy(w["row_ptr"]).to(dev)
+    col = torch.from_numpy(w["col"].astype(np.int32)).to(dev)
+    val = torch.from_numpy(w["val"].astype(np.int64)).to(dev)
+    v = torch.from_numpy(w["v"].astype(np.int64)).to(dev)
+    out = torch.zeros(w["R"], dtype=torch.int64, device=dev)
+    want = torch.from_numpy(W.spmv_mod_t(w)).to(dev)
+    r = {"workload": "laplace256: 65536 x 65536 5-point Laplacian (values 4, -1), vector in [-3,3], matrix values and "
+                     "vector encrypted; ring N=32768, 12x50-bit data primes + 2 special primes, t=65537; paper aggregation"}
+    for label, lazy in (("eager", 0), ("lazy", 1)):
+        ctx = H.Context(15, 12, 50, 2, agg_mode=0, lazy_relin=lazy)
+        ks = ctx.keygen(0x5EED + 4)
+
+        def step(i):
+            m = H.Matrix(ctx, w["R"], w["C"], rp, col, val, True, ks, 500 + i)
+            x = H.encrypt(ctx, ks, m, v, 600 + i)
+            y = H.he_spmv(ctx, ks, m, x)
+            H.decrypt(ctx, ks, m, y, out)
+            return m, x, y
+
+        step(0)
+        torch.cuda.synchronize()
+        if not torch.equal(out, want):
+            raise RuntimeError("laplace256 " + label + ": decrypted result differs from the integer SpMV")
+        torch.cuda.synchronize(); t0 = time.perf_counter()
+        for i in range(reps):
+            step(1 + i)
+        torch.cuda.synchronize()
+        step_ms = (time.perf_counter() - t0) * 1e3 / reps
+        m = H.Matrix(ctx, w["R"], w["C"], rp, col, val, True, ks, 9)
+        x = H.encrypt(ctx, ks, m, v, 9)
+        torch.cuda.synchronize(); t0 = time.perf_counter()
+        for i in range(reps):
+            H.he_spmv(ctx, ks, m, x)
+        torch.cuda.synchronize()
+        r[label] = {"step_ms": round(step_ms, 2), "spmv_ms": round((time.perf_counter() - t0) * 1e3 / reps, 2),
+                    "chunk_ciphertexts": m.info()[1], "result_ciphertexts": m.groups()}
+        del m, x
+        ks.close()
+        ctx.close()
     return r
 
 

@@ -74,6 +74,11 @@ typedef struct hs_params {
                              rows (a rotation turns each slot row on its own); half the chunks,
                              products and rotations for matrices of two or more partitions, one
                              result ciphertext per pair.  Decrypted results are the same. */
+  uint32_t relin_mode; /* matrices with encrypted values: 0 = relinearise after every ct x ct product
+                            (the paper's placement); 1 = lazy: a one-column chunk (no totalSum
+                            rotation) keeps its unrelinearised product (d0, d1, d2), which is masked
+                            and summed component by component, and each result ciphertext is
+                            relinearised once.  Decrypted results are the same; limbs differ. */
 } hs_params;
 
 typedef struct hs_ctx hs_ctx;

@@ -37,7 +37,8 @@ def lib():
         build()
         L = ctypes.CDLL(_SO)
         sig = {
-            "orc_ctx_new": (vp, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int]),
+            "orc_ctx_new": (vp, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
+                                 ctypes.c_int]),
             "orc_ctx_free": (None, [vp]),
             "orc_n_moduli": (ctypes.c_int, [vp]),
             "orc_n_aux": (ctypes.c_int, [vp]),
@@ -158,10 +159,10 @@ def chunks(CP, s, uniform=False):
 class Context:
     """Scheme parameters + keys (single key-set)."""
 
-    def __init__(self, logn, L, qbits, K, pbits=None, t=65537, agg_mode=0, slot_rows=1):
+    def __init__(self, logn, L, qbits, K, pbits=None, t=65537, agg_mode=0, slot_rows=1, lazy_relin=0):
         self.logn, self.N, self.L, self.K, self.t = logn, 1 << logn, L, K, t
-        self.slot_rows = slot_rows
-        self.h = lib().orc_ctx_new(logn, L, qbits, K, pbits or qbits, t, agg_mode, slot_rows)
+        self.slot_rows, self.lazy_relin = slot_rows, lazy_relin
+        self.h = lib().orc_ctx_new(logn, L, qbits, K, pbits or qbits, t, agg_mode, slot_rows, int(lazy_relin))
         if not self.h:
             raise ValueError("oracle: unsupported parameters")
         self.agg_mode = agg_mode

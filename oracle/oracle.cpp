@@ -383,6 +383,8 @@ struct Ctx {
   int logn = 0; u64 N = 0; u64 t = 0;
   int L = 0, K = 0, alpha = 0, dnum = 0, qbits = 0, pbits = 0, agg_mode = 0;
   int slot_rows = 1;             /* 1: data in slot row 0 only; 2: two row partitions per ciphertext */
+  int lazy_relin = 0;            /* 1: chunks without totalSum rotations keep (d0, d1, d2) until the
+                                    inter-chunk sum, relinearised once per result ciphertext */
   int n_aux = 0;                 /* extra primes for the exact ct x ct tensor */
   std::vector<u64> mod;          /* [L data primes][K special primes][n_aux tensor primes] */
   std::vector<NttTable> tab;
@@ -441,11 +443,13 @@ std::vector<u64> ntt_of_int(const Ctx& c, const std::vector<i64>& a, int m) {
   return r;
 }
 
-bool ctx_init(Ctx& c, int logn, int L, int qbits, int K, int pbits, u64 t, int agg_mode, int slot_rows = 1) {
+bool ctx_init(Ctx& c, int logn, int L, int qbits, int K, int pbits, u64 t, int agg_mode, int slot_rows = 1, int lazy_relin = 0) {
   c.logn = logn; c.N = 1ULL << logn; c.t = t; c.L = L; c.K = K; c.qbits = qbits; c.pbits = pbits;
   c.agg_mode = agg_mode;
   if (slot_rows != 1 && slot_rows != 2) return false;
   c.slot_rows = slot_rows;
+  if (lazy_relin != 0 && lazy_relin != 1) return false;
+  c.lazy_relin = lazy_relin;
   c.alpha = K; c.dnum = (L + K - 1) / K;
   if (t % (2 * c.N) != 1 || !is_prime(t)) return false;
   /* Prime choice: the primes q = 1 mod 2N below 2^b in decreasing order; the first K are the
@@ -847,12 +851,12 @@ void add_step_key(Ctx& c, u64 k) {
   c.gk_step[k] = make_ksk(c, sg, step_key_id(k));
 }
 
-/* HE-Mult (both operands encrypted): the exact scaled tensor
+/* HE-Mult (both operands encrypted), before relinearisation: the exact scaled tensor
      (d0, d1, d2) = round(t/Q * (c0 e0, c0 e1 + c1 e0, c1 e1)) mod Q
    of the centered lifts, computed through the exact integer negacyclic products (CRT over the
-   data, special and tensor primes, whose product exceeds 4 N Q^2), followed by relinearisation
-   of d2 with the relinearisation key (a key switch for s^2). */
-std::vector<u64> ct_mul_ct(const Ctx& c, const std::vector<u64>& x, const std::vector<u64>& y) {
+   data, special and tensor primes, whose product exceeds 4 N Q^2).  Returns [3][L][N], NTT form;
+   it decrypts under (1, s, s^2). */
+std::vector<u64> ct_tensor(const Ctx& c, const std::vector<u64>& x, const std::vector<u64>& y) {
   u64 N = c.N; int L = c.L, T = (int)c.mod.size();
   Big halfQ; { Big a, b; bdivmod(c.Q, bfrom(2), a, b); halfQ = a; }
   /* centered lifts of the four input polynomials, coefficient form, reduced to every modulus */
@@ -908,16 +912,29 @@ std::vector<u64> ct_mul_ct(const Ctx& c, const std::vector<u64>& x, const std::v
     }
     for (int i = 0; i < L; i++) c.tab[i].forward(d[w].data() + (u64)i * N);
   }
+  std::vector<u64> r(3ULL * L * N);
+  for (int w = 0; w < 3; w++) memcpy(r.data() + (u64)w * L * N, d[w].data(), (u64)L * N * 8);
+  return r;
+}
+/* Relinearisation of (d0, d1, d2): (d0, d1) + KeySwitch(d2) under the relinearisation key (a key
+   switch for s^2 -> s), so the result decrypts under (1, s) to the same plaintext. */
+std::vector<u64> relinearize(const Ctx& c, const std::vector<u64>& d3) {
+  u64 N = c.N, LN = (u64)c.L * N;
+  std::vector<u64> d2(d3.begin() + 2 * LN, d3.end());
   std::vector<u64> k0, k1;
-  keyswitch(c, d[2], c.rk, k0, k1);
-  std::vector<u64> r(2ULL * L * N);
-  for (int i = 0; i < L; i++)
+  keyswitch(c, d2, c.rk, k0, k1);
+  std::vector<u64> r(2 * LN);
+  for (int i = 0; i < c.L; i++)
     for (u64 k = 0; k < N; k++) {
       u64 o = (u64)i * N + k;
-      r[o] = addmod(d[0][o], k0[o], c.mod[i]);
-      r[(u64)L * N + o] = addmod(d[1][o], k1[o], c.mod[i]);
+      r[o] = addmod(d3[o], k0[o], c.mod[i]);
+      r[LN + o] = addmod(d3[LN + o], k1[o], c.mod[i]);
     }
   return r;
+}
+/* HE-Mult with relinearisation immediately after the product. */
+std::vector<u64> ct_mul_ct(const Ctx& c, const std::vector<u64>& x, const std::vector<u64>& y) {
+  return relinearize(c, ct_tensor(c, x, y));
 }
 
 /* ------------------------------------------------------------------ CSSC (Sec. 4.3, App. B) */
@@ -1051,9 +1068,9 @@ struct Matrix {
 /* ====================================================================== C API (for tests) */
 extern "C" {
 
-void* orc_ctx_new(int logn, int L, int qbits, int K, int pbits, u64 t, int agg_mode, int slot_rows) {
+void* orc_ctx_new(int logn, int L, int qbits, int K, int pbits, u64 t, int agg_mode, int slot_rows, int lazy_relin) {
   Ctx* c = new Ctx();
-  if (!ctx_init(*c, logn, L, qbits, K, pbits, t, agg_mode, slot_rows)) { delete c; return nullptr; }
+  if (!ctx_init(*c, logn, L, qbits, K, pbits, t, agg_mode, slot_rows, lazy_relin)) { delete c; return nullptr; }
   return c;
 }
 void orc_ctx_free(void* h) { delete (Ctx*)h; }
@@ -1256,20 +1273,40 @@ void orc_encrypt_vector(void* h, void* m, const i64* v, u64 seed, u64* out) {
 
 /* Cloud: per chunk HE product, totalSum, mask (paper mode), sum per group (partition, or pair of
    partitions with two slot rows).  x: [n_chunks][2][L][N]; out: [n_groups][2][L][N].  stats
-   (optional): [key switches, rotations]. */
+   (optional): [key switches, rotations].
+   Lazy relinearisation (encrypted matrix values, lazy_relin = 1; not in the paper, which
+   relinearises after every product): a chunk of one column has no totalSum rotation, so its
+   unrelinearised product (d0, d1, d2) is masked component by component and summed with the
+   group's other such chunks; the sum is relinearised once and added to the group's result.
+   The mask product and the sum are linear in each component, so the result decrypts to the
+   same plaintext; only its limbs (noise) differ. */
 void orc_he_spmv(void* h, void* m, const u64* x, u64* out, i64* stats) {
-  Ctx* c = (Ctx*)h; Matrix* M = (Matrix*)m; u64 ctsz = 2ULL * c->L * c->N;
+  Ctx* c = (Ctx*)h; Matrix* M = (Matrix*)m; u64 ctsz = 2ULL * c->L * c->N, LN = (u64)c->L * c->N;
   int g = 0, nks = 0, nrot = 0;
   for (size_t p = 0; p < M->groups.size(); p++) {
-    std::vector<u64> res(ctsz, 0);
+    std::vector<u64> res(ctsz, 0), lazy;
     for (const Chunk& ch : M->groups[p].chunks) {
       std::vector<u64> xv(x + (u64)g * ctsz, x + (u64)(g + 1) * ctsz);
+      if (M->encrypted && c->lazy_relin && ch.c == 1) {
+        std::vector<u64> d3 = ct_tensor(*c, M->pts[g], xv);
+        if (lazy.empty()) lazy.assign(3 * LN, 0);
+        for (int w = 0; w < 3; w++)
+          for (int i = 0; i < c->L; i++)
+            for (u64 k = 0; k < c->N; k++) {
+              u64 o = (u64)w * LN + (u64)i * c->N + k, q = c->mod[i];
+              u64 v = c->agg_mode == 0 ? mulmod(d3[o], M->masks[g][(u64)i * c->N + k], q) : d3[o];
+              lazy[o] = addmod(lazy[o], v, q);
+            }
+        g++;
+        continue;
+      }
       std::vector<u64> prod = M->encrypted ? ct_mul_ct(*c, M->pts[g], xv) : ct_mul_plain(*c, xv, M->pts[g]);
       std::vector<u64> w = total_sum(*c, prod, ch.h, ch.c, &nks, &nrot);
       if (c->agg_mode == 0) w = ct_mul_plain(*c, w, M->masks[g]);
       ct_add(*c, res, w);
       g++;
     }
+    if (!lazy.empty()) ct_add(*c, res, relinearize(*c, lazy));
     memcpy(out + p * ctsz, res.data(), ctsz * 8);
   }
   if (stats) { stats[0] = nks; stats[1] = nrot; }

@@ -417,9 +417,10 @@ static bool use_split(const hs_ctx* c) { return !lds_limb_fits(c) || g_opt_aux.l
 static bool use_split_client(const hs_ctx* c) { return use_split(c) || (c->logn >= 14 && g_opt_aux.load() == 0); }
 
 // Exact ciphertext products a_i x b_i (NTT form [2][L][N] each) with relinearisation: n items,
-// keys[i] = the relinearisation key of item i.
+// keys[i] = the relinearisation key of item i.  With lazy[i] set, item i is not relinearised: its
+// scaled tensor goes to lazy[i] as [4][L][N] = (d0, d2, 0, d1) (out[i] is not written).
 static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const* b, u64* const* out, const u64* const* rkeys,
-                         hipStream_t st) {
+                         hipStream_t st, u64* const* lazy = nullptr) {
   if (n <= 0) return;
   HS_REQUIRE(c->has_tensor, HS_EPARAM, "parameters too large for the exact ciphertext product");
   const size_t N = c->N;
@@ -448,6 +449,10 @@ static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const
   ntt_any(c, D4.as<u64>(), (i64)n * 4 * L, L, 0, 0, st, hold);
   std::vector<std::vector<RotItem>> lv(1);
   for (int i = 0; i < n; i++) {
+    if (lazy && lazy[i]) {
+      HS_CHECK_HIP(hipMemcpyAsync(lazy[i], D4.as<u64>() + (size_t)i * 4 * LN, 4 * LN * sizeof(u64), hipMemcpyDeviceToDevice, st));
+      continue;
+    }
     RotItem it{};
     it.in = D4.as<u64>() + (size_t)i * 4 * LN;            // (d0, d2)
     it.addend = D4.as<u64>() + (size_t)i * 4 * LN + 2 * LN;  // (0, d1)
@@ -457,7 +462,18 @@ static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const
     lv[0].push_back(it);
   }
   run_rotation_levels(c, lv, st);
-  g_counters[0] -= n;  // relinearisations are not rotations; counted separately below
+  g_counters[0] -= (int64_t)lv[0].size();  // relinearisations are not rotations
+}
+
+// Lazy relinearisation (hs_params.relin_mode = 1; matrices with encrypted values): a one-column
+// chunk has no totalSum rotation, so its product stays unrelinearised, (d0, d2 | 0, d1) in the
+// [4][L][N] layout above.  Per result ciphertext (group) two masked sums are formed over its
+// chunks: LA = (sum m d0, sum m d2) over the one-column chunks (a zero ciphertext stands for the
+// others) and Y2 = sum m (result) over the other chunks + (0, sum m d1) over the one-column ones;
+// the group's result is LA's first component + KeySwitch(LA's second) + Y2, one key switch per
+// group instead of one per chunk.  A group without one-column chunks takes Y2 as it is.
+static bool lazy_chunk(const hs_ctx* c, const hs_matrix* m, int g) {
+  return m->encrypted && c->prm.relin_mode == 1 && m->chunks[g].c == 1;
 }
 
 // Pack + encode G chunks (mode 0 matrix values, 1 vector, 2 mask) into mod-t coefficients.
@@ -1009,8 +1025,10 @@ struct BatchWork {
   struct Mask { const u64* const* wp; const u64* mask; const int* pc0; const int* pnc; u64* y; int nP; };
   std::vector<Prod> prods;
   std::vector<const u64*> pa, pb, rk;   // exact ct x ct products (encrypted matrices)
-  std::vector<u64*> po;
+  std::vector<u64*> po, lz;             // lz: destination of an unrelinearised product, or null
   LevelPlan levels;
+  LevelPlan relin;                      // lazy relinearisation: one key switch per group
+  std::vector<std::pair<u64*, const u64*>> copies;  // lazy mode, groups without one-column chunks
   std::vector<Mask> masks;
   std::vector<DBuf> keep;
   int64_t counters[5] = {0, 0, 0, 0, 0};
@@ -1025,6 +1043,9 @@ struct BatchWork {
       int nwt = 0;
       u64* vbuf = nullptr;
       u64* wtbuf = nullptr;
+      std::vector<int> lidx;   // lazy relinearisation: slot of a one-column chunk's product, or -1
+      int nlazy = 0;
+      u64* d4 = nullptr;       // [nlazy][4][L][N]
     };
     std::vector<Req> rq(n);
     int nlog = 0;
@@ -1045,6 +1066,13 @@ struct BatchWork {
       q.vbuf = keep.back().as<u64>();
       keep.emplace_back(&c->pool, (size_t)std::max(q.nwt, 1) * CW * sizeof(u64));
       q.wtbuf = keep.back().as<u64>();
+      q.lidx.assign(q.G, -1);
+      for (int g = 0; g < q.G; g++)
+        if (lazy_chunk(c, m[r], g)) q.lidx[g] = q.nlazy++;
+      if (q.nlazy) {
+        keep.emplace_back(&c->pool, (size_t)q.nlazy * 2 * CW * sizeof(u64));
+        q.d4 = keep.back().as<u64>();
+      }
     }
     auto buf = [&](int r, int g, int id) -> u64* {
       Req& q = rq[r];
@@ -1059,6 +1087,7 @@ struct BatchWork {
           pb.push_back(x[r]->d + (size_t)g * CW);
           po.push_back(rq[r].vbuf + (size_t)g * CW);
           rk.push_back(ks[r]->rk);
+          lz.push_back(rq[r].lidx[g] >= 0 ? rq[r].d4 + (size_t)rq[r].lidx[g] * 2 * CW : nullptr);
         }
       } else {
         prods.push_back(Prod{x[r]->d, m[r]->d_pt, rq[r].vbuf, rq[r].G});
@@ -1092,19 +1121,39 @@ struct BatchWork {
     // 3. masks and the per-partition sums; the argument arrays of every request in one upload:
     //    per request [chunk result pointers (G, at least 1)][first chunk per partition][chunks
     //    per partition], 8-byte words
+    //    (lazy relinearisation: the chunk pointers give Y2's operands, and a second pointer
+    //    array after the partition words gives LA's)
     std::vector<u64> words;
-    std::vector<size_t> at(n, 0);
+    std::vector<size_t> at(n, 0), at2(n, 0);
+    bool any_lazy = false;
+    for (auto& q : rq) any_lazy |= q.nlazy > 0;
+    u64* zero = nullptr;
+    if (any_lazy) {
+      keep.emplace_back(&c->pool, CW * sizeof(u64));
+      zero = keep.back().as<u64>();
+      HS_CHECK_HIP(hipMemsetAsync(zero, 0, CW * sizeof(u64), st));
+    }
     for (int r = 0; r < n; r++) {
       Req& q = rq[r];
       at[r] = words.size();
       if (!q.nP) continue;
-      for (int g = 0; g < std::max(q.G, 1); g++) words.push_back(g < q.G ? (u64)(uintptr_t)buf(r, g, q.progs[g].back().in) : 0);
+      for (int g = 0; g < std::max(q.G, 1); g++) {
+        const u64* src = g >= q.G ? nullptr
+                         : q.lidx[g] >= 0 ? q.d4 + (size_t)q.lidx[g] * 2 * CW + CW   // (0, d1)
+                                          : buf(r, g, q.progs[g].back().in);
+        words.push_back((u64)(uintptr_t)src);
+      }
       std::vector<int> pcn(2 * (size_t)q.nP);
       for (int p = 0; p < q.nP; p++) { pcn[p] = m[r]->groups[p].chunk0; pcn[q.nP + p] = m[r]->groups[p].nchunks; }
       const size_t w0 = words.size();
       words.resize(w0 + (pcn.size() * sizeof(int) + 7) / 8, 0);
       std::memcpy(words.data() + w0, pcn.data(), pcn.size() * sizeof(int));
+      at2[r] = words.size();
+      if (q.nlazy)
+        for (int g = 0; g < q.G; g++)
+          words.push_back((u64)(uintptr_t)(q.lidx[g] >= 0 ? q.d4 + (size_t)q.lidx[g] * 2 * CW : zero));   // (d0, d2)
     }
+    std::vector<RotItem> relin_items;
     if (!words.empty()) {
       keep.emplace_back(&c->pool, words.size() * sizeof(u64));
       u64* dw = keep.back().as<u64>();
@@ -1114,10 +1163,37 @@ struct BatchWork {
         if (!q.nP) continue;
         const u64* const* dwp = (const u64* const*)(dw + at[r]);
         const int* dpc0 = (const int*)(dw + at[r] + std::max(q.G, 1));
-        masks.push_back(Mask{dwp, c->prm.agg_mode == 0 ? m[r]->d_mask : nullptr, dpc0, dpc0 + q.nP, y[r]->d, q.nP});
-        counters[2]++;
+        const u64* mask = c->prm.agg_mode == 0 ? m[r]->d_mask : nullptr;
         counters[4] += c->prm.agg_mode == 0 ? q.G : 0;
+        if (!q.nlazy) {
+          masks.push_back(Mask{dwp, mask, dpc0, dpc0 + q.nP, y[r]->d, q.nP});
+          counters[2]++;
+          continue;
+        }
+        keep.emplace_back(&c->pool, (size_t)q.nP * 2 * CW * sizeof(u64));
+        u64* LA = keep.back().as<u64>();
+        u64* Y2 = LA + (size_t)q.nP * CW;
+        masks.push_back(Mask{dwp, mask, dpc0, dpc0 + q.nP, Y2, q.nP});
+        masks.push_back(Mask{(const u64* const*)(dw + at2[r]), mask, dpc0, dpc0 + q.nP, LA, q.nP});
+        counters[2] += 2;
+        for (int p = 0; p < q.nP; p++) {
+          const hs_group& Gr = m[r]->groups[p];
+          bool has = false;
+          for (int g = Gr.chunk0; g < Gr.chunk0 + Gr.nchunks; g++) has |= q.lidx[g] >= 0;
+          if (!has) { copies.emplace_back(y[r]->d + (size_t)p * CW, Y2 + (size_t)p * CW); continue; }
+          RotItem it{};
+          it.in = LA + (size_t)p * CW;
+          it.addend = Y2 + (size_t)p * CW;
+          it.out = y[r]->d + (size_t)p * CW;
+          it.key = ks[r]->rk;
+          it.galois = 1;
+          relin_items.push_back(it);
+        }
       }
+    }
+    if (!relin_items.empty()) {
+      prepare_levels(c, {relin_items}, st, relin);
+      counters[2] += relin.launches;
     }
   }
 
@@ -1125,9 +1201,12 @@ struct BatchWork {
 
   void enqueue(hs_ctx* c, hipStream_t st) const {
     for (const Prod& p : prods) launch_mul_plain(c, p.x, p.pt, p.out, p.G, c->L, st);
-    if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), st);
+    if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), st, lz.data());
     enqueue_levels(c, levels, st);
     for (const Mask& k : masks) launch_mask_acc(c, k.wp, k.mask, k.pc0, k.pnc, k.y, k.nP, st);
+    enqueue_levels(c, relin, st);
+    for (const auto& cp : copies)
+      HS_CHECK_HIP(hipMemcpyAsync(cp.first, cp.second, ct_words(c) * sizeof(u64), hipMemcpyDeviceToDevice, st));
   }
 };
 
@@ -1980,6 +2059,8 @@ struct SrvReq {
   std::vector<size_t> pc;
   std::vector<int> wt_base;
   DBuf vbuf, wtbuf;
+  std::vector<int> lidx;  // lazy relinearisation: slot of a one-column chunk's product, or -1
+  DBuf d4;                // those products, [4][L][N] each
   size_t footprint = 0;
   double t_submit = 0, t_admit = 0, t_done = 0;
   int status = 0;  // 0 queued, 1 active, 2 done, <0 error code
@@ -2012,7 +2093,10 @@ static size_t request_footprint(const hs_ctx* c, const hs_matrix* m, int* nwt_ou
   for (const hs_chunk& ch : m->chunks)
     if (ch.c > 1) nwt += 4;
   if (nwt_out) *nwt_out = nwt;
-  return ((size_t)m->chunks.size() + nwt + m->groups.size()) * CW;
+  size_t lazy = 0;  // unrelinearised products (two ciphertexts' worth each) and LA, Y2 per group
+  for (int g = 0; g < (int)m->chunks.size(); g++) lazy += lazy_chunk(c, m, g) ? 2 : 0;
+  if (lazy) lazy += 2 * m->groups.size();
+  return ((size_t)m->chunks.size() + nwt + m->groups.size() + lazy) * CW;
 }
 
 static void server_tick(hs_server* S) {
@@ -2036,7 +2120,7 @@ static void server_tick(hs_server* S) {
   }
   // set up and launch the products of the newly admitted requests
   std::vector<const u64*> pa, pb, rk;
-  std::vector<u64*> po;
+  std::vector<u64*> po, lz;
   for (auto& r : fresh) {
     const hs_matrix* m = r->m;
     const int G = (int)m->chunks.size();
@@ -2054,17 +2138,23 @@ static void server_tick(hs_server* S) {
     if (!G) continue;
     if (m->ready) HS_CHECK_HIP(hipStreamWaitEvent(S->st, m->ready, 0));
     if (m->encrypted) {
+      r->lidx.assign(G, -1);
+      int nl = 0;
+      for (int g = 0; g < G; g++)
+        if (lazy_chunk(c, m, g)) r->lidx[g] = nl++;
+      if (nl) r->d4 = DBuf(&c->pool, (size_t)nl * 2 * CW * sizeof(u64));
       for (int g = 0; g < G; g++) {
         pa.push_back(m->d_pt + (size_t)g * CW);
         pb.push_back(r->x->d + (size_t)g * CW);
         po.push_back(r->vbuf.as<u64>() + (size_t)g * CW);
         rk.push_back(r->ks->rk);
+        lz.push_back(r->lidx[g] >= 0 ? r->d4.as<u64>() + (size_t)r->lidx[g] * 2 * CW : nullptr);
       }
     } else {
       launch_mul_plain(c, r->x->d, m->d_pt, r->vbuf.as<u64>(), G, c->L, S->st);
     }
   }
-  if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), S->st);
+  if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), S->st, lz.data());
   // rotation levels across every active request: one when requests wait for admission, else as
   // many as every active request still has (at most 4), enqueued without host waits in between, so
   // no request finishes in the middle of a tick and admission stays responsive
@@ -2106,6 +2196,9 @@ static void server_tick(hs_server* S) {
   // retire finished requests
   std::vector<std::shared_ptr<SrvReq>> done;
   std::vector<DBuf> keep;
+  std::vector<RotItem> relin_items;  // lazy relinearisation (see BatchWork): one per group
+  std::vector<std::pair<u64*, const u64*>> copies;
+  u64* zero = nullptr;
   for (auto& r : S->active) {
     bool fin = true;
     for (size_t g = 0; g < r->progs.size(); g++) fin &= (r->pc[g] + 1 >= r->progs[g].size());
@@ -2113,29 +2206,70 @@ static void server_tick(hs_server* S) {
     const hs_matrix* m = r->m;
     const int G = (int)m->chunks.size(), nP = (int)m->groups.size();
     if (nP) {
-      std::vector<const u64*> wp(std::max(G, 1), nullptr);
-      for (int g = 0; g < G; g++) wp[g] = buf(r.get(), g, r->progs[g].back().in);
+      const bool lazy = r->d4.p != nullptr;
+      auto lz_at = [&](int g) { return r->d4.as<u64>() + (size_t)r->lidx[g] * 2 * CW; };
+      if (lazy && !zero) {
+        keep.emplace_back(&c->pool, CW * sizeof(u64));
+        zero = keep.back().as<u64>();
+        HS_CHECK_HIP(hipMemsetAsync(zero, 0, CW * sizeof(u64), S->st));
+      }
+      std::vector<const u64*> wp(std::max(G, 1), nullptr), wa(std::max(G, 1), nullptr);
+      for (int g = 0; g < G; g++) {
+        const bool lg = lazy && r->lidx[g] >= 0;
+        wp[g] = lg ? lz_at(g) + CW : buf(r.get(), g, r->progs[g].back().in);
+        wa[g] = lg ? lz_at(g) : zero;
+      }
       std::vector<int> pc0(nP), pnc(nP);
       for (int p = 0; p < nP; p++) { pc0[p] = m->groups[p].chunk0; pnc[p] = m->groups[p].nchunks; }
-      keep.emplace_back(&c->pool, wp.size() * sizeof(u64*));
+      keep.emplace_back(&c->pool, 2 * wp.size() * sizeof(u64*));
       const u64* const* dw = keep.back().as<const u64*>();
       h2d(keep.back().as<const u64*>(), wp.data(), wp.size(), S->st);
+      h2d(keep.back().as<const u64*>() + wp.size(), wa.data(), wa.size(), S->st);
       keep.emplace_back(&c->pool, nP * sizeof(int));
       int* dpc0 = keep.back().as<int>();
       h2d(dpc0, pc0.data(), nP, S->st);
       keep.emplace_back(&c->pool, nP * sizeof(int));
       int* dpnc = keep.back().as<int>();
       h2d(dpnc, pnc.data(), nP, S->st);
-      launch_mask_acc(c, dw, c->prm.agg_mode == 0 ? m->d_mask : nullptr, dpc0, dpnc, r->y->d, nP, S->st);
+      const u64* mask = c->prm.agg_mode == 0 ? m->d_mask : nullptr;
+      if (!lazy) {
+        launch_mask_acc(c, dw, mask, dpc0, dpnc, r->y->d, nP, S->st);
+      } else {
+        keep.emplace_back(&c->pool, (size_t)nP * 2 * CW * sizeof(u64));
+        u64* LA = keep.back().as<u64>();
+        u64* Y2 = LA + (size_t)nP * CW;
+        launch_mask_acc(c, dw, mask, dpc0, dpnc, Y2, nP, S->st);
+        launch_mask_acc(c, dw + wp.size(), mask, dpc0, dpnc, LA, nP, S->st);
+        for (int p = 0; p < nP; p++) {
+          const hs_group& Gr = m->groups[p];
+          bool has = false;
+          for (int g = Gr.chunk0; g < Gr.chunk0 + Gr.nchunks; g++) has |= r->lidx[g] >= 0;
+          if (!has) { copies.emplace_back(r->y->d + (size_t)p * CW, Y2 + (size_t)p * CW); continue; }
+          RotItem it{};
+          it.in = LA + (size_t)p * CW;
+          it.addend = Y2 + (size_t)p * CW;
+          it.out = r->y->d + (size_t)p * CW;
+          it.key = r->ks->rk;
+          it.galois = 1;
+          relin_items.push_back(it);
+        }
+      }
     }
     done.push_back(r);
   }
+  if (!relin_items.empty()) {
+    run_rotation_levels(c, {relin_items}, S->st);
+    g_counters[0] -= (int64_t)relin_items.size();   // relinearisations are not rotations
+  }
+  for (const auto& cp : copies)
+    HS_CHECK_HIP(hipMemcpyAsync(cp.first, cp.second, CW * sizeof(u64), hipMemcpyDeviceToDevice, S->st));
   HS_CHECK_HIP(hipStreamSynchronize(S->st));
   const double t = S->now();
   std::lock_guard<std::mutex> lk(S->mu);
   for (auto& r : done) {
     r->vbuf.reset();
     r->wtbuf.reset();
+    r->d4.reset();
     r->t_done = t;
     r->status = 2;
     S->used -= r->footprint;

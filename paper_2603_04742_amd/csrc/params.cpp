@@ -198,6 +198,7 @@ void build_ctx(hs_ctx* c) {
              "t must be a prime < 2^50 with t = 1 mod 2N");
   HS_REQUIRE(p.agg_mode <= 1, HS_EPARAM, "agg_mode must be 0 or 1");
   HS_REQUIRE(p.slot_rows <= 2, HS_EPARAM, "slot_rows must be 0, 1 or 2");
+  HS_REQUIRE(p.relin_mode <= 1, HS_EPARAM, "relin_mode must be 0 or 1");
   c->L = (int)p.n_q;
   c->K = (int)p.n_p;
   c->alpha = c->K;

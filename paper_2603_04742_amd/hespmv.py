@@ -26,7 +26,8 @@ class HespmvError(RuntimeError):
 class Params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("q_bits", ctypes.c_uint32),
                 ("n_p", ctypes.c_uint32), ("p_bits", ctypes.c_uint32), ("t", ctypes.c_uint64),
-                ("sigma", ctypes.c_double), ("agg_mode", ctypes.c_uint32), ("slot_rows", ctypes.c_uint32)]
+                ("sigma", ctypes.c_double), ("agg_mode", ctypes.c_uint32), ("slot_rows", ctypes.c_uint32),
+                ("relin_mode", ctypes.c_uint32)]
 
 
 _vp = ctypes.c_void_p
@@ -134,8 +135,8 @@ def _np(a, dt, ptr):
 class Context:
     """hs_ctx: parameter set, primes, tables."""
 
-    def __init__(self, log_n, n_q, q_bits, n_p, t=65537, agg_mode=0, sigma=3.2, slot_rows=1):
-        self.params = Params(log_n, n_q, q_bits, n_p, q_bits, t, sigma, agg_mode, slot_rows)
+    def __init__(self, log_n, n_q, q_bits, n_p, t=65537, agg_mode=0, sigma=3.2, slot_rows=1, lazy_relin=0):
+        self.params = Params(log_n, n_q, q_bits, n_p, q_bits, t, sigma, agg_mode, slot_rows, int(lazy_relin))
         h = ctypes.c_void_p()
         _check(lib.hs_ctx_create(ctypes.byref(self.params), ctypes.byref(h)))
         self.h = h

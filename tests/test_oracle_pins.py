@@ -5,6 +5,7 @@ Each test checks the oracle against something other than itself: values printed 
 big integers, brute force on tiny inputs, and invariants.  A plausible slip in the oracle (a
 dropped term, a wrong sign or index, a transposed operand) fails at least one of them.
 """
+import collections
 import math
 import os
 
@@ -378,6 +379,42 @@ def test_ct_times_ct_with_relinearisation():
     mask[:10] = 1
     pm = c.ct_mul_plain(p, c.plain_ntt(c.encode(mask)))
     assert np.array_equal(c.decode(c.decrypt(pm)), (x * y * mask) % T)
+
+
+@pytest.mark.parametrize("agg", [0, 1])
+@pytest.mark.parametrize("kind", ["laplace", "mixed"])
+def test_lazy_relinearisation_protocol(kind, agg):
+    """Both-encrypted SpMV with lazy relinearisation: the decrypted product is the integer SpMV.
+    A group's limbs equal those of relinearising after every product when it has no one-column
+    chunk, or a single one and no mask (then the same key switch of the same d2 is added); they
+    differ when several one-column products are summed, or masked, before their key switch (the
+    key switch is not linear in the limbs), which shows the lazy sum ran."""
+    eager = O.Context(8, 3, 50, 1, agg_mode=agg)
+    lazy = O.Context(8, 3, 50, 1, agg_mode=agg, lazy_relin=1)
+    eager.keygen(3)
+    lazy.keygen(3)
+    if kind == "laplace":
+        w = W.laplace256(n=10)   # 100 x 100: every chunk one column wide
+        w["v"] = w["v"][:100]
+    else:
+        g = np.random.default_rng(77)
+        rp, col, val = W.uniform_matrix(150, 90, 500, 7, g)   # chunks of one and of several columns
+        w = dict(R=150, C=90, row_ptr=rp, col=col, val=val, v=g.integers(-7, 8, 90))
+    runs = []
+    for c in (eager, lazy):
+        M = O.Matrix(c, w["R"], w["C"], w["row_ptr"], w["col"], w["val"], True, 31)
+        res, stats = M.he_spmv(M.encrypt_vector(w["v"], 41))
+        assert np.array_equal(M.decrypt_result(res), W.spmv_mod_t(w))
+        runs.append((M, res))
+    M = runs[0][0]
+    cs = [M.chunk(k) for k in range(M.n_chunks())]
+    n1 = collections.Counter(k[0] for k in cs if k[2] == 1)
+    if kind == "mixed":
+        assert any(k[2] > 1 for k in cs) and n1
+    ct = lazy.ct_size()
+    for gi in range(M.n_groups()):
+        same = np.array_equal(runs[0][1][gi * ct:(gi + 1) * ct], runs[1][1][gi * ct:(gi + 1) * ct])
+        assert same == (n1[gi] == 0 or (n1[gi] == 1 and agg == 1)), gi
 
 
 def test_ct_times_ct_exact_tensor_definition_tiny():
