@@ -47,12 +47,11 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batched-vs-plain measurement")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving run (Poisson arrivals at 200/s; 10000 for the full stream; 0 skips)")
-    ap.add_argument("--no-diagonal", action="store_true", help="skip the diagonal-method comparison")
-    ap.add_argument("--diagonal-zipf16k", action="store_true",
-                    help="also run the diagonal method on the 16384 x 16384 Zipf workload (tens of GB of plaintexts)")
-    ap.add_argument("--lazy-relin-laplace256", action="store_true",
-                    help="also time the both-encrypted 256 x 256-grid Laplacian (N = 32768) with relinearisation after "
-                         "every product and with lazy relinearisation")
+    ap.add_argument("--no-diagonal", action="store_true",
+                    help="skip the diagonal-method comparison (256 x 256 workload, and the Zipf workload: ~70 GB of HBM)")
+    ap.add_argument("--no-laplace256", action="store_true",
+                    help="skip the both-encrypted 256 x 256-grid Laplacian (N = 32768) with relinearisation after every "
+                         "product and with lazy relinearisation")
     ap.add_argument("--profile-only", action="store_true", help="run warmup + steps only (for rocprofv3)")
     ap.add_argument("--profile-ntt", action="store_true",
                     help="with --profile-only: also run the standalone NTT measurement (256 MiB of limbs, 5 launches)")
@@ -221,10 +220,9 @@ def main():
                                                              "two slot rows + exact-step keys")
     ctx2.close()
     if not args.no_diagonal:
-        result["diagonal_baseline"] = {"small": diagonal_baseline(H, W, torch, dev, "small", reps=10)}
-        if args.diagonal_zipf16k:
-            result["diagonal_baseline"]["zipf16k"] = diagonal_baseline(H, W, torch, dev, "zipf16k", reps=2)
-    if args.lazy_relin_laplace256:
+        result["diagonal_baseline"] = {"small": diagonal_baseline(H, W, torch, dev, "small", reps=10),
+                                       "zipf16k": diagonal_baseline(H, W, torch, dev, "zipf16k", reps=2)}
+    if not args.no_laplace256:
         result["lazy_relin_laplace256"] = lazy_relin_laplace256(H, W, torch, dev)
     if args.workload == "zipf16k" and not args.no_batch:
         result["batched_vs_plain"] = batched_vs_plain(H, W, torch, dev)
