@@ -157,9 +157,10 @@ def main():
         for k, dt in zip(stage_ms, (b - a, c - b, d - c, e - d)):
             stage_ms[k] += dt * 1e3 / reps
 
-    ntt_ms, ntt_bytes, ntt_limbs = ntt_bandwidth(H, torch, dev, ctx, logn, L, K)
+    ntt_ms, ntt_bytes, ntt_limbs, ntt_kernel = ntt_bandwidth(H, torch, dev, ctx, logn, L, K)
     N = 1 << logn
     ntt_gbps = ntt_bytes / (ntt_ms * 1e-3) / 1e9
+    copy_gbps = copy_bandwidth(torch, dev)
 
     # roofline of the dominant kernel of the timed steps
     dom, (dcount, dms) = max(prof.items(), key=lambda kv: kv[1][1])
@@ -202,7 +203,9 @@ def main():
         "stage_ms": {k: round(x, 3) for k, x in stage_ms.items()},
         "ops_per_spmv": counters,
         "kernel_ms_per_step": kernel_ms,
-        "ntt": {"GBps": round(ntt_gbps, 1), "hbm_frac": round(ntt_gbps / HBM_PEAK_GBPS, 4), "limbs_per_launch": ntt_limbs,
+        "hbm_copy": {"GBps": round(copy_gbps, 1), "hbm_frac": round(copy_gbps / HBM_PEAK_GBPS, 4),
+                     "what": "device-to-device copy of 1 GiB (read + write), mean of 5 after one warm-up"},
+        "ntt": {"kernel": ntt_kernel, "GBps": round(ntt_gbps, 1), "hbm_frac": round(ntt_gbps / HBM_PEAK_GBPS, 4), "limbs_per_launch": ntt_limbs,
                 "avg_launch_ms": round(ntt_ms, 4), "bytes_per_limb": 16 * N},
         "roofline": roof,
         "keyswitch_unit": keyswitch,
@@ -390,6 +393,22 @@ def diagonal_baseline(H, W, torch, dev, name, reps):
     return r
 
 
+def copy_bandwidth(torch, dev, reps=5):
+    """Achievable HBM bandwidth for context: a 1 GiB device-to-device copy (bytes read + written)."""
+    a = torch.ones(128 << 20, dtype=torch.int64, device=dev)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    return 2 * (128 << 20) * 8 / (ms * 1e-3) / 1e9
+
+
 def ntt_bandwidth(H, torch, dev, ctx, logn, L, K, reps=5):
     """Standalone forward NTT of a 256 MiB batch of (L + K)-limb polynomials (random residues), one
     launch per call; kernel time from the library's HIP events on the launch stream.  Returns
@@ -410,7 +429,8 @@ def ntt_bandwidth(H, torch, dev, ctx, logn, L, K, reps=5):
     torch.cuda.synchronize()
     nprof = H.profile_summary()
     H.profile(False)
-    return nprof["k_ntt"][1] / nprof["k_ntt"][0], 16.0 * N * nl * npoly, nl * npoly
+    name = max((k for k in nprof if k.startswith("k_ntt")), key=lambda k: nprof[k][1])
+    return nprof[name][1] / nprof[name][0], 16.0 * N * nl * npoly, nl * npoly, name
 
 
 def keyswitch_saturated(H, torch, ctx, ks, L, K, N, B=128, reps=5):

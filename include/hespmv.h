@@ -318,12 +318,17 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
    HS_OPT_MODUP_GROUP  two-pass ModUp: targets per workgroup, 0 = automatic (by level size), 1 = one
                        (the digit's inverse pass repeated per target), 2 or 3 = one inverse pass
                        shared by that many targets
+   HS_OPT_NTT_PIPE     forward transforms of many N = 2^14 limbs (hs_ntt, encryption): 0 = automatic
+                       (a persistent grid of two workgroups per CU that reads each workgroup's next
+                       limb while it finishes the current one, used from two limbs per workgroup
+                       on), 1 = one workgroup per limb
    HS_EINVAL for an unknown key or value. */
 #define HS_OPT_KS_PIPELINE 1
 #define HS_OPT_NTT_PATH 2
 #define HS_OPT_KS_THRESHOLD 3
 #define HS_OPT_AUX_PATH 4
 #define HS_OPT_MODUP_GROUP 5
+#define HS_OPT_NTT_PIPE 6
 int hs_set_option(int key, int64_t value);
 
 /* Autotuner.  Times, on synthetic operands and the key-switching key of `ks`, (1) the two variants

@@ -5,7 +5,7 @@
 // oracle at sizes the oracle handles quickly.
 #include "hs_device.hpp"
 #include "kernels.hpp"
-#include "diag.hpp"
+#include "extra.hpp"
 
 namespace hs {
 

@@ -13,7 +13,7 @@
 #include <unordered_map>
 
 #include "kernels.hpp"
-#include "diag.hpp"
+#include "extra.hpp"
 
 namespace hs {
 const char* last_error_cstr();
@@ -1622,6 +1622,10 @@ int hs_set_option(int key, int64_t value) {
       case HS_OPT_NTT_PATH:
         HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "path must be 0, 1 or 2");
         g_opt_ntt = (int)value;
+        break;
+      case HS_OPT_NTT_PIPE:
+        HS_REQUIRE(value == 0 || value == 1, HS_EINVAL, "ntt pipe option must be 0 or 1");
+        set_ntt_pipe(value == 0);
         break;
       case HS_OPT_MODUP_GROUP:
         HS_REQUIRE(value >= 0 && value <= 3, HS_EINVAL, "group must be 0, 1, 2 or 3");

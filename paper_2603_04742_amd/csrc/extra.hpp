@@ -1,4 +1,5 @@
-// Launchers of the diagonal method's packing kernels (defined in aux2.hip).
+// Launchers beside those of kernels.hpp: the diagonal method's packing kernels (aux2.hip) and the
+// switch of the pipelined forward transform (kernels.hip).
 #pragma once
 #include "hs_internal.hpp"
 
@@ -7,4 +8,5 @@ void launch_diag_mark(const i64* row_ptr, const int* col, i64 R, i64 C, i64 B, i
 void launch_diag_place(const hs_ctx* c, const i64* row_ptr, const int* col, const i64* val, i64 R, i64 B, i64 ncb, const i64* ids, int nd,
                        u64* out, hipStream_t st);
 void launch_diag_vector(const hs_ctx* c, const i64* v, i64 C, i64 B, int ncb, u64* out, hipStream_t st);
+void set_ntt_pipe(bool on);
 }  // namespace hs

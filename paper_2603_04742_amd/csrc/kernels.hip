@@ -7,8 +7,10 @@
 // rounds whose first and last rounds read and write global memory directly.
 #include "hs_device.hpp"
 #include "kernels.hpp"
+#include "extra.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <map>
 #include <mutex>
 
@@ -124,6 +126,65 @@ HS_XF_KERNEL k_ntt(u64* data, int nl, int mod0, int inverse, const ModTab* __res
   auto out = [p, m](int i, double x) { p[i] = d2u(canon(x, m)); };
   if (inverse) xf.inv(in, out, smem, t.iv, t.ninv, m);
   else xf.fwd(in, out, smem, t.fw, m);
+}
+
+// Forward transforms of many N = 2^14 limbs, software-pipelined: a grid of two workgroups per CU
+// loops over the limbs (stride = grid size).  The half-limb schedule above holds both halves in
+// registers after the first stage; once the first half has gone to LDS its registers are free, so
+// the first-half words of the workgroup's next limb are read into them while the second half runs
+// its LDS rounds (prefetching both halves would exceed the 128 registers that keep two workgroups
+// on a CU).  The last limb reloads itself: those words are not used.
+__global__ void __launch_bounds__(kSplitNT) __attribute__((amdgpu_waves_per_eu(4)))
+k_ntt_fwd_pipe(u64* data, i64 nlimbs, int nl, int mod0, const ModTab* __restrict__ tab) {
+  SMEM();
+  constexpr int LOGN = kSplitLogn, NT = kSplitNT, H = 1 << (LOGN - 1), EH = H / NT;
+  const int tid = threadIdx.x;
+  const i64 stride = gridDim.x;
+  i64 b = blockIdx.x;
+  if (b >= nlimbs) return;
+  const LdsHalf<LOGN - 1> L{smem};
+  u64 wa[EH], wb[EH];
+#pragma unroll
+  for (int k = 0; k < EH; k++) wa[k] = gld(data + ((size_t)b << LOGN) + tid + k * NT);
+  for (; b < nlimbs; b += stride) {
+    const ModTab t = tab[mod0 + (int)(b % nl)];
+    const ModD m = mod_of(t);
+    const double2* tw = t.fw;
+    u64* p = data + ((size_t)b << LOGN);
+#pragma unroll
+    for (int k = 0; k < EH; k++) wb[k] = gld(p + tid + k * NT + H);
+    auto out = [p, m](int i, double x) { gst(p + i, d2u(canon(x, m))); };
+    double a[EH], c[EH];
+    const double2 w1 = ldtw(tw, 1);
+#pragma unroll
+    for (int k = 0; k < EH; k++) {
+      const double x = u2d(wa[k]), y = u2d(wb[k]);
+      const double tt = mul_tw(y, w1.x, w1.y, m);
+      a[k] = x + tt;
+      c[k] = x - tt;
+    }
+    ct_group<4, 1>(a, 0, tw, m);
+    L.template put<4, 9>(a, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 5, 3, 2>(L, L, tw, m, 0, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 8, 3, 2>(L, L, tw, m, 0, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 11, 3, 2>(L, elem_out(out), tw, m, 0, tid);
+    __syncthreads();
+    ct_group<4, 1>(c, 1, tw, m);
+    L.template put<4, 9>(c, H + tid);
+    const i64 nb = b + stride < nlimbs ? b + stride : b;
+#pragma unroll
+    for (int k = 0; k < EH; k++) wa[k] = gld(data + ((size_t)nb << LOGN) + tid + k * NT);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 5, 3, 2>(L, L, tw, m, 1 << 10, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 8, 3, 2>(L, L, tw, m, 1 << 10, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 11, 3, 2>(L, elem_out(out), tw, m, 1 << 10, tid);
+    __syncthreads();
+  }
 }
 
 // ------------------------------------------------------------------ sampling
@@ -828,8 +889,32 @@ static size_t split_lds_bytes() { return (size_t)split_lds_doubles() * sizeof(do
 
 void upload_cdt(const u64* tab20) { HS_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_cdt), tab20, 20 * sizeof(u64))); }
 
+static std::atomic<bool> g_pipe_ntt{true};
+void set_ntt_pipe(bool on) { g_pipe_ntt = on; }
+
+static int cu_count(int device) {
+  static std::atomic<int> cache[64];
+  if (device < 0 || device >= 64) return 256;
+  int v = cache[device].load();
+  if (!v) {
+    HS_CHECK_HIP(hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device));
+    cache[device] = v;
+  }
+  return v;
+}
+
 void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st) {
   if (nblocks <= 0) return;
+  const i64 grid = 2 * (i64)cu_count(c->device);
+  if (c->logn == kSplitLogn && c->xf_variant_ntt == 0 && !inverse && nblocks >= 2 * grid && g_pipe_ntt.load()) {
+    // enough limbs for every workgroup of the grid to loop over at least two
+    ProfScope _prof("k_ntt_fwd_pipe", st);
+    ensure_lds((const void*)k_ntt_fwd_pipe, split_lds_bytes());
+    hipLaunchKernelGGL(k_ntt_fwd_pipe, dim3((unsigned)grid), dim3(kSplitNT), split_lds_bytes(), st, data, nblocks, nl, mod0,
+                       (const ModTab*)c->d_tab);
+    HS_CHECK_HIP(hipGetLastError());
+    return;
+  }
   HS_DISPATCH_XF(c->xf_variant_ntt, c, k_ntt, dim3((unsigned)nblocks), st, data, nl, mod0, inverse, (const ModTab*)c->d_tab, c->logn);
 }
 
