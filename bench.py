@@ -580,7 +580,7 @@ def serving(H, W, torch, dev, n_requests, rate=200.0, n_keysets=8, pool=16):
     per column).  Matrices come from a pool of `pool` packed matrices whose sizes are the quantiles
     of the stream's sizes (each request takes the nearest); vectors are encrypted beforehand per
     (matrix, key-set) pair (client work, untimed).  Latency = completion - submission on the
-    server clock; the driver submits each request at its arrival time."""
+    server clock; the submitting thread submits each request at its arrival time."""
     import threading
     ctx = H.Context(14, 6, 50, 1, agg_mode=0)
     kss = [ctx.keygen(0x5E7 + k) for k in range(n_keysets)]
@@ -642,7 +642,7 @@ def serving(H, W, torch, dev, n_requests, rate=200.0, n_keysets=8, pool=16):
                         "[1024,32768], Zipf(1.2) 8 nnz/col; %d pooled matrices" % (n_requests, rate, n_keysets, len(mats)),
             "throughput_req_per_s": round(n_requests / span, 2), "p50_ms": round(float(np.percentile(lat_ms, 50)), 3),
             "p99_ms": round(float(np.percentile(lat_ms, 99)), 3), "mean_ms": round(float(lat_ms.mean()), 3),
-            "max_active": st["max_active"], "engine_ticks": st["ticks"], "driver_max_late_ms": round(late * 1e3, 2),
+            "max_active": st["max_active"], "engine_ticks": st["ticks"], "submitter_max_late_ms": round(late * 1e3, 2),
             "decrypt_check": ok}
 
 
