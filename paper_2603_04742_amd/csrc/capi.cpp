@@ -726,7 +726,18 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
     HS_REQUIRE(nnz == 0 || (col_idx && vals), HS_EINVAL, "null col_idx/vals");
     hs_matrix* M = new hs_matrix();
     M->ctx = c; M->R = rows; M->C = cols; M->nnz = nnz; M->encrypted = encrypt_values ? 1 : 0;
+    std::vector<DBuf> keep;  // scratch released only after the final synchronisation
+    keep.reserve(8);         // references into it stay valid
     try {
+      // the column check runs on the device while the host sorts the rows; its flag is read back
+      // with the final synchronisation (no kernel below uses a column index as an address)
+      if (nnz) {
+        keep.emplace_back(&c->pool, 256);
+        int* dbad = keep.back().as<int>();
+        HS_CHECK_HIP(hipMemsetAsync(dbad, 0, sizeof(int), st));
+        launch_csr_check(row_ptr, col_idx, rows, cols, dbad, st);
+        d2h(hbad_p, dbad, 1, st);
+      }
       std::vector<int> rank(std::max<i64>(rows, 1), 0);
       std::vector<i64> part_cp_off, part_nnz_off;
       std::vector<std::vector<i64>> cps;
@@ -799,7 +810,7 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
       const int G = (int)M->chunks.size();
       // one upload of every structure array (pinned staging, one device allocation):
       //   cp | rm | chunk table | partition info (row0, rows, nz rows, rm offset, group, slot
-      //   offset) | rank | cp and nnz offsets per partition | the column-check flag
+      //   offset) | rank | cp and nnz offsets per partition
       std::vector<i64> cd(8ULL * std::max(G, 1), 0);
       for (int g = 0; g < G; g++) {
         const hs_chunk& k = M->chunks[g];
@@ -820,8 +831,7 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
       auto seg = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
       const size_t o_cp = 0, o_rm = o_cp + seg(M->h_cp.size() * 8), o_ch = o_rm + seg(M->h_rm.size() * 4 + 4),
                    o_pi = o_ch + seg(cd.size() * 8), o_rk = o_pi + seg(pinfo.size() * 8), o_po = o_rk + seg(rank.size() * 4),
-                   o_no = o_po + seg(part_cp_off.size() * 8 + 8), o_bad = o_no + seg(part_nnz_off.size() * 8 + 8),
-                   total = o_bad + 256;
+                   o_no = o_po + seg(part_cp_off.size() * 8 + 8), total = o_no + seg(part_nnz_off.size() * 8 + 8);
       char* up = (char*)t_stage_up.get(total);
       auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(up + off, src, bytes); };
       put(o_cp, M->h_cp.data(), M->h_cp.size() * 8);
@@ -831,27 +841,17 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
       put(o_rk, rank.data(), rank.size() * 4);
       put(o_po, part_cp_off.data(), part_cp_off.size() * 8);
       put(o_no, part_nnz_off.data(), part_nnz_off.size() * 8);
-      std::memset(up + o_bad, 0, 256);
       M->d_struct = pmalloc<char>(c, total);
       HS_CHECK_HIP(hipMemcpyAsync(M->d_struct, up, total, hipMemcpyHostToDevice, st));
       M->d_cp = (i64*)(M->d_struct + o_cp);
       M->d_rm = (i32*)(M->d_struct + o_rm);
       M->d_chunk = (i64*)(M->d_struct + o_ch);
       M->d_pinfo = (i64*)(M->d_struct + o_pi);
-      int* dbad = (int*)(M->d_struct + o_bad);
       M->d_va = pmalloc<i64>(c, nnz);
       M->d_ci = pmalloc<i32>(c, nnz);
-      // the column check runs on the device and is read back with the final synchronisation (no
-      // kernel below uses a column index as an address)
-      if (nnz) {
-        launch_csr_check(row_ptr, col_idx, rows, cols, dbad, st);
-        d2h(hbad_p, dbad, 1, st);
-      }
       if (rows && nnz)
         launch_cssc_scatter(row_ptr, col_idx, vals, (const int*)(M->d_struct + o_rk), M->d_cp, (const i64*)(M->d_struct + o_po),
                             (const i64*)(M->d_struct + o_no), rows, s, M->d_va, M->d_ci, st);
-      std::vector<DBuf> keep;  // scratch released only after the final synchronisation
-      keep.reserve(8);         // references into it stay valid
       const int hbad_dummy = 0;
       const int& hbad = nnz ? *hbad_p : hbad_dummy;
       // --- pack + encode (+ encrypt) every chunk; masks
@@ -865,9 +865,12 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         M->d_coef = pmalloc<u64>(c, (size_t)np * N);
         M->d_pt = pmalloc<u64>(c, (size_t)np * c->L * N);
         if (masks) { M->d_mask = M->d_pt + (size_t)G * c->L * N; M->mask_in_pt = true; }
-        HS_CHECK_HIP(hipStreamSynchronize(st));
-        HS_REQUIRE(!hbad, HS_EINVAL, "column indices out of range or not strictly ascending within a row");
+        // the side stream starts once the values are scattered (the event's first record); a
+        // malformed CSR is reported at the final synchronisation below, and whatever the encoding
+        // then reads stays inside M's buffers (its indices come from the host structure)
         HS_CHECK_HIP(hipEventCreateWithFlags(&M->ready, hipEventDisableTiming));
+        HS_CHECK_HIP(hipEventRecord(M->ready, st));
+        HS_CHECK_HIP(hipStreamWaitEvent(c->side, M->ready, 0));
         PackArgs pa{};
         pa.va = M->d_va; pa.ci = M->d_ci; pa.v = nullptr; pa.cp = M->d_cp; pa.chunk = M->d_chunk;
         pa.out = M->d_coef; pa.mode = masks ? 3 : 0; pa.nG = G;
