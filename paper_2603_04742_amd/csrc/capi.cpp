@@ -738,25 +738,27 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         launch_csr_check(row_ptr, col_idx, rows, cols, dbad, st);
         d2h(hbad_p, dbad, 1, st);
       }
-      std::vector<int> rank(std::max<i64>(rows, 1), 0);
+      std::vector<int> rank(std::max<i64>(rows, 1));
       std::vector<i64> part_cp_off, part_nnz_off;
       std::vector<std::vector<i64>> cps;
+      M->h_rm.resize(rows);
+      std::vector<i64> cnt64(std::min<i64>(rows, s));
       for (i64 r0 = 0, p = 0; r0 < rows; r0 += s, p++) {
         hs_part P{};
         P.row0 = r0;
         P.rows = std::min(s, rows - r0);
-        std::vector<i64> cnt(P.rows);
+        i64* cnt = cnt64.data();
         i64 Lw = 0;
         for (i64 i = 0; i < P.rows; i++) { cnt[i] = rp[r0 + i + 1] - rp[r0 + i]; Lw = std::max(Lw, cnt[i]); }
         HS_REQUIRE(Lw <= (1 << 30), HS_ECAPACITY, "row too long");
         P.Lw = (int)Lw;
-        // stable counting sort by descending count
+        // stable counting sort by descending count; the row map goes straight into h_rm
         std::vector<i64> hist(Lw + 2, 0);
         for (i64 i = 0; i < P.rows; i++) hist[cnt[i]]++;
         std::vector<i64> startpos(Lw + 2, 0);
         for (i64 v = Lw - 1, acc = hist[Lw]; v >= 0; v--) { startpos[v] = acc; acc += hist[v]; }
         startpos[Lw] = 0;
-        std::vector<i32> rm(P.rows);
+        i32* rm = M->h_rm.data() + r0;
         for (i64 i = 0; i < P.rows; i++) {
           const i64 pos = startpos[cnt[i]]++;
           rm[pos] = (i32)i;
@@ -771,7 +773,6 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         }
         P.nz_rows = Lw > 0 ? cp[1] : 0;
         P.nnz_off = rp[r0] - rp[0];
-        M->h_rm.insert(M->h_rm.end(), rm.begin(), rm.end());
         cps.push_back(std::move(cp));
         M->parts.push_back(P);
       }
@@ -888,9 +889,7 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
           M->d_pt = pmalloc<u64>(c, (size_t)G * ct_words(c));
           keep.emplace_back(&c->pool, (size_t)G * 3 * N * sizeof(int));
           DBuf& smp = keep.back();
-          launch_sample_small(c, smp.as<int>(), G, 3 * (i64)N, seed, P_ENC_U, 0, 1, 0, st);
-          launch_sample_small(c, smp.as<int>() + N, G, 3 * (i64)N, seed, P_ENC_E0, 0, 1, 1, st);
-          launch_sample_small(c, smp.as<int>() + 2 * N, G, 3 * (i64)N, seed, P_ENC_E1, 0, 1, 1, st);
+          launch_sample_enc(c, smp.as<int>(), G, seed, P_ENC_U, P_ENC_E0, P_ENC_E1, st);
           encrypt_coefs(c, coef.as<u64>(), smp.as<int>(), ks->pk, M->d_pt, G, st, hold);
         } else {
           M->d_pt = pmalloc<u64>(c, (size_t)G * c->L * N);
@@ -1000,9 +999,7 @@ int hs_encrypt(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const int64_t
         pa.out = coef.as<u64>(); pa.mode = 1;
         pack_encode(c, pa, G, st, hold, use_split_client(c));
         DBuf smp(&c->pool, (size_t)G * 3 * N * sizeof(int));
-        launch_sample_small(c, smp.as<int>(), G, 3 * (i64)N, seed, P_ENC_U, 0, 1, 0, st);
-        launch_sample_small(c, smp.as<int>() + N, G, 3 * (i64)N, seed, P_ENC_E0, 0, 1, 1, st);
-        launch_sample_small(c, smp.as<int>() + 2 * N, G, 3 * (i64)N, seed, P_ENC_E1, 0, 1, 1, st);
+        launch_sample_enc(c, smp.as<int>(), G, seed, P_ENC_U, P_ENC_E0, P_ENC_E1, st);
         encrypt_coefs(c, coef.as<u64>(), smp.as<int>(), ks->pk, x->d, G, st, hold);
         HS_CHECK_HIP(hipStreamSynchronize(st));
       }
@@ -1887,9 +1884,7 @@ int hs_diag_encrypt(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const int6
         launch_diag_vector(c, v, D->C, D->B, G, coef.as<u64>(), st);
         ntt_any(c, coef.as<u64>(), G, 1, c->n_mod, 1, st, hold);
         DBuf smp(&c->pool, (size_t)G * 3 * N * sizeof(int));
-        launch_sample_small(c, smp.as<int>(), G, 3 * (i64)N, seed, P_ENC_U, 0, 1, 0, st);
-        launch_sample_small(c, smp.as<int>() + N, G, 3 * (i64)N, seed, P_ENC_E0, 0, 1, 1, st);
-        launch_sample_small(c, smp.as<int>() + 2 * N, G, 3 * (i64)N, seed, P_ENC_E1, 0, 1, 1, st);
+        launch_sample_enc(c, smp.as<int>(), G, seed, P_ENC_U, P_ENC_E0, P_ENC_E1, st);
         encrypt_coefs(c, coef.as<u64>(), smp.as<int>(), ks->pk, x->d, G, st, hold);
         HS_CHECK_HIP(hipStreamSynchronize(st));
       }

@@ -191,7 +191,8 @@ k_ntt_fwd_pipe(u64* data, i64 nlimbs, int nl, int mod0, const ModTab* __restrict
 // Small-integer samples (int32) of nobj polynomials: object o uses stream (seed, purpose,
 // index0 + o * index_step) and is written at out + o * obj_stride.  kind 0: ternary, word i -> (w mod 3) - 1.  kind 1: discrete Gaussian by CDT,
 // 64 bits (words 2i, 2i+1) per coefficient: top bit sign, low 63 bits r, |e| = #{k: T[k] <= r}.
-__global__ void k_sample_small(int* out, int nobj, i64 obj_stride, u64 seed, u32 purpose, u64 index0, u64 index_step, int kind, int logn) {
+__device__ __forceinline__ void sample_small_body(int* out, int nobj, i64 obj_stride, u64 seed, u32 purpose, u64 index0, u64 index_step, int kind,
+                                                  int logn) {
   const int n = 1 << logn;
   const int per = kind == 0 ? 16 : 8;
   const int nblk = n / per;
@@ -215,6 +216,17 @@ __global__ void k_sample_small(int* out, int nobj, i64 obj_stride, u64 seed, u32
       dst[i] = (x >> 63) ? -mag : mag;
     }
   }
+}
+__global__ void k_sample_small(int* out, int nobj, i64 obj_stride, u64 seed, u32 purpose, u64 index0, u64 index_step, int kind, int logn) {
+  sample_small_body(out, nobj, obj_stride, seed, purpose, index0, index_step, kind, logn);
+}
+// The three sample polynomials of public-key encryption in one launch: object o (index o) gets
+// u (ternary, purpose pu) at out[o][0], e0 and e1 (Gaussian, purposes pe0, pe1) at out[o][1..2];
+// blockIdx.y selects the polynomial.
+__global__ void k_sample_enc(int* out, int nobj, u64 seed, u32 pu, u32 pe0, u32 pe1, int logn) {
+  const int job = blockIdx.y;
+  const i64 n = (i64)1 << logn;
+  sample_small_body(out + job * n, nobj, 3 * n, seed, job == 0 ? pu : job == 1 ? pe0 : pe1, 0, 1, job == 0 ? 0 : 1, logn);
 }
 
 // 128-bit little-endian value (w0..w3) mod q, q < 2^50.
@@ -925,6 +937,14 @@ void launch_sample_small(const hs_ctx* c, int* out, int nobj, i64 obj_stride, u6
   const i64 threads = (i64)nobj * (c->N / per);
   ProfScope _prof("k_sample_small", st);
   hipLaunchKernelGGL(k_sample_small, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, out, nobj, obj_stride, seed, purpose, index0, index_step, kind, c->logn);
+  HS_CHECK_HIP(hipGetLastError());
+}
+
+void launch_sample_enc(const hs_ctx* c, int* out, int nobj, u64 seed, u32 pu, u32 pe0, u32 pe1, hipStream_t st) {
+  if (nobj <= 0) return;
+  const i64 threads = (i64)nobj * (c->N / 8);   // the Gaussian polynomials' blocks (the ternary one has half)
+  ProfScope _prof("k_sample_enc", st);
+  hipLaunchKernelGGL(k_sample_enc, dim3((unsigned)((threads + 255) / 256), 3), dim3(256), 0, st, out, nobj, seed, pu, pe0, pe1, c->logn);
   HS_CHECK_HIP(hipGetLastError());
 }
 
