@@ -247,7 +247,9 @@ int hs_decrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ct
    v[bj B + (i + d) mod B] in slot i.  Result block bi = sum over its diagonals of
    diag (.) Rot(x_bj, d); its slots [0, B) hold rows bi B .. bi B + B - 1 of A v mod t. */
 /* Client A: CSR (device row_ptr int64[rows+1], col_idx int32[nnz], vals int64[nnz], columns
-   strictly ascending within a row) -> the diagonal plaintexts.  HS_EINVAL for malformed CSR. */
+   strictly ascending within a row) -> the diagonal plaintexts.  HS_EINVAL for malformed CSR;
+   HS_ECAPACITY when block rows x block columns x B reaches 2^31 (one flag byte per possible
+   diagonal is kept on host and device while packing). */
 int hs_diag_pack(hs_ctx* ctx, int64_t rows, int64_t cols, const int64_t* row_ptr,
                  const int32_t* col_idx, const int64_t* vals, void* stream, hs_diag** out);
 void hs_diag_destroy(hs_diag* d);

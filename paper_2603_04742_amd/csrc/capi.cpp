@@ -1749,7 +1749,7 @@ int hs_diag_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
     D->ncb = (int)((cols + D->B - 1) / D->B);
     try {
       const i64 B = D->B, nids = (i64)D->nrb * D->ncb * B;
-      HS_REQUIRE(nids < (1LL << 33), HS_ECAPACITY, "too many block diagonals for the diagonal method");
+      HS_REQUIRE(nids < (1LL << 31), HS_ECAPACITY, "too many block diagonals for the diagonal method (one flag byte each on host and device)");
       // non-empty diagonals: flagged on the device, listed in ascending id order on the host
       std::vector<i64> ids;
       if (nnz) {
