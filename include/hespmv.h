@@ -324,6 +324,11 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
                        (a persistent grid of two workgroups per CU that reads each workgroup's next
                        limb while it finishes the current one, used from two limbs per workgroup
                        on), 1 = one workgroup per limb
+   HS_OPT_KS_BLOCK     two-pass key switching at N = 2^14, elements per workgroup block: 1 = 2048
+                       (the inner product on 1024), 2 = 1024 throughout, 3 = 512 for the single-pass
+                       kernels and 1024 for ModUp and the key inner product (more, shorter
+                       workgroups for latency-bound small levels), 0 = automatic (3 up to 8 items
+                       per level, else 1)
    HS_EINVAL for an unknown key or value. */
 #define HS_OPT_KS_PIPELINE 1
 #define HS_OPT_NTT_PATH 2
@@ -331,6 +336,7 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
 #define HS_OPT_AUX_PATH 4
 #define HS_OPT_MODUP_GROUP 5
 #define HS_OPT_NTT_PIPE 6
+#define HS_OPT_KS_BLOCK 7
 int hs_set_option(int key, int64_t value);
 
 /* Autotuner.  Times, on synthetic operands and the key-switching key of `ks`, (1) the two variants

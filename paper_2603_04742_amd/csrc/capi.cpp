@@ -1623,6 +1623,10 @@ int hs_set_option(int key, int64_t value) {
         HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "path must be 0, 1 or 2");
         g_opt_ntt = (int)value;
         break;
+      case HS_OPT_KS_BLOCK:
+        HS_REQUIRE(value >= 0 && value <= 3, HS_EINVAL, "key-switch block option must be 0, 1, 2 or 3");
+        set_ks_block((int)value);
+        break;
       case HS_OPT_NTT_PIPE:
         HS_REQUIRE(value == 0 || value == 1, HS_EINVAL, "ntt pipe option must be 0 or 1");
         set_ntt_pipe(value == 0);

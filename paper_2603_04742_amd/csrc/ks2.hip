@@ -16,6 +16,7 @@
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "hs_pass.hpp"
 #include "kernels.hpp"
@@ -649,7 +650,14 @@ static void ensure_lds2(const void* f, size_t bytes) {
 }
 
 template <class GT>
-static int nt2(const GT& G) { return G.BE >= 2048 ? 256 : 64; }
+static int nt2(const GT& G) { return (G.BE >= 2048 || (G.BE >= 512 && G.logn >= 14)) ? 256 : 64; }
+// geometry of the all-digit inner product (K3): half-size blocks of the level's geometry, and never
+// below 1024 elements
+template <class GT> struct IpGeom { using type = typename HalfBlocks<GT>::type; };
+template <> struct IpGeom<PassGeomC<14, 9>> { using type = PassGeomC<14, 10>; };
+// geometry of the ModUp kernel (K2): the level's, and never below 1024 elements
+template <class GT> struct ModupGeom { using type = GT; };
+template <> struct ModupGeom<PassGeomC<14, 9>> { using type = PassGeomC<14, 10>; };
 
 // Launch KERNEL<NT, GT> (GT = the geometry type in scope) with 256 or 64 threads.
 #define HS2_LAUNCH(KERNEL, GRID, LDS, STREAM, ...)                                                  \
@@ -694,10 +702,17 @@ void launch_ntt2(const hs_ctx* c, u64* data, double* scratch, i64 rows, int nl, 
   });
 }
 
+// Block size of the two-pass key switch at N = 2^14: 3 = 512-element blocks for the single-pass
+// kernels (K1, K4, K5) with ModUp and the inner product on 1024 (more, shorter workgroups: the
+// kernels are latency-bound at a few items per level), 1 = 2048-element blocks throughout (K3 on
+// 1024), 2 = 1024-element blocks throughout, 0 = automatic: 3 up to kSmallLevel items, else 1.
+static std::atomic<int> g_ks_block{0};
+void set_ks_block(int mode) { g_ks_block = mode; }
+
 void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, double* T1, double* E, double* ACC, double* T2,
                           double* F, hipStream_t st) {
   if (B <= 0) return;
-  with_geom(c->logn, [&](auto G) {
+  auto body = [&](auto G) {
     using GT = decltype(G);
     const size_t LB = (size_t)lds_doubles(G.BE) * sizeof(double);
     const size_t TW = (size_t)2 * G.BE * sizeof(double);
@@ -706,6 +721,10 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     const int LK = c->L + c->K;
     HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B), TW + LB, st, d_items, T1, c->L, tab, G);
     const int tg = g_modup_tg.load() > 0 ? g_modup_tg.load() : (B >= 5 ? 3 : 2);
+    using G2T = typename ModupGeom<GT>::type;
+    G2T G2{};
+    if constexpr (std::is_same<G2T, GT>::value) G2 = G;   // a runtime geometry carries its fields
+    const size_t LB2 = (size_t)lds_doubles(G2.BE) * sizeof(double);
     if (tg <= 1) {
       HS2_LAUNCH(k2_modup_high, dim3(G.nblk, c->dnum * LK, B), (TWH + LB) * (c->alpha + 1), st, (const double*)T1, E, S,
                  (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
@@ -713,22 +732,22 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
       // enough groups for the digit with the fewest primes (the last one), which has the most targets
       const int na_min = c->L - (c->dnum - 1) * c->alpha;
       const int ngrp = (LK - na_min + tg - 1) / tg;
-      const size_t lds = (TWH + LB) * (c->alpha + tg) + 16 * (size_t)tg;
+      const size_t lds = (TWH + LB2) * (c->alpha + tg) + 16 * (size_t)tg;
       ProfScope _prof("k2_modup_grp", st);
       if (tg == 2) {
-        ensure_lds2((const void*)k2_modup_grp<512, 2, GT>, lds);
-        hipLaunchKernelGGL((k2_modup_grp<512, 2, GT>), dim3(G.nblk, c->dnum * ngrp, B), dim3(512), lds, st, (const double*)T1, E, S, ngrp,
-                           (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
+        ensure_lds2((const void*)k2_modup_grp<512, 2, G2T>, lds);
+        hipLaunchKernelGGL((k2_modup_grp<512, 2, G2T>), dim3(G2.nblk, c->dnum * ngrp, B), dim3(512), lds, st, (const double*)T1, E, S, ngrp,
+                           (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G2);
       } else {
-        ensure_lds2((const void*)k2_modup_grp<512, 3, GT>, lds);
-        hipLaunchKernelGGL((k2_modup_grp<512, 3, GT>), dim3(G.nblk, c->dnum * ngrp, B), dim3(512), lds, st, (const double*)T1, E, S, ngrp,
-                           (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G);
+        ensure_lds2((const void*)k2_modup_grp<512, 3, G2T>, lds);
+        hipLaunchKernelGGL((k2_modup_grp<512, 3, G2T>), dim3(G2.nblk, c->dnum * ngrp, B), dim3(512), lds, st, (const double*)T1, E, S, ngrp,
+                           (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, G2);
       }
       HS_CHECK_HIP(hipGetLastError());
     }
     // the all-digit inner product on half-size blocks where the geometry is compile-time (twice
     // the workgroups, each with half the serial work; two fit a CU)
-    using G3T = typename HalfBlocks<GT>::type;
+    using G3T = typename IpGeom<GT>::type;
     const G3T G3{};
     constexpr int NT3 = G3T::kMaxBE >= 2048 ? 1024 : 512;
     const size_t LB3 = (size_t)lds_doubles(G3.BE) * sizeof(double), TW3 = (size_t)2 * G3.BE * sizeof(double);
@@ -745,7 +764,12 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
                (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, tab, G);
     HS2_LAUNCH(k2_final_low, dim3(G.nblk, 2 * c->L, B), TW + LB, st, d_items, (const double*)F, (const double*)ACC,
                (const double2*)c->d_pinv, S, tab, G);
-  });
+  };
+  constexpr int kSmallLevel = 8;
+  const int blk = g_ks_block.load() == 0 ? (B <= kSmallLevel ? 3 : 1) : g_ks_block.load();
+  if (c->logn == 14 && blk == 3) body(PassGeomC<14, 9>{});
+  else if (c->logn == 14 && blk == 2) body(PassGeomC<14, 10>{});
+  else with_geom(c->logn, body);
 }
 
 }  // namespace hs
