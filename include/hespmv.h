@@ -317,7 +317,8 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
    HS_OPT_AUX_PATH     keygen, encoding, encryption, decryption: 0 = automatic, 1 = fused kernels
                        with the limb in LDS, 2 = elementwise kernels around batched transforms
                        (always used for N = 32768)
-   HS_OPT_MODUP_GROUP  two-pass ModUp: targets per workgroup, 0 = automatic (by level size), 1 = one
+   HS_OPT_MODUP_GROUP  two-pass ModUp: targets per workgroup, 0 = automatic (by level size and block
+                       geometry), 1 = one
                        (the digit's inverse pass repeated per target), 2 or 3 = one inverse pass
                        shared by that many targets
    HS_OPT_NTT_PIPE     forward transforms of many N = 2^14 limbs (hs_ntt, encryption): 0 = automatic

@@ -634,8 +634,9 @@ __global__ void __launch_bounds__(NT) k2_final_low(const RotItem* __restrict__ i
 }
 
 // ------------------------------------------------------------------ launchers
-// ModUp targets per workgroup of K2: 1 = k2_modup_high, 2 or 3 = k2_modup_grp, 0 = by level size
-// (measured at N = 16384: two below 5 items, three from 5 on; the shared inverse pass saves work
+// ModUp targets per workgroup of K2: 1 = k2_modup_high, 2 or 3 = k2_modup_grp, 0 = automatic
+// (three on the small-level geometry of N = 16384, whose ModUp blocks are smaller than the
+// level's; otherwise two below 5 items and three from 5 on: the shared inverse pass saves work
 // while fewer, longer workgroups cost latency).
 static std::atomic<int> g_modup_tg{0};
 void set_modup_group(int tg) { g_modup_tg = tg; }
@@ -720,8 +721,10 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     const ModTab* tab = (const ModTab*)c->d_tab;
     const int LK = c->L + c->K;
     HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B), TW + LB, st, d_items, T1, c->L, tab, G);
-    const int tg = g_modup_tg.load() > 0 ? g_modup_tg.load() : (B >= 5 ? 3 : 2);
     using G2T = typename ModupGeom<GT>::type;
+    // targets per ModUp workgroup: three on 1024-element blocks (the small-level geometry at
+    // N = 2^14, where it measured fastest at every level size), else two below 5 items
+    const int tg = g_modup_tg.load() > 0 ? g_modup_tg.load() : ((B >= 5 || !std::is_same<G2T, GT>::value) ? 3 : 2);
     G2T G2{};
     if constexpr (std::is_same<G2T, GT>::value) G2 = G;   // a runtime geometry carries its fields
     const size_t LB2 = (size_t)lds_doubles(G2.BE) * sizeof(double);
