@@ -691,13 +691,18 @@ HS_XF_KERNEL k_dec_phase(const u64* __restrict__ ct, const u64* __restrict__ sk,
 
 // m = round(t x / Q) mod t from the residues x_i (exact):  with y_i = [x_i Qhat_i^-1]_{q_i},
 // t y_i = a_i q_i + r_i, round(t x / Q) = sum a_i + round(sum_i r_i Qhat_i / Q) (mod t).
+// WT > 0: the word count of Q as a compile-time constant (the multiword arrays stay in registers
+// and every word loop unrolls); WT = 0: runtime W <= 16.
+template <int WT>
 __global__ void k_dec_round(const u64* __restrict__ X, u64* M, int n_ct, int L, u64 t, const double2* __restrict__ dinv,
-                            const u64* __restrict__ dhat, const u64* __restrict__ dq, int W, const ModTab* __restrict__ tab, int logn) {
+                            const u64* __restrict__ dhat, const u64* __restrict__ dq, int W_, const ModTab* __restrict__ tab, int logn) {
+  constexpr int WA = WT > 0 ? WT : 16;
+  const int W = WT > 0 ? WT : W_;
   const int n = 1 << logn;
   const int gid = blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= n_ct * n) return;
   const int g = gid >> logn, k = gid & (n - 1);
-  u64 S[16];
+  u64 S[WA];
   for (int w = 0; w < W; w++) S[w] = 0;
   u64 asum = 0;
   for (int i = 0; i < L; i++) {
@@ -727,7 +732,7 @@ __global__ void k_dec_round(const u64* __restrict__ X, u64* M, int n_ct, int L, 
     }
   }
   // T = 2 S + Q; kq = floor(T / 2Q) by repeated subtraction (kq <= L)
-  u64 T[16], twoq[16];
+  u64 T[WA], twoq[WA];
   {
     u64 sh = 0, cadd = 0, shq = 0;
     for (int w = 0; w < W; w++) {
@@ -1011,9 +1016,26 @@ void launch_dec_round(const hs_ctx* c, const u64* X, u64* M, int n_ct, hipStream
   if (n_ct <= 0) return;
   const i64 total = (i64)n_ct * c->N;
   ProfScope _prof("k_dec_round", st);
-  hipLaunchKernelGGL(k_dec_round, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, X, M, n_ct, c->L, c->t,
-                     (const double2*)c->d_dec_inv, (const u64*)c->d_dec_hat, (const u64*)c->d_dec_q, c->dec_words,
-                     (const ModTab*)c->d_tab, c->logn);
+  const dim3 grid((unsigned)((total + 255) / 256));
+#define HS_DEC_ROUND(WT)                                                                                          \
+  hipLaunchKernelGGL(k_dec_round<WT>, grid, dim3(256), 0, st, X, M, n_ct, c->L, c->t, (const double2*)c->d_dec_inv, \
+                     (const u64*)c->d_dec_hat, (const u64*)c->d_dec_q, c->dec_words, (const ModTab*)c->d_tab, c->logn)
+  switch (c->dec_words) {
+    case 2: HS_DEC_ROUND(2); break;
+    case 3: HS_DEC_ROUND(3); break;
+    case 4: HS_DEC_ROUND(4); break;
+    case 5: HS_DEC_ROUND(5); break;
+    case 6: HS_DEC_ROUND(6); break;
+    case 7: HS_DEC_ROUND(7); break;
+    case 8: HS_DEC_ROUND(8); break;
+    case 9: HS_DEC_ROUND(9); break;
+    case 10: HS_DEC_ROUND(10); break;
+    case 11: HS_DEC_ROUND(11); break;
+    default:
+      HS_REQUIRE(c->dec_words <= 16, HS_EPARAM, "ciphertext modulus too wide for decryption");
+      HS_DEC_ROUND(0);
+  }
+#undef HS_DEC_ROUND
   HS_CHECK_HIP(hipGetLastError());
 }
 
