@@ -397,11 +397,12 @@ static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem
 // Batched transform of `rows` limbs: one workgroup per limb, or the two-pass form (N / 2048
 // workgroups per limb) for limbs larger than LDS and, automatically, for a handful of limbs, whose
 // one-workgroup transforms would occupy a few CUs for a whole transform's latency.
-static constexpr i64 kTwoPassMaxRows = 16;
+static constexpr i64 kTwoPassMaxRows = 16, kTwoPassMaxRows14 = 64;  // N = 2^14: 512-element blocks
 static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int inverse, hipStream_t st, std::vector<DBuf>& hold) {
   if (rows <= 0) return;
   const int opt = g_opt_ntt.load();
-  if (!lds_limb_fits(c) || opt == 2 || (opt == 0 && c->logn >= 12 && rows <= kTwoPassMaxRows)) {
+  const i64 two_max = c->logn == 14 ? kTwoPassMaxRows14 : kTwoPassMaxRows;
+  if (!lds_limb_fits(c) || opt == 2 || (opt == 0 && c->logn >= 12 && rows <= two_max)) {
     hold.emplace_back(&c->pool, (size_t)rows * c->N * sizeof(double));
     launch_ntt2(c, data, hold.back().as<double>(), rows, nl, mod0, inverse, st);
   } else {
