@@ -503,8 +503,13 @@ static void encrypt_coefs(hs_ctx* c, const u64* coef, const int* samples, const 
   if (use_split_client(c)) {
     hold.emplace_back(&c->pool, (size_t)G * 3 * c->L * c->N * sizeof(u64));
     u64* prep = hold.back().as<u64>();
-    launch_enc_prep(c, coef, samples, G, prep, st);
-    ntt_any(c, prep, (i64)G * 3 * c->L, c->L, 0, 0, st, hold);
+    const i64 rows = (i64)G * 3 * c->L;
+    if (lds_limb_fits(c) && g_opt_ntt.load() != 2 && g_opt_aux.load() == 0 && rows > (c->logn == 14 ? kTwoPassMaxRows14 : kTwoPassMaxRows)) {
+      launch_enc_ntt(c, coef, samples, G, prep, st);   // the one-workgroup transforms, prologue in their input
+    } else {
+      launch_enc_prep(c, coef, samples, G, prep, st);
+      ntt_any(c, prep, rows, c->L, 0, 0, st, hold);
+    }
     launch_enc_combine(c, prep, pk, out, G, st);
   } else {
     launch_encrypt(c, coef, samples, pk, out, G, st);

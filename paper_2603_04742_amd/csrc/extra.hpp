@@ -1,5 +1,6 @@
 // Launchers beside those of kernels.hpp: the diagonal method's packing kernels (aux2.hip), the
-// encryption samples in one launch and the switch of the pipelined forward transform (kernels.hip),
+// encryption samples in one launch, encryption's transforms with the prologue in their input,
+// the switch of the pipelined forward transform (kernels.hip),
 // the block size of the two-pass key switch (ks2.hip).
 #pragma once
 #include "hs_internal.hpp"
@@ -12,4 +13,5 @@ void launch_diag_vector(const hs_ctx* c, const i64* v, i64 C, i64 B, int ncb, u6
 void set_ntt_pipe(bool on);
 void set_ks_block(int mode);
 void launch_sample_enc(const hs_ctx* c, int* out, int nobj, u64 seed, u32 pu, u32 pe0, u32 pe1, hipStream_t st);
+void launch_enc_ntt(const hs_ctx* c, const u64* mcoef, const int* samples, int n_ct, u64* prep, hipStream_t st);
 }  // namespace hs

@@ -187,6 +187,45 @@ k_ntt_fwd_pipe(u64* data, i64 nlimbs, int nl, int mod0, const ModTab* __restrict
   }
 }
 
+// Encryption's forward transforms with the prologue folded into their input: row b = (g, which, l)
+// of [G][3][L] transforms U = u (which 0), E1 = e1 (1) or D0 = e0 + floor(Q m / t + 1/2) (2),
+// reduced modulo q_l, into NTT form (the same values as the elementwise prologue followed by the
+// plain transform, without writing and re-reading them).  Samples [G][3][N] = (u, e0, e1).
+HS_XF_KERNEL k_enc_ntt(const u64* __restrict__ mcoef, const int* __restrict__ samples, u64* prep, int L, u64 t, u64 q_mod_t,
+                       const double2* __restrict__ qdt, const ModTab* __restrict__ tab, int logn, XF xf) {
+  SMEM();
+  const int n = 1 << logn;
+  const int b = blockIdx.x;
+  const int l = b % L, which = (b / L) % 3, g = b / (3 * L);
+  const ModTab tb = tab[l];
+  const ModD m = mod_of(tb);
+  const double q = tb.q;
+  const int* u = samples + (size_t)g * 3 * n;
+  const u64* mc = mcoef + (size_t)g * n;
+  u64* p = prep + (size_t)b * n;
+  auto out = [p, m](int i, double x) { p[i] = d2u(canon(x, m)); };
+  if (which == 0) {
+    xf.fwd([u, q](int i) { const int v = u[i]; return v < 0 ? (double)v + q : (double)v; }, out, smem, tb.fw, m);
+  } else if (which == 1) {
+    const int* e1 = u + 2 * n;
+    xf.fwd([e1, q](int i) { const int v = e1[i]; return v < 0 ? (double)v + q : (double)v; }, out, smem, tb.fw, m);
+  } else {
+    const int* e0 = u + n;
+    const double2 qd = qdt[l];
+    const double tt = (double)t, th = (double)(t / 2);
+    xf.fwd(
+        [=](int i) {
+          const u64 mv = mc[i];
+          const double d1 = mul_tw((double)mv, qd.x, qd.y, m);
+          // floor(((Q mod t) m + floor(t/2)) / t): the numerator is below 2^34, so the quotient of
+          // exactly represented doubles is within 2^-18 of the true one and floor is exact
+          const double d2 = floor(((double)(q_mod_t * mv) + th) / tt);
+          return canon(reduce((double)e0[i] + d1 + d2, m), m);
+        },
+        out, smem, tb.fw, m);
+  }
+}
+
 // ------------------------------------------------------------------ sampling
 // Small-integer samples (int32) of nobj polynomials: object o uses stream (seed, purpose,
 // index0 + o * index_step) and is written at out + o * obj_stride.  kind 0: ternary, word i -> (w mod 3) - 1.  kind 1: discrete Gaussian by CDT,
@@ -951,6 +990,12 @@ void launch_sample_enc(const hs_ctx* c, int* out, int nobj, u64 seed, u32 pu, u3
   ProfScope _prof("k_sample_enc", st);
   hipLaunchKernelGGL(k_sample_enc, dim3((unsigned)((threads + 255) / 256), 3), dim3(256), 0, st, out, nobj, seed, pu, pe0, pe1, c->logn);
   HS_CHECK_HIP(hipGetLastError());
+}
+
+void launch_enc_ntt(const hs_ctx* c, const u64* mcoef, const int* samples, int n_ct, u64* prep, hipStream_t st) {
+  if (n_ct <= 0) return;
+  HS_DISPATCH_XF(c->xf_variant_ntt, c, k_enc_ntt, dim3((unsigned)(n_ct * 3 * c->L)), st, mcoef, samples, prep, c->L, c->t, c->q_mod_t,
+                 (const double2*)c->d_qdt, (const ModTab*)c->d_tab, c->logn);
 }
 
 void launch_sk_ntt(const hs_ctx* c, u64* sk, const int* s_coef, hipStream_t st) {
