@@ -1388,6 +1388,7 @@ int hs_autotune(hs_ctx* c, const hs_keyset* ks, void* stream, double* report, in
       rep.push_back(tn[0]);
       rep.push_back(tn[1]);
       // 2. key-switch pipeline per batch-size bucket
+      double t1_64 = 0.0, t2_64 = 0.0;
       for (int b = 0; b < 7; b++) {
         const int B = 1 << b;
         const double t1 = one_ok ? time_ms(false, B) : 0.0;
@@ -1396,8 +1397,12 @@ int hs_autotune(hs_ctx* c, const hs_keyset* ks, void* stream, double* report, in
         rep.push_back(B);
         rep.push_back(t1);
         rep.push_back(t2);
+        t1_64 = t1; t2_64 = t2;
       }
-      c->ks_pick[7] = c->ks_pick[6];
+      // levels above 64 items (not timed): the one-workgroup pipeline gains on the two-pass one
+      // as levels grow (measured at 128 items: 104 K vs 88 K key switches/s at N = 16384), so the
+      // two-pass one keeps them only if it is clearly ahead at 64
+      c->ks_pick[7] = (!one_ok || t2_64 < 0.9 * t1_64) ? 1 : 0;
       HS_CHECK_HIP(hipStreamSynchronize(st));
     } catch (...) {
       (void)hipStreamSynchronize(st);
