@@ -485,10 +485,25 @@ __global__ void k_mask_acc(const u64* const* __restrict__ w, const u64* __restri
   const int g0 = part_chunk0[P], ng = part_nchunks[P];
   const ModD m = mod_of(tab[l]);
   double acc = 0.0;
-  for (int g = g0; g < g0 + ng; g++) {
-    double v = u2d(w[g][(size_t)row * n + k]);
-    if (mask) v = mulmod(v, u2d(mask[((size_t)g * L + l) * n + k]), m);
-    acc = reduce(acc + v, m);
+  // four chunks at a time: their words (and masks) are all requested before the first is used
+  constexpr int U = 4;
+  for (int g = g0; g < g0 + ng; g += U) {
+    u64 wv[U], mv[U];
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      const int gg = g + u < g0 + ng ? g + u : g;
+      const u64* wp = w[gg] + (size_t)row * n + k;
+      wv[u] = gld(wp);
+      mv[u] = gld(mask ? mask + ((size_t)gg * L + l) * n + k : wp);   // no branch around the load
+    }
+#pragma unroll
+    for (int u = 0; u < U; u++) {
+      if (g + u < g0 + ng) {
+        double v = u2d(wv[u]);
+        if (mask) v = mulmod(v, u2d(mv[u]), m);
+        acc = reduce(acc + v, m);
+      }
+    }
   }
   res[((size_t)P * 2 * L + row) * n + k] = d2u(canon(acc, m));
 }
