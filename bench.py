@@ -45,8 +45,8 @@ def main():
     ap.add_argument("--workload", default="zipf16k", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-matrix batched-vs-plain measurement")
-    ap.add_argument("--serve-requests", type=int, default=2000,
-                    help="requests of the serving run (Poisson arrivals at 200/s; 10000 for the full stream; 0 skips)")
+    ap.add_argument("--serve-requests", type=int, default=10000,
+                    help="requests of the serving run (Poisson arrivals at 200/s; 0 skips)")
     ap.add_argument("--no-diagonal", action="store_true",
                     help="skip the diagonal-method comparison (256 x 256 workload, and the Zipf workload: ~70 GB of HBM)")
     ap.add_argument("--no-laplace256", action="store_true",
