@@ -58,6 +58,9 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="with --profile-only: also copy 256 MiB once (device to device), the known-size kernel used to "
                          "scale rocprofv3 FETCH_SIZE / WRITE_SIZE")
+    ap.add_argument("--leg", choices=["laplace256", "batch64"],
+                    help="run only this leg once (for rocprofv3: batch64 then keeps the default launch rules, "
+                         "no autotuner) and print its result")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU; the encrypted-SpMV path here has no multi-GPU mode "
@@ -68,10 +71,15 @@ def main():
     from paper_2603_04742_amd import hespmv as H
     from paper_2603_04742_amd import workloads as W
 
-    gen, logn, L, bits, K, agg, desc = WORKLOADS[args.workload]
-    w = getattr(W, gen)()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.leg:
+        r = (lazy_relin_laplace256(H, W, torch, dev, reps=1) if args.leg == "laplace256"
+             else batched_vs_plain(H, W, torch, dev, reps=1, tune=False))
+        print(json.dumps(r), flush=True)
+        return
+    gen, logn, L, bits, K, agg, desc = WORKLOADS[args.workload]
+    w = getattr(W, gen)()
     ctx = H.Context(logn, L, bits, K, agg_mode=agg)
     ks = ctx.keygen(0x5EED)
     # launch variants for this context (untimed, once).  Not under --profile-only: a profiler that
@@ -514,15 +522,15 @@ def keyswitch_kernel_bytes(L, K, N):
     }
 
 
-def batched_vs_plain(H, W, torch, dev, reps=3):
+def batched_vs_plain(H, W, torch, dev, reps=3, tune=True):
     """The 64-matrix batch (rows log-uniform in [512, 16384], densities log-uniform in [0.05%, 1%],
     values in [-7, 7]; ring N=16384, 6x50-bit + 1): 64 sequential hs_he_spmv calls against one
     hs_he_spmv_batch call and against replays of the batch recorded as a HIP graph; matrices packed
     and vectors encrypted beforehand, launch variants chosen by the autotuner (untimed, once per
-    context)."""
+    context; with tune=False the default launch rules)."""
     ctx = H.Context(14, 6, 50, 1, agg_mode=0)
     ks = ctx.keygen(0xBA7C)
-    tune = H.autotune(ctx, ks)
+    tune = H.autotune(ctx, ks) if tune else None
     ws = W.batch64()
     ms, xs = [], []
     for i, w in enumerate(ws):
@@ -570,8 +578,9 @@ def batched_vs_plain(H, W, torch, dev, reps=3):
             "plain_spmv_per_s": round(len(ms) / t_plain, 2),
             "batched_ms": round(t_batch * 1e3, 2), "graph_ms": round(t_graph * 1e3, 2), "plain_ms": round(t_plain * 1e3, 2),
             "speedup": round(t_plain / t_batch, 2), "graph_speedup": round(t_plain / t_graph, 2), "decrypt_check": ok,
-            "autotune": {"keyswitch_transform_variant": tune["variant"], "pipeline_two_pass_by_B": {str(b): int(t2 <= t1 or t1 == 0)
-                                                                                          for b, t1, t2 in tune["pipelines"]}}}
+            "autotune": None if tune is None else
+            {"keyswitch_transform_variant": tune["variant"], "pipeline_two_pass_by_B": {str(b): int(t2 <= t1 or t1 == 0)
+                                                                                     for b, t1, t2 in tune["pipelines"]}}}
 
 
 def serving(H, W, torch, dev, n_requests, rate=200.0, n_keysets=8, pool=16):

@@ -122,7 +122,7 @@ struct hs_ctx {
   hs::u64* d_dec_q = nullptr;      // [dec_words] Q
   // exact ciphertext product over the tensor basis (all n_mod moduli)
   bool has_tensor = false;
-  int tq_words = 0, tm_words = 0, td_words = 0, tmu_words = 0, ta_words = 0;
+  int tq_words = 0, tm_words = 0, td_words = 0, tmu_words = 0, ta_words = 0, t_kw = 0;
   hs::u64* d_t_halfq = nullptr;
   double2* d_t_mhat_inv = nullptr;
   hs::u64* d_t_mhat = nullptr;

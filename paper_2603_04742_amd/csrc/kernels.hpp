@@ -56,11 +56,12 @@ struct TensorConst {
   int WM;
   const u64* D;             // [WD] 2Q
   int WD;
-  const u64* mu;            // [WMU] floor(2^(64 WA) / 2Q)
+  const u64* mu;            // [WMU + 1] floor(2^(64 kw) / 2Q)
   int WMU, WA;
   const double2* r64;       // [T] 2^64 mod m
   int T, L;
   u64 t;
+  int kw;                   // word capacity of the kernels (8, 16 or 24); mu = floor(2^(64 kw) / 2Q)
 };
 
 // HIP-event timing of kernel launches (profiler.cpp)

@@ -345,10 +345,13 @@ void build_ctx(hs_ctx* c) {
     const int WA = (int)A_max.size() + 1;
     const Words D = words_shl1(Q, 0);
     const int WD = (int)D.size();
-    const Words mu = words_pow2_div(64 * WA, D);
+    // word capacity of the tensor kernels: the widest value (S mod M with one spare word, A, the
+    // CRT sum mod Q with one spare word) rounded up to an instantiated size
+    const int need = std::max(std::max(WM + 1, WA), WQ + 1);
+    const int kw = need <= 8 ? 8 : need <= 16 ? 16 : need <= 24 ? 24 : 0;
+    const Words mu = words_pow2_div(64 * std::max(kw, 1), D);
     const int WMU = (int)mu.size();
-    const int kMaxW = 24;
-    if (WM + 1 <= kMaxW && WA <= kMaxW && WMU + 1 <= kMaxW && WQ + 1 <= kMaxW) {
+    if (kw && WMU <= kw) {
       std::vector<double2> minv(T), r64(T);
       std::vector<u64> mhat((size_t)T * WM, 0);
       for (int i = 0; i < T; i++) {
@@ -360,7 +363,7 @@ void build_ctx(hs_ctx* c) {
         for (size_t w = 0; w < h.size(); w++) mhat[(size_t)i * WM + w] = h[w];
         r64[i] = make_const((u64)(((u128)1 << 64) % c->mod[i]), c->mod[i]);
       }
-      c->tq_words = WQ; c->tm_words = WM; c->td_words = WD; c->tmu_words = WMU; c->ta_words = WA;
+      c->tq_words = WQ; c->tm_words = WM; c->td_words = WD; c->tmu_words = WMU; c->ta_words = WA; c->t_kw = kw;
       c->d_t_halfq = upload(padded(words_shr1(Q), WQ));
       c->d_t_mhat_inv = upload(minv);
       c->d_t_mhat = upload(mhat);

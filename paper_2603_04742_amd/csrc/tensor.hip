@@ -5,88 +5,152 @@
 // negacyclic products are formed in NTT form there, and each coefficient is reconstructed by CRT
 // as an integer in (-M/2, M/2) before the exact rounding.  Per-coefficient multiword arithmetic in
 // 64-bit words; the division by 2Q uses a Barrett reciprocal.
+//
+// The kernels are instantiated for a word capacity KW (8, 16 or 24) chosen by the context: every
+// multiword loop is unrolled to KW and predicated on the value's runtime width, so each word has a
+// compile-time index and the values stay in registers (with runtime indices they would live in
+// private scratch memory, whose traffic dominated these kernels).  The Barrett reciprocal is
+// floor(2^(64 KW) / 2Q), which puts the quotient at the fixed word offset KW of the product.
+#include <utility>
+
 #include "hs_device.hpp"
 #include "kernels.hpp"
 
 namespace hs {
 
-static constexpr int kMaxW = 24;  // words of the largest multiword value (A = 2 t |X| + Q)
-
 __device__ __forceinline__ ModD mody(const ModTab& t) { return ModD{t.q, t.qinv}; }
 
-// acc[0..W) += a[0..W) * v  (returns nothing; acc must have room for the carry)
-__device__ __forceinline__ void mw_mac(u64* acc, const u64* a, int W, u64 v) {
+// f(std::integral_constant<int, I>) for I = 0 .. N-1, expanded at compile time (the nested word
+// loops below are too long for the loop unroller to flatten on its own)
+template <class F, int... I>
+__device__ __forceinline__ void static_for_seq(F&& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_seq(f, std::make_integer_sequence<int, N>{});
+}
+
+// acc += a[0..W) * v, the carry running through the words of acc above W
+template <int KW>
+__device__ __forceinline__ void mw_mac(u64 (&acc)[KW], const u64* a, int W, u64 v) {
   u64 carry = 0;
-  for (int w = 0; w < W; w++) {
-    const u64 lo = a[w] * v, hi = __umul64hi(a[w], v);
-    const u64 s1 = acc[w] + lo;
-    const u64 c1 = s1 < lo;
-    const u64 s2 = s1 + carry;
-    const u64 c2 = s2 < carry;
-    acc[w] = s2;
-    carry = hi + c1 + c2;
-  }
-  for (int w = W; carry && w < kMaxW; w++) {
-    const u64 s = acc[w] + carry;
-    carry = s < carry;
-    acc[w] = s;
+#pragma unroll
+  for (int w = 0; w < KW; w++) {
+    if (w < W) {
+      const u64 x = a[w];
+      const u64 lo = x * v, hi = __umul64hi(x, v);
+      const u64 s1 = acc[w] + lo;
+      const u64 c1 = s1 < lo;
+      const u64 s2 = s1 + carry;
+      const u64 c2 = s2 < carry;
+      acc[w] = s2;
+      carry = hi + c1 + c2;
+    } else {
+      const u64 s = acc[w] + carry;
+      carry = s < carry;
+      acc[w] = s;
+    }
   }
 }
-__device__ __forceinline__ int mw_cmp(const u64* a, const u64* b, int W) {
-  for (int w = W - 1; w >= 0; w--)
-    if (a[w] != b[w]) return a[w] < b[w] ? -1 : 1;
-  return 0;
+// sign of a - b over the low W words (b: device words)
+template <int KW>
+__device__ __forceinline__ int mw_cmp(const u64 (&a)[KW], const u64* b, int W) {
+  int r = 0;
+#pragma unroll
+  for (int w = KW - 1; w >= 0; w--)
+    if (w < W && r == 0) {
+      const u64 y = b[w];
+      if (a[w] != y) r = a[w] < y ? -1 : 1;
+    }
+  return r;
 }
-__device__ __forceinline__ void mw_sub(u64* a, const u64* b, int W) {  // a -= b, a >= b
+// a -= b over the low W words (a >= b)
+template <int KW>
+__device__ __forceinline__ void mw_sub(u64 (&a)[KW], const u64* b, int W) {
   u64 br = 0;
-  for (int w = 0; w < W; w++) {
-    const u64 x = a[w], y = b[w];
-    const u64 d = x - y;
-    const u64 b1 = x < y;
-    const u64 d2 = d - br;
-    const u64 b2 = d < br;
-    a[w] = d2;
-    br = b1 | b2;
-  }
+#pragma unroll
+  for (int w = 0; w < KW; w++)
+    if (w < W) {
+      const u64 x = a[w], y = b[w];
+      const u64 d = x - y;
+      const u64 b1 = x < y;
+      const u64 d2 = d - br;
+      const u64 b2 = d < br;
+      a[w] = d2;
+      br = b1 | b2;
+    }
 }
-// value mod q for a multiword value (Horner from the top word)
-__device__ __forceinline__ u64 mw_mod(const u64* a, int W, u64 q, double2 r64, ModD m) {
+// a = b - a over the low W words (b >= a)
+template <int KW>
+__device__ __forceinline__ void mw_rsub(u64 (&a)[KW], const u64* b, int W) {
+  u64 br = 0;
+#pragma unroll
+  for (int w = 0; w < KW; w++)
+    if (w < W) {
+      const u64 x = b[w], y = a[w];
+      const u64 d = x - y;
+      const u64 b1 = x < y;
+      const u64 d2 = d - br;
+      const u64 b2 = d < br;
+      a[w] = d2;
+      br = b1 | b2;
+    }
+}
+// value of the low W words mod q (Horner from the top word)
+template <int KW>
+__device__ __forceinline__ u64 mw_mod(const u64 (&a)[KW], int W, u64 q, double2 r64, ModD m) {
   double r = 0.0;
-  for (int w = W - 1; w >= 0; w--) r = canon(mul_tw(r, r64.x, r64.y, m) + u2d(a[w] % q), m);
+#pragma unroll
+  for (int w = KW - 1; w >= 0; w--)
+    if (w < W) r = canon(mul_tw(r, r64.x, r64.y, m) + u2d(a[w] % q), m);
   return d2u(r);
+}
+// (c0, c1, c2) += x * y
+__device__ __forceinline__ void acc3(u64& c0, u64& c1, u64& c2, u64 x, u64 y) {
+  const u64 lo = x * y, hi = __umul64hi(x, y);
+  c0 += lo;
+  const u64 k0 = c0 < lo;
+  c1 += hi;
+  const u64 k1 = c1 < hi;
+  c1 += k0;
+  const u64 k2 = c1 < k0;
+  c2 += k1 + k2;
 }
 
 // Centered lift of data-prime residues to the T tensor moduli.  x: [rows][L][N] coefficient form;
 // out: [rows][T][N].  grid-stride over rows * N coefficients.
-__global__ void k_crt_lift(const u64* __restrict__ x, u64* out, int rows, TensorConst C, const ModTab* __restrict__ tab, int logn) {
+template <int KW>
+__global__ void __launch_bounds__(256) k_crt_lift(const u64* __restrict__ x, u64* out, int rows, TensorConst C,
+                                                  const ModTab* __restrict__ tab, int logn) {
   const i64 n = 1 << logn;
   const i64 total = (i64)rows * n;
   for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
     const i64 row = idx >> logn, k = idx & (n - 1);
     const u64* xr = x + (size_t)row * C.L * n;
-    u64 S[kMaxW];
-    for (int w = 0; w < C.WQ + 1; w++) S[w] = 0;
+    // S = sum_i [x_i (Q/q_i)^-1]_{q_i} Q/q_i  (< L Q), then S mod Q
+    u64 S[KW];
+#pragma unroll
+    for (int w = 0; w < KW; w++) S[w] = 0;
     for (int i = 0; i < C.L; i++) {
       const ModTab tb = tab[i];
       const ModD m = mody(tb);
       const u64 y = d2u(canon(mul_tw(u2d(xr[(size_t)i * n + k]), C.qhat_inv[i].x, C.qhat_inv[i].y, m), m));
-      mw_mac(S, C.qhat + (size_t)i * C.WQ, C.WQ, y);
+      mw_mac<KW>(S, C.qhat + (size_t)i * C.WQ, C.WQ, y);
     }
-    for (int guard = 0; guard <= C.L && mw_cmp(S, C.Q, C.WQ) >= 0; guard++) mw_sub(S, C.Q, C.WQ);
-    const bool neg = mw_cmp(S, C.halfQ, C.WQ) > 0;
-    if (neg) {  // mag = Q - S
-      u64 t[kMaxW];
-      for (int w = 0; w < C.WQ; w++) t[w] = C.Q[w];
-      mw_sub(t, S, C.WQ);
-      for (int w = 0; w < C.WQ; w++) S[w] = t[w];
+    for (int guard = 0; guard <= C.L; guard++) {
+      if (mw_cmp<KW>(S, C.Q, C.WQ) < 0) break;
+      mw_sub<KW>(S, C.Q, C.WQ);
     }
+    const bool neg = mw_cmp<KW>(S, C.halfQ, C.WQ) > 0;
+    if (neg) mw_rsub<KW>(S, C.Q, C.WQ);  // magnitude Q - S
     u64* o = out + (size_t)row * C.T * n;
     for (int mi = 0; mi < C.T; mi++) {
       if (mi < C.L) { o[(size_t)mi * n + k] = xr[(size_t)mi * n + k]; continue; }
       const ModTab tb = tab[mi];
       const ModD m = mody(tb);
       const u64 q = (u64)tb.q;
-      const u64 r = mw_mod(S, C.WQ, q, C.r64[mi], m);
+      const u64 r = mw_mod<KW>(S, C.WQ, q, C.r64[mi], m);
       o[(size_t)mi * n + k] = neg ? (r ? q - r : 0) : r;
     }
   }
@@ -113,7 +177,10 @@ __global__ void k_tensor(const u64* __restrict__ lift, u64* prod, int items, int
 
 // Scale and round: prod [item][3][T][N] coefficient form -> out [item][4][L][N] coefficient form
 // laid out (d0, d2, 0, d1) so that (d0, d2) is the ciphertext to relinearise and (0, d1) its addend.
-__global__ void k_scale_round(const u64* __restrict__ prod, u64* out, int items, TensorConst C, const ModTab* __restrict__ tab, int logn) {
+// (registers over occupancy: the widest instantiation holds about 60 live words per lane)
+template <int KW>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_scale_round(const u64* __restrict__ prod, u64* out, int items, TensorConst C,
+                                                     const ModTab* __restrict__ tab, int logn) {
   const i64 n = 1 << logn;
   const i64 total = (i64)items * 3 * n;
   for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
@@ -122,100 +189,139 @@ __global__ void k_scale_round(const u64* __restrict__ prod, u64* out, int items,
     const int w = (int)(r % 3), it = (int)(r / 3);
     const u64* P = prod + ((size_t)it * 3 + w) * C.T * n;
     // X = sum_m [x_m Mhat_m^-1]_m Mhat_m  - floor(sum_m y_m / m) M
-    u64 S[kMaxW];
-    for (int i = 0; i < kMaxW; i++) S[i] = 0;
+    u64 S[KW];
+#pragma unroll
+    for (int i = 0; i < KW; i++) S[i] = 0;
     double est = 0.0;
     for (int mi = 0; mi < C.T; mi++) {
       const ModTab tb = tab[mi];
       const ModD m = mody(tb);
       const u64 y = d2u(canon(mul_tw(u2d(P[(size_t)mi * n + k]), C.mhat_inv[mi].x, C.mhat_inv[mi].y, m), m));
-      mw_mac(S, C.mhat + (size_t)mi * C.WM, C.WM, y);
+      mw_mac<KW>(S, C.mhat + (size_t)mi * C.WM, C.WM, y);
       est += (double)y / tb.q;
     }
     u64 kq = (u64)est;
     if (kq > 0) kq -= 1;  // never above the true quotient; the loop below finishes it
-    if (kq) {
-      u64 t[kMaxW];
-      for (int i = 0; i < kMaxW; i++) t[i] = 0;
-      mw_mac(t, C.M, C.WM, kq);
-      mw_sub(S, t, C.WM + 1);
+    if (kq) {             // S -= kq M over WM + 1 words (M is stored with WM + 1)
+      u64 carry = 0, br = 0;
+#pragma unroll
+      for (int i = 0; i < KW; i++)
+        if (i < C.WM + 1) {
+          const u64 x = C.M[i];
+          const u64 lo = x * kq, hi = __umul64hi(x, kq);
+          const u64 p = lo + carry;
+          carry = hi + (p < lo);
+          const u64 d = S[i] - p;
+          const u64 b1 = S[i] < p;
+          const u64 d2 = d - br;
+          const u64 b2 = d < br;
+          S[i] = d2;
+          br = b1 | b2;
+        }
     }
-    for (int guard = 0; guard < 4 && mw_cmp(S, C.M, C.WM + 1) >= 0; guard++) mw_sub(S, C.M, C.WM + 1);
-    const bool neg = mw_cmp(S, C.halfM, C.WM) > 0;
-    if (neg) {
-      u64 t[kMaxW];
-      for (int i = 0; i < C.WM; i++) t[i] = C.M[i];
-      mw_sub(t, S, C.WM);
-      for (int i = 0; i < C.WM; i++) S[i] = t[i];
-    }
-    // A = 2 t |X| + Q
-    u64 A[kMaxW];
-    for (int i = 0; i < kMaxW; i++) A[i] = 0;
-    mw_mac(A, S, C.WM, 2 * C.t);
+#pragma unroll
+    for (int guard = 0; guard < 4; guard++)
+      if (mw_cmp<KW>(S, C.M, C.WM + 1) >= 0) mw_sub<KW>(S, C.M, C.WM + 1);
+    const bool neg = mw_cmp<KW>(S, C.halfM, C.WM) > 0;
+    if (neg) mw_rsub<KW>(S, C.M, C.WM);  // |X| = M - S
+    // A = 2 t |X| + Q  (WA words, below 2^(64 KW))
+    u64 A[KW];
+#pragma unroll
+    for (int i = 0; i < KW; i++) A[i] = 0;
     {
-      u64 q2[kMaxW];
-      for (int i = 0; i < kMaxW; i++) q2[i] = i < C.WQ ? C.Q[i] : 0;
       u64 carry = 0;
-      for (int i = 0; i < C.WA; i++) {
-        const u64 s1 = A[i] + q2[i];
-        const u64 c1 = s1 < q2[i];
-        const u64 s2 = s1 + carry;
-        const u64 c2 = s2 < carry;
-        A[i] = s2;
-        carry = c1 + c2;
-      }
-    }
-    // quotient estimate floor(A mu / 2^(64 WA)), then fix with remainders (at most 2 steps)
-    u64 qe[kMaxW];
-    for (int i = 0; i < kMaxW; i++) qe[i] = 0;
-    {
-      // top words of A * mu: word WA + j of the product, j = 0 .. WMU
-      u64 prodw[2 * kMaxW + 2];
-      for (int i = 0; i < C.WA + C.WMU + 1; i++) prodw[i] = 0;
-      for (int i = 0; i < C.WA; i++) {
-        u64 carry = 0;
-        for (int j = 0; j < C.WMU; j++) {
-          const u64 lo = A[i] * C.mu[j], hi = __umul64hi(A[i], C.mu[j]);
-          const u64 s1 = prodw[i + j] + lo;
-          const u64 c1 = s1 < lo;
+      const u64 v = 2 * C.t;
+#pragma unroll
+      for (int i = 0; i < KW; i++)
+        if (i < C.WM) {
+          const u64 lo = S[i] * v, hi = __umul64hi(S[i], v);
+          const u64 s = lo + carry;
+          carry = hi + (s < lo);
+          A[i] = s;
+        } else if (i == C.WM) {
+          A[i] = carry;
+        }
+      carry = 0;
+#pragma unroll
+      for (int i = 0; i < KW; i++)
+        if (i < C.WA) {
+          const u64 qv = i < C.WQ ? C.Q[i] : 0;
+          const u64 s1 = A[i] + qv;
+          const u64 c1 = s1 < qv;
           const u64 s2 = s1 + carry;
           const u64 c2 = s2 < carry;
-          prodw[i + j] = s2;
-          carry = hi + c1 + c2;
+          A[i] = s2;
+          carry = c1 + c2;
         }
-        prodw[i + C.WMU] += carry;
-      }
-      for (int j = 0; j < kMaxW && C.WA + j < C.WA + C.WMU + 1; j++) qe[j] = prodw[C.WA + j];
     }
+    // quotient estimate floor(A mu / 2^(64 KW)): words KW .. 2 KW of the product, by columns
+    u64 qe[KW + 1];
     {
-      u64 R[kMaxW], QD[kMaxW];
-      for (int i = 0; i < kMaxW; i++) { R[i] = A[i]; QD[i] = 0; }
-      for (int j = 0; j <= C.WMU; j++)
-        if (qe[j]) {
-          u64 carry = 0;
-          for (int i = 0; i < C.WD && i + j < kMaxW; i++) {
-            const u64 lo = qe[j] * C.D[i], hi = __umul64hi(qe[j], C.D[i]);
-            const u64 s1 = QD[i + j] + lo;
-            const u64 c1 = s1 < lo;
-            const u64 s2 = s1 + carry;
-            const u64 c2 = s2 < carry;
-            QD[i + j] = s2;
-            carry = hi + c1 + c2;
+      u64 c0 = 0, c1 = 0, c2 = 0;
+      static_for<2 * KW>([&](auto cc) {
+        constexpr int col = decltype(cc)::value;
+        static_for<KW>([&](auto ic) {
+          constexpr int i = decltype(ic)::value;
+          constexpr int j = col - i;
+          if constexpr (j >= 0 && j < KW) {
+            if (i < C.WA && j < C.WMU) acc3(c0, c1, c2, A[i], C.mu[j]);
           }
-          for (int i = j + C.WD; carry && i < kMaxW; i++) {
-            const u64 s = QD[i] + carry;
-            carry = s < carry;
-            QD[i] = s;
-          }
+        });
+        if constexpr (col >= KW) qe[col - KW] = c0;
+        c0 = c1; c1 = c2; c2 = 0;
+      });
+      qe[KW] = c0;
+    }
+    // R = A - qe * 2Q, kept in the low WD + 1 words of A (0 <= R < 3 (2Q)); then fix the quotient
+    {
+      u64 c0 = 0, c1 = 0, c2 = 0, br = 0;
+      static_for<KW>([&](auto cc) {
+        constexpr int col = decltype(cc)::value;
+        if (col <= C.WD) {
+          static_for<col + 1>([&](auto jc) {
+            constexpr int j = decltype(jc)::value;
+            constexpr int i = col - j;
+            if (i < C.WD && j <= C.WMU) acc3(c0, c1, c2, qe[j], C.D[i]);
+          });
+          const u64 x = A[col];
+          const u64 d = x - c0;
+          const u64 b1 = x < c0;
+          const u64 d2 = d - br;
+          const u64 b2 = d < br;
+          A[col] = d2;
+          br = b1 | b2;
+          c0 = c1; c1 = c2; c2 = 0;
         }
-      mw_sub(R, QD, C.WA);
-      u64 Dw[kMaxW];
-      for (int i = 0; i < kMaxW; i++) Dw[i] = i < C.WD ? C.D[i] : 0;
-      for (int guard = 0; guard < 4 && mw_cmp(R, Dw, C.WA) >= 0; guard++) {
-        mw_sub(R, Dw, C.WA);
-        for (int i = 0; i < kMaxW; i++) {  // qe += 1
-          qe[i] += 1;
-          if (qe[i] != 0) break;
+      });
+#pragma unroll
+      for (int guard = 0; guard < 4; guard++) {
+        // R >= 2Q over WD + 1 words (the word of 2Q above WD is zero)
+        int cmp = 0;
+#pragma unroll
+        for (int i = KW - 1; i >= 0; i--)
+          if (i <= C.WD && cmp == 0) {
+            const u64 y = i < C.WD ? C.D[i] : 0;
+            if (A[i] != y) cmp = A[i] < y ? -1 : 1;
+          }
+        if (cmp < 0) break;
+        u64 bb = 0;
+#pragma unroll
+        for (int i = 0; i < KW; i++)
+          if (i <= C.WD) {
+            const u64 x = A[i], y = i < C.WD ? C.D[i] : 0;
+            const u64 d = x - y;
+            const u64 b1 = x < y;
+            const u64 d2 = d - bb;
+            const u64 b2 = d < bb;
+            A[i] = d2;
+            bb = b1 | b2;
+          }
+        u64 inc = 1;
+#pragma unroll
+        for (int i = 0; i <= KW; i++) {  // qe += 1
+          const u64 s = qe[i] + inc;
+          inc = s < inc;
+          qe[i] = s;
         }
       }
     }
@@ -227,7 +333,7 @@ __global__ void k_scale_round(const u64* __restrict__ prod, u64* out, int items,
       const ModTab tb = tab[i];
       const ModD m = mody(tb);
       const u64 q = (u64)tb.q;
-      const u64 rr = mw_mod(qe, C.WMU + 1, q, C.r64[i], m);
+      const u64 rr = mw_mod<KW + 1>(qe, C.WMU + 1, q, C.r64[i], m);
       o[(size_t)i * n + k] = neg ? (rr ? q - rr : 0) : rr;
       if (w == 0) z[(size_t)i * n + k] = 0;
     }
@@ -237,10 +343,19 @@ __global__ void k_scale_round(const u64* __restrict__ prod, u64* out, int items,
 // ------------------------------------------------------------------ launchers
 static dim3 grid_t(i64 total) { return dim3((unsigned)std::min<i64>((total + 255) / 256, 256 * 32)); }
 
+// the word capacity the context chose (8, 16 or 24) selects the instantiation
+#define HS_TENSOR_KW(KERNEL, GRID, ...)                                                                 \
+  do {                                                                                                  \
+    if (C.kw == 8) hipLaunchKernelGGL(KERNEL<8>, GRID, dim3(256), 0, st, __VA_ARGS__);                  \
+    else if (C.kw == 16) hipLaunchKernelGGL(KERNEL<16>, GRID, dim3(256), 0, st, __VA_ARGS__);           \
+    else if (C.kw == 24) hipLaunchKernelGGL(KERNEL<24>, GRID, dim3(256), 0, st, __VA_ARGS__);           \
+    else throw ::hs::Error{HS_EPARAM, "no tensor kernel for this word capacity"};                     \
+  } while (0)
+
 void launch_crt_lift(const hs_ctx* c, const TensorConst& C, const u64* x, u64* out, int rows, hipStream_t st) {
   if (rows <= 0) return;
   ProfScope _prof("k_crt_lift", st);
-  hipLaunchKernelGGL(k_crt_lift, grid_t((i64)rows * c->N), dim3(256), 0, st, x, out, rows, C, (const ModTab*)c->d_tab, c->logn);
+  HS_TENSOR_KW(k_crt_lift, grid_t((i64)rows * c->N), x, out, rows, C, (const ModTab*)c->d_tab, c->logn);
   HS_CHECK_HIP(hipGetLastError());
 }
 void launch_tensor(const hs_ctx* c, const u64* lift, u64* prod, int items, int T, hipStream_t st) {
@@ -252,7 +367,7 @@ void launch_tensor(const hs_ctx* c, const u64* lift, u64* prod, int items, int T
 void launch_scale_round(const hs_ctx* c, const TensorConst& C, const u64* prod, u64* out, int items, hipStream_t st) {
   if (items <= 0) return;
   ProfScope _prof("k_scale_round", st);
-  hipLaunchKernelGGL(k_scale_round, grid_t((i64)items * 3 * c->N), dim3(256), 0, st, prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
+  HS_TENSOR_KW(k_scale_round, grid_t((i64)items * 3 * c->N), prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
   HS_CHECK_HIP(hipGetLastError());
 }
 
