@@ -438,7 +438,7 @@ static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const
   C.qhat_inv = (const double2*)c->d_dec_inv; C.qhat = c->d_dec_hat; C.Q = c->d_dec_q; C.halfQ = c->d_t_halfq; C.WQ = c->tq_words;
   C.mhat_inv = (const double2*)c->d_t_mhat_inv; C.mhat = c->d_t_mhat; C.M = c->d_t_m; C.halfM = c->d_t_halfm; C.WM = c->tm_words;
   C.D = c->d_t_d; C.WD = c->td_words; C.mu = c->d_t_mu; C.WMU = c->tmu_words; C.WA = c->ta_words;
-  C.r64 = (const double2*)c->d_t_r64; C.T = T; C.L = L; C.t = c->t; C.kw = c->t_kw;
+  C.r32 = (const double2*)c->d_t_r32; C.T = T; C.L = L; C.t = c->t; C.kw = c->t_kw;
   DBuf LIFT(&c->pool, (size_t)n * 4 * T * N * sizeof(u64));
   launch_crt_lift(c, C, X.as<u64>(), LIFT.as<u64>(), n * 4, st);
   ntt_any(c, LIFT.as<u64>(), (i64)n * 4 * T, T, 0, 0, st, hold);

@@ -130,7 +130,7 @@ struct hs_ctx {
   hs::u64* d_t_halfm = nullptr;
   hs::u64* d_t_d = nullptr;
   hs::u64* d_t_mu = nullptr;
-  double2* d_t_r64 = nullptr;
+  double2* d_t_r32 = nullptr;
   hs::Pool pool;
   // stream of the matrix plaintext encoding, which runs after hs_cssc_pack returns (default
   // priority, non-blocking); each matrix records an event on it when its plaintexts are ready

@@ -58,7 +58,7 @@ struct TensorConst {
   int WD;
   const u64* mu;            // [WMU + 1] floor(2^(64 kw) / 2Q)
   int WMU, WA;
-  const double2* r64;       // [T] 2^64 mod m
+  const double2* r32;       // [T] 2^32 mod m
   int T, L;
   u64 t;
   int kw;                   // word capacity of the kernels (8, 16 or 24); mu = floor(2^(64 kw) / 2Q)

@@ -352,7 +352,7 @@ void build_ctx(hs_ctx* c) {
     const Words mu = words_pow2_div(64 * std::max(kw, 1), D);
     const int WMU = (int)mu.size();
     if (kw && WMU <= kw) {
-      std::vector<double2> minv(T), r64(T);
+      std::vector<double2> minv(T), r32(T);
       std::vector<u64> mhat((size_t)T * WM, 0);
       for (int i = 0; i < T; i++) {
         std::vector<u64> others;
@@ -361,7 +361,7 @@ void build_ctx(hs_ctx* c) {
         const Words h = words_product(others);
         minv[i] = make_const(inv_mod(words_mod(h, c->mod[i]), c->mod[i]), c->mod[i]);
         for (size_t w = 0; w < h.size(); w++) mhat[(size_t)i * WM + w] = h[w];
-        r64[i] = make_const((u64)(((u128)1 << 64) % c->mod[i]), c->mod[i]);
+        r32[i] = make_const((1ULL << 32) % c->mod[i], c->mod[i]);
       }
       c->tq_words = WQ; c->tm_words = WM; c->td_words = WD; c->tmu_words = WMU; c->ta_words = WA; c->t_kw = kw;
       c->d_t_halfq = upload(padded(words_shr1(Q), WQ));
@@ -371,7 +371,7 @@ void build_ctx(hs_ctx* c) {
       c->d_t_halfm = upload(padded(words_shr1(M), WM));
       c->d_t_d = upload(padded(D, WD));
       c->d_t_mu = upload(padded(mu, WMU + 1));
-      c->d_t_r64 = upload(r64);
+      c->d_t_r32 = upload(r32);
       c->has_tensor = true;
     }
   }
@@ -380,7 +380,7 @@ void build_ctx(hs_ctx* c) {
 void free_ctx(hs_ctx* c) {
   void* ptrs[] = {c->d_tab, c->d_tw, c->d_slot_pos, c->d_qdt, c->d_pmod, c->d_pinv, c->d_up_inv,
                   c->d_up_hat, c->d_dn_inv, c->d_dn_hat, c->d_dec_inv, c->d_dec_hat, c->d_dec_q,
-                  c->d_t_halfq, c->d_t_mhat_inv, c->d_t_mhat, c->d_t_m, c->d_t_halfm, c->d_t_d, c->d_t_mu, c->d_t_r64};
+                  c->d_t_halfq, c->d_t_mhat_inv, c->d_t_mhat, c->d_t_m, c->d_t_halfm, c->d_t_d, c->d_t_mu, c->d_t_r32};
   for (void* p : ptrs)
     if (p) (void)hipFree(p);
   if (c->side) {

@@ -97,14 +97,18 @@ __device__ __forceinline__ void mw_rsub(u64 (&a)[KW], const u64* b, int W) {
       br = b1 | b2;
     }
 }
-// value of the low W words mod q (Horner from the top word)
+// value of the low W words mod q: Horner over 32-bit digits from the top, r = r 2^32 + digit
+// with r32 = 2^32 mod q, no integer division (|r| stays below 0.625 q + 2^32 < 2^51)
 template <int KW>
-__device__ __forceinline__ u64 mw_mod(const u64 (&a)[KW], int W, u64 q, double2 r64, ModD m) {
+__device__ __forceinline__ u64 mw_mod(const u64 (&a)[KW], int W, double2 r32, ModD m) {
   double r = 0.0;
 #pragma unroll
   for (int w = KW - 1; w >= 0; w--)
-    if (w < W) r = canon(mul_tw(r, r64.x, r64.y, m) + u2d(a[w] % q), m);
-  return d2u(r);
+    if (w < W) {
+      r = mul_tw(r, r32.x, r32.y, m) + (double)(u32)(a[w] >> 32);
+      r = mul_tw(r, r32.x, r32.y, m) + (double)(u32)a[w];
+    }
+  return d2u(canon(r, m));
 }
 // (c0, c1, c2) += x * y
 __device__ __forceinline__ void acc3(u64& c0, u64& c1, u64& c2, u64 x, u64 y) {
@@ -150,7 +154,7 @@ __global__ void __launch_bounds__(256) k_crt_lift(const u64* __restrict__ x, u64
       const ModTab tb = tab[mi];
       const ModD m = mody(tb);
       const u64 q = (u64)tb.q;
-      const u64 r = mw_mod<KW>(S, C.WQ, q, C.r64[mi], m);
+      const u64 r = mw_mod<KW>(S, C.WQ, C.r32[mi], m);
       o[(size_t)mi * n + k] = neg ? (r ? q - r : 0) : r;
     }
   }
@@ -198,7 +202,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       const ModD m = mody(tb);
       const u64 y = d2u(canon(mul_tw(u2d(P[(size_t)mi * n + k]), C.mhat_inv[mi].x, C.mhat_inv[mi].y, m), m));
       mw_mac<KW>(S, C.mhat + (size_t)mi * C.WM, C.WM, y);
-      est += (double)y / tb.q;
+      est += (double)y * tb.qinv;  // error ~1e-13: the estimate minus one stays a lower bound
     }
     u64 kq = (u64)est;
     if (kq > 0) kq -= 1;  // never above the true quotient; the loop below finishes it
@@ -333,7 +337,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       const ModTab tb = tab[i];
       const ModD m = mody(tb);
       const u64 q = (u64)tb.q;
-      const u64 rr = mw_mod<KW + 1>(qe, C.WMU + 1, q, C.r64[i], m);
+      const u64 rr = mw_mod<KW + 1>(qe, C.WMU + 1, C.r32[i], m);
       o[(size_t)i * n + k] = neg ? (rr ? q - rr : 0) : rr;
       if (w == 0) z[(size_t)i * n + k] = 0;
     }
