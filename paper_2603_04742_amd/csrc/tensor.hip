@@ -31,6 +31,16 @@ __device__ __forceinline__ void static_for(F&& f) {
   static_for_seq(f, std::make_integer_sequence<int, N>{});
 }
 
+// the 128-bit product a b from four 32 x 32 -> 64 multiply-adds (no partial sum exceeds 2^64 - 1)
+__device__ __forceinline__ void mul128(u64 a, u64 b, u64& lo, u64& hi) {
+  const u64 a0 = (u32)a, a1 = a >> 32, b0 = (u32)b, b1 = b >> 32;
+  const u64 p0 = a0 * b0;
+  const u64 p1 = a0 * b1 + (p0 >> 32);
+  const u64 p2 = a1 * b0 + (u32)p1;
+  hi = a1 * b1 + (p1 >> 32) + (p2 >> 32);
+  lo = (p2 << 32) | (u32)p0;
+}
+
 // acc += a[0..W) * v, the carry running through the words of acc above W
 template <int KW>
 __device__ __forceinline__ void mw_mac(u64 (&acc)[KW], const u64* a, int W, u64 v) {
@@ -38,8 +48,8 @@ __device__ __forceinline__ void mw_mac(u64 (&acc)[KW], const u64* a, int W, u64 
 #pragma unroll
   for (int w = 0; w < KW; w++) {
     if (w < W) {
-      const u64 x = a[w];
-      const u64 lo = x * v, hi = __umul64hi(x, v);
+      u64 lo, hi;
+      mul128(a[w], v, lo, hi);
       const u64 s1 = acc[w] + lo;
       const u64 c1 = s1 < lo;
       const u64 s2 = s1 + carry;
@@ -112,7 +122,8 @@ __device__ __forceinline__ u64 mw_mod(const u64 (&a)[KW], int W, double2 r32, Mo
 }
 // (c0, c1, c2) += x * y
 __device__ __forceinline__ void acc3(u64& c0, u64& c1, u64& c2, u64 x, u64 y) {
-  const u64 lo = x * y, hi = __umul64hi(x, y);
+  u64 lo, hi;
+  mul128(x, y, lo, hi);
   c0 += lo;
   const u64 k0 = c0 < lo;
   c1 += hi;
@@ -211,8 +222,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 #pragma unroll
       for (int i = 0; i < KW; i++)
         if (i < C.WM + 1) {
-          const u64 x = C.M[i];
-          const u64 lo = x * kq, hi = __umul64hi(x, kq);
+          u64 lo, hi;
+          mul128(C.M[i], kq, lo, hi);
           const u64 p = lo + carry;
           carry = hi + (p < lo);
           const u64 d = S[i] - p;
@@ -238,7 +249,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 #pragma unroll
       for (int i = 0; i < KW; i++)
         if (i < C.WM) {
-          const u64 lo = S[i] * v, hi = __umul64hi(S[i], v);
+          u64 lo, hi;
+          mul128(S[i], v, lo, hi);
           const u64 s = lo + carry;
           carry = hi + (s < lo);
           A[i] = s;
