@@ -358,10 +358,11 @@ def check_protocol_seeded(p, seed, w):
             _cache[(p, 7)] = saved
 
 
-@pytest.mark.parametrize("p", [(6, 3, 50, 1, 0), (8, 4, 40, 2, 0), (10, 3, 50, 2, 0)])
+@pytest.mark.parametrize("p", [(6, 3, 50, 1, 0), (8, 4, 40, 2, 0), (10, 3, 50, 2, 0), (13, 4, 50, 2, 0), (10, 12, 50, 2, 0)])
 def test_mul_ct_parity(p):
     """Exact scaled tensor + relinearisation against the oracle, bit for bit (K = 1 and K = 2
-    digits), and the product decrypts to the slot-wise product."""
+    digits; the last two rings need the 16- and 24-word instantiations of the multiword kernels,
+    the others the 8-word one), and the product decrypts to the slot-wise product."""
     logn, L, bits, K, agg = p
     g = H.Context(logn, L, bits, K, agg_mode=agg)
     o = O.Context(logn, L, bits, K, agg_mode=agg)
