@@ -198,6 +198,31 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
                                                      const ModTab* __restrict__ tab, int logn) {
   const i64 n = 1 << logn;
   const i64 total = (i64)items * 3 * n;
+  // the constant tables in LDS, once per workgroup (read word by word in the loops below)
+  extern __shared__ __align__(16) u64 tc_lds[];
+  const int T = C.T, WM = C.WM;
+  u64* l_mhat = tc_lds;                  // [T][WM]
+  u64* l_M = l_mhat + (size_t)T * WM;    // [WM + 1]
+  u64* l_halfM = l_M + (WM + 1);         // [WM]
+  u64* l_mu = l_halfM + WM;              // [WMU + 1]
+  u64* l_D = l_mu + (C.WMU + 1);         // [WD]
+  u64* l_Q = l_D + C.WD;                 // [WQ]
+  const int nu = T * WM + 2 * WM + 2 + C.WMU + C.WD + C.WQ;   // u64 words above, padded to 16 bytes
+  double2* l_qm = (double2*)(tc_lds + nu + (nu & 1));            // (q, 1/q) [T]
+  double2* l_minv = l_qm + T;            // [T]
+  double2* l_r32 = l_minv + T;           // [T]
+  for (int i = threadIdx.x; i < T * WM; i += blockDim.x) l_mhat[i] = C.mhat[i];
+  for (int i = threadIdx.x; i < WM + 1; i += blockDim.x) l_M[i] = C.M[i];
+  for (int i = threadIdx.x; i < WM; i += blockDim.x) l_halfM[i] = C.halfM[i];
+  for (int i = threadIdx.x; i < C.WMU + 1; i += blockDim.x) l_mu[i] = C.mu[i];
+  for (int i = threadIdx.x; i < C.WD; i += blockDim.x) l_D[i] = C.D[i];
+  for (int i = threadIdx.x; i < C.WQ; i += blockDim.x) l_Q[i] = C.Q[i];
+  for (int i = threadIdx.x; i < T; i += blockDim.x) {
+    l_qm[i] = double2{tab[i].q, tab[i].qinv};
+    l_minv[i] = C.mhat_inv[i];
+    l_r32[i] = C.r32[i];
+  }
+  __syncthreads();
   for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
     const i64 k = idx & (n - 1);
     const i64 r = idx >> logn;
@@ -208,12 +233,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 #pragma unroll
     for (int i = 0; i < KW; i++) S[i] = 0;
     double est = 0.0;
-    for (int mi = 0; mi < C.T; mi++) {
-      const ModTab tb = tab[mi];
-      const ModD m = mody(tb);
-      const u64 y = d2u(canon(mul_tw(u2d(P[(size_t)mi * n + k]), C.mhat_inv[mi].x, C.mhat_inv[mi].y, m), m));
-      mw_mac<KW>(S, C.mhat + (size_t)mi * C.WM, C.WM, y);
-      est += (double)y * tb.qinv;  // error ~1e-13: the estimate minus one stays a lower bound
+    for (int mi = 0; mi < T; mi++) {
+      const double2 qm = l_qm[mi], mv = l_minv[mi];
+      const ModD m{qm.x, qm.y};
+      const u64 y = d2u(canon(mul_tw(u2d(P[(size_t)mi * n + k]), mv.x, mv.y, m), m));
+      mw_mac<KW>(S, l_mhat + (size_t)mi * WM, WM, y);
+      est += (double)y * qm.y;  // error ~1e-13: the estimate minus one stays a lower bound
     }
     u64 kq = (u64)est;
     if (kq > 0) kq -= 1;  // never above the true quotient; the loop below finishes it
@@ -223,7 +248,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       for (int i = 0; i < KW; i++)
         if (i < C.WM + 1) {
           u64 lo, hi;
-          mul128(C.M[i], kq, lo, hi);
+          mul128(l_M[i], kq, lo, hi);
           const u64 p = lo + carry;
           carry = hi + (p < lo);
           const u64 d = S[i] - p;
@@ -236,9 +261,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     }
 #pragma unroll
     for (int guard = 0; guard < 4; guard++)
-      if (mw_cmp<KW>(S, C.M, C.WM + 1) >= 0) mw_sub<KW>(S, C.M, C.WM + 1);
-    const bool neg = mw_cmp<KW>(S, C.halfM, C.WM) > 0;
-    if (neg) mw_rsub<KW>(S, C.M, C.WM);  // |X| = M - S
+      if (mw_cmp<KW>(S, l_M, WM + 1) >= 0) mw_sub<KW>(S, l_M, WM + 1);
+    const bool neg = mw_cmp<KW>(S, l_halfM, WM) > 0;
+    if (neg) mw_rsub<KW>(S, l_M, WM);  // |X| = M - S
     // A = 2 t |X| + Q  (WA words, below 2^(64 KW))
     u64 A[KW];
 #pragma unroll
@@ -261,7 +286,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 #pragma unroll
       for (int i = 0; i < KW; i++)
         if (i < C.WA) {
-          const u64 qv = i < C.WQ ? C.Q[i] : 0;
+          const u64 qv = i < C.WQ ? l_Q[i] : 0;
           const u64 s1 = A[i] + qv;
           const u64 c1 = s1 < qv;
           const u64 s2 = s1 + carry;
@@ -280,7 +305,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
           constexpr int i = decltype(ic)::value;
           constexpr int j = col - i;
           if constexpr (j >= 0 && j < KW) {
-            if (i < C.WA && j < C.WMU) acc3(c0, c1, c2, A[i], C.mu[j]);
+            if (i < C.WA && j < C.WMU) acc3(c0, c1, c2, A[i], l_mu[j]);
           }
         });
         if constexpr (col >= KW) qe[col - KW] = c0;
@@ -297,7 +322,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
           static_for<col + 1>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
             constexpr int i = col - j;
-            if (i < C.WD && j <= C.WMU) acc3(c0, c1, c2, qe[j], C.D[i]);
+            if (i < C.WD && j <= C.WMU) acc3(c0, c1, c2, qe[j], l_D[i]);
           });
           const u64 x = A[col];
           const u64 d = x - c0;
@@ -316,7 +341,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 #pragma unroll
         for (int i = KW - 1; i >= 0; i--)
           if (i <= C.WD && cmp == 0) {
-            const u64 y = i < C.WD ? C.D[i] : 0;
+            const u64 y = i < C.WD ? l_D[i] : 0;
             if (A[i] != y) cmp = A[i] < y ? -1 : 1;
           }
         if (cmp < 0) break;
@@ -324,7 +349,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 #pragma unroll
         for (int i = 0; i < KW; i++)
           if (i <= C.WD) {
-            const u64 x = A[i], y = i < C.WD ? C.D[i] : 0;
+            const u64 x = A[i], y = i < C.WD ? l_D[i] : 0;
             const u64 d = x - y;
             const u64 b1 = x < y;
             const u64 d2 = d - bb;
@@ -346,10 +371,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
     u64* o = out + ((size_t)it * 4 + slot) * C.L * n;
     u64* z = out + ((size_t)it * 4 + 2) * C.L * n;
     for (int i = 0; i < C.L; i++) {
-      const ModTab tb = tab[i];
-      const ModD m = mody(tb);
-      const u64 q = (u64)tb.q;
-      const u64 rr = mw_mod<KW + 1>(qe, C.WMU + 1, C.r32[i], m);
+      const double2 qm = l_qm[i];
+      const ModD m{qm.x, qm.y};
+      const u64 q = (u64)qm.x;
+      const u64 rr = mw_mod<KW + 1>(qe, C.WMU + 1, l_r32[i], m);
       o[(size_t)i * n + k] = neg ? (rr ? q - rr : 0) : rr;
       if (w == 0) z[(size_t)i * n + k] = 0;
     }
@@ -383,7 +408,13 @@ void launch_tensor(const hs_ctx* c, const u64* lift, u64* prod, int items, int T
 void launch_scale_round(const hs_ctx* c, const TensorConst& C, const u64* prod, u64* out, int items, hipStream_t st) {
   if (items <= 0) return;
   ProfScope _prof("k_scale_round", st);
-  HS_TENSOR_KW(k_scale_round, grid_t((i64)items * 3 * c->N), prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
+  const size_t u64s = (size_t)C.T * C.WM + 2 * C.WM + 2 + C.WMU + C.WD + C.WQ;
+  const size_t lds = 8 * (u64s + (u64s & 1)) + 3 * 16 * (size_t)C.T;   // the tables staged by k_scale_round
+  const dim3 grid = grid_t((i64)items * 3 * c->N);
+  if (C.kw == 8) hipLaunchKernelGGL(k_scale_round<8>, grid, dim3(256), lds, st, prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
+  else if (C.kw == 16) hipLaunchKernelGGL(k_scale_round<16>, grid, dim3(256), lds, st, prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
+  else if (C.kw == 24) hipLaunchKernelGGL(k_scale_round<24>, grid, dim3(256), lds, st, prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
+  else throw ::hs::Error{HS_EPARAM, "no tensor kernel for this word capacity"};
   HS_CHECK_HIP(hipGetLastError());
 }
 
