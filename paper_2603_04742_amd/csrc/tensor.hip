@@ -193,30 +193,33 @@ __global__ void k_tensor(const u64* __restrict__ lift, u64* prod, int items, int
 // Scale and round: prod [item][3][T][N] coefficient form -> out [item][4][L][N] coefficient form
 // laid out (d0, d2, 0, d1) so that (d0, d2) is the ciphertext to relinearise and (0, d1) its addend.
 // (registers over occupancy: the widest instantiation holds about 60 live words per lane)
-template <int KW>
+// Optional compile-time word widths (0: the context's runtime values) fold the width predicates.
+template <int KW, int WMc = 0, int WAc = 0, int WDc = 0, int WMUc = 0, int WQc = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))) k_scale_round(const u64* __restrict__ prod, u64* out, int items, TensorConst C,
                                                      const ModTab* __restrict__ tab, int logn) {
   const i64 n = 1 << logn;
   const i64 total = (i64)items * 3 * n;
   // the constant tables in LDS, once per workgroup (read word by word in the loops below)
   extern __shared__ __align__(16) u64 tc_lds[];
-  const int T = C.T, WM = C.WM;
+  const int T = C.T;
+  const int WM = WMc ? WMc : C.WM, WA = WAc ? WAc : C.WA, WD = WDc ? WDc : C.WD;
+  const int WMU = WMUc ? WMUc : C.WMU, WQ = WQc ? WQc : C.WQ;
   u64* l_mhat = tc_lds;                  // [T][WM]
   u64* l_M = l_mhat + (size_t)T * WM;    // [WM + 1]
   u64* l_halfM = l_M + (WM + 1);         // [WM]
   u64* l_mu = l_halfM + WM;              // [WMU + 1]
-  u64* l_D = l_mu + (C.WMU + 1);         // [WD]
-  u64* l_Q = l_D + C.WD;                 // [WQ]
-  const int nu = T * WM + 2 * WM + 2 + C.WMU + C.WD + C.WQ;   // u64 words above, padded to 16 bytes
+  u64* l_D = l_mu + (WMU + 1);         // [WD]
+  u64* l_Q = l_D + WD;                 // [WQ]
+  const int nu = T * WM + 2 * WM + 2 + WMU + WD + WQ;   // u64 words above, padded to 16 bytes
   double2* l_qm = (double2*)(tc_lds + nu + (nu & 1));            // (q, 1/q) [T]
   double2* l_minv = l_qm + T;            // [T]
   double2* l_r32 = l_minv + T;           // [T]
   for (int i = threadIdx.x; i < T * WM; i += blockDim.x) l_mhat[i] = C.mhat[i];
   for (int i = threadIdx.x; i < WM + 1; i += blockDim.x) l_M[i] = C.M[i];
   for (int i = threadIdx.x; i < WM; i += blockDim.x) l_halfM[i] = C.halfM[i];
-  for (int i = threadIdx.x; i < C.WMU + 1; i += blockDim.x) l_mu[i] = C.mu[i];
-  for (int i = threadIdx.x; i < C.WD; i += blockDim.x) l_D[i] = C.D[i];
-  for (int i = threadIdx.x; i < C.WQ; i += blockDim.x) l_Q[i] = C.Q[i];
+  for (int i = threadIdx.x; i < WMU + 1; i += blockDim.x) l_mu[i] = C.mu[i];
+  for (int i = threadIdx.x; i < WD; i += blockDim.x) l_D[i] = C.D[i];
+  for (int i = threadIdx.x; i < WQ; i += blockDim.x) l_Q[i] = C.Q[i];
   for (int i = threadIdx.x; i < T; i += blockDim.x) {
     l_qm[i] = double2{tab[i].q, tab[i].qinv};
     l_minv[i] = C.mhat_inv[i];
@@ -246,7 +249,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       u64 carry = 0, br = 0;
 #pragma unroll
       for (int i = 0; i < KW; i++)
-        if (i < C.WM + 1) {
+        if (i < WM + 1) {
           u64 lo, hi;
           mul128(l_M[i], kq, lo, hi);
           const u64 p = lo + carry;
@@ -273,20 +276,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       const u64 v = 2 * C.t;
 #pragma unroll
       for (int i = 0; i < KW; i++)
-        if (i < C.WM) {
+        if (i < WM) {
           u64 lo, hi;
           mul128(S[i], v, lo, hi);
           const u64 s = lo + carry;
           carry = hi + (s < lo);
           A[i] = s;
-        } else if (i == C.WM) {
+        } else if (i == WM) {
           A[i] = carry;
         }
       carry = 0;
 #pragma unroll
       for (int i = 0; i < KW; i++)
-        if (i < C.WA) {
-          const u64 qv = i < C.WQ ? l_Q[i] : 0;
+        if (i < WA) {
+          const u64 qv = i < WQ ? l_Q[i] : 0;
           const u64 s1 = A[i] + qv;
           const u64 c1 = s1 < qv;
           const u64 s2 = s1 + carry;
@@ -305,7 +308,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
           constexpr int i = decltype(ic)::value;
           constexpr int j = col - i;
           if constexpr (j >= 0 && j < KW) {
-            if (i < C.WA && j < C.WMU) acc3(c0, c1, c2, A[i], l_mu[j]);
+            if (i < WA && j < WMU) acc3(c0, c1, c2, A[i], l_mu[j]);
           }
         });
         if constexpr (col >= KW) qe[col - KW] = c0;
@@ -318,11 +321,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       u64 c0 = 0, c1 = 0, c2 = 0, br = 0;
       static_for<KW>([&](auto cc) {
         constexpr int col = decltype(cc)::value;
-        if (col <= C.WD) {
+        if (col <= WD) {
           static_for<col + 1>([&](auto jc) {
             constexpr int j = decltype(jc)::value;
             constexpr int i = col - j;
-            if (i < C.WD && j <= C.WMU) acc3(c0, c1, c2, qe[j], l_D[i]);
+            if (i < WD && j <= WMU) acc3(c0, c1, c2, qe[j], l_D[i]);
           });
           const u64 x = A[col];
           const u64 d = x - c0;
@@ -340,16 +343,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
         int cmp = 0;
 #pragma unroll
         for (int i = KW - 1; i >= 0; i--)
-          if (i <= C.WD && cmp == 0) {
-            const u64 y = i < C.WD ? l_D[i] : 0;
+          if (i <= WD && cmp == 0) {
+            const u64 y = i < WD ? l_D[i] : 0;
             if (A[i] != y) cmp = A[i] < y ? -1 : 1;
           }
         if (cmp < 0) break;
         u64 bb = 0;
 #pragma unroll
         for (int i = 0; i < KW; i++)
-          if (i <= C.WD) {
-            const u64 x = A[i], y = i < C.WD ? l_D[i] : 0;
+          if (i <= WD) {
+            const u64 x = A[i], y = i < WD ? l_D[i] : 0;
             const u64 d = x - y;
             const u64 b1 = x < y;
             const u64 d2 = d - bb;
@@ -374,7 +377,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
       const double2 qm = l_qm[i];
       const ModD m{qm.x, qm.y};
       const u64 q = (u64)qm.x;
-      const u64 rr = mw_mod<KW + 1>(qe, C.WMU + 1, l_r32[i], m);
+      const u64 rr = mw_mod<KW + 1>(qe, WMU + 1, l_r32[i], m);
       o[(size_t)i * n + k] = neg ? (rr ? q - rr : 0) : rr;
       if (w == 0) z[(size_t)i * n + k] = 0;
     }
@@ -411,7 +414,10 @@ void launch_scale_round(const hs_ctx* c, const TensorConst& C, const u64* prod, 
   const size_t u64s = (size_t)C.T * C.WM + 2 * C.WM + 2 + C.WMU + C.WD + C.WQ;
   const size_t lds = 8 * (u64s + (u64s & 1)) + 3 * 16 * (size_t)C.T;   // the tables staged by k_scale_round
   const dim3 grid = grid_t((i64)items * 3 * c->N);
-  if (C.kw == 8) hipLaunchKernelGGL(k_scale_round<8>, grid, dim3(256), lds, st, prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
+  // 12 x 50-bit data primes (N = 1024 ... 32768, 2 special primes): the widths at compile time
+  if (C.kw == 24 && C.WM == 21 && C.WA == 21 && C.WD == 10 && C.WMU == 15 && C.WQ == 11)
+    hipLaunchKernelGGL((k_scale_round<24, 21, 21, 10, 15, 11>), grid, dim3(256), lds, st, prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
+  else if (C.kw == 8) hipLaunchKernelGGL(k_scale_round<8>, grid, dim3(256), lds, st, prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
   else if (C.kw == 16) hipLaunchKernelGGL(k_scale_round<16>, grid, dim3(256), lds, st, prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
   else if (C.kw == 24) hipLaunchKernelGGL(k_scale_round<24>, grid, dim3(256), lds, st, prod, out, items, C, (const ModTab*)c->d_tab, c->logn);
   else throw ::hs::Error{HS_EPARAM, "no tensor kernel for this word capacity"};
