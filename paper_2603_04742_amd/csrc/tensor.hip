@@ -134,38 +134,56 @@ __device__ __forceinline__ void acc3(u64& c0, u64& c1, u64& c2, u64 x, u64 y) {
 }
 
 // Centered lift of data-prime residues to the T tensor moduli.  x: [rows][L][N] coefficient form;
-// out: [rows][T][N].  grid-stride over rows * N coefficients.
-template <int KW>
+// out: [rows][T][N].  grid-stride over rows * N coefficients.  The constant tables sit in LDS; a
+// nonzero WQc fixes the word width at compile time.
+template <int KW, int WQc = 0>
 __global__ void __launch_bounds__(256) k_crt_lift(const u64* __restrict__ x, u64* out, int rows, TensorConst C,
                                                   const ModTab* __restrict__ tab, int logn) {
   const i64 n = 1 << logn;
   const i64 total = (i64)rows * n;
+  extern __shared__ __align__(16) u64 cl_lds[];
+  const int L = C.L, T = C.T, WQ = WQc ? WQc : C.WQ;
+  u64* l_qhat = cl_lds;                  // [L][WQ]
+  u64* l_Q = l_qhat + (size_t)L * WQ;    // [WQ]
+  u64* l_halfQ = l_Q + WQ;               // [WQ]
+  const int nu = L * WQ + 2 * WQ;        // u64 words above, padded to 16 bytes
+  double2* l_qm = (double2*)(cl_lds + nu + (nu & 1));  // (q, 1/q) [T]
+  double2* l_qinv = l_qm + T;            // (Q/q_i)^-1 mod q_i [L]
+  double2* l_r32 = l_qinv + L;           // [T]
+  for (int i = threadIdx.x; i < L * WQ; i += blockDim.x) l_qhat[i] = C.qhat[i];
+  for (int i = threadIdx.x; i < WQ; i += blockDim.x) { l_Q[i] = C.Q[i]; l_halfQ[i] = C.halfQ[i]; }
+  for (int i = threadIdx.x; i < T; i += blockDim.x) {
+    l_qm[i] = double2{tab[i].q, tab[i].qinv};
+    l_r32[i] = C.r32[i];
+    if (i < L) l_qinv[i] = C.qhat_inv[i];
+  }
+  __syncthreads();
   for (i64 idx = blockIdx.x * (i64)blockDim.x + threadIdx.x; idx < total; idx += (i64)gridDim.x * blockDim.x) {
     const i64 row = idx >> logn, k = idx & (n - 1);
-    const u64* xr = x + (size_t)row * C.L * n;
+    const u64* xr = x + (size_t)row * L * n;
     // S = sum_i [x_i (Q/q_i)^-1]_{q_i} Q/q_i  (< L Q), then S mod Q
     u64 S[KW];
 #pragma unroll
     for (int w = 0; w < KW; w++) S[w] = 0;
-    for (int i = 0; i < C.L; i++) {
-      const ModTab tb = tab[i];
-      const ModD m = mody(tb);
-      const u64 y = d2u(canon(mul_tw(u2d(xr[(size_t)i * n + k]), C.qhat_inv[i].x, C.qhat_inv[i].y, m), m));
-      mw_mac<KW>(S, C.qhat + (size_t)i * C.WQ, C.WQ, y);
+    for (int i = 0; i < L; i++) {
+      const double2 qm = l_qm[i], qi = l_qinv[i];
+      const ModD m{qm.x, qm.y};
+      const u64 y = d2u(canon(mul_tw(u2d(xr[(size_t)i * n + k]), qi.x, qi.y, m), m));
+      mw_mac<KW>(S, l_qhat + (size_t)i * WQ, WQ, y);
     }
-    for (int guard = 0; guard <= C.L; guard++) {
-      if (mw_cmp<KW>(S, C.Q, C.WQ) < 0) break;
-      mw_sub<KW>(S, C.Q, C.WQ);
+    for (int guard = 0; guard <= L; guard++) {
+      if (mw_cmp<KW>(S, l_Q, WQ) < 0) break;
+      mw_sub<KW>(S, l_Q, WQ);
     }
-    const bool neg = mw_cmp<KW>(S, C.halfQ, C.WQ) > 0;
-    if (neg) mw_rsub<KW>(S, C.Q, C.WQ);  // magnitude Q - S
-    u64* o = out + (size_t)row * C.T * n;
-    for (int mi = 0; mi < C.T; mi++) {
-      if (mi < C.L) { o[(size_t)mi * n + k] = xr[(size_t)mi * n + k]; continue; }
-      const ModTab tb = tab[mi];
-      const ModD m = mody(tb);
-      const u64 q = (u64)tb.q;
-      const u64 r = mw_mod<KW>(S, C.WQ, C.r32[mi], m);
+    const bool neg = mw_cmp<KW>(S, l_halfQ, WQ) > 0;
+    if (neg) mw_rsub<KW>(S, l_Q, WQ);  // magnitude Q - S
+    u64* o = out + (size_t)row * T * n;
+    for (int mi = 0; mi < T; mi++) {
+      if (mi < L) { o[(size_t)mi * n + k] = xr[(size_t)mi * n + k]; continue; }
+      const double2 qm = l_qm[mi];
+      const ModD m{qm.x, qm.y};
+      const u64 q = (u64)qm.x;
+      const u64 r = mw_mod<KW>(S, WQ, l_r32[mi], m);
       o[(size_t)mi * n + k] = neg ? (r ? q - r : 0) : r;
     }
   }
@@ -387,19 +405,18 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 2))
 // ------------------------------------------------------------------ launchers
 static dim3 grid_t(i64 total) { return dim3((unsigned)std::min<i64>((total + 255) / 256, 256 * 32)); }
 
-// the word capacity the context chose (8, 16 or 24) selects the instantiation
-#define HS_TENSOR_KW(KERNEL, GRID, ...)                                                                 \
-  do {                                                                                                  \
-    if (C.kw == 8) hipLaunchKernelGGL(KERNEL<8>, GRID, dim3(256), 0, st, __VA_ARGS__);                  \
-    else if (C.kw == 16) hipLaunchKernelGGL(KERNEL<16>, GRID, dim3(256), 0, st, __VA_ARGS__);           \
-    else if (C.kw == 24) hipLaunchKernelGGL(KERNEL<24>, GRID, dim3(256), 0, st, __VA_ARGS__);           \
-    else throw ::hs::Error{HS_EPARAM, "no tensor kernel for this word capacity"};                     \
-  } while (0)
-
 void launch_crt_lift(const hs_ctx* c, const TensorConst& C, const u64* x, u64* out, int rows, hipStream_t st) {
   if (rows <= 0) return;
   ProfScope _prof("k_crt_lift", st);
-  HS_TENSOR_KW(k_crt_lift, grid_t((i64)rows * c->N), x, out, rows, C, (const ModTab*)c->d_tab, c->logn);
+  const size_t u64s = (size_t)C.L * C.WQ + 2 * C.WQ;
+  const size_t lds = 8 * (u64s + (u64s & 1)) + 16 * (2 * (size_t)C.T + C.L);   // the tables staged by k_crt_lift
+  const dim3 grid = grid_t((i64)rows * c->N);
+  const ModTab* tab = (const ModTab*)c->d_tab;
+  if (C.kw == 24 && C.WQ == 11) hipLaunchKernelGGL((k_crt_lift<24, 11>), grid, dim3(256), lds, st, x, out, rows, C, tab, c->logn);
+  else if (C.kw == 8) hipLaunchKernelGGL(k_crt_lift<8>, grid, dim3(256), lds, st, x, out, rows, C, tab, c->logn);
+  else if (C.kw == 16) hipLaunchKernelGGL(k_crt_lift<16>, grid, dim3(256), lds, st, x, out, rows, C, tab, c->logn);
+  else if (C.kw == 24) hipLaunchKernelGGL(k_crt_lift<24>, grid, dim3(256), lds, st, x, out, rows, C, tab, c->logn);
+  else throw ::hs::Error{HS_EPARAM, "no tensor kernel for this word capacity"};
   HS_CHECK_HIP(hipGetLastError());
 }
 void launch_tensor(const hs_ctx* c, const u64* lift, u64* prod, int items, int T, hipStream_t st) {
