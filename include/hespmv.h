@@ -45,8 +45,10 @@ extern "C" {
 /* ---------------------------------------------------------------- status codes */
 #define HS_OK 0
 #define HS_EINVAL (-1)     /* bad argument or malformed CSR (unsorted row pointers, index out of range) */
-#define HS_EPARAM (-2)     /* unsupported parameters: N not a power of two in [2^3, 2^16], t prime with t = 1 mod 2N required,
-                              not enough NTT-friendly primes, prime width above 50 bits */
+#define HS_EPARAM (-2)     /* unsupported parameters: N not a power of two in [2^3, 2^15], t prime below 2^26 with
+                              t = 1 mod 2N required, not enough NTT-friendly primes, prime width above 50 bits;
+                              also hs_mul_ct and encrypted matrices on a ring whose NTT-friendly primes cannot
+                              form a basis above 4 N Q^2 for the exact ciphertext product */
 #define HS_ECAPACITY (-3)  /* a size exceeds what the handle or parameter set can hold */
 #define HS_EKEY (-4)       /* keys missing or from another context */
 #define HS_ENOMEM (-5)     /* host or device allocation failed */
@@ -62,7 +64,7 @@ typedef struct hs_params {
   uint32_t q_bits;   /* bit width of data and special primes (<= 50) */
   uint32_t n_p;      /* K: number of special (key-switching) primes, >= 1; also the digit size */
   uint32_t p_bits;   /* must equal q_bits */
-  uint64_t t;        /* plaintext modulus, prime, t = 1 mod 2N (65537 for N <= 32768) */
+  uint64_t t;        /* plaintext modulus, prime, t = 1 mod 2N, t < 2^26 (65537 for N <= 32768) */
   double sigma;      /* error width; only 3.2 is supported */
   uint32_t agg_mode; /* 0 = paper aggregation: chunk heights NNZ[start] and masks (Alg. Aggregation);
                         1 = uniform heights NNZ[0] in a partition and no masks (one fewer ct x pt,
@@ -280,8 +282,19 @@ int hs_diag_decrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_diag* d, const hs
 int hs_ctvec_count(const hs_ctvec* v, int64_t* n);
 /* Ciphertext i as [2][L][N] NTT-form residues, into host memory (synchronises the device). */
 int hs_ct_export(const hs_ctvec* v, int64_t i, uint64_t* host_limbs, int64_t cap);
+/* Ciphertext i in the canonical coefficient form: [2][L][N] residues in [0, q_i) of the
+   polynomials c0, c1 (coefficient k of limb i is c_p(X) mod q_i at X^k), into host memory.  The
+   inverse NTT runs on the device (its own scratch, on `stream`, which is then synchronised);
+   `v` is not modified.  cap in u64 words (HS_ECAPACITY if short); HS_EINVAL for i out of range. */
+int hs_ct_export_coeff(const hs_ctvec* v, int64_t i, uint64_t* host_limbs, int64_t cap, void* stream);
 /* Build a vector of n ciphertexts from host limbs [n][2][L][N] (NTT form, residues < q_i). */
 int hs_ctvec_import(hs_ctx* ctx, const uint64_t* host_limbs, int64_t n, hs_ctvec** out);
+/* Wrap caller-owned device memory (e.g. a torch tensor's data_ptr()) holding n ciphertexts
+   [n][2][L][N] u64, NTT form, residues < q_i, as a vector handle without copying: every call that
+   takes an hs_ctvec reads it (hs_he_spmv's x, hs_ctvec_copy's dst ...) in place.  `dev` must be
+   8-byte aligned on the context's device and stay allocated until hs_ctvec_destroy, which frees
+   the handle only, never the memory.  HS_EINVAL for a null pointer, n < 1 or misalignment. */
+int hs_ctvec_wrap(hs_ctx* ctx, void* dev, int64_t n, hs_ctvec** out);
 void hs_ctvec_destroy(hs_ctvec* v);
 
 /* ---------------------------------------------------------------- primitive operations
@@ -306,7 +319,12 @@ int hs_rotate(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* in, int64_t k, v
 int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctvec* b,
               void* stream, hs_ctvec** out);
 
-/* Process-wide execution options (they never change results, only which kernels compute them):
+/* Execution options (they never change results, only which kernels compute them).  Each context
+   holds its own setting of every option (hs_ctx_set_option; value -1 = unset); an unset option
+   takes the process-wide default set by hs_set_option, read at each call.  The process-wide
+   defaults are the one piece of global mutable state of the library: they exist so that a test or
+   benchmark can switch kernels for every context at once.  Setting an option must not race with
+   calls that use it (on the context, or on any context for a process-wide default).  Keys:
    HS_OPT_KS_PIPELINE  key switching of a rotation level: 0 = automatic, 1 = one workgroup per limb
                        transform (least HBM traffic; large batches), 2 = two-pass transforms over
                        N/2048 workgroups per limb (lowest latency; small batches; always used for
@@ -339,6 +357,7 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
 #define HS_OPT_NTT_PIPE 6
 #define HS_OPT_KS_BLOCK 7
 int hs_set_option(int key, int64_t value);
+int hs_ctx_set_option(hs_ctx* ctx, int key, int64_t value);
 
 /* Autotuner.  Times, on synthetic operands and the key-switching key of `ks`, (1) the two variants
    of the one-workgroup-per-limb transforms (N = 2^14: half-limb LDS with 512 threads vs whole limb

@@ -65,7 +65,9 @@ def lib():
             "orc_decrypt": (None, [vp, u64p, u64p]),
             "orc_noise_log2": (ctypes.c_double, [vp, u64p, u64p]),
             "orc_ct_mul_plain": (None, [vp, u64p, u64p, u64p]),
-            "orc_ct_mul_ct": (None, [vp, u64p, u64p, u64p]),
+            "orc_ct_mul_ct": (ctypes.c_int, [vp, u64p, u64p, u64p]),
+            "orc_ct_tensor": (ctypes.c_int, [vp, u64p, u64p, u64p]),
+            "orc_has_tensor": (ctypes.c_int, [vp]),
             "orc_keyswitch": (None, [vp, u64p, ctypes.c_int, u64p]),
             "orc_automorph_ntt": (None, [vp, u64p, ctypes.c_uint64, u64p]),
             "orc_rotate": (None, [vp, u64p, ctypes.c_uint64, u64p]),
@@ -293,8 +295,21 @@ class Context:
         a = np.ascontiguousarray(a, np.uint64)
         b = np.ascontiguousarray(b, np.uint64)
         out = np.zeros(self.ct_size(), np.uint64)
-        lib().orc_ct_mul_ct(self.h, _p(a, u64p), _p(b, u64p), _p(out, u64p))
+        if lib().orc_ct_mul_ct(self.h, _p(a, u64p), _p(b, u64p), _p(out, u64p)) != 0:
+            raise ValueError("oracle: the primes of this ring cannot hold the exact ciphertext product")
         return out
+
+    def ct_tensor(self, a, b):
+        """The exact three-component product (d0, d1, d2) before relinearisation, [3][L][N] NTT form."""
+        a = np.ascontiguousarray(a, np.uint64)
+        b = np.ascontiguousarray(b, np.uint64)
+        out = np.zeros(3 * self.L * self.N, np.uint64)
+        if lib().orc_ct_tensor(self.h, _p(a, u64p), _p(b, u64p), _p(out, u64p)) != 0:
+            raise ValueError("oracle: the primes of this ring cannot hold the exact ciphertext product")
+        return out
+
+    def has_tensor(self):
+        return bool(lib().orc_has_tensor(self.h))
 
     def keyswitch(self, d, key_id):
         d = np.ascontiguousarray(d, np.uint64)
@@ -330,6 +345,8 @@ class Matrix:
         self.col = np.ascontiguousarray(col, np.int32)
         self.val = np.ascontiguousarray(val, np.int64)
         self.h = lib().orc_matrix_new(ctx.h, R, C, _p(self.row_ptr, i64p), _p(self.col, i32p), _p(self.val, i64p), int(encrypted), mat_seed)
+        if not self.h:
+            raise ValueError("oracle: encrypted matrix values need the exact ciphertext product, which this ring cannot hold")
 
     def __del__(self):
         if getattr(self, "h", None):

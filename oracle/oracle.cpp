@@ -386,6 +386,7 @@ struct Ctx {
   int lazy_relin = 0;            /* 1: chunks without totalSum rotations keep (d0, d1, d2) until the
                                     inter-chunk sum, relinearised once per result ciphertext */
   int n_aux = 0;                 /* extra primes for the exact ct x ct tensor */
+  bool has_tensor = false;       /* the basis product exceeds 4 N Q^2 (else no ct x ct) */
   std::vector<u64> mod;          /* [L data primes][K special primes][n_aux tensor primes] */
   std::vector<NttTable> tab;
   NttTable ttab;                 /* plaintext modulus t */
@@ -451,7 +452,9 @@ bool ctx_init(Ctx& c, int logn, int L, int qbits, int K, int pbits, u64 t, int a
   if (lazy_relin != 0 && lazy_relin != 1) return false;
   c.lazy_relin = lazy_relin;
   c.alpha = K; c.dnum = (L + K - 1) / K;
-  if (t % (2 * c.N) != 1 || !is_prime(t)) return false;
+  /* t < 2^26: the integer numerator (Q mod t) m + floor(t/2) of the scaled encoding then stays
+     far below 2^64 */
+  if (t % (2 * c.N) != 1 || !is_prime(t) || t >= (1ULL << 26)) return false;
   /* Prime choice: the primes q = 1 mod 2N below 2^b in decreasing order; the first K are the
      special primes, the next L the data primes (same width b for both), then tensor primes. */
   if (qbits != pbits) return false;
@@ -469,6 +472,8 @@ bool ctx_init(Ctx& c, int logn, int L, int qbits, int K, int pbits, u64 t, int a
   int aux = 0;
   while (bcmp(have, need) <= 0 && L + K + aux < (int)pr.size()) { have = bmulu(have, pr[L + K + aux]); aux++; }
   c.n_aux = aux;
+  /* when the primes of this width run out first, the exact products would wrap: no ct x ct */
+  c.has_tensor = bcmp(have, need) > 0;
   for (int i = 0; i < aux; i++) c.mod.push_back(pr[L + K + i]);
   total = L + K + aux;
   c.tab.resize(total);
@@ -1131,10 +1136,20 @@ void orc_ct_mul_plain(void* h, const u64* ct, const u64* pt_ntt, u64* out) {
   std::vector<u64> x(ct, ct + n), p(pt_ntt, pt_ntt + (u64)c->L * c->N);
   auto r = ct_mul_plain(*c, x, p); memcpy(out, r.data(), n * 8);
 }
-void orc_ct_mul_ct(void* h, const u64* a, const u64* b, u64* out) {
+int orc_ct_mul_ct(void* h, const u64* a, const u64* b, u64* out) {
   Ctx* c = (Ctx*)h; u64 n = 2ULL * c->L * c->N;
+  if (!c->has_tensor) return -1;
   std::vector<u64> x(a, a + n), y(b, b + n); auto r = ct_mul_ct(*c, x, y); memcpy(out, r.data(), n * 8);
+  return 0;
 }
+/* The three-component product before relinearisation, [3][L][N] NTT form. */
+int orc_ct_tensor(void* h, const u64* a, const u64* b, u64* out) {
+  Ctx* c = (Ctx*)h; u64 n = 2ULL * c->L * c->N;
+  if (!c->has_tensor) return -1;
+  std::vector<u64> x(a, a + n), y(b, b + n); auto r = ct_tensor(*c, x, y); memcpy(out, r.data(), r.size() * 8);
+  return 0;
+}
+int orc_has_tensor(void* h) { return ((Ctx*)h)->has_tensor ? 1 : 0; }
 void orc_keyswitch(void* h, const u64* d, int key_id, u64* out) {
   Ctx* c = (Ctx*)h; u64 n = (u64)c->L * c->N;
   std::vector<u64> x(d, d + n), o0, o1;
@@ -1195,6 +1210,7 @@ int orc_chunks(int Lw, const i64* CP, i64 s, int uniform, i64* out3) {
 void* orc_matrix_new(void* h, i64 R, i64 C, const i64* row_ptr, const i32* col, const i64* val,
                      int encrypted, u64 mat_seed) {
   Ctx* c = (Ctx*)h;
+  if (encrypted && !c->has_tensor) return nullptr;
   Matrix* M = new Matrix(); M->R = R; M->C = C; M->encrypted = encrypted;
   i64 s = (i64)c->N / 2;
   u64 ct_idx = 0;

@@ -130,7 +130,7 @@ __global__ void k_enc_prep(const u64* __restrict__ mcoef, const int* __restrict_
     const int* u = samples + (size_t)g * 3 * n;
     const u64 mv = mcoef[(size_t)g * n + k];
     const double d1 = mul_tw((double)mv, qdt[l].x, qdt[l].y, m);
-    // floor(((Q mod t) m + floor(t/2)) / t): the numerator is below 2^34, so the quotient of the
+    // floor(((Q mod t) m + floor(t/2)) / t): the numerator is below 2^53 (t < 2^26), so the quotient of the
     // exactly represented doubles rounds to within 2^-18 of the true one and floor is exact
     const double d2 = floor(((double)(q_mod_t * mv) + (double)(t / 2)) / (double)t);
     u64* o = out + ((size_t)g * 3 * L) * n;

@@ -21,10 +21,14 @@ const char* last_error_cstr();
 static thread_local int64_t g_counters[5] = {0, 0, 0, 0, 0};
 
 // process-wide options (hs_set_option)
-static std::atomic<int> g_opt_ks{0};    // key-switch pipeline: 0 auto, 1 one workgroup per limb, 2 two-pass
-static std::atomic<int> g_opt_ntt{0};   // hs_ntt path: 0 auto, 1 one workgroup per limb, 2 two-pass
-static std::atomic<int> g_opt_ks_threshold{512};  // auto: two-pass below this many (target x item) pairs
-static std::atomic<int> g_opt_aux{0};   // keygen/encode/encrypt/decrypt: 0 auto, 1 fused kernels, 2 split path
+// process-wide defaults of the execution options, by HS_OPT_* key (hs_set_option); a context's own
+// setting (hs_ctx_set_option) takes precedence.  Key 3 (two-pass threshold) defaults to 512.
+static std::atomic<int> g_opt[8] = {{0}, {0}, {0}, {512}, {0}, {0}, {0}, {0}};
+int option(const hs_ctx* c, int key) {
+  if (key <= 0 || key >= 8) return 0;
+  if (c && c->opt[key] >= 0) return c->opt[key];
+  return g_opt[key].load();
+}
 
 template <class F>
 static int guarded(F&& f) {
@@ -310,13 +314,13 @@ static int ks_bucket(int B) {
 }
 
 static bool use_two_pass(const hs_ctx* c, int B) {
-  const int opt = g_opt_ks.load();
+  const int opt = option(c, HS_OPT_KS_PIPELINE);
   if (!lds_limb_fits(c)) return true;
   if (opt == 1) return false;
   if (opt == 2) return true;
   const int pick = c->ks_pick[ks_bucket(B)];
   if (pick >= 0) return pick == 1;
-  return (c->L + c->K) * B < g_opt_ks_threshold.load();
+  return (c->L + c->K) * B < option(c, HS_OPT_KS_THRESHOLD);
 }
 
 // Scratch, item arrays and per-level shapes of a sequence of rotation levels (prepared on the
@@ -400,7 +404,7 @@ static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem
 static constexpr i64 kTwoPassMaxRows = 16, kTwoPassMaxRows14 = 64;  // N = 2^14: 512-element blocks
 static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int inverse, hipStream_t st, std::vector<DBuf>& hold) {
   if (rows <= 0) return;
-  const int opt = g_opt_ntt.load();
+  const int opt = option(c, HS_OPT_NTT_PATH);
   const i64 two_max = c->logn == 14 ? kTwoPassMaxRows14 : kTwoPassMaxRows;
   if (!lds_limb_fits(c) || opt == 2 || (opt == 0 && c->logn >= 12 && rows <= two_max)) {
     hold.emplace_back(&c->pool, (size_t)rows * c->N * sizeof(double));
@@ -411,11 +415,11 @@ static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int invers
 }
 
 // keygen / encoding / encryption / decryption as elementwise kernels around batched transforms
-static bool use_split(const hs_ctx* c) { return !lds_limb_fits(c) || g_opt_aux.load() == 2; }
+static bool use_split(const hs_ctx* c) { return !lds_limb_fits(c) || option(c, HS_OPT_AUX_PATH) == 2; }
 // The same choice for the vector's encoding and encryption and for decryption: from N = 16384 on
 // the split form wins (measured: its batched transforms spread a limb over two or more workgroups),
 // while the matrix's encoding keeps the fused kernels, which run on the side stream.
-static bool use_split_client(const hs_ctx* c) { return use_split(c) || (c->logn >= 14 && g_opt_aux.load() == 0); }
+static bool use_split_client(const hs_ctx* c) { return use_split(c) || (c->logn >= 14 && option(c, HS_OPT_AUX_PATH) == 0); }
 
 // Exact ciphertext products a_i x b_i (NTT form [2][L][N] each) with relinearisation: n items,
 // keys[i] = the relinearisation key of item i.  With lazy[i] set, item i is not relinearised: its
@@ -504,7 +508,7 @@ static void encrypt_coefs(hs_ctx* c, const u64* coef, const int* samples, const 
     hold.emplace_back(&c->pool, (size_t)G * 3 * c->L * c->N * sizeof(u64));
     u64* prep = hold.back().as<u64>();
     const i64 rows = (i64)G * 3 * c->L;
-    if (lds_limb_fits(c) && g_opt_ntt.load() != 2 && g_opt_aux.load() == 0 && rows > (c->logn == 14 ? kTwoPassMaxRows14 : kTwoPassMaxRows)) {
+    if (lds_limb_fits(c) && option(c, HS_OPT_NTT_PATH) != 2 && option(c, HS_OPT_AUX_PATH) == 0 && rows > (c->logn == 14 ? kTwoPassMaxRows14 : kTwoPassMaxRows)) {
       launch_enc_ntt(c, coef, samples, G, prep, st);   // the one-workgroup transforms, prologue in their input
     } else {
       launch_enc_prep(c, coef, samples, G, prep, st);
@@ -1569,6 +1573,38 @@ int hs_ct_export(const hs_ctvec* v, int64_t i, uint64_t* host_limbs, int64_t cap
   });
 }
 
+int hs_ct_export_coeff(const hs_ctvec* v, int64_t i, uint64_t* host_limbs, int64_t cap, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(v && host_limbs, HS_EINVAL, "null argument");
+    HS_REQUIRE(i >= 0 && i < v->n, HS_EINVAL, "ciphertext index out of range");
+    hs_ctx* c = v->ctx;
+    const size_t n = ct_words(c);
+    HS_REQUIRE((size_t)cap >= n, HS_ECAPACITY, "output too small");
+    const hipStream_t st = S(stream);
+    std::vector<DBuf> hold;
+    DBuf tmp(&c->pool, n * sizeof(u64));
+    HS_CHECK_HIP(hipMemcpyAsync(tmp.as<u64>(), v->d + i * n, n * sizeof(u64), hipMemcpyDeviceToDevice, st));
+    ntt_any(c, tmp.as<u64>(), 2 * c->L, c->L, 0, 1, st, hold);
+    HS_CHECK_HIP(hipMemcpyAsync(host_limbs, tmp.as<u64>(), n * sizeof(u64), hipMemcpyDeviceToHost, st));
+    HS_CHECK_HIP(hipStreamSynchronize(st));
+  });
+}
+
+int hs_ctvec_wrap(hs_ctx* c, void* dev, int64_t n, hs_ctvec** out) {
+  return guarded([&] {
+    HS_REQUIRE(c && dev && out, HS_EINVAL, "null argument");
+    HS_REQUIRE(n >= 1, HS_EINVAL, "need at least one ciphertext");
+    HS_REQUIRE(((uintptr_t)dev & 7) == 0, HS_EINVAL, "device pointer not 8-byte aligned");
+    *out = nullptr;
+    hs_ctvec* v = new hs_ctvec();
+    v->ctx = c;
+    v->n = n;
+    v->d = (u64*)dev;
+    v->owned = false;
+    *out = v;
+  });
+}
+
 int hs_ctvec_import(hs_ctx* c, const uint64_t* host_limbs, int64_t n, hs_ctvec** out) {
   return guarded([&] {
     HS_REQUIRE(c && out && (n == 0 || host_limbs) && n >= 0, HS_EINVAL, "bad argument");
@@ -1608,7 +1644,7 @@ int hs_ntt(hs_ctx* c, uint64_t* d_limbs, int64_t n_polys, int mod0, int n_limbs,
     } else {
       HS_REQUIRE(mod0 + n_limbs <= c->n_mod, HS_EINVAL, "modulus index out of range");
     }
-    const bool two = !lds_limb_fits(c) || g_opt_ntt.load() == 2;
+    const bool two = !lds_limb_fits(c) || option(c, HS_OPT_NTT_PATH) == 2;
     if (two) {
       DBuf scratch(&c->pool, (size_t)n_polys * n_limbs * c->N * sizeof(double));
       launch_ntt2(c, d_limbs, scratch.as<double>(), n_polys * n_limbs, n_limbs, m0, inverse, S(stream));
@@ -1619,40 +1655,47 @@ int hs_ntt(hs_ctx* c, uint64_t* d_limbs, int64_t n_polys, int mod0, int n_limbs,
   });
 }
 
+static void check_option(int key, int64_t value) {
+  switch (key) {
+    case HS_OPT_AUX_PATH:
+      HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "path must be 0, 1 or 2");
+      break;
+    case HS_OPT_KS_PIPELINE:
+      HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "pipeline must be 0, 1 or 2");
+      break;
+    case HS_OPT_NTT_PATH:
+      HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "path must be 0, 1 or 2");
+      break;
+    case HS_OPT_KS_BLOCK:
+      HS_REQUIRE(value >= 0 && value <= 3, HS_EINVAL, "key-switch block option must be 0, 1, 2 or 3");
+      break;
+    case HS_OPT_NTT_PIPE:
+      HS_REQUIRE(value == 0 || value == 1, HS_EINVAL, "ntt pipe option must be 0 or 1");
+      break;
+    case HS_OPT_MODUP_GROUP:
+      HS_REQUIRE(value >= 0 && value <= 3, HS_EINVAL, "group must be 0, 1, 2 or 3");
+      break;
+    case HS_OPT_KS_THRESHOLD:
+      HS_REQUIRE(value >= 0 && value < (1 << 30), HS_EINVAL, "bad threshold");
+      break;
+    default:
+      throw Error{HS_EINVAL, "unknown option"};
+  }
+}
+
 int hs_set_option(int key, int64_t value) {
   return guarded([&] {
-    switch (key) {
-      case HS_OPT_AUX_PATH:
-        HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "path must be 0, 1 or 2");
-        g_opt_aux = (int)value;
-        break;
-      case HS_OPT_KS_PIPELINE:
-        HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "pipeline must be 0, 1 or 2");
-        g_opt_ks = (int)value;
-        break;
-      case HS_OPT_NTT_PATH:
-        HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "path must be 0, 1 or 2");
-        g_opt_ntt = (int)value;
-        break;
-      case HS_OPT_KS_BLOCK:
-        HS_REQUIRE(value >= 0 && value <= 3, HS_EINVAL, "key-switch block option must be 0, 1, 2 or 3");
-        set_ks_block((int)value);
-        break;
-      case HS_OPT_NTT_PIPE:
-        HS_REQUIRE(value == 0 || value == 1, HS_EINVAL, "ntt pipe option must be 0 or 1");
-        set_ntt_pipe(value == 0);
-        break;
-      case HS_OPT_MODUP_GROUP:
-        HS_REQUIRE(value >= 0 && value <= 3, HS_EINVAL, "group must be 0, 1, 2 or 3");
-        set_modup_group((int)value);
-        break;
-      case HS_OPT_KS_THRESHOLD:
-        HS_REQUIRE(value >= 0 && value < (1 << 30), HS_EINVAL, "bad threshold");
-        g_opt_ks_threshold = (int)value;
-        break;
-      default:
-        throw Error{HS_EINVAL, "unknown option"};
-    }
+    check_option(key, value);
+    g_opt[key] = (int)value;
+  });
+}
+
+int hs_ctx_set_option(hs_ctx* c, int key, int64_t value) {
+  return guarded([&] {
+    HS_REQUIRE(c, HS_EINVAL, "null context");
+    if (value != -1) check_option(key, value);
+    else HS_REQUIRE(key > 0 && key < 8, HS_EINVAL, "unknown option");
+    c->opt[key] = (int)value;
   });
 }
 

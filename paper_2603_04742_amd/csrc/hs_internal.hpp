@@ -144,6 +144,9 @@ struct hs_ctx {
   int xf_variant = 0;
   int xf_variant_ntt = 0;
   signed char ks_pick[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  // execution options of this context (hs_ctx_set_option), by HS_OPT_* key; -1 = the process-wide
+  // default (hs_set_option)
+  int opt[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
 };
 
 struct hs_keyset {
@@ -231,6 +234,8 @@ u64 pow_mod(u64 b, u64 e, u64 m);
 u64 mul_mod(u64 a, u64 b, u64 m);
 u64 inv_mod(u64 a, u64 q);
 void build_ctx(hs_ctx* c);
+// value of execution option `key` (HS_OPT_*) for context c: its own setting, else the process-wide one
+int option(const hs_ctx* c, int key);
 void free_ctx(hs_ctx* c);
 size_t ct_words(const hs_ctx* c);
 }  // namespace hs

@@ -217,7 +217,7 @@ HS_XF_KERNEL k_enc_ntt(const u64* __restrict__ mcoef, const int* __restrict__ sa
         [=](int i) {
           const u64 mv = mc[i];
           const double d1 = mul_tw((double)mv, qd.x, qd.y, m);
-          // floor(((Q mod t) m + floor(t/2)) / t): the numerator is below 2^34, so the quotient of
+          // floor(((Q mod t) m + floor(t/2)) / t): the numerator is below 2^53 (t < 2^26), so the quotient of
           // exactly represented doubles is within 2^-18 of the true one and floor is exact
           const double d2 = floor(((double)(q_mod_t * mv) + th) / tt);
           return canon(reduce((double)e0[i] + d1 + d2, m), m);
@@ -960,8 +960,6 @@ static size_t split_lds_bytes() { return (size_t)split_lds_doubles() * sizeof(do
 
 void upload_cdt(const u64* tab20) { HS_CHECK_HIP(hipMemcpyToSymbol(HIP_SYMBOL(c_cdt), tab20, 20 * sizeof(u64))); }
 
-static std::atomic<bool> g_pipe_ntt{true};
-void set_ntt_pipe(bool on) { g_pipe_ntt = on; }
 
 static int cu_count(int device) {
   static std::atomic<int> cache[64];
@@ -977,7 +975,7 @@ static int cu_count(int device) {
 void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st) {
   if (nblocks <= 0) return;
   const i64 grid = 2 * (i64)cu_count(c->device);
-  if (c->logn == kSplitLogn && c->xf_variant_ntt == 0 && !inverse && nblocks >= 2 * grid && g_pipe_ntt.load()) {
+  if (c->logn == kSplitLogn && c->xf_variant_ntt == 0 && !inverse && nblocks >= 2 * grid && option(c, HS_OPT_NTT_PIPE) == 0) {
     // enough limbs for every workgroup of the grid to loop over at least two
     ProfScope _prof("k_ntt_fwd_pipe", st);
     ensure_lds((const void*)k_ntt_fwd_pipe, split_lds_bytes());

@@ -94,7 +94,6 @@ void launch_mask_acc(const hs_ctx* c, const u64* const* w, const u64* mask, cons
 void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, u64* D, double* ACC, double* PC, hipStream_t st);
 // two-pass (multi-workgroup) transforms and key switching (ks2.hip)
 void launch_ntt2(const hs_ctx* c, u64* data, double* scratch, i64 rows, int nl, int mod0, int inverse, hipStream_t st);
-void set_modup_group(int tg);
 void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, double* T1, double* E, double* ACC, double* T2,
                           double* F, hipStream_t st);
 

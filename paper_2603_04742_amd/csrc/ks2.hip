@@ -638,8 +638,6 @@ __global__ void __launch_bounds__(NT) k2_final_low(const RotItem* __restrict__ i
 // (three on the small-level geometry of N = 16384, whose ModUp blocks are smaller than the
 // level's; otherwise two below 5 items and three from 5 on: the shared inverse pass saves work
 // while fewer, longer workgroups cost latency).
-static std::atomic<int> g_modup_tg{0};
-void set_modup_group(int tg) { g_modup_tg = tg; }
 static std::mutex g2_mu;
 static std::map<const void*, size_t> g2_set;
 static void ensure_lds2(const void* f, size_t bytes) {
@@ -712,8 +710,6 @@ void launch_ntt2(const hs_ctx* c, u64* data, double* scratch, i64 rows, int nl, 
 // kernels (K1, K4, K5) with ModUp and the inner product on 1024 (more, shorter workgroups: the
 // kernels are latency-bound at a few items per level), 1 = 2048-element blocks throughout (K3 on
 // 1024), 2 = 1024-element blocks throughout, 0 = automatic: 3 up to kSmallLevel items, else 1.
-static std::atomic<int> g_ks_block{0};
-void set_ks_block(int mode) { g_ks_block = mode; }
 
 void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, double* T1, double* E, double* ACC, double* T2,
                           double* F, hipStream_t st) {
@@ -729,7 +725,8 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     using G2T = typename ModupGeom<GT>::type;
     // targets per ModUp workgroup: three on 1024-element blocks (the small-level geometry at
     // N = 2^14, where it measured fastest at every level size), else two below 5 items
-    const int tg = g_modup_tg.load() > 0 ? g_modup_tg.load() : ((B >= 5 || !std::is_same<G2T, GT>::value) ? 3 : 2);
+    const int tg_opt = option(c, HS_OPT_MODUP_GROUP);
+    const int tg = tg_opt > 0 ? tg_opt : ((B >= 5 || !std::is_same<G2T, GT>::value) ? 3 : 2);
     G2T G2{};
     if constexpr (std::is_same<G2T, GT>::value) G2 = G;   // a runtime geometry carries its fields
     const size_t LB2 = (size_t)lds_doubles(G2.BE) * sizeof(double);
@@ -774,7 +771,8 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
                (const double2*)c->d_pinv, S, tab, G);
   };
   constexpr int kSmallLevel = 8;
-  const int blk = g_ks_block.load() == 0 ? (B <= kSmallLevel ? 3 : 1) : g_ks_block.load();
+  const int blk_opt = option(c, HS_OPT_KS_BLOCK);
+  const int blk = blk_opt == 0 ? (B <= kSmallLevel ? 3 : 1) : blk_opt;
   if (c->logn == 14 && blk == 3) body(PassGeomC<14, 9>{});
   else if (c->logn == 14 && blk == 2) body(PassGeomC<14, 10>{});
   else with_geom(c->logn, body);

@@ -194,8 +194,10 @@ void build_ctx(hs_ctx* c) {
   c->logn = (int)p.log_n;
   c->N = 1ULL << c->logn;
   c->t = p.t;
-  HS_REQUIRE(is_prime_u64(c->t) && c->t % (2 * c->N) == 1 && c->t < (1ULL << 50), HS_EPARAM,
-             "t must be a prime < 2^50 with t = 1 mod 2N");
+  // t < 2^26 keeps (Q mod t) m + floor(t/2) of the scaled encoding below 2^53, so the encryption
+  // kernels' double quotient is exact
+  HS_REQUIRE(is_prime_u64(c->t) && c->t % (2 * c->N) == 1 && c->t < (1ULL << 26), HS_EPARAM,
+             "t must be a prime < 2^26 with t = 1 mod 2N");
   HS_REQUIRE(p.agg_mode <= 1, HS_EPARAM, "agg_mode must be 0 or 1");
   HS_REQUIRE(p.slot_rows <= 2, HS_EPARAM, "slot_rows must be 0, 1 or 2");
   HS_REQUIRE(p.relin_mode <= 1, HS_EPARAM, "relin_mode must be 0 or 1");
@@ -203,6 +205,7 @@ void build_ctx(hs_ctx* c) {
   c->K = (int)p.n_p;
   c->alpha = c->K;
   c->dnum = (c->L + c->alpha - 1) / c->alpha;
+  bool tensor_basis_ok = false;
 
   // tensor primes for the exact ct x ct: enough that prod(all) > 4 N Q^2
   std::vector<u64> pr = primes_1_mod_2n(c->N, (int)p.q_bits, c->L + c->K + 48);
@@ -225,6 +228,9 @@ void build_ctx(hs_ctx* c) {
     }
     c->n_aux = aux;
     for (int i = 0; i < aux; i++) c->mod.push_back(pr[c->L + c->K + i]);
+    // when the NTT-friendly primes of this width run out first, the basis cannot hold the exact
+    // products: the ciphertext product stays unavailable (HS_EPARAM) rather than wrap
+    tensor_basis_ok = words_cmp(words_product(have_f), need) > 0;
   }
   c->n_mod = (int)c->mod.size();
 
@@ -351,7 +357,7 @@ void build_ctx(hs_ctx* c) {
     const int kw = need <= 8 ? 8 : need <= 16 ? 16 : need <= 24 ? 24 : 0;
     const Words mu = words_pow2_div(64 * std::max(kw, 1), D);
     const int WMU = (int)mu.size();
-    if (kw && WMU <= kw) {
+    if (tensor_basis_ok && kw && WMU <= kw) {
       std::vector<double2> minv(T), r32(T);
       std::vector<u64> mhat((size_t)T * WM, 0);
       for (int i = 0; i < T; i++) {

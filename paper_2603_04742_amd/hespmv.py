@@ -65,6 +65,9 @@ SIGNATURES = {
     "hs_ctvec_count": (_int, [_vp, _i64p]),
     "hs_ct_export": (_int, [_vp, _i64, _u64p, _i64]),
     "hs_ctvec_import": (_int, [_vp, _u64p, _i64, _pp]),
+    "hs_ct_export_coeff": (_int, [_vp, _i64, _u64p, _i64, _vp]),
+    "hs_ctvec_wrap": (_int, [_vp, _vp, _i64, _pp]),
+    "hs_ctx_set_option": (_int, [_vp, _int, _i64]),
     "hs_ctvec_destroy": (None, [_vp]),
     "hs_ntt": (_int, [_vp, _vp, _i64, _int, _int, _int, _vp]),
     "hs_mul_plain": (_int, [_vp, _vp, _vp, _vp, _pp]),
@@ -168,6 +171,10 @@ class Context:
     def keygen(self, seed):
         return Keyset(self, seed)
 
+    def set_option(self, key, value):
+        """hs_ctx_set_option: this context's own setting of an execution option (-1: unset)."""
+        _check(lib.hs_ctx_set_option(self.h, key, value))
+
 
 def cdt_table():
     out = np.zeros(20, np.uint64)
@@ -215,6 +222,18 @@ class CtVec:
         _check(lib.hs_ctvec_import(ctx.h, ptr, n, ctypes.byref(h)))
         return cls(ctx, h)
 
+    @classmethod
+    def wrap(cls, ctx, tensor, n):
+        """hs_ctvec_wrap: n ciphertexts held in a caller-owned CUDA tensor (int64 view of the u64
+        limbs, [n][2][L][N]), without copying; the tensor must outlive the handle."""
+        if tensor.numel() < n * ctx.ct_words():
+            raise ValueError("tensor smaller than n ciphertexts")
+        h = ctypes.c_void_p()
+        _check(lib.hs_ctvec_wrap(ctx.h, _dptr(tensor), n, ctypes.byref(h)))
+        v = cls(ctx, h)
+        v.backing = tensor
+        return v
+
     def close(self):
         if getattr(self, "h", None) and lib is not None and getattr(self, "owner", None) is None:  # lib: None at shutdown
             lib.hs_ctvec_destroy(self.h)
@@ -239,6 +258,12 @@ class CtVec:
 
     def export_all(self):
         return np.concatenate([self.export(i) for i in range(self.count())]) if self.count() else np.zeros(0, np.uint64)
+
+    def export_coeff(self, i):
+        """Ciphertext i in coefficient form, residues in [0, q) ([2][L][N])."""
+        out = np.zeros(self.ctx.ct_words(), np.uint64)
+        _check(lib.hs_ct_export_coeff(self.h, i, out.ctypes.data_as(_u64p), out.size, _stream()))
+        return out
 
 
 class Matrix:

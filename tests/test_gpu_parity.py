@@ -358,11 +358,15 @@ def check_protocol_seeded(p, seed, w):
             _cache[(p, 7)] = saved
 
 
-@pytest.mark.parametrize("p", [(6, 3, 50, 1, 0), (8, 4, 40, 2, 0), (10, 3, 50, 2, 0), (13, 4, 50, 2, 0), (10, 12, 50, 2, 0)])
+@pytest.mark.parametrize("p", [(6, 3, 50, 1, 0), (8, 4, 40, 2, 0), (10, 3, 50, 2, 0), (13, 4, 50, 2, 0), (10, 12, 50, 2, 0),
+                               (10, 11, 50, 2, 0), (10, 14, 45, 2, 0)])
 def test_mul_ct_parity(p):
     """Exact scaled tensor + relinearisation against the oracle, bit for bit (K = 1 and K = 2
-    digits; the last two rings need the 16- and 24-word instantiations of the multiword kernels,
-    the others the 8-word one), and the product decrypts to the slot-wise product."""
+    digits).  The multiword kernels come in word capacities of 8, 16 and 24; the 24-word rings
+    cover the instance with the widths of 12 x 50-bit primes fixed at compile time (12 primes),
+    the runtime-width 24-word kernels (11 x 50-bit primes) and a ring whose CRT lift takes the fixed
+    instance while its scaled rounding takes the runtime-width one (14 x 45-bit).  The product
+    decrypts to the slot-wise product."""
     logn, L, bits, K, agg = p
     g = H.Context(logn, L, bits, K, agg_mode=agg)
     o = O.Context(logn, L, bits, K, agg_mode=agg)
@@ -407,17 +411,88 @@ def test_protocol_both_encrypted(p, pipeline):
     assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
 
 
+def test_mul_ct_refused_without_a_large_enough_basis():
+    """N = 2^14 with two 20-bit data primes: the NTT-friendly 20-bit primes run out before their
+    product exceeds 4 N Q^2, so the exact ciphertext product and encrypted matrices are refused
+    (HS_EPARAM) instead of wrapping; the same ring still runs the plaintext-matrix path."""
+    g = H.Context(14, 2, 20, 1, agg_mode=0)
+    o = O.Context(14, 2, 20, 1, agg_mode=0)
+    assert g.moduli() == o.moduli() and not o.has_tensor()
+    kg = g.keygen(3)
+    z = H.CtVec.from_host(g, np.zeros(o.ct_size(), np.uint64), 1)
+    with pytest.raises(H.HespmvError) as e:
+        H.mul_ct(g, kg, z, z)
+    assert e.value.code == H.HS_EPARAM
+    w = W.laplace256(n=8)
+    with pytest.raises(H.HespmvError) as e:
+        H.Matrix(g, w["R"], w["C"], dev(w["row_ptr"], torch.int64), dev(w["col"], torch.int32), dev(w["val"], torch.int64), True, kg, 1)
+    assert e.value.code == H.HS_EPARAM
+
+
+_lap = {}
+
+
+def _laplace_contexts(relin):
+    """Library and oracle contexts of the laplace256 ring (N = 32768, 12 x 50-bit data primes, 2
+    special primes), keys from seed 29 (the oracle's keys are made once and shared)."""
+    p = (15, 12, 50, 2)
+    if "o" not in _lap:
+        _lap["o"] = O.Context(*p, agg_mode=0)
+        _lap["o"].keygen(29)
+        _lap["o_lazy"] = O.Context(*p, agg_mode=0, lazy_relin=1)
+        _lap["o_lazy"].keygen(29)
+    if relin not in _lap:
+        g = H.Context(*p, agg_mode=0, lazy_relin=relin)
+        _lap[relin] = (g, g.keygen(29))
+    g, kg = _lap[relin]
+    return g, kg, _lap["o_lazy" if relin else "o"]
+
+
+@pytest.mark.parametrize("relin", [0, 1], ids=["eager", "lazy"])
+def test_laplace256_full_size_result_limbs(relin):
+    """The whole both-encrypted laplace256 SpMV at its full size (65536 rows, 4 partitions of 5
+    one-column chunks, N = 32768 with 12 + 2 primes), relinearising after every product (eager)
+    and once per result ciphertext (lazy): every limb of the 4 result ciphertexts equals the
+    oracle's, and the result decrypts to the integer SpMV."""
+    g, kg, o = _laplace_contexts(relin)
+    w = W.laplace256()
+    print("laplace256 full size, relin_mode %d" % relin, flush=True)
+    M = H.Matrix(g, w["R"], w["C"], dev(w["row_ptr"], torch.int64), dev(w["col"], torch.int32), dev(w["val"], torch.int64), True, kg, 31)
+    x = H.encrypt(g, kg, M, dev(w["v"], torch.int64), 41)
+    y = H.he_spmv(g, kg, M, x)
+    OM = O.Matrix(o, w["R"], w["C"], w["row_ptr"], w["col"], w["val"], True, 31)
+    assert M.info() == (OM.n_parts(), OM.n_chunks()) == (4, 20)
+    oy, _ = OM.he_spmv(OM.encrypt_vector(w["v"], 41))
+    assert np.array_equal(y.export_all(), oy)
+    out = torch.zeros(w["R"], dtype=torch.int64, device="cuda")
+    H.decrypt(g, kg, M, y, out)
+    assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
+
+
+@pytest.mark.parametrize("relin", [0, 1], ids=["eager", "lazy"])
+def test_laplace_full_ring_mixed_chunks(relin):
+    """A 64 x 64-grid Laplacian on the same N = 32768 ring: one partition whose first chunk has four
+    columns (totalSum rotations by 4096 and 8192 slots on the two-pass transforms) and whose
+    second has one (lazy relinearisation applies to it alone): every result limb against the
+    oracle."""
+    g, kg, o = _laplace_contexts(relin)
+    w = W.laplace256(n=64)
+    M = H.Matrix(g, w["R"], w["C"], dev(w["row_ptr"], torch.int64), dev(w["col"], torch.int32), dev(w["val"], torch.int64), True, kg, 32)
+    OM = O.Matrix(o, w["R"], w["C"], w["row_ptr"], w["col"], w["val"], True, 32)
+    assert [M.chunk(k)[2] for k in range(M.info()[1])] == [OM.chunk(k)[2] for k in range(OM.n_chunks())] == [4, 1]
+    x = H.encrypt(g, kg, M, dev(w["v"], torch.int64), 42)
+    y = H.he_spmv(g, kg, M, x)
+    oy, _ = OM.he_spmv(OM.encrypt_vector(w["v"], 42))
+    assert np.array_equal(y.export_all(), oy)
+
+
 def test_laplace256_full_size():
     """The both-encrypted 5-point Laplacian on a 256 x 256 grid at N = 32768 (12 x 50-bit data
     primes, 2 special): keys sampled against the oracle, the decrypted result equal to the
     integer SpMV, and the first chunk's encryption and exact product + relinearisation against
     the oracle, limb for limb."""
-    p = (15, 12, 50, 2, 0)
-    g = H.Context(*p[:4], agg_mode=0)
-    o = O.Context(*p[:4], agg_mode=0)
+    g, kg, o = _laplace_contexts(0)
     assert g.moduli() == o.moduli()
-    kg = g.keygen(29)
-    o.keygen(29)
     assert np.array_equal(kg.export(0), o.sk_ntt())
     assert np.array_equal(kg.export(2, 3), o.ksk(3))
     assert np.array_equal(kg.export(3), o.ksk(-1))

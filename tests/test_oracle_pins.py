@@ -465,6 +465,115 @@ def test_ct_times_ct_exact_tensor_definition_tiny():
     assert np.array_equal(c.decrypt(c.ct_mul_ct(cx, cy)), np.array(m, np.uint64))
 
 
+def _negint(a, b):
+    """Exact integer negacyclic product in Z[X]/(X^n + 1) (schoolbook)."""
+    n = len(a)
+    o = [0] * n
+    for i in range(n):
+        if a[i] == 0:
+            continue
+        for j in range(n):
+            if i + j < n:
+                o[i + j] += a[i] * b[j]
+            else:
+                o[i + j - n] -= a[i] * b[j]
+    return o
+
+
+@pytest.mark.parametrize("logn,L,bits,K", [(3, 2, 30, 1), (3, 3, 30, 2), (4, 2, 50, 1), (4, 3, 50, 1),
+                                           (4, 3, 50, 2), (3, 2, 50, 2)])
+def test_ct_tensor_limbs_equal_the_scaled_exact_product(logn, L, bits, K):
+    """Sec. 2.1 HE-Mult, limb by limb: every residue of the oracle's three-component product equals
+    [round(t/Q * (c0 d0, c0 d1 + c1 d0, c1 d1))]_{q_i}, where the c's and d's are the centered lifts
+    of the inputs (coefficients in (-Q/2, Q/2]), the products are exact integer negacyclic
+    convolutions and the rounding is to the nearest integer (t, Q odd: no ties).  Inputs are
+    uniform residues, so about half of every polynomial's coefficients lift to negative values and
+    the scaled products take both signs; a floor in place of the rounding, a non-centered lift or a
+    swapped cross term changes limbs here."""
+    c = O.Context(logn, L, bits, K)
+    N = c.N
+    qs = c.moduli()[:L]
+    Q = math.prod(qs)
+    g = np.random.default_rng(1000 * logn + 10 * L + K)
+    coef = [[int.from_bytes(g.bytes(32), "little") % Q for _ in range(N)] for _ in range(4)]
+    # a few coefficients at the edges of the lift: 0, (Q-1)/2 (positive), (Q+1)/2 and Q - 1 (negative)
+    coef[0][:4] = [0, (Q - 1) // 2, (Q + 1) // 2, Q - 1]
+
+    def to_ct(p0, p1):   # two coefficient-form polynomials -> [2][L][N] NTT form (pinned transform)
+        out = []
+        for poly in (p0, p1):
+            for i, q in enumerate(qs):
+                out.append(c.ntt(i, np.array([v % q for v in poly], np.uint64)))
+        return np.concatenate(out)
+
+    x, y = to_ct(coef[0], coef[1]), to_ct(coef[2], coef[3])
+    got = c.ct_tensor(x, y).reshape(3, L, N)
+    lift = [[v - Q if v > Q // 2 else v for v in poly] for poly in coef]
+    c0, c1, d0, d1 = lift
+
+    def sr(v):
+        return (2 * T * v + Q) // (2 * Q) if v >= 0 else -((2 * T * (-v) + Q) // (2 * Q))
+
+    want = [[sr(v) for v in _negint(c0, d0)],
+            [sr(a + b) for a, b in zip(_negint(c0, d1), _negint(c1, d0))],
+            [sr(v) for v in _negint(c1, d1)]]
+    for w in range(3):
+        for i, q in enumerate(qs):
+            coeff = [int(v) for v in c.intt(i, got[w, i].copy())]
+            assert coeff == [v % q for v in want[w]], (w, i)
+
+
+def test_ct_tensor_needs_a_basis_above_4nq2():
+    """The exact products need a CRT basis above 4 N Q^2; on a ring whose NTT-friendly primes of the
+    given width run out first (N = 2^14, two 20-bit data primes) the oracle refuses the product
+    instead of wrapping, while a ring with room keeps it."""
+    assert O.Context(4, 2, 30, 1).has_tensor()
+    c = O.Context(14, 2, 20, 1)
+    assert not c.has_tensor()
+    z = np.zeros(c.ct_size(), np.uint64)
+    with pytest.raises(ValueError):
+        c.ct_tensor(z, z)
+    with pytest.raises(ValueError):
+        c.ct_mul_ct(z, z)
+
+
+def test_plaintext_modulus_bound():
+    """t must be a prime = 1 mod 2N below 2^26 (the encoding's integer numerator then stays exact)."""
+    assert O.Context(3, 2, 30, 1, t=65537).L == 2
+    big = next(p for p in range((1 << 26) + 1, (1 << 26) + 10 ** 6, 16) if mr_prime(p))
+    assert big % 16 == 1
+    with pytest.raises(ValueError):
+        O.Context(3, 2, 30, 1, t=big)
+
+
+@pytest.mark.parametrize("logn,L,bits,K", [(4, 2, 30, 1), (4, 3, 50, 2), (5, 3, 30, 1)])
+def test_relinearisation_key_relation(logn, L, bits, K):
+    """The relinearisation key is a key-switching key for s^2 -> s in the hybrid form: on every
+    modulus m of the digit j, b_j + a_j s = e_j + P [s^2]_m, and on the other moduli
+    b_j + a_j s = e_j, with |e_j| <= 19 (the Gaussian tail) -- s^2 the exact negacyclic square of
+    the ternary secret, P the product of the special primes."""
+    c = small_ctx(logn=logn, L=L, bits=bits, K=K, seed=5)
+    N = c.N
+    mods = c.moduli()
+    P = math.prod(mods[L:L + K])
+    s = [int(v) for v in c.sk()]
+    s2 = _negint(s, s)
+    key = c.ksk(-1).reshape(2, c.dnum, L + K, N)
+    for j in range(c.dnum):
+        for m in range(L + K):
+            q = mods[m]
+            b = [int(v) for v in c.intt(m, key[0, j, m].copy())]
+            a = [int(v) for v in c.intt(m, key[1, j, m].copy())]
+            e = [(x + y) % q for x, y in zip(b, negacyclic(a, [v % q for v in s], q))]
+            if m < L and m // K == j:
+                e = [(x - P * v) % q for x, v in zip(e, s2)]
+            e = [v - q if v > q // 2 else v for v in e]
+            assert max(abs(v) for v in e) <= 19, (j, m)
+            # and the key is not trivially zero on the digit
+            if m < L and m // K == j:
+                assert any(v % q for v in b)
+
+
 # ----------------------------------------------------------------- CSSC (Sec. 4.3, App. B)
 def dense_from_csr(R, C, rp, col, val):
     D = np.zeros((R, C), np.int64)
