@@ -141,7 +141,8 @@ int hs_keyset_add_rotation_keys(hs_ctx* ctx, hs_keyset* ks, const int64_t* host_
    for the structure (CSSC arrays, chunks, column index); the plaintext and mask encoding of the
    plain path may still be running on the context's internal stream when the call returns, so it
    overlaps the caller's next work: every call that reads the plaintexts (hs_he_spmv, its batched,
-   graph and server forms, hs_matrix_export) waits for it first. */
+   graph and server forms, hs_matrix_export) waits for it first.  HS_EPARAM for encrypt_values = 1
+   on parameters whose tensor basis cannot hold the exact ciphertext product (hs_mul_ct). */
 int hs_cssc_pack(hs_ctx* ctx, int64_t rows, int64_t cols, const int64_t* row_ptr,
                  const int32_t* col_idx, const int64_t* vals, int encrypt_values,
                  const hs_keyset* ks, uint64_t seed, void* stream, hs_matrix** out);

@@ -717,6 +717,8 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
     HS_REQUIRE(rows >= 0 && cols >= 0 && rows < (1LL << 31) && cols < (1LL << 31), HS_EINVAL, "bad matrix shape");
     HS_REQUIRE(rows == 0 || row_ptr, HS_EINVAL, "null row_ptr");
     HS_REQUIRE(!encrypt_values || (ks && ks->ctx == c), HS_EKEY, "encrypted values need the key-set of this context");
+    HS_REQUIRE(!encrypt_values || c->has_tensor, HS_EPARAM,
+               "encrypted values need the exact ciphertext product, which these parameters do not support");
     hipStream_t st = S(stream);
     const size_t N = c->N;
     const i64 s = (i64)N / 2;
