@@ -192,6 +192,22 @@ int hs_he_spmv(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ct
 int hs_he_spmv_batch(hs_ctx* ctx, int n, const hs_keyset* const* ks, const hs_matrix* const* m,
                      const hs_ctvec* const* x, void* stream, hs_ctvec** y);
 
+/* Allocation-free form of hs_he_spmv, for callers that cannot allocate device memory (code under
+   HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same arithmetic
+   and result as hs_he_spmv, written to caller-owned device memory y (u64[y_words], 8-byte
+   aligned, on the context's device): hs_matrix_groups(m) ciphertexts [2][L][N] in NTT form, one
+   after another; wrap it with hs_ctvec_wrap to decrypt or export it.  Every intermediate buffer
+   (slot products, totalSum ciphertexts, key-switch scratch, item arrays) is a slice of one fixed
+   device array of 256 MiB that the library holds on each GPU it runs on until the process ends;
+   the call makes no device allocation and no free.  Errors: HS_ECAPACITY if y_words is below the
+   result's size; HS_ENOMEM (message: the size needed) if the call's intermediates exceed the
+   fixed array -- the single 16384 x 16384 Zipf SpMV at N = 16384 with 6 + 1 primes fits, an
+   encrypted-matrix SpMV at N = 32768 does not.  Every call on a GPU (any context, any thread)
+   shares that GPU's array and leaves its last contents there: calls that overlap in time on one
+   GPU race and must be serialised by the caller.  Returns after `stream` has drained. */
+int hs_he_spmv_noalloc(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* x,
+                       uint64_t* y, int64_t y_words, void* stream);
+
 /* Batched form recorded as a HIP graph, for a batch that is run repeatedly with new vector
    contents (same handles): hs_batch_plan_create does all host work of hs_he_spmv_batch once (chunk
    programs, rotation levels, item arrays, scratch and the result vectors), runs the batch once,

@@ -161,7 +161,8 @@ static const u64* rotation_key(const hs_keyset* ks, i64 step) {
 
 // ------------------------------------------------------------------ key generation
 static bool use_split(const hs_ctx* c);
-static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int inverse, hipStream_t st, std::vector<DBuf>& hold);
+static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int inverse, hipStream_t st, std::vector<DBuf>& hold,
+                    Alloc* al = nullptr);
 
 static u64* make_ksk(hs_ctx* c, hs_keyset* ks, u32 key_id, int sprime_mode, u32 galois, hipStream_t st) {
   const int LK = c->L + c->K;
@@ -333,7 +334,7 @@ struct LevelPlan {
   int64_t key_switches = 0, launches = 0;
 };
 
-static void prepare_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels, hipStream_t st, LevelPlan& P) {
+static void prepare_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels, hipStream_t st, LevelPlan& P, Alloc& al) {
   size_t total = 0, widest = 0;
   for (auto& l : levels) { total += l.size(); widest = std::max(widest, l.size()); }
   if (!total) return;
@@ -354,18 +355,18 @@ static void prepare_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& l
     P.launches += t ? 5 : 4;
   }
   const KsShape Smax = ks_shape(c, 1);  // the most digit groups any level uses
-  P.ditems = DBuf(&c->pool, total * sizeof(RotItem));
+  P.ditems = DBuf(&al, total * sizeof(RotItem));
   if (any1) {
-    P.D = DBuf(&c->pool, widest * c->L * N * sizeof(u64));
-    P.ACC = DBuf(&c->pool, widest * Smax.ndg * 2 * LK * N * sizeof(double));
-    P.PC = DBuf(&c->pool, widest * 2 * c->K * N * sizeof(double));
+    P.D = DBuf(&al, widest * c->L * N * sizeof(u64));
+    P.ACC = DBuf(&al, widest * Smax.ndg * 2 * LK * N * sizeof(double));
+    P.PC = DBuf(&al, widest * 2 * c->K * N * sizeof(double));
   }
   if (any2) {
-    P.T1 = DBuf(&c->pool, widest * c->L * N * sizeof(double));
-    P.E = DBuf(&c->pool, widest * c->dnum * LK * N * sizeof(double));
-    P.ACC2 = DBuf(&c->pool, widest * 2 * c->L * N * sizeof(double));
-    P.T2 = DBuf(&c->pool, widest * 2 * c->K * N * sizeof(double));
-    P.F = DBuf(&c->pool, widest * 2 * c->L * N * sizeof(double));
+    P.T1 = DBuf(&al, widest * c->L * N * sizeof(double));
+    P.E = DBuf(&al, widest * c->dnum * LK * N * sizeof(double));
+    P.ACC2 = DBuf(&al, widest * 2 * c->L * N * sizeof(double));
+    P.T2 = DBuf(&al, widest * 2 * c->K * N * sizeof(double));
+    P.F = DBuf(&al, widest * 2 * c->L * N * sizeof(double));
   }
   h2d(P.ditems.as<RotItem>(), flat.data(), flat.size(), st);
 }
@@ -385,9 +386,9 @@ static void enqueue_levels(hs_ctx* c, const LevelPlan& P, hipStream_t st) {
   }
 }
 
-static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels, hipStream_t st) {
+static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels, hipStream_t st, Alloc* al = nullptr) {
   LevelPlan P;
-  prepare_levels(c, levels, st, P);
+  prepare_levels(c, levels, st, P, al ? *al : c->pool);
   enqueue_levels(c, P, st);
   g_counters[0] += P.key_switches;
   g_counters[2] += P.launches;
@@ -402,12 +403,13 @@ static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem
 // workgroups per limb) for limbs larger than LDS and, automatically, for a handful of limbs, whose
 // one-workgroup transforms would occupy a few CUs for a whole transform's latency.
 static constexpr i64 kTwoPassMaxRows = 16, kTwoPassMaxRows14 = 64;  // N = 2^14: 512-element blocks
-static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int inverse, hipStream_t st, std::vector<DBuf>& hold) {
+static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int inverse, hipStream_t st, std::vector<DBuf>& hold,
+                    Alloc* al) {
   if (rows <= 0) return;
   const int opt = option(c, HS_OPT_NTT_PATH);
   const i64 two_max = c->logn == 14 ? kTwoPassMaxRows14 : kTwoPassMaxRows;
   if (!lds_limb_fits(c) || opt == 2 || (opt == 0 && c->logn >= 12 && rows <= two_max)) {
-    hold.emplace_back(&c->pool, (size_t)rows * c->N * sizeof(double));
+    hold.emplace_back(al ? al : &c->pool, (size_t)rows * c->N * sizeof(double));
     launch_ntt2(c, data, hold.back().as<double>(), rows, nl, mod0, inverse, st);
   } else {
     launch_ntt(c, data, rows, nl, mod0, inverse, st);
@@ -425,33 +427,34 @@ static bool use_split_client(const hs_ctx* c) { return use_split(c) || (c->logn 
 // keys[i] = the relinearisation key of item i.  With lazy[i] set, item i is not relinearised: its
 // scaled tensor goes to lazy[i] as [4][L][N] = (d0, d2, 0, d1) (out[i] is not written).
 static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const* b, u64* const* out, const u64* const* rkeys,
-                         hipStream_t st, u64* const* lazy = nullptr) {
+                         hipStream_t st, u64* const* lazy = nullptr, Alloc* al = nullptr) {
   if (n <= 0) return;
   HS_REQUIRE(c->has_tensor, HS_EPARAM, "parameters too large for the exact ciphertext product");
   const size_t N = c->N;
   const int L = c->L, T = c->n_mod;
   const size_t LN = (size_t)L * N;
+  Alloc* A = al ? al : &c->pool;
   std::vector<DBuf> hold;
-  DBuf X(&c->pool, (size_t)n * 4 * LN * sizeof(u64));
+  DBuf X(A, (size_t)n * 4 * LN * sizeof(u64));
   for (int i = 0; i < n; i++) {
     HS_CHECK_HIP(hipMemcpyAsync(X.as<u64>() + (size_t)i * 4 * LN, a[i], 2 * LN * sizeof(u64), hipMemcpyDeviceToDevice, st));
     HS_CHECK_HIP(hipMemcpyAsync(X.as<u64>() + (size_t)i * 4 * LN + 2 * LN, b[i], 2 * LN * sizeof(u64), hipMemcpyDeviceToDevice, st));
   }
-  ntt_any(c, X.as<u64>(), (i64)n * 4 * L, L, 0, 1, st, hold);
+  ntt_any(c, X.as<u64>(), (i64)n * 4 * L, L, 0, 1, st, hold, A);
   TensorConst C{};
   C.qhat_inv = (const double2*)c->d_dec_inv; C.qhat = c->d_dec_hat; C.Q = c->d_dec_q; C.halfQ = c->d_t_halfq; C.WQ = c->tq_words;
   C.mhat_inv = (const double2*)c->d_t_mhat_inv; C.mhat = c->d_t_mhat; C.M = c->d_t_m; C.halfM = c->d_t_halfm; C.WM = c->tm_words;
   C.D = c->d_t_d; C.WD = c->td_words; C.mu = c->d_t_mu; C.WMU = c->tmu_words; C.WA = c->ta_words;
   C.r32 = (const double2*)c->d_t_r32; C.T = T; C.L = L; C.t = c->t; C.kw = c->t_kw;
-  DBuf LIFT(&c->pool, (size_t)n * 4 * T * N * sizeof(u64));
+  DBuf LIFT(A, (size_t)n * 4 * T * N * sizeof(u64));
   launch_crt_lift(c, C, X.as<u64>(), LIFT.as<u64>(), n * 4, st);
-  ntt_any(c, LIFT.as<u64>(), (i64)n * 4 * T, T, 0, 0, st, hold);
-  DBuf PROD(&c->pool, (size_t)n * 3 * T * N * sizeof(u64));
+  ntt_any(c, LIFT.as<u64>(), (i64)n * 4 * T, T, 0, 0, st, hold, A);
+  DBuf PROD(A, (size_t)n * 3 * T * N * sizeof(u64));
   launch_tensor(c, LIFT.as<u64>(), PROD.as<u64>(), n, T, st);
-  ntt_any(c, PROD.as<u64>(), (i64)n * 3 * T, T, 0, 1, st, hold);
-  DBuf D4(&c->pool, (size_t)n * 4 * LN * sizeof(u64));
+  ntt_any(c, PROD.as<u64>(), (i64)n * 3 * T, T, 0, 1, st, hold, A);
+  DBuf D4(A, (size_t)n * 4 * LN * sizeof(u64));
   launch_scale_round(c, C, PROD.as<u64>(), D4.as<u64>(), n, st);
-  ntt_any(c, D4.as<u64>(), (i64)n * 4 * L, L, 0, 0, st, hold);
+  ntt_any(c, D4.as<u64>(), (i64)n * 4 * L, L, 0, 0, st, hold, A);
   std::vector<std::vector<RotItem>> lv(1);
   for (int i = 0; i < n; i++) {
     if (lazy && lazy[i]) {
@@ -466,7 +469,7 @@ static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const
     it.galois = 1;  // identity automorphism: a plain key switch of d2 under s^2 -> s
     lv[0].push_back(it);
   }
-  run_rotation_levels(c, lv, st);
+  run_rotation_levels(c, lv, st, A);
   g_counters[0] -= (int64_t)lv[0].size();  // relinearisations are not rotations
 }
 
@@ -544,6 +547,7 @@ int hs_ctx_create(const hs_params* params, hs_ctx** out) {
     c->prm = *params;
     try {
       HS_CHECK_HIP(hipGetDevice(&c->device));
+      HS_REQUIRE(noalloc_scratch(&c->na_scratch, &c->na_bytes) == HS_OK, HS_EDEVICE, "address of the fixed scratch array");
       HS_CHECK_HIP(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
       build_ctx(c);
       HS_REQUIRE(c->dec_words <= 16, HS_EPARAM, "modulus too large for the decryption kernel (at most 16 words)");
@@ -1044,9 +1048,12 @@ struct BatchWork {
   std::vector<Mask> masks;
   std::vector<DBuf> keep;
   int64_t counters[5] = {0, 0, 0, 0, 0};
+  Alloc* al = nullptr;                  // every device buffer of the call (set by prepare)
 
+  // `arena`: take every buffer from this region instead of the context's pool
   void prepare(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_matrix* const* m, const hs_ctvec* const* x, hipStream_t st,
-               hs_ctvec** y) {
+               hs_ctvec** y, Alloc* arena = nullptr) {
+    al = arena ? arena : &c->pool;
     const size_t CW = ct_words(c);
     struct Req {
       int G, nP;
@@ -1074,15 +1081,15 @@ struct BatchWork {
         q.progs[g] = total_sum_program(c, ks[r], m[r]->chunks[g].h, m[r]->chunks[g].c, &nlog);
         if (q.progs[g].size() > 1) { q.wt_base[g] = q.nwt; q.nwt += 4; }
       }
-      keep.emplace_back(&c->pool, (size_t)std::max(q.G, 1) * CW * sizeof(u64));
+      keep.emplace_back(al, (size_t)std::max(q.G, 1) * CW * sizeof(u64));
       q.vbuf = keep.back().as<u64>();
-      keep.emplace_back(&c->pool, (size_t)std::max(q.nwt, 1) * CW * sizeof(u64));
+      keep.emplace_back(al, (size_t)std::max(q.nwt, 1) * CW * sizeof(u64));
       q.wtbuf = keep.back().as<u64>();
       q.lidx.assign(q.G, -1);
       for (int g = 0; g < q.G; g++)
         if (lazy_chunk(c, m[r], g)) q.lidx[g] = q.nlazy++;
       if (q.nlazy) {
-        keep.emplace_back(&c->pool, (size_t)q.nlazy * 2 * CW * sizeof(u64));
+        keep.emplace_back(al, (size_t)q.nlazy * 2 * CW * sizeof(u64));
         q.d4 = keep.back().as<u64>();
       }
     }
@@ -1126,7 +1133,7 @@ struct BatchWork {
           it.galois = (u32)galois_step(c, op.step);
           lv_items[lv].push_back(it);
         }
-    prepare_levels(c, lv_items, st, levels);
+    prepare_levels(c, lv_items, st, levels, *al);
     counters[0] += levels.key_switches;
     counters[2] += levels.launches;
     counters[1] = nlog;
@@ -1141,9 +1148,9 @@ struct BatchWork {
     for (auto& q : rq) any_lazy |= q.nlazy > 0;
     u64* zero = nullptr;
     if (any_lazy) {
-      keep.emplace_back(&c->pool, CW * sizeof(u64));
+      keep.emplace_back(al, CW * sizeof(u64));
       zero = keep.back().as<u64>();
-      HS_CHECK_HIP(hipMemsetAsync(zero, 0, CW * sizeof(u64), st));
+      launch_fill_u64(zero, CW, 0, st);
     }
     for (int r = 0; r < n; r++) {
       Req& q = rq[r];
@@ -1167,7 +1174,7 @@ struct BatchWork {
     }
     std::vector<RotItem> relin_items;
     if (!words.empty()) {
-      keep.emplace_back(&c->pool, words.size() * sizeof(u64));
+      keep.emplace_back(al, words.size() * sizeof(u64));
       u64* dw = keep.back().as<u64>();
       h2d(dw, words.data(), words.size(), st);
       for (int r = 0; r < n; r++) {
@@ -1182,7 +1189,7 @@ struct BatchWork {
           counters[2]++;
           continue;
         }
-        keep.emplace_back(&c->pool, (size_t)q.nP * 2 * CW * sizeof(u64));
+        keep.emplace_back(al, (size_t)q.nP * 2 * CW * sizeof(u64));
         u64* LA = keep.back().as<u64>();
         u64* Y2 = LA + (size_t)q.nP * CW;
         masks.push_back(Mask{dwp, mask, dpc0, dpc0 + q.nP, Y2, q.nP});
@@ -1204,7 +1211,7 @@ struct BatchWork {
       }
     }
     if (!relin_items.empty()) {
-      prepare_levels(c, {relin_items}, st, relin);
+      prepare_levels(c, {relin_items}, st, relin, *al);
       counters[2] += relin.launches;
     }
   }
@@ -1213,7 +1220,7 @@ struct BatchWork {
 
   void enqueue(hs_ctx* c, hipStream_t st) const {
     for (const Prod& p : prods) launch_mul_plain(c, p.x, p.pt, p.out, p.G, c->L, st);
-    if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), st, lz.data());
+    if (!pa.empty()) mul_ct_batch(c, (int)pa.size(), pa.data(), pb.data(), po.data(), rk.data(), st, lz.data(), al);
     enqueue_levels(c, levels, st);
     for (const Mask& k : masks) launch_mask_acc(c, k.wp, k.mask, k.pc0, k.pnc, k.y, k.nP, st);
     enqueue_levels(c, relin, st);
@@ -1261,6 +1268,37 @@ int hs_he_spmv_batch(hs_ctx* c, int n, const hs_keyset* const* ks, const hs_matr
 }
 
 }  // extern "C"
+
+int hs_he_spmv_noalloc(hs_ctx* c, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* x, uint64_t* y, int64_t y_words,
+                       void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks && m && x && y, HS_EINVAL, "null argument");
+    HS_REQUIRE(ks->ctx == c && m->ctx == c && x->ctx == c, HS_EKEY, "handles from another context");
+    HS_REQUIRE(x->n == (i64)m->chunks.size(), HS_EINVAL, "the vector must hold one ciphertext per chunk");
+    HS_REQUIRE(((uintptr_t)y & 7) == 0, HS_EINVAL, "output pointer not 8-byte aligned");
+    const i64 need = (i64)m->groups.size() * (i64)ct_words(c);
+    HS_REQUIRE(y_words >= need, HS_ECAPACITY, "output holds " + std::to_string(y_words) + " words; the result needs " + std::to_string(need));
+    HS_REQUIRE(c->na_scratch, HS_EDEVICE, "no fixed scratch array on this device");
+    hs_ctvec out;
+    out.ctx = c;
+    out.n = (i64)m->groups.size();
+    out.d = (u64*)y;
+    out.owned = false;
+    hs_ctvec* yp = &out;
+    hipStream_t st = S(stream);
+    Arena arena(c->na_scratch, c->na_bytes);
+    BatchWork w;
+    try {
+      w.prepare(c, 1, &ks, &m, &x, st, &yp, &arena);
+      for (int i = 0; i < 5; i++) g_counters[i] = w.counters[i];
+      w.enqueue(c, st);
+    } catch (...) {
+      (void)hipStreamSynchronize(st);  // no launch of this call may still use the region after it returns
+      throw;
+    }
+    HS_CHECK_HIP(hipStreamSynchronize(st));
+  });
+}
 
 struct hs_batch_plan {
   hs_ctx* ctx = nullptr;

@@ -46,11 +46,21 @@ struct ModTab {
 // pair (w, fl(w/q)) for a constant w in [0, q)
 inline double2 make_const(u64 w, u64 q) { return double2{(double)w, (double)w / (double)q}; }
 
-// Device memory pool: size-bucketed free lists so that steady-state calls do not hipMalloc.
-class Pool {
+// Source of the device buffers of one call: the context's pool, or a fixed region (Arena).
+class Alloc {
  public:
-  void* get(size_t bytes);
-  void put(void* p);
+  virtual void* get(size_t bytes) = 0;
+  virtual void put(void* p) = 0;
+
+ protected:
+  ~Alloc() = default;
+};
+
+// Device memory pool: size-bucketed free lists so that steady-state calls do not hipMalloc.
+class Pool : public Alloc {
+ public:
+  void* get(size_t bytes) override;
+  void put(void* p) override;
   void release_all();
   ~Pool() { release_all(); }
 
@@ -60,13 +70,28 @@ class Pool {
   std::map<void*, size_t> size_of_;
 };
 
-// RAII device buffer from the pool
+// Slices of a device region that the caller owns, handed out in order (256-byte aligned) and
+// never returned: the buffers of one call of the allocation-free entry point.  get() past the end
+// throws HS_ENOMEM naming the size needed; put() does nothing.
+class Arena : public Alloc {
+ public:
+  Arena(void* base, size_t cap) : base_((char*)base), cap_(cap) {}
+  void* get(size_t bytes) override;
+  void put(void*) override {}
+  size_t used() const { return used_; }
+
+ private:
+  char* base_;
+  size_t cap_, used_ = 0;
+};
+
+// RAII device buffer from a pool or an arena
 struct DBuf {
-  Pool* pool = nullptr;
+  Alloc* pool = nullptr;
   void* p = nullptr;
   size_t bytes = 0;
   DBuf() {}
-  DBuf(Pool* pl, size_t b) : pool(pl), p(b ? pl->get(b) : nullptr), bytes(b) {}
+  DBuf(Alloc* pl, size_t b) : pool(pl), p(b ? pl->get(b) : nullptr), bytes(b) {}
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
   DBuf(DBuf&& o) noexcept { *this = std::move(o); }
@@ -147,6 +172,10 @@ struct hs_ctx {
   // execution options of this context (hs_ctx_set_option), by HS_OPT_* key; -1 = the process-wide
   // default (hs_set_option)
   int opt[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  // device address and size of the fixed scratch array on this context's device (allocation-free
+  // entry point), looked up when the context is created
+  void* na_scratch = nullptr;
+  size_t na_bytes = 0;
 };
 
 struct hs_keyset {

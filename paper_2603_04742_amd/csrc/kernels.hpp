@@ -80,6 +80,9 @@ void profile_capturing(bool on);  // calling thread is recording a graph: no tim
 std::string profile_summary();
 
 void upload_cdt(const u64* tab20);
+// fixed scratch region of the allocation-free entry point on the current device (noalloc.hip)
+int noalloc_scratch(void** ptr, size_t* bytes);
+void launch_fill_u64(u64* p, size_t n, u64 v, hipStream_t st);
 void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st);
 void launch_sample_small(const hs_ctx* c, int* out, int nobj, i64 obj_stride, u64 seed, u32 purpose, u64 index0, u64 index_step,
                          int kind, hipStream_t st);

@@ -420,6 +420,15 @@ void* Pool::get(size_t bytes) {
   size_of_[p] = bytes;
   return p;
 }
+void* Arena::get(size_t bytes) {
+  const size_t b = (bytes + 255) & ~(size_t)255;
+  if (b > cap_ - used_)
+    throw Error{HS_ENOMEM, "the fixed scratch region holds " + std::to_string(cap_) + " bytes; this call needs more than " +
+                               std::to_string(used_ + b)};
+  void* p = base_ + used_;
+  used_ += b;
+  return p;
+}
 void Pool::put(void* p) {
   std::lock_guard<std::mutex> g(mu_);
   auto it = size_of_.find(p);

@@ -67,6 +67,7 @@ SIGNATURES = {
     "hs_ctvec_import": (_int, [_vp, _u64p, _i64, _pp]),
     "hs_ct_export_coeff": (_int, [_vp, _i64, _u64p, _i64, _vp]),
     "hs_ctvec_wrap": (_int, [_vp, _vp, _i64, _pp]),
+    "hs_he_spmv_noalloc": (_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp]),
     "hs_ctx_set_option": (_int, [_vp, _int, _i64]),
     "hs_ctvec_destroy": (None, [_vp]),
     "hs_ntt": (_int, [_vp, _vp, _i64, _int, _int, _int, _vp]),
@@ -396,6 +397,14 @@ def he_spmv(ctx, ks, m, x):
     h = ctypes.c_void_p()
     _check(lib.hs_he_spmv(ctx.h, ks.h, m.h, x.h, _stream(), ctypes.byref(h)))
     return CtVec(ctx, h)
+
+
+def he_spmv_noalloc(ctx, ks, m, x, y):
+    """hs_he_spmv_noalloc: the result written into the caller's CUDA tensor y (int64 view of the
+    u64 limbs, at least m.groups() ciphertexts), intermediates in the library's fixed scratch
+    array; returns y wrapped as a vector handle (no copy)."""
+    _check(lib.hs_he_spmv_noalloc(ctx.h, ks.h, m.h, x.h, _dptr(y), y.numel(), _stream()))
+    return CtVec.wrap(ctx, y, m.groups())
 
 
 def he_spmv_batch(ctx, kss, ms, xs):
