@@ -22,21 +22,47 @@ vp = ctypes.c_void_p
 
 
 def build(force=False):
-    """Compile the oracle (plain g++, -O2; no GPU code)."""
+    """Compile the oracle (plain g++, -O2, no OpenMP; no GPU code)."""
     if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
         subprocess.check_call(["g++", "-O2", "-std=c++17", "-shared", "-fPIC", "-o", _SO, _SRC])
     return _SO
 
 
+def build_native(out_dir):
+    """Compile the same source with -O3 -march=native -fopenmp into out_dir (for timing the oracle
+    on the machine that runs it: the instruction set is that host's, so the library is built
+    there, never shipped).  Returns the library path."""
+    so = os.path.join(out_dir, "liboracle_native.so")
+    subprocess.check_call(["g++", "-O3", "-march=native", "-fopenmp", "-std=c++17", "-shared", "-fPIC", "-o", so, _SRC])
+    return so
+
+
 _lib = None
+_lib_path = None
+
+
+def use_library(path):
+    """Load the oracle from `path` (e.g. build_native's output) instead of the plain build; only
+    before the first call into the oracle in this process."""
+    global _lib_path
+    if _lib is not None and path != (_lib_path or _SO):
+        raise RuntimeError("the oracle library is already loaded in this process")
+    _lib_path = path
+
+
+def set_threads(n):
+    """Threads of the OpenMP build (the plain build always runs one); returns the count in effect."""
+    return lib().orc_set_threads(n)
 
 
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = ctypes.CDLL(_SO)
+        if _lib_path is None:
+            build()
+        L = ctypes.CDLL(_lib_path or _SO)
         sig = {
+            "orc_set_threads": (ctypes.c_int, [ctypes.c_int]),
             "orc_ctx_new": (vp, [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint64, ctypes.c_int, ctypes.c_int,
                                  ctypes.c_int]),
             "orc_ctx_free": (None, [vp]),

@@ -34,6 +34,9 @@
 #include <array>
 
 #include "cdt_sigma3p2.h"
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 typedef uint64_t u64;
 typedef uint32_t u32;
@@ -516,6 +519,7 @@ std::vector<u64> encode(const Ctx& c, const std::vector<u64>& slots) {
 /* Plaintext for ct x pt: centered lift of each coefficient (c > (t-1)/2 -> c - t), NTT mod q_i. */
 std::vector<u64> plain_ntt(const Ctx& c, const std::vector<u64>& m) {
   std::vector<u64> out((u64)c.L * c.N);
+#pragma omp parallel for schedule(dynamic)
   for (int i = 0; i < c.L; i++) {
     u64* o = limb(out, c.N, i);
     for (u64 k = 0; k < c.N; k++) {
@@ -605,6 +609,7 @@ std::vector<u64> encrypt(Ctx& c, const std::vector<u64>& m, u64 seed, u64 idx) {
   std::vector<i64> e0 = sample_gauss(seed, P_ENC_E0, idx, N);
   std::vector<i64> e1 = sample_gauss(seed, P_ENC_E1, idx, N);
   std::vector<u64> ct(2ULL * c.L * N);
+#pragma omp parallel for schedule(dynamic)
   for (int i = 0; i < c.L; i++) {
     u64 q = c.mod[i];
     std::vector<u64> un = ntt_of_int(c, u, i);
@@ -628,6 +633,7 @@ std::vector<u64> encrypt(Ctx& c, const std::vector<u64>& m, u64 seed, u64 idx) {
 std::vector<u64> phase(const Ctx& c, const std::vector<u64>& ct) {
   u64 N = c.N;
   std::vector<u64> x((u64)c.L * N);
+#pragma omp parallel for schedule(dynamic)
   for (int i = 0; i < c.L; i++) {
     u64 q = c.mod[i];
     for (u64 k = 0; k < N; k++)
@@ -643,6 +649,7 @@ std::vector<u64> decrypt(const Ctx& c, const std::vector<u64>& ct) {
   std::vector<u64> x = phase(c, ct);
   std::vector<u64> m(N);
   Big twoQ = bshl1(c.Q);
+#pragma omp parallel for schedule(dynamic, 64)
   for (u64 k = 0; k < N; k++) {
     std::vector<u64> r(c.L);
     for (int i = 0; i < c.L; i++) r[i] = x[(u64)i * N + k];
@@ -741,6 +748,7 @@ void keyswitch(const Ctx& c, const std::vector<u64>& d, const std::vector<u64>& 
                std::vector<u64>& out0, std::vector<u64>& out1) {
   u64 N = c.N; int L = c.L, K = c.K, LK = L + K;
   std::vector<u64> dc(d);
+#pragma omp parallel for schedule(dynamic)
   for (int i = 0; i < L; i++) c.tab[i].inverse(dc.data() + (u64)i * N);
   std::vector<u64> acc0((u64)LK * N, 0), acc1((u64)LK * N, 0);
   std::vector<u64> all(c.mod.begin(), c.mod.begin() + LK);
@@ -748,9 +756,10 @@ void keyswitch(const Ctx& c, const std::vector<u64>& d, const std::vector<u64>& 
     int lo = j * c.alpha, hi = std::min((j + 1) * c.alpha, L);
     std::vector<u64> src(c.mod.begin() + lo, c.mod.begin() + hi);
     BasisConv conv(src, all);
-    std::vector<u64> x(hi - lo);
+#pragma omp parallel for schedule(dynamic)
     for (int m = 0; m < LK; m++) {
       u64 q = c.mod[m];
+      std::vector<u64> x(hi - lo);
       std::vector<u64> ext(N);
       if (m >= lo && m < hi) {
         memcpy(ext.data(), d.data() + (u64)m * N, N * 8);   /* own limb: already in NTT form */
@@ -773,7 +782,6 @@ void keyswitch(const Ctx& c, const std::vector<u64>& d, const std::vector<u64>& 
   BasisConv down(psrc, qtgt);
   std::vector<u64>* accs[2] = {&acc0, &acc1};
   std::vector<u64>* outs[2] = {&out0, &out1};
-  std::vector<u64> x(K);
   for (int w = 0; w < 2; w++) {
     std::vector<u64>& acc = *accs[w];
     std::vector<u64> pc((u64)K * N);
@@ -782,8 +790,10 @@ void keyswitch(const Ctx& c, const std::vector<u64>& d, const std::vector<u64>& 
       c.tab[L + k].inverse(pc.data() + (u64)k * N);
     }
     outs[w]->assign((u64)L * N, 0);
+#pragma omp parallel for schedule(dynamic)
     for (int i = 0; i < L; i++) {
       u64 q = c.mod[i];
+      std::vector<u64> x(K);
       std::vector<u64> cv(N);
       for (u64 k = 0; k < N; k++) {
         for (int kk = 0; kk < K; kk++) x[kk] = pc[(u64)kk * N + k];
@@ -800,6 +810,7 @@ void keyswitch(const Ctx& c, const std::vector<u64>& d, const std::vector<u64>& 
 /* Automorphism of an NTT-form polynomial, carried out in the coefficient domain. */
 std::vector<u64> automorph_poly_ntt(const Ctx& c, const std::vector<u64>& a, u64 g, int nlimbs) {
   std::vector<u64> r((u64)nlimbs * c.N);
+#pragma omp parallel for schedule(dynamic)
   for (int i = 0; i < nlimbs; i++) {
     std::vector<u64> x(a.begin() + (u64)i * c.N, a.begin() + (u64)(i + 1) * c.N);
     c.tab[i].inverse(x.data());
@@ -870,11 +881,13 @@ std::vector<u64> ct_tensor(const Ctx& c, const std::vector<u64>& x, const std::v
   for (int s = 0; s < 2; s++)
     for (int p = 0; p < 2; p++) {
       std::vector<u64> cf((u64)L * N);
+#pragma omp parallel for schedule(dynamic)
       for (int i = 0; i < L; i++) {
         memcpy(cf.data() + (u64)i * N, srcs[s]->data() + ((u64)p * L + i) * N, N * 8);
         c.tab[i].inverse(cf.data() + (u64)i * N);
       }
       std::vector<u64>& out = lift[s * 2 + p];
+#pragma omp parallel for schedule(dynamic, 64)
       for (u64 k = 0; k < N; k++) {
         std::vector<u64> r(L); for (int i = 0; i < L; i++) r[i] = cf[(u64)i * N + k];
         Big X = crt(r, c.crtQ);
@@ -885,10 +898,12 @@ std::vector<u64> ct_tensor(const Ctx& c, const std::vector<u64>& x, const std::v
           out[(u64)m * N + k] = neg ? negmod(v, c.mod[m]) : v;
         }
       }
+#pragma omp parallel for schedule(dynamic)
       for (int m = 0; m < T; m++) c.tab[m].forward(out.data() + (u64)m * N);
     }
   /* exact products over the tensor basis */
   std::vector<std::vector<u64>> prod(3, std::vector<u64>((u64)T * N));
+#pragma omp parallel for schedule(dynamic)
   for (int m = 0; m < T; m++) {
     u64 q = c.mod[m];
     for (u64 k = 0; k < N; k++) {
@@ -902,7 +917,9 @@ std::vector<u64> ct_tensor(const Ctx& c, const std::vector<u64>& x, const std::v
   Big twoQ = bshl1(c.Q);
   std::vector<std::vector<u64>> d(3, std::vector<u64>((u64)L * N));
   for (int w = 0; w < 3; w++) {
+#pragma omp parallel for schedule(dynamic)
     for (int m = 0; m < T; m++) c.tab[m].inverse(prod[w].data() + (u64)m * N);
+#pragma omp parallel for schedule(dynamic, 64)
     for (u64 k = 0; k < N; k++) {
       std::vector<u64> r(T); for (int m = 0; m < T; m++) r[m] = prod[w][(u64)m * N + k];
       Big X = crt(r, c.crtT);
@@ -915,6 +932,7 @@ std::vector<u64> ct_tensor(const Ctx& c, const std::vector<u64>& x, const std::v
         d[w][(u64)i * N + k] = neg ? negmod(v, c.mod[i]) : v;
       }
     }
+#pragma omp parallel for schedule(dynamic)
     for (int i = 0; i < L; i++) c.tab[i].forward(d[w].data() + (u64)i * N);
   }
   std::vector<u64> r(3ULL * L * N);
@@ -1072,6 +1090,19 @@ struct Matrix {
 
 /* ====================================================================== C API (for tests) */
 extern "C" {
+
+/* Threads of the OpenMP build (independent limbs and coefficients split across host cores; the
+   arithmetic and its order per value are unchanged).  Returns the count in effect; the plain
+   build has no OpenMP and always returns 1. */
+int orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+  return omp_get_max_threads();
+#else
+  (void)n;
+  return 1;
+#endif
+}
 
 void* orc_ctx_new(int logn, int L, int qbits, int K, int pbits, u64 t, int agg_mode, int slot_rows, int lazy_relin) {
   Ctx* c = new Ctx();
