@@ -160,6 +160,14 @@ int hs_matrix_chunk(const hs_matrix* m, int64_t k, int64_t out4[4]);
 /* The CSSC column-index array (all partitions, concatenated) that Client A sends to Client B
    (Alg. "Sparse Matrix-Vector Multiplication"), into host memory. *len receives nnz. */
 int hs_matrix_column_index(const hs_matrix* m, int32_t* host_ci, int64_t cap, int64_t* len);
+/* The CSSC structure of row partition `part` (App. B; built on the device): the row map RM (the
+   partition's local row indices ordered by descending nonzero count, equal counts in ascending
+   row order; host int32[rows of the partition]) and the column pointers CP[0..Lw] (host
+   int64[Lw + 1], Lw = the partition's longest row; CP[j + 1] - CP[j] = rows with more than j
+   nonzeros).  lens[0], lens[1] receive the two lengths; HS_ECAPACITY if a capacity is short,
+   HS_EINVAL for a partition out of range.  Synchronises the device. */
+int hs_matrix_cssc(const hs_matrix* m, int64_t part, int32_t* host_rm, int64_t rm_cap, int64_t* host_cp,
+                   int64_t cp_cap, int64_t lens[2]);
 /* The distinct rotation steps (mod N/2, ascending) of the totalSum of every chunk of the matrix
    (Alg. Aggregation: e r and r for the chunk height r), into host memory; *len receives the count
    (HS_ECAPACITY if cap is short).  The layout is public, so a key holder can add exactly these

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libhespmv.so")
-SOURCES = ["kernels.hip", "ks2.hip", "aux2.hip", "tensor.hip", "params.cpp", "capi.cpp", "profiler.cpp", "noalloc.hip"]
+SOURCES = ["kernels.hip", "ks2.hip", "aux2.hip", "tensor.hip", "params.cpp", "capi.cpp", "profiler.cpp", "noalloc.hip", "cssc.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     "-ffp-contract=off",                      # the FP64 modular products rely on unfused rounding

@@ -726,108 +726,125 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
     hipStream_t st = S(stream);
     const size_t N = c->N;
     const i64 s = (i64)N / 2;
-    // --- structure on the host: the sparsity pattern is public (Sec. 3.1)
-    PinnedStage& down = t_stage_down;
-    i64* rp = (i64*)down.get((size_t)(rows + 1) * sizeof(i64) + 256);
-    int* hbad_p = (int*)((char*)rp + (((size_t)(rows + 1) * sizeof(i64) + 255) & ~(size_t)255));
-    *hbad_p = 0;
-    rp[0] = 0;
-    if (rows) {
-      d2h(rp, row_ptr, rows + 1, st);
-      HS_CHECK_HIP(hipStreamSynchronize(st));
-    }
-    HS_REQUIRE(rp[0] == 0, HS_EINVAL, "row_ptr[0] must be 0");
-    for (i64 i = 0; i < rows; i++) HS_REQUIRE(rp[i + 1] >= rp[i], HS_EINVAL, "row_ptr must be nondecreasing");
-    const i64 nnz = rp[rows];
-    HS_REQUIRE(nnz == 0 || (col_idx && vals), HS_EINVAL, "null col_idx/vals");
+    // --- CSSC structure on the device (App. B): row counts, the stable descending order, RM and
+    // CP.  The host reads back two words per partition (longest row, first nonzero) and, once the
+    // order is built, the CP arrays (a few words per partition), from which it cuts the chunks.
+    const i64 nP0 = rows ? (rows + s - 1) / s : 0;
+    const int BR = cssc_sort_block(s);
+    const i64 nblk = rows ? (rows + BR - 1) / BR : 0;
+    const size_t R1 = (size_t)std::max<i64>(rows, 1);
+    auto seg = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
+    const size_t nstat = 2 + 2 * (size_t)nP0;
+    // scratch: stat | counts | keys (2) | order (2) | block histograms | rank | cp_off, cp_len,
+    // nnz_off per partition
+    const size_t o_cnt = seg(nstat * 8), o_ka = o_cnt + seg(R1 * 4), o_kb = o_ka + seg(R1 * 4), o_ia = o_kb + seg(R1 * 4),
+                 o_ib = o_ia + seg(R1 * 4), o_bh = o_ib + seg(R1 * 4), o_rk = o_bh + seg((size_t)std::max<i64>(nblk, 1) * 256 * 4),
+                 o_pm = o_rk + seg(R1 * 4), scratch_bytes = o_pm + seg(3 * (size_t)std::max<i64>(nP0, 1) * 8);
     hs_matrix* M = new hs_matrix();
-    M->ctx = c; M->R = rows; M->C = cols; M->nnz = nnz; M->encrypted = encrypt_values ? 1 : 0;
+    M->ctx = c; M->R = rows; M->C = cols; M->encrypted = encrypt_values ? 1 : 0;
     std::vector<DBuf> keep;  // scratch released only after the final synchronisation
     keep.reserve(8);         // references into it stay valid
     try {
-      // the column check runs on the device while the host sorts the rows; its flag is read back
-      // with the final synchronisation (no kernel below uses a column index as an address)
+      keep.emplace_back(&c->pool, scratch_bytes);
+      char* ws = keep.back().as<char>();
+      unsigned long long* dstat = (unsigned long long*)ws;
+      int* dcnt = (int*)(ws + o_cnt);
+      int* drank = (int*)(ws + o_rk);
+      i64* dpm = (i64*)(ws + o_pm);
+      PinnedStage& down = t_stage_down;
+      u64* hstat = (u64*)down.get(nstat * 8 + 256);
+      std::fill(hstat, hstat + nstat, 0);
+      if (rows) {
+        launch_fill_u64((u64*)dstat, nstat, 0, st);
+        launch_csr_rows(row_ptr, rows, s, dcnt, dstat, st);
+        d2h(hstat, (const u64*)dstat, nstat, st);
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+      }
+      HS_REQUIRE(hstat[0] == 0, HS_EINVAL, "row_ptr must start at 0 and be nondecreasing, with at most 2^30 entries per row");
+      const i64 nnz = rows ? (i64)hstat[1] : 0;
+      M->nnz = nnz;
+      HS_REQUIRE(nnz == 0 || (col_idx && vals), HS_EINVAL, "null col_idx/vals");
+      // the column check runs on the device (row_ptr is valid now); its flag is read back with the
+      // final synchronisation (no kernel below uses a column index as an address)
+      int* hbad_p = (int*)((char*)hstat + seg(nstat * 8));
+      *hbad_p = 0;
       if (nnz) {
         keep.emplace_back(&c->pool, 256);
         int* dbad = keep.back().as<int>();
-        HS_CHECK_HIP(hipMemsetAsync(dbad, 0, sizeof(int), st));
+        launch_fill_u64((u64*)dbad, 1, 0, st);
         launch_csr_check(row_ptr, col_idx, rows, cols, dbad, st);
         d2h(hbad_p, dbad, 1, st);
       }
-      std::vector<int> rank(std::max<i64>(rows, 1));
-      std::vector<i64> part_cp_off, part_nnz_off;
-      std::vector<std::vector<i64>> cps;
-      M->h_rm.resize(rows);
-      std::vector<i64> cnt64(std::min<i64>(rows, s));
-      for (i64 r0 = 0, p = 0; r0 < rows; r0 += s, p++) {
+      // partitions, their pairing into result ciphertexts, and the CP array lengths: with two slot
+      // rows both partitions of a pair are padded to the joint width
+      const int srows = c->prm.slot_rows == 2 ? 2 : 1;
+      i64 maxLw = 0;
+      for (i64 p = 0; p < nP0; p++) {
         hs_part P{};
-        P.row0 = r0;
-        P.rows = std::min(s, rows - r0);
-        i64* cnt = cnt64.data();
-        i64 Lw = 0;
-        for (i64 i = 0; i < P.rows; i++) { cnt[i] = rp[r0 + i + 1] - rp[r0 + i]; Lw = std::max(Lw, cnt[i]); }
-        HS_REQUIRE(Lw <= (1 << 30), HS_ECAPACITY, "row too long");
-        P.Lw = (int)Lw;
-        // stable counting sort by descending count; the row map goes straight into h_rm
-        std::vector<i64> hist(Lw + 2, 0);
-        for (i64 i = 0; i < P.rows; i++) hist[cnt[i]]++;
-        std::vector<i64> startpos(Lw + 2, 0);
-        for (i64 v = Lw - 1, acc = hist[Lw]; v >= 0; v--) { startpos[v] = acc; acc += hist[v]; }
-        startpos[Lw] = 0;
-        i32* rm = M->h_rm.data() + r0;
-        for (i64 i = 0; i < P.rows; i++) {
-          const i64 pos = startpos[cnt[i]]++;
-          rm[pos] = (i32)i;
-          rank[r0 + i] = (int)pos;
-        }
-        // CP[j] = sum_{j' < j} #{rows with count > j'}
-        std::vector<i64> cp(Lw + 1, 0);
-        {
-          std::vector<i64> atleast(Lw + 2, 0);  // #rows with count >= v
-          for (i64 v = Lw; v >= 0; v--) atleast[v] = atleast[v + 1] + hist[v];
-          for (i64 j = 0; j < Lw; j++) cp[j + 1] = cp[j] + atleast[j + 1];
-        }
-        P.nz_rows = Lw > 0 ? cp[1] : 0;
-        P.nnz_off = rp[r0] - rp[0];
-        cps.push_back(std::move(cp));
+        P.row0 = p * s;
+        P.rows = std::min(s, rows - P.row0);
+        P.Lw = (int)hstat[2 + 2 * p];
+        P.nnz_off = (i64)hstat[3 + 2 * p];
+        maxLw = std::max<i64>(maxLw, P.Lw);
         M->parts.push_back(P);
       }
       const int nP = (int)M->parts.size();
+      std::vector<i64> pm(3 * (size_t)std::max(nP, 1), 0);  // cp_off | cp_len | nnz_off
+      i64 cp_total = 0;
+      for (int p = 0; p < nP; p++) {
+        const int mate = srows == 2 ? (p % 2 == 0 ? p + 1 : p - 1) : -1;
+        i64 len = (i64)M->parts[p].Lw + 1;
+        if (mate >= 0 && mate < nP) len = std::max<i64>(len, (i64)M->parts[mate].Lw + 1);
+        M->parts[p].cp_off = cp_total;
+        pm[p] = cp_total;
+        pm[nP + p] = len;
+        pm[2 * nP + p] = M->parts[p].nnz_off;
+        cp_total += len;
+      }
+      M->d_struct = pmalloc<char>(c, seg((size_t)std::max<i64>(cp_total, 1) * 8) + R1 * 4 + 4);
+      M->d_cp = (i64*)M->d_struct;
+      M->d_rm = (i32*)(M->d_struct + seg((size_t)std::max<i64>(cp_total, 1) * 8));
+      M->h_cp.assign(cp_total, 0);
+      if (nP) {
+        h2d(dpm, pm.data(), pm.size(), st);
+        int bits = 0;
+        while (bits < 63 && (maxLw >> bits) != 0) bits++;
+        const int passes = std::max(1, (bits + 7) / 8);
+        const u32* sorted = launch_cssc_order(dcnt, dstat, rows, s, passes, (u32*)(ws + o_ka), (u32*)(ws + o_kb), (int*)(ws + o_ia),
+                                              (int*)(ws + o_ib), (int*)(ws + o_bh), M->d_rm, drank, st);
+        launch_cssc_cp(sorted, dstat, rows, s, dpm, dpm + nP, M->d_cp, st);
+        d2h(M->h_cp.data(), M->d_cp, (size_t)cp_total, st);
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+      }
+      std::vector<std::vector<i64>> cps(nP);
+      for (int p = 0; p < nP; p++) {
+        hs_part& P = M->parts[p];
+        cps[p].assign(M->h_cp.begin() + P.cp_off, M->h_cp.begin() + P.cp_off + P.Lw + 1);
+        P.nz_rows = P.Lw > 0 ? cps[p][1] : 0;
+      }
       // result ciphertexts: one per partition, or (two slot rows) per pair of partitions whose
-      // chunks follow the joint column profile max(NNZ_A[j], NNZ_B[j]); each partition's CP is then
-      // padded to the joint width (columns past its own have no entries)
-      const int srows = c->prm.slot_rows == 2 ? 2 : 1;
+      // chunks follow the joint column profile max(NNZ_A[j], NNZ_B[j])
       for (int p = 0; p < nP; p += srows) {
         hs_group Gr{p, (srows == 2 && p + 1 < nP) ? p + 1 : -1, (int)M->chunks.size(), 0};
         std::vector<i64> jcp;
         if (Gr.pb >= 0) {
-          std::vector<i64>& a = cps[p];
-          std::vector<i64>& bb = cps[Gr.pb];
+          const std::vector<i64>& a = cps[p];
+          const std::vector<i64>& bb = cps[Gr.pb];
           const size_t W = std::max(a.size(), bb.size());
           jcp.assign(W, 0);
           for (size_t j = 0; j + 1 < W; j++) {
             const i64 na = j + 1 < a.size() ? a[j + 1] - a[j] : 0, nb = j + 1 < bb.size() ? bb[j + 1] - bb[j] : 0;
             jcp[j + 1] = jcp[j] + std::max(na, nb);
           }
-          a.resize(W, a.back());
-          bb.resize(W, bb.back());
         }
         std::vector<hs_chunk> ch = make_chunks(Gr.pb >= 0 ? jcp : cps[p], s, c->prm.agg_mode == 1, (int)M->groups.size());
         Gr.nchunks = (int)ch.size();
         M->chunks.insert(M->chunks.end(), ch.begin(), ch.end());
         M->groups.push_back(Gr);
       }
-      for (int p = 0; p < nP; p++) {
-        hs_part& P = M->parts[p];
-        P.cp_off = (i64)M->h_cp.size();
-        M->h_cp.insert(M->h_cp.end(), cps[p].begin(), cps[p].end());
-        part_cp_off.push_back(P.cp_off);
-        part_nnz_off.push_back(P.nnz_off);
-      }
       const int G = (int)M->chunks.size();
-      // one upload of every structure array (pinned staging, one device allocation):
-      //   cp | rm | chunk table | partition info (row0, rows, nz rows, rm offset, group, slot
-      //   offset) | rank | cp and nnz offsets per partition
+      // chunk table and partition info (row0, rows, nz rows, rm offset, group, slot offset): one
+      // pinned upload
       std::vector<i64> cd(8ULL * std::max(G, 1), 0);
       for (int g = 0; g < G; g++) {
         const hs_chunk& k = M->chunks[g];
@@ -839,36 +856,23 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         d[7] = Gr.pb >= 0 ? M->parts[Gr.pb].nnz_off : 0;
       }
       std::vector<i64> pinfo(6ULL * std::max(nP, 1), 0);
-      for (int p = 0, rm_off = 0; p < nP; p++) {
+      for (int p = 0; p < nP; p++) {
         const hs_part& P = M->parts[p];
         i64* q = &pinfo[6ULL * p];
-        q[0] = P.row0; q[1] = P.rows; q[2] = P.nz_rows; q[3] = rm_off; q[4] = p / srows; q[5] = (p % srows) * s;
-        rm_off += (int)P.rows;
+        q[0] = P.row0; q[1] = P.rows; q[2] = P.nz_rows; q[3] = P.row0; q[4] = p / srows; q[5] = (p % srows) * s;
       }
-      auto seg = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
-      const size_t o_cp = 0, o_rm = o_cp + seg(M->h_cp.size() * 8), o_ch = o_rm + seg(M->h_rm.size() * 4 + 4),
-                   o_pi = o_ch + seg(cd.size() * 8), o_rk = o_pi + seg(pinfo.size() * 8), o_po = o_rk + seg(rank.size() * 4),
-                   o_no = o_po + seg(part_cp_off.size() * 8 + 8), total = o_no + seg(part_nnz_off.size() * 8 + 8);
-      char* up = (char*)t_stage_up.get(total);
-      auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(up + off, src, bytes); };
-      put(o_cp, M->h_cp.data(), M->h_cp.size() * 8);
-      put(o_rm, M->h_rm.data(), M->h_rm.size() * 4);
-      put(o_ch, cd.data(), cd.size() * 8);
-      put(o_pi, pinfo.data(), pinfo.size() * 8);
-      put(o_rk, rank.data(), rank.size() * 4);
-      put(o_po, part_cp_off.data(), part_cp_off.size() * 8);
-      put(o_no, part_nnz_off.data(), part_nnz_off.size() * 8);
-      M->d_struct = pmalloc<char>(c, total);
-      HS_CHECK_HIP(hipMemcpyAsync(M->d_struct, up, total, hipMemcpyHostToDevice, st));
-      M->d_cp = (i64*)(M->d_struct + o_cp);
-      M->d_rm = (i32*)(M->d_struct + o_rm);
-      M->d_chunk = (i64*)(M->d_struct + o_ch);
-      M->d_pinfo = (i64*)(M->d_struct + o_pi);
+      const size_t o_pi = seg(cd.size() * 8), meta_bytes = o_pi + seg(pinfo.size() * 8);
+      char* up = (char*)t_stage_up.get(meta_bytes);
+      std::memcpy(up, cd.data(), cd.size() * 8);
+      std::memcpy(up + o_pi, pinfo.data(), pinfo.size() * 8);
+      M->d_meta = pmalloc<char>(c, meta_bytes);
+      HS_CHECK_HIP(hipMemcpyAsync(M->d_meta, up, meta_bytes, hipMemcpyHostToDevice, st));
+      M->d_chunk = (i64*)M->d_meta;
+      M->d_pinfo = (i64*)(M->d_meta + o_pi);
       M->d_va = pmalloc<i64>(c, nnz);
       M->d_ci = pmalloc<i32>(c, nnz);
       if (rows && nnz)
-        launch_cssc_scatter(row_ptr, col_idx, vals, (const int*)(M->d_struct + o_rk), M->d_cp, (const i64*)(M->d_struct + o_po),
-                            (const i64*)(M->d_struct + o_no), rows, s, M->d_va, M->d_ci, st);
+        launch_cssc_scatter(row_ptr, col_idx, vals, drank, M->d_cp, dpm, dpm + 2 * nP, rows, s, M->d_va, M->d_ci, st);
       const int hbad_dummy = 0;
       const int& hbad = nnz ? *hbad_p : hbad_dummy;
       // --- pack + encode (+ encrypt) every chunk; masks
@@ -934,7 +938,7 @@ void hs_matrix_destroy(hs_matrix* m) {
   // the memory returns to the context's pool, from which work on any stream may take it next:
   // wait for the device so no operation still in flight (an asynchronous call) uses it
   (void)hipDeviceSynchronize();
-  void* ptrs[] = {m->d_struct, m->d_va, m->d_ci, m->d_pt, m->mask_in_pt ? nullptr : m->d_mask, m->d_coef};
+  void* ptrs[] = {m->d_struct, m->d_meta, m->d_va, m->d_ci, m->d_pt, m->mask_in_pt ? nullptr : m->d_mask, m->d_coef};
   for (void* p : ptrs) pfree(m->ctx, p);
   if (m->ready) (void)hipEventDestroy(m->ready);
   delete m;
@@ -961,6 +965,20 @@ int hs_matrix_chunk(const hs_matrix* m, int64_t k, int64_t out4[4]) {
     HS_REQUIRE(k >= 0 && k < (int64_t)m->chunks.size(), HS_EINVAL, "chunk index out of range");
     const hs_chunk& c = m->chunks[k];
     out4[0] = c.part; out4[1] = c.start; out4[2] = c.c; out4[3] = c.h;
+  });
+}
+
+int hs_matrix_cssc(const hs_matrix* m, int64_t part, int32_t* host_rm, int64_t rm_cap, int64_t* host_cp, int64_t cp_cap,
+                   int64_t lens[2]) {
+  return guarded([&] {
+    HS_REQUIRE(m && lens, HS_EINVAL, "null argument");
+    HS_REQUIRE(part >= 0 && part < (i64)m->parts.size(), HS_EINVAL, "partition out of range");
+    const hs_part& P = m->parts[part];
+    lens[0] = P.rows;
+    lens[1] = (i64)P.Lw + 1;
+    HS_REQUIRE(host_rm && host_cp && rm_cap >= lens[0] && cp_cap >= lens[1], HS_ECAPACITY, "output too small");
+    HS_CHECK_HIP(hipMemcpy(host_rm, m->d_rm + P.row0, P.rows * sizeof(i32), hipMemcpyDeviceToHost));
+    for (i64 j = 0; j < lens[1]; j++) host_cp[j] = m->h_cp[P.cp_off + j];
   });
 }
 

@@ -1,0 +1,194 @@
+// CSR -> CSSC on the device (App. B, conversion from CSR to CSSC), per row partition of s rows
+// (Sec. 4.7): the nonzero count of every row, the rows ordered by descending count -- stable, so
+// equal counts keep ascending row order -- the row map RM and each row's rank in that order, and
+// the column pointers CP[j] = sum_{j' < j} #{rows with count > j'} (j = 0 .. Lw, Lw the longest
+// row).  The order is a least-significant-digit radix sort, 8 bits per pass, of the key
+// Lw_p - count over blocks of rows that never straddle a partition; a pass is a per-block digit
+// histogram, a per-partition scan of the histograms (digit-major, then block) and a stable
+// scatter (the rank of an element among the block's elements of its digit that precede it).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+
+namespace hs {
+
+// Per row: its count (clamped to [0, 2^30 + 1]); stat[0] |= 1 when row_ptr[0] != 0, a count is
+// negative or above 2^30; stat[1] = row_ptr[R]; per partition p: stat[2 + 2p] = its longest row,
+// stat[3 + 2p] = row_ptr[p s].  Reads row_ptr only (no other address comes from it).
+__global__ void k_csr_rows(const i64* __restrict__ rp, i64 R, i64 s, int* __restrict__ cnt, unsigned long long* stat) {
+  const i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  if (i >= R) return;
+  const i64 a = rp[i], b = rp[i + 1];
+  const i64 c = b - a;
+  const i64 cmax = (i64)1 << 30;
+  if ((i == 0 && a != 0) || c < 0 || c > cmax) atomicOr(&stat[0], 1ull);
+  const i64 cc = c < 0 ? 0 : (c > cmax ? cmax + 1 : c);
+  cnt[i] = (int)cc;
+  const i64 p = i / s;
+  atomicMax(&stat[2 + 2 * p], (unsigned long long)cc);
+  if (i == p * s) stat[3 + 2 * p] = (unsigned long long)a;
+  if (i == R - 1) stat[1] = (unsigned long long)b;
+}
+
+// Sort keys Lw_p - count and the identity order.
+__global__ void k_sort_init(const int* __restrict__ cnt, const unsigned long long* __restrict__ stat, i64 R, i64 s, u32* key, int* idx) {
+  const i64 i = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  if (i >= R) return;
+  const i64 lw = (i64)stat[2 + 2 * (i / s)];
+  key[i] = (u32)(lw - cnt[i]);
+  idx[i] = (int)i;
+}
+
+// Digit histogram of each block of BR positions: bh[b][d].
+__global__ void k_sort_hist(const u32* __restrict__ key, i64 R, int BR, int sh, int* bh) {
+  __shared__ int h[256];
+  const int b = blockIdx.x;
+  for (int d = threadIdx.x; d < 256; d += blockDim.x) h[d] = 0;
+  __syncthreads();
+  const i64 pos = (i64)b * BR + threadIdx.x;
+  if (threadIdx.x < BR && pos < R) atomicAdd(&h[(key[pos] >> sh) & 255], 1);
+  __syncthreads();
+  for (int d = threadIdx.x; d < 256; d += blockDim.x) bh[(size_t)b * 256 + d] = h[d];
+}
+
+// One workgroup (256 threads) per partition: bh[b][d] becomes the first destination position of
+// digit d of block b -- the partition's first row + the elements of smaller digits in the
+// partition + the elements of digit d in earlier blocks of the partition.
+__global__ void k_sort_scan(int* bh, i64 R, i64 s, int BR) {
+  __shared__ int tot[256];
+  const int p = blockIdx.x, d = threadIdx.x;
+  const i64 nblk = (R + BR - 1) / BR;
+  const i64 b0 = p * (s / BR), b1 = std::min<i64>(nblk, (p + 1) * (s / BR));
+  int t = 0;
+  for (i64 b = b0; b < b1; b++) t += bh[(size_t)b * 256 + d];
+  tot[d] = t;
+  __syncthreads();
+  if (d == 0) {
+    int run = 0;
+    for (int k = 0; k < 256; k++) {
+      const int v = tot[k];
+      tot[k] = run;
+      run += v;
+    }
+  }
+  __syncthreads();
+  int run = (int)(p * s) + tot[d];
+  for (i64 b = b0; b < b1; b++) {
+    const int v = bh[(size_t)b * 256 + d];
+    bh[(size_t)b * 256 + d] = run;
+    run += v;
+  }
+}
+
+// Stable scatter of one pass: blockDim = BR; the element at position b BR + t goes to the first
+// position of its digit in this block + the number of the block's earlier elements with that digit.
+__global__ void k_sort_scatter(const u32* __restrict__ kin, const int* __restrict__ iin, u32* kout, int* iout, const int* __restrict__ off,
+                               i64 R, int BR, int sh) {
+  __shared__ int dg[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const i64 pos = (i64)b * BR + t;
+  const bool ok = pos < R;
+  const u32 k = ok ? kin[pos] : 0u;
+  const int v = ok ? iin[pos] : 0;
+  const int d = ok ? (int)((k >> sh) & 255) : -1;
+  dg[t] = d;
+  __syncthreads();
+  if (!ok) return;
+  int rank = 0;
+  for (int u = 0; u < t; u++) rank += dg[u] == d;
+  const int dst = off[(size_t)b * 256 + d] + rank;
+  kout[dst] = k;
+  iout[dst] = v;
+}
+
+// RM[pos] = local row at sorted position pos; rank[row] = its local sorted position.
+__global__ void k_sort_finish(const int* __restrict__ idx, i64 R, i64 s, int* rm, int* rank) {
+  const i64 pos = blockIdx.x * (i64)blockDim.x + threadIdx.x;
+  if (pos >= R) return;
+  const i64 base = (pos / s) * s;
+  const int row = idx[pos];
+  rm[pos] = (int)(row - base);
+  rank[row] = (int)(pos - base);
+}
+
+// One workgroup of 256 threads per partition: CP of the partition at cp + cp_off[p], Lw + 1
+// entries, then padded with its last value up to cp_len[p] entries.  From the sorted keys: the
+// rows with count > j are the first k + 1 sorted rows for every j in [count(k + 1), count(k)), so
+// each j < Lw is written once; CP is the running sum of those numbers.
+__global__ void k_cssc_cp(const u32* __restrict__ key, const unsigned long long* __restrict__ stat, i64 R, i64 s,
+                          const i64* __restrict__ cp_off, const i64* __restrict__ cp_len, i64* cp) {
+  __shared__ i64 sc[256];
+  __shared__ i64 carry;
+  const int p = blockIdx.x, t = threadIdx.x;
+  const i64 lw = (i64)stat[2 + 2 * p];
+  const i64 base = (i64)p * s, rows = std::min<i64>(s, R - base);
+  i64* out = cp + cp_off[p];
+  for (i64 k = t; k < rows; k += blockDim.x) {
+    const i64 c = lw - key[base + k];
+    const i64 cn = k + 1 < rows ? lw - key[base + k + 1] : 0;
+    for (i64 j = cn; j < c; j++) out[1 + j] = k + 1;
+  }
+  if (t == 0) { out[0] = 0; carry = 0; }
+  __syncthreads();
+  for (i64 j0 = 0; j0 < lw; j0 += blockDim.x) {
+    const i64 j = j0 + t;
+    i64 v = j < lw ? out[1 + j] : 0;
+    sc[t] = v;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+      const i64 w = t >= o ? sc[t - o] : 0;
+      __syncthreads();
+      sc[t] += w;
+      __syncthreads();
+    }
+    if (j < lw) out[1 + j] = carry + sc[t];
+    __syncthreads();
+    if (t == (int)blockDim.x - 1) carry += sc[t];
+    __syncthreads();
+  }
+  const i64 last = out[lw];
+  for (i64 j = lw + 1 + t; j < cp_len[p]; j += blockDim.x) out[j] = last;
+}
+
+static unsigned grid_of(i64 n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_csr_rows(const i64* row_ptr, i64 R, i64 s, int* cnt, unsigned long long* stat, hipStream_t st) {
+  if (R <= 0) return;
+  ProfScope _prof("k_csr_rows", st);
+  hipLaunchKernelGGL(k_csr_rows, dim3(grid_of(R, 256)), dim3(256), 0, st, row_ptr, R, s, cnt, stat);
+  HS_CHECK_HIP(hipGetLastError());
+}
+
+int cssc_sort_block(i64 s) { return (int)std::min<i64>(256, s); }
+
+// Returns the buffer (keyA or keyB) that holds the sorted keys.
+const u32* launch_cssc_order(const int* cnt, const unsigned long long* stat, i64 R, i64 s, int passes, u32* keyA, u32* keyB, int* idxA,
+                             int* idxB, int* bh, int* rm, int* rank, hipStream_t st) {
+  if (R <= 0) return keyA;
+  const int BR = cssc_sort_block(s);
+  const i64 nblk = (R + BR - 1) / BR;
+  const int nP = (int)((R + s - 1) / s);
+  ProfScope _prof("k_cssc_order", st);
+  hipLaunchKernelGGL(k_sort_init, dim3(grid_of(R, 256)), dim3(256), 0, st, cnt, stat, R, s, keyA, idxA);
+  for (int ps = 0; ps < passes; ps++) {
+    hipLaunchKernelGGL(k_sort_hist, dim3((unsigned)nblk), dim3(BR), 0, st, keyA, R, BR, 8 * ps, bh);
+    hipLaunchKernelGGL(k_sort_scan, dim3((unsigned)nP), dim3(256), 0, st, bh, R, s, BR);
+    hipLaunchKernelGGL(k_sort_scatter, dim3((unsigned)nblk), dim3(BR), 0, st, keyA, idxA, keyB, idxB, bh, R, BR, 8 * ps);
+    std::swap(keyA, keyB);
+    std::swap(idxA, idxB);
+  }
+  hipLaunchKernelGGL(k_sort_finish, dim3(grid_of(R, 256)), dim3(256), 0, st, idxA, R, s, rm, rank);
+  HS_CHECK_HIP(hipGetLastError());
+  return keyA;
+}
+
+void launch_cssc_cp(const u32* key_sorted, const unsigned long long* stat, i64 R, i64 s, const i64* cp_off, const i64* cp_len, i64* cp,
+                    hipStream_t st) {
+  if (R <= 0) return;
+  const int nP = (int)((R + s - 1) / s);
+  ProfScope _prof("k_cssc_cp", st);
+  hipLaunchKernelGGL(k_cssc_cp, dim3((unsigned)nP), dim3(256), 0, st, key_sorted, stat, R, s, cp_off, cp_len, cp);
+  HS_CHECK_HIP(hipGetLastError());
+}
+
+}  // namespace hs

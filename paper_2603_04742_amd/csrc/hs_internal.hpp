@@ -217,9 +217,9 @@ struct hs_matrix {
   std::vector<hs_part> parts;
   std::vector<hs_group> groups;
   std::vector<hs_chunk> chunks;
-  std::vector<hs::i64> h_cp;     // all partitions' CP arrays, concatenated
-  std::vector<hs::i32> h_rm;     // row map per partition (local rows), concatenated = R entries
-  char* d_struct = nullptr;      // one allocation: d_cp, d_rm, d_chunk, d_pinfo and upload scratch
+  std::vector<hs::i64> h_cp;     // all partitions' CP arrays, concatenated (a copy of d_cp)
+  char* d_struct = nullptr;      // one allocation: d_cp, d_rm
+  char* d_meta = nullptr;        // one allocation: d_chunk, d_pinfo
   hs::i64* d_cp = nullptr;
   hs::i32* d_rm = nullptr;
   hs::i64* d_pinfo = nullptr;    // per partition: (row0, rows, nonzero rows, row-map offset, group, slot offset)

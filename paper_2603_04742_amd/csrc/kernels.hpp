@@ -120,5 +120,12 @@ void launch_decode_scatter(const hs_ctx* c, const u64* M, const int* rm, const i
 void launch_cssc_scatter(const i64* row_ptr, const int* col, const i64* val, const int* rank, const i64* cp, const i64* part_cp_off,
                          const i64* part_nnz_off, i64 R, i64 s, i64* va, int* ci, hipStream_t st);
 void launch_csr_check(const i64* row_ptr, const int* col, i64 R, i64 C, int* bad, hipStream_t st);
+// CSR -> CSSC structure on the device (cssc.hip)
+void launch_csr_rows(const i64* row_ptr, i64 R, i64 s, int* cnt, unsigned long long* stat, hipStream_t st);
+int cssc_sort_block(i64 s);
+const u32* launch_cssc_order(const int* cnt, const unsigned long long* stat, i64 R, i64 s, int passes, u32* keyA, u32* keyB, int* idxA,
+                             int* idxB, int* bh, int* rm, int* rank, hipStream_t st);
+void launch_cssc_cp(const u32* key_sorted, const unsigned long long* stat, i64 R, i64 s, const i64* cp_off, const i64* cp_len, i64* cp,
+                    hipStream_t st);
 
 }  // namespace hs

@@ -56,6 +56,7 @@ SIGNATURES = {
     "hs_matrix_info": (_int, [_vp, _i64p, _i64p]),
     "hs_matrix_chunk": (_int, [_vp, _i64, _i64p]),
     "hs_matrix_column_index": (_int, [_vp, _i32p, _i64, _i64p]),
+    "hs_matrix_cssc": (_int, [_vp, _i64, _i32p, _i64, _i64p, _i64, _i64p]),
     "hs_matrix_groups": (_int, [_vp, _i64p]),
     "hs_matrix_export": (_int, [_vp, _int, _i64, _u64p, _i64]),
     "hs_encrypt": (_int, [_vp, _vp, _vp, _vp, _i64, _u64, _vp, _pp]),
@@ -308,6 +309,15 @@ class Matrix:
         out = np.zeros(max(n.value, 1), np.int64)
         _check(lib.hs_matrix_rotation_steps(self.h, out.ctypes.data_as(_i64p), out.size, ctypes.byref(n)))
         return [int(x) for x in out[:n.value]]
+
+    def cssc(self, part):
+        """(RM, CP) of row partition `part` (local row indices; CP[0..Lw])."""
+        lens = (ctypes.c_int64 * 2)()
+        lib.hs_matrix_cssc(self.h, part, None, 0, None, 0, lens)
+        rm = np.zeros(max(lens[0], 1), np.int32)
+        cp = np.zeros(max(lens[1], 1), np.int64)
+        _check(lib.hs_matrix_cssc(self.h, part, rm.ctypes.data_as(_i32p), rm.size, cp.ctypes.data_as(_i64p), cp.size, lens))
+        return rm[:lens[0]], cp[:lens[1]]
 
     def column_index(self):
         n = ctypes.c_int64()

@@ -133,13 +133,16 @@ def check_protocol(p, w, mat_seed=31, vec_seed=41):
         if p[4] == 0:
             assert np.array_equal(M.export(1, k), OM.mask(k)), ("mask", k)
     # column index array (Client A -> Client B): the CSSC CI of every partition in order
+    # and the row map and column pointers of every partition (built on the device)
     s = (1 << p[0]) // 2
     ci = []
-    for r0 in range(0, w["R"], s):
+    for part, r0 in enumerate(range(0, w["R"], s)):
         r1 = min(w["R"], r0 + s)
         rp = w["row_ptr"][r0:r1 + 1] - w["row_ptr"][r0]
         sl = slice(w["row_ptr"][r0], w["row_ptr"][r1])
-        _, CI, _, _ = O.cssc(r1 - r0, rp, w["col"][sl], w["val"][sl])
+        _, CI, RM, CP = O.cssc(r1 - r0, rp, w["col"][sl], w["val"][sl])
+        grm, gcp = M.cssc(part)
+        assert np.array_equal(grm, RM) and np.array_equal(gcp, CP), ("cssc", part)
         ci.append(CI)
     ci = np.concatenate(ci) if ci else np.zeros(0, np.int32)
     assert np.array_equal(M.column_index(), ci)
