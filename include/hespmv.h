@@ -250,9 +250,13 @@ int hs_server_submit(hs_server* s, const hs_keyset* ks, const hs_matrix* m, cons
 /* Block until request `id` is done; *y receives its result (caller owns it).  times (optional,
    host): submit, admission and completion time in seconds since the server started. */
 int hs_server_wait(hs_server* s, int64_t id, hs_ctvec** y, double times[3]);
-/* out = [ticks, most requests active at once, admitted, completed, bytes in use]; *now (optional)
-   = seconds since the server started. */
-int hs_server_stats(hs_server* s, int64_t out[5], double* now);
+/* out = [ticks, most requests active at once, admitted, completed, bytes in use, ticks whose
+   admission left requests queued because the next one did not fit the budget, ticks that left
+   requests queued because max_active were running, requests that stayed queued through at least
+   one tick]; *now (optional) = seconds since the server started.  A request's footprint counts
+   its chunk products, totalSum buffers and results, and for an encrypted matrix the exact-product
+   scratch of the tick that admits it. */
+int hs_server_stats(hs_server* s, int64_t out[8], double* now);
 /* Drain the queue, stop the worker and free the server (results not yet collected are freed). */
 void hs_server_destroy(hs_server* s);
 

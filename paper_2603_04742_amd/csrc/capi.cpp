@@ -727,85 +727,99 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
     const size_t N = c->N;
     const i64 s = (i64)N / 2;
     // --- CSSC structure on the device (App. B): row counts, the stable descending order, RM and
-    // CP.  The host reads back two words per partition (longest row, first nonzero) and, once the
-    // order is built, the CP arrays (a few words per partition), from which it cuts the chunks.
+    // CP.  When every row holds at most 255 nonzeros (one 8-bit sort digit) the order and CP come
+    // from one histogram / scan / scatter and the host reads the partition statistics and CP back
+    // in one copy; otherwise the statistics come back first, then a multi-pass sort builds the
+    // order and CP.  The host cuts the chunks from CP (a few words per partition).
     const i64 nP0 = rows ? (rows + s - 1) / s : 0;
     const int BR = cssc_sort_block(s);
     const i64 nblk = rows ? (rows + BR - 1) / BR : 0;
     const size_t R1 = (size_t)std::max<i64>(rows, 1);
     auto seg = [](size_t bytes) { return (bytes + 255) & ~(size_t)255; };
-    const size_t nstat = 2 + 2 * (size_t)nP0;
-    // scratch: stat | counts | keys (2) | order (2) | block histograms | rank | cp_off, cp_len,
-    // nnz_off per partition
-    const size_t o_cnt = seg(nstat * 8), o_ka = o_cnt + seg(R1 * 4), o_kb = o_ka + seg(R1 * 4), o_ia = o_kb + seg(R1 * 4),
-                 o_ib = o_ia + seg(R1 * 4), o_bh = o_ib + seg(R1 * 4), o_rk = o_bh + seg((size_t)std::max<i64>(nblk, 1) * 256 * 4),
-                 o_pm = o_rk + seg(R1 * 4), scratch_bytes = o_pm + seg(3 * (size_t)std::max<i64>(nP0, 1) * 8);
     hs_matrix* M = new hs_matrix();
     M->ctx = c; M->R = rows; M->C = cols; M->encrypted = encrypt_values ? 1 : 0;
     std::vector<DBuf> keep;  // scratch released only after the final synchronisation
     keep.reserve(8);         // references into it stay valid
     try {
-      keep.emplace_back(&c->pool, scratch_bytes);
-      char* ws = keep.back().as<char>();
-      unsigned long long* dstat = (unsigned long long*)ws;
-      int* dcnt = (int*)(ws + o_cnt);
-      int* drank = (int*)(ws + o_rk);
-      i64* dpm = (i64*)(ws + o_pm);
+      const int srows = c->prm.slot_rows == 2 ? 2 : 1;
       PinnedStage& down = t_stage_down;
-      u64* hstat = (u64*)down.get(nstat * 8 + 256);
-      std::fill(hstat, hstat + nstat, 0);
+      // one-pass form; scratch: block histograms | block flags | digits | rank
+      const size_t o1_bf = seg((size_t)std::max<i64>(nblk, 1) * 256 * 4), o1_dg = o1_bf + seg((size_t)std::max<i64>(nblk, 1) * 4),
+                   o1_rk = o1_dg + seg(R1 * 4), s1_bytes = o1_rk + seg(R1 * 4);
+      const size_t hdr_bytes = seg((1 + 3 * (size_t)nP0) * 8), cp1_words = 256 * (size_t)nP0;
+      keep.emplace_back(&c->pool, s1_bytes);
+      char* w1 = keep.back().as<char>();
+      int* drank = (int*)(w1 + o1_rk);
+      M->d_struct = pmalloc<char>(c, hdr_bytes + cp1_words * 8 + R1 * 4 + 4);
+      i64* dhdr = (i64*)M->d_struct;
+      M->d_cp = (i64*)(M->d_struct + hdr_bytes);
+      M->d_rm = (i32*)(M->d_struct + hdr_bytes + cp1_words * 8);
+      i64* hh = (i64*)down.get(hdr_bytes + cp1_words * 8 + 512);
+      std::fill(hh, hh + hdr_bytes / 8, 0);
       if (rows) {
-        launch_fill_u64((u64*)dstat, nstat, 0, st);
-        launch_csr_rows(row_ptr, rows, s, dcnt, dstat, st);
-        d2h(hstat, (const u64*)dstat, nstat, st);
+        launch_cssc_one_pass(row_ptr, rows, s, (int*)(w1 + o1_dg), (int*)w1, (int*)(w1 + o1_bf), dhdr, M->d_cp, M->d_rm, drank, st);
+        d2h(hh, dhdr, hdr_bytes / 8 + cp1_words, st);
         HS_CHECK_HIP(hipStreamSynchronize(st));
       }
-      HS_REQUIRE(hstat[0] == 0, HS_EINVAL, "row_ptr must start at 0 and be nondecreasing, with at most 2^30 entries per row");
-      const i64 nnz = rows ? (i64)hstat[1] : 0;
+      i64 flags = 0;
+      for (i64 p = 0; p < nP0; p++) flags |= hh[2 + 3 * p];
+      HS_REQUIRE(!(flags & 1), HS_EINVAL, "row_ptr must start at 0 and be nondecreasing, with at most 2^30 entries per row");
+      const bool one_pass = !(flags & 2);
+      const i64 nnz = rows ? hh[0] : 0;
       M->nnz = nnz;
       HS_REQUIRE(nnz == 0 || (col_idx && vals), HS_EINVAL, "null col_idx/vals");
-      // the column check runs on the device (row_ptr is valid now); its flag is read back with the
-      // final synchronisation (no kernel below uses a column index as an address)
-      int* hbad_p = (int*)((char*)hstat + seg(nstat * 8));
-      *hbad_p = 0;
-      if (nnz) {
-        keep.emplace_back(&c->pool, 256);
-        int* dbad = keep.back().as<int>();
-        launch_fill_u64((u64*)dbad, 1, 0, st);
-        launch_csr_check(row_ptr, col_idx, rows, cols, dbad, st);
-        d2h(hbad_p, dbad, 1, st);
-      }
-      // partitions, their pairing into result ciphertexts, and the CP array lengths: with two slot
-      // rows both partitions of a pair are padded to the joint width
-      const int srows = c->prm.slot_rows == 2 ? 2 : 1;
-      i64 maxLw = 0;
       for (i64 p = 0; p < nP0; p++) {
         hs_part P{};
         P.row0 = p * s;
         P.rows = std::min(s, rows - P.row0);
-        P.Lw = (int)hstat[2 + 2 * p];
-        P.nnz_off = (i64)hstat[3 + 2 * p];
-        maxLw = std::max<i64>(maxLw, P.Lw);
+        P.Lw = (int)hh[1 + 3 * p];
+        P.nnz_off = hh[3 + 3 * p];
+        P.cp_off = p * 256;
         M->parts.push_back(P);
       }
       const int nP = (int)M->parts.size();
-      std::vector<i64> pm(3 * (size_t)std::max(nP, 1), 0);  // cp_off | cp_len | nnz_off
-      i64 cp_total = 0;
-      for (int p = 0; p < nP; p++) {
-        const int mate = srows == 2 ? (p % 2 == 0 ? p + 1 : p - 1) : -1;
-        i64 len = (i64)M->parts[p].Lw + 1;
-        if (mate >= 0 && mate < nP) len = std::max<i64>(len, (i64)M->parts[mate].Lw + 1);
-        M->parts[p].cp_off = cp_total;
-        pm[p] = cp_total;
-        pm[nP + p] = len;
-        pm[2 * nP + p] = M->parts[p].nnz_off;
-        cp_total += len;
-      }
-      M->d_struct = pmalloc<char>(c, seg((size_t)std::max<i64>(cp_total, 1) * 8) + R1 * 4 + 4);
-      M->d_cp = (i64*)M->d_struct;
-      M->d_rm = (i32*)(M->d_struct + seg((size_t)std::max<i64>(cp_total, 1) * 8));
-      M->h_cp.assign(cp_total, 0);
-      if (nP) {
+      if (one_pass) {
+        M->h_cp.assign(hh + hdr_bytes / 8, hh + hdr_bytes / 8 + cp1_words);
+      } else {
+        // multi-pass form: the statistics (longest row per partition), then the order and CP
+        const size_t nstat = 2 + 2 * (size_t)nP0;
+        const size_t o_cnt = seg(nstat * 8), o_ka = o_cnt + seg(R1 * 4), o_kb = o_ka + seg(R1 * 4), o_ia = o_kb + seg(R1 * 4),
+                     o_ib = o_ia + seg(R1 * 4), o_bh = o_ib + seg(R1 * 4), o_pm = o_bh + seg((size_t)nblk * 256 * 4),
+                     scratch_bytes = o_pm + seg(2 * (size_t)nP0 * 8);
+        keep.emplace_back(&c->pool, scratch_bytes);
+        char* ws = keep.back().as<char>();
+        unsigned long long* dstat = (unsigned long long*)ws;
+        int* dcnt = (int*)(ws + o_cnt);
+        i64* dpm = (i64*)(ws + o_pm);
+        u64* hstat = (u64*)hh;
+        launch_fill_u64((u64*)dstat, nstat, 0, st);
+        launch_csr_rows(row_ptr, rows, s, dcnt, dstat, st);
+        d2h(hstat, (const u64*)dstat, nstat, st);
+        HS_CHECK_HIP(hipStreamSynchronize(st));
+        HS_REQUIRE(hstat[0] == 0 && (i64)hstat[1] == nnz, HS_EINVAL, "malformed row_ptr");
+        i64 maxLw = 0;
+        for (int p = 0; p < nP; p++) {
+          M->parts[p].Lw = (int)hstat[2 + 2 * p];
+          maxLw = std::max<i64>(maxLw, M->parts[p].Lw);
+        }
+        // CP array lengths: with two slot rows both partitions of a pair are padded to the joint width
+        std::vector<i64> pm(2 * (size_t)std::max(nP, 1), 0);  // cp_off | cp_len
+        i64 cp_total = 0;
+        for (int p = 0; p < nP; p++) {
+          const int mate = srows == 2 ? (p % 2 == 0 ? p + 1 : p - 1) : -1;
+          i64 len = (i64)M->parts[p].Lw + 1;
+          if (mate >= 0 && mate < nP) len = std::max<i64>(len, (i64)M->parts[mate].Lw + 1);
+          M->parts[p].cp_off = cp_total;
+          pm[p] = cp_total;
+          pm[nP + p] = len;
+          cp_total += len;
+        }
+        pfree(c, M->d_struct);
+        M->d_struct = nullptr;
+        M->d_struct = pmalloc<char>(c, seg((size_t)std::max<i64>(cp_total, 1) * 8) + R1 * 4 + 4);
+        M->d_cp = (i64*)M->d_struct;
+        M->d_rm = (i32*)(M->d_struct + seg((size_t)std::max<i64>(cp_total, 1) * 8));
+        M->h_cp.assign(cp_total, 0);
         h2d(dpm, pm.data(), pm.size(), st);
         int bits = 0;
         while (bits < 63 && (maxLw >> bits) != 0) bits++;
@@ -815,6 +829,17 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         launch_cssc_cp(sorted, dstat, rows, s, dpm, dpm + nP, M->d_cp, st);
         d2h(M->h_cp.data(), M->d_cp, (size_t)cp_total, st);
         HS_CHECK_HIP(hipStreamSynchronize(st));
+      }
+      // the column check runs on the device (row_ptr is valid now); its flag is read back with the
+      // final synchronisation (no kernel below uses a column index as an address)
+      int* hbad_p = (int*)((char*)hh + hdr_bytes + cp1_words * 8 + 256);
+      *hbad_p = 0;
+      if (nnz) {
+        keep.emplace_back(&c->pool, 256);
+        int* dbad = keep.back().as<int>();
+        launch_fill_u64((u64*)dbad, 1, 0, st);
+        launch_csr_check(row_ptr, col_idx, rows, cols, dbad, st);
+        d2h(hbad_p, dbad, 1, st);
       }
       std::vector<std::vector<i64>> cps(nP);
       for (int p = 0; p < nP; p++) {
@@ -861,10 +886,13 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
         i64* q = &pinfo[6ULL * p];
         q[0] = P.row0; q[1] = P.rows; q[2] = P.nz_rows; q[3] = P.row0; q[4] = p / srows; q[5] = (p % srows) * s;
       }
-      const size_t o_pi = seg(cd.size() * 8), meta_bytes = o_pi + seg(pinfo.size() * 8);
+      std::vector<i64> poff(2 * (size_t)std::max(nP, 1), 0);  // per partition: CP offset | nonzero offset
+      for (int p = 0; p < nP; p++) { poff[p] = M->parts[p].cp_off; poff[nP + p] = M->parts[p].nnz_off; }
+      const size_t o_pi = seg(cd.size() * 8), o_po = o_pi + seg(pinfo.size() * 8), meta_bytes = o_po + seg(poff.size() * 8);
       char* up = (char*)t_stage_up.get(meta_bytes);
       std::memcpy(up, cd.data(), cd.size() * 8);
       std::memcpy(up + o_pi, pinfo.data(), pinfo.size() * 8);
+      std::memcpy(up + o_po, poff.data(), poff.size() * 8);
       M->d_meta = pmalloc<char>(c, meta_bytes);
       HS_CHECK_HIP(hipMemcpyAsync(M->d_meta, up, meta_bytes, hipMemcpyHostToDevice, st));
       M->d_chunk = (i64*)M->d_meta;
@@ -872,7 +900,8 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
       M->d_va = pmalloc<i64>(c, nnz);
       M->d_ci = pmalloc<i32>(c, nnz);
       if (rows && nnz)
-        launch_cssc_scatter(row_ptr, col_idx, vals, drank, M->d_cp, dpm, dpm + 2 * nP, rows, s, M->d_va, M->d_ci, st);
+        launch_cssc_scatter(row_ptr, col_idx, vals, drank, M->d_cp, (const i64*)(M->d_meta + o_po), (const i64*)(M->d_meta + o_po) + nP,
+                            rows, s, M->d_va, M->d_ci, st);
       const int hbad_dummy = 0;
       const int& hbad = nnz ? *hbad_p : hbad_dummy;
       // --- pack + encode (+ encrypt) every chunk; masks
@@ -2180,6 +2209,7 @@ struct SrvReq {
   std::vector<int> lidx;  // lazy relinearisation: slot of a one-column chunk's product, or -1
   DBuf d4;                // those products, [4][L][N] each
   size_t footprint = 0;
+  bool held = false;      // left in the queue by a tick's admission at least once
   double t_submit = 0, t_admit = 0, t_done = 0;
   int status = 0;  // 0 queued, 1 active, 2 done, <0 error code
   std::string err;
@@ -2201,6 +2231,7 @@ struct hs_server {
   std::thread worker;
   std::chrono::steady_clock::time_point t0;
   hs::i64 ticks = 0, max_conc = 0, admitted = 0, completed = 0;
+  hs::i64 held_budget = 0, held_slots = 0, waited = 0;  // ticks that left requests queued (budget / max_active); requests held
   double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
 };
 
@@ -2214,7 +2245,12 @@ static size_t request_footprint(const hs_ctx* c, const hs_matrix* m, int* nwt_ou
   size_t lazy = 0;  // unrelinearised products (two ciphertexts' worth each) and LA, Y2 per group
   for (int g = 0; g < (int)m->chunks.size(); g++) lazy += lazy_chunk(c, m, g) ? 2 : 0;
   if (lazy) lazy += 2 * m->groups.size();
-  return ((size_t)m->chunks.size() + nwt + m->groups.size() + lazy) * CW;
+  size_t tensor = 0;  // the exact products of an encrypted matrix: the scratch of its admission tick
+  if (m->encrypted) {
+    const size_t per = (size_t)(8 * c->L + 7 * c->n_mod) * c->N * sizeof(u64);
+    tensor = m->chunks.size() * per * (lds_limb_fits(c) ? 1 : 2);  // two-pass transforms: as much again
+  }
+  return ((size_t)m->chunks.size() + nwt + m->groups.size() + lazy) * CW + tensor;
 }
 
 static void server_tick(hs_server* S) {
@@ -2223,9 +2259,11 @@ static void server_tick(hs_server* S) {
   std::vector<std::shared_ptr<SrvReq>> fresh;
   {
     std::unique_lock<std::mutex> lk(S->mu);
-    while (!S->queue.empty() && (int)S->active.size() < S->max_active) {
+    int held = 0;  // 1: the budget, 2: max_active left requests in the queue
+    while (!S->queue.empty()) {
+      if ((int)S->active.size() >= S->max_active) { held = 2; break; }
       auto& r = S->queue.front();
-      if (!S->active.empty() && S->used + r->footprint > S->budget) break;  // admission by footprint
+      if (!S->active.empty() && S->used + r->footprint > S->budget) { held = 1; break; }  // admission by footprint
       S->used += r->footprint;
       r->status = 1;
       r->t_admit = S->now();
@@ -2233,6 +2271,11 @@ static void server_tick(hs_server* S) {
       fresh.push_back(r);
       S->queue.pop_front();
       S->admitted++;
+    }
+    if (held) {
+      (held == 1 ? S->held_budget : S->held_slots)++;
+      for (auto& q : S->queue)
+        if (!q->held) { q->held = true; S->waited++; }
     }
     S->max_conc = std::max<i64>(S->max_conc, (i64)S->active.size());
   }
@@ -2477,11 +2520,12 @@ int hs_server_wait(hs_server* S, int64_t id, hs_ctvec** y, double times[3]) {
   });
 }
 
-int hs_server_stats(hs_server* S, int64_t out[5], double* now) {
+int hs_server_stats(hs_server* S, int64_t out[8], double* now) {
   return guarded([&] {
     HS_REQUIRE(S && out, HS_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(S->mu);
     out[0] = S->ticks; out[1] = S->max_conc; out[2] = S->admitted; out[3] = S->completed; out[4] = (int64_t)S->used;
+    out[5] = S->held_budget; out[6] = S->held_slots; out[7] = S->waited;
     if (now) *now = S->now();
   });
 }

@@ -12,6 +12,8 @@
 
 namespace hs {
 
+int cssc_sort_block(i64 s) { return (int)std::min<i64>(256, s); }
+
 // Per row: its count (clamped to [0, 2^30 + 1]); stat[0] |= 1 when row_ptr[0] != 0, a count is
 // negative or above 2^30; stat[1] = row_ptr[R]; per partition p: stat[2 + 2p] = its longest row,
 // stat[3 + 2p] = row_ptr[p s].  Reads row_ptr only (no other address comes from it).
@@ -150,7 +152,118 @@ __global__ void k_cssc_cp(const u32* __restrict__ key, const unsigned long long*
   for (i64 j = lw + 1 + t; j < cp_len[p]; j += blockDim.x) out[j] = last;
 }
 
+// ---- one-pass form, for partitions whose rows hold at most 255 nonzeros (the common case): the
+// key 255 - count fits one 8-bit digit, so one histogram / scan / scatter orders the rows, and
+// CP follows from the partition's histogram; the host reads the statistics and CP in one copy.
+// hdr (i64): [0] row_ptr[R], then per partition p: [1 + 3p] longest row, [2 + 3p] flags (1: a
+// malformed row pointer, 2: a row longer than 255), [3 + 3p] row_ptr[p s].  cp: 256 entries per
+// partition (CP[0..Lw], then its last value repeated).
+
+// Blocks of BR rows (one partition each): the digit of every row, the block's digit histogram
+// and flags, row_ptr at the partition starts and at R.
+__global__ void k_cssc_rows1(const i64* __restrict__ rp, i64 R, i64 s, int BR, int* __restrict__ dig, int* __restrict__ bh,
+                             int* __restrict__ bflag, i64* __restrict__ hdr) {
+  __shared__ int h[256];
+  __shared__ int fl;
+  const int b = blockIdx.x, t = threadIdx.x;
+  for (int d = t; d < 256; d += blockDim.x) h[d] = 0;
+  if (t == 0) fl = 0;
+  __syncthreads();
+  const i64 i = (i64)b * BR + t;
+  if (i < R) {
+    const i64 a = rp[i], e = rp[i + 1];
+    const i64 c = e - a;
+    int f = ((i == 0 && a != 0) || c < 0 || c > ((i64)1 << 30)) ? 1 : 0;
+    if (c > 255) f |= 2;
+    if (f) atomicOr(&fl, f);
+    const int d = 255 - (int)(c < 0 ? 0 : (c > 255 ? 255 : c));
+    dig[i] = d;
+    atomicAdd(&h[d], 1);
+    const i64 p = i / s;
+    if (i == p * s) hdr[3 + 3 * p] = a;
+    if (i == R - 1) hdr[0] = e;
+  }
+  __syncthreads();
+  for (int d = t; d < 256; d += blockDim.x) bh[(size_t)b * 256 + d] = h[d];
+  if (t == 0) bflag[b] = fl;
+}
+
+// One workgroup of 256 threads per partition: the partition's histogram tot[d] and flags; bh[b][d]
+// becomes the first destination of digit d of block b (as k_sort_scan); CP[j + 1] - CP[j] = rows
+// with count > j = rows with digit < 255 - j = the exclusive prefix of tot at 255 - j.
+__global__ void k_cssc_scan1(int* bh, const int* __restrict__ bflag, i64 R, i64 s, int BR, i64* hdr, i64* cp) {
+  __shared__ int tot[256];
+  __shared__ int fl;
+  const int p = blockIdx.x, d = threadIdx.x;
+  const i64 nblk = (R + BR - 1) / BR;
+  const i64 b0 = p * (s / BR), b1 = std::min<i64>(nblk, (p + 1) * (s / BR));
+  if (d == 0) fl = 0;
+  __syncthreads();
+  int t = 0, f = 0;
+  for (i64 b = b0; b < b1; b++) t += bh[(size_t)b * 256 + d];
+  for (i64 b = b0 + d; b < b1; b += 256) f |= bflag[b];
+  if (f) atomicOr(&fl, f);
+  tot[d] = t;
+  __syncthreads();
+  if (d == 0) {
+    int dmin = 255;   // the smallest digit present (the longest row); 255 when every row is empty
+    for (int k = 0; k < 255; k++)
+      if (tot[k]) { dmin = k; break; }
+    int run = 0;
+    for (int k = 0; k < 256; k++) {
+      const int v = tot[k];
+      tot[k] = run;
+      run += v;
+    }
+    const i64 lw = 255 - dmin;
+    i64* out = cp + (size_t)p * 256;
+    out[0] = 0;
+    for (i64 j = 0; j < lw; j++) out[j + 1] = out[j] + tot[255 - j];
+    for (i64 j = lw + 1; j < 256; j++) out[j] = out[lw];
+    hdr[1 + 3 * p] = lw;
+    hdr[2 + 3 * p] = fl;
+  }
+  __syncthreads();
+  int run = (int)(p * s) + tot[d];
+  for (i64 b = b0; b < b1; b++) {
+    const int v = bh[(size_t)b * 256 + d];
+    bh[(size_t)b * 256 + d] = run;
+    run += v;
+  }
+}
+
+// The scatter of the one pass (rows in their original order): RM and each row's rank.
+__global__ void k_cssc_scatter1(const int* __restrict__ dig, const int* __restrict__ off, i64 R, i64 s, int BR, int* rm, int* rank) {
+  __shared__ int dg[256];
+  const int b = blockIdx.x, t = threadIdx.x;
+  const i64 i = (i64)b * BR + t;
+  const bool ok = i < R;
+  const int d = ok ? dig[i] : -1;
+  dg[t] = d;
+  __syncthreads();
+  if (!ok) return;
+  int r = 0;
+  for (int u = 0; u < t; u++) r += dg[u] == d;
+  const i64 dst = off[(size_t)b * 256 + d] + r;
+  const i64 base = (i / s) * s;
+  rm[dst] = (int)(i - base);
+  rank[i] = (int)(dst - base);
+}
+
 static unsigned grid_of(i64 n, int bs) { return (unsigned)((n + bs - 1) / bs); }
+
+void launch_cssc_one_pass(const i64* row_ptr, i64 R, i64 s, int* dig, int* bh, int* bflag, i64* hdr, i64* cp, int* rm, int* rank,
+                          hipStream_t st) {
+  if (R <= 0) return;
+  const int BR = cssc_sort_block(s);
+  const i64 nblk = (R + BR - 1) / BR;
+  const int nP = (int)((R + s - 1) / s);
+  ProfScope _prof("k_cssc_one_pass", st);
+  hipLaunchKernelGGL(k_cssc_rows1, dim3((unsigned)nblk), dim3(BR), 0, st, row_ptr, R, s, BR, dig, bh, bflag, hdr);
+  hipLaunchKernelGGL(k_cssc_scan1, dim3((unsigned)nP), dim3(256), 0, st, bh, bflag, R, s, BR, hdr, cp);
+  hipLaunchKernelGGL(k_cssc_scatter1, dim3((unsigned)nblk), dim3(BR), 0, st, dig, bh, R, s, BR, rm, rank);
+  HS_CHECK_HIP(hipGetLastError());
+}
 
 void launch_csr_rows(const i64* row_ptr, i64 R, i64 s, int* cnt, unsigned long long* stat, hipStream_t st) {
   if (R <= 0) return;
@@ -158,8 +271,6 @@ void launch_csr_rows(const i64* row_ptr, i64 R, i64 s, int* cnt, unsigned long l
   hipLaunchKernelGGL(k_csr_rows, dim3(grid_of(R, 256)), dim3(256), 0, st, row_ptr, R, s, cnt, stat);
   HS_CHECK_HIP(hipGetLastError());
 }
-
-int cssc_sort_block(i64 s) { return (int)std::min<i64>(256, s); }
 
 // Returns the buffer (keyA or keyB) that holds the sorted keys.
 const u32* launch_cssc_order(const int* cnt, const unsigned long long* stat, i64 R, i64 s, int passes, u32* keyA, u32* keyB, int* idxA,

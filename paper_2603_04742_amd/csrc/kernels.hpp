@@ -123,6 +123,8 @@ void launch_csr_check(const i64* row_ptr, const int* col, i64 R, i64 C, int* bad
 // CSR -> CSSC structure on the device (cssc.hip)
 void launch_csr_rows(const i64* row_ptr, i64 R, i64 s, int* cnt, unsigned long long* stat, hipStream_t st);
 int cssc_sort_block(i64 s);
+void launch_cssc_one_pass(const i64* row_ptr, i64 R, i64 s, int* dig, int* bh, int* bflag, i64* hdr, i64* cp, int* rm, int* rank,
+                          hipStream_t st);
 const u32* launch_cssc_order(const int* cnt, const unsigned long long* stat, i64 R, i64 s, int passes, u32* keyA, u32* keyB, int* idxA,
                              int* idxB, int* bh, int* rm, int* rank, hipStream_t st);
 void launch_cssc_cp(const u32* key_sorted, const unsigned long long* stat, i64 R, i64 s, const i64* cp_off, const i64* cp_len, i64* cp,

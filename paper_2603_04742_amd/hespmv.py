@@ -559,10 +559,11 @@ class Server:
         return CtVec(self.ctx, y), (t[0], t[1], t[2])
 
     def stats(self):
-        out = np.zeros(5, np.int64)
+        out = np.zeros(8, np.int64)
         now = ctypes.c_double()
         _check(lib.hs_server_stats(self.h, out.ctypes.data_as(_i64p), ctypes.byref(now)))
-        return dict(zip(["ticks", "max_active", "admitted", "completed", "bytes_in_use"], (int(v) for v in out)), now=now.value)
+        return dict(zip(["ticks", "max_active", "admitted", "completed", "bytes_in_use", "held_by_budget", "held_by_slots",
+                         "requests_waited"], (int(v) for v in out)), now=now.value)
 
     def close(self):
         if getattr(self, "h", None) and lib is not None:  # lib is None during interpreter shutdown

@@ -577,3 +577,7 @@ def test_server_admission_by_footprint():
     """A budget below any two requests' footprint admits one request at a time."""
     stats = _serve_mix(1, 64, 0.0)
     assert stats["completed"] == 8 and stats["max_active"] == 1
+    assert stats["held_by_budget"] >= 1 and stats["requests_waited"] >= 1 and stats["held_by_slots"] == 0
+    stats = _serve_mix(64 << 30, 1, 0.0)   # one slot: requests wait for max_active instead
+    assert stats["completed"] == 8 and stats["max_active"] == 1
+    assert stats["held_by_slots"] >= 1 and stats["held_by_budget"] == 0
