@@ -145,7 +145,7 @@ def main():
         step(args.warmup + args.steps + i)
     torch.cuda.synchronize()
     t1p = time.perf_counter()
-    prof = H.profile_summary()
+    prof = H.profile_summary(units=True)
     H.profile(False)
     ms_per_step_profiled = (t1p - t0) * 1e3 / args.steps
 
@@ -173,34 +173,15 @@ def main():
     # roofline of the dominant kernel of the timed steps.  Its unit of work is the key switch:
     # algorithmic bytes per key switch = key + ciphertext in + ciphertext out
     # = 2 dnum (L+K) N 8 + 2 L N 8 + 2 L N 8, times the rotation items one launch processes.
-    dom, (dcount, dms) = max(prof.items(), key=lambda kv: kv[1][1])
-    avg_ms = dms / dcount
     per_item = keyswitch_kernel_bytes(L, K, N)
     ks_unit = keyswitch_unit_bytes(L, K, N)
-    launches_per_step = dcount / args.steps
-    ks_ms = sum(ms for k, (cnt, ms) in prof.items() if k in per_item) / args.steps
-    roof = None
-    if dom in per_item:
-        items_per_launch = counters["key_switches"] / launches_per_step
-        alg = ks_unit * items_per_launch
-        achieved = alg / (avg_ms * 1e-3) / 1e9
-        comp = per_item[dom] * items_per_launch
-        whole = counters["key_switches"] * ks_unit / (ks_ms * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": measured_traffic(dom),
-                "avg_launch_ms": round(avg_ms, 4), "launches_per_step": launches_per_step,
-                "key_switches_per_launch": round(items_per_launch, 3),
-                "algorithmic_bytes_per_key_switch": ks_unit, "algorithmic_bytes_per_launch": int(alg),
-                "whole_key_switch": {"kernels": sorted(k for k in prof if k in per_item), "ms_per_step": round(ks_ms, 4),
-                                     "achieved": round(whole, 1), "frac": round(whole / HBM_PEAK_GBPS, 4)},
-                "kernel_compulsory": {"bytes_per_launch": int(comp), "achieved": round(comp / (avg_ms * 1e-3) / 1e9, 1),
-                                      "frac": round(comp / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
-                                      "what": "this kernel's own inputs read once and outputs written once, incl. the "
-                                              "extended digits between key-switch kernels"}}
+    ks_ms = sum(v[1] for k, v in prof.items() if k in per_item) / args.steps
+    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    roof = keyswitch_roofline(prof, args.steps, counters["key_switches"], L, K, N, measured_traffic(dom))
     keyswitch = {"key_switches_per_step": counters["key_switches"], "ms_per_step": round(ks_ms, 4),
                  "algorithmic_GBps": round(counters["key_switches"] * ks_unit / (ks_ms * 1e-3) / 1e9, 1),
                  "algorithmic_bytes_per_key_switch": ks_unit}
-    kernel_ms = {k: round(ms / args.steps, 4) for k, (cnt, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1])}
+    kernel_ms = {k: round(v[1] / args.steps, 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])}
 
     result = {
         "metric": "encrypted SpMVs/s + NTT GB/s (% HBM peak), batched vs plain; p99 latency",
@@ -343,6 +324,28 @@ def lazy_relin_laplace256(H, W, torch, dev, reps=3):
         torch.cuda.synchronize()
         r[label] = {"step_ms": round(step_ms, 2), "spmv_ms": round((time.perf_counter() - t0) * 1e3 / reps, 2),
                     "chunk_ciphertexts": m.info()[1], "result_ciphertexts": m.groups()}
+        # the same SpMV with HIP events on every launch: the dominant kernel's roofline
+        H.profile(True)
+        for i in range(reps):
+            H.he_spmv(ctx, ks, m, x)
+        torch.cuda.synchronize()
+        prof = H.profile_summary(units=True)
+        H.profile(False)
+        dom, (cnt, dms, _) = max(prof.items(), key=lambda kv: kv[1][1])
+        avg = dms / cnt
+        r[label]["kernel_ms_per_spmv"] = {k: round(v[1] / reps, 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:6]}
+        if dom == "k_scale_round":
+            tw = ctx.tensor_widths()
+            products = m.info()[1] / (cnt / reps)            # ciphertext products per launch
+            coeffs = products * 3 * ctx.N                     # (d0, d1, d2) coefficients
+            mads = 4 * scale_round_word_products(tw) * coeffs  # four 32 x 32 -> 64 multiply-adds per word product
+            ach = mads / (avg * 1e-3) / 1e12
+            r[label]["roofline"] = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3), "peak": MAD_PEAK_T,
+                                    "unit": "T mad/s", "frac": round(ach / MAD_PEAK_T, 4), "traffic": None,
+                                    "avg_launch_ms": round(avg, 4), "products_per_launch": products,
+                                    "word_products_per_coefficient": scale_round_word_products(tw), "tensor_widths": tw}
+        else:
+            r[label]["roofline"] = keyswitch_roofline(prof, reps, H.last_counters()["key_switches"], 12, 2, ctx.N)
         del m, x
         ks.close()
         ctx.close()
@@ -511,6 +514,50 @@ def measured_traffic(kernel):
     return None
 
 
+MAD_PEAK_T = 1024 * 16 / 4 * 2.4e9 / 1e12   # 32 x 32 -> 64-bit multiply-adds, quarter rate on 1024 SIMDs
+
+
+def keyswitch_roofline(prof, calls, key_switches, L, K, N, traffic=None):
+    """Roofline entry of the dominant kernel of `calls` profiled calls (HIP events per launch,
+    profile name -> (launches, ms, key switches processed)) whose work is `key_switches` key
+    switches per call: achieved = the dominant kernel's key switches per launch x algorithmic bytes
+    per key switch / its average launch time, and the whole key switch (all key-switch kernels'
+    time per call) beside it."""
+    per_item = keyswitch_kernel_bytes(L, K, N)
+    unit = keyswitch_unit_bytes(L, K, N)
+    dom, (dcount, dms, dunits) = max(prof.items(), key=lambda kv: kv[1][1])
+    if dom not in per_item:
+        return {"kernel": dom, "bound": None, "note": "the dominant kernel is not a key-switch kernel"}
+    avg_ms = dms / dcount
+    per_launch = dunits / dcount
+    alg = unit * per_launch
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    ks_ms = sum(v[1] for k, v in prof.items() if k in per_item) / calls
+    whole = key_switches * unit / (ks_ms * 1e-3) / 1e9
+    comp = per_item[dom] * per_launch
+    return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4), "traffic": traffic,
+            "avg_launch_ms": round(avg_ms, 4), "launches_per_call": round(dcount / calls, 3),
+            "key_switches_per_launch": round(per_launch, 3), "algorithmic_bytes_per_key_switch": unit,
+            "algorithmic_bytes_per_launch": int(alg),
+            "whole_key_switch": {"kernels": sorted(k for k in prof if k in per_item), "ms_per_call": round(ks_ms, 4),
+                                 "achieved": round(whole, 1), "frac": round(whole / HBM_PEAK_GBPS, 4)},
+            "kernel_compulsory": {"bytes_per_launch": int(comp), "achieved": round(comp / (avg_ms * 1e-3) / 1e9, 1),
+                                  "frac": round(comp / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+                                  "what": "this kernel's own inputs read once and outputs written once, incl. the "
+                                          "extended digits between key-switch kernels"}}
+
+
+def scale_round_word_products(w):
+    """64 x 64 -> 128-bit word products per output coefficient of the exact scaled rounding
+    (schoolbook multiword arithmetic over the word widths w): the CRT sum T WM, the quotient
+    correction WM + 1, 2 t |X| WM, the reciprocal product WA WMU, and the low WD + 1 words of
+    quotient x 2Q.  The residues of the quotient (FP64 Horner steps) are not counted."""
+    T, WM, WA, WD, WMU = w["T"], w["WM"], w["WA"], w["WD"], w["WMU"]
+    low = sum(1 for col in range(WD + 1) for j in range(col + 1) if col - j < WD and j <= WMU)
+    return T * WM + (WM + 1) + WM + WA * WMU + low
+
+
 def keyswitch_unit_bytes(L, K, N):
     """Algorithmic HBM bytes of one key switch: the key [2][dnum][L+K][N], the ciphertext in and
     the ciphertext out ([2][L][N] each), u64 words; dnum = ceil(L/K)."""
@@ -576,6 +623,13 @@ def batched_vs_plain(H, W, torch, dev, reps=3, tune=True):
     t_graph = (time.perf_counter() - t0) / reps
     graph_same = all(np.array_equal(a.export_all(), b.export_all()) for a, b in zip(plan.outputs()[:8], ys[:8]))
     plan.close()
+    # one batched call with HIP events on every launch: the dominant kernel's roofline
+    H.profile(True)
+    H.he_spmv_batch(ctx, [ks] * len(ms), ms, xs)
+    torch.cuda.synchronize()
+    bprof = H.profile_summary(units=True)
+    H.profile(False)
+    broof = keyswitch_roofline(bprof, 1, counters["key_switches"], 6, 1, 1 << 14)
     for m, x in zip(ms, xs):
         H.he_spmv(ctx, ks, m, x)
     torch.cuda.synchronize()
@@ -597,6 +651,7 @@ def batched_vs_plain(H, W, torch, dev, reps=3, tune=True):
             "plain_spmv_per_s": round(len(ms) / t_plain, 2),
             "batched_ms": round(t_batch * 1e3, 2), "graph_ms": round(t_graph * 1e3, 2), "plain_ms": round(t_plain * 1e3, 2),
             "speedup": round(t_plain / t_batch, 2), "graph_speedup": round(t_plain / t_graph, 2), "decrypt_check": ok,
+            "roofline": broof,
             "autotune": None if tune is None else
             {"keyswitch_transform_variant": tune["variant"], "pipeline_two_pass_by_B": {str(b): int(t2 <= t1 or t1 == 0)
                                                                                      for b, t1, t2 in tune["pipelines"]}}}

@@ -97,6 +97,10 @@ void hs_ctx_destroy(hs_ctx* ctx);
 /* Moduli in chain order (L data, K special, then tensor primes) into host `out` (capacity
    `cap`); *n receives the total count.  HS_ECAPACITY if cap is too small. */
 int hs_ctx_moduli(const hs_ctx* ctx, uint64_t* out, int cap, int* n);
+/* Word widths (64-bit words) of the exact ciphertext product's multiword values, into host
+   out[7]: [tensor moduli T, Q, M (product of the T moduli), 2Q, the Barrett reciprocal of 2Q,
+   2 t |X| + Q, word capacity of the kernels]; all 0 when the ring has no exact product. */
+int hs_ctx_tensor_widths(const hs_ctx* ctx, int64_t out[7]);
 
 /* The 20 thresholds of the discrete Gaussian sampler, T[k] = floor(2^63 P(|e| <= k)) for sigma = 3.2
    truncated at |e| <= 19, computed by the library in 128-bit fixed point (host `out`). */

@@ -578,6 +578,14 @@ int hs_ctx_moduli(const hs_ctx* c, uint64_t* out, int cap, int* n) {
   });
 }
 
+int hs_ctx_tensor_widths(const hs_ctx* c, int64_t out[7]) {
+  return guarded([&] {
+    HS_REQUIRE(c && out, HS_EINVAL, "null argument");
+    const int64_t v[7] = {c->n_mod, c->tq_words, c->tm_words, c->td_words, c->tmu_words, c->ta_words, c->t_kw};
+    for (int i = 0; i < 7; i++) out[i] = c->has_tensor ? v[i] : 0;
+  });
+}
+
 int hs_cdt_table(uint64_t out[20]) {
   return guarded([&] {
     HS_REQUIRE(out, HS_EINVAL, "null argument");

@@ -8,6 +8,8 @@
 // scatter (the rank of an element among the block's elements of its digit that precede it).
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "kernels.hpp"
 
 namespace hs {
@@ -190,19 +192,25 @@ __global__ void k_cssc_rows1(const i64* __restrict__ rp, i64 R, i64 s, int BR, i
 
 // One workgroup of 256 threads per partition: the partition's histogram tot[d] and flags; bh[b][d]
 // becomes the first destination of digit d of block b (as k_sort_scan); CP[j + 1] - CP[j] = rows
-// with count > j = rows with digit < 255 - j = the exclusive prefix of tot at 255 - j.
+// with count > j = rows with digit < 255 - j = the exclusive prefix of tot at 255 - j.  The
+// partition's block histograms (at most N / 512 blocks) are staged in LDS with coalesced loads,
+// so the per-digit running sums over the blocks read LDS, not global memory.
 __global__ void k_cssc_scan1(int* bh, const int* __restrict__ bflag, i64 R, i64 s, int BR, i64* hdr, i64* cp) {
+  extern __shared__ int sh[];            // [nb][256] block histograms of the partition
   __shared__ int tot[256];
   __shared__ int fl;
   const int p = blockIdx.x, d = threadIdx.x;
   const i64 nblk = (R + BR - 1) / BR;
   const i64 b0 = p * (s / BR), b1 = std::min<i64>(nblk, (p + 1) * (s / BR));
+  const int nb = (int)(b1 - b0);
   if (d == 0) fl = 0;
+  for (int i = d; i < nb * 256; i += 256) sh[i] = bh[(size_t)b0 * 256 + i];
+  int f = 0;
+  for (int b = d; b < nb; b += 256) f |= bflag[b0 + b];
   __syncthreads();
-  int t = 0, f = 0;
-  for (i64 b = b0; b < b1; b++) t += bh[(size_t)b * 256 + d];
-  for (i64 b = b0 + d; b < b1; b += 256) f |= bflag[b];
   if (f) atomicOr(&fl, f);
+  int t = 0;
+  for (int b = 0; b < nb; b++) t += sh[b * 256 + d];
   tot[d] = t;
   __syncthreads();
   if (d == 0) {
@@ -225,11 +233,13 @@ __global__ void k_cssc_scan1(int* bh, const int* __restrict__ bflag, i64 R, i64 
   }
   __syncthreads();
   int run = (int)(p * s) + tot[d];
-  for (i64 b = b0; b < b1; b++) {
-    const int v = bh[(size_t)b * 256 + d];
-    bh[(size_t)b * 256 + d] = run;
+  for (int b = 0; b < nb; b++) {
+    const int v = sh[b * 256 + d];
+    sh[b * 256 + d] = run;
     run += v;
   }
+  __syncthreads();
+  for (int i = d; i < nb * 256; i += 256) bh[(size_t)b0 * 256 + i] = sh[i];
 }
 
 // The scatter of the one pass (rows in their original order): RM and each row's rank.
@@ -260,7 +270,12 @@ void launch_cssc_one_pass(const i64* row_ptr, i64 R, i64 s, int* dig, int* bh, i
   const int nP = (int)((R + s - 1) / s);
   ProfScope _prof("k_cssc_one_pass", st);
   hipLaunchKernelGGL(k_cssc_rows1, dim3((unsigned)nblk), dim3(BR), 0, st, row_ptr, R, s, BR, dig, bh, bflag, hdr);
-  hipLaunchKernelGGL(k_cssc_scan1, dim3((unsigned)nP), dim3(256), 0, st, bh, bflag, R, s, BR, hdr, cp);
+  const size_t lds = (size_t)(s / BR) * 256 * sizeof(int);   // one partition's block histograms
+  static std::once_flag attr;   // up to 64 KiB (N = 32768) beside the static arrays
+  std::call_once(attr, [] {
+    (void)hipFuncSetAttribute((const void*)k_cssc_scan1, hipFuncAttributeMaxDynamicSharedMemorySize, 64 * 1024);
+  });
+  hipLaunchKernelGGL(k_cssc_scan1, dim3((unsigned)nP), dim3(256), lds, st, bh, bflag, R, s, BR, hdr, cp);
   hipLaunchKernelGGL(k_cssc_scatter1, dim3((unsigned)nblk), dim3(BR), 0, st, dig, bh, R, s, BR, rm, rank);
   HS_CHECK_HIP(hipGetLastError());
 }

@@ -1056,6 +1056,7 @@ void launch_mask_acc(const hs_ctx* c, const u64* const* w, const u64* mask, cons
 
 void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, u64* D, double* ACC, double* PC, hipStream_t st) {
   if (B <= 0) return;
+  ProfUnits units(B);
   const ModTab* tab = (const ModTab*)c->d_tab;
   HS_DISPATCH_XF(c->xf_variant, c, k_rot_intt, dim3(c->L, B), st, d_items, D, c->L, tab, c->logn);
   HS_DISPATCH_XF(c->xf_variant, c, k_modup_ip, dim3(c->L + c->K, B, S.ndg), st, d_items, (const u64*)D, ACC, S,

@@ -75,6 +75,15 @@ class ProfScope {
   hipEvent_t a_ = nullptr;
   bool active_ = false;
 };
+// The launches the calling thread makes while it lives process `n` units of work each (key
+// switches of a rotation level), summed per kernel in the profile summary.
+class ProfUnits {
+ public:
+  explicit ProfUnits(long n);
+  ~ProfUnits();
+ private:
+  long prev_;
+};
 void profile_enable(bool on);
 void profile_capturing(bool on);  // calling thread is recording a graph: no timing events
 std::string profile_summary();

@@ -714,6 +714,7 @@ void launch_ntt2(const hs_ctx* c, u64* data, double* scratch, i64 rows, int nl, 
 void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, double* T1, double* E, double* ACC, double* T2,
                           double* F, hipStream_t st) {
   if (B <= 0) return;
+  ProfUnits units(B);
   auto body = [&](auto G) {
     using GT = decltype(G);
     const size_t LB = (size_t)lds_doubles(G.BE) * sizeof(double);

@@ -14,6 +14,7 @@ namespace {
 struct Rec {
   const char* name;
   hipEvent_t a, b;
+  long units;
 };
 std::mutex g_mu;
 bool g_on = false;
@@ -35,6 +36,10 @@ hipEvent_t take_event() {
 // Launches recorded into a graph are not timed (their events would become graph nodes).
 static thread_local bool t_capturing = false;
 void profile_capturing(bool on) { t_capturing = on; }
+// Units of work (key switches of a rotation level) of the launches the calling thread makes next.
+static thread_local long t_units = 0;
+ProfUnits::ProfUnits(long n) : prev_(t_units) { t_units = n; }
+ProfUnits::~ProfUnits() { t_units = prev_; }
 
 ProfScope::ProfScope(const char* name, hipStream_t st) : name_(name), st_(st) {
   if (t_capturing) return;
@@ -49,7 +54,7 @@ ProfScope::~ProfScope() {
   if (!active_) return;
   std::lock_guard<std::mutex> g(g_mu);
   hipEvent_t b = take_event();
-  if (hipEventRecord(b, st_) == hipSuccess) g_recs.push_back(Rec{name_, a_, b});
+  if (hipEventRecord(b, st_) == hipSuccess) g_recs.push_back(Rec{name_, a_, b, t_units});
 }
 
 void profile_enable(bool on) {
@@ -64,17 +69,23 @@ void profile_enable(bool on) {
 
 std::string profile_summary() {
   std::lock_guard<std::mutex> g(g_mu);
-  std::map<std::string, std::pair<long, double>> agg;
+  struct Agg {
+    long n = 0, units = 0;
+    double ms = 0;
+  };
+  std::map<std::string, Agg> agg;
   for (Rec& r : g_recs) {
     HS_CHECK_HIP(hipEventSynchronize(r.b));
     float ms = 0.f;
     HS_CHECK_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-    auto& v = agg[r.name];
-    v.first++;
-    v.second += ms;
+    Agg& v = agg[r.name];
+    v.n++;
+    v.ms += ms;
+    v.units += r.units;
   }
   std::string out;
-  for (auto& kv : agg) out += kv.first + " " + std::to_string(kv.second.first) + " " + std::to_string(kv.second.second) + "\n";
+  for (auto& kv : agg)
+    out += kv.first + " " + std::to_string(kv.second.n) + " " + std::to_string(kv.second.ms) + " " + std::to_string(kv.second.units) + "\n";
   return out;
 }
 

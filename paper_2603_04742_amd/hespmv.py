@@ -68,6 +68,7 @@ SIGNATURES = {
     "hs_ctvec_import": (_int, [_vp, _u64p, _i64, _pp]),
     "hs_ct_export_coeff": (_int, [_vp, _i64, _u64p, _i64, _vp]),
     "hs_ctvec_wrap": (_int, [_vp, _vp, _i64, _pp]),
+    "hs_ctx_tensor_widths": (_int, [_vp, _i64p]),
     "hs_he_spmv_noalloc": (_int, [_vp, _vp, _vp, _vp, _vp, _i64, _vp]),
     "hs_ctx_set_option": (_int, [_vp, _int, _i64]),
     "hs_ctvec_destroy": (None, [_vp]),
@@ -161,6 +162,12 @@ class Context:
         buf = np.zeros(256, np.uint64)
         _check(lib.hs_ctx_moduli(self.h, buf.ctypes.data_as(_u64p), 256, ctypes.byref(n)))
         return [int(x) for x in buf[:n.value]]
+
+    def tensor_widths(self):
+        """{T, WQ, WM, WD, WMU, WA, KW}: word widths of the exact ciphertext product (zeros without one)."""
+        out = np.zeros(7, np.int64)
+        _check(lib.hs_ctx_tensor_widths(self.h, out.ctypes.data_as(_i64p)))
+        return dict(zip(["T", "WQ", "WM", "WD", "WMU", "WA", "KW"], (int(v) for v in out)))
 
     def ct_words(self):
         return 2 * self.L * self.N
@@ -512,16 +519,17 @@ def profile(enable):
     _check(lib.hs_profile(int(bool(enable))))
 
 
-def profile_summary():
-    """{kernel name: (launches, total ms)} of the launches recorded since profile(True)."""
+def profile_summary(units=False):
+    """{kernel name: (launches, total ms)} of the launches recorded since profile(True); with
+    units=True also the key switches those launches processed: (launches, total ms, units)."""
     n = ctypes.c_int64()
     lib.hs_profile_summary(None, 0, ctypes.byref(n))
     buf = ctypes.create_string_buffer(n.value + 1)
     _check(lib.hs_profile_summary(buf, n.value + 1, ctypes.byref(n)))
     out = {}
     for line in buf.value.decode().splitlines():
-        name, cnt, ms = line.split()
-        out[name] = (int(cnt), float(ms))
+        name, cnt, ms, u = line.split()
+        out[name] = (int(cnt), float(ms), int(u)) if units else (int(cnt), float(ms))
     return out
 
 
