@@ -67,16 +67,14 @@ __global__ void k_sort_scan(int* bh, i64 R, i64 s, int BR) {
   for (i64 b = b0; b < b1; b++) t += bh[(size_t)b * 256 + d];
   tot[d] = t;
   __syncthreads();
-  if (d == 0) {
-    int run = 0;
-    for (int k = 0; k < 256; k++) {
-      const int v = tot[k];
-      tot[k] = run;
-      run += v;
-    }
+  for (int o = 1; o < 256; o <<= 1) {   // inclusive scan over the digits, then exclusive
+    const int w = d >= o ? tot[d - o] : 0;
+    __syncthreads();
+    tot[d] += w;
+    __syncthreads();
   }
-  __syncthreads();
-  int run = (int)(p * s) + tot[d];
+  const int excl = tot[d] - t;
+  int run = (int)(p * s) + excl;
   for (i64 b = b0; b < b1; b++) {
     const int v = bh[(size_t)b * 256 + d];
     bh[(size_t)b * 256 + d] = run;
@@ -197,13 +195,14 @@ __global__ void k_cssc_rows1(const i64* __restrict__ rp, i64 R, i64 s, int BR, i
 // so the per-digit running sums over the blocks read LDS, not global memory.
 __global__ void k_cssc_scan1(int* bh, const int* __restrict__ bflag, i64 R, i64 s, int BR, i64* hdr, i64* cp) {
   extern __shared__ int sh[];            // [nb][256] block histograms of the partition
-  __shared__ int tot[256];
-  __shared__ int fl;
+  __shared__ int base[256];              // exclusive prefix of the partition histogram over digits
+  __shared__ i64 cps[256];               // CP[1 + j] before the running sum
+  __shared__ int fl, dmin;
   const int p = blockIdx.x, d = threadIdx.x;
   const i64 nblk = (R + BR - 1) / BR;
   const i64 b0 = p * (s / BR), b1 = std::min<i64>(nblk, (p + 1) * (s / BR));
   const int nb = (int)(b1 - b0);
-  if (d == 0) fl = 0;
+  if (d == 0) { fl = 0; dmin = 255; }
   for (int i = d; i < nb * 256; i += 256) sh[i] = bh[(size_t)b0 * 256 + i];
   int f = 0;
   for (int b = d; b < nb; b += 256) f |= bflag[b0 + b];
@@ -211,28 +210,39 @@ __global__ void k_cssc_scan1(int* bh, const int* __restrict__ bflag, i64 R, i64 
   if (f) atomicOr(&fl, f);
   int t = 0;
   for (int b = 0; b < nb; b++) t += sh[b * 256 + d];
-  tot[d] = t;
+  if (t && d < 255) atomicMin(&dmin, d);   // the smallest digit present: the longest row (else 255)
+  // exclusive scan of the histogram over the digits (Hillis-Steele on 256 lanes)
+  base[d] = t;
   __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const int w = d >= o ? base[d - o] : 0;
+    __syncthreads();
+    base[d] += w;
+    __syncthreads();
+  }
+  const int incl = base[d];
+  __syncthreads();
+  base[d] = incl - t;
+  __syncthreads();
+  // CP[j + 1] = sum_{i <= j} base[255 - i] for j < Lw, then the last value repeated
+  const i64 lw = 255 - dmin;
+  cps[d] = d < lw ? (i64)base[255 - d] : 0;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const i64 w = d >= o ? cps[d - o] : 0;
+    __syncthreads();
+    cps[d] += w;
+    __syncthreads();
+  }
+  i64* out = cp + (size_t)p * 256;
+  out[d] = d == 0 ? 0 : cps[d - 1];   // entries past Lw were zero, so the sum stays at CP[Lw]
   if (d == 0) {
-    int dmin = 255;   // the smallest digit present (the longest row); 255 when every row is empty
-    for (int k = 0; k < 255; k++)
-      if (tot[k]) { dmin = k; break; }
-    int run = 0;
-    for (int k = 0; k < 256; k++) {
-      const int v = tot[k];
-      tot[k] = run;
-      run += v;
-    }
-    const i64 lw = 255 - dmin;
-    i64* out = cp + (size_t)p * 256;
-    out[0] = 0;
-    for (i64 j = 0; j < lw; j++) out[j + 1] = out[j] + tot[255 - j];
-    for (i64 j = lw + 1; j < 256; j++) out[j] = out[lw];
     hdr[1 + 3 * p] = lw;
     hdr[2 + 3 * p] = fl;
   }
-  __syncthreads();
-  int run = (int)(p * s) + tot[d];
+  // destinations: digit d of block b starts after the partition's rows of smaller digits and
+  // the rows of digit d in earlier blocks
+  int run = (int)(p * s) + base[d];
   for (int b = 0; b < nb; b++) {
     const int v = sh[b * 256 + d];
     sh[b * 256 + d] = run;
