@@ -150,8 +150,12 @@ int hs_keyset_add_rotation_keys(hs_ctx* ctx, hs_keyset* ks, const int64_t* host_
 int hs_cssc_pack(hs_ctx* ctx, int64_t rows, int64_t cols, const int64_t* row_ptr,
                  const int32_t* col_idx, const int64_t* vals, int encrypt_values,
                  const hs_keyset* ks, uint64_t seed, void* stream, hs_matrix** out);
-/* Matrices and ciphertext vectors take their device memory from the context's pool; their destroy
-   functions wait for the device (hipDeviceSynchronize) before handing it back, and must be called
+/* Matrices and ciphertext vectors take their device memory from the context's pool.  Every call
+   that uses them synchronises its stream before returning except hs_mul_plain, hs_ctvec_copy and
+   hs_batch_plan_run (and a matrix's plaintext encoding on the context's internal stream); their
+   destroy functions wait for that work -- not for the whole device -- before handing the memory
+   back.  A handle must not be destroyed while a call that uses it runs on another thread, while a
+   server request holding it is not yet waited for, or while a batch plan borrows it; destroy
    before the context's hs_ctx_destroy. */
 void hs_matrix_destroy(hs_matrix* m);
 int hs_matrix_info(const hs_matrix* m, int64_t* n_parts, int64_t* n_chunks);

@@ -69,6 +69,41 @@ static T* pmalloc(hs_ctx* c, size_t n) {
 static void pfree(hs_ctx* c, void* p) {
   if (p) c->pool.put(p);
 }
+// Calls that return with work still in flight on the caller's stream (hs_mul_plain,
+// hs_ctvec_copy, hs_batch_plan_run) record an event here; destroying a matrix or a vector waits
+// for these events (and for the matrix's own encoding) before its memory goes back to the pool.
+// Every other call synchronises its stream before returning, so no wait for the whole device is
+// needed.
+static void note_async(hs_ctx* c, hipStream_t st) {
+  std::lock_guard<std::mutex> g(c->async_mu);
+  for (size_t i = 0; i < c->async_ev.size();)  // drop completed ones
+    if (hipEventQuery(c->async_ev[i]) == hipSuccess) {
+      (void)hipEventDestroy(c->async_ev[i]);
+      c->async_ev[i] = c->async_ev.back();
+      c->async_ev.pop_back();
+    } else {
+      i++;
+    }
+  hipEvent_t e = nullptr;
+  if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamSynchronize(st);  // no event: finish the work instead
+    return;
+  }
+  if (hipEventRecord(e, st) != hipSuccess) {
+    (void)hipEventDestroy(e);
+    (void)hipStreamSynchronize(st);
+    return;
+  }
+  c->async_ev.push_back(e);
+}
+static void drain_async(hs_ctx* c) {
+  std::lock_guard<std::mutex> g(c->async_mu);
+  for (hipEvent_t e : c->async_ev) {
+    (void)hipEventSynchronize(e);
+    (void)hipEventDestroy(e);
+  }
+  c->async_ev.clear();
+}
 // Pinned host staging per thread for the structure copies of hs_cssc_pack (pageable copies cost
 // a driver-side staging copy and a wait each).  Every call that uses it synchronises its stream
 // before returning, so a thread's buffer is never in use by two copies at once.  The buffers live
@@ -973,8 +1008,9 @@ int hs_cssc_pack(hs_ctx* c, int64_t rows, int64_t cols, const int64_t* row_ptr, 
 void hs_matrix_destroy(hs_matrix* m) {
   if (!m) return;
   // the memory returns to the context's pool, from which work on any stream may take it next:
-  // wait for the device so no operation still in flight (an asynchronous call) uses it
-  (void)hipDeviceSynchronize();
+  // wait for the matrix's own encoding and for the library's asynchronous calls in flight
+  if (m->ready) (void)hipEventSynchronize(m->ready);
+  drain_async(m->ctx);
   void* ptrs[] = {m->d_struct, m->d_meta, m->d_va, m->d_ci, m->d_pt, m->mask_in_pt ? nullptr : m->d_mask, m->d_coef};
   for (void* p : ptrs) pfree(m->ctx, p);
   if (m->ready) (void)hipEventDestroy(m->ready);
@@ -1371,8 +1407,10 @@ int hs_ctvec_copy(hs_ctvec* dst, const hs_ctvec* src, void* stream) {
   return guarded([&] {
     HS_REQUIRE(dst && src && dst->ctx == src->ctx, HS_EINVAL, "vectors of one context required");
     HS_REQUIRE(dst->n == src->n, HS_EINVAL, "ciphertext counts differ");
-    if (dst->n && dst->d != src->d)
+    if (dst->n && dst->d != src->d) {
       HS_CHECK_HIP(hipMemcpyAsync(dst->d, src->d, (size_t)src->n * ct_words(src->ctx) * sizeof(u64), hipMemcpyDeviceToDevice, S(stream)));
+      note_async(dst->ctx, S(stream));
+    }
   });
 }
 
@@ -1596,6 +1634,7 @@ int hs_batch_plan_run(hs_batch_plan* P, void* stream) {
     HS_REQUIRE(P && P->exec, HS_EINVAL, "null plan");
     hipStream_t st = S(stream);
     HS_CHECK_HIP(hipGraphLaunch(P->exec, st));
+    note_async(P->ctx, st);
     P->last = st;
     P->ran = true;
   });
@@ -1722,7 +1761,7 @@ int hs_ctvec_import(hs_ctx* c, const uint64_t* host_limbs, int64_t n, hs_ctvec**
 void hs_ctvec_destroy(hs_ctvec* v) {
   if (!v) return;
   if (v->d && v->owned) {
-    (void)hipDeviceSynchronize();  // as for matrices: nothing in flight may still use the memory
+    drain_async(v->ctx);  // as for matrices: no asynchronous call in flight may still use the memory
     pfree(v->ctx, v->d);
   }
   delete v;
@@ -1800,6 +1839,7 @@ int hs_mul_plain(hs_ctx* c, const hs_ctvec* in, const uint64_t* d_pt, void* stre
     *out = nullptr;
     hs_ctvec* r = new_ctvec(c, in->n);
     launch_mul_plain(c, in->d, d_pt, r->d, in->n, 0, S(stream));
+    note_async(c, S(stream));
     *out = r;
   });
 }

@@ -172,6 +172,9 @@ struct hs_ctx {
   // execution options of this context (hs_ctx_set_option), by HS_OPT_* key; -1 = the process-wide
   // default (hs_set_option)
   int opt[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+  // events of the asynchronous calls still in flight (see note_async), guarded by async_mu
+  std::mutex async_mu;
+  std::vector<hipEvent_t> async_ev;
   // device address and size of the fixed scratch array on this context's device (allocation-free
   // entry point), looked up when the context is created
   void* na_scratch = nullptr;

@@ -394,6 +394,11 @@ void free_ctx(hs_ctx* c) {
     (void)hipStreamDestroy(c->side);
     c->side = nullptr;
   }
+  for (hipEvent_t e : c->async_ev) {
+    (void)hipEventSynchronize(e);
+    (void)hipEventDestroy(e);
+  }
+  c->async_ev.clear();
   c->pool.release_all();
 }
 
