@@ -320,6 +320,29 @@ def test_batch64_workload_sample():
         assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
 
 
+def test_batch64_full_batch_against_oracle():
+    """The whole 64-matrix batch (rows log-uniform in [512, 16384], densities log-uniform in
+    [0.05 %, 1 %]) on the 16384 ring in one hs_he_spmv_batch call, rotation levels merged across all
+    requests; three of its requests (the two smallest and a mid-size one) equal the oracle's
+    he_spmv limb for limb, and every request equals its own hs_he_spmv."""
+    g, kg, o = contexts(RING16K)
+    ws = W.batch64()
+    pairs = [_pack_and_encrypt(g, kg, w, 50 + i) for i, w in enumerate(ws)]
+    print("batch64: %d requests" % len(ws), flush=True)
+    ys = H.he_spmv_batch(g, [kg] * len(ws), [p[0] for p in pairs], [p[1] for p in pairs])
+    order = sorted(range(len(ws)), key=lambda i: ws[i]["R"])
+    for i in (order[0], order[1], order[20]):
+        w = ws[i]
+        print("batch64 request %d: %d x %d, %d nnz" % (i, w["R"], w["C"], int(w["row_ptr"][-1])), flush=True)
+        OM = O.Matrix(o, w["R"], w["C"], w["row_ptr"], w["col"], w["val"], False, 31)
+        ox = OM.encrypt_vector(w["v"], 50 + i)
+        assert np.array_equal(pairs[i][1].export_all(), ox)
+        oy, _ = OM.he_spmv(ox)
+        assert np.array_equal(ys[i].export_all(), oy)
+    for (M, x), y in zip(pairs[::8], ys[::8]):
+        assert np.array_equal(y.export_all(), H.he_spmv(g, kg, M, x).export_all())
+
+
 @pytest.fixture
 def split_path():
     """Force keygen/encoding/encryption/decryption onto the elementwise + two-pass-NTT path (the
