@@ -583,6 +583,7 @@ def keyswitch_kernel_bytes(L, K, N):
         # one-workgroup-per-limb pipeline
         "k_rot_intt": (L + L) * limb,
         "k_modup_ip": (L + L + key + 2 * LK) * limb,
+        "k_modup_ip_reg": (L + L + key + 2 * LK) * limb,
         "k_moddown_intt": (2 * K + 2 * K) * limb,
         "k_moddown_ntt": (2 * K + 2 * L + L + 2 * L) * limb,
     }

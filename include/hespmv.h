@@ -385,6 +385,11 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
                        kernels and 1024 for ModUp and the key inner product (more, shorter
                        workgroups for latency-bound small levels), 0 = automatic (3 up to 8 items
                        per level, else 1)
+   HS_OPT_MODUP_ACC    one-workgroup-per-limb key switching at N = 2^14, ModUp + key inner product:
+                       0 = automatic (2), 1 = one workgroup per (target modulus, item) with the
+                       accumulators read and written in memory for every digit, 2 = one workgroup
+                       per (half of the target limb, item) with the accumulators in registers
+                       across the digits (written once)
    HS_EINVAL for an unknown key or value. */
 #define HS_OPT_KS_PIPELINE 1
 #define HS_OPT_NTT_PATH 2
@@ -393,6 +398,7 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
 #define HS_OPT_MODUP_GROUP 5
 #define HS_OPT_NTT_PIPE 6
 #define HS_OPT_KS_BLOCK 7
+#define HS_OPT_MODUP_ACC 8
 int hs_set_option(int key, int64_t value);
 int hs_ctx_set_option(hs_ctx* ctx, int key, int64_t value);
 

@@ -23,9 +23,9 @@ static thread_local int64_t g_counters[5] = {0, 0, 0, 0, 0};
 // process-wide options (hs_set_option)
 // process-wide defaults of the execution options, by HS_OPT_* key (hs_set_option); a context's own
 // setting (hs_ctx_set_option) takes precedence.  Key 3 (two-pass threshold) defaults to 512.
-static std::atomic<int> g_opt[8] = {{0}, {0}, {0}, {512}, {0}, {0}, {0}, {0}};
+static std::atomic<int> g_opt[9] = {{0}, {0}, {0}, {512}, {0}, {0}, {0}, {0}, {0}};
 int option(const hs_ctx* c, int key) {
-  if (key <= 0 || key >= 8) return 0;
+  if (key <= 0 || key >= 9) return 0;
   if (c && c->opt[key] >= 0) return c->opt[key];
   return g_opt[key].load();
 }
@@ -1809,6 +1809,9 @@ static void check_option(int key, int64_t value) {
     case HS_OPT_MODUP_GROUP:
       HS_REQUIRE(value >= 0 && value <= 3, HS_EINVAL, "group must be 0, 1, 2 or 3");
       break;
+    case HS_OPT_MODUP_ACC:
+      HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "accumulator option must be 0, 1 or 2");
+      break;
     case HS_OPT_KS_THRESHOLD:
       HS_REQUIRE(value >= 0 && value < (1 << 30), HS_EINVAL, "bad threshold");
       break;
@@ -1828,7 +1831,7 @@ int hs_ctx_set_option(hs_ctx* c, int key, int64_t value) {
   return guarded([&] {
     HS_REQUIRE(c, HS_EINVAL, "null context");
     if (value != -1) check_option(key, value);
-    else HS_REQUIRE(key > 0 && key < 8, HS_EINVAL, "unknown option");
+    else HS_REQUIRE(key > 0 && key < 9, HS_EINVAL, "unknown option");
     c->opt[key] = (int)value;
   });
 }

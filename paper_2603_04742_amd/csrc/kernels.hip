@@ -635,6 +635,142 @@ HS_XF_KERNEL k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict
   }
 }
 
+// k_modup_ip at N = 2^14 with the accumulators in registers.  One workgroup of 512 threads per
+// (output half h, target modulus mi), item b and digit group dg; thread t owns the element pairs
+// h 2^13 + 2t + 1024 k + {0, 1} (k < 8) of both accumulators through all digits of the group and
+// writes them once, after the last digit, where k_modup_ip reads and writes them in memory for
+// every digit.  A digit's forward transform runs on half h only: stage 0 pairs e with e + 2^13, so
+// each half's workgroup reads the whole digit and forms its own half, whose stages 1..13 are
+// independent of the other half (stages 1..12 as radix-8 rounds through LDS, one task per thread
+// and call; stage 13 pairs adjacent elements and runs in registers as the accumulation reads
+// them).  The radix-8 rounds and the just-in-time twiddle loads keep the transform's registers
+// beside the 64 that hold the accumulators.  LDS: one half limb (68 KiB), two workgroups per CU.
+// The accumulators start at zero and every digit's products are added and reduced, so they hold
+// the residues of k_modup_ip's accumulators (the first digit's products reduced once more).
+__global__ void __launch_bounds__(kSplitNT) __attribute__((amdgpu_waves_per_eu(4)))
+k_modup_ip_reg(const RotItem* __restrict__ items, const u64* __restrict__ D, double* ACC, KsShape S,
+               const double2* __restrict__ up_inv, const double2* __restrict__ up_hat, const ModTab* __restrict__ tab) {
+  SMEM();
+  constexpr int LOGN = kSplitLogn, NT = kSplitNT, H = 1 << (LOGN - 1), EH = H / NT, NP = EH / 2;
+  constexpr int n = 1 << LOGN;
+  const int LK = S.L + S.K;
+  // XCD-aware order: workgroup g of the grid runs on XCD g % 8, so each XCD takes a contiguous
+  // range of the (item, digit group) tasks and the 2 (L + K) workgroups of a task, which read the
+  // same digits, share one L2
+  int h, mi, b, dg;
+  {
+    const int per_task = 2 * LK;   // == gridDim.x
+    const int T = per_task * gridDim.y * gridDim.z;
+    const int g = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const int x = g & 7, r = g >> 3, per = T >> 3, rem = T & 7;
+    const int l = x < rem ? x * (per + 1) + r : rem * (per + 1) + (x - rem) * per + r;
+    const int task = l / per_task, part = l % per_task;
+    h = part & 1;
+    mi = part >> 1;
+    b = task % gridDim.y;
+    dg = task / gridDim.y;
+  }
+  const RotItem it = items[b];
+  const ModTab tb = tab[mi];
+  const ModD m = mod_of(tb);
+  const int j0 = dg * S.dpg, j1 = min(S.dnum, j0 + S.dpg);
+  const int hoff = h * H;
+  const LdsHalf<LOGN - 1> Lh{smem};
+  double acc0[EH], acc1[EH];   // element 2t + 1024 k + c of the half at index 2k + c
+#pragma unroll
+  for (int k = 0; k < EH; k++) acc0[k] = acc1[k] = 0.0;
+  for (int j = j0; j < j1; j++) {
+    int tid = threadIdx.x;   // recomputed per digit (not held in registers across the loop)
+    const double2* tw = tb.fw;
+    asm volatile("" : "+v"(tid), "+s"(tw));
+    const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha);
+    const u64* kb = it.key + (((size_t)0 * S.dnum + j) * LK + mi) * n + hoff;
+    const u64* ka = it.key + (((size_t)1 * S.dnum + j) * LK + mi) * n + hoff;
+    // pair k of the thread: (x0, x1) at elements 2t + 1024 k + {0, 1} of the half
+    auto accumulate = [&](int k, double x0, double x1) {
+      const int e = 2 * tid + k * 2 * NT;
+      asm volatile("" : "+s"(kb), "+s"(ka));   // one pair's key words in flight at a time
+      const u64 b0 = gld(kb + e), b1 = gld(kb + e + 1), a0 = gld(ka + e), a1 = gld(ka + e + 1);
+      const double xs[2] = {reduce(x0, m), reduce(x1, m)};
+      const u64 wb[2] = {b0, b1}, wa[2] = {a0, a1};
+#pragma unroll
+      for (int c = 0; c < 2; c++) {
+        const double v0 = mulmod(xs[c], u2d(wb[c]), m);
+        const double v1 = mulmod(xs[c], u2d(wa[c]), m);
+        acc0[2 * k + c] = reduce(v0 + acc0[2 * k + c], m);
+        acc1[2 * k + c] = reduce(v1 + acc1[2 * k + c], m);
+      }
+    };
+    if (mi >= lo && mi < hi) {
+      // the digit holds modulus mi: its extension is sigma_g(c1)_mi itself (NTT form, gathered)
+      const u64* c1 = it.in + ((size_t)S.L + mi) * n;
+#pragma unroll
+      for (int k = 0; k < NP; k++) {
+        const int e = hoff + 2 * tid + k * 2 * NT;
+        const double x0 = u2d(gld(c1 + galois_index((u32)e, it.galois, LOGN)));
+        const double x1 = u2d(gld(c1 + galois_index((u32)(e + 1), it.galois, LOGN)));
+        accumulate(k, x0, x1);
+      }
+    } else {
+      const u64* Dj = D + ((size_t)b * S.L + lo) * n;
+      const int na = hi - lo;
+      const double2* cinv = up_inv + j * S.alpha;
+      const double2* chat = up_hat + (size_t)j * S.alpha * LK + mi;
+      auto src = [=](int i) {
+        if (na == 1) return reduce(u2d(gld(Dj + i)), m);   // one source prime: [x]_q taken mod mi
+        double acc = 0.0;                                   // fast basis conversion D_j -> mi
+        for (int a = 0; a < na; a++) {
+          const ModTab sa = tab[lo + a];
+          const ModD ms = mod_of(sa);
+          const double y = canon(mul_tw(u2d(gld(Dj + (size_t)a * n + i)), cinv[a].x, cinv[a].y, ms), ms);
+          const double2 hm = chat[(size_t)a * LK];
+          acc = reduce(acc + mul_tw(y, hm.x, hm.y, m), m);
+        }
+        return acc;
+      };
+      // stage 0 for this half only, into LDS a few elements at a time
+      const double2 w1 = ldtw(tw, 1);
+#pragma unroll 4
+      for (int k = 0; k < EH; k++) {
+        const int e = tid + k * NT;
+        const double x0 = src(e), t = mul_tw(src(e + H), w1.x, w1.y, m);
+        smem[lpad(e)] = h ? x0 - t : x0 + t;
+      }
+      __syncthreads();
+      // stages 1..12: four radix-8 rounds, the half's 1024 tasks of each as two calls of one task
+      // per thread; the opaque twiddle base keeps a call's twiddle loads from being hoisted into
+      // the previous one
+#define HS_R8(ST0)                                                                     \
+  fwd_round_g<LOGN, NT, ST0, 3, 1>(Lh, Lh, tw, m, h << 10, tid);                        \
+  asm volatile("" : "+s"(tw));                                                          \
+  fwd_round_g<LOGN, NT, ST0, 3, 1>(Lh, Lh, tw, m, (h << 10) + NT, tid);                 \
+  asm volatile("" : "+s"(tw));                                                          \
+  __syncthreads();
+      HS_R8(1) HS_R8(4) HS_R8(7) HS_R8(10)
+#undef HS_R8
+      // stage 13 (pairs e, e + 1; twiddle 2^13 + e / 2 of the whole limb) and the accumulation
+#pragma unroll
+      for (int k = 0; k < NP; k++) {
+        const int e = 2 * tid + k * 2 * NT;
+        const double2 w = ldtw(tw, (1 << 13) + ((hoff + e) >> 1));
+        const double x0 = smem[lpad(e)], t = mul_tw(smem[lpad(e + 1)], w.x, w.y, m);
+        accumulate(k, x0 + t, x0 - t);
+      }
+      __syncthreads();   // the next digit's stage 0 overwrites LDS
+    }
+  }
+  double* o0 = ACC + ((((size_t)b * S.ndg + dg) * 2 + 0) * LK + mi) * n + hoff;
+  double* o1 = ACC + ((((size_t)b * S.ndg + dg) * 2 + 1) * LK + mi) * n + hoff;
+#pragma unroll
+  for (int k = 0; k < NP; k++) {
+    const int e = 2 * threadIdx.x + k * 2 * NT;
+    gst(o0 + e, acc0[2 * k]);
+    gst(o0 + e + 1, acc0[2 * k + 1]);
+    gst(o1 + e, acc1[2 * k]);
+    gst(o1 + e + 1, acc1[2 * k + 1]);
+  }
+}
+
 HS_XF_KERNEL k_moddown_intt(const double* __restrict__ ACC, double* PC, KsShape S, const ModTab* __restrict__ tab, int logn, XF xf) {
   SMEM();
   const int n = 1 << logn;
@@ -1059,8 +1195,16 @@ void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const K
   ProfUnits units(B);
   const ModTab* tab = (const ModTab*)c->d_tab;
   HS_DISPATCH_XF(c->xf_variant, c, k_rot_intt, dim3(c->L, B), st, d_items, D, c->L, tab, c->logn);
-  HS_DISPATCH_XF(c->xf_variant, c, k_modup_ip, dim3(c->L + c->K, B, S.ndg), st, d_items, (const u64*)D, ACC, S,
-                 (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, c->logn);
+  if (c->logn == kSplitLogn && option(c, HS_OPT_MODUP_ACC) != 1) {
+    ProfScope _prof("k_modup_ip_reg", st);
+    ensure_lds((const void*)k_modup_ip_reg, split_lds_bytes());
+    hipLaunchKernelGGL(k_modup_ip_reg, dim3(2 * (c->L + c->K), B, S.ndg), dim3(kSplitNT), split_lds_bytes(), st, d_items, (const u64*)D,
+                       ACC, S, (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab);
+    HS_CHECK_HIP(hipGetLastError());
+  } else {
+    HS_DISPATCH_XF(c->xf_variant, c, k_modup_ip, dim3(c->L + c->K, B, S.ndg), st, d_items, (const u64*)D, ACC, S,
+                   (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab, c->logn);
+  }
   HS_DISPATCH_XF(c->xf_variant, c, k_moddown_intt, dim3(c->K, 2, B), st, (const double*)ACC, PC, S, tab, c->logn);
   HS_DISPATCH_XF(c->xf_variant, c, k_moddown_ntt, dim3(c->L, 2, B), st, d_items, (const double*)ACC, (const double*)PC, S,
                  (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, (const double2*)c->d_pinv, tab, c->logn);
