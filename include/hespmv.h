@@ -368,7 +368,8 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
                        N = 32768, whose limb does not fit in LDS)
    HS_OPT_NTT_PATH     hs_ntt: 0 = automatic, 1 = one workgroup per limb, 2 = two-pass
    HS_OPT_KS_THRESHOLD automatic choice: two-pass when (L + K) x items of a level is below this
-                       value (default 512)
+                       value; 0 = default (192 at N = 2^14 with the register accumulators of
+                       HS_OPT_MODUP_ACC, else 512)
    HS_OPT_AUX_PATH     keygen, encoding, encryption, decryption: 0 = automatic, 1 = fused kernels
                        with the limb in LDS, 2 = elementwise kernels around batched transforms
                        (always used for N = 32768)

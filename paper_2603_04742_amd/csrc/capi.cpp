@@ -22,8 +22,8 @@ static thread_local int64_t g_counters[5] = {0, 0, 0, 0, 0};
 
 // process-wide options (hs_set_option)
 // process-wide defaults of the execution options, by HS_OPT_* key (hs_set_option); a context's own
-// setting (hs_ctx_set_option) takes precedence.  Key 3 (two-pass threshold) defaults to 512.
-static std::atomic<int> g_opt[9] = {{0}, {0}, {0}, {512}, {0}, {0}, {0}, {0}, {0}};
+// setting (hs_ctx_set_option) takes precedence.  Every default is 0 (automatic).
+static std::atomic<int> g_opt[9] = {{0}, {0}, {0}, {0}, {0}, {0}, {0}, {0}, {0}};
 int option(const hs_ctx* c, int key) {
   if (key <= 0 || key >= 9) return 0;
   if (c && c->opt[key] >= 0) return c->opt[key];
@@ -356,7 +356,12 @@ static bool use_two_pass(const hs_ctx* c, int B) {
   if (opt == 2) return true;
   const int pick = c->ks_pick[ks_bucket(B)];
   if (pick >= 0) return pick == 1;
-  return (c->L + c->K) * B < option(c, HS_OPT_KS_THRESHOLD);
+  // untuned default: the crossover measured on MI355X, about 28 items per level at N = 2^14 with the
+  // register-accumulator ModUp (which halves the one-workgroup pipeline's time on large levels),
+  // about 73 otherwise
+  int thr = option(c, HS_OPT_KS_THRESHOLD);
+  if (thr == 0) thr = (c->logn == 14 && option(c, HS_OPT_MODUP_ACC) != 1) ? 192 : 512;
+  return (c->L + c->K) * B < thr;
 }
 
 // Scratch, item arrays and per-level shapes of a sequence of rotation levels (prepared on the
