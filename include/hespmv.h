@@ -391,6 +391,10 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
                        accumulators read and written in memory for every digit, 2 = one workgroup
                        per (half of the target limb, item) with the accumulators in registers
                        across the digits (written once)
+   HS_OPT_KS_FUSE      consecutive two-pass rotation levels: 0 = automatic (the last kernel of a
+                       level also runs the first step of the next level's key switch for each
+                       item whose input is an output of this level), 1 = every level runs its own
+                       first step
    HS_EINVAL for an unknown key or value. */
 #define HS_OPT_KS_PIPELINE 1
 #define HS_OPT_NTT_PATH 2
@@ -400,6 +404,7 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
 #define HS_OPT_NTT_PIPE 6
 #define HS_OPT_KS_BLOCK 7
 #define HS_OPT_MODUP_ACC 8
+#define HS_OPT_KS_FUSE 9
 int hs_set_option(int key, int64_t value);
 int hs_ctx_set_option(hs_ctx* ctx, int key, int64_t value);
 

@@ -23,9 +23,9 @@ static thread_local int64_t g_counters[5] = {0, 0, 0, 0, 0};
 // process-wide options (hs_set_option)
 // process-wide defaults of the execution options, by HS_OPT_* key (hs_set_option); a context's own
 // setting (hs_ctx_set_option) takes precedence.  Every default is 0 (automatic).
-static std::atomic<int> g_opt[9] = {{0}, {0}, {0}, {0}, {0}, {0}, {0}, {0}, {0}};
+static std::atomic<int> g_opt[10] = {{0}, {0}, {0}, {0}, {0}, {0}, {0}, {0}, {0}, {0}};
 int option(const hs_ctx* c, int key) {
-  if (key <= 0 || key >= 9) return 0;
+  if (key <= 0 || key >= 10) return 0;
   if (c && c->opt[key] >= 0) return c->opt[key];
   return g_opt[key].load();
 }
@@ -368,32 +368,79 @@ static bool use_two_pass(const hs_ctx* c, int B) {
 // host, then enqueued without host waits; the enqueue step alone can be captured into a graph).
 struct LevelPlan {
   std::vector<int> B;
+  std::vector<int> B1;      // two-pass levels: items that run their own first step (K1)
+  std::vector<char> fused;  // two-pass level whose last kernel runs the next level's K1 for some items
   std::vector<KsShape> shape;
   std::vector<char> two;
   DBuf ditems, D, ACC, PC, T1, E, ACC2, T2, F;
   int64_t key_switches = 0, launches = 0;
 };
 
-static void prepare_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels, hipStream_t st, LevelPlan& P, Alloc& al) {
+// Cross-level fusion of consecutive two-pass levels: an item of level k + 1 whose input is the
+// output of an item of level k gets its first step (Galois gather + inverse low pass of c1, K1)
+// from that item's last kernel (K5); the level's items are reordered so that those still needing
+// K1 come first.  One successor per output (a second item reading the same input keeps its K1).
+static void fuse_levels(const hs_ctx* c, std::vector<std::vector<RotItem>>& lv, const std::vector<char>& two, std::vector<int>& B1,
+                        std::vector<char>& fused) {
+  const size_t nl = lv.size();
+  B1.assign(nl, 0);
+  fused.assign(nl, 0);
+  for (size_t k = 0; k < nl; k++) B1[k] = (int)lv[k].size();
+  if (option(c, HS_OPT_KS_FUSE) == 1) return;
+  for (size_t k = 0; k + 1 < nl; k++) {
+    if (!two[k] || !two[k + 1]) continue;
+    std::map<const u64*, int> prod;   // output buffer -> item of level k
+    for (size_t p = 0; p < lv[k].size(); p++) prod[lv[k][p].out] = (int)p;
+    std::vector<int> pred(lv[k + 1].size(), -1);
+    std::vector<char> taken(lv[k].size(), 0);
+    for (size_t j = 0; j < lv[k + 1].size(); j++) {
+      auto f = prod.find(lv[k + 1][j].in);
+      if (f != prod.end() && !taken[f->second]) { pred[j] = f->second; taken[f->second] = 1; }
+    }
+    std::vector<RotItem> re;
+    std::vector<int> rp;
+    re.reserve(lv[k + 1].size());
+    for (int pass = 0; pass < 2; pass++)
+      for (size_t j = 0; j < lv[k + 1].size(); j++)
+        if ((pred[j] >= 0) == (pass == 1)) { re.push_back(lv[k + 1][j]); rp.push_back(pred[j]); }
+    int nk1 = 0;
+    for (size_t j = 0; j < re.size(); j++) {
+      if (rp[j] < 0) { nk1++; continue; }
+      lv[k][rp[j]].next = (u32)(j + 1);
+      fused[k] = 1;
+    }
+    lv[k + 1] = std::move(re);
+    B1[k + 1] = nk1;
+  }
+}
+
+static void prepare_levels(hs_ctx* c, const std::vector<std::vector<RotItem>>& levels_in, hipStream_t st, LevelPlan& P, Alloc& al) {
   size_t total = 0, widest = 0;
-  for (auto& l : levels) { total += l.size(); widest = std::max(widest, l.size()); }
+  std::vector<std::vector<RotItem>> levels;
+  for (auto& l : levels_in) {
+    if (l.empty()) continue;
+    total += l.size();
+    widest = std::max(widest, l.size());
+    levels.push_back(l);
+    for (auto& it : levels.back()) it.next = 0;
+  }
   if (!total) return;
   const size_t N = c->N;
   const int LK = c->L + c->K;
-  std::vector<RotItem> flat;
-  flat.reserve(total);
-  for (auto& l : levels) flat.insert(flat.end(), l.begin(), l.end());
   bool any1 = false, any2 = false;
   for (auto& l : levels) {
-    if (l.empty()) continue;
     const bool t = use_two_pass(c, (int)l.size());
     P.B.push_back((int)l.size());
     P.shape.push_back(ks_shape(c, (int)l.size()));
     P.two.push_back(t ? 1 : 0);
     if (t) any2 = true; else any1 = true;
     P.key_switches += (int64_t)l.size();
-    P.launches += t ? 5 : 4;
   }
+  fuse_levels(c, levels, P.two, P.B1, P.fused);
+  for (size_t k = 0; k < levels.size(); k++) P.launches += P.two[k] ? (P.B1[k] > 0 ? 5 : 4) : 4;
+  std::vector<RotItem> flat;
+  flat.reserve(total);
+  for (auto& l : levels) flat.insert(flat.end(), l.begin(), l.end());
   const KsShape Smax = ks_shape(c, 1);  // the most digit groups any level uses
   P.ditems = DBuf(&al, total * sizeof(RotItem));
   if (any1) {
@@ -418,7 +465,7 @@ static void enqueue_levels(hs_ctx* c, const LevelPlan& P, hipStream_t st) {
     const RotItem* items = P.ditems.as<RotItem>() + off;
     if (P.two[lv]) {
       launch_rotate_batch2(c, items, B, P.shape[lv], P.T1.as<double>(), P.E.as<double>(), P.ACC2.as<double>(), P.T2.as<double>(),
-                           P.F.as<double>(), st);
+                           P.F.as<double>(), st, P.B1[lv], P.fused[lv] ? items + B : nullptr);
     } else {
       launch_rotate_batch(c, items, B, P.shape[lv], P.D.as<u64>(), P.ACC.as<double>(), P.PC.as<double>(), st);
     }
@@ -1817,6 +1864,9 @@ static void check_option(int key, int64_t value) {
     case HS_OPT_MODUP_ACC:
       HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "accumulator option must be 0, 1 or 2");
       break;
+    case HS_OPT_KS_FUSE:
+      HS_REQUIRE(value == 0 || value == 1, HS_EINVAL, "fusion option must be 0 or 1");
+      break;
     case HS_OPT_KS_THRESHOLD:
       HS_REQUIRE(value >= 0 && value < (1 << 30), HS_EINVAL, "bad threshold");
       break;
@@ -1836,7 +1886,7 @@ int hs_ctx_set_option(hs_ctx* c, int key, int64_t value) {
   return guarded([&] {
     HS_REQUIRE(c, HS_EINVAL, "null context");
     if (value != -1) check_option(key, value);
-    else HS_REQUIRE(key > 0 && key < 9, HS_EINVAL, "unknown option");
+    else HS_REQUIRE(key > 0 && key < 10, HS_EINVAL, "unknown option");
     c->opt[key] = (int)value;
   });
 }

@@ -171,7 +171,7 @@ struct hs_ctx {
   signed char ks_pick[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
   // execution options of this context (hs_ctx_set_option), by HS_OPT_* key; -1 = the process-wide
   // default (hs_set_option)
-  int opt[9] = {-1, -1, -1, -1, -1, -1, -1, -1, -1};
+  int opt[10] = {-1, -1, -1, -1, -1, -1, -1, -1, -1, -1};
   // events of the asynchronous calls still in flight (see note_async), guarded by async_mu
   std::mutex async_mu;
   std::vector<hipEvent_t> async_ev;

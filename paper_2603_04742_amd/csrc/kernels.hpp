@@ -13,7 +13,9 @@ struct RotItem {
   const u64* addend;  // optional ciphertext added to the result (may alias `out`), else nullptr
   const u64* key;     // key-switching key [2][dnum][L+K][N] for sigma_g(s) -> s
   u32 galois;         // Galois element g
-  u32 pad;
+  u32 next;           // two-pass levels: 1 + index, in the next level, of the item whose input is
+                      // this item's output and whose first key-switch step (Galois gather +
+                      // inverse low pass of c1) this item's last kernel performs; 0 = none
 };
 
 struct KsShape {
@@ -106,8 +108,10 @@ void launch_mask_acc(const hs_ctx* c, const u64* const* w, const u64* mask, cons
 void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, u64* D, double* ACC, double* PC, hipStream_t st);
 // two-pass (multi-workgroup) transforms and key switching (ks2.hip)
 void launch_ntt2(const hs_ctx* c, u64* data, double* scratch, i64 rows, int nl, int mod0, int inverse, hipStream_t st);
+// Items [0, B1) get the first step (K1) here; the others had it from the previous level's last
+// kernel.  d_next: the next level's items when some items here have `next` set, else nullptr.
 void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, double* T1, double* E, double* ACC, double* T2,
-                          double* F, hipStream_t st);
+                          double* F, hipStream_t st, int B1 = -1, const RotItem* d_next = nullptr);
 
 // split path (aux2.hip): elementwise prologues / epilogues around batched transforms
 void launch_ints_to_limbs(const hs_ctx* c, const int* src, i64 src_stride, int nobj, u64* out, int nl, int mod0, hipStream_t st);

@@ -10,7 +10,11 @@
 //                                                                                     -> ACC, T2
 //  K4 k2_moddown_high   inverse high pass of the special limbs, conversion P -> q_i, forward high
 //                       pass                                                          -> F
-//  K5 k2_final_low      forward low pass, out = (ACC - F) P^-1 + sigma_g(c0) (+ addend)
+//  K5 k2_final_low      forward low pass, out = (ACC - F) P^-1 + sigma_g(c0) (+ addend); where the
+//                       output is the next level's input, also the next level's K1 for it
+//                       (the Galois permutation of NTT slots maps every contiguous block onto
+//                       one block, so the block this workgroup holds is exactly the source of
+//                       one block of the next gather)
 // Intermediates are balanced doubles in HBM (mostly served from the 256 MB Infinity Cache).
 #include <algorithm>
 #include <atomic>
@@ -584,8 +588,10 @@ __global__ void __launch_bounds__(NT) k2_moddown_high(const double* __restrict__
 // the pass, so their latency hides behind it.
 template <int NT, class GT>
 __global__ void __launch_bounds__(NT) k2_final_low(const RotItem* __restrict__ items, const double* __restrict__ F, const double* __restrict__ ACC,
-                                                   const double2* __restrict__ pinv, KsShape S, const ModTab* __restrict__ tab, GT G) {
+                                                   const double2* __restrict__ pinv, KsShape S, const ModTab* __restrict__ tab, GT G,
+                                                   const RotItem* __restrict__ next_items, double* T1) {
   SMEM2(G);
+  __shared__ int s_dst;
   constexpr int PER = (GT::kMaxBE + NT - 1) / NT;
   const int n = 1 << G.logn;
   const int blk = blockIdx.x, wi = blockIdx.y, b = blockIdx.z;
@@ -593,6 +599,12 @@ __global__ void __launch_bounds__(NT) k2_final_low(const RotItem* __restrict__ i
   const RotItem it = items[b];
   const ModTab tq = tab[i];
   const ModD m = mod_of2(tq);
+  // fused next-level K1 (see below): the gather block it fills, found before the first barrier
+  const bool fuse = w == 1 && next_items != nullptr && it.next != 0;   // uniform per workgroup
+  const int bn = fuse ? (int)it.next - 1 : 0;
+  const u32 g2 = (fuse ? next_items + bn : items + b)->galois;          // a valid item either way
+  for (int t = threadIdx.x; t < G.nblk; t += NT)
+    if ((galois_index2((u32)(t << G.lbe), g2, G.logn) >> G.lbe) == (u32)blk) s_dst = t;
   TwPre<NT, false, true, GT> tw;
   tw.load(G, blk, tq.fw);
   const double* src = F + (((size_t)b * 2 + w) * S.L + i) * n;
@@ -618,6 +630,11 @@ __global__ void __launch_bounds__(NT) k2_final_low(const RotItem* __restrict__ i
     if (e < G.BE) smem[lpad(e)] = x[r];
   }
   __syncthreads();
+  // the fused step's inverse twiddles, in flight during the forward pass (loaded by every
+  // workgroup: no branch around the loads)
+  const int dst = s_dst;
+  TwPre<NT, false, false, GT> twi;
+  twi.load(G, dst, tq.iv);
   pass_fwd<NT, false>(smem, twl, G, blk, tq.fw, m, false);
   const double2 pv = pinv[i];
   u64* out = it.out + ((size_t)w * S.L + i) * n;
@@ -627,10 +644,34 @@ __global__ void __launch_bounds__(NT) k2_final_low(const RotItem* __restrict__ i
     if (e < G.BE) {
       const int gi = gidx_of_lds<false>(G, blk, e);
       const double cv = (w == 0 ? u2d(c0w[r]) : 0.0) + (add ? u2d(adw[r]) : 0.0);
-      const double v = mul_tw(reduce(av[r] - smem[lpad(e)], m), pv.x, pv.y, m) + cv;
-      gst(out + gi, d2u(canon(v, m)));
+      const double v = canon(mul_tw(reduce(av[r] - smem[lpad(e)], m), pv.x, pv.y, m) + cv, m);
+      gst(out + gi, d2u(v));
+      if (fuse) smem[lpad(e)] = v;   // the element this thread has just read
     }
   }
+  if (!fuse) return;
+  // The next level's K1 for this output: sigma_g'(c1') gathered block by block, inverse low pass.
+  // Block dst of the gather reads only this block (the permutation maps blocks onto blocks).
+  __syncthreads();   // the output block is in LDS; the forward pass's twiddles are no longer read
+  twi.store(twl, G);
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    const int e = threadIdx.x + r * NT;
+    if (e < G.BE) {
+      const u32 sidx = galois_index2((u32)gidx_of_lds<false>(G, dst, e), g2, G.logn);
+      x[r] = smem[lpad((int)sidx - (blk << G.lbe))];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < PER; r++) {
+    const int e = threadIdx.x + r * NT;
+    if (e < G.BE) smem[lpad(e)] = x[r];
+  }
+  __syncthreads();
+  pass_inv<NT, false>(smem, twl, G, dst, false, tq.iv, tq.ninv, m, false);
+  double* o = T1 + ((size_t)bn * S.L + i) * n;
+  for (int e = threadIdx.x; e < G.BE; e += NT) gst(o + gidx_of_lds<false>(G, dst, e), smem[lpad(e)]);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -712,8 +753,9 @@ void launch_ntt2(const hs_ctx* c, u64* data, double* scratch, i64 rows, int nl, 
 // 1024), 2 = 1024-element blocks throughout, 0 = automatic: 3 up to kSmallLevel items, else 1.
 
 void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const KsShape& S, double* T1, double* E, double* ACC, double* T2,
-                          double* F, hipStream_t st) {
+                          double* F, hipStream_t st, int B1, const RotItem* d_next) {
   if (B <= 0) return;
+  if (B1 < 0 || B1 > B) B1 = B;
   ProfUnits units(B);
   auto body = [&](auto G) {
     using GT = decltype(G);
@@ -722,7 +764,7 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     const size_t TWH = (size_t)2 * (1 << G.S) * sizeof(double);
     const ModTab* tab = (const ModTab*)c->d_tab;
     const int LK = c->L + c->K;
-    HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B), TW + LB, st, d_items, T1, c->L, tab, G);
+    if (B1 > 0) HS2_LAUNCH(k2_rot_intt_low, dim3(G.nblk, c->L, B1), TW + LB, st, d_items, T1, c->L, tab, G);
     using G2T = typename ModupGeom<GT>::type;
     // targets per ModUp workgroup: three on 1024-element blocks (the small-level geometry at
     // N = 2^14, where it measured fastest at every level size), else two below 5 items
@@ -769,7 +811,7 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     HS2_LAUNCH(k2_moddown_high, dim3(G.nblk, 2 * c->L, B), (TWH + LB) * (c->K + 1), st, (const double*)T2, F, S,
                (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, tab, G);
     HS2_LAUNCH(k2_final_low, dim3(G.nblk, 2 * c->L, B), TW + LB, st, d_items, (const double*)F, (const double*)ACC,
-               (const double2*)c->d_pinv, S, tab, G);
+               (const double2*)c->d_pinv, S, tab, G, d_next, T1);
   };
   constexpr int kSmallLevel = 8;
   const int blk_opt = option(c, HS_OPT_KS_BLOCK);

@@ -507,8 +507,8 @@ def rotate(ctx, ks, x, k):
     return CtVec(ctx, h)
 
 
-OPT_KS_PIPELINE, OPT_NTT_PATH, OPT_KS_THRESHOLD, OPT_AUX_PATH, OPT_MODUP_GROUP, OPT_NTT_PIPE, OPT_KS_BLOCK, OPT_MODUP_ACC = \
-    1, 2, 3, 4, 5, 6, 7, 8
+OPT_KS_PIPELINE, OPT_NTT_PATH, OPT_KS_THRESHOLD, OPT_AUX_PATH, OPT_MODUP_GROUP, OPT_NTT_PIPE, OPT_KS_BLOCK, OPT_MODUP_ACC, \
+    OPT_KS_FUSE = 1, 2, 3, 4, 5, 6, 7, 8, 9
 
 
 def set_option(key, value):
