@@ -579,7 +579,8 @@ def keyswitch_kernel_bytes(L, K, N):
         "k2_ip_low": (ext + L + key + 2 * L + 2 * K) * limb,
         "k2_ip_par": (ext + L + key + 2 * L + 2 * K) * limb,
         "k2_moddown_high": (2 * K + 2 * L) * limb,
-        "k2_final_low": (2 * L + 2 * L + L + 2 * L) * limb,
+        # F, ACC, sigma_g(c0), addend in, result out, and the next level's T1 (its first step runs here)
+        "k2_final_low": (2 * L + 2 * L + L + 2 * L + L) * limb,
         # one-workgroup-per-limb pipeline
         "k_rot_intt": (L + L) * limb,
         "k_modup_ip": (L + L + key + 2 * LK) * limb,
