@@ -190,6 +190,7 @@ class Context:
     def __init__(self, logn, L, qbits, K, pbits=None, t=65537, agg_mode=0, slot_rows=1, lazy_relin=0):
         self.logn, self.N, self.L, self.K, self.t = logn, 1 << logn, L, K, t
         self.slot_rows, self.lazy_relin = slot_rows, lazy_relin
+        self._free = lib().orc_ctx_free
         self.h = lib().orc_ctx_new(logn, L, qbits, K, pbits or qbits, t, agg_mode, slot_rows, int(lazy_relin))
         if not self.h:
             raise ValueError("oracle: unsupported parameters")
@@ -197,8 +198,10 @@ class Context:
         self.dnum = (L + K - 1) // K
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orc_ctx_free(self.h)
+        # the free function is looked up while the module is alive (not at interpreter shutdown)
+        free = getattr(self, "_free", None)
+        if getattr(self, "h", None) and free is not None:
+            free(self.h)
             self.h = None
 
     # --- parameters
@@ -370,13 +373,16 @@ class Matrix:
         self.row_ptr = np.ascontiguousarray(row_ptr, np.int64)
         self.col = np.ascontiguousarray(col, np.int32)
         self.val = np.ascontiguousarray(val, np.int64)
+        self._free = lib().orc_matrix_free
         self.h = lib().orc_matrix_new(ctx.h, R, C, _p(self.row_ptr, i64p), _p(self.col, i32p), _p(self.val, i64p), int(encrypted), mat_seed)
         if not self.h:
             raise ValueError("oracle: encrypted matrix values need the exact ciphertext product, which this ring cannot hold")
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orc_matrix_free(self.h)
+        # the free function is looked up while the module is alive (not at interpreter shutdown)
+        free = getattr(self, "_free", None)
+        if getattr(self, "h", None) and free is not None:
+            free(self.h)
             self.h = None
 
     def n_parts(self):
@@ -433,11 +439,14 @@ class DiagMatrix:
         self.row_ptr = np.ascontiguousarray(row_ptr, np.int64)
         self.col = np.ascontiguousarray(col, np.int32)
         self.val = np.ascontiguousarray(val, np.int64)
+        self._free = lib().orc_diag_free
         self.h = lib().orc_diag_new(ctx.h, R, C, _p(self.row_ptr, i64p), _p(self.col, i32p), _p(self.val, i64p))
 
     def __del__(self):
-        if getattr(self, "h", None):
-            lib().orc_diag_free(self.h)
+        # the free function is looked up while the module is alive (not at interpreter shutdown)
+        free = getattr(self, "_free", None)
+        if getattr(self, "h", None) and free is not None:
+            free(self.h)
             self.h = None
 
     def info(self):
