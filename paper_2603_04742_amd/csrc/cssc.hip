@@ -188,6 +188,24 @@ __global__ void k_cssc_rows1(const i64* __restrict__ rp, i64 R, i64 s, int BR, i
   if (t == 0) bflag[b] = fl;
 }
 
+// Inclusive prefix sum over the 256 threads of a workgroup: within each 64-lane wave by shuffles,
+// then the totals of the earlier waves (ws: 4 values of LDS; two barriers).
+template <class T>
+__device__ __forceinline__ T scan256_incl(T v, T* ws) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  if (lane == 63) ws[wv] = v;
+  __syncthreads();
+  T add = 0;
+  for (int i = 0; i < wv; i++) add += ws[i];
+  __syncthreads();
+  return v + add;
+}
+
 // One workgroup of 256 threads per partition: the partition's histogram tot[d] and flags; bh[b][d]
 // becomes the first destination of digit d of block b (as k_sort_scan); CP[j + 1] - CP[j] = rows
 // with count > j = rows with digit < 255 - j = the exclusive prefix of tot at 255 - j.  The
@@ -196,7 +214,7 @@ __global__ void k_cssc_rows1(const i64* __restrict__ rp, i64 R, i64 s, int BR, i
 __global__ void k_cssc_scan1(int* bh, const int* __restrict__ bflag, i64 R, i64 s, int BR, i64* hdr, i64* cp) {
   extern __shared__ int sh[];            // [nb][256] block histograms of the partition
   __shared__ int base[256];              // exclusive prefix of the partition histogram over digits
-  __shared__ i64 cps[256];               // CP[1 + j] before the running sum
+  __shared__ i64 ws[4];                  // wave totals of the scans
   __shared__ int fl, dmin;
   const int p = blockIdx.x, d = threadIdx.x;
   const i64 nblk = (R + BR - 1) / BR;
@@ -211,31 +229,16 @@ __global__ void k_cssc_scan1(int* bh, const int* __restrict__ bflag, i64 R, i64 
   int t = 0;
   for (int b = 0; b < nb; b++) t += sh[b * 256 + d];
   if (t && d < 255) atomicMin(&dmin, d);   // the smallest digit present: the longest row (else 255)
-  // exclusive scan of the histogram over the digits (Hillis-Steele on 256 lanes)
-  base[d] = t;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const int w = d >= o ? base[d - o] : 0;
-    __syncthreads();
-    base[d] += w;
-    __syncthreads();
-  }
-  const int incl = base[d];
-  __syncthreads();
+  // exclusive scan of the histogram over the digits
+  const int incl = (int)scan256_incl<i64>(t, ws);
   base[d] = incl - t;
   __syncthreads();
   // CP[j + 1] = sum_{i <= j} base[255 - i] for j < Lw, then the last value repeated
   const i64 lw = 255 - dmin;
-  cps[d] = d < lw ? (i64)base[255 - d] : 0;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const i64 w = d >= o ? cps[d - o] : 0;
-    __syncthreads();
-    cps[d] += w;
-    __syncthreads();
-  }
+  const i64 cpi = scan256_incl<i64>(d < lw ? (i64)base[255 - d] : 0, ws);
   i64* out = cp + (size_t)p * 256;
-  out[d] = d == 0 ? 0 : cps[d - 1];   // entries past Lw were zero, so the sum stays at CP[Lw]
+  if (d < 255) out[d + 1] = cpi;   // entries past Lw add zero, so the sum stays at CP[Lw]
+  if (d == 0) out[0] = 0;
   if (d == 0) {
     hdr[1 + 3 * p] = lw;
     hdr[2 + 3 * p] = fl;
@@ -252,18 +255,33 @@ __global__ void k_cssc_scan1(int* bh, const int* __restrict__ bflag, i64 R, i64 
   for (int i = d; i < nb * 256; i += 256) bh[(size_t)b0 * 256 + i] = sh[i];
 }
 
-// The scatter of the one pass (rows in their original order): RM and each row's rank.
+// The scatter of the one pass (rows in their original order): RM and each row's rank.  A row's
+// rank among the block's rows of its digit = the rows of that digit in earlier waves (per-wave
+// histograms in LDS) + the earlier lanes of its wave with the same digit (eight ballots give the
+// lanes whose digit equals this lane's).
 __global__ void k_cssc_scatter1(const int* __restrict__ dig, const int* __restrict__ off, i64 R, i64 s, int BR, int* rm, int* rank) {
-  __shared__ int dg[256];
+  __shared__ int wh[4][256];   // BR <= 256: at most four waves
   const int b = blockIdx.x, t = threadIdx.x;
+  const int lane = t & 63, wv = t >> 6, nw = ((int)blockDim.x + 63) >> 6;
+  for (int x = t; x < nw * 256; x += blockDim.x) wh[x >> 8][x & 255] = 0;
+  __syncthreads();
   const i64 i = (i64)b * BR + t;
   const bool ok = i < R;
-  const int d = ok ? dig[i] : -1;
-  dg[t] = d;
+  const int d = ok ? dig[i] : 0;
+  int r = 0;
+  if (ok) {
+    unsigned long long same = __ballot(1);
+#pragma unroll
+    for (int bit = 0; bit < 8; bit++) {
+      const unsigned long long m = __ballot((d >> bit) & 1);
+      same &= ((d >> bit) & 1) ? m : ~m;
+    }
+    r = __popcll(same & ((1ull << lane) - 1));
+    if ((same >> lane) == 1ull) wh[wv][d] = __popcll(same);   // the wave's last lane of this digit
+  }
   __syncthreads();
   if (!ok) return;
-  int r = 0;
-  for (int u = 0; u < t; u++) r += dg[u] == d;
+  for (int u = 0; u < wv; u++) r += wh[u][d];
   const i64 dst = off[(size_t)b * 256 + d] + r;
   const i64 base = (i / s) * s;
   rm[dst] = (int)(i - base);
