@@ -366,7 +366,9 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
                        transform (least HBM traffic; large batches), 2 = two-pass transforms over
                        N/2048 workgroups per limb (lowest latency; small batches; always used for
                        N = 32768, whose limb does not fit in LDS)
-   HS_OPT_NTT_PATH     hs_ntt: 0 = automatic, 1 = one workgroup per limb, 2 = two-pass
+   HS_OPT_NTT_PATH     hs_ntt and the library's batched transforms: 0 = automatic (N = 2^15: one
+                       workgroup per limb on half-limb LDS from 256 limbs on, else two-pass),
+                       1 = one workgroup per limb, 2 = two-pass
    HS_OPT_KS_THRESHOLD automatic choice: two-pass when (L + K) x items of a level is below this
                        value; 0 = default (192 at N = 2^14 with the register accumulators of
                        HS_OPT_MODUP_ACC, else 512)

@@ -490,12 +490,21 @@ static void run_rotation_levels(hs_ctx* c, const std::vector<std::vector<RotItem
 // workgroups per limb) for limbs larger than LDS and, automatically, for a handful of limbs, whose
 // one-workgroup transforms would occupy a few CUs for a whole transform's latency.
 static constexpr i64 kTwoPassMaxRows = 16, kTwoPassMaxRows14 = 64;  // N = 2^14: 512-element blocks
+// N = 2^15 (a limb exceeds LDS): one workgroup per limb on half-limb LDS for batches that fill
+// the GPU (k_ntt15, one workgroup per CU), the two-pass transforms below that
+static constexpr i64 kOneWgMinRows15 = 256;
+static bool ntt15_one_wg(const hs_ctx* c, i64 rows) {
+  const int opt = option(c, HS_OPT_NTT_PATH);
+  return c->logn == 15 && opt != 2 && (opt == 1 || rows >= kOneWgMinRows15);
+}
 static void ntt_any(hs_ctx* c, u64* data, i64 rows, int nl, int mod0, int inverse, hipStream_t st, std::vector<DBuf>& hold,
                     Alloc* al) {
   if (rows <= 0) return;
   const int opt = option(c, HS_OPT_NTT_PATH);
   const i64 two_max = c->logn == 14 ? kTwoPassMaxRows14 : kTwoPassMaxRows;
-  if (!lds_limb_fits(c) || opt == 2 || (opt == 0 && c->logn >= 12 && rows <= two_max)) {
+  if (ntt15_one_wg(c, rows)) {
+    launch_ntt(c, data, rows, nl, mod0, inverse, st);
+  } else if (!lds_limb_fits(c) || opt == 2 || (opt == 0 && c->logn >= 12 && rows <= two_max)) {
     hold.emplace_back(al ? al : &c->pool, (size_t)rows * c->N * sizeof(double));
     launch_ntt2(c, data, hold.back().as<double>(), rows, nl, mod0, inverse, st);
   } else {
@@ -1830,7 +1839,7 @@ int hs_ntt(hs_ctx* c, uint64_t* d_limbs, int64_t n_polys, int mod0, int n_limbs,
     } else {
       HS_REQUIRE(mod0 + n_limbs <= c->n_mod, HS_EINVAL, "modulus index out of range");
     }
-    const bool two = !lds_limb_fits(c) || option(c, HS_OPT_NTT_PATH) == 2;
+    const bool two = (!lds_limb_fits(c) && !ntt15_one_wg(c, (i64)n_polys * n_limbs)) || option(c, HS_OPT_NTT_PATH) == 2;
     if (two) {
       DBuf scratch(&c->pool, (size_t)n_polys * n_limbs * c->N * sizeof(double));
       launch_ntt2(c, d_limbs, scratch.as<double>(), n_polys * n_limbs, n_limbs, m0, inverse, S(stream));

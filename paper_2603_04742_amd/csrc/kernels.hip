@@ -128,6 +128,106 @@ HS_XF_KERNEL k_ntt(u64* data, int nl, int mod0, int inverse, const ModTab* __res
   else xf.fwd(in, out, smem, t.fw, m);
 }
 
+// One workgroup of 1024 threads per N = 2^15 limb (in place, canonical u64 in and out), for
+// batches of many limbs (the exact ciphertext product's transforms): the half-limb schedule of
+// N = 2^14 with twice the threads.  Forward: stage 0 pairs e with e + 2^14 in registers as the
+// limb is read (thread t owns elements t + 1024 k of both halves, k < 16, exactly its register
+// group of stages 1..4); each half then runs stages 5..14 through LDS (radix-8 rounds at stages
+// 5, 8, 11 with two tasks per thread, stage 14 as a radix-2 round into the output) while the other
+// half waits in registers.  Inverse: the mirror image (per half stages 0..9 through LDS, 10..13
+// in registers; stage 14 and the 1/N scaling on both halves at the end).  LDS: one half limb
+// (136 KiB), one workgroup per CU.
+static constexpr int kN15Logn = 15, kN15NT = 1024;
+__host__ __device__ constexpr int n15_lds_doubles() { return lds_doubles(1 << (kN15Logn - 1)); }
+
+__global__ void __launch_bounds__(kN15NT) __attribute__((amdgpu_waves_per_eu(4)))
+k_ntt15(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab) {
+  SMEM();
+  constexpr int LOGN = kN15Logn, NT = kN15NT, H = 1 << (LOGN - 1), EH = H / NT;
+  static_assert(EH == 16, "16 elements per thread and half");
+  const int b = blockIdx.x;
+  const ModTab t = tab[mod0 + b % nl];
+  const ModD m = mod_of(t);
+  u64* p = data + ((size_t)b << LOGN);
+  const int tid = threadIdx.x;
+  const LdsHalf<LOGN - 1> Lh{smem};
+  if (!inverse) {
+    const double2* tw = t.fw;
+    auto out = [p, m](int i, double x) { gst(p + i, d2u(canon(x, m))); };
+    double a[EH], c[EH];
+#pragma unroll
+    for (int k = 0; k < EH; k++) {
+      a[k] = u2d(gld(p + tid + k * NT));
+      c[k] = u2d(gld(p + tid + k * NT + H));
+    }
+    const double2 w1 = ldtw(tw, 1);
+#pragma unroll
+    for (int k = 0; k < EH; k++) {
+      const double tt = mul_tw(c[k], w1.x, w1.y, m);
+      c[k] = a[k] - tt;
+      a[k] = a[k] + tt;
+    }
+    ct_group<4, 1>(a, 0, tw, m);
+    Lh.template put<4, 10>(a, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 5, 3, 2>(Lh, Lh, tw, m, 0, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 8, 3, 2>(Lh, Lh, tw, m, 0, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 11, 3, 2>(Lh, Lh, tw, m, 0, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 14, 1, 8>(Lh, elem_out(out), tw, m, 0, tid);
+    __syncthreads();
+    ct_group<4, 1>(c, 1, tw, m);
+    Lh.template put<4, 10>(c, H + tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 5, 3, 2>(Lh, Lh, tw, m, 1 << 11, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 8, 3, 2>(Lh, Lh, tw, m, 1 << 11, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 11, 3, 2>(Lh, Lh, tw, m, 1 << 11, tid);
+    __syncthreads();
+    fwd_round_g<LOGN, NT, 14, 1, 8>(Lh, elem_out(out), tw, m, 1 << 13, tid);
+  } else {
+    const double2* tw = t.iv;
+    const double2 ninv = t.ninv;
+    auto in = [p](int i) { return u2d(gld(p + i)); };
+    double a[EH], c[EH];
+    inv_round_g<LOGN, NT, 0, 3, 2, false>(elem_in(in), Lh, tw, ninv, m, 0, tid);
+    __syncthreads();
+    inv_round_g<LOGN, NT, 3, 3, 2, false>(Lh, Lh, tw, ninv, m, 0, tid);
+    __syncthreads();
+    inv_round_g<LOGN, NT, 6, 3, 2, false>(Lh, Lh, tw, ninv, m, 0, tid);
+    __syncthreads();
+    inv_round_g<LOGN, NT, 9, 1, 8, false>(Lh, Lh, tw, ninv, m, 0, tid);
+    __syncthreads();
+    Lh.template get<4, 10>(a, tid);
+    gs_group<4, 10, LOGN, false>(a, 0, tw, ninv, m);
+    __syncthreads();
+    inv_round_g<LOGN, NT, 0, 3, 2, false>(elem_in(in), Lh, tw, ninv, m, 1 << 11, tid);
+    __syncthreads();
+    inv_round_g<LOGN, NT, 3, 3, 2, false>(Lh, Lh, tw, ninv, m, 1 << 11, tid);
+    __syncthreads();
+    inv_round_g<LOGN, NT, 6, 3, 2, false>(Lh, Lh, tw, ninv, m, 1 << 11, tid);
+    __syncthreads();
+    inv_round_g<LOGN, NT, 9, 1, 8, false>(Lh, Lh, tw, ninv, m, 1 << 13, tid);
+    __syncthreads();
+    Lh.template get<4, 10>(c, H + tid);
+    gs_group<4, 10, LOGN, false>(c, 1, tw, ninv, m);
+    // stage 14 with the scaling merged into its twiddle: w' = w / N mod q
+    const double2 w = ldtw(tw, 1);
+    const double wn = canon(mul_tw(w.x, ninv.x, ninv.y, m), m);
+    const double wnq = wn / m.q;
+#pragma unroll
+    for (int k = 0; k < EH; k++) {
+      const int e = tid + k * NT;
+      const double x = a[k], y = c[k];
+      gst(p + e, d2u(canon(mul_tw(x + y, ninv.x, ninv.y, m), m)));
+      gst(p + e + H, d2u(canon(mul_tw(x - y, wn, wnq, m), m)));
+    }
+  }
+}
+
 // Forward transforms of many N = 2^14 limbs, software-pipelined: a grid of two workgroups per CU
 // loops over the limbs (stride = grid size).  The half-limb schedule above holds both halves in
 // registers after the first stage; once the first half has gone to LDS its registers are free, so
@@ -1110,6 +1210,14 @@ static int cu_count(int device) {
 
 void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st) {
   if (nblocks <= 0) return;
+  if (c->logn == kN15Logn) {
+    const size_t lds = (size_t)n15_lds_doubles() * sizeof(double);
+    ProfScope _prof("k_ntt15", st);
+    ensure_lds((const void*)k_ntt15, lds);
+    hipLaunchKernelGGL(k_ntt15, dim3((unsigned)nblocks), dim3(kN15NT), lds, st, data, nl, mod0, inverse, (const ModTab*)c->d_tab);
+    HS_CHECK_HIP(hipGetLastError());
+    return;
+  }
   const i64 grid = 2 * (i64)cu_count(c->device);
   if (c->logn == kSplitLogn && c->xf_variant_ntt == 0 && !inverse && nblocks >= 2 * grid && option(c, HS_OPT_NTT_PIPE) == 0) {
     // enough limbs for every workgroup of the grid to loop over at least two

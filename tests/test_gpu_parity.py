@@ -240,7 +240,7 @@ def test_repeated_runs_are_bit_identical(pipeline):
 
 
 def test_ntt_32768_two_pass():
-    """N = 32768 (limb larger than LDS) always takes the two-pass transform."""
+    """N = 32768 (limb larger than LDS): a handful of limbs takes the two-pass transform."""
     g = H.Context(15, 2, 50, 1)
     o = O.Context(15, 2, 50, 1)
     rng = np.random.default_rng(15)
@@ -253,6 +253,35 @@ def test_ntt_32768_two_pass():
         assert np.array_equal(got[m], o.ntt(m, x[m]))
     g.ntt(d, 0, 3, inverse=True)
     assert np.array_equal(d.cpu().numpy().view(np.uint64).reshape(3, -1), x)
+
+
+@pytest.mark.parametrize("path", [0, 1], ids=["auto_300_limbs", "forced_3_limbs"])
+def test_ntt_32768_one_workgroup_per_limb(path):
+    """N = 32768 with one workgroup per limb on half-limb LDS (k_ntt15): a batch of 300 limbs (the
+    automatic choice from 256 on) and 3 limbs with the path forced; sampled limbs equal the
+    oracle's transform, and the inverse restores every limb."""
+    g = H.Context(15, 12, 50, 2)
+    o = O.Context(15, 12, 50, 2)
+    rng = np.random.default_rng(16)
+    nl = 14
+    mods = o.moduli()[:nl]
+    npoly = 22 if path == 0 else 1   # 308 limbs, or 14
+    base = np.stack([rng.integers(0, q, 1 << 15, dtype=np.uint64) for q in mods])
+    x = np.concatenate([np.roll(base, p, axis=1) for p in range(npoly)])
+    if path == 1:
+        x = x[:3]
+        nl = 3
+        H.set_option(H.OPT_NTT_PATH, 1)
+    try:
+        d = dev(x.reshape(-1), torch.int64)
+        g.ntt(d, 0, nl)
+        got = d.cpu().numpy().view(np.uint64).reshape(x.shape[0], -1)
+        for r in sorted({0, 1, x.shape[0] // 2, x.shape[0] - 1}):
+            assert np.array_equal(got[r], o.ntt(r % nl, x[r])), r
+        g.ntt(d, 0, nl, inverse=True)
+        assert np.array_equal(d.cpu().numpy().view(np.uint64).reshape(x.shape[0], -1), x)
+    finally:
+        H.set_option(H.OPT_NTT_PATH, 0)
 
 
 def test_options_rejected():
