@@ -519,6 +519,16 @@ static bool use_split(const hs_ctx* c) { return !lds_limb_fits(c) || option(c, H
 // while the matrix's encoding keeps the fused kernels, which run on the side stream.
 static bool use_split_client(const hs_ctx* c) { return use_split(c) || (c->logn >= 14 && option(c, HS_OPT_AUX_PATH) == 0); }
 
+// (dst, src) pairs of `words` u64 words each, in batched copy launches
+static void copy_pairs(const std::vector<std::pair<u64*, const u64*>>& pairs, size_t words, hipStream_t st) {
+  if (pairs.empty()) return;
+  std::vector<const u64*> src;
+  std::vector<u64*> dst;
+  for (const auto& p : pairs) { dst.push_back(p.first); src.push_back(p.second); }
+  std::vector<size_t> w(pairs.size(), words);
+  launch_copy_batch(src.data(), dst.data(), w.data(), (int)pairs.size(), st);
+}
+
 // Exact ciphertext products a_i x b_i (NTT form [2][L][N] each) with relinearisation: n items,
 // keys[i] = the relinearisation key of item i.  With lazy[i] set, item i is not relinearised: its
 // scaled tensor goes to lazy[i] as [4][L][N] = (d0, d2, 0, d1) (out[i] is not written).
@@ -532,9 +542,17 @@ static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const
   Alloc* A = al ? al : &c->pool;
   std::vector<DBuf> hold;
   DBuf X(A, (size_t)n * 4 * LN * sizeof(u64));
-  for (int i = 0; i < n; i++) {
-    HS_CHECK_HIP(hipMemcpyAsync(X.as<u64>() + (size_t)i * 4 * LN, a[i], 2 * LN * sizeof(u64), hipMemcpyDeviceToDevice, st));
-    HS_CHECK_HIP(hipMemcpyAsync(X.as<u64>() + (size_t)i * 4 * LN + 2 * LN, b[i], 2 * LN * sizeof(u64), hipMemcpyDeviceToDevice, st));
+  {
+    std::vector<const u64*> src(2 * n);
+    std::vector<u64*> dst(2 * n);
+    std::vector<size_t> words(2 * n, 2 * LN);
+    for (int i = 0; i < n; i++) {
+      src[2 * i] = a[i];
+      src[2 * i + 1] = b[i];
+      dst[2 * i] = X.as<u64>() + (size_t)i * 4 * LN;
+      dst[2 * i + 1] = X.as<u64>() + (size_t)i * 4 * LN + 2 * LN;
+    }
+    launch_copy_batch(src.data(), dst.data(), words.data(), 2 * n, st);
   }
   ntt_any(c, X.as<u64>(), (i64)n * 4 * L, L, 0, 1, st, hold, A);
   TensorConst C{};
@@ -552,11 +570,19 @@ static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const
   launch_scale_round(c, C, PROD.as<u64>(), D4.as<u64>(), n, st);
   ntt_any(c, D4.as<u64>(), (i64)n * 4 * L, L, 0, 0, st, hold, A);
   std::vector<std::vector<RotItem>> lv(1);
+  {
+    std::vector<const u64*> src;
+    std::vector<u64*> dst;
+    for (int i = 0; i < n; i++)
+      if (lazy && lazy[i]) {
+        src.push_back(D4.as<u64>() + (size_t)i * 4 * LN);
+        dst.push_back(lazy[i]);
+      }
+    std::vector<size_t> words(src.size(), 4 * LN);
+    launch_copy_batch(src.data(), dst.data(), words.data(), (int)src.size(), st);
+  }
   for (int i = 0; i < n; i++) {
-    if (lazy && lazy[i]) {
-      HS_CHECK_HIP(hipMemcpyAsync(lazy[i], D4.as<u64>() + (size_t)i * 4 * LN, 4 * LN * sizeof(u64), hipMemcpyDeviceToDevice, st));
-      continue;
-    }
+    if (lazy && lazy[i]) continue;
     RotItem it{};
     it.in = D4.as<u64>() + (size_t)i * 4 * LN;            // (d0, d2)
     it.addend = D4.as<u64>() + (size_t)i * 4 * LN + 2 * LN;  // (0, d1)
@@ -1376,8 +1402,7 @@ struct BatchWork {
     enqueue_levels(c, levels, st);
     for (const Mask& k : masks) launch_mask_acc(c, k.wp, k.mask, k.pc0, k.pnc, k.y, k.nP, st);
     enqueue_levels(c, relin, st);
-    for (const auto& cp : copies)
-      HS_CHECK_HIP(hipMemcpyAsync(cp.first, cp.second, ct_words(c) * sizeof(u64), hipMemcpyDeviceToDevice, st));
+    copy_pairs(copies, ct_words(c), st);
   }
 };
 
@@ -2537,8 +2562,7 @@ static void server_tick(hs_server* S) {
     run_rotation_levels(c, {relin_items}, S->st);
     g_counters[0] -= (int64_t)relin_items.size();   // relinearisations are not rotations
   }
-  for (const auto& cp : copies)
-    HS_CHECK_HIP(hipMemcpyAsync(cp.first, cp.second, CW * sizeof(u64), hipMemcpyDeviceToDevice, S->st));
+  copy_pairs(copies, CW, S->st);
   HS_CHECK_HIP(hipStreamSynchronize(S->st));
   const double t = S->now();
   std::lock_guard<std::mutex> lk(S->mu);

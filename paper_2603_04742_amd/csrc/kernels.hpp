@@ -94,6 +94,9 @@ void upload_cdt(const u64* tab20);
 // fixed scratch region of the allocation-free entry point on the current device (noalloc.hip)
 int noalloc_scratch(void** ptr, size_t* bytes);
 void launch_fill_u64(u64* p, size_t n, u64 v, hipStream_t st);
+// n device-to-device copies of words[j] u64 words (src[j] -> dst[j]; host arrays of device
+// pointers), batched into launches of up to 32 (one launch instead of one copy call each)
+void launch_copy_batch(const u64* const* src, u64* const* dst, const size_t* words, int n, hipStream_t st);
 void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st);
 void launch_sample_small(const hs_ctx* c, int* out, int nobj, i64 obj_stride, u64 seed, u32 purpose, u64 index0, u64 index_step,
                          int kind, hipStream_t st);
