@@ -695,9 +695,13 @@ static int nt2(const GT& G) { return (G.BE >= 2048 || (G.BE >= 512 && G.logn >= 
 // below 1024 elements
 template <class GT> struct IpGeom { using type = typename HalfBlocks<GT>::type; };
 template <> struct IpGeom<PassGeomC<14, 9>> { using type = PassGeomC<14, 10>; };
-// geometry of the ModUp kernel (K2): the level's, and never below 1024 elements
+// geometry of the ModUp kernel (K2): the level's, never below 1024 elements, and 1024 at N = 2^15
+// (with two-prime digits its LDS, (digit primes + targets) x (block + twiddles), allows one
+// workgroup per CU on 2048-element blocks and three on 1024: 0.57 -> 0.47 ms for a level of 20
+// relinearisations; at N = 2^14 the 2048-element levels measured faster as they are)
 template <class GT> struct ModupGeom { using type = GT; };
 template <> struct ModupGeom<PassGeomC<14, 9>> { using type = PassGeomC<14, 10>; };
+template <> struct ModupGeom<PassGeomC<15, 11>> { using type = PassGeomC<15, 10>; };
 
 // Launch KERNEL<NT, GT> (GT = the geometry type in scope) with 256 or 64 threads.
 #define HS2_LAUNCH(KERNEL, GRID, LDS, STREAM, ...)                                                  \
