@@ -700,6 +700,9 @@ template <> struct IpGeom<PassGeomC<14, 9>> { using type = PassGeomC<14, 10>; };
 // workgroup per CU on 2048-element blocks and three on 1024: 0.57 -> 0.47 ms for a level of 20
 // relinearisations; at N = 2^14 the 2048-element levels measured faster as they are)
 template <class GT> struct ModupGeom { using type = GT; };
+// geometry of the ModDown kernel (K4): the level's, 1024 elements at N = 2^15
+template <class GT> struct ModdownGeom { using type = GT; };
+template <> struct ModdownGeom<PassGeomC<15, 11>> { using type = PassGeomC<15, 10>; };
 template <> struct ModupGeom<PassGeomC<14, 9>> { using type = PassGeomC<14, 10>; };
 template <> struct ModupGeom<PassGeomC<15, 11>> { using type = PassGeomC<15, 10>; };
 
@@ -812,8 +815,19 @@ void launch_rotate_batch2(const hs_ctx* c, const RotItem* d_items, int B, const 
     } else {
       HS2_LAUNCH(k2_ip_low, dim3(G.nblk, LK, B), TW + LB, st, d_items, (const double*)E, ACC, T2, S, tab, G);
     }
-    HS2_LAUNCH(k2_moddown_high, dim3(G.nblk, 2 * c->L, B), (TWH + LB) * (c->K + 1), st, (const double*)T2, F, S,
-               (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, tab, G);
+    using G4T = typename ModdownGeom<GT>::type;
+    if constexpr (std::is_same<G4T, GT>::value) {
+      HS2_LAUNCH(k2_moddown_high, dim3(G.nblk, 2 * c->L, B), (TWH + LB) * (c->K + 1), st, (const double*)T2, F, S,
+                 (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, tab, G);
+    } else {
+      auto k4 = [&](auto G) {   // the macro launches on this geometry
+        using GT = decltype(G);
+        const size_t LB4 = (size_t)lds_doubles(G.BE) * sizeof(double);
+        HS2_LAUNCH(k2_moddown_high, dim3(G.nblk, 2 * c->L, B), (TWH + LB4) * (c->K + 1), st, (const double*)T2, F, S,
+                   (const double2*)c->d_dn_inv, (const double2*)c->d_dn_hat, tab, G);
+      };
+      k4(G4T{});
+    }
     HS2_LAUNCH(k2_final_low, dim3(G.nblk, 2 * c->L, B), TW + LB, st, d_items, (const double*)F, (const double*)ACC,
                (const double2*)c->d_pinv, S, tab, G, d_next, T1);
   };
