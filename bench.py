@@ -331,21 +331,32 @@ def lazy_relin_laplace256(H, W, torch, dev, reps=3):
         torch.cuda.synchronize()
         prof = H.profile_summary(units=True)
         H.profile(False)
-        dom, (cnt, dms, _) = max(prof.items(), key=lambda kv: kv[1][1])
-        avg = dms / cnt
+        dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
         r[label]["kernel_ms_per_spmv"] = {k: round(v[1] / reps, 3) for k, v in sorted(prof.items(), key=lambda kv: -kv[1][1])[:6]}
-        if dom == "k_scale_round":
+        roofs = {}
+        if "k_scale_round" in prof:
+            cnt, dms, _ = prof["k_scale_round"]
+            avg = dms / cnt
             tw = ctx.tensor_widths()
             products = m.info()[1] / (cnt / reps)            # ciphertext products per launch
             coeffs = products * 3 * ctx.N                     # (d0, d1, d2) coefficients
             mads = 4 * scale_round_word_products(tw) * coeffs  # four 32 x 32 -> 64 multiply-adds per word product
             ach = mads / (avg * 1e-3) / 1e12
-            r[label]["roofline"] = {"kernel": dom, "bound": "alu", "achieved": round(ach, 3), "peak": MAD_PEAK_T,
-                                    "unit": "T mad/s", "frac": round(ach / MAD_PEAK_T, 4), "traffic": None,
-                                    "avg_launch_ms": round(avg, 4), "products_per_launch": products,
-                                    "word_products_per_coefficient": scale_round_word_products(tw), "tensor_widths": tw}
-        else:
-            r[label]["roofline"] = keyswitch_roofline(prof, reps, H.last_counters()["key_switches"], 12, 2, ctx.N)
+            roofs["k_scale_round"] = {"kernel": "k_scale_round", "bound": "alu", "achieved": round(ach, 3), "peak": MAD_PEAK_T,
+                                      "unit": "T mad/s", "frac": round(ach / MAD_PEAK_T, 4), "traffic": None,
+                                      "avg_launch_ms": round(avg, 4), "products_per_launch": products,
+                                      "word_products_per_coefficient": scale_round_word_products(tw), "tensor_widths": tw}
+        if "k_ntt15" in prof:
+            # limb transform unit: 16 N bytes (read + write u64), limbs per launch counted by the library's profiler
+            cnt, dms, limbs = prof["k_ntt15"]
+            avg = dms / cnt
+            ach = limbs / cnt * 16 * ctx.N / (avg * 1e-3) / 1e9
+            roofs["k_ntt15"] = {"kernel": "k_ntt15", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
+                                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None,
+                                "avg_launch_ms": round(avg, 4), "limbs_per_launch": round(limbs / cnt, 1),
+                                "algorithmic_bytes_per_limb": 16 * ctx.N}
+        r[label]["roofline"] = roofs.get(dom) or keyswitch_roofline(prof, reps, H.last_counters()["key_switches"], 12, 2, ctx.N)
+        r[label]["rooflines"] = roofs
         del m, x
         ks.close()
         ctx.close()

@@ -431,8 +431,10 @@ int hs_set_tuning(hs_ctx* ctx, const int64_t in[10]);
 
 /* Kernel timing: hs_profile(1) clears the records and brackets every subsequent kernel launch with
    two HIP events on its stream; hs_profile(0) stops.  hs_profile_summary waits for the recorded
-   events and writes one text line per kernel, "name launches total_ms", NUL-terminated, into host
-   `buf` (capacity `cap` bytes; *len receives the length; HS_ECAPACITY if it does not fit). */
+   events and writes one text line per kernel, "name launches total_ms units", NUL-terminated, into
+   host `buf` (capacity `cap` bytes; *len receives the length; HS_ECAPACITY if it does not fit);
+   units = the work the launches processed: rotation items (key switches) for the key-switch
+   kernels, limbs for the one-workgroup N = 2^15 transform, 0 for the others. */
 int hs_profile(int enable);
 int hs_profile_summary(char* buf, int64_t cap, int64_t* len);
 

@@ -1212,6 +1212,7 @@ void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int i
   if (nblocks <= 0) return;
   if (c->logn == kN15Logn) {
     const size_t lds = (size_t)n15_lds_doubles() * sizeof(double);
+    ProfUnits units(nblocks);   // limbs per launch, for the profile's roofline
     ProfScope _prof("k_ntt15", st);
     ensure_lds((const void*)k_ntt15, lds);
     hipLaunchKernelGGL(k_ntt15, dim3((unsigned)nblocks), dim3(kN15NT), lds, st, data, nl, mod0, inverse, (const ModTab*)c->d_tab);

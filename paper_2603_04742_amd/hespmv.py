@@ -522,7 +522,8 @@ def profile(enable):
 
 def profile_summary(units=False):
     """{kernel name: (launches, total ms)} of the launches recorded since profile(True); with
-    units=True also the key switches those launches processed: (launches, total ms, units)."""
+    units=True also the work those launches processed (key switches for the key-switch kernels,
+    limbs for k_ntt15): (launches, total ms, units)."""
     n = ctypes.c_int64()
     lib.hs_profile_summary(None, 0, ctypes.byref(n))
     buf = ctypes.create_string_buffer(n.value + 1)
