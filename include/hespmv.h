@@ -389,10 +389,11 @@ int hs_mul_ct(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* a, const hs_ctve
                        workgroups for latency-bound small levels), 0 = automatic (3 up to 8 items
                        per level, else 1)
    HS_OPT_MODUP_ACC    one-workgroup-per-limb key switching at N = 2^14, ModUp + key inner product:
-                       0 = automatic (2), 1 = one workgroup per (target modulus, item) with the
-                       accumulators read and written in memory for every digit, 2 = one workgroup
-                       per (half of the target limb, item) with the accumulators in registers
-                       across the digits (written once)
+                       0 = automatic (3 from 64 items per level on, else 2), 1 = one workgroup per
+                       (target modulus, item) with the accumulators read and written in memory
+                       for every digit, 2 = one workgroup of 512 threads per (half of the target
+                       limb, item) with the accumulators in registers across the digits (written
+                       once), 3 = the same with one workgroup of 1024 threads per whole limb
    HS_OPT_KS_FUSE      consecutive two-pass rotation levels: 0 = automatic (the last kernel of a
                        level also runs the first step of the next level's key switch for each
                        item whose input is an output of this level), 1 = every level runs its own

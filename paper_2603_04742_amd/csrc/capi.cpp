@@ -1896,7 +1896,7 @@ static void check_option(int key, int64_t value) {
       HS_REQUIRE(value >= 0 && value <= 3, HS_EINVAL, "group must be 0, 1, 2 or 3");
       break;
     case HS_OPT_MODUP_ACC:
-      HS_REQUIRE(value >= 0 && value <= 2, HS_EINVAL, "accumulator option must be 0, 1 or 2");
+      HS_REQUIRE(value >= 0 && value <= 3, HS_EINVAL, "accumulator option must be 0, 1, 2 or 3");
       break;
     case HS_OPT_KS_FUSE:
       HS_REQUIRE(value == 0 || value == 1, HS_EINVAL, "fusion option must be 0 or 1");

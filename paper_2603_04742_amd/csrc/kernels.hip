@@ -735,38 +735,41 @@ HS_XF_KERNEL k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict
   }
 }
 
-// k_modup_ip at N = 2^14 with the accumulators in registers.  One workgroup of 512 threads per
-// (output half h, target modulus mi), item b and digit group dg; thread t owns the element pairs
-// h 2^13 + 2t + 1024 k + {0, 1} (k < 8) of both accumulators through all digits of the group and
-// writes them once, after the last digit, where k_modup_ip reads and writes them in memory for
-// every digit.  A digit's forward transform runs on half h only: stage 0 pairs e with e + 2^13, so
-// each half's workgroup reads the whole digit and forms its own half, whose stages 1..13 are
-// independent of the other half (stages 1..12 as radix-8 rounds through LDS, one task per thread
-// and call; stage 13 pairs adjacent elements and runs in registers as the accumulation reads
-// them).  The radix-8 rounds and the just-in-time twiddle loads keep the transform's registers
-// beside the 64 that hold the accumulators.  LDS: one half limb (68 KiB), two workgroups per CU.
-// The accumulators start at zero and every digit's products are added and reduced, so they hold
-// the residues of k_modup_ip's accumulators (the first digit's products reduced once more).
-__global__ void __launch_bounds__(kSplitNT) __attribute__((amdgpu_waves_per_eu(4)))
+// k_modup_ip at N = 2^14 with the accumulators in registers.  One workgroup per (part h of the
+// output, target modulus mi), item b and digit group dg, PARTS = 2 (halves, 512 threads) or 1
+// (the whole limb, 1024 threads); thread t owns the element pairs h P + 2t + 2 NT k + {0, 1}
+// (k < 8, P = N / PARTS) of both accumulators through all digits of the group and writes them
+// once, after the last digit, where k_modup_ip reads and writes them in memory for every digit.
+// A digit's forward transform: stage 0 pairs e with e + 2^13 (with halves, each half's workgroup
+// reads the whole digit and forms its own half, whose stages 1..13 are independent of the other
+// half); stages 1..12 as radix-8 rounds through LDS, one task per thread and call; stage 13 pairs
+// adjacent elements and runs in registers as the accumulation reads them.  The radix-8 rounds and
+// the just-in-time twiddle loads keep the transform's registers beside the 64 that hold the
+// accumulators.  LDS: one part (68 KiB, two workgroups per CU; or 136 KiB, one).  The
+// accumulators start at zero and every digit's products are added and reduced, so they hold the
+// residues of k_modup_ip's accumulators (the first digit's products reduced once more).
+template <int PARTS>
+__global__ void __launch_bounds__(1024 / PARTS) __attribute__((amdgpu_waves_per_eu(4)))
 k_modup_ip_reg(const RotItem* __restrict__ items, const u64* __restrict__ D, double* ACC, KsShape S,
                const double2* __restrict__ up_inv, const double2* __restrict__ up_hat, const ModTab* __restrict__ tab) {
   SMEM();
-  constexpr int LOGN = kSplitLogn, NT = kSplitNT, H = 1 << (LOGN - 1), EH = H / NT, NP = EH / 2;
+  constexpr int LOGN = kSplitLogn, NT = 1024 / PARTS, H = 1 << (LOGN - 1), P = (1 << LOGN) / PARTS, EH = P / NT, NP = EH / 2;
+  static_assert(EH == 16, "16 elements per thread");
   constexpr int n = 1 << LOGN;
   const int LK = S.L + S.K;
   // XCD-aware order: workgroup g of the grid runs on XCD g % 8, so each XCD takes a contiguous
-  // range of the (item, digit group) tasks and the 2 (L + K) workgroups of a task, which read the
-  // same digits, share one L2
+  // range of the (item, digit group) tasks and the PARTS (L + K) workgroups of a task, which read
+  // the same digits, share one L2
   int h, mi, b, dg;
   {
-    const int per_task = 2 * LK;   // == gridDim.x
+    const int per_task = PARTS * LK;   // == gridDim.x
     const int T = per_task * gridDim.y * gridDim.z;
     const int g = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
     const int x = g & 7, r = g >> 3, per = T >> 3, rem = T & 7;
     const int l = x < rem ? x * (per + 1) + r : rem * (per + 1) + (x - rem) * per + r;
     const int task = l / per_task, part = l % per_task;
-    h = part & 1;
-    mi = part >> 1;
+    h = part % PARTS;
+    mi = part / PARTS;
     b = task % gridDim.y;
     dg = task / gridDim.y;
   }
@@ -774,9 +777,10 @@ k_modup_ip_reg(const RotItem* __restrict__ items, const u64* __restrict__ D, dou
   const ModTab tb = tab[mi];
   const ModD m = mod_of(tb);
   const int j0 = dg * S.dpg, j1 = min(S.dnum, j0 + S.dpg);
-  const int hoff = h * H;
-  const LdsHalf<LOGN - 1> Lh{smem};
-  double acc0[EH], acc1[EH];   // element 2t + 1024 k + c of the half at index 2k + c
+  const int hoff = h * P;
+  using LT = typename std::conditional<PARTS == 2, LdsHalf<LOGN - 1>, LdsIO>::type;
+  const LT Lh{smem};
+  double acc0[EH], acc1[EH];   // element 2t + 2 NT k + c of the part at index 2k + c
 #pragma unroll
   for (int k = 0; k < EH; k++) acc0[k] = acc1[k] = 0.0;
   for (int j = j0; j < j1; j++) {
@@ -786,7 +790,7 @@ k_modup_ip_reg(const RotItem* __restrict__ items, const u64* __restrict__ D, dou
     const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha);
     const u64* kb = it.key + (((size_t)0 * S.dnum + j) * LK + mi) * n + hoff;
     const u64* ka = it.key + (((size_t)1 * S.dnum + j) * LK + mi) * n + hoff;
-    // pair k of the thread: (x0, x1) at elements 2t + 1024 k + {0, 1} of the half
+    // pair k of the thread: (x0, x1) at elements 2t + 2 NT k + {0, 1} of the part
     auto accumulate = [&](int k, double x0, double x1) {
       const int e = 2 * tid + k * 2 * NT;
       asm volatile("" : "+s"(kb), "+s"(ka));   // one pair's key words in flight at a time
@@ -828,22 +832,32 @@ k_modup_ip_reg(const RotItem* __restrict__ items, const u64* __restrict__ D, dou
         }
         return acc;
       };
-      // stage 0 for this half only, into LDS a few elements at a time
+      // stage 0 (this part only), into LDS a few elements at a time
       const double2 w1 = ldtw(tw, 1);
+      if constexpr (PARTS == 2) {
 #pragma unroll 4
-      for (int k = 0; k < EH; k++) {
-        const int e = tid + k * NT;
-        const double x0 = src(e), t = mul_tw(src(e + H), w1.x, w1.y, m);
-        smem[lpad(e)] = h ? x0 - t : x0 + t;
+        for (int k = 0; k < EH; k++) {
+          const int e = tid + k * NT;
+          const double x0 = src(e), t = mul_tw(src(e + H), w1.x, w1.y, m);
+          smem[lpad(e)] = h ? x0 - t : x0 + t;
+        }
+      } else {
+#pragma unroll 4
+        for (int k = 0; k < EH / 2; k++) {
+          const int e = tid + k * NT;
+          const double x0 = src(e), t = mul_tw(src(e + H), w1.x, w1.y, m);
+          smem[lpad(e)] = x0 + t;
+          smem[lpad(e + H)] = x0 - t;
+        }
       }
       __syncthreads();
-      // stages 1..12: four radix-8 rounds, the half's 1024 tasks of each as two calls of one task
+      // stages 1..12: four radix-8 rounds, the part's P / 8 tasks of each as two calls of one task
       // per thread; the opaque twiddle base keeps a call's twiddle loads from being hoisted into
       // the previous one
 #define HS_R8(ST0)                                                                     \
-  fwd_round_g<LOGN, NT, ST0, 3, 1>(Lh, Lh, tw, m, h << 10, tid);                        \
+  fwd_round_g<LOGN, NT, ST0, 3, 1>(Lh, Lh, tw, m, h * (P / 8), tid);                    \
   asm volatile("" : "+s"(tw));                                                          \
-  fwd_round_g<LOGN, NT, ST0, 3, 1>(Lh, Lh, tw, m, (h << 10) + NT, tid);                 \
+  fwd_round_g<LOGN, NT, ST0, 3, 1>(Lh, Lh, tw, m, h * (P / 8) + NT, tid);               \
   asm volatile("" : "+s"(tw));                                                          \
   __syncthreads();
       HS_R8(1) HS_R8(4) HS_R8(7) HS_R8(10)
@@ -1304,10 +1318,20 @@ void launch_rotate_batch(const hs_ctx* c, const RotItem* d_items, int B, const K
   ProfUnits units(B);
   const ModTab* tab = (const ModTab*)c->d_tab;
   HS_DISPATCH_XF(c->xf_variant, c, k_rot_intt, dim3(c->L, B), st, d_items, D, c->L, tab, c->logn);
-  if (c->logn == kSplitLogn && option(c, HS_OPT_MODUP_ACC) != 1) {
+  // register accumulators: whole limbs (one workgroup per CU) from 64 items per level on, halves
+  // (two per CU) below: measured 0.66 vs 0.68 ms at 128 items, 1.21 vs 1.29 at 256, 0.19 vs
+  // 0.18 at 32
+  const int acc_opt = option(c, HS_OPT_MODUP_ACC);
+  if (c->logn == kSplitLogn && (acc_opt == 3 || (acc_opt == 0 && B >= 64))) {
     ProfScope _prof("k_modup_ip_reg", st);
-    ensure_lds((const void*)k_modup_ip_reg, split_lds_bytes());
-    hipLaunchKernelGGL(k_modup_ip_reg, dim3(2 * (c->L + c->K), B, S.ndg), dim3(kSplitNT), split_lds_bytes(), st, d_items, (const u64*)D,
+    ensure_lds((const void*)k_modup_ip_reg<1>, lds_bytes(14));
+    hipLaunchKernelGGL(k_modup_ip_reg<1>, dim3(c->L + c->K, B, S.ndg), dim3(1024), lds_bytes(14), st, d_items, (const u64*)D, ACC, S,
+                       (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab);
+    HS_CHECK_HIP(hipGetLastError());
+  } else if (c->logn == kSplitLogn && acc_opt != 1) {
+    ProfScope _prof("k_modup_ip_reg", st);
+    ensure_lds((const void*)k_modup_ip_reg<2>, split_lds_bytes());
+    hipLaunchKernelGGL(k_modup_ip_reg<2>, dim3(2 * (c->L + c->K), B, S.ndg), dim3(kSplitNT), split_lds_bytes(), st, d_items, (const u64*)D,
                        ACC, S, (const double2*)c->d_up_inv, (const double2*)c->d_up_hat, tab);
     HS_CHECK_HIP(hipGetLastError());
   } else {

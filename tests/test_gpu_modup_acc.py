@@ -1,7 +1,8 @@
 """GPU: ModUp + key inner product of the one-workgroup-per-limb key switch at N = 2^14 with the
-accumulators in registers (HS_OPT_MODUP_ACC = 2, one workgroup per half of the target limb) and in
-memory (1, one workgroup per target limb): rotations equal the oracle's under both, for one-prime
-and two-prime digits, at level sizes with six, two and one digit groups."""
+accumulators in registers (HS_OPT_MODUP_ACC = 2, one workgroup per half of the target limb; 3, one
+workgroup of 1024 threads per target limb) and in memory (1): rotations equal the oracle's under
+all three, for one-prime and two-prime digits, at level sizes with six, two and one digit
+groups."""
 import numpy as np
 import pytest
 
@@ -41,7 +42,7 @@ def test_rotations_match_oracle_under_both_accumulator_forms(one_wg, p):
     for B in (3, 40, 80):   # digit groups per level: dnum, two, one (one-prime digits)
         idx = [i % n_distinct for i in range(B)]
         x = H.CtVec.from_host(g, np.concatenate([cts[i] for i in idx]), B)
-        for mode in (1, 2):
+        for mode in (1, 2, 3):
             H.set_option(H.OPT_MODUP_ACC, mode)
             for step in (1, 5):
                 print("B=%d mode=%d step=%d" % (B, mode, step), flush=True)
