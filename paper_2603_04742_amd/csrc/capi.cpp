@@ -542,7 +542,18 @@ static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const
   Alloc* A = al ? al : &c->pool;
   std::vector<DBuf> hold;
   DBuf X(A, (size_t)n * 4 * LN * sizeof(u64));
-  {
+  // the operands' limbs reach coefficient form in X: the one-workgroup N = 2^15 transform reads
+  // them where they are (row map), the others transform a gathered copy in place
+  const bool rowmap = ntt15_one_wg(c, (i64)n * 4 * L);
+  if (rowmap) {
+    for (int i0 = 0; i0 < n; i0 += kNttRowItems) {
+      const int m = std::min(kNttRowItems, n - i0);
+      NttRows rm;
+      rm.mode = 1; rm.per = 4 * L; rm.split = 2 * L;
+      for (int i = 0; i < m; i++) { rm.opA[i] = a[i0 + i]; rm.opB[i] = b[i0 + i]; }
+      launch_ntt15_rows(c, X.as<u64>() + (size_t)i0 * 4 * LN, (i64)m * 4 * L, L, 0, 1, rm, st);
+    }
+  } else {
     std::vector<const u64*> src(2 * n);
     std::vector<u64*> dst(2 * n);
     std::vector<size_t> words(2 * n, 2 * LN);
@@ -553,8 +564,8 @@ static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const
       dst[2 * i + 1] = X.as<u64>() + (size_t)i * 4 * LN + 2 * LN;
     }
     launch_copy_batch(src.data(), dst.data(), words.data(), 2 * n, st);
+    ntt_any(c, X.as<u64>(), (i64)n * 4 * L, L, 0, 1, st, hold, A);
   }
-  ntt_any(c, X.as<u64>(), (i64)n * 4 * L, L, 0, 1, st, hold, A);
   TensorConst C{};
   C.qhat_inv = (const double2*)c->d_dec_inv; C.qhat = c->d_dec_hat; C.Q = c->d_dec_q; C.halfQ = c->d_t_halfq; C.WQ = c->tq_words;
   C.mhat_inv = (const double2*)c->d_t_mhat_inv; C.mhat = c->d_t_mhat; C.M = c->d_t_m; C.halfM = c->d_t_halfm; C.WM = c->tm_words;
@@ -568,9 +579,18 @@ static void mul_ct_batch(hs_ctx* c, int n, const u64* const* a, const u64* const
   ntt_any(c, PROD.as<u64>(), (i64)n * 3 * T, T, 0, 1, st, hold, A);
   DBuf D4(A, (size_t)n * 4 * LN * sizeof(u64));
   launch_scale_round(c, C, PROD.as<u64>(), D4.as<u64>(), n, st);
-  ntt_any(c, D4.as<u64>(), (i64)n * 4 * L, L, 0, 0, st, hold, A);
   std::vector<std::vector<RotItem>> lv(1);
-  {
+  if (rowmap) {
+    // unrelinearised products go straight to their lazy outputs (row map), the others stay in D4
+    for (int i0 = 0; i0 < n; i0 += kNttRowItems) {
+      const int m = std::min(kNttRowItems, n - i0);
+      NttRows rm;
+      rm.mode = 2; rm.per = 4 * L;
+      for (int i = 0; i < m; i++) rm.out[i] = lazy ? lazy[i0 + i] : nullptr;
+      launch_ntt15_rows(c, D4.as<u64>() + (size_t)i0 * 4 * LN, (i64)m * 4 * L, L, 0, 0, rm, st);
+    }
+  } else {
+    ntt_any(c, D4.as<u64>(), (i64)n * 4 * L, L, 0, 0, st, hold, A);
     std::vector<const u64*> src;
     std::vector<u64*> dst;
     for (int i = 0; i < n; i++)

@@ -141,14 +141,22 @@ static constexpr int kN15Logn = 15, kN15NT = 1024;
 __host__ __device__ constexpr int n15_lds_doubles() { return lds_doubles(1 << (kN15Logn - 1)); }
 
 __global__ void __launch_bounds__(kN15NT) __attribute__((amdgpu_waves_per_eu(4)))
-k_ntt15(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab) {
+k_ntt15(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab, NttRows rows) {
   SMEM();
   constexpr int LOGN = kN15Logn, NT = kN15NT, H = 1 << (LOGN - 1), EH = H / NT;
   static_assert(EH == 16, "16 elements per thread and half");
   const int b = blockIdx.x;
   const ModTab t = tab[mod0 + b % nl];
   const ModD m = mod_of(t);
+  // the row's source and destination (the same limb of `data` unless the row map says otherwise;
+  // every element is read before any is written, so in place is fine)
+  const u64* src = data + ((size_t)b << LOGN);
   u64* p = data + ((size_t)b << LOGN);
+  if (rows.mode != 0) {
+    const int i = b / rows.per, q = b % rows.per;
+    if (rows.mode == 1) src = (q < rows.split ? rows.opA[i] + ((size_t)q << LOGN) : rows.opB[i] + ((size_t)(q - rows.split) << LOGN));
+    else if (rows.out[i]) p = rows.out[i] + ((size_t)q << LOGN);
+  }
   const int tid = threadIdx.x;
   const LdsHalf<LOGN - 1> Lh{smem};
   if (!inverse) {
@@ -157,8 +165,8 @@ k_ntt15(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab
     double a[EH], c[EH];
 #pragma unroll
     for (int k = 0; k < EH; k++) {
-      a[k] = u2d(gld(p + tid + k * NT));
-      c[k] = u2d(gld(p + tid + k * NT + H));
+      a[k] = u2d(gld(src + tid + k * NT));
+      c[k] = u2d(gld(src + tid + k * NT + H));
     }
     const double2 w1 = ldtw(tw, 1);
 #pragma unroll
@@ -191,7 +199,7 @@ k_ntt15(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab
   } else {
     const double2* tw = t.iv;
     const double2 ninv = t.ninv;
-    auto in = [p](int i) { return u2d(gld(p + i)); };
+    auto in = [src](int i) { return u2d(gld(src + i)); };
     double a[EH], c[EH];
     inv_round_g<LOGN, NT, 0, 3, 2, false>(elem_in(in), Lh, tw, ninv, m, 0, tid);
     __syncthreads();
@@ -1222,15 +1230,22 @@ static int cu_count(int device) {
   return v;
 }
 
+void launch_ntt15_rows(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, const NttRows& rows, hipStream_t st) {
+  if (nblocks <= 0) return;
+  HS_REQUIRE(c->logn == kN15Logn, HS_EPARAM, "one-workgroup N = 2^15 transform on another ring");
+  HS_REQUIRE(rows.mode == 0 || (rows.per > 0 && (nblocks + rows.per - 1) / rows.per <= kNttRowItems), HS_EPARAM, "row map too large");
+  const size_t lds = (size_t)n15_lds_doubles() * sizeof(double);
+  ProfUnits units(nblocks);   // limbs per launch, for the profile's roofline
+  ProfScope _prof("k_ntt15", st);
+  ensure_lds((const void*)k_ntt15, lds);
+  hipLaunchKernelGGL(k_ntt15, dim3((unsigned)nblocks), dim3(kN15NT), lds, st, data, nl, mod0, inverse, (const ModTab*)c->d_tab, rows);
+  HS_CHECK_HIP(hipGetLastError());
+}
+
 void launch_ntt(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, hipStream_t st) {
   if (nblocks <= 0) return;
   if (c->logn == kN15Logn) {
-    const size_t lds = (size_t)n15_lds_doubles() * sizeof(double);
-    ProfUnits units(nblocks);   // limbs per launch, for the profile's roofline
-    ProfScope _prof("k_ntt15", st);
-    ensure_lds((const void*)k_ntt15, lds);
-    hipLaunchKernelGGL(k_ntt15, dim3((unsigned)nblocks), dim3(kN15NT), lds, st, data, nl, mod0, inverse, (const ModTab*)c->d_tab);
-    HS_CHECK_HIP(hipGetLastError());
+    launch_ntt15_rows(c, data, nblocks, nl, mod0, inverse, NttRows{}, st);
     return;
   }
   const i64 grid = 2 * (i64)cu_count(c->device);

@@ -94,6 +94,18 @@ void upload_cdt(const u64* tab20);
 // fixed scratch region of the allocation-free entry point on the current device (noalloc.hip)
 int noalloc_scratch(void** ptr, size_t* bytes);
 void launch_fill_u64(u64* p, size_t n, u64 v, hipStream_t st);
+// Where each row (limb) of a batched N = 2^15 transform is read and written: mode 0 in place at
+// data + r N; mode 1 (gather) row r of item i = r / per reads limb q = r % per of opA[i] (q < split)
+// or limb q - split of opB[i] and writes data + r N; mode 2 (scatter) reads data + r N and writes
+// limb q of out[i] when out[i] is set, else in place.  At most kNttRowItems items per launch.
+static constexpr int kNttRowItems = 32;
+struct NttRows {
+  int mode = 0, per = 0, split = 0;
+  const u64* opA[kNttRowItems] = {};
+  const u64* opB[kNttRowItems] = {};
+  u64* out[kNttRowItems] = {};
+};
+void launch_ntt15_rows(const hs_ctx* c, u64* data, i64 nblocks, int nl, int mod0, int inverse, const NttRows& rows, hipStream_t st);
 // n device-to-device copies of words[j] u64 words (src[j] -> dst[j]; host arrays of device
 // pointers), batched into launches of up to 32 (one launch instead of one copy call each)
 void launch_copy_batch(const u64* const* src, u64* const* dst, const size_t* words, int n, hipStream_t st);
