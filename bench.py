@@ -30,7 +30,7 @@ WORKLOADS = {
     "zipf16k": ("zipf16k", 14, 6, 50, 1, 0,
                 "zipf16k: 16384x16384 int matrix, Zipf(1.2) column degrees, 8 nnz/column (131072 nnz), values and "
                 "vector in [-15,15]; ring N=16384, 6x50-bit data primes + 1 special prime, t=65537; paper aggregation "
-                "(variable chunk heights, masks); power-of-two rotation keys"),
+                "(variable chunk heights, masks); power-of-two rotation keys in both directions"),
     "small": ("small", 12, 2, 30, 1, 1,
               "small: 256x256 int matrix, 2% density uniform, values and vector in [-7,7]; ring N=4096, 2x30-bit + 1 "
               "special prime, t=65537; uniform aggregation"),
@@ -238,7 +238,7 @@ def main():
 def layout_variant(H, torch, ctx, w, tensors, out, want, n_steps, exact_keys, label):
     """The same protocol step under a variant that leaves the decrypted product unchanged:
     exact_keys adds a rotation key for every totalSum step of the matrix (one key switch per
-    logical rotation instead of one per binary digit of its step; the keys are generated once,
+    logical rotation instead of one per signed power-of-two digit of its step; the keys are generated once,
     before timing); a context made with slot_rows = 2 packs two row partitions per ciphertext."""
     rp, col, val, v = tensors
     ks2 = ctx.keygen(0x5EED + 1)

@@ -82,6 +82,7 @@ def lib():
             "orc_decode": (None, [vp, u64p, u64p]),
             "orc_plain_ntt": (None, [vp, u64p, u64p]),
             "orc_galois_elt": (ctypes.c_uint64, [vp, ctypes.c_int]),
+            "orc_rotation_digits": (ctypes.c_int, [vp, ctypes.c_uint64, i64p]),
             "orc_keygen": (None, [vp, ctypes.c_uint64]),
             "orc_export_sk": (None, [vp, i64p]),
             "orc_export_sk_ntt": (None, [vp, u64p]),
@@ -222,7 +223,16 @@ class Context:
         return out
 
     def galois_elt(self, i):
+        """Galois element of rotation key index i: left by 2^i for i < log2 N - 1, else right
+        by 2^(i - log2 N + 1)."""
         return int(lib().orc_galois_elt(self.h, i))
+
+    def rotation_digits(self, k):
+        """Signed power-of-two steps (+-2^i, lowest first) that a rotation by k mod N/2 applies
+        when no exact-step key is held: the non-adjacent form of k without a digit of N/2."""
+        out = np.zeros(64, np.int64)
+        n = lib().orc_rotation_digits(self.h, k % (self.N // 2), _p(out, i64p))
+        return [int(v) for v in out[:n]]
 
     # --- transforms
     def ntt(self, m, a):
@@ -273,6 +283,10 @@ class Context:
         return out
 
     def ksk(self, key_id):
+        """Key-switching key: key_id < 0 the relinearisation key, else rotation key index key_id
+        (left by 2^key_id below log2 N - 1, else right by 2^(key_id - log2 N + 1))."""
+        if key_id >= 2 * (self.logn - 1):
+            raise IndexError("no rotation key with index %d" % key_id)
         out = np.zeros(2 * self.dnum * (self.L + self.K) * self.N, np.uint64)
         lib().orc_export_ksk(self.h, key_id, _p(out, u64p))
         return out

@@ -17,6 +17,10 @@
  *   - Protocol and row-map scatter: Sec. 4.4, Alg. "Sparse Matrix-Vector Multiplication".
  *   - Row partitioning of large matrices: Sec. 4.7.
  *   - HE operations (Add, Mult, CMult, Rot): Sec. 2.1.
+   - Rotation keys: Sec. 5 (experimental setup) generates power-of-two rotation keys with its BFV
+     library; read here as that library's default set, powers of two in both directions, with a
+     rotation by any other amount applied as the signed power-of-two digits of its non-adjacent
+     form.
  * The paper leaves the HE scheme internals to its library; the conventions pinned here (prime
  * choice, NTT order, slot order, sampling, key switching, BFV multiplication) are listed in the
  * design notes and repeated next to the code that implements them.
@@ -403,7 +407,7 @@ struct Ctx {
   std::vector<i64> s;            /* secret, coefficient form */
   std::vector<u64> s_ntt;        /* [L+K+n_aux][N] */
   std::vector<u64> pk0, pk1;     /* [L][N] */
-  std::vector<std::vector<u64>> gk; /* per power-of-two rotation: [2][dnum][L+K][N] (b then a) */
+  std::vector<std::vector<u64>> gk; /* power-of-two rotation keys, index as rot_key_step: [2][dnum][L+K][N] (b then a) */
   std::map<u64, std::vector<u64>> gk_step; /* optional exact-step rotation keys, by step k */
   std::vector<u64> rk;           /* relinearisation key, same layout */
   u64 keyseed = 0;
@@ -411,14 +415,43 @@ struct Ctx {
 
 u64* limb(std::vector<u64>& v, u64 N, int i) { return v.data() + (u64)i * N; }
 
-/* Rotation key id i rotates the slots left by 2^i; its Galois element is 3^(2^i) mod 2N. */
-u64 galois_elt_pow2(const Ctx& c, int i) { return powmod(3, 1ULL << i, 2 * c.N); }
 /* A left rotation by k slots within each slot row has Galois element 3^k mod 2N (Sec. 2.1,
-   HE-Rot; 3 generates the slot-row rotations of the power-of-two cyclotomic ring). */
-u64 galois_elt_step(const Ctx& c, u64 k) { return powmod(3, k, 2 * c.N); }
-/* Sampling id of an exact-step rotation key: above the power-of-two ids (< 64) and the
+   HE-Rot; 3 generates the slot-row rotations of the power-of-two cyclotomic ring and has order
+   N/2 modulo 2N, so a right rotation by k is the left rotation by N/2 - k). */
+u64 galois_elt_step(const Ctx& c, u64 k) { return powmod(3, k % (c.N / 2), 2 * c.N); }
+/* Power-of-two rotation keys, both directions: index i < logn - 1 rotates left by 2^i, index
+   (logn - 1) + i rotates right by 2^i.  rot_key_step gives the signed step (+2^i or -2^i). */
+int n_pow2(const Ctx& c) { return c.logn - 1; }
+i64 rot_key_step(const Ctx& c, int idx) { return idx < n_pow2(c) ? (1LL << idx) : -(1LL << (idx - n_pow2(c))); }
+u64 galois_elt_key(const Ctx& c, int idx) {
+  i64 st = rot_key_step(c, idx);
+  return galois_elt_step(c, st > 0 ? (u64)st : c.N / 2 - (u64)(-st));
+}
+/* Sampling ids of the rotation keys: left 2^i -> i, right 2^i -> 64 + i; below the
+   relinearisation id (255). */
+u32 rot_key_id(const Ctx& c, int idx) { return idx < n_pow2(c) ? (u32)idx : 64u + (u32)(idx - n_pow2(c)); }
+/* Sampling id of an exact-step rotation key: above the power-of-two ids and the
    relinearisation id (255), one per step. */
 u32 step_key_id(u64 k) { return 256u + (u32)k; }
+
+/* The power-of-two key switches of a left rotation by k slots, 0 <= k < N/2, as key indices in
+   the order they are applied: the digits of the non-adjacent form of k (signed binary, no two
+   adjacent digits nonzero; Reitwiesner), lowest first.  A digit of +-N/2 rotates every row by a
+   whole row, the identity, and is left out. */
+std::vector<int> rotation_digits(const Ctx& c, u64 k) {
+  std::vector<int> out;
+  const int nl = n_pow2(c);
+  int i = 0;
+  while (k) {
+    if (k & 1) {
+      if ((k & 3) == 1) { if (i < nl) out.push_back(i); k -= 1; }       /* digit +1 */
+      else { if (i < nl) out.push_back(nl + i); k += 1; }                /* digit -1 */
+    }
+    k >>= 1;
+    i++;
+  }
+  return out;
+}
 
 /* Coefficient-domain automorphism a(X) -> a(X^g) mod (X^N + 1) over Z_m. */
 std::vector<u64> automorph_coeff(const std::vector<u64>& a, u64 g, u64 N, u64 m) {
@@ -582,9 +615,9 @@ void keygen(Ctx& c, u64 seed) {
   }
   c.gk.clear();
   c.gk_step.clear();
-  for (int i = 0; i + 1 < c.logn; i++) {
-    std::vector<i64> sg = automorph_int(c.s, galois_elt_pow2(c, i), N);
-    c.gk.push_back(make_ksk(c, sg, (u32)i));
+  for (int i = 0; i < 2 * n_pow2(c); i++) {
+    std::vector<i64> sg = automorph_int(c.s, galois_elt_key(c, i), N);
+    c.gk.push_back(make_ksk(c, sg, rot_key_id(c, i)));
   }
   /* s^2 as an integer negacyclic product (|coeff| <= N) */
   std::vector<i64> s2(N, 0);
@@ -838,13 +871,10 @@ std::vector<u64> rotate_with_key(const Ctx& c, const std::vector<u64>& ct, u64 g
     }
   return r;
 }
-std::vector<u64> rotate_pow2(const Ctx& c, const std::vector<u64>& ct, int i) {
-  return rotate_with_key(c, ct, galois_elt_pow2(c, i), c.gk[i]);
-}
 /* HE-Rot by k slots (left, within each row of N/2 slots).  With a rotation key for exactly k,
-   one key switch with it; otherwise the binary digits of k in ascending order, each one
-   power-of-two rotation with its own key.  Both decrypt to the same rotated slots; their noise
-   (and so their limbs) differ. */
+   one key switch with it; otherwise the signed power-of-two digits of k (rotation_digits), each
+   one rotation with its own key.  Both decrypt to the same rotated slots; their noise (and so
+   their limbs) differ. */
 std::vector<u64> rotate(const Ctx& c, const std::vector<u64>& ct, u64 k, int* nks) {
   std::vector<u64> r(ct);
   k %= c.N / 2;
@@ -853,8 +883,10 @@ std::vector<u64> rotate(const Ctx& c, const std::vector<u64>& ct, u64 k, int* nk
     if (nks) (*nks)++;
     return rotate_with_key(c, r, galois_elt_step(c, k), it->second);
   }
-  for (int i = 0; i + 1 < c.logn; i++)
-    if ((k >> i) & 1) { r = rotate_pow2(c, r, i); if (nks) (*nks)++; }
+  for (int idx : rotation_digits(c, k)) {
+    r = rotate_with_key(c, r, galois_elt_key(c, idx), c.gk[idx]);
+    if (nks) (*nks)++;
+  }
   return r;
 }
 
@@ -1138,7 +1170,15 @@ void orc_decode(void* h, const u64* m, u64* slots) {
 void orc_plain_ntt(void* h, const u64* m, u64* out) {
   Ctx* c = (Ctx*)h; std::vector<u64> s(m, m + c->N); auto r = plain_ntt(*c, s); memcpy(out, r.data(), r.size() * 8);
 }
-u64 orc_galois_elt(void* h, int i) { return galois_elt_pow2(*(Ctx*)h, i); }
+/* Galois element of rotation key index i (left 2^i for i < logn - 1, else right 2^(i - logn + 1)). */
+u64 orc_galois_elt(void* h, int i) { return galois_elt_key(*(Ctx*)h, i); }
+/* The key switches of a rotation by k (mod N/2) without an exact-step key, as signed steps
+   +-2^i in the order applied; returns the count (at most log2 N). */
+int orc_rotation_digits(void* h, u64 k, i64* out) {
+  Ctx* c = (Ctx*)h; auto v = rotation_digits(*c, k % (c->N / 2));
+  for (size_t i = 0; i < v.size(); i++) out[i] = rot_key_step(*c, v[i]);
+  return (int)v.size();
+}
 
 void orc_keygen(void* h, u64 seed) { keygen(*(Ctx*)h, seed); }
 void orc_export_sk(void* h, i64* s) { Ctx* c = (Ctx*)h; memcpy(s, c->s.data(), c->N * 8); }
@@ -1147,7 +1187,8 @@ void orc_export_pk(void* h, u64* out) {
   Ctx* c = (Ctx*)h; u64 n = (u64)c->L * c->N;
   memcpy(out, c->pk0.data(), n * 8); memcpy(out + n, c->pk1.data(), n * 8);
 }
-/* key_id < 0: relinearisation key; else rotation key for 2^key_id.  Layout [2][dnum][L+K][N]. */
+/* key_id < 0: relinearisation key; else rotation key index key_id (left by 2^key_id below
+   log2 N - 1, else right by 2^(key_id - log2 N + 1)).  Layout [2][dnum][L+K][N]. */
 void orc_export_ksk(void* h, int key_id, u64* out) {
   Ctx* c = (Ctx*)h; const std::vector<u64>& k = key_id < 0 ? c->rk : c->gk[key_id];
   memcpy(out, k.data(), k.size() * 8);

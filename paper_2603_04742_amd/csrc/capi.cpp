@@ -180,18 +180,48 @@ static void compute_cdt(u64 out[20]) {
 enum : u32 { P_SK = 1, P_PK_A = 2, P_PK_E = 3, P_KSK_A = 4, P_KSK_E = 5, P_ENC_U = 6, P_ENC_E0 = 7, P_ENC_E1 = 8 };
 static const u32 RELIN_ID = 255;
 
-static u64 galois_pow2(const hs_ctx* c, int i) { return pow_mod(3, 1ULL << i, 2 * c->N); }
-// Left rotation by k slots within each slot row: Galois element 3^k mod 2N (Sec. 2.1, HE-Rot).
-static u64 galois_step(const hs_ctx* c, i64 k) { return pow_mod(3, (u64)k, 2 * c->N); }
+// Left rotation by k slots within each slot row (k < 0: right by -k): Galois element 3^k mod 2N
+// (Sec. 2.1, HE-Rot); 3 has order N/2 modulo 2N, so k is taken mod N/2.
+static u64 galois_step(const hs_ctx* c, i64 k) {
+  const i64 half = (i64)c->N / 2;
+  return pow_mod(3, (u64)(((k % half) + half) % half), 2 * c->N);
+}
+// Power-of-two rotation keys in both directions (the power-of-two key set of Sec. 5, its BFV
+// library's default of left and right powers): key index i < log2 N - 1 rotates left by 2^i,
+// index log2 N - 1 + i right by 2^i.  Sampling ids: i, and 64 + i; RELIN_ID above them.
+static int n_pow2(const hs_ctx* c) { return c->logn - 1; }
+static i64 key_index_step(const hs_ctx* c, int idx) { return idx < n_pow2(c) ? (1LL << idx) : -(1LL << (idx - n_pow2(c))); }
+static u32 key_index_id(const hs_ctx* c, int idx) { return idx < n_pow2(c) ? (u32)idx : 64u + (u32)(idx - n_pow2(c)); }
 // Sampling id of the exact-step rotation key for k: above the power-of-two ids and RELIN_ID.
 static u32 step_key_id(i64 k) { return 256u + (u32)k; }
 static bool is_pow2(i64 k) { return k > 0 && (k & (k - 1)) == 0; }
-// Key of a rotation micro-op: a power-of-two key, or the exact-step key for k.
+// Key of a rotation micro-op: a power-of-two key (+-2^i), or the exact-step key for k.
 static const u64* rotation_key(const hs_keyset* ks, i64 step) {
   if (is_pow2(step)) return ks->gk[__builtin_ctzll((unsigned long long)step)];
+  if (is_pow2(-step)) return ks->gk[n_pow2(ks->ctx) + __builtin_ctzll((unsigned long long)-step)];
   auto it = ks->step_keys.find(step);
   if (it == ks->step_keys.end()) throw Error{HS_EKEY, "internal: no rotation key for a planned step"};
   return it->second;
+}
+// The key switches of a left rotation by k slots, 0 <= k < N/2, in the order they are applied:
+// one with the exact-step key when the key-set holds one for k; otherwise the digits of the
+// non-adjacent form of k (signed binary digits, no two adjacent ones nonzero, which has the
+// fewest nonzero digits of any signed binary expansion), lowest first, each a power-of-two
+// rotation +-2^i; a digit of N/2 rotates by a whole row, the identity, and is left out.
+static std::vector<i64> rotation_digits(const hs_ctx* c, const hs_keyset* ks, i64 k) {
+  std::vector<i64> out;
+  if (!is_pow2(k) && ks->step_keys.count(k)) {
+    out.push_back(k);
+    return out;
+  }
+  const i64 half = (i64)c->N / 2;
+  for (i64 v = k, bit = 1; v; v >>= 1, bit <<= 1) {
+    if (!(v & 1)) continue;
+    const i64 z = (v & 3) == 1 ? 1 : -1;
+    if (bit < half) out.push_back(z * bit);
+    v -= z;
+  }
+  return out;
 }
 
 // ------------------------------------------------------------------ key generation
@@ -290,14 +320,9 @@ static std::vector<MicroOp> total_sum_program(const hs_ctx* c, const hs_keyset* 
   const i64 half = (i64)c->N / 2;
   auto rotate_into = [&](int src, i64 amount, int addend) {
     // rotation by `amount` as one key switch when the key-set holds a key for the whole step,
-    // else as its binary digits (ascending); the last one lands in the W buffer that is not the
-    // current accumulator, plus `addend`
-    const i64 k = amount % half;
-    std::vector<i64> bits;
-    if (!is_pow2(k) && ks->step_keys.count(k)) bits.push_back(k);
-    else
-      for (int i = 0; i + 1 < c->logn; i++)
-        if ((k >> i) & 1) bits.push_back(1LL << i);
+    // else as its signed power-of-two digits (rotation_digits); the last one lands in the W
+    // buffer that is not the current accumulator, plus `addend`
+    const std::vector<i64> bits = rotation_digits(c, ks, amount % half);
     if (bits.empty()) throw Error{HS_EINVAL, "internal: zero rotation in totalSum"};
     const int dst_w = (w == 1) ? 2 : 1;
     int cur = src;
@@ -790,7 +815,8 @@ int hs_keygen(hs_ctx* c, uint64_t seed, void* stream, hs_keyset** out) {
         launch_ksk_limbs(c, dargs.as<KskArgs>(), (int)args.size(), st);
       }
       HS_CHECK_HIP(hipStreamSynchronize(st));
-      for (int i = 0; i + 1 < c->logn; i++) ks->gk.push_back(make_ksk(c, ks, (u32)i, 1, (u32)galois_pow2(c, i), st));
+      for (int i = 0; i < 2 * n_pow2(c); i++)
+        ks->gk.push_back(make_ksk(c, ks, key_index_id(c, i), 1, (u32)galois_step(c, key_index_step(c, i)), st));
       ks->rk = make_ksk(c, ks, RELIN_ID, 2, 0, st);
     } catch (...) {
       hs_keyset_destroy(ks);
@@ -1544,7 +1570,7 @@ int hs_autotune(hs_ctx* c, const hs_keyset* ks, void* stream, double* report, in
       items[i].in = in.as<u64>() + (size_t)(i % kIn) * CW;
       items[i].out = outb.as<u64>() + (size_t)i * CW;
       items[i].key = ks->gk[0];
-      items[i].galois = (u32)galois_pow2(c, 0);
+      items[i].galois = (u32)galois_step(c, 1);
     }
     DBuf ditems(&c->pool, items.size() * sizeof(RotItem));
     h2d(ditems.as<RotItem>(), items.data(), items.size(), st);
@@ -1972,11 +1998,7 @@ int hs_rotate(hs_ctx* c, const hs_keyset* ks, const hs_ctvec* in, int64_t k, voi
       u64* cur = r->d;
       u64* other = tmp.as<u64>();
       std::vector<std::vector<RotItem>> levels;
-      std::vector<i64> steps;  // one exact-step key switch, or the binary digits of kk
-      if (!is_pow2(kk) && ks->step_keys.count(kk)) steps.push_back(kk);
-      else
-        for (int i = 0; i + 1 < c->logn; i++)
-          if ((kk >> i) & 1) steps.push_back(1LL << i);
+      const std::vector<i64> steps = rotation_digits(c, ks, kk);  // one exact-step key switch, or the signed digits
       for (i64 step : steps) {
         std::vector<RotItem> items;
         for (i64 g = 0; g < in->n; g++) {
@@ -2203,11 +2225,13 @@ int hs_diag_encrypt(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const int6
 }
 
 // Rotations of the vector blocks: Rot(x_bj, d) for every (bj, d) a diagonal needs.  With an
-// exact-step key for d, one key switch from x_bj; otherwise the binary digits of d in ascending
-// order, so Rot(x_bj, d) = Rot_{2^h}(Rot(x_bj, d - 2^h)) with h the top bit of d: every such
-// partial rotation is computed once per block column and shared.  Level h holds the partial
-// rotations whose top bit is h (the exact-step ones go to level 0); levels are cut into batches of
-// at most kDiagBatch key switches.
+// exact-step key for d, one key switch from x_bj; otherwise the signed power-of-two digits of d
+// (rotation_digits, lowest first), so Rot(x_bj, v) = Rot_z(Rot(x_bj, v - z)) for every partial
+// sum v of those digits with z its top digit: every such partial rotation is computed once per
+// block column and shared (a partial sum of a non-adjacent form is the non-adjacent form of its
+// value, so the partial rotation of a value is the same whichever step reaches it).  Level h
+// holds the partial rotations whose top digit is +-2^h (the exact-step ones go to level 0);
+// levels are cut into batches of at most kDiagBatch key switches.
 static constexpr size_t kDiagBatch = 256;
 int hs_diag_spmv(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const hs_ctvec* x, void* stream, hs_ctvec** y) {
   return guarded([&] {
@@ -2220,10 +2244,13 @@ int hs_diag_spmv(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const hs_ctve
     const i64 B = D->B, nd = (i64)D->key.size() / 3;
     hs_ctvec* r = new_ctvec(c, D->nrb);
     try {
-      // per block column: slot of each partial (digit) rotation and each exact-step rotation
-      // (a step with an exact key may also be a partial rotation of another step's digits: the
-      // two are different ciphertexts and both are kept)
-      std::vector<std::vector<int>> tree(D->ncb, std::vector<int>(B, -1)), direct(D->ncb, std::vector<int>(B, -1));
+      // per block column: slot of each partial (digit) rotation, by its value, and of each
+      // exact-step rotation (a step with an exact key may also be a partial rotation of another
+      // step's digits: the two are different ciphertexts and both are kept)
+      struct Part { int buf; i64 parent, digit; };   // parent 0: the vector block itself
+      std::vector<std::map<i64, Part>> tree(D->ncb);
+      std::vector<std::vector<int>> direct(D->ncb, std::vector<int>(B, -1));
+      std::vector<std::vector<i64>> whole(D->ncb, std::vector<i64>(B, 0));   // d -> its last partial sum
       std::vector<std::vector<char>> seen(D->ncb, std::vector<char>(B, 0));
       int nbuf = 0, nlog = 0;
       for (i64 k = 0; k < nd; k++) {
@@ -2232,18 +2259,22 @@ int hs_diag_spmv(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const hs_ctve
         seen[bj][d] = 1;
         nlog++;
         if (!is_pow2(d) && ks->step_keys.count(d)) { direct[bj][d] = nbuf++; continue; }
-        for (i64 p = d; p && tree[bj][p] < 0; p &= ~(1LL << (63 - __builtin_clzll((u64)p)))) tree[bj][p] = nbuf++;
+        i64 v = 0;
+        for (i64 z : rotation_digits(c, ks, d)) {
+          if (!tree[bj].count(v + z)) tree[bj][v + z] = Part{nbuf++, v, z};
+          v += z;
+        }
+        if (v == 0) throw Error{HS_EINVAL, "internal: diagonal offset that rotates by whole rows"};
+        whole[bj][d] = v;
       }
       DBuf rot(&c->pool, (size_t)std::max(nbuf, 1) * CW * sizeof(u64));
       auto at = [&](int idx) { return rot.as<u64>() + (size_t)idx * CW; };
-      int top = 0;
-      while ((2LL << top) < B) top++;
       std::vector<std::vector<RotItem>> levels;
       auto push = [&](std::vector<RotItem>& lv, const RotItem& it) {
         lv.push_back(it);
         if (lv.size() == kDiagBatch) { levels.push_back(lv); lv.clear(); }
       };
-      for (int h = 0; h <= top; h++) {
+      for (int h = 0; h < n_pow2(c); h++) {
         std::vector<RotItem> lv;
         for (int bj = 0; bj < D->ncb; bj++) {
           const u64* xb = x->d + (size_t)bj * CW;
@@ -2255,14 +2286,14 @@ int hs_diag_spmv(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const hs_ctve
                 it.key = rotation_key(ks, d); it.galois = (u32)galois_step(c, d);
                 push(lv, it);
               }
-          for (i64 d = 1LL << h; d < std::min<i64>(2LL << h, B); d++)
-            if (tree[bj][d] >= 0) {
-              const i64 p = d - (1LL << h);
-              RotItem it{};
-              it.in = p ? at(tree[bj][p]) : xb; it.out = at(tree[bj][d]); it.addend = nullptr;
-              it.key = rotation_key(ks, 1LL << h); it.galois = (u32)galois_step(c, 1LL << h);
-              push(lv, it);
-            }
+          for (const auto& kv : tree[bj]) {
+            const Part& pt = kv.second;
+            if ((pt.digit < 0 ? -pt.digit : pt.digit) != (1LL << h)) continue;
+            RotItem it{};
+            it.in = pt.parent ? at(tree[bj].at(pt.parent).buf) : xb; it.out = at(pt.buf); it.addend = nullptr;
+            it.key = rotation_key(ks, pt.digit); it.galois = (u32)galois_step(c, pt.digit);
+            push(lv, it);
+          }
         }
         if (!lv.empty()) levels.push_back(lv);
       }
@@ -2275,7 +2306,7 @@ int hs_diag_spmv(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const hs_ctve
         std::vector<u64> words(std::max<i64>(nd, 1), 0);
         for (i64 k = 0; k < nd; k++) {
           const i64 bj = D->key[3 * k + 1], d = D->key[3 * k + 2];
-          const u64* src = !d ? x->d + (size_t)bj * CW : at(direct[bj][d] >= 0 ? direct[bj][d] : tree[bj][d]);
+          const u64* src = !d ? x->d + (size_t)bj * CW : at(direct[bj][d] >= 0 ? direct[bj][d] : tree[bj].at(whole[bj][d]).buf);
           words[k] = (u64)(uintptr_t)src;
         }
         const size_t w0 = words.size();

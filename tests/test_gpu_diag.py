@@ -3,7 +3,8 @@ the oracle, bit for bit, through the C ABI.
 
 Every diagonal plaintext, the diagonal keys, the encrypted vector blocks, every result limb and the
 decrypted product must equal the oracle's; with exact-step keys for some of the steps, rotations
-by those steps take one key switch and the rest keep the binary digits, as in the oracle.
+by those steps take one key switch and the rest keep the signed power-of-two digits, as in the
+oracle.
 """
 import numpy as np
 import pytest
@@ -88,12 +89,12 @@ def check(p, w, step_keys=None, seed=41):
     H.diag_decrypt(g, kg, D, y, out)
     assert np.array_equal(out.cpu().numpy(), W.spmv_mod_t(w))
     assert np.array_equal(out.cpu().numpy(), OD.decrypt_result(oy))
-    return D, cnt
+    return D, cnt, o
 
 
-def expected_key_switches(D, held=()):
-    """One per partial rotation of the binary-digit tree per block column, plus one per step
-    rotated with its exact key."""
+def expected_key_switches(D, o, held=()):
+    """One per distinct partial sum of the oracle's rotation digits (lowest first) per block
+    column, plus one per step rotated with its exact key."""
     keys = D.keys()
     want = 0
     for bj in range(D.info()[2]):
@@ -102,9 +103,10 @@ def expected_key_switches(D, held=()):
             if d in held:
                 want += 1
                 continue
-            while d:
-                nodes.add(d)
-                d &= ~(1 << (d.bit_length() - 1))
+            v = 0
+            for z in o.rotation_digits(d):
+                v += z
+                nodes.add(v)
         want += len(nodes)
     return want
 
@@ -112,8 +114,8 @@ def expected_key_switches(D, held=()):
 @pytest.mark.parametrize("case", ["tiny", "ragged", "small", "rect", "tall"])
 def test_diagonal_method_matches_oracle(case):
     p, w = workload(case)
-    D, cnt = check(p, w)
-    assert cnt["key_switches"] == expected_key_switches(D)
+    D, cnt, o = check(p, w)
+    assert cnt["key_switches"] == expected_key_switches(D, o)
 
 
 @pytest.mark.parametrize("case", ["empty", "one", "nocols", "emptyrows"])
@@ -128,9 +130,9 @@ def test_diagonal_method_with_exact_step_keys():
     that also have an exact key, computed both ways as the oracle does)."""
     p, w = workload("tiny")
     pick = []
-    D, cnt = check(p, w, step_keys=lambda steps: pick.extend([s for s in steps if s & (s - 1)][::3]) or pick)
+    D, cnt, o = check(p, w, step_keys=lambda steps: pick.extend([s for s in steps if s & (s - 1)][::3]) or pick)
     assert any(d in pick for d in (3, 5, 6, 7, 9, 10, 11)), "no exact-step key on a partial rotation"
-    assert cnt["key_switches"] == expected_key_switches(D, set(pick))
+    assert cnt["key_switches"] == expected_key_switches(D, o, set(pick))
 
 
 def test_diagonal_pack_rejects_bad_columns():

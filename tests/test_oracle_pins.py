@@ -351,6 +351,95 @@ def test_exact_step_rotation_keys():
         assert np.array_equal(c.decode(c.decrypt(c.rotate(cx, k))), want), k
 
 
+def test_rotation_keys_both_directions():
+    """Power-of-two rotation keys in both directions (the power-of-two key set of Sec. 5, read as
+    its BFV library's default of left and right powers): key index i < log2 N - 1 has Galois
+    element 3^(2^i) mod 2N and index log2 N - 1 + i the inverse of 3^(2^i); each key holds
+    b + a s = e + P sigma_g(s) on its digit, and one key switch with a right key rotates the slot
+    rows right by 2^i."""
+    c = small_ctx(logn=6, L=2, bits=30, K=1)
+    N, h, L, K = c.N, c.N // 2, c.L, c.K
+    nl = c.logn - 1
+    mods = c.moduli()
+    P = math.prod(mods[L:L + K])
+    s = [int(v) for v in c.sk()]
+    for idx in (0, 2, nl - 1, nl, nl + 1, 2 * nl - 1):
+        g = c.galois_elt(idx)
+        want = pow(3, 1 << idx, 2 * N) if idx < nl else pow(pow(3, 1 << (idx - nl), 2 * N), -1, 2 * N)
+        assert g == want, idx
+        key = c.ksk(idx).reshape(2, c.dnum, L + K, N)
+        sp = coeff_automorph(s, g, 2 ** 62)
+        sp = [v - 2 ** 62 if v > 2 ** 61 else v for v in sp]
+        for j in range(c.dnum):
+            for m in range(L + K):
+                q = mods[m]
+                b = [int(v) for v in c.intt(m, key[0, j, m].copy())]
+                a = [int(v) for v in c.intt(m, key[1, j, m].copy())]
+                e = [(x + y) % q for x, y in zip(b, negacyclic(a, [v % q for v in s], q))]
+                if m < L and m // K == j:
+                    e = [(x - P * v) % q for x, v in zip(e, sp)]
+                e = [v - q if v > q // 2 else v for v in e]
+                assert max(abs(v) for v in e) <= 19, (idx, j, m)
+    with pytest.raises(IndexError):
+        c.ksk(2 * nl)
+    g = np.random.default_rng(4)
+    x = g.integers(0, T, N)
+    cx = c.encrypt(c.encode(x), 6, 0)
+    qv = np.repeat(np.array(mods[:L] * 2, dtype=object), N)
+    for i in (0, 3):
+        gelt = c.galois_elt(nl + i)
+        a0 = c.automorph_ntt(cx[:L * N], gelt)
+        ks = c.keyswitch(c.automorph_ntt(cx[L * N:], gelt), nl + i)
+        out = np.concatenate([a0.astype(object) + ks[:L * N].astype(object), ks[L * N:].astype(object)])
+        out = np.array([int(a) % int(q) for a, q in zip(out, qv)], np.uint64)
+        assert np.array_equal(out, c.rotate(cx, h - (1 << i))), i
+        want = np.concatenate([np.roll(x[:h], 1 << i), np.roll(x[h:], 1 << i)])
+        assert np.array_equal(c.decode(c.decrypt(out)), want), i
+
+
+@pytest.mark.parametrize("logn", [6, 9])
+def test_rotation_digits_fewest_key_switches(logn):
+    """A rotation by k without an exact-step key applies signed powers of two below N/2, lowest
+    first, that sum to k mod N/2 with no two at adjacent positions (the non-adjacent form), and no
+    sequence of power-of-two keys in either direction reaches k in fewer key switches (breadth-first
+    search over the N/2 slot-row rotations)."""
+    c = O.Context(logn, 2, 30, 1)
+    h = c.N // 2
+    gens = [1 << i for i in range(logn - 1)] + [-(1 << i) for i in range(logn - 1)]
+    dist = {0: 0}
+    frontier = [0]
+    while frontier:
+        nxt = []
+        for v in frontier:
+            for s_ in gens:
+                w = (v + s_) % h
+                if w not in dist:
+                    dist[w] = dist[v] + 1
+                    nxt.append(w)
+        frontier = nxt
+    for k in range(h):
+        d = c.rotation_digits(k)
+        assert sum(d) % h == k, k
+        assert all(v in gens for v in d), k
+        pos = [abs(v).bit_length() - 1 for v in d]
+        assert all(b - a >= 2 for a, b in zip(pos, pos[1:])), (k, d)
+        assert len(d) == dist[k], (k, d, dist[k])
+    assert c.rotation_digits(h - 1) == [-1] and c.rotation_digits(3) == [-1, 4] and c.rotation_digits(0) == []
+
+
+def test_rotation_by_every_amount_decrypts():
+    """Every left rotation amount at N = 64 (power-of-two keys in both directions, digits of the
+    non-adjacent form) decrypts to the slot rows rotated left by k, with one key switch per digit."""
+    c = small_ctx(logn=6, L=2, bits=30, K=1)
+    N, h = c.N, c.N // 2
+    g = np.random.default_rng(12)
+    x = g.integers(0, T, N)
+    cx = c.encrypt(c.encode(x), 9, 0)
+    for k in range(h):
+        want = np.concatenate([np.roll(x[:h], -k), np.roll(x[h:], -k)])
+        assert np.array_equal(c.decode(c.decrypt(c.rotate(cx, k))), want), k
+
+
 def test_total_sum_steps_follow_the_recurrence():
     c = small_ctx(logn=8)
     h = c.N // 2
@@ -765,7 +854,7 @@ def test_spmv_small_workload_uniform_aggregation():
 
 def test_spmv_with_exact_step_keys_one_key_switch_per_rotation():
     """With a key for every totalSum step the decrypted product is unchanged and every logical
-    rotation costs one key switch instead of one per binary digit of its step."""
+    rotation costs one key switch instead of one per signed power-of-two digit of its step."""
     g = np.random.default_rng(17)
     rp, col, val = W.uniform_matrix(300, 200, 1200, 15, g)
     w = dict(R=300, C=200, row_ptr=rp, col=col, val=val, v=g.integers(-15, 16, 200))
