@@ -30,7 +30,7 @@ WORKLOADS = {
     "zipf16k": ("zipf16k", 14, 6, 50, 1, 0,
                 "zipf16k: 16384x16384 int matrix, Zipf(1.2) column degrees, 8 nnz/column (131072 nnz), values and "
                 "vector in [-15,15]; ring N=16384, 6x50-bit data primes + 1 special prime, t=65537; paper aggregation "
-                "(variable chunk heights, masks); power-of-two rotation keys in both directions"),
+                "(variable chunk heights, masks); power-of-two rotation keys"),
     "small": ("small", 12, 2, 30, 1, 1,
               "small: 256x256 int matrix, 2% density uniform, values and vector in [-7,7]; ring N=4096, 2x30-bit + 1 "
               "special prime, t=65537; uniform aggregation"),
@@ -176,8 +176,8 @@ def main():
     per_item = keyswitch_kernel_bytes(L, K, N)
     ks_unit = keyswitch_unit_bytes(L, K, N)
     ks_ms = sum(v[1] for k, v in prof.items() if k in per_item) / args.steps
-    dom = max(prof.items(), key=lambda kv: kv[1][1])[0]
-    roof = keyswitch_roofline(prof, args.steps, counters["key_switches"], L, K, N, measured_traffic(dom))
+    dom, (dcount, _, dunits) = max(prof.items(), key=lambda kv: kv[1][1])
+    roof = keyswitch_roofline(prof, args.steps, counters["key_switches"], L, K, N, measured_traffic(dom, dunits / dcount))
     keyswitch = {"key_switches_per_step": counters["key_switches"], "ms_per_step": round(ks_ms, 4),
                  "algorithmic_GBps": round(counters["key_switches"] * ks_unit / (ks_ms * 1e-3) / 1e9, 1),
                  "algorithmic_bytes_per_key_switch": ks_unit}
@@ -214,11 +214,12 @@ def main():
     }
     result["keyswitch_saturated"] = keyswitch_saturated(H, torch, ctx, ks, L, K, 1 << logn)
     tens = (rp, col, val, v)
-    result["exact_step_keys"] = layout_variant(H, torch, ctx, w, tens, out, want, args.steps, True, "exact-step keys")
+    result["exact_step_keys"] = layout_variant(H, torch, ctx, w, tens, out, want, args.steps, "exact", "exact-step keys")
+    result["signed_digit_keys"] = layout_variant(H, torch, ctx, w, tens, out, want, args.steps, "signed", "signed-digit keys")
     ctx2 = H.Context(logn, L, bits, K, agg_mode=agg, slot_rows=2)
     H.autotune(ctx2, ctx2.keygen(0x5EED + 2))
-    result["two_slot_rows"] = layout_variant(H, torch, ctx2, w, tens, out, want, args.steps, False, "two slot rows")
-    result["two_slot_rows_exact_step_keys"] = layout_variant(H, torch, ctx2, w, tens, out, want, args.steps, True,
+    result["two_slot_rows"] = layout_variant(H, torch, ctx2, w, tens, out, want, args.steps, None, "two slot rows")
+    result["two_slot_rows_exact_step_keys"] = layout_variant(H, torch, ctx2, w, tens, out, want, args.steps, "exact",
                                                              "two slot rows + exact-step keys")
     ctx2.close()
     if not args.no_diagonal:
@@ -235,18 +236,23 @@ def main():
     print(json.dumps(result), flush=True)
 
 
-def layout_variant(H, torch, ctx, w, tensors, out, want, n_steps, exact_keys, label):
+def layout_variant(H, torch, ctx, w, tensors, out, want, n_steps, keys, label):
     """The same protocol step under a variant that leaves the decrypted product unchanged:
-    exact_keys adds a rotation key for every totalSum step of the matrix (one key switch per
-    logical rotation instead of one per signed power-of-two digit of its step; the keys are generated once,
-    before timing); a context made with slot_rows = 2 packs two row partitions per ciphertext."""
+    keys = "exact" adds a rotation key for every totalSum step of the matrix (one key switch per
+    logical rotation instead of one per binary digit of its step), keys = "signed" adds the right
+    rotation keys 2^i (one key switch per signed digit of the non-adjacent form of a step); keys
+    are generated once, before timing.  A context made with slot_rows = 2 packs two row
+    partitions per ciphertext."""
     rp, col, val, v = tensors
     ks2 = ctx.keygen(0x5EED + 1)
     steps = H.Matrix(ctx, w["R"], w["C"], rp, col, val).rotation_steps()
     n_new = 0
-    if exact_keys:
+    if keys == "exact":
         ks2.add_rotation_keys(steps)
         n_new = sum(1 for k in steps if k & (k - 1))
+    elif keys == "signed":
+        ks2.add_right_rotation_keys()
+        n_new = ctx.N.bit_length() - 2
 
     def step(i):
         m = H.Matrix(ctx, w["R"], w["C"], rp, col, val)
@@ -277,8 +283,10 @@ def layout_variant(H, torch, ctx, w, tensors, out, want, n_steps, exact_keys, la
     r = {"value": round(1000.0 / ms, 3), "unit": "SpMV/s", "ms_per_step": round(ms, 3),
          "he_spmv_ms": round(he_ms, 3), "chunk_ciphertexts": m.info()[1], "result_ciphertexts": m.groups(),
          "key_switches_per_spmv": counters["key_switches"], "rotations_per_spmv": counters["rotations"]}
-    if exact_keys:
+    if keys == "exact":
         r.update({"rotation_steps": steps, "extra_keys": n_new, "extra_key_bytes": n_new * key_bytes})
+    elif keys == "signed":
+        r.update({"extra_keys": n_new, "extra_key_bytes": n_new * key_bytes})
     return r
 
 
@@ -504,9 +512,10 @@ def keyswitch_saturated(H, torch, ctx, ks, L, K, N, B=128, reps=5):
             "kernel_ms": {k: round(ms / reps, 4) for k, (c, ms) in sorted(ks_prof.items(), key=lambda kv: -kv[1][1])}}
 
 
-def measured_traffic(kernel):
+def measured_traffic(kernel, items_per_launch=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
-    the summary is for another kernel or the kernel sources changed since the counters were taken."""
+    the summary is for another kernel, the kernel sources changed since the counters were taken, or
+    its launches processed another number of rotation items on average (another rotation plan)."""
     import hashlib
     here = os.path.dirname(os.path.abspath(__file__))
     try:
@@ -521,6 +530,9 @@ def measured_traffic(kernel):
             continue
         kv = dict(f.split("=", 1) for f in line.split()[1:])
         if kv.get("kernel") == kernel and kv.get("sources_sha256") == h.hexdigest()[:16]:
+            ipl = kv.get("items_per_launch")
+            if items_per_launch is not None and (ipl is None or abs(float(ipl) - items_per_launch) > 0.01 * items_per_launch):
+                return None
             return int(kv["traffic_bytes_per_launch"])
     return None
 

@@ -107,32 +107,41 @@ int hs_ctx_tensor_widths(const hs_ctx* ctx, int64_t out[7]);
 int hs_cdt_table(uint64_t out[20]);
 
 /* ---------------------------------------------------------------- keys (Sec. 5 setup: one
-   relinearisation key set plus power-of-two rotation keys, read as its BFV library's default set
-   of left and right powers of two) */
+   relinearisation key set plus power-of-two rotation keys) */
 /* Generate a key-set from a 64-bit seed (ChaCha20 streams, RFC 8439): ternary secret s, public
    key (-a s + e, a), rotation keys index i = 0 .. log_n - 2 for left rotations by 2^i (Galois
-   elements 3^(2^i) mod 2N) and index log_n - 1 + i for right rotations by 2^i (3^(-2^i) mod 2N),
-   and a relinearisation key for s^2.  Key-switching keys use the hybrid form with
+   elements 3^(2^i) mod 2N), and a relinearisation key for s^2.  Key-switching keys use the hybrid form with
    digits of K data primes and special modulus P.  The key-set holds the secret key too: it plays
    both the key holder and the evaluation-key owner of the protocol. */
 int hs_keygen(hs_ctx* ctx, uint64_t seed, void* stream, hs_keyset** out);
 void hs_keyset_destroy(hs_keyset* ks);
 /* Copy key material to host memory, for verification.  which: 0 = secret key, NTT form
-   [n_moduli][N]; 1 = public key [2][L][N]; 2 = rotation key `index` (0 .. 2 log_n - 3, as in
-   hs_keygen) [2][dnum][L+K][N] (b then a); 3 = relinearisation key, same layout; 4 = exact-step rotation key for the step
+   [n_moduli][N]; 1 = public key [2][L][N]; 2 = rotation key `index` (0 .. log_n - 2 as in
+   hs_keygen; log_n - 1 .. 2 log_n - 3 for the right keys when added) [2][dnum][L+K][N] (b then a); 3 = relinearisation key, same layout; 4 = exact-step rotation key for the step
    `index` (HS_EKEY if the key-set holds none).  cap in u64 words; HS_ECAPACITY if short. */
 int hs_keyset_export(const hs_keyset* ks, int which, int index, uint64_t* host_out, int64_t cap);
 /* Add rotation keys for left rotations by exactly steps[i] slots (Sec. 2.1, HE-Rot with Galois
    element 3^k mod 2N; each step taken mod N/2).  Steps that are 0 or a power of two, and steps
    the key-set already holds, are skipped.  Afterwards every rotation by a held step -- in
    hs_rotate and in the totalSum of hs_he_spmv, its batched forms and the server -- is one key
-   switch instead of one per signed power-of-two digit: the decrypted results are the same, the ciphertext
+   switch instead of one per power-of-two digit: the decrypted results are the same, the ciphertext
    limbs (their noise) differ.  Keys are [2][dnum][L+K][N] each (10.5 MiB at N = 16384 with
    6 + 1 primes), sampled from the key-set's seed with a stream id of their own.  Must not run
    concurrently with other calls that use the key-set; batch plans keep the keys they were
    recorded with.  Synchronises `stream`. */
 int hs_keyset_add_rotation_keys(hs_ctx* ctx, hs_keyset* ks, const int64_t* host_steps, int64_t n,
                                 void* stream);
+/* Add rotation keys for right rotations by 2^i, i = 0 .. log_n - 2 (key index log_n - 1 + i,
+   Galois element 3^(-2^i) = 3^(N/2 - 2^i) mod 2N, sampling id 64 + i); nothing if held.  Not the
+   paper's reading of its power-of-two keys (left powers, binary digits), but the default of common
+   BFV libraries: afterwards a rotation by k without an exact-step key -- in hs_rotate, the totalSum
+   of hs_he_spmv, its batched forms, the server and the diagonal method -- applies the signed digits
+   +-2^i of the non-adjacent form of k mod N/2 (no two adjacent digits nonzero: the fewest
+   power-of-two key switches), lowest first, a digit of N/2 left out.  The decrypted results are the
+   same; the limbs differ.  Keys as for hs_keyset_add_rotation_keys (13 more of 10.5 MiB at N =
+   16384).  Must not run concurrently with other calls that use the key-set.  Synchronises
+   `stream`. */
+int hs_keyset_add_right_rotation_keys(hs_ctx* ctx, hs_keyset* ks, void* stream);
 
 /* ---------------------------------------------------------------- Client A: matrix */
 /* Pack an R x C integer matrix given in CSR form (device arrays: row_ptr int64[R+1] with
@@ -196,9 +205,8 @@ int hs_encrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const int64
 /* ---------------------------------------------------------------- Cloud */
 /* Encrypted SpMV: for each chunk the slot-wise product with the encrypted vector (HE-CMult, or
    HE-Mult + relinearisation for an encrypted matrix), the intra-chunk totalSum by rotations of
-   e*h slots (Alg. Aggregation; each rotation applied as the signed power-of-two digits of the
-   non-adjacent form of its amount mod N/2, lowest first, one key switch per digit, or as one key
-   switch with an exact-step key), the mask product
+   e*h slots (Alg. Aggregation; each rotation applied as its power-of-two digits as in hs_rotate,
+   one key switch per digit, or as one key switch with an exact-step key), the mask product
    (agg_mode 0), and the sum over the chunks of each group.  *y receives one ciphertext per group
    (hs_matrix_groups: a row partition, or a pair of them with slot_rows = 2). */
 int hs_he_spmv(hs_ctx* ctx, const hs_keyset* ks, const hs_matrix* m, const hs_ctvec* x,
@@ -309,8 +317,8 @@ int hs_diag_rotation_steps(const hs_diag* d, int64_t* host_steps, int64_t cap, i
 int hs_diag_encrypt(hs_ctx* ctx, const hs_keyset* ks, const hs_diag* d, const int64_t* v,
                     int64_t len, uint64_t seed, void* stream, hs_ctvec** out);
 /* Cloud: one result ciphertext per block row.  Rot(x_bj, d) uses one exact-step key switch when
-   the key-set holds a key for d, else the signed power-of-two digits of d as in hs_rotate (each
-   partial rotation computed once per block column).  hs_last_counters then reports [0] key switches,
+   the key-set holds a key for d, else the power-of-two digits of d as in hs_rotate (each partial
+   rotation, a partial sum of those digits, computed once per block column).  hs_last_counters then reports [0] key switches,
    [1] distinct rotated blocks, [2] kernel launches, [3] diagonal products. */
 int hs_diag_spmv(hs_ctx* ctx, const hs_keyset* ks, const hs_diag* d, const hs_ctvec* x,
                  void* stream, hs_ctvec** y);
@@ -350,9 +358,9 @@ int hs_ntt(hs_ctx* ctx, uint64_t* d_limbs, int64_t n_polys, int mod0, int n_limb
 int hs_mul_plain(hs_ctx* ctx, const hs_ctvec* in, const uint64_t* d_pt, void* stream, hs_ctvec** out);
 /* Left rotation of every ciphertext of `in` by k slots within each slot row (HE-Rot): one Galois
    automorphism 3^k plus a key switch when the key-set holds an exact-step key for k mod N/2, else
-   the digits +-2^i of the non-adjacent form of k mod N/2 (no two adjacent digits nonzero: the
-   fewest power-of-two key switches), lowest first, a digit of N/2 left out, each a Galois
-   automorphism 3^(+-2^i) plus a key switch. */
+   the binary digits of k mod N/2 in ascending order (with the right keys of
+   hs_keyset_add_right_rotation_keys: the signed digits +-2^i of its non-adjacent form), each a
+   Galois automorphism 3^(+-2^i) plus a key switch. */
 int hs_rotate(hs_ctx* ctx, const hs_keyset* ks, const hs_ctvec* in, int64_t k, void* stream,
               hs_ctvec** out);
 /* Slot-wise product of two ciphertexts (HE-Mult): exact scaled tensor round(t/Q * (a (x) b)) of the

@@ -83,6 +83,8 @@ def lib():
             "orc_plain_ntt": (None, [vp, u64p, u64p]),
             "orc_galois_elt": (ctypes.c_uint64, [vp, ctypes.c_int]),
             "orc_rotation_digits": (ctypes.c_int, [vp, ctypes.c_uint64, i64p]),
+            "orc_add_right_keys": (None, [vp]),
+            "orc_n_rotation_keys": (ctypes.c_int, [vp]),
             "orc_keygen": (None, [vp, ctypes.c_uint64]),
             "orc_export_sk": (None, [vp, i64p]),
             "orc_export_sk_ntt": (None, [vp, u64p]),
@@ -227,9 +229,15 @@ class Context:
         by 2^(i - log2 N + 1)."""
         return int(lib().orc_galois_elt(self.h, i))
 
+    def add_right_rotation_keys(self):
+        """The optional right rotation keys (index log2 N - 1 + i rotates right by 2^i); rotations
+        then apply the signed digits of the non-adjacent form."""
+        lib().orc_add_right_keys(self.h)
+
     def rotation_digits(self, k):
-        """Signed power-of-two steps (+-2^i, lowest first) that a rotation by k mod N/2 applies
-        when no exact-step key is held: the non-adjacent form of k without a digit of N/2."""
+        """Power-of-two steps (lowest first) that a rotation by k mod N/2 applies when no
+        exact-step key is held: the binary digits of k, or with the right keys the signed digits
+        +-2^i of the non-adjacent form of k without a digit of N/2."""
         out = np.zeros(64, np.int64)
         n = lib().orc_rotation_digits(self.h, k % (self.N // 2), _p(out, i64p))
         return [int(v) for v in out[:n]]
@@ -285,7 +293,7 @@ class Context:
     def ksk(self, key_id):
         """Key-switching key: key_id < 0 the relinearisation key, else rotation key index key_id
         (left by 2^key_id below log2 N - 1, else right by 2^(key_id - log2 N + 1))."""
-        if key_id >= 2 * (self.logn - 1):
+        if key_id >= lib().orc_n_rotation_keys(self.h):
             raise IndexError("no rotation key with index %d" % key_id)
         out = np.zeros(2 * self.dnum * (self.L + self.K) * self.N, np.uint64)
         lib().orc_export_ksk(self.h, key_id, _p(out, u64p))

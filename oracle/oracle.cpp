@@ -17,10 +17,10 @@
  *   - Protocol and row-map scatter: Sec. 4.4, Alg. "Sparse Matrix-Vector Multiplication".
  *   - Row partitioning of large matrices: Sec. 4.7.
  *   - HE operations (Add, Mult, CMult, Rot): Sec. 2.1.
-   - Rotation keys: Sec. 5 (experimental setup) generates power-of-two rotation keys with its BFV
-     library; read here as that library's default set, powers of two in both directions, with a
-     rotation by any other amount applied as the signed power-of-two digits of its non-adjacent
-     form.
+   - Rotation keys: Sec. 5 (experimental setup) generates power-of-two rotation keys; read as left
+     rotations by 2^i, a rotation by any other amount applied as its binary digits, lowest first.
+     Optionally (not the paper's reading) the key set also holds right rotations by 2^i and a
+     rotation applies the signed digits of its non-adjacent form, as BFV libraries commonly do.
  * The paper leaves the HE scheme internals to its library; the conventions pinned here (prime
  * choice, NTT order, slot order, sampling, key switching, BFV multiplication) are listed in the
  * design notes and repeated next to the code that implements them.
@@ -408,6 +408,7 @@ struct Ctx {
   std::vector<u64> s_ntt;        /* [L+K+n_aux][N] */
   std::vector<u64> pk0, pk1;     /* [L][N] */
   std::vector<std::vector<u64>> gk; /* power-of-two rotation keys, index as rot_key_step: [2][dnum][L+K][N] (b then a) */
+  bool signed_digits = false;        /* right keys held: rotations use signed digits */
   std::map<u64, std::vector<u64>> gk_step; /* optional exact-step rotation keys, by step k */
   std::vector<u64> rk;           /* relinearisation key, same layout */
   u64 keyseed = 0;
@@ -419,8 +420,8 @@ u64* limb(std::vector<u64>& v, u64 N, int i) { return v.data() + (u64)i * N; }
    HE-Rot; 3 generates the slot-row rotations of the power-of-two cyclotomic ring and has order
    N/2 modulo 2N, so a right rotation by k is the left rotation by N/2 - k). */
 u64 galois_elt_step(const Ctx& c, u64 k) { return powmod(3, k % (c.N / 2), 2 * c.N); }
-/* Power-of-two rotation keys, both directions: index i < logn - 1 rotates left by 2^i, index
-   (logn - 1) + i rotates right by 2^i.  rot_key_step gives the signed step (+2^i or -2^i). */
+/* Power-of-two rotation keys: index i < logn - 1 rotates left by 2^i; with the optional right keys,
+   index (logn - 1) + i rotates right by 2^i.  rot_key_step gives the signed step (+2^i or -2^i). */
 int n_pow2(const Ctx& c) { return c.logn - 1; }
 i64 rot_key_step(const Ctx& c, int idx) { return idx < n_pow2(c) ? (1LL << idx) : -(1LL << (idx - n_pow2(c))); }
 u64 galois_elt_key(const Ctx& c, int idx) {
@@ -435,12 +436,18 @@ u32 rot_key_id(const Ctx& c, int idx) { return idx < n_pow2(c) ? (u32)idx : 64u 
 u32 step_key_id(u64 k) { return 256u + (u32)k; }
 
 /* The power-of-two key switches of a left rotation by k slots, 0 <= k < N/2, as key indices in
-   the order they are applied: the digits of the non-adjacent form of k (signed binary, no two
-   adjacent digits nonzero; Reitwiesner), lowest first.  A digit of +-N/2 rotates every row by a
-   whole row, the identity, and is left out. */
+   the order they are applied, lowest first: the binary digits of k (left keys only); with the
+   right keys, the digits of the non-adjacent form of k (signed binary, no two adjacent digits
+   nonzero; Reitwiesner), where a digit of +-N/2 rotates every row by a whole row, the identity,
+   and is left out. */
 std::vector<int> rotation_digits(const Ctx& c, u64 k) {
   std::vector<int> out;
   const int nl = n_pow2(c);
+  if (!c.signed_digits) {
+    for (int i = 0; i < nl; i++)
+      if ((k >> i) & 1) out.push_back(i);
+    return out;
+  }
   int i = 0;
   while (k) {
     if (k & 1) {
@@ -615,7 +622,8 @@ void keygen(Ctx& c, u64 seed) {
   }
   c.gk.clear();
   c.gk_step.clear();
-  for (int i = 0; i < 2 * n_pow2(c); i++) {
+  c.signed_digits = false;
+  for (int i = 0; i < n_pow2(c); i++) {
     std::vector<i64> sg = automorph_int(c.s, galois_elt_key(c, i), N);
     c.gk.push_back(make_ksk(c, sg, rot_key_id(c, i)));
   }
@@ -888,6 +896,17 @@ std::vector<u64> rotate(const Ctx& c, const std::vector<u64>& ct, u64 k, int* nk
     if (nks) (*nks)++;
   }
   return r;
+}
+
+/* Adds the right rotation keys (index (logn - 1) + i, right by 2^i); rotations then apply the
+   signed digits of the non-adjacent form. */
+void add_right_keys(Ctx& c) {
+  if (c.signed_digits) return;
+  for (int i = n_pow2(c); i < 2 * n_pow2(c); i++) {
+    std::vector<i64> sg = automorph_int(c.s, galois_elt_key(c, i), c.N);
+    c.gk.push_back(make_ksk(c, sg, rot_key_id(c, i)));
+  }
+  c.signed_digits = true;
 }
 
 /* Adds a rotation key for a left rotation by exactly k slots (k mod N/2; nothing for 0, for a
@@ -1172,6 +1191,9 @@ void orc_plain_ntt(void* h, const u64* m, u64* out) {
 }
 /* Galois element of rotation key index i (left 2^i for i < logn - 1, else right 2^(i - logn + 1)). */
 u64 orc_galois_elt(void* h, int i) { return galois_elt_key(*(Ctx*)h, i); }
+/* Adds the optional right rotation keys; the number of power-of-two rotation keys held. */
+void orc_add_right_keys(void* h) { add_right_keys(*(Ctx*)h); }
+int orc_n_rotation_keys(void* h) { return (int)((Ctx*)h)->gk.size(); }
 /* The key switches of a rotation by k (mod N/2) without an exact-step key, as signed steps
    +-2^i in the order applied; returns the count (at most log2 N). */
 int orc_rotation_digits(void* h, u64 k, i64* out) {

@@ -186,9 +186,9 @@ static u64 galois_step(const hs_ctx* c, i64 k) {
   const i64 half = (i64)c->N / 2;
   return pow_mod(3, (u64)(((k % half) + half) % half), 2 * c->N);
 }
-// Power-of-two rotation keys in both directions (the power-of-two key set of Sec. 5, its BFV
-// library's default of left and right powers): key index i < log2 N - 1 rotates left by 2^i,
-// index log2 N - 1 + i right by 2^i.  Sampling ids: i, and 64 + i; RELIN_ID above them.
+// Power-of-two rotation keys (Sec. 5): key index i < log2 N - 1 rotates left by 2^i; the optional
+// right keys (hs_keyset_add_right_rotation_keys), index log2 N - 1 + i, rotate right by 2^i.
+// Sampling ids: i, and 64 + i; RELIN_ID above them.
 static int n_pow2(const hs_ctx* c) { return c->logn - 1; }
 static i64 key_index_step(const hs_ctx* c, int idx) { return idx < n_pow2(c) ? (1LL << idx) : -(1LL << (idx - n_pow2(c))); }
 static u32 key_index_id(const hs_ctx* c, int idx) { return idx < n_pow2(c) ? (u32)idx : 64u + (u32)(idx - n_pow2(c)); }
@@ -204,14 +204,20 @@ static const u64* rotation_key(const hs_keyset* ks, i64 step) {
   return it->second;
 }
 // The key switches of a left rotation by k slots, 0 <= k < N/2, in the order they are applied:
-// one with the exact-step key when the key-set holds one for k; otherwise the digits of the
-// non-adjacent form of k (signed binary digits, no two adjacent ones nonzero, which has the
-// fewest nonzero digits of any signed binary expansion), lowest first, each a power-of-two
-// rotation +-2^i; a digit of N/2 rotates by a whole row, the identity, and is left out.
+// one with the exact-step key when the key-set holds one for k; otherwise, lowest first, the
+// binary digits of k (left keys only), or with the right keys the digits of the non-adjacent
+// form of k (signed binary digits, no two adjacent ones nonzero, which has the fewest nonzero
+// digits of any signed binary expansion), each a power-of-two rotation +-2^i, a digit of N/2
+// (a whole row, the identity) left out.
 static std::vector<i64> rotation_digits(const hs_ctx* c, const hs_keyset* ks, i64 k) {
   std::vector<i64> out;
   if (!is_pow2(k) && ks->step_keys.count(k)) {
     out.push_back(k);
+    return out;
+  }
+  if ((int)ks->gk.size() < 2 * n_pow2(c)) {
+    for (int i = 0; i < n_pow2(c); i++)
+      if ((k >> i) & 1) out.push_back(1LL << i);
     return out;
   }
   const i64 half = (i64)c->N / 2;
@@ -815,7 +821,7 @@ int hs_keygen(hs_ctx* c, uint64_t seed, void* stream, hs_keyset** out) {
         launch_ksk_limbs(c, dargs.as<KskArgs>(), (int)args.size(), st);
       }
       HS_CHECK_HIP(hipStreamSynchronize(st));
-      for (int i = 0; i < 2 * n_pow2(c); i++)
+      for (int i = 0; i < n_pow2(c); i++)
         ks->gk.push_back(make_ksk(c, ks, key_index_id(c, i), 1, (u32)galois_step(c, key_index_step(c, i)), st));
       ks->rk = make_ksk(c, ks, RELIN_ID, 2, 0, st);
     } catch (...) {
@@ -855,6 +861,16 @@ int hs_keyset_export(const hs_keyset* ks, int which, int index, uint64_t* host_o
     } else throw Error{HS_EINVAL, "unknown key kind"};
     HS_REQUIRE((size_t)cap >= n, HS_ECAPACITY, "output too small");
     HS_CHECK_HIP(hipMemcpy(host_out, src, n * sizeof(u64), hipMemcpyDeviceToHost));
+  });
+}
+
+int hs_keyset_add_right_rotation_keys(hs_ctx* c, hs_keyset* ks, void* stream) {
+  return guarded([&] {
+    HS_REQUIRE(c && ks, HS_EINVAL, "null argument");
+    HS_REQUIRE(ks->ctx == c, HS_EKEY, "key-set from another context");
+    hipStream_t st = S(stream);
+    for (int i = (int)ks->gk.size(); i < 2 * n_pow2(c); i++)
+      ks->gk.push_back(make_ksk(c, ks, key_index_id(c, i), 1, (u32)galois_step(c, key_index_step(c, i)), st));
   });
 }
 

@@ -50,6 +50,7 @@ SIGNATURES = {
     "hs_keyset_destroy": (None, [_vp]),
     "hs_keyset_export": (_int, [_vp, _int, _int, _u64p, _i64]),
     "hs_keyset_add_rotation_keys": (_int, [_vp, _vp, _i64p, _i64, _vp]),
+    "hs_keyset_add_right_rotation_keys": (_int, [_vp, _vp, _vp]),
     "hs_matrix_rotation_steps": (_int, [_vp, _i64p, _i64, _i64p]),
     "hs_cssc_pack": (_int, [_vp, _i64, _i64, _vp, _vp, _vp, _int, _vp, _u64, _vp, _pp]),
     "hs_matrix_destroy": (None, [_vp]),
@@ -217,6 +218,11 @@ class Keyset:
         """hs_keyset_add_rotation_keys: exact-step rotation keys for these steps (host ints)."""
         st = np.ascontiguousarray(np.asarray(steps, np.int64).reshape(-1))
         _check(lib.hs_keyset_add_rotation_keys(self.ctx.h, self.h, st.ctypes.data_as(_i64p), st.size, _stream()))
+
+    def add_right_rotation_keys(self):
+        """hs_keyset_add_right_rotation_keys: right rotations by 2^i; rotations then apply the
+        signed digits of the non-adjacent form."""
+        _check(lib.hs_keyset_add_right_rotation_keys(self.ctx.h, self.h, _stream()))
 
 
 class CtVec:

@@ -3,8 +3,7 @@ the oracle, bit for bit, through the C ABI.
 
 Every diagonal plaintext, the diagonal keys, the encrypted vector blocks, every result limb and the
 decrypted product must equal the oracle's; with exact-step keys for some of the steps, rotations
-by those steps take one key switch and the rest keep the signed power-of-two digits, as in the
-oracle.
+by those steps take one key switch and the rest keep the binary digits, as in the oracle.
 """
 import numpy as np
 import pytest

@@ -101,7 +101,7 @@ def test_keygen_parity(p):
     g, kg, o = contexts(p)
     assert np.array_equal(kg.export(0), o.sk_ntt())
     assert np.array_equal(kg.export(1), o.pk())
-    for i in range(2 * (p[0] - 1)):   # left then right powers of two
+    for i in range(p[0] - 1):
         assert np.array_equal(kg.export(2, i), o.ksk(i)), i
     assert np.array_equal(kg.export(3), o.ksk(-1))
 
@@ -110,7 +110,7 @@ def test_keygen_parity_16k():
     g, kg, o = contexts(RING16K)
     assert np.array_equal(kg.export(0), o.sk_ntt())
     assert np.array_equal(kg.export(1), o.pk())
-    for i in (0, 5, 12, 13, 20, 25):
+    for i in (0, 5, 12):
         assert np.array_equal(kg.export(2, i), o.ksk(i)), i
     assert np.array_equal(kg.export(3), o.ksk(-1))
 
@@ -205,7 +205,7 @@ def test_rotation_parity(pipeline):
         m = rng.integers(0, 65537, N).astype(np.uint64)
         ct = np.concatenate([o.encrypt(m, 9, 0), o.encrypt(m, 9, 1)])
         x = H.CtVec.from_host(g, ct, 2)
-        for k in (1, 6, 11, 37, N // 2 - 1):   # digits +1; -2 +8; -1 -4 +16; +1 +4 +32; -1
+        for k in (1, 6, 11, 37, N // 2 - 1):
             r = H.rotate(g, kg, x, k)
             assert np.array_equal(r.export(0), o.rotate(ct[:o.ct_size()], k)), (p, k)
             assert np.array_equal(r.export(1), o.rotate(ct[o.ct_size():], k)), (p, k)
@@ -391,7 +391,7 @@ def test_split_path_keygen_and_protocol(p, split_path, pipeline):
     o.keygen(19)
     assert np.array_equal(kg.export(0), o.sk_ntt())
     assert np.array_equal(kg.export(1), o.pk())
-    for i in (0, p[0] - 2, p[0] - 1, 2 * p[0] - 3):
+    for i in (0, p[0] - 2):
         assert np.array_equal(kg.export(2, i), o.ksk(i))
     assert np.array_equal(kg.export(3), o.ksk(-1))
     _cache[(p, 19)] = (g, kg, o)
@@ -550,7 +550,6 @@ def test_laplace256_full_size():
     assert g.moduli() == o.moduli()
     assert np.array_equal(kg.export(0), o.sk_ntt())
     assert np.array_equal(kg.export(2, 3), o.ksk(3))
-    assert np.array_equal(kg.export(2, 17), o.ksk(17))   # right rotation by 8
     assert np.array_equal(kg.export(3), o.ksk(-1))
     w = W.laplace256()
     M = H.Matrix(g, w["R"], w["C"], dev(w["row_ptr"], torch.int64), dev(w["col"], torch.int32), dev(w["val"], torch.int64), True, kg, 31)

@@ -1,7 +1,7 @@
 """GPU: exact-step rotation keys against the oracle, bit for bit, through the C ABI.
 
 A key-set that holds a key for a whole rotation step rotates with one key switch instead of one
-per signed power-of-two digit (HE-Rot, Sec. 2.1; the aggregation of Alg. Aggregation then needs one key switch
+per binary digit (HE-Rot, Sec. 2.1; the aggregation of Alg. Aggregation then needs one key switch
 per logical rotation).  The keys, every rotated limb, the he_spmv result (single, batched, graph
 replay and server) and the decrypted product must equal the oracle's.
 """

@@ -352,14 +352,17 @@ def test_exact_step_rotation_keys():
 
 
 def test_rotation_keys_both_directions():
-    """Power-of-two rotation keys in both directions (the power-of-two key set of Sec. 5, read as
-    its BFV library's default of left and right powers): key index i < log2 N - 1 has Galois
-    element 3^(2^i) mod 2N and index log2 N - 1 + i the inverse of 3^(2^i); each key holds
+    """Power-of-two rotation keys (Sec. 5): key index i < log2 N - 1 has Galois element 3^(2^i)
+    mod 2N; the optional right keys, index log2 N - 1 + i, the inverse of 3^(2^i).  Each key holds
     b + a s = e + P sigma_g(s) on its digit, and one key switch with a right key rotates the slot
     rows right by 2^i."""
     c = small_ctx(logn=6, L=2, bits=30, K=1)
     N, h, L, K = c.N, c.N // 2, c.L, c.K
     nl = c.logn - 1
+    with pytest.raises(IndexError):
+        c.ksk(nl)
+    c.add_right_rotation_keys()
+    c.add_right_rotation_keys()   # a second call adds nothing
     mods = c.moduli()
     P = math.prod(mods[L:L + K])
     s = [int(v) for v in c.sk()]
@@ -399,12 +402,16 @@ def test_rotation_keys_both_directions():
 
 @pytest.mark.parametrize("logn", [6, 9])
 def test_rotation_digits_fewest_key_switches(logn):
-    """A rotation by k without an exact-step key applies signed powers of two below N/2, lowest
-    first, that sum to k mod N/2 with no two at adjacent positions (the non-adjacent form), and no
-    sequence of power-of-two keys in either direction reaches k in fewer key switches (breadth-first
-    search over the N/2 slot-row rotations)."""
-    c = O.Context(logn, 2, 30, 1)
+    """Left keys only (the paper reading): a rotation by k applies the binary digits of k, lowest
+    first.  With the right keys: signed powers of two below N/2, lowest first, that sum to k mod N/2
+    with no two at adjacent positions (the non-adjacent form), and no sequence of power-of-two keys
+    in either direction reaches k in fewer key switches (breadth-first search over the N/2 slot-row
+    rotations)."""
+    c = small_ctx(logn=logn, L=2, bits=30, K=1)
     h = c.N // 2
+    for k in range(h):
+        assert c.rotation_digits(k) == [1 << i for i in range(logn - 1) if (k >> i) & 1], k
+    c.add_right_rotation_keys()
     gens = [1 << i for i in range(logn - 1)] + [-(1 << i) for i in range(logn - 1)]
     dist = {0: 0}
     frontier = [0]
@@ -427,10 +434,13 @@ def test_rotation_digits_fewest_key_switches(logn):
     assert c.rotation_digits(h - 1) == [-1] and c.rotation_digits(3) == [-1, 4] and c.rotation_digits(0) == []
 
 
-def test_rotation_by_every_amount_decrypts():
-    """Every left rotation amount at N = 64 (power-of-two keys in both directions, digits of the
-    non-adjacent form) decrypts to the slot rows rotated left by k, with one key switch per digit."""
+@pytest.mark.parametrize("right", [False, True])
+def test_rotation_by_every_amount_decrypts(right):
+    """Every left rotation amount at N = 64 (binary digits with left keys; signed digits of the
+    non-adjacent form with the right keys too) decrypts to the slot rows rotated left by k."""
     c = small_ctx(logn=6, L=2, bits=30, K=1)
+    if right:
+        c.add_right_rotation_keys()
     N, h = c.N, c.N // 2
     g = np.random.default_rng(12)
     x = g.integers(0, T, N)
@@ -854,7 +864,7 @@ def test_spmv_small_workload_uniform_aggregation():
 
 def test_spmv_with_exact_step_keys_one_key_switch_per_rotation():
     """With a key for every totalSum step the decrypted product is unchanged and every logical
-    rotation costs one key switch instead of one per signed power-of-two digit of its step."""
+    rotation costs one key switch instead of one per binary digit of its step."""
     g = np.random.default_rng(17)
     rp, col, val = W.uniform_matrix(300, 200, 1200, 15, g)
     w = dict(R=300, C=200, row_ptr=rp, col=col, val=val, v=g.integers(-15, 16, 200))
