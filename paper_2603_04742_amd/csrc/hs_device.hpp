@@ -60,6 +60,19 @@ __device__ __forceinline__ double mulmod(double a, double b, ModD m) {
   return r + l;
 }
 
+// a * w mod q for a twiddle |w| < q given alone (no precomputed quotient): the quotient is
+// estimated from the rounded product, fl(a w) fl(1/q), which errs from a w / q by at most
+// 2^-52 |a w| / q < 2^-52 |a|.  For |a| <= 1.9 * 2^50 that keeps the estimate below 2^51 (exact
+// rounding by kRound) and the result r = a w - k q exact with |r| <= q (1/2 + 2^-52 |a|), i.e.
+// <= 0.625 q, 0.79 q, 0.975 q for |a| <= q/2 + 1, 1.125 q, 1.9 q.  Same operations as mul_tw.
+__device__ __forceinline__ double mul_twc(double a, double w, ModD m) {
+  double h = a * w;
+  double l = __builtin_fma(a, w, -h);
+  double k = __builtin_fma(h, m.qinv, kRound) - kRound;
+  double r = __builtin_fma(-k, m.q, h);
+  return r + l;
+}
+
 // Balanced value (|x| < 2^52) -> canonical residue in [0, q).
 __device__ __forceinline__ double canon(double x, ModD m) {
   double r = reduce(x, m);
@@ -306,6 +319,34 @@ __device__ __forceinline__ void ct_group(double (&x)[1 << R], int hb, const doub
   }
 }
 
+// ct_group over the 8-byte twiddle table (w alone, mul_twc): half the twiddle bytes of ct_group,
+// for rounds of at most three stages that start at a reduction point, so that the inputs of the
+// first stage are within q/2 + 1; the bounds of mul_twc then give products within 0.625 q, 0.79 q,
+// 0.975 q and outputs within 1.125 q, 1.9 q, 2.9 q < 2^52 at the three stages.
+template <int R, int ST0>
+__device__ __forceinline__ void ct_group_c(double (&x)[1 << R], int hb, const double* __restrict__ twc, ModD m) {
+  static_assert(R <= 3 && fwd_reduces_before(ST0), "the bounds need a reduction at the first stage and at most three stages");
+#pragma unroll
+  for (int u = 0; u < (1 << R); u++) x[u] = reduce(x[u], m);
+#pragma unroll
+  for (int k = 0; k < R; k++) {
+    const double __attribute__((address_space(1)))* twk =
+        (const double __attribute__((address_space(1)))*)(twc + (1 << (ST0 + k)) + (hb << k));
+#pragma unroll
+    for (int j = 0; j < (1 << k); j++) {
+      const double w = twk[j];
+#pragma unroll
+      for (int v = 0; v < (1 << (R - 1 - k)); v++) {
+        const int u = (j << (R - k)) | v;
+        const int u2 = u | (1 << (R - 1 - k));
+        const double t = mul_twc(x[u2], w, m);
+        x[u2] = x[u] - t;
+        x[u] = x[u] + t;
+      }
+    }
+  }
+}
+
 // Stages [ST0, ST0 + R) of the inverse transform (Gentleman-Sande, stage s pairs bit s).
 template <int R, int ST0, int LOGN, bool LAST>
 __device__ __forceinline__ void gs_group(double (&x)[1 << R], int hb, const double2* __restrict__ tw, double2 ninv, ModD m) {
@@ -343,6 +384,21 @@ __device__ __forceinline__ void fwd_round_g(const In& in, const Out& out, const 
     double x[1 << R];
     in.template get<R, LO>(x, base);
     ct_group<R, ST0>(x, sg >> LO, tw, m);
+    out.template put<R, LO>(x, base);
+  }
+}
+
+// fwd_round_g with ct_group_c (8-byte twiddles).
+template <int LOGN, int NT, int ST0, int R, int TPT, class In, class Out>
+__device__ __forceinline__ void fwd_round_gc(const In& in, const Out& out, const double* __restrict__ twc, ModD m, int sg0, int tid) {
+  constexpr int LO = LOGN - ST0 - R;
+#pragma unroll
+  for (int it = 0; it < TPT; it++) {
+    const int sg = sg0 + tid + it * NT;
+    const int base = ((sg >> LO) << (LO + R)) | (sg & ((1 << LO) - 1));
+    double x[1 << R];
+    in.template get<R, LO>(x, base);
+    ct_group_c<R, ST0>(x, sg >> LO, twc, m);
     out.template put<R, LO>(x, base);
   }
 }

@@ -41,6 +41,7 @@ struct ModTab {
   double2 ninv;          // (N^-1 mod q, quotient)
   const double2* fw;     // forward twiddles (psi^bitrev(i), fl(./q))
   const double2* iv;     // inverse twiddles (psi^-bitrev(i), fl(./q))
+  const double* fwc;     // forward twiddles psi^bitrev(i) alone, 8 bytes each (ct_group_c)
 };
 
 // pair (w, fl(w/q)) for a constant w in [0, q)
@@ -125,6 +126,7 @@ struct hs_ctx {
   hs::ModTab* d_tab = nullptr;     // device [n_mod + 1], entry n_mod = plaintext modulus t
   std::vector<hs::ModTab> h_tab;
   double2* d_tw = nullptr;         // twiddle storage
+  double* d_twc = nullptr;         // forward twiddles without quotients
   hs::u32* d_slot_pos = nullptr;   // slot j -> index of the mod-t NTT output
   // encryption: floor(Q/t) mod q_i as (w, w/q), Q mod t
   double2* d_qdt = nullptr;

@@ -161,6 +161,7 @@ k_ntt15(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab
   const LdsHalf<LOGN - 1> Lh{smem};
   if (!inverse) {
     const double2* tw = t.fw;
+    const double* twc = t.fwc;
     auto out = [p, m](int i, double x) { gst(p + i, d2u(canon(x, m))); };
     double a[EH], c[EH];
 #pragma unroll
@@ -178,24 +179,24 @@ k_ntt15(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab
     ct_group<4, 1>(a, 0, tw, m);
     Lh.template put<4, 10>(a, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 5, 3, 2>(Lh, Lh, tw, m, 0, tid);
+    fwd_round_gc<LOGN, NT, 5, 3, 2>(Lh, Lh, twc, m, 0, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 8, 3, 2>(Lh, Lh, tw, m, 0, tid);
+    fwd_round_gc<LOGN, NT, 8, 3, 2>(Lh, Lh, twc, m, 0, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 11, 3, 2>(Lh, Lh, tw, m, 0, tid);
+    fwd_round_gc<LOGN, NT, 11, 3, 2>(Lh, Lh, twc, m, 0, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 14, 1, 8>(Lh, elem_out(out), tw, m, 0, tid);
+    fwd_round_gc<LOGN, NT, 14, 1, 8>(Lh, elem_out(out), twc, m, 0, tid);
     __syncthreads();
     ct_group<4, 1>(c, 1, tw, m);
     Lh.template put<4, 10>(c, H + tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 5, 3, 2>(Lh, Lh, tw, m, 1 << 11, tid);
+    fwd_round_gc<LOGN, NT, 5, 3, 2>(Lh, Lh, twc, m, 1 << 11, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 8, 3, 2>(Lh, Lh, tw, m, 1 << 11, tid);
+    fwd_round_gc<LOGN, NT, 8, 3, 2>(Lh, Lh, twc, m, 1 << 11, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 11, 3, 2>(Lh, Lh, tw, m, 1 << 11, tid);
+    fwd_round_gc<LOGN, NT, 11, 3, 2>(Lh, Lh, twc, m, 1 << 11, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 14, 1, 8>(Lh, elem_out(out), tw, m, 1 << 13, tid);
+    fwd_round_gc<LOGN, NT, 14, 1, 8>(Lh, elem_out(out), twc, m, 1 << 13, tid);
   } else {
     const double2* tw = t.iv;
     const double2 ninv = t.ninv;
@@ -241,7 +242,9 @@ k_ntt15(u64* data, int nl, int mod0, int inverse, const ModTab* __restrict__ tab
 // registers after the first stage; once the first half has gone to LDS its registers are free, so
 // the first-half words of the workgroup's next limb are read into them while the second half runs
 // its LDS rounds (prefetching both halves would exceed the 128 registers that keep two workgroups
-// on a CU).  The last limb reloads itself: those words are not used.
+// on a CU).  The LDS rounds read the 8-byte twiddle table (ct_group_c): half the twiddle bytes,
+// which come from L2 and are as many as the limb's own.  The last limb reloads itself: those
+// words are not used.
 __global__ void __launch_bounds__(kSplitNT) __attribute__((amdgpu_waves_per_eu(4)))
 k_ntt_fwd_pipe(u64* data, i64 nlimbs, int nl, int mod0, const ModTab* __restrict__ tab) {
   SMEM();
@@ -258,6 +261,7 @@ k_ntt_fwd_pipe(u64* data, i64 nlimbs, int nl, int mod0, const ModTab* __restrict
     const ModTab t = tab[mod0 + (int)(b % nl)];
     const ModD m = mod_of(t);
     const double2* tw = t.fw;
+    const double* twc = t.fwc;
     u64* p = data + ((size_t)b << LOGN);
 #pragma unroll
     for (int k = 0; k < EH; k++) wb[k] = gld(p + tid + k * NT + H);
@@ -274,11 +278,11 @@ k_ntt_fwd_pipe(u64* data, i64 nlimbs, int nl, int mod0, const ModTab* __restrict
     ct_group<4, 1>(a, 0, tw, m);
     L.template put<4, 9>(a, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 5, 3, 2>(L, L, tw, m, 0, tid);
+    fwd_round_gc<LOGN, NT, 5, 3, 2>(L, L, twc, m, 0, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 8, 3, 2>(L, L, tw, m, 0, tid);
+    fwd_round_gc<LOGN, NT, 8, 3, 2>(L, L, twc, m, 0, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 11, 3, 2>(L, elem_out(out), tw, m, 0, tid);
+    fwd_round_gc<LOGN, NT, 11, 3, 2>(L, elem_out(out), twc, m, 0, tid);
     __syncthreads();
     ct_group<4, 1>(c, 1, tw, m);
     L.template put<4, 9>(c, H + tid);
@@ -286,11 +290,11 @@ k_ntt_fwd_pipe(u64* data, i64 nlimbs, int nl, int mod0, const ModTab* __restrict
 #pragma unroll
     for (int k = 0; k < EH; k++) wa[k] = gld(data + ((size_t)nb << LOGN) + tid + k * NT);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 5, 3, 2>(L, L, tw, m, 1 << 10, tid);
+    fwd_round_gc<LOGN, NT, 5, 3, 2>(L, L, twc, m, 1 << 10, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 8, 3, 2>(L, L, tw, m, 1 << 10, tid);
+    fwd_round_gc<LOGN, NT, 8, 3, 2>(L, L, twc, m, 1 << 10, tid);
     __syncthreads();
-    fwd_round_g<LOGN, NT, 11, 3, 2>(L, elem_out(out), tw, m, 1 << 10, tid);
+    fwd_round_gc<LOGN, NT, 11, 3, 2>(L, elem_out(out), twc, m, 1 << 10, tid);
     __syncthreads();
   }
 }

@@ -239,6 +239,7 @@ void build_ctx(hs_ctx* c) {
   all.push_back(c->t);
   const u64 N = c->N;
   std::vector<double2> tw(all.size() * 2 * N);
+  std::vector<double> twc(all.size() * N);
   c->psi.clear();
   c->h_tab.assign(all.size(), ModTab{});
   std::vector<u64> pw(N);
@@ -253,6 +254,7 @@ void build_ctx(hs_ctx* c) {
     for (u64 i = 0; i < N; i++) {
       const u32 r = bit_reverse((u32)i, c->logn);
       fw[i] = make_const(pw[r], q);
+      twc[mi * N + i] = (double)pw[r];
       iv[i] = make_const(r == 0 ? 1 : q - pw[N - r], q);  // psi^-r = -psi^(N-r)
     }
     ModTab& t = c->h_tab[mi];
@@ -261,9 +263,11 @@ void build_ctx(hs_ctx* c) {
     t.ninv = make_const(inv_mod(N % q, q), q);
   }
   c->d_tw = upload(tw);
+  c->d_twc = upload(twc);
   for (size_t mi = 0; mi < all.size(); mi++) {
     c->h_tab[mi].fw = c->d_tw + mi * 2 * N;
     c->h_tab[mi].iv = c->d_tw + mi * 2 * N + N;
+    c->h_tab[mi].fwc = c->d_twc + mi * N;
   }
   c->d_tab = upload(c->h_tab);
 
@@ -384,7 +388,7 @@ void build_ctx(hs_ctx* c) {
 }
 
 void free_ctx(hs_ctx* c) {
-  void* ptrs[] = {c->d_tab, c->d_tw, c->d_slot_pos, c->d_qdt, c->d_pmod, c->d_pinv, c->d_up_inv,
+  void* ptrs[] = {c->d_tab, c->d_tw, c->d_twc, c->d_slot_pos, c->d_qdt, c->d_pmod, c->d_pinv, c->d_up_inv,
                   c->d_up_hat, c->d_dn_inv, c->d_dn_hat, c->d_dec_inv, c->d_dec_hat, c->d_dec_q,
                   c->d_t_halfq, c->d_t_mhat_inv, c->d_t_mhat, c->d_t_m, c->d_t_halfm, c->d_t_d, c->d_t_mu, c->d_t_r32};
   for (void* p : ptrs)
