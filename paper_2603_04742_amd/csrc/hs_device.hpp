@@ -62,9 +62,9 @@ __device__ __forceinline__ double mulmod(double a, double b, ModD m) {
 
 // a * w mod q for a twiddle |w| < q given alone (no precomputed quotient): the quotient is
 // estimated from the rounded product, fl(a w) fl(1/q), which errs from a w / q by at most
-// 2^-52 |a w| / q < 2^-52 |a|.  For |a| <= 1.9 * 2^50 that keeps the estimate below 2^51 (exact
+// 2^-52 |a w| / q < 2^-52 |a|.  For |a| <= 1.91 * 2^50 that keeps the estimate below 2^51 (exact
 // rounding by kRound) and the result r = a w - k q exact with |r| <= q (1/2 + 2^-52 |a|), i.e.
-// <= 0.625 q, 0.79 q, 0.975 q for |a| <= q/2 + 1, 1.125 q, 1.9 q.  Same operations as mul_tw.
+// <= 0.625 q, 0.79 q, 0.98 q for |a| <= q/2 + 1, 1.125 q, 1.91 q.  Same operations as mul_tw.
 __device__ __forceinline__ double mul_twc(double a, double w, ModD m) {
   double h = a * w;
   double l = __builtin_fma(a, w, -h);
@@ -320,16 +320,20 @@ __device__ __forceinline__ void ct_group(double (&x)[1 << R], int hb, const doub
 }
 
 // ct_group over the 8-byte twiddle table (w alone, mul_twc): half the twiddle bytes of ct_group,
-// for rounds of at most three stages that start at a reduction point, so that the inputs of the
-// first stage are within q/2 + 1; the bounds of mul_twc then give products within 0.625 q, 0.79 q,
-// 0.975 q and outputs within 1.125 q, 1.9 q, 2.9 q < 2^52 at the three stages.
+// with the same reductions (before stages 2, 5, 8, ...).  After a reduction the inputs of the
+// next three stages are within q/2 + 1, 1.125 q and 1.91 q (products within 0.625 q, 0.79 q,
+// 0.98 q by the bounds of mul_twc) and the third stage's outputs within 2.9 q < 2^52; stages 0
+// and 1 take inputs within q and 1.75 q (canonical inputs; stage 0 by either table).  So every
+// stage input stays within 1.91 q, whichever stage a round starts at, and a round that ends
+// between reductions leaves its outputs within 1.91 q (one stage after one) or 2.9 q.
 template <int R, int ST0>
 __device__ __forceinline__ void ct_group_c(double (&x)[1 << R], int hb, const double* __restrict__ twc, ModD m) {
-  static_assert(R <= 3 && fwd_reduces_before(ST0), "the bounds need a reduction at the first stage and at most three stages");
-#pragma unroll
-  for (int u = 0; u < (1 << R); u++) x[u] = reduce(x[u], m);
 #pragma unroll
   for (int k = 0; k < R; k++) {
+    if (fwd_reduces_before(ST0 + k)) {
+#pragma unroll
+      for (int u = 0; u < (1 << R); u++) x[u] = reduce(x[u], m);
+    }
     const double __attribute__((address_space(1)))* twk =
         (const double __attribute__((address_space(1)))*)(twc + (1 << (ST0 + k)) + (hb << k));
 #pragma unroll

@@ -798,7 +798,8 @@ k_modup_ip_reg(const RotItem* __restrict__ items, const u64* __restrict__ D, dou
   for (int j = j0; j < j1; j++) {
     int tid = threadIdx.x;   // recomputed per digit (not held in registers across the loop)
     const double2* tw = tb.fw;
-    asm volatile("" : "+v"(tid), "+s"(tw));
+    const double* twc = tb.fwc;
+    asm volatile("" : "+v"(tid), "+s"(tw), "+s"(twc));
     const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha);
     const u64* kb = it.key + (((size_t)0 * S.dnum + j) * LK + mi) * n + hoff;
     const u64* ka = it.key + (((size_t)1 * S.dnum + j) * LK + mi) * n + hoff;
@@ -867,10 +868,10 @@ k_modup_ip_reg(const RotItem* __restrict__ items, const u64* __restrict__ D, dou
       // per thread; the opaque twiddle base keeps a call's twiddle loads from being hoisted into
       // the previous one
 #define HS_R8(ST0)                                                                     \
-  fwd_round_g<LOGN, NT, ST0, 3, 1>(Lh, Lh, tw, m, h * (P / 8), tid);                    \
-  asm volatile("" : "+s"(tw));                                                          \
-  fwd_round_g<LOGN, NT, ST0, 3, 1>(Lh, Lh, tw, m, h * (P / 8) + NT, tid);               \
-  asm volatile("" : "+s"(tw));                                                          \
+  fwd_round_gc<LOGN, NT, ST0, 3, 1>(Lh, Lh, twc, m, h * (P / 8), tid);                  \
+  asm volatile("" : "+s"(twc));                                                         \
+  fwd_round_gc<LOGN, NT, ST0, 3, 1>(Lh, Lh, twc, m, h * (P / 8) + NT, tid);             \
+  asm volatile("" : "+s"(twc));                                                         \
   __syncthreads();
       HS_R8(1) HS_R8(4) HS_R8(7) HS_R8(10)
 #undef HS_R8
@@ -878,8 +879,8 @@ k_modup_ip_reg(const RotItem* __restrict__ items, const u64* __restrict__ D, dou
 #pragma unroll
       for (int k = 0; k < NP; k++) {
         const int e = 2 * tid + k * 2 * NT;
-        const double2 w = ldtw(tw, (1 << 13) + ((hoff + e) >> 1));
-        const double x0 = smem[lpad(e)], t = mul_tw(smem[lpad(e + 1)], w.x, w.y, m);
+        const double w = gld(twc + (1 << 13) + ((hoff + e) >> 1));
+        const double x0 = smem[lpad(e)], t = mul_twc(smem[lpad(e + 1)], w, m);
         accumulate(k, x0 + t, x0 - t);
       }
       __syncthreads();   // the next digit's stage 0 overwrites LDS
