@@ -527,13 +527,15 @@ struct LdsHalf {
 // halves are then independent 13-stage problems.  Each thread owns elements tid + 512 k of both
 // halves, which is exactly its register group of stages 1..4 (LO = 9), so that round needs no LDS.
 // The second half waits in registers while the first runs stages 5..13 through LDS
-// (rounds 3,3,3 with two tasks per thread).  Inverse: the mirror image (stages 0..12 per half,
-// stage 13 and the 1/N scaling in registers at the end).
+// (rounds 3,3,3 with two tasks per thread, reading the 8-byte twiddles: ct_group_c, outputs
+// within 2.9 q).  Inverse: the mirror image (stages 0..12 per half, stage 13 and the 1/N scaling
+// in registers at the end).
 static constexpr int kSplitLogn = 14, kSplitNT = 512;
 __host__ __device__ constexpr int split_lds_doubles() { return lds_doubles(1 << (kSplitLogn - 1)); }
 
 template <class In, class Out>
-__device__ __forceinline__ void ntt_fwd_split(const In& in, const Out& out, double* s, const double2* __restrict__ tw, ModD m,
+__device__ __forceinline__ void ntt_fwd_split(const In& in, const Out& out, double* s, const double2* __restrict__ tw,
+                                              const double* __restrict__ twc, ModD m,
                                               int tid = threadIdx.x) {
   constexpr int LOGN = kSplitLogn, NT = kSplitNT, H = 1 << (LOGN - 1), EH = H / NT;
   static_assert(EH == 16, "split layout assumes 16 elements per thread and half");
@@ -554,27 +556,28 @@ __device__ __forceinline__ void ntt_fwd_split(const In& in, const Out& out, doub
   ct_group<4, 1>(a, 0, tw, m);
   LdsHalf<LOGN - 1>{s}.template put<4, 9>(a, tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 5, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, m, 0, tid);
+  fwd_round_gc<LOGN, NT, 5, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, twc, m, 0, tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 8, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, m, 0, tid);
+  fwd_round_gc<LOGN, NT, 8, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, twc, m, 0, tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 11, 3, 2>(LdsHalf<LOGN - 1>{s}, elem_out(out), tw, m, 0, tid);
+  fwd_round_gc<LOGN, NT, 11, 3, 2>(LdsHalf<LOGN - 1>{s}, elem_out(out), twc, m, 0, tid);
   __syncthreads();
   ct_group<4, 1>(b, 1, tw, m);
   LdsHalf<LOGN - 1>{s}.template put<4, 9>(b, H + tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 5, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, m, 1 << 10, tid);
+  fwd_round_gc<LOGN, NT, 5, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, twc, m, 1 << 10, tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 8, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, tw, m, 1 << 10, tid);
+  fwd_round_gc<LOGN, NT, 8, 3, 2>(LdsHalf<LOGN - 1>{s}, LdsHalf<LOGN - 1>{s}, twc, m, 1 << 10, tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 11, 3, 2>(LdsHalf<LOGN - 1>{s}, elem_out(out), tw, m, 1 << 10, tid);
+  fwd_round_gc<LOGN, NT, 11, 3, 2>(LdsHalf<LOGN - 1>{s}, elem_out(out), twc, m, 1 << 10, tid);
 }
 
 // As ntt_fwd_split, but each half's result stays in LDS and seg(base, count) is called (after a
 // barrier) to consume elements base .. base + count - 1, element base + e at s[lpad(e)]; for
 // epilogues too heavy to inline into the last round.  Ends with a barrier.
 template <class In, class Seg>
-__device__ __forceinline__ void ntt_fwd_split_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, ModD m,
+__device__ __forceinline__ void ntt_fwd_split_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw,
+                                                  const double* __restrict__ twc, ModD m,
                                                   int tid = threadIdx.x) {
   constexpr int LOGN = kSplitLogn, NT = kSplitNT, H = 1 << (LOGN - 1), EH = H / NT;
   double a[EH], b[EH];
@@ -595,22 +598,22 @@ __device__ __forceinline__ void ntt_fwd_split_seg(const In& in, const Seg& seg, 
   ct_group<4, 1>(a, 0, tw, m);
   L.template put<4, 9>(a, tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 5, 3, 2>(L, L, tw, m, 0, tid);
+  fwd_round_gc<LOGN, NT, 5, 3, 2>(L, L, twc, m, 0, tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 8, 3, 2>(L, L, tw, m, 0, tid);
+  fwd_round_gc<LOGN, NT, 8, 3, 2>(L, L, twc, m, 0, tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 11, 3, 2>(L, L, tw, m, 0, tid);
+  fwd_round_gc<LOGN, NT, 11, 3, 2>(L, L, twc, m, 0, tid);
   __syncthreads();
   seg(0, H);
   __syncthreads();
   ct_group<4, 1>(b, 1, tw, m);
   L.template put<4, 9>(b, H + tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 5, 3, 2>(L, L, tw, m, 1 << 10, tid);
+  fwd_round_gc<LOGN, NT, 5, 3, 2>(L, L, twc, m, 1 << 10, tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 8, 3, 2>(L, L, tw, m, 1 << 10, tid);
+  fwd_round_gc<LOGN, NT, 8, 3, 2>(L, L, twc, m, 1 << 10, tid);
   __syncthreads();
-  fwd_round_g<LOGN, NT, 11, 3, 2>(L, L, tw, m, 1 << 10, tid);
+  fwd_round_gc<LOGN, NT, 11, 3, 2>(L, L, twc, m, 1 << 10, tid);
   __syncthreads();
   seg(H, H);
   __syncthreads();

@@ -50,7 +50,8 @@ struct XfRuntime {
   static constexpr int NT = NT_;
   int logn;
   template <class In, class Out>
-  __device__ __forceinline__ void fwd(const In& in, const Out& out, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
+  __device__ __forceinline__ void fwd(const In& in, const Out& out, double* s, const double2* __restrict__ tw, const double* __restrict__ twc, ModD m,
+                                      int tid = threadIdx.x) const {
     const int n = 1 << logn;
     for (int i = threadIdx.x; i < n; i += NT) s[lpad(i)] = in(i);
     __syncthreads();
@@ -58,7 +59,8 @@ struct XfRuntime {
     for (int i = threadIdx.x; i < n; i += NT) out(i, s[lpad(i)]);
   }
   template <class In, class Seg>
-  __device__ __forceinline__ void fwd_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
+  __device__ __forceinline__ void fwd_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, const double* __restrict__ twc, ModD m,
+                                          int tid = threadIdx.x) const {
     const int n = 1 << logn;
     for (int i = threadIdx.x; i < n; i += NT) s[lpad(i)] = in(i);
     __syncthreads();
@@ -80,11 +82,13 @@ struct XfStatic {
   static constexpr int NT = NT_;
   static constexpr int LOGN = static_logn(NT_);
   template <class In, class Out>
-  __device__ __forceinline__ void fwd(const In& in, const Out& out, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
+  __device__ __forceinline__ void fwd(const In& in, const Out& out, double* s, const double2* __restrict__ tw, const double* __restrict__ twc, ModD m,
+                                      int tid = threadIdx.x) const {
     ntt_fwd_c<LOGN, NT>(elem_in(in), elem_out(out), s, tw, m, tid);
   }
   template <class In, class Seg>
-  __device__ __forceinline__ void fwd_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
+  __device__ __forceinline__ void fwd_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, const double* __restrict__ twc, ModD m,
+                                          int tid = threadIdx.x) const {
     ntt_fwd_c<LOGN, NT>(elem_in(in), LdsIO{s}, s, tw, m, tid);
     __syncthreads();
     seg(0, 1 << LOGN);
@@ -98,12 +102,14 @@ struct XfStatic {
 struct XfSplit {
   static constexpr int NT = kSplitNT;
   template <class In, class Out>
-  __device__ __forceinline__ void fwd(const In& in, const Out& out, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
-    ntt_fwd_split(in, out, s, tw, m, tid);
+  __device__ __forceinline__ void fwd(const In& in, const Out& out, double* s, const double2* __restrict__ tw, const double* __restrict__ twc, ModD m,
+                                      int tid = threadIdx.x) const {
+    ntt_fwd_split(in, out, s, tw, twc, m, tid);
   }
   template <class In, class Seg>
-  __device__ __forceinline__ void fwd_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, ModD m, int tid = threadIdx.x) const {
-    ntt_fwd_split_seg(in, seg, s, tw, m, tid);
+  __device__ __forceinline__ void fwd_seg(const In& in, const Seg& seg, double* s, const double2* __restrict__ tw, const double* __restrict__ twc, ModD m,
+                                          int tid = threadIdx.x) const {
+    ntt_fwd_split_seg(in, seg, s, tw, twc, m, tid);
   }
   template <class In, class Out>
   __device__ __forceinline__ void inv(const In& in, const Out& out, double* s, const double2* __restrict__ tw, double2 ninv, ModD m, int tid = threadIdx.x) const {
@@ -125,7 +131,7 @@ HS_XF_KERNEL k_ntt(u64* data, int nl, int mod0, int inverse, const ModTab* __res
   auto in = [p](int i) { return u2d(p[i]); };
   auto out = [p, m](int i, double x) { p[i] = d2u(canon(x, m)); };
   if (inverse) xf.inv(in, out, smem, t.iv, t.ninv, m);
-  else xf.fwd(in, out, smem, t.fw, m);
+  else xf.fwd(in, out, smem, t.fw, t.fwc, m);
 }
 
 // One workgroup of 1024 threads per N = 2^15 limb (in place, canonical u64 in and out), for
@@ -317,10 +323,10 @@ HS_XF_KERNEL k_enc_ntt(const u64* __restrict__ mcoef, const int* __restrict__ sa
   u64* p = prep + (size_t)b * n;
   auto out = [p, m](int i, double x) { p[i] = d2u(canon(x, m)); };
   if (which == 0) {
-    xf.fwd([u, q](int i) { const int v = u[i]; return v < 0 ? (double)v + q : (double)v; }, out, smem, tb.fw, m);
+    xf.fwd([u, q](int i) { const int v = u[i]; return v < 0 ? (double)v + q : (double)v; }, out, smem, tb.fw, tb.fwc, m);
   } else if (which == 1) {
     const int* e1 = u + 2 * n;
-    xf.fwd([e1, q](int i) { const int v = e1[i]; return v < 0 ? (double)v + q : (double)v; }, out, smem, tb.fw, m);
+    xf.fwd([e1, q](int i) { const int v = e1[i]; return v < 0 ? (double)v + q : (double)v; }, out, smem, tb.fw, tb.fwc, m);
   } else {
     const int* e0 = u + n;
     const double2 qd = qdt[l];
@@ -334,7 +340,7 @@ HS_XF_KERNEL k_enc_ntt(const u64* __restrict__ mcoef, const int* __restrict__ sa
           const double d2 = floor(((double)(q_mod_t * mv) + th) / tt);
           return canon(reduce((double)e0[i] + d1 + d2, m), m);
         },
-        out, smem, tb.fw, m);
+        out, smem, tb.fw, tb.fwc, m);
   }
 }
 
@@ -499,7 +505,7 @@ HS_XF_KERNEL k_plain_ntt(const u64* __restrict__ coef, u64* out, int L, u64 t, c
     return v > (t - 1) / 2 ? (double)v - (double)t : (double)v;
   };
   auto sink = [o, m](int i, double x) { o[i] = d2u(canon(x, m)); };
-  xf.fwd(in, sink, smem, tb.fw, m);
+  xf.fwd(in, sink, smem, tb.fw, tb.fwc, m);
 }
 
 // ------------------------------------------------------------------ encryption
@@ -673,7 +679,8 @@ HS_XF_KERNEL k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict
     // instead of being hoisted out of the loop and held in registers across it
     int tid = threadIdx.x;
     const double2* tw = tb.fw;
-    asm volatile("" : "+v"(tid), "+s"(tw));
+    const double* twc = tb.fwc;
+    asm volatile("" : "+v"(tid), "+s"(tw), "+s"(twc));
     const int lo = j * S.alpha, hi = min(S.L, lo + S.alpha);
     const bool own = (mi >= lo && mi < hi);
     const bool first = (j == j0);
@@ -697,9 +704,12 @@ HS_XF_KERNEL k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict
         const int e = e0 + c * NT;
         if (e < cnt) {
           const double x = reduce(value(c, e), m);
+          // the transform's outputs are within 2.9 q, so the products are exact but may reach
+          // about 2.2 q: reduced before they are stored or summed
           double v0 = mulmod(x, u2d(wb[c]), m);
           double v1 = mulmod(x, u2d(wa[c]), m);
-          if (!first) { v0 = reduce(v0 + a0[c], m); v1 = reduce(v1 + a1[c], m); }
+          v0 = reduce(first ? v0 : v0 + a0[c], m);
+          v1 = reduce(first ? v1 : v1 + a1[c], m);
           gst(o0 + base + e, v0);
           gst(o1 + base + e, v1);
         }
@@ -724,7 +734,7 @@ HS_XF_KERNEL k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict
       };
       if (na == 1) {
         // one source prime (alpha = 1): [x]_q as an integer, taken mod mi
-        xf.fwd_seg([=](int i) { return reduce(u2d(Dj[i]), m); }, seg, smem, tw, m, tid);
+        xf.fwd_seg([=](int i) { return reduce(u2d(Dj[i]), m); }, seg, smem, tw, twc, m, tid);
       } else {
         // fast basis conversion from the digit's primes to modulus mi
         const double2* cinv = up_inv + j * S.alpha;
@@ -740,7 +750,7 @@ HS_XF_KERNEL k_modup_ip(const RotItem* __restrict__ items, const u64* __restrict
           }
           return acc;
         };
-        xf.fwd_seg(src, seg, smem, tw, m, tid);
+        xf.fwd_seg(src, seg, smem, tw, twc, m, tid);
       }
     }
     __syncthreads();
@@ -986,7 +996,7 @@ HS_XF_KERNEL k_moddown_ntt(const RotItem* __restrict__ items, const double* __re
       }
     }
   };
-  xf.fwd_seg(src, seg, smem, tb.fw, m);
+  xf.fwd_seg(src, seg, smem, tb.fw, tb.fwc, m);
 }
 
 // ------------------------------------------------------------------ decryption
