@@ -64,14 +64,9 @@ __device__ __forceinline__ double mulmod(double a, double b, ModD m) {
 // estimated from the rounded product, fl(a w) fl(1/q), which errs from a w / q by at most
 // 2^-52 |a w| / q < 2^-52 |a|.  For |a| <= 1.91 * 2^50 that keeps the estimate below 2^51 (exact
 // rounding by kRound) and the result r = a w - k q exact with |r| <= q (1/2 + 2^-52 |a|), i.e.
-// <= 0.625 q, 0.79 q, 0.98 q for |a| <= q/2 + 1, 1.125 q, 1.91 q.  Same operations as mul_tw.
-__device__ __forceinline__ double mul_twc(double a, double w, ModD m) {
-  double h = a * w;
-  double l = __builtin_fma(a, w, -h);
-  double k = __builtin_fma(h, m.qinv, kRound) - kRound;
-  double r = __builtin_fma(-k, m.q, h);
-  return r + l;
-}
+// <= 0.625 q, 0.79 q, 0.98 q for |a| <= q/2 + 1, 1.125 q, 1.91 q.  It is mulmod's arithmetic
+// (as many operations as mul_tw) under these bounds.
+__device__ __forceinline__ double mul_twc(double a, double w, ModD m) { return mulmod(a, w, m); }
 
 // Balanced value (|x| < 2^52) -> canonical residue in [0, q).
 __device__ __forceinline__ double canon(double x, ModD m) {
