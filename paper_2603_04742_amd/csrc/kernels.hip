@@ -37,9 +37,10 @@ __device__ __forceinline__ void store_canon(u64* out, const double* s, int n, Mo
 
 // ------------------------------------------------------------------ limb-transform policies
 // How a workgroup of XF::NT threads runs one length-N transform from an element source in(e)
-// (|x| <= q) to an element sink out(e, x) (balanced x, |x| <= 2.375 q + 1 forward, 0.625 q
-// inverse).  Every element is read once and written once, each by one thread; the functions end
-// without a barrier, so a caller that reuses LDS synchronises first.  fwd_seg leaves the result
+// (|x| <= q) to an element sink out(e, x) (balanced x, |x| <= 2.9 q forward with the half-limb
+// policy's 8-byte twiddles, 2.375 q + 1 with the others, 0.625 q inverse).  Every element is read
+// once and written once, each by one thread; the functions end without a barrier, so a caller
+// that reuses LDS synchronises first.  fwd_seg leaves the result
 // in LDS and hands it to seg(base, count) in one or two segments (element base + e at
 // s[lpad(e)]), ending with a barrier.
 //   XfRuntime<NT>: any N <= 16 NT, limb in LDS, runtime log N (small rings)
@@ -486,6 +487,14 @@ __global__ void __launch_bounds__(NT) k_pack_encode(PackArgs A, const u32* __res
     smem[lpad(slot_pos[k])] = (double)val;
   }
   __syncthreads();
+  if constexpr (static_logn(NT) > 0) {
+    if (logn == static_logn(NT)) {   // the compile-time whole-limb schedule, in place from LDS
+      u64* o = A.out + (size_t)g * n;
+      ntt_inv_c<static_logn(NT), NT>(LdsIO{smem}, elem_out([o, m](int i, double x) { o[i] = d2u(canon(x, m)); }), smem, t.iv,
+                                     t.ninv, m);
+      return;
+    }
+  }
   lds_ntt_inv<NT>(smem, logn, t.iv, t.ninv, m);
   store_canon(A.out + (size_t)g * n, smem, n, m, NT);
 }
