@@ -880,8 +880,8 @@ std::vector<u64> rotate_with_key(const Ctx& c, const std::vector<u64>& ct, u64 g
   return r;
 }
 /* HE-Rot by k slots (left, within each row of N/2 slots).  With a rotation key for exactly k,
-   one key switch with it; otherwise the signed power-of-two digits of k (rotation_digits), each
-   one rotation with its own key.  Both decrypt to the same rotated slots; their noise (and so
+   one key switch with it; otherwise the power-of-two digits of k (rotation_digits: binary, or
+   signed with the right keys), each one rotation with its own key.  Both decrypt to the same rotated slots; their noise (and so
    their limbs) differ. */
 std::vector<u64> rotate(const Ctx& c, const std::vector<u64>& ct, u64 k, int* nks) {
   std::vector<u64> r(ct);

@@ -326,8 +326,8 @@ static std::vector<MicroOp> total_sum_program(const hs_ctx* c, const hs_keyset* 
   const i64 half = (i64)c->N / 2;
   auto rotate_into = [&](int src, i64 amount, int addend) {
     // rotation by `amount` as one key switch when the key-set holds a key for the whole step,
-    // else as its signed power-of-two digits (rotation_digits); the last one lands in the W
-    // buffer that is not the current accumulator, plus `addend`
+    // else as its power-of-two digits (rotation_digits); the last one lands in the W buffer
+    // that is not the current accumulator, plus `addend`
     const std::vector<i64> bits = rotation_digits(c, ks, amount % half);
     if (bits.empty()) throw Error{HS_EINVAL, "internal: zero rotation in totalSum"};
     const int dst_w = (w == 1) ? 2 : 1;
@@ -2014,7 +2014,7 @@ int hs_rotate(hs_ctx* c, const hs_keyset* ks, const hs_ctvec* in, int64_t k, voi
       u64* cur = r->d;
       u64* other = tmp.as<u64>();
       std::vector<std::vector<RotItem>> levels;
-      const std::vector<i64> steps = rotation_digits(c, ks, kk);  // one exact-step key switch, or the signed digits
+      const std::vector<i64> steps = rotation_digits(c, ks, kk);  // one exact-step key switch, or the digits
       for (i64 step : steps) {
         std::vector<RotItem> items;
         for (i64 g = 0; g < in->n; g++) {
@@ -2241,13 +2241,14 @@ int hs_diag_encrypt(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const int6
 }
 
 // Rotations of the vector blocks: Rot(x_bj, d) for every (bj, d) a diagonal needs.  With an
-// exact-step key for d, one key switch from x_bj; otherwise the signed power-of-two digits of d
-// (rotation_digits, lowest first), so Rot(x_bj, v) = Rot_z(Rot(x_bj, v - z)) for every partial
-// sum v of those digits with z its top digit: every such partial rotation is computed once per
-// block column and shared (a partial sum of a non-adjacent form is the non-adjacent form of its
-// value, so the partial rotation of a value is the same whichever step reaches it).  Level h
-// holds the partial rotations whose top digit is +-2^h (the exact-step ones go to level 0);
-// levels are cut into batches of at most kDiagBatch key switches.
+// exact-step key for d, one key switch from x_bj; otherwise the power-of-two digits of d
+// (rotation_digits, lowest first: binary, or signed with the right keys), so
+// Rot(x_bj, v) = Rot_z(Rot(x_bj, v - z)) for every partial sum v of those digits with z its top
+// digit: every such partial rotation is computed once per block column and shared (the low
+// digits of a binary expansion or of a non-adjacent form are the expansion of their own sum, so
+// the partial rotation of a value is the same whichever offset reaches it).  Level h holds the
+// partial rotations whose top digit is +-2^h (the exact-step ones go to level 0); levels are cut
+// into batches of at most kDiagBatch key switches.
 static constexpr size_t kDiagBatch = 256;
 int hs_diag_spmv(hs_ctx* c, const hs_keyset* ks, const hs_diag* D, const hs_ctvec* x, void* stream, hs_ctvec** y) {
   return guarded([&] {
