@@ -284,6 +284,29 @@ def test_ntt_32768_one_workgroup_per_limb(path):
         H.set_option(H.OPT_NTT_PATH, 0)
 
 
+def test_ntt_32768_extreme_residues():
+    """k_ntt15 (8-byte twiddles in its LDS rounds) on residues at the top of [0, q): all q - 1 and
+    alternating q - 1 / 0 limbs equal the oracle's transform; the inverse restores them."""
+    g = H.Context(15, 12, 50, 2)
+    o = O.Context(15, 12, 50, 2)
+    nl = 14
+    mods = o.moduli()[:nl]
+    H.set_option(H.OPT_NTT_PATH, 1)
+    try:
+        for kind in (0, 1):
+            x = np.stack([np.full(1 << 15, q - 1, np.uint64) if kind == 0 else
+                          np.where(np.arange(1 << 15) % 2 == 0, q - 1, 0).astype(np.uint64) for q in mods[:3]])
+            d = dev(x.reshape(-1), torch.int64)
+            g.ntt(d, 0, 3)
+            got = d.cpu().numpy().view(np.uint64).reshape(3, -1)
+            for r in range(3):
+                assert np.array_equal(got[r], o.ntt(r, x[r])), (kind, r)
+            g.ntt(d, 0, 3, inverse=True)
+            assert np.array_equal(d.cpu().numpy().view(np.uint64).reshape(3, -1), x)
+    finally:
+        H.set_option(H.OPT_NTT_PATH, 0)
+
+
 def test_options_rejected():
     with pytest.raises(H.HespmvError):
         H.set_option(99, 1)
