@@ -188,7 +188,7 @@ struct hs_keyset {
   hs::u64 seed = 0;
   hs::u64* sk = nullptr;        // [n_mod][N] NTT form, canonical
   hs::u64* pk = nullptr;        // [2][L][N]
-  std::vector<hs::u64*> gk;     // per power-of-two rotation i: [2][dnum][L+K][N]
+  std::vector<hs::u64*> gk;     // rotation keys [2][dnum][L+K][N]: left by 2^i at i < log2 N - 1, then the optional right ones
   std::map<hs::i64, hs::u64*> step_keys;  // exact-step rotation keys by step k, same layout
   hs::u64* rk = nullptr;        // relinearisation key, same layout
   size_t ksk_words = 0;
