@@ -363,6 +363,10 @@ class Context:
         return bool(lib().orc_has_tensor(self.h))
 
     def keyswitch(self, d, key_id):
+        """Key switch of d ([L][N], NTT form) with the relinearisation key (key_id < 0) or rotation
+        key index key_id (as ksk)."""
+        if key_id >= lib().orc_n_rotation_keys(self.h):
+            raise IndexError("no rotation key with index %d" % key_id)
         d = np.ascontiguousarray(d, np.uint64)
         out = np.zeros(self.ct_size(), np.uint64)
         lib().orc_keyswitch(self.h, _p(d, u64p), key_id, _p(out, u64p))
